@@ -1,0 +1,203 @@
+/*
+ * dec.h -- C ABI of the MI355X (gfx950) DEC steady-diffusion library.
+ *
+ * The library solves the steady conduction problem of the paper's
+ * Section 2.1 (Fourier law f = -kappa grad T, conservation div f = 0,
+ * Dirichlet T = T0, Neumann f.n = f0; eqs. 1-4) in its exterior-calculus
+ * form (eqs. 5-8) with the temperature a primal 0-form on the vertices of a
+ * tetrahedral mesh:
+ *
+ *     L T = b,   L = d0^T *1 d0,
+ *
+ * d0 the vertex-to-edge coboundary (Section 2.1, eqs. 9-10) and *1 the
+ * diagonal circumcentric Hodge star on edges (dual-area / edge-length,
+ * Section 2.1), scaled per edge by the conductivity of the dual face
+ * (Section 2.1) and set to zero on edges a crack cuts (Section 2.5).
+ *
+ * Conventions, common to every call:
+ *  - Every function returns an int status (DEC_OK = 0 or a negative
+ *    DEC_E* code); dec_last_error() gives a message for the last failure on
+ *    a context.  No C++ exception crosses this interface.
+ *  - Array arguments are DEVICE pointers unless stated otherwise; scalar
+ *    outputs (k_eff, counts, stats) are HOST pointers.
+ *  - Work is ordered on the context's HIP stream.  Calls that return a
+ *    count or a scalar to the host synchronise that stream before returning.
+ *    Input buffers only need to stay valid until the call returns.
+ *  - The caller owns every buffer it passes; the library copies what it
+ *    keeps.  The library's own device memory comes from the alloc/free
+ *    callbacks given to dec_create (hipMalloc/hipFree when they are NULL).
+ *  - Indices are 0-based int32 (V, E and nnz below 2^31); offsets inside the
+ *    library are int64 where counts may exceed that.
+ *  - One context per host thread; a context and its meshes must not be used
+ *    from two threads at once.
+ */
+#ifndef DEC_H
+#define DEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define DEC_OK 0
+#define DEC_EINVAL (-1)      /* bad argument (NULL, negative size, bad option)        */
+#define DEC_ENOMEM (-2)      /* device allocation failed                               */
+#define DEC_EHIP (-3)        /* a HIP runtime call failed                              */
+#define DEC_ENOTCONV (-4)    /* max_iters reached before the tolerance                 */
+#define DEC_EBREAKDOWN (-5)  /* CG breakdown: p.Ap <= 0 or a non-finite scalar         */
+#define DEC_ETOPO (-6)       /* invalid mesh: index out of range, repeated vertex,
+                                zero-volume tet, face shared by more than two tets      */
+#define DEC_EBUDGET (-7)     /* request does not fit the server's HBM budget           */
+#define DEC_ESTATE (-8)      /* call out of order (e.g. solve before apply_bc)         */
+
+typedef struct dec_ctx dec_ctx;
+typedef struct dec_mesh dec_mesh;
+
+typedef void* (*dec_alloc_fn)(size_t bytes, void* user);
+typedef void (*dec_free_fn)(void* ptr, void* user);
+
+/* Create a context on HIP device `device`, ordering work on `stream`
+ * (a hipStream_t; NULL = the device's null stream).  `alloc`/`free` provide
+ * the library's device memory (both NULL: hipMalloc/hipFree). */
+int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_free_fn free_fn,
+               void* user);
+int dec_destroy(dec_ctx* ctx);
+const char* dec_status_string(int status);
+const char* dec_last_error(const dec_ctx* ctx);
+
+/* ---- topology (Section 2.1: cells, incidence, coboundary d) ------------
+ * xyz: [V x 3] float64, tets: [T x 4] int32, device.  Builds the edge set
+ * (unique vertex pairs (lo < hi), numbered in lexicographic order, oriented
+ * lo -> hi so (d0 a)_e = a_hi - a_lo), the edge-to-tet incidence in
+ * ascending tet order, the static CSR pattern of L (full edge graph plus
+ * diagonal, columns ascending) and the boundary faces.  Returns DEC_ETOPO
+ * for an invalid mesh.  Synchronises the stream. */
+int dec_build_topology(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets,
+                       dec_mesh** out);
+/* Counts of vertices, tets, edges, faces, boundary faces and nonzeros of L (host outputs; any
+ * may be NULL). */
+int dec_mesh_info(const dec_mesh* m, int64_t* V, int64_t* T, int64_t* E, int64_t* F,
+                  int64_t* F_boundary, int64_t* nnz);
+/* Copy the edge list [E x 2] int32 (lo, hi) into a device buffer. */
+int dec_get_edges(const dec_mesh* m, int32_t* edges);
+/* Copy the CSR of the current system matrix into device buffers (any may be NULL):
+ * row_ptr [V+1] int32, col [nnz] int32, val64 [nnz] float64, val32 [nnz] float32.  Before
+ * dec_apply_bc the values are those of L; after, those of the eliminated system A. */
+int dec_get_csr(const dec_mesh* m, int32_t* row_ptr, int32_t* col, double* val64, float* val32);
+int dec_mesh_destroy(dec_mesh* m);
+
+/* ---- Hodge star *1 with conductivity and cracks (Sections 2.1, 2.5) ----
+ * |*e| = sum over the edge's tets (ascending tet id) of the signed area of
+ * the circumcentric dual quadrilateral (m_e, c_f1, c_T, c_f2); |*e| is
+ * snapped to 0 when |*e| <= 1e-12 |e|^2.  *1_e = kappa_e * (|*e| / |e|),
+ * and 0 on edges cut by a crack disc.
+ * kappa: [E] float64 (NULL: kappa = 1).  cracks: [n_cracks x 7] float64 rows
+ * (cx, cy, cz, nx, ny, nz, r), unit normal (NULL when n_cracks == 0).  An
+ * edge (p0 = lo, p1 = hi) is cut when (s0 < 0) != (s1 < 0) with
+ * s = (p - c).n, and the crossing point q = p0 + s0/(s0 - s1) (p1 - p0)
+ * has |q - c|^2 <= r^2 (FP64, fixed operation order, no contraction).
+ * cut_out: [E] uint8 (NULL ok), star1_out: [E] float64 (NULL ok).  The mesh
+ * keeps *1 for dec_assemble and the flux. */
+int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, const double* cracks,
+               uint8_t* cut_out, double* star1_out);
+
+/* ---- assembly of L = d0^T *1 d0 ---------------------------------------
+ * L_ij = -*1_e for e = (i, j), L_ii = sum of *1_e over the row's edges in
+ * ascending column order, pattern fixed (zeros kept), no atomics.  Fills the
+ * FP64 and FP32 CSR and sliced-ELL copies.  flags: DEC_ASM_DEFAULT. */
+#define DEC_ASM_DEFAULT 0u
+int dec_assemble(dec_mesh* m, uint32_t flags);
+
+/* ---- boundary data (eqs. 3-4, 12-13) -----------------------------------
+ * bc_type [V] int8: 0 free, 1 Dirichlet (T = bc_value), 2 Neumann vertex
+ * (outward flux density neumann_f0[v]).  bc_value [V] float64.
+ * neumann_f0 [V] float64 or NULL.  Dirichlet rows and columns are
+ * eliminated symmetrically (identity rows, b_i -= L_ij T_j); a boundary face
+ * whose vertices are all Neumann or Dirichlet, at least one Neumann, loads
+ * b_v -= f0_v A*_{v,f} on its Neumann vertices (A*_{v,f}: v's circumcentric
+ * part of the face); connected parts of the graph of edges with *1 != 0
+ * that hold no Dirichlet vertex are pinned to T = 0.  n_pinned_out (host,
+ * NULL ok) receives their vertex count; b_out [V] float64 device (NULL ok)
+ * the right-hand side.  Synchronises the stream. */
+int dec_apply_bc(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
+                 const double* neumann_f0, int64_t* n_pinned_out, double* b_out);
+
+/* ---- solve ------------------------------------------------------------- */
+#define DEC_PREC_FP64 0   /* FP64 PCG                                              */
+#define DEC_PREC_MIXED 1  /* FP32 PCG inner solves inside FP64 iterative refinement */
+#define DEC_PRECOND_JACOBI 0
+#define DEC_PRECOND_FSAI 1 /* factored sparse approximate inverse, pattern lower(L)  */
+#define DEC_FMT_AUTO 0
+#define DEC_FMT_CSR 1
+#define DEC_FMT_SELL 2
+
+typedef struct dec_solve_opts {
+    int32_t precision;           /* DEC_PREC_*                                     */
+    int32_t precond;             /* DEC_PRECOND_*                                  */
+    double tol;                  /* stop at ||b - A T||_2 <= tol ||b||_2 (FP64)    */
+    double inner_tol;            /* mixed: relative tolerance of each FP32 solve   */
+    int32_t adaptive_final_inner;/* mixed: inner tol max(inner_tol, 0.5 tol||b||/||r||) */
+    int32_t warm_start;          /* T holds the initial guess (Dirichlet values are imposed) */
+    int64_t max_iters;           /* cap on PCG iterations (FP64) / inner iterations (mixed) */
+    int32_t format;              /* DEC_FMT_* for the SpMV                         */
+    int32_t chunk;               /* iterations per launch batch (0: default)       */
+    int32_t use_graph;           /* capture each batch in a hipGraph               */
+    int32_t profile;             /* time every SpMV launch with HIP events          */
+} dec_solve_opts;
+
+typedef struct dec_solve_stats {
+    int64_t iterations;       /* FP64: PCG iterations. mixed: sum of inner iterations    */
+    int64_t outer_iterations; /* mixed: refinement steps (FP64 residuals)                */
+    int64_t restarts;         /* FP64: restarts from the true residual                    */
+    int32_t fp64_fallback;    /* mixed: 1 when refinement stagnated and FP64 PCG finished */
+    int32_t status;           /* DEC_OK / DEC_ENOTCONV / DEC_EBREAKDOWN                   */
+    double rel_residual;      /* true FP64 ||b - A T|| / ||b|| at exit                     */
+    double solve_ms;          /* wall time of the call on the stream (HIP events)          */
+    int64_t spmv_launches;    /* profile: SpMV launches timed                              */
+    double spmv_ms;           /* profile: summed duration of those launches                */
+    double spmv_bytes;        /* algorithmic bytes of one SpMV launch (CSR definition)     */
+} dec_solve_stats;
+
+/* Fill opts with the defaults: FP64, Jacobi, tol 1e-10, inner_tol 1e-5,
+ * adaptive final inner tolerance on, cold start, max_iters 100000, auto
+ * format, chunk 32, graphs on, profiling off. */
+int dec_solve_opts_default(dec_solve_opts* opts);
+/* Solve A T = b (after dec_apply_bc).  T [V] float64 device: initial guess
+ * when opts->warm_start, solution on return.  stats (host) may be NULL.
+ * Returns DEC_OK, DEC_ENOTCONV or DEC_EBREAKDOWN (T then holds the last
+ * iterate).  Synchronises the stream. */
+int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats);
+
+/* y = A x with the current system matrix.  precision DEC_PREC_FP64 (x, y
+ * float64) or DEC_PREC_MIXED (x, y float32), format DEC_FMT_*.  Device
+ * vectors of length V.  Asynchronous. */
+int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void* y);
+
+/* The FSAI factor G of the current system (built on first use): nnz_out
+ * (host) receives its entry count; g_ptr [V+1] int32, g_col [nnz] int32,
+ * g_val [nnz] float64 device buffers (any may be NULL).  Row i holds
+ * y / sqrt(y_i) with A[S_i,S_i] y = e_i over S_i = {j <= i : A_ij stored}
+ * (Kolotilina-Yeremin factored sparse approximate inverse, the role
+ * ParaSails has in Section 2.3).  Synchronises the stream. */
+int dec_get_fsai(dec_mesh* m, int64_t* nnz_out, int32_t* g_ptr, int32_t* g_col, double* g_val);
+
+/* ---- flux and effective conductivity (Section 2.5) ---------------------
+ * T [V] float64, side [V] int8 (1 inflow face, 2 outflow face, 0 other).
+ * Q_in = sum over side 1 of (L T)_v, Q_out = -sum over side 2, with L before
+ * boundary elimination; energy E = sum_e *1_e (T_hi - T_lo)^2 and
+ * k_eff = E length / (area dT^2).  Host scalar outputs (NULL ok);
+ * edge_flux_out [E] float64 device (NULL ok): *1_e (T_lo - T_hi).
+ * Synchronises the stream. */
+int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* side,
+                                    double length, double area, double dT, double* k_eff,
+                                    double* q_in, double* q_out, double* energy,
+                                    double* edge_flux_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEC_H */

@@ -1,0 +1,211 @@
+"""DEC steady diffusion on tetrahedral meshes for MI355X (gfx950).
+
+Thin Python binding over the C ABI of libdec_hip.so (include/dec.h): every
+step of the path -- topology, circumcentric Hodge star with cracks,
+assembly of L = d0^T *1 d0, boundary data, PCG / mixed-precision
+refinement, flux and effective conductivity -- runs in the HIP kernels of
+that library.  This module only checks and marshals arguments; PyTorch
+provides device memory (its caching allocator backs the library's
+allocations) and streams.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_PREC_FP64, DEC_PREC_MIXED, DEC_PRECOND_FSAI,
+                   DEC_PRECOND_JACOBI, SolveOpts, SolveStats)
+
+__all__ = ["DecError", "Context", "Mesh", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
+           "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL"]
+
+
+class DecError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{_lib.STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+def _ptr(t, dtype, n=None, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A dec_ctx bound to a CUDA device and a torch stream; allocations go through torch."""
+
+    def __init__(self, device=None, stream=None, torch_allocator=True):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        dev_index = self.device.index if self.device.index is not None else 0
+        if torch_allocator:
+            s = self.stream
+
+            def _alloc(size, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(size, dev_index, s)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = _lib.ALLOC_FN(_alloc)
+            self._free = _lib.FREE_FN(_free)
+        else:
+            self._alloc = ctypes.cast(None, _lib.ALLOC_FN)
+            self._free = ctypes.cast(None, _lib.FREE_FN)
+        h = ctypes.c_void_p()
+        rc = self.lib.dec_create(ctypes.byref(h), dev_index, ctypes.c_void_p(self.stream.cuda_stream),
+                                 self._alloc, self._free, None)
+        if rc != 0:
+            raise DecError(rc, "dec_create failed")
+        self.handle = h
+
+    def check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.dec_last_error(self.handle).decode(errors="replace")
+            raise DecError(rc, f"{what}: {msg}")
+        return rc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dec_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mesh(self, xyz, tets):
+        return Mesh(self, xyz, tets)
+
+
+class Mesh:
+    """dec_mesh: topology built from (xyz [V,3] float64, tets [T,4] int32) device tensors."""
+
+    def __init__(self, ctx, xyz, tets):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        V, T = int(xyz.shape[0]), int(tets.shape[0])
+        h = ctypes.c_void_p()
+        rc = self.lib.dec_build_topology(ctx.handle, V, _ptr(xyz, torch.float64, 3 * V, "xyz"), T,
+                                         _ptr(tets, torch.int32, 4 * T, "tets"), ctypes.byref(h))
+        ctx.check(rc, "dec_build_topology")
+        self.handle = h
+        vals = [ctypes.c_int64() for _ in range(6)]
+        ctx.check(self.lib.dec_mesh_info(h, *[ctypes.byref(v) for v in vals]), "dec_mesh_info")
+        self.V, self.T, self.E, self.F, self.F_boundary, self.nnz = (v.value for v in vals)
+
+    @property
+    def dev(self):
+        return self.ctx.device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dec_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def edges(self):
+        out = torch.empty((self.E, 2), dtype=torch.int32, device=self.dev)
+        self.ctx.check(self.lib.dec_get_edges(self.handle, _ptr(out, torch.int32)), "dec_get_edges")
+        return out
+
+    def csr(self, values=True):
+        rp = torch.empty(self.V + 1, dtype=torch.int32, device=self.dev)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=self.dev)
+        v64 = torch.empty(self.nnz, dtype=torch.float64, device=self.dev) if values else None
+        v32 = torch.empty(self.nnz, dtype=torch.float32, device=self.dev) if values else None
+        self.ctx.check(self.lib.dec_get_csr(self.handle, _ptr(rp, torch.int32), _ptr(col, torch.int32),
+                                            _ptr(v64, torch.float64), _ptr(v32, torch.float32)), "dec_get_csr")
+        return rp, col, v64, v32
+
+    def hodge1(self, kappa=None, cracks=None, want_cut=True, want_star=True):
+        n = 0 if cracks is None else int(cracks.shape[0])
+        cut = torch.empty(self.E, dtype=torch.uint8, device=self.dev) if want_cut else None
+        star = torch.empty(self.E, dtype=torch.float64, device=self.dev) if want_star else None
+        rc = self.lib.dec_hodge1(self.handle, _ptr(kappa, torch.float64, self.E, "kappa"), n,
+                                 _ptr(cracks, torch.float64, 7 * n, "cracks") if n else None,
+                                 _ptr(cut, torch.uint8), _ptr(star, torch.float64))
+        self.ctx.check(rc, "dec_hodge1")
+        return cut, star
+
+    def assemble(self):
+        self.ctx.check(self.lib.dec_assemble(self.handle, 0), "dec_assemble")
+
+    def apply_bc(self, bc_type, bc_value, neumann_f0=None, want_rhs=True):
+        npin = ctypes.c_int64()
+        b = torch.empty(self.V, dtype=torch.float64, device=self.dev) if want_rhs else None
+        rc = self.lib.dec_apply_bc(self.handle, _ptr(bc_type, torch.int8, self.V, "bc_type"),
+                                   _ptr(bc_value, torch.float64, self.V, "bc_value"),
+                                   _ptr(neumann_f0, torch.float64, self.V, "neumann_f0"), ctypes.byref(npin),
+                                   _ptr(b, torch.float64))
+        self.ctx.check(rc, "dec_apply_bc")
+        return npin.value, b
+
+    @staticmethod
+    def options(**kw):
+        o = SolveOpts()
+        _lib.load().dec_solve_opts_default(ctypes.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        return o
+
+    def solve(self, T=None, opts=None, check=True, **kw):
+        """Solve the system; returns (T, stats dict, status)."""
+        o = opts if opts is not None else self.options(**kw)
+        if T is None:
+            T = torch.zeros(self.V, dtype=torch.float64, device=self.dev)
+        st = SolveStats()
+        rc = self.lib.dec_solve(self.handle, ctypes.byref(o), _ptr(T, torch.float64, self.V, "T"), ctypes.byref(st))
+        if check:
+            self.ctx.check(rc, "dec_solve")
+        return T, st.as_dict(), rc
+
+    def spmv(self, x, y=None, precision=DEC_PREC_FP64, fmt=DEC_FMT_SELL):
+        dt = torch.float64 if precision == DEC_PREC_FP64 else torch.float32
+        if y is None:
+            y = torch.empty(self.V, dtype=dt, device=self.dev)
+        self.ctx.check(self.lib.dec_spmv(self.handle, precision, fmt, _ptr(x, dt, self.V, "x"), _ptr(y, dt, self.V, "y")),
+                       "dec_spmv")
+        return y
+
+    def fsai(self):
+        nnz = ctypes.c_int64()
+        self.ctx.check(self.lib.dec_get_fsai(self.handle, ctypes.byref(nnz), None, None, None), "dec_get_fsai")
+        ptr = torch.empty(self.V + 1, dtype=torch.int32, device=self.dev)
+        col = torch.empty(nnz.value, dtype=torch.int32, device=self.dev)
+        val = torch.empty(nnz.value, dtype=torch.float64, device=self.dev)
+        self.ctx.check(self.lib.dec_get_fsai(self.handle, ctypes.byref(nnz), _ptr(ptr, torch.int32),
+                                             _ptr(col, torch.int32), _ptr(val, torch.float64)), "dec_get_fsai")
+        return ptr, col, val
+
+    def flux(self, T, side=None, length=1.0, area=1.0, dT=1.0, want_edge_flux=False):
+        vals = [ctypes.c_double() for _ in range(4)]
+        ef = torch.empty(self.E, dtype=torch.float64, device=self.dev) if want_edge_flux else None
+        rc = self.lib.dec_flux_effective_conductivity(
+            self.handle, _ptr(T, torch.float64, self.V, "T"), _ptr(side, torch.int8, self.V, "side"),
+            length, area, dT, *[ctypes.byref(v) for v in vals], _ptr(ef, torch.float64))
+        self.ctx.check(rc, "dec_flux_effective_conductivity")
+        k, qi, qo, en = (v.value for v in vals)
+        return {"k_eff": k, "q_in": qi, "q_out": qo, "energy": en, "edge_flux": ef}

@@ -1,0 +1,263 @@
+// Boundary data (eqs. 3-4 and 12-13 restated for vertex unknowns).
+//
+// * Parts of the mesh that cracks cut off from every Dirichlet vertex
+//   (connected components of the graph of edges with *1 != 0) have no unique
+//   solution; they are found by monotone reachability sweeps from the
+//   Dirichlet set and pinned to T = 0.
+// * Neumann faces load b_v -= f0_v A*_{v,f}, A*_{v,f} the circumcentric
+//   part of boundary face f belonging to vertex v.
+// * Dirichlet and pinned rows/columns are eliminated symmetrically: for a
+//   free row, b_i -= sum_j L_ij T_j over Dirichlet j; fixed rows and columns
+//   become identity rows with b = T0 (or 0 when pinned).  The pattern stays.
+//
+// Compiled without floating-point contraction (fixed operation order).
+#include "common.h"
+
+void refresh_sell_values(dec_mesh* m);
+
+namespace {
+
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 sub(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 scale(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ d3 load3(const double* p) { return {p[0], p[1], p[2]}; }
+
+__device__ d3 tri_circumcentre(d3 p0, d3 p1, d3 p2) {
+    const d3 a = sub(p1, p0), b = sub(p2, p0);
+    const d3 axb = cross(a, b);
+    const double sa = dot(a, a), sb = dot(b, b);
+    const d3 num = cross(sub(scale(sa, b), scale(sb, a)), axb);
+    const double den = 2.0 * dot(axb, axb);
+    return {p0.x + num.x / den, p0.y + num.y / den, p0.z + num.z / den};
+}
+
+__device__ double edge_to_face(d3 pi, d3 pj, d3 pk, d3 cf) {
+    const d3 m = {0.5 * (pi.x + pj.x), 0.5 * (pi.y + pj.y), 0.5 * (pi.z + pj.z)};
+    const d3 e = sub(pj, pi), w = sub(pk, pi);
+    const double f = dot(w, e) / dot(e, e);
+    d3 u = sub(w, scale(f, e));
+    const double nu = sqrt(dot(u, u));
+    u = {u.x / nu, u.y / nu, u.z / nu};
+    return dot(sub(cf, m), u);
+}
+
+__device__ __forceinline__ int vget(const int4& q, int k) {
+    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+}
+
+__global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const double* __restrict__ bc_value,
+                          uint32_t* __restrict__ reach, double* __restrict__ dval, unsigned* __restrict__ err) {
+    GRID_STRIDE_LOOP(v, V) {
+        const int8_t t = bc_type[v];
+        if (t < 0 || t > 2) atomicOr(err, 1u);
+        reach[v] = (t == 1);
+        dval[v] = (t == 1) ? bc_value[v] : 0.0;
+    }
+}
+
+// One monotone sweep: a vertex becomes reached when a neighbour across an
+// edge with *1 != 0 is reached.  Reads may see updates of the same sweep;
+// the fixed point (the set reachable from the Dirichlet vertices) is unique.
+__global__ void k_reach_sweep(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                              const int32_t* __restrict__ nz_edge, const double* __restrict__ star1,
+                              uint32_t* reach, unsigned* changed) {
+    GRID_STRIDE_LOOP(v, V) {
+        if (reach[v]) continue;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t e = nz_edge[k];
+            if (e < 0 || star1[e] == 0.0) continue;
+            if (__hip_atomic_load(reach + col[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(reach + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *changed = 1u;
+                break;
+            }
+        }
+    }
+}
+
+__global__ void k_mark_fixed(int64_t V, const int8_t* __restrict__ bc_type, const uint32_t* __restrict__ reach,
+                             uint8_t* __restrict__ fixed, unsigned long long* __restrict__ n_pinned) {
+    unsigned long long local = 0;
+    GRID_STRIDE_LOOP(v, V) {
+        uint8_t f = 0;
+        if (bc_type[v] == 1)
+            f = 1;
+        else if (!reach[v]) {
+            f = 2;
+            ++local;
+        }
+        fixed[v] = f;
+    }
+    if (local) atomicAdd(n_pinned, local);
+}
+
+// Neumann load g_v = sum over Neumann faces at v (ascending tet, then local
+// face) of f0_v * (v's circumcentric part of the face).
+__constant__ int kFaceV[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+
+__global__ void k_neumann_load(int64_t V, const int8_t* __restrict__ bc_type, const double* __restrict__ f0,
+                               const int4* __restrict__ tets, const uint8_t* __restrict__ bface,
+                               const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_list,
+                               const double* __restrict__ xyz, double* __restrict__ g) {
+    GRID_STRIDE_LOOP(v, V) {
+        double acc = 0.0;
+        if (bc_type[v] == 2) {
+            for (int64_t j = vt_ptr[v]; j < vt_ptr[v + 1]; ++j) {
+                const int t = vt_list[j];
+                const uint8_t mask = bface[t];
+                if (!mask) continue;
+                const int4 q = tets[t];
+                for (int k = 0; k < 4; ++k) {
+                    if (!(mask & (1u << k))) continue;
+                    int verts[3];
+                    int a = -1;
+                    bool ok = true;
+                    for (int r = 0; r < 3; ++r) {
+                        verts[r] = vget(q, kFaceV[k][r]);
+                        const int8_t ty = bc_type[verts[r]];
+                        ok &= (ty == 1 || ty == 2);
+                        if (verts[r] == v) a = r;
+                    }
+                    if (a < 0 || !ok) continue;
+                    const d3 p[3] = {load3(xyz + 3 * (int64_t)verts[0]), load3(xyz + 3 * (int64_t)verts[1]),
+                                     load3(xyz + 3 * (int64_t)verts[2])};
+                    const d3 cf = tri_circumcentre(p[0], p[1], p[2]);
+                    const int b = a == 0 ? 1 : 0;
+                    const int c = a == 2 ? 1 : 2;
+                    const d3 dab = sub(p[b], p[a]), dac = sub(p[c], p[a]);
+                    const double lab = sqrt(dot(dab, dab));
+                    const double lac = sqrt(dot(dac, dac));
+                    const double hab = edge_to_face(p[a], p[b], p[c], cf);
+                    const double hac = edge_to_face(p[a], p[c], p[b], cf);
+                    const double part = 0.5 * (0.5 * lab) * hab + 0.5 * (0.5 * lac) * hac;
+                    acc = acc + f0[v] * part;
+                }
+            }
+        }
+        g[v] = acc;
+    }
+}
+
+// b for free rows: (-g_v) - sum_k L_vk xd_k (all stored entries, ascending);
+// fixed rows: T0 (Dirichlet) or 0 (pinned).
+__global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                      const double* __restrict__ val, const uint8_t* __restrict__ fixed,
+                      const double* __restrict__ dval, const double* __restrict__ g, double* __restrict__ b) {
+    GRID_STRIDE_LOOP(v, V) {
+        const uint8_t f = fixed[v];
+        if (f) {
+            b[v] = (f == 1) ? dval[v] : 0.0;
+            continue;
+        }
+        double acc = 0.0;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) acc += val[k] * dval[col[k]];
+        const double base = g ? (0.0 - g[v]) : 0.0;
+        b[v] = base - acc;
+    }
+}
+
+__global__ void k_eliminate(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const uint8_t* __restrict__ fixed, double* __restrict__ val64, float* __restrict__ val32,
+                            const int32_t* __restrict__ diag_pos, double* __restrict__ inv64,
+                            float* __restrict__ inv32) {
+    GRID_STRIDE_LOOP(v, V) {
+        const bool fv = fixed[v] != 0;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t c = col[k];
+            if (fv || fixed[c]) {
+                const double nv = (c == v && fv) ? 1.0 : 0.0;
+                val64[k] = nv;
+                val32[k] = static_cast<float>(nv);
+            }
+        }
+        const int32_t d = diag_pos[v];
+        inv64[v] = 1.0 / val64[d];
+        inv32[v] = 1.0f / val32[d];
+    }
+}
+
+void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* f0) {
+    dec_ctx* ctx = m->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t V = m->V;
+    DEC_REQUIRE(m->assembled, DEC_ESTATE, "dec_apply_bc needs dec_assemble first");
+    DBuf<unsigned> flags;
+    flags.alloc(ctx, 16);
+    flags.zero();
+    DBuf<uint32_t> reach;
+    reach.alloc(ctx, V);
+    m->bc_value.alloc(ctx, V);
+    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, bc_value, reach.p,
+                       m->bc_value.p, flags.p);
+    HIP_CHECK(hipGetLastError());
+    unsigned e0 = *static_cast<unsigned*>(ctx->readback(flags.p, sizeof(unsigned)));
+    DEC_REQUIRE(e0 == 0, DEC_EINVAL, "bc_type must be 0, 1 or 2");
+
+    // reachability from the Dirichlet set, 8 sweeps per host check; stop
+    // after a batch whose last sweep changed nothing
+    const unsigned g = grid_for(V);
+    for (int batch = 0;; ++batch) {
+        DEC_REQUIRE(batch < (int)(V / 8 + 16), DEC_EINVAL, "reachability did not settle");
+        HIP_CHECK(hipMemsetAsync(flags.p + 1, 0, 8 * sizeof(unsigned), s));
+        for (int k = 0; k < 8; ++k)
+            hipLaunchKernelGGL(k_reach_sweep, dim3(g), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
+                               m->star1.p, reach.p, flags.p + 1 + k);
+        HIP_CHECK(hipGetLastError());
+        unsigned ch[8];
+        std::memcpy(ch, ctx->readback(flags.p + 1, sizeof(ch)), sizeof(ch));
+        if (ch[7] == 0) break;
+    }
+    m->fixed.alloc(ctx, V);
+    DBuf<unsigned long long> npin;
+    npin.alloc(ctx, 1);
+    npin.zero();
+    hipLaunchKernelGGL(k_mark_fixed, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, reach.p, m->fixed.p, npin.p);
+    DBuf<double> gload;
+    if (f0) {
+        gload.alloc(ctx, V);
+        hipLaunchKernelGGL(k_neumann_load, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, f0,
+                           reinterpret_cast<const int4*>(m->tets.p), m->tet_bface.p, m->vt_ptr.p, m->vt_list.p,
+                           m->xyz.p, gload.p);
+    }
+    m->rhs.alloc(ctx, V);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->val64.p,
+                       m->fixed.p, m->bc_value.p, f0 ? gload.p : nullptr, m->rhs.p);
+    m->invdiag64.alloc(ctx, V);
+    m->invdiag32.alloc(ctx, V);
+    hipLaunchKernelGGL(k_eliminate, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->fixed.p,
+                       m->val64.p, m->val32.p, m->diag_pos.p, m->invdiag64.p, m->invdiag32.p);
+    HIP_CHECK(hipGetLastError());
+    refresh_sell_values(m);
+    m->n_pinned = (int64_t) * static_cast<unsigned long long*>(ctx->readback(npin.p, sizeof(unsigned long long)));
+    m->bc_ready = true;
+    m->fsai.ready = false;
+}
+
+}  // namespace
+
+void apply_bc_internal(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* f0) {
+    apply_bc_device(m, bc_type, bc_value, f0);
+}
+
+extern "C" int dec_apply_bc(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* neumann_f0,
+                            int64_t* n_pinned_out, double* b_out) {
+    if (!m) return DEC_EINVAL;
+    try {
+        DEC_REQUIRE(bc_type && bc_value, DEC_EINVAL, "NULL bc_type or bc_value");
+        m->ctx->set_device();
+        apply_bc_device(m, bc_type, bc_value, neumann_f0);
+        if (n_pinned_out) *n_pinned_out = m->n_pinned;
+        if (b_out)
+            HIP_CHECK(hipMemcpyAsync(b_out, m->rhs.p, m->V * sizeof(double), hipMemcpyDeviceToDevice, m->ctx->stream));
+    } catch (const DecError& e) {
+        m->ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}

@@ -1,0 +1,246 @@
+// Internal runtime of the DEC library: context, device buffers, the mesh
+// object, error handling and the device-side reduction/scan building blocks
+// shared by the kernels.  Nothing here is visible through the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "dec.h"
+
+// ---------------------------------------------------------------- errors
+struct DecError {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] inline void dec_fail(int code, const std::string& msg) { throw DecError{code, msg}; }
+
+#define HIP_CHECK(expr)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            dec_fail(DEC_EHIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define DEC_REQUIRE(cond, code, msg) \
+    do {                             \
+        if (!(cond)) dec_fail((code), (msg)); \
+    } while (0)
+
+// ---------------------------------------------------------------- context
+struct dec_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    dec_alloc_fn alloc = nullptr;
+    dec_free_fn free_fn = nullptr;
+    void* user = nullptr;
+    std::string last_error;
+    int num_cus = 256;
+    int num_xcds = 8;
+    // small pinned staging area for scalar read-backs
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    void* dalloc(size_t bytes);
+    void dfree(void* p);
+    void set_device() const { HIP_CHECK(hipSetDevice(device)); }
+    void sync() const { HIP_CHECK(hipStreamSynchronize(stream)); }
+    // copy `bytes` from device to the pinned area and wait; returns the pinned pointer
+    void* readback(const void* dptr, size_t bytes);
+};
+
+// Device buffer owned through the context's allocator.
+template <class T>
+struct DBuf {
+    dec_ctx* ctx = nullptr;
+    T* p = nullptr;
+    size_t n = 0;
+
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept { swap(o); }
+    DBuf& operator=(DBuf&& o) noexcept {
+        release();
+        swap(o);
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void swap(DBuf& o) noexcept {
+        std::swap(ctx, o.ctx);
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+    }
+    void alloc(dec_ctx* c, size_t count) {
+        if (p && n >= count && ctx == c) return;
+        release();
+        ctx = c;
+        n = count;
+        p = count ? static_cast<T*>(c->dalloc(count * sizeof(T))) : nullptr;
+    }
+    void release() {
+        if (p && ctx) ctx->dfree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    void zero() const {
+        if (p) HIP_CHECK(hipMemsetAsync(p, 0, n * sizeof(T), ctx->stream));
+    }
+};
+
+// ---------------------------------------------------------------- matrices
+// Sliced ELLPACK with slice height SELL_C (one row per lane of a wavefront),
+// entries stored column-major inside a slice: entry j of row r of slice s is
+// at ptr[s] + j * SELL_C + (r - s * SELL_C).  Padding entries repeat the row's
+// own column with value 0.
+constexpr int SELL_C = 64;
+
+struct SellMatrix {
+    int64_t nslices = 0;
+    int64_t entries = 0;
+    DBuf<int64_t> ptr;   // [nslices + 1]
+    DBuf<int32_t> col;   // [entries]
+    DBuf<int32_t> src;   // [entries]: CSR entry index, -1 for padding
+    DBuf<double> val64;  // [entries]
+    DBuf<float> val32;   // [entries]
+};
+
+// Lower-triangular FSAI factor G (CSR) and its transpose (CSR of G^T).
+struct FsaiFactor {
+    bool ready = false;
+    int64_t nnz = 0;
+    DBuf<int32_t> g_ptr, g_col, gt_ptr, gt_col, gt_src;
+    DBuf<double> g_val64, gt_val64;
+    DBuf<float> g_val32, gt_val32;
+};
+
+struct SolveCache;  // Krylov vectors, reduction scratch and captured graphs
+
+// ---------------------------------------------------------------- mesh
+struct dec_mesh {
+    dec_ctx* ctx = nullptr;
+    int64_t V = 0, T = 0, E = 0, F = 0, Fb = 0, nnz = 0;
+
+    DBuf<double> xyz;        // [V*3]
+    DBuf<int32_t> tets;      // [T*4]
+    DBuf<int64_t> vt_ptr;    // [V+1]   vertex -> tets (ascending)
+    DBuf<int32_t> vt_list;   // [4T]
+    DBuf<int32_t> edges;     // [E*2]   (lo, hi), lexicographic
+    DBuf<int64_t> up_ptr;    // [V+1]   edges with lo = v are up_ptr[v] .. up_ptr[v+1]-1
+    DBuf<int64_t> et_ptr;    // [E+1]   edge -> (tet*6 + local edge), ascending tet
+    DBuf<int32_t> et_inc;    // [6T]
+    DBuf<uint8_t> tet_bface; // [T]     bit k: face opposite local vertex k is on the boundary
+
+    // CSR pattern of L (static) and values
+    DBuf<int32_t> row_ptr;   // [V+1]
+    DBuf<int32_t> col;       // [nnz]
+    DBuf<int32_t> nz_edge;   // [nnz]  edge of the entry, -1 on the diagonal
+    DBuf<int32_t> diag_pos;  // [V]
+    DBuf<double> val64;      // [nnz]
+    DBuf<float> val32;       // [nnz]
+    SellMatrix sell;
+
+    // Hodge star
+    bool geo_ready = false;
+    DBuf<double> geo;        // [E]  |*e| / |e| after the snap
+    DBuf<double> star1;      // [E]
+    DBuf<uint8_t> cut;       // [E]
+    bool star_ready = false;
+    bool assembled = false;
+
+    // boundary data
+    bool bc_ready = false;
+    DBuf<uint8_t> fixed;     // [V] 1 Dirichlet, 2 pinned, 0 free
+    DBuf<double> rhs;        // [V]
+    DBuf<double> bc_value;   // [V] Dirichlet values (0 elsewhere)
+    DBuf<double> invdiag64;  // [V]
+    DBuf<float> invdiag32;   // [V]
+    int64_t n_pinned = 0;
+
+    FsaiFactor fsai;
+    SolveCache* solve = nullptr;
+
+    ~dec_mesh();
+};
+
+// ---------------------------------------------------------------- launch helpers
+constexpr int BLOCK = 256;
+
+inline unsigned grid_for(int64_t n, int block = BLOCK, int64_t cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return static_cast<unsigned>(g);
+}
+
+#define GRID_STRIDE_LOOP(i, n)                                                     \
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; \
+         i < (n); i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+
+// ---------------------------------------------------------------- device reductions
+// Butterfly sum across a 64-lane wavefront (fixed pattern: deterministic).
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a block of BLOCK threads; the result is valid in thread 0.
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int w = 0; w < nw; ++w) r += lds[w];
+    }
+    return r;
+}
+
+// Called by every thread of a block after thread 0 has stored the block's
+// partial results.  Returns true in the block that finishes last; its loads
+// after this point see every other block's partials.
+__device__ __forceinline__ bool last_block_arrived(unsigned* counter) {
+    __shared__ int am_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        am_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (am_last) __threadfence();
+    return am_last != 0;
+}
+
+template <class T>
+__device__ __forceinline__ T coherent_load(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic sum of `n` partials by one block (fixed order, independent
+// of which block arrived last).  Result valid in thread 0.
+template <class T>
+__device__ __forceinline__ T reduce_partials(const T* partials, int n, T* lds) {
+    T acc = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += coherent_load(partials + i);
+    return block_sum(acc, lds);
+}
+
+// ---------------------------------------------------------------- host primitives
+// out[0] = 0, out[i+1] = in[0] + ... + in[i]; returns out[n] (synchronises) when want_total.
+int64_t scan_exclusive_i32_to_i64(dec_ctx* ctx, const int32_t* in, int64_t* out, int64_t n,
+                                  bool want_total);
+void copy_i64_to_i32(dec_ctx* ctx, const int64_t* in, int32_t* out, int64_t n);

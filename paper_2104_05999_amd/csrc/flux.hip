@@ -1,0 +1,98 @@
+// Heat flux and effective conductivity (Section 2.5): with T fixed on two
+// opposite faces, the effective conductivity equals the flux density through
+// either Dirichlet face.  (L T)_v over the operator before boundary
+// elimination is the heat leaving v's dual cell, so
+//     Q_in = sum over inflow-face vertices of (L T)_v,
+//     Q_out = -sum over outflow-face vertices of (L T)_v,
+// and the dissipated energy E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at
+// the exact solution; k_eff = E length / (area dT^2).  One pass over the
+// rows, deterministic block partials.
+#include "solver.h"
+
+namespace {
+
+__global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, const int32_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
+                                                const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
+                                                const double* __restrict__ star1, const double* __restrict__ T,
+                                                const int8_t* __restrict__ side, double* __restrict__ edge_flux,
+                                                double* __restrict__ partials, double* __restrict__ out,
+                                                unsigned* __restrict__ counter) {
+    __shared__ double lds[BLOCK / 64];
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    double qin = 0.0, qout = 0.0, en = 0.0;
+    for (int64_t v = i0 + threadIdx.x; v < i1; v += BLOCK) {
+        const double tv = T[v];
+        double o = 0.0;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t e = nz_edge[k];
+            if (e < 0) continue;
+            o += star1[e] * (tv - T[col[k]]);
+        }
+        const int8_t sd = side ? side[v] : 0;
+        if (sd == 1) qin += o;
+        if (sd == 2) qout -= o;
+        for (int64_t e = up_ptr[v]; e < up_ptr[v + 1]; ++e) {
+            const double d = T[edges[2 * e + 1]] - tv;
+            en += star1[e] * d * d;
+            if (edge_flux) edge_flux[e] = star1[e] * (tv - T[edges[2 * e + 1]]);
+        }
+    }
+    const int G = gridDim.x;
+    const double a = block_sum(qin, lds);
+    const double b = block_sum(qout, lds);
+    const double c = block_sum(en, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = a;
+        partials[G + blockIdx.x] = b;
+        partials[2 * G + blockIdx.x] = c;
+    }
+    if (last_block_arrived(counter)) {
+        const double ta = reduce_partials(partials, G, lds);
+        const double tb = reduce_partials(partials + G, G, lds);
+        const double tc = reduce_partials(partials + 2 * G, G, lds);
+        if (threadIdx.x == 0) {
+            out[0] = ta;
+            out[1] = tb;
+            out[2] = tc;
+            *counter = 0;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* side, double length,
+                                               double area, double dT, double* k_eff, double* q_in, double* q_out,
+                                               double* energy, double* edge_flux_out) {
+    if (!m || !T) return DEC_EINVAL;
+    dec_ctx* ctx = m->ctx;
+    try {
+        DEC_REQUIRE(m->star_ready, DEC_ESTATE, "flux needs dec_hodge1 first");
+        DEC_REQUIRE(area > 0.0 && length > 0.0 && dT != 0.0, DEC_EINVAL, "bad length/area/dT");
+        ctx->set_device();
+        int64_t G = 8 * (int64_t)ctx->num_cus;
+        const int64_t want = ((m->V + BLOCK - 1) / BLOCK + 7) / 8 * 8;
+        if (want < G) G = want;
+        DBuf<double> part, out;
+        part.alloc(ctx, 3 * G);
+        out.alloc(ctx, 4);
+        DBuf<unsigned> counter;
+        counter.alloc(ctx, 1);
+        counter.zero();
+        hipLaunchKernelGGL(k_flux, dim3(G), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p, m->col.p, m->nz_edge.p,
+                           m->up_ptr.p, m->edges.p, m->star1.p, T, side, edge_flux_out, part.p, out.p, counter.p);
+        HIP_CHECK(hipGetLastError());
+        double h[3];
+        std::memcpy(h, ctx->readback(out.p, sizeof(h)), sizeof(h));
+        if (q_in) *q_in = h[0];
+        if (q_out) *q_out = h[1];
+        if (energy) *energy = h[2];
+        if (k_eff) *k_eff = h[2] * length / (area * dT * dT);
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}

@@ -1,0 +1,206 @@
+// Circumcentric Hodge star *1 with conductivity and cracks (Sections 2.1, 2.5).
+//
+// Geometry (once per mesh): every tet computes the signed area of the part
+// of each of its six edges' dual 2-cells that it holds -- the planar
+// quadrilateral (edge midpoint, circumcentre of face 1, tet circumcentre,
+// circumcentre of face 2) in the edge's bisector plane -- then every edge
+// gathers its pieces in ascending tet order (no atomics), snaps near-zero
+// areas (|*e| <= 1e-12 |e|^2) to zero and stores |*e| / |e|.
+//
+// Per call: the crack predicate marks the edges whose segment passes
+// through a penny disc, and *1_e = kappa_e * (|*e| / |e|), zero when cut.
+//
+// This file is compiled without floating-point contraction and follows a
+// fixed operation order, so that integer decisions taken from floating
+// point (the cut mask, the snap) match an FP64 reference evaluated in the
+// same order.
+#include "common.h"
+
+namespace {
+
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 sub(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 scale(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ d3 load3(const double* p) { return {p[0], p[1], p[2]}; }
+
+// c_T = p0 + (|a|^2 (b x c) + |b|^2 (c x a) + |c|^2 (a x b)) / (2 a.(b x c))
+__device__ d3 tet_circumcentre(d3 p0, d3 p1, d3 p2, d3 p3) {
+    const d3 a = sub(p1, p0), b = sub(p2, p0), c = sub(p3, p0);
+    const d3 bc = cross(b, c), ca = cross(c, a), ab = cross(a, b);
+    const double sa = dot(a, a), sb = dot(b, b), sc = dot(c, c);
+    const d3 num = {(sa * bc.x + sb * ca.x) + sc * ab.x, (sa * bc.y + sb * ca.y) + sc * ab.y,
+                    (sa * bc.z + sb * ca.z) + sc * ab.z};
+    const double den = 2.0 * dot(a, bc);
+    return {p0.x + num.x / den, p0.y + num.y / den, p0.z + num.z / den};
+}
+
+// c_f = p0 + ((|a|^2 b - |b|^2 a) x (a x b)) / (2 |a x b|^2)
+__device__ d3 tri_circumcentre(d3 p0, d3 p1, d3 p2) {
+    const d3 a = sub(p1, p0), b = sub(p2, p0);
+    const d3 axb = cross(a, b);
+    const double sa = dot(a, a), sb = dot(b, b);
+    const d3 w = sub(scale(sa, b), scale(sb, a));
+    const d3 num = cross(w, axb);
+    const double den = 2.0 * dot(axb, axb);
+    return {p0.x + num.x / den, p0.y + num.y / den, p0.z + num.z / den};
+}
+
+// signed in-plane distance from the midpoint of (pi, pj) to cf, positive toward pk
+__device__ double edge_to_face(d3 pi, d3 pj, d3 pk, d3 cf) {
+    const d3 m = {0.5 * (pi.x + pj.x), 0.5 * (pi.y + pj.y), 0.5 * (pi.z + pj.z)};
+    const d3 e = sub(pj, pi), w = sub(pk, pi);
+    const double f = dot(w, e) / dot(e, e);
+    d3 u = sub(w, scale(f, e));
+    const double nu = sqrt(dot(u, u));
+    u = {u.x / nu, u.y / nu, u.z / nu};
+    return dot(sub(cf, m), u);
+}
+
+// signed distance from cf to ct along the normal of (pi, pj, pk), positive toward pl
+__device__ double face_to_tet(d3 pi, d3 pj, d3 pk, d3 pl, d3 cf, d3 ct) {
+    d3 n = cross(sub(pj, pi), sub(pk, pi));
+    const double sgn = dot(n, sub(pl, pi)) < 0.0 ? -1.0 : 1.0;
+    const double f = sgn / sqrt(dot(n, n));
+    n = scale(f, n);
+    return dot(sub(ct, cf), n);
+}
+
+__constant__ int kEdgeI[6] = {0, 0, 0, 1, 1, 2};
+__constant__ int kEdgeJ[6] = {1, 2, 3, 2, 3, 3};
+__constant__ int kEdgeK[6] = {2, 1, 1, 0, 0, 0};
+__constant__ int kEdgeL[6] = {3, 3, 2, 3, 2, 1};
+
+__global__ void k_elementary_areas(int64_t T, const int32_t* __restrict__ tets, const double* __restrict__ xyz,
+                                   double* __restrict__ elem) {
+    GRID_STRIDE_LOOP(t, T) {
+        const int4 q = reinterpret_cast<const int4*>(tets)[t];
+        d3 p[4] = {load3(xyz + 3 * (int64_t)q.x), load3(xyz + 3 * (int64_t)q.y), load3(xyz + 3 * (int64_t)q.z),
+                   load3(xyz + 3 * (int64_t)q.w)};
+        const d3 ct = tet_circumcentre(p[0], p[1], p[2], p[3]);
+        for (int e = 0; e < 6; ++e) {
+            const d3 pi = p[kEdgeI[e]], pj = p[kEdgeJ[e]], pk = p[kEdgeK[e]], pl = p[kEdgeL[e]];
+            const d3 cf1 = tri_circumcentre(pi, pj, pk);
+            const d3 cf2 = tri_circumcentre(pi, pj, pl);
+            const double t1 = edge_to_face(pi, pj, pk, cf1) * face_to_tet(pi, pj, pk, pl, cf1, ct);
+            const double t2 = edge_to_face(pi, pj, pl, cf2) * face_to_tet(pi, pj, pl, pk, cf2, ct);
+            elem[6 * t + e] = 0.5 * (t1 + t2);
+        }
+    }
+}
+
+// |*e| in ascending tet order, snapped, over |e|
+__global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
+                                const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
+                                const double* __restrict__ elem, double* __restrict__ geo) {
+    GRID_STRIDE_LOOP(e, E) {
+        double area = 0.0;
+        for (int64_t k = et_ptr[e]; k < et_ptr[e + 1]; ++k) area += elem[et_inc[k]];
+        const d3 d = sub(load3(xyz + 3 * (int64_t)edges[2 * e + 1]), load3(xyz + 3 * (int64_t)edges[2 * e]));
+        const double len = sqrt(dot(d, d));
+        if (fabs(area) <= 1e-12 * len * len) area = 0.0;
+        geo[e] = area / len;
+    }
+}
+
+constexpr int kMaxDiscsLds = 256;  // 256 * 7 doubles = 14 KiB of LDS per block
+
+__global__ void k_crack_cut(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
+                            int32_t n_discs, const double* __restrict__ discs, uint8_t* __restrict__ cut) {
+    __shared__ double sd[kMaxDiscsLds * 7];
+    for (int32_t base = 0; base < n_discs || base == 0; base += kMaxDiscsLds) {
+        const int32_t nd = min(kMaxDiscsLds, n_discs - base);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nd * 7; i += blockDim.x) sd[i] = discs[(int64_t)base * 7 + i];
+        __syncthreads();
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
+             e += (int64_t)gridDim.x * blockDim.x) {
+            const d3 p0 = load3(xyz + 3 * (int64_t)edges[2 * e]);
+            const d3 p1 = load3(xyz + 3 * (int64_t)edges[2 * e + 1]);
+            uint8_t hit = base == 0 ? 0 : cut[e];
+            for (int i = 0; i < nd && !hit; ++i) {
+                const double* d = sd + 7 * i;
+                const double cx = d[0], cy = d[1], cz = d[2], nx = d[3], ny = d[4], nz = d[5], r = d[6];
+                const double s0 = ((p0.x - cx) * nx + (p0.y - cy) * ny) + (p0.z - cz) * nz;
+                const double s1 = ((p1.x - cx) * nx + (p1.y - cy) * ny) + (p1.z - cz) * nz;
+                if ((s0 < 0.0) == (s1 < 0.0)) continue;
+                const double t = s0 / (s0 - s1);
+                const double qx = p0.x + t * (p1.x - p0.x);
+                const double qy = p0.y + t * (p1.y - p0.y);
+                const double qz = p0.z + t * (p1.z - p0.z);
+                const double d2 = ((qx - cx) * (qx - cx) + (qy - cy) * (qy - cy)) + (qz - cz) * (qz - cz);
+                if (d2 <= r * r) hit = 1;
+            }
+            cut[e] = hit;
+        }
+        if (n_discs == 0) break;
+    }
+}
+
+__global__ void k_star1(int64_t E, const double* __restrict__ geo, const double* __restrict__ kappa,
+                        const uint8_t* __restrict__ cut, double* __restrict__ star1) {
+    GRID_STRIDE_LOOP(e, E) {
+        const double k = kappa ? kappa[e] : 1.0;
+        star1[e] = cut[e] ? 0.0 : k * geo[e];
+    }
+}
+
+void ensure_geometry(dec_mesh* m) {
+    if (m->geo_ready) return;
+    dec_ctx* ctx = m->ctx;
+    DBuf<double> elem;
+    elem.alloc(ctx, 6 * m->T);
+    hipLaunchKernelGGL(k_elementary_areas, dim3(grid_for(m->T)), dim3(BLOCK), 0, ctx->stream, m->T, m->tets.p,
+                       m->xyz.p, elem.p);
+    m->geo.alloc(ctx, m->E);
+    hipLaunchKernelGGL(k_edge_geometry, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
+                       m->xyz.p, m->et_ptr.p, m->et_inc.p, elem.p, m->geo.p);
+    HIP_CHECK(hipGetLastError());
+    ctx->sync();  // elem is released on return
+    m->geo_ready = true;
+}
+
+}  // namespace
+
+// Used by the crack-growth and serving paths as well as dec_hodge1.
+void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const double* cracks) {
+    dec_ctx* ctx = m->ctx;
+    ensure_geometry(m);
+    m->cut.alloc(ctx, m->E);
+    m->star1.alloc(ctx, m->E);
+    const unsigned g = grid_for(m->E, BLOCK, 8 * (int64_t)ctx->num_cus);
+    hipLaunchKernelGGL(k_crack_cut, dim3(g), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p, m->xyz.p,
+                       n_cracks, cracks, m->cut.p);
+    hipLaunchKernelGGL(k_star1, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->geo.p, kappa,
+                       m->cut.p, m->star1.p);
+    HIP_CHECK(hipGetLastError());
+    m->star_ready = true;
+    m->assembled = false;
+    m->bc_ready = false;
+}
+
+extern "C" int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, const double* cracks,
+                          uint8_t* cut_out, double* star1_out) {
+    if (!m) return DEC_EINVAL;
+    dec_ctx* ctx = m->ctx;
+    try {
+        DEC_REQUIRE(n_cracks >= 0, DEC_EINVAL, "negative crack count");
+        DEC_REQUIRE(n_cracks == 0 || cracks, DEC_EINVAL, "NULL crack array");
+        ctx->set_device();
+        hodge1_device(m, kappa, n_cracks, cracks);
+        if (cut_out)
+            HIP_CHECK(hipMemcpyAsync(cut_out, m->cut.p, m->E, hipMemcpyDeviceToDevice, ctx->stream));
+        if (star1_out)
+            HIP_CHECK(hipMemcpyAsync(star1_out, m->star1.p, m->E * sizeof(double), hipMemcpyDeviceToDevice,
+                                     ctx->stream));
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}

@@ -1,0 +1,755 @@
+// Preconditioned conjugate gradients on the DEC system, FP64 and FP32, and
+// FP64 iterative refinement around FP32 inner solves.
+//
+// The paper solves its system with PETSc (Section 2.3); the vertex system
+// A T = b here is symmetric positive definite, so the recurrence is the
+// textbook PCG (Hestenes-Stiefel; Saad, Algorithm 9.1):
+//     q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;
+//     z = M^-1 r; rho' = r.z; beta = rho'/rho; p = z + beta p.
+// One iteration is three fused kernels with Jacobi (SpMV + p.q; updates +
+// z + r.z + r.r; p update) or five with FSAI (two more for z = G^T (G r)).
+// Every reduction is a fixed-shape block tree followed by a fixed-order sum
+// of per-block partials in the block that arrives last, so results do not
+// depend on scheduling.  Scalars stay on the device; the host launches
+// batches of iterations (optionally a captured hipGraph) and reads the
+// state once per batch.
+#include <cmath>
+
+#include "solver.h"
+
+namespace {
+
+enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
+
+// ---------------------------------------------------------------- SpMV kernels
+template <class VT, int MODE, int U>
+__global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
+                                                const VT* __restrict__ b, double* __restrict__ partials,
+                                                PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    if (MODE == MODE_DOT && st->done) return;
+    int64_t s0, s1;
+    block_range(A.nslices, &s0, &s1);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    VT d = 0;
+    for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+        const int64_t base = A.ptr[s];
+        const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
+        const int64_t row = s * SELL_C + lane;
+        const VT acc = sell_row<VT, U>(A, base, width, lane, x);
+        if (row < A.V) {
+            if (MODE == MODE_RESID) {
+                const VT ri = b[row] - acc;
+                y[row] = ri;
+                d += ri * ri;
+            } else {
+                y[row] = acc;
+                if (MODE == MODE_DOT) d += x[row] * acc;
+            }
+        }
+    }
+    if (MODE == MODE_PLAIN) return;
+    const double bs = block_sum(static_cast<double>(d), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_arrived(&st->counter)) {
+        const double tot = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            if (MODE == MODE_DOT) {
+                st->pq = tot;
+                if (!(tot > 0.0) || !isfinite(tot))
+                    st->done = PCG_BREAKDOWN;
+                else
+                    st->alpha = st->rho / tot;
+            } else {
+                st->rr = tot;
+                st->aux = tot;
+            }
+            st->counter = 0;
+        }
+    }
+}
+
+template <class VT>
+__global__ void k_csr_plain(CsrView<VT> A, const VT* __restrict__ x, VT* __restrict__ y) {
+    GRID_STRIDE_LOOP(row, A.V) y[row] = csr_row(A, row, x);
+}
+
+// ---------------------------------------------------------------- vector kernels
+// b.b into st->aux (and rr_stop = tol2 * b.b)
+__global__ void k_norm2(int64_t V, const double* __restrict__ b, double tol2, double* __restrict__ partials,
+                        PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) s += b[i] * b[i];
+    const double bs = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_arrived(&st->counter)) {
+        const double tot = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            st->aux = tot;
+            st->rr_stop = tol2 * tot;
+            st->counter = 0;
+        }
+    }
+}
+
+__global__ void k_reset(PcgScalars* st, int64_t max_iter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->iter = 0;
+        st->max_iter = max_iter;
+        st->done = PCG_RUNNING;
+        st->counter = 0;
+        st->rho = st->pq = st->alpha = st->beta = 0.0;
+    }
+}
+
+// x0: Dirichlet values on Dirichlet rows, 0 on pinned rows, the warm start
+// (or 0) elsewhere
+__global__ void k_init_x(int64_t V, const uint8_t* __restrict__ fixed, const double* __restrict__ dval,
+                         const double* __restrict__ warm, double* __restrict__ x) {
+    GRID_STRIDE_LOOP(i, V) {
+        const uint8_t f = fixed[i];
+        x[i] = f == 1 ? dval[i] : (f == 2 ? 0.0 : (warm ? warm[i] : 0.0));
+    }
+}
+
+// Jacobi start: z = D^-1 r, p = z, rho = r.z; rr_stop = factor * (relative ? r.r : rr_stop_base)
+template <class VT>
+__global__ void k_init_jacobi(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd, VT* __restrict__ p,
+                              double stop_factor, int relative, double* __restrict__ partials,
+                              PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    VT rz = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const VT ri = r[i];
+        const VT z = invd[i] * ri;
+        p[i] = z;
+        rz += ri * z;
+    }
+    const double bs = block_sum(static_cast<double>(rz), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_arrived(&st->counter)) {
+        const double tot = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            st->rho = tot;
+            if (relative) st->rr_stop = stop_factor * st->rr;
+            st->iter = 0;
+            st->done = (st->rr <= st->rr_stop) ? PCG_CONVERGED : PCG_RUNNING;
+            st->counter = 0;
+        }
+    }
+}
+
+// Jacobi iteration, part 2: x += alpha p, r -= alpha q, z = D^-1 r, r.z, r.r;
+// the last block decides convergence and forms beta.
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_update_jacobi(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
+                                                         const VT* __restrict__ p, const VT* __restrict__ q,
+                                                         const VT* __restrict__ invd, double* __restrict__ partials,
+                                                         PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    if (st->done) return;
+    const VT a = static_cast<VT>(st->alpha);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    VT rz = 0, rr = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const VT xi = x[i] + a * p[i];
+        const VT ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        rz += ri * (invd[i] * ri);
+        rr += ri * ri;
+    }
+    const int G = gridDim.x;
+    const double b1 = block_sum(static_cast<double>(rz), lds);
+    const double b2 = block_sum(static_cast<double>(rr), lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = b1;
+        partials[G + blockIdx.x] = b2;
+    }
+    if (last_block_arrived(&st->counter)) {
+        const double trz = reduce_partials(partials, G, lds);
+        const double trr = reduce_partials(partials + G, G, lds);
+        if (threadIdx.x == 0) {
+            st->rr = trr;
+            st->iter += 1;
+            if (!isfinite(trz) || !isfinite(trr))
+                st->done = PCG_BREAKDOWN;
+            else if (trr <= st->rr_stop)
+                st->done = PCG_CONVERGED;
+            else if (st->iter >= st->max_iter)
+                st->done = PCG_MAXITER;
+            else {
+                st->beta = trz / st->rho;
+                st->rho = trz;
+            }
+            st->counter = 0;
+        }
+    }
+}
+
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_p_jacobi(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
+                                                    VT* __restrict__ p, const PcgScalars* __restrict__ st) {
+    if (st->done) return;
+    const VT beta = static_cast<VT>(st->beta);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) p[i] = invd[i] * r[i] + beta * p[i];
+}
+
+// FSAI iteration, part 2: x += alpha p, r -= alpha q, r.r and the convergence test
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_update_plain(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
+                                                        const VT* __restrict__ p, const VT* __restrict__ q,
+                                                        double* __restrict__ partials, PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    if (st->done) return;
+    const VT a = static_cast<VT>(st->alpha);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    VT rr = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const VT xi = x[i] + a * p[i];
+        const VT ri = r[i] - a * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        rr += ri * ri;
+    }
+    const double b2 = block_sum(static_cast<double>(rr), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b2;
+    if (last_block_arrived(&st->counter)) {
+        const double trr = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            st->rr = trr;
+            st->iter += 1;
+            if (!isfinite(trr))
+                st->done = PCG_BREAKDOWN;
+            else if (trr <= st->rr_stop)
+                st->done = PCG_CONVERGED;
+            else if (st->iter >= st->max_iter)
+                st->done = PCG_MAXITER;
+            st->counter = 0;
+        }
+    }
+}
+
+// w = G r (rows of the lower-triangular factor)
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_fsai_g(CsrView<VT> G, const VT* __restrict__ r, VT* __restrict__ w,
+                                                  const PcgScalars* __restrict__ st) {
+    if (st->done) return;
+    int64_t i0, i1;
+    block_range(G.V, &i0, &i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) w[i] = csr_row(G, i, r);
+}
+
+// z = G^T w and r.z.  init: p = z, rho = r.z, convergence test on the
+// current rr; iteration: beta = r.z / rho, rho = r.z.
+template <class VT, bool INIT>
+__global__ __launch_bounds__(BLOCK) void k_fsai_gt(CsrView<VT> GT, const VT* __restrict__ w, VT* __restrict__ z,
+                                                   const VT* __restrict__ r, VT* __restrict__ p, double stop_factor,
+                                                   int relative, double* __restrict__ partials,
+                                                   PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64];
+    if (!INIT && st->done) return;
+    int64_t i0, i1;
+    block_range(GT.V, &i0, &i1);
+    VT rz = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const VT zi = csr_row(GT, i, w);
+        if (INIT)
+            p[i] = zi;
+        else
+            z[i] = zi;
+        rz += r[i] * zi;
+    }
+    const double bs = block_sum(static_cast<double>(rz), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_arrived(&st->counter)) {
+        const double tot = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            if (INIT) {
+                st->rho = tot;
+                if (relative) st->rr_stop = stop_factor * st->rr;
+                st->iter = 0;
+                st->done = (st->rr <= st->rr_stop) ? PCG_CONVERGED : PCG_RUNNING;
+            } else {
+                if (!isfinite(tot)) st->done = PCG_BREAKDOWN;
+                st->beta = tot / st->rho;
+                st->rho = tot;
+            }
+            st->counter = 0;
+        }
+    }
+}
+
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_p_plain(int64_t V, const VT* __restrict__ z, VT* __restrict__ p,
+                                                   const PcgScalars* __restrict__ st) {
+    if (st->done) return;
+    const VT beta = static_cast<VT>(st->beta);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) p[i] = z[i] + beta * p[i];
+}
+
+// ---------------------------------------------------------------- refinement kernels
+// r32 = r64 / ||r64|| (||r64||^2 in src->rr), x32 = 0, r32.r32 into dst->rr
+__global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgScalars* __restrict__ src,
+                         float* __restrict__ r32, float* __restrict__ x32, double* __restrict__ partials,
+                         PcgScalars* __restrict__ dst) {
+    __shared__ double lds[BLOCK / 64];
+    const double inv = 1.0 / sqrt(src->rr);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    float s = 0.0f;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const float ri = static_cast<float>(r64[i] * inv);
+        r32[i] = ri;
+        x32[i] = 0.0f;
+        s += ri * ri;
+    }
+    const double bs = block_sum(static_cast<double>(s), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block_arrived(&dst->counter)) {
+        const double tot = reduce_partials(partials, gridDim.x, lds);
+        if (threadIdx.x == 0) {
+            dst->rr = tot;
+            dst->counter = 0;
+        }
+    }
+}
+
+// x64 += ||r64|| * x32
+__global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __restrict__ x32,
+                          const PcgScalars* __restrict__ src) {
+    const double scale = sqrt(src->rr);
+    GRID_STRIDE_LOOP(i, V) x64[i] = x64[i] + scale * static_cast<double>(x32[i]);
+}
+
+// ---------------------------------------------------------------- host driver
+template <class VT>
+struct Run {
+    SellView<VT> A;
+    CsrView<VT> G, GT;
+    VT *x, *r, *p, *q, *z, *w;
+    const VT* invd;
+    PcgScalars* st;
+    int precond;
+};
+
+template <class VT, int MODE>
+void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, PcgScalars* st) {
+    double* part = c->partials.p;
+    switch (c->unroll) {
+        case 4:
+            hipLaunchKernelGGL((k_sell<VT, MODE, 4>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_sell<VT, MODE, 16>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            break;
+        default:
+            hipLaunchKernelGGL((k_sell<VT, MODE, 8>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            break;
+    }
+}
+
+template <class VT>
+void enqueue_iteration(SolveCache* c, const Run<VT>& R, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+    const int64_t V = R.A.V;
+    if (ev_a) HIP_CHECK(hipEventRecord(ev_a, c->stream));
+    launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, R.st);
+    if (ev_b) HIP_CHECK(hipEventRecord(ev_b, c->stream));
+    if (R.precond == DEC_PRECOND_JACOBI) {
+        hipLaunchKernelGGL(k_update_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
+                           c->partials.p, R.st);
+        hipLaunchKernelGGL(k_p_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p, R.st);
+    } else {
+        hipLaunchKernelGGL(k_update_plain<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
+                           c->partials.p, R.st);
+        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w, R.st);
+        hipLaunchKernelGGL((k_fsai_gt<VT, false>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r,
+                           (VT*)nullptr, 0.0, 0, c->partials.p, R.st);
+        hipLaunchKernelGGL(k_p_plain<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.z, R.p, R.st);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+// residual r = b - A x (r.r into st->rr), then the preconditioner start
+template <class VT>
+void enqueue_start(SolveCache* c, const Run<VT>& R, const VT* b, double stop_factor, int relative) {
+    const int64_t V = R.A.V;
+    if (b) launch_sell<VT, MODE_RESID>(c, R.A, R.x, R.r, b, R.st);
+    if (R.precond == DEC_PRECOND_JACOBI) {
+        hipLaunchKernelGGL(k_init_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
+                           stop_factor, relative, c->partials.p, R.st);
+    } else {
+        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w,
+                           (const PcgScalars*)(c->st.p + 2));
+        hipLaunchKernelGGL((k_fsai_gt<VT, true>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r, R.p,
+                           stop_factor, relative, c->partials.p, R.st);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+PcgScalars read_state(SolveCache* c, const PcgScalars* st) {
+    PcgScalars h;
+    HIP_CHECK(hipMemcpyAsync(c->ctx->pinned, st, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    std::memcpy(&h, c->ctx->pinned, sizeof(h));
+    return h;
+}
+
+// Run batches of iterations until the state says done.  Returns the final state.
+template <class VT>
+PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec_solve_stats* stats) {
+    const int chunk = o.chunk > 0 ? o.chunk : 32;
+    const int prec = sizeof(VT) == 8 ? 0 : 1;
+    int64_t last_iter = -1;
+    for (int64_t batch = 0;; ++batch) {
+        // every batch must advance the iteration count until the state says done
+        DEC_REQUIRE(batch <= o.max_iters / chunk + 4, DEC_EHIP, "PCG batches exceed the iteration cap");
+        if (o.profile) {
+            while ((int)c->events.size() < 2 * chunk) {
+                hipEvent_t e;
+                HIP_CHECK(hipEventCreate(&e));
+                c->events.push_back(e);
+            }
+            const PcgScalars before = read_state(c, R.st);
+            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, c->events[2 * k], c->events[2 * k + 1]);
+            const PcgScalars after = read_state(c, R.st);
+            const int64_t ran = after.iter - before.iter;
+            for (int64_t k = 0; k < ran && k < chunk; ++k) {
+                float ms = 0.0f;
+                HIP_CHECK(hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
+                if (stats) {
+                    stats->spmv_ms += ms;
+                    stats->spmv_launches += 1;
+                }
+            }
+            if (after.done) return after;
+            DEC_REQUIRE(after.iter > last_iter, DEC_EHIP, "PCG made no progress in a batch");
+            last_iter = after.iter;
+            continue;
+        }
+        if (o.use_graph) {
+            GraphKey key{prec, R.precond, chunk, c->unroll};
+            auto it = c->graphs.find(key);
+            hipGraphExec_t exec = nullptr;
+            if (it == c->graphs.end()) {
+                hipGraph_t g;
+                HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R);
+                HIP_CHECK(hipStreamEndCapture(c->stream, &g));
+                HIP_CHECK(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+                HIP_CHECK(hipGraphDestroy(g));
+                c->graphs[key] = exec;
+            } else {
+                exec = it->second;
+            }
+            HIP_CHECK(hipGraphLaunch(exec, c->stream));
+        } else {
+            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R);
+        }
+        const PcgScalars s = read_state(c, R.st);
+        if (s.done) return s;
+        DEC_REQUIRE(s.iter > last_iter, DEC_EHIP, "PCG made no progress in a batch");
+        last_iter = s.iter;
+    }
+}
+
+Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
+    Run<double> R{};
+    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V};
+    R.G = {m->fsai.g_ptr.p, m->fsai.g_col.p, m->fsai.g_val64.p, m->V};
+    R.GT = {m->fsai.gt_ptr.p, m->fsai.gt_col.p, m->fsai.gt_val64.p, m->V};
+    R.x = c->x64.p;
+    R.r = c->r64.p;
+    R.p = c->p64.p;
+    R.q = c->q64.p;
+    R.z = c->z64.p;
+    R.w = c->w64.p;
+    R.invd = m->invdiag64.p;
+    R.st = c->st.p;
+    R.precond = precond;
+    return R;
+}
+
+Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
+    Run<float> R{};
+    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V};
+    R.G = {m->fsai.g_ptr.p, m->fsai.g_col.p, m->fsai.g_val32.p, m->V};
+    R.GT = {m->fsai.gt_ptr.p, m->fsai.gt_col.p, m->fsai.gt_val32.p, m->V};
+    R.x = c->x32.p;
+    R.r = c->r32.p;
+    R.p = c->p32.p;
+    R.q = c->q32.p;
+    R.z = c->z32.p;
+    R.w = c->w32.p;
+    R.invd = m->invdiag32.p;
+    R.st = c->st.p + 1;
+    R.precond = precond;
+    return R;
+}
+
+// true FP64 residual of x64 against b: ||b - A x||^2 (via t64)
+double true_rr(dec_mesh* m, SolveCache* c) {
+    Run<double> R = run64(m, c, DEC_PRECOND_JACOBI);
+    PcgScalars* s2 = c->st.p + 2;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
+    launch_sell<double, MODE_RESID>(c, R.A, c->x64.p, c->t64.p, m->rhs.p, s2);
+    HIP_CHECK(hipGetLastError());
+    return read_state(c, s2).rr;
+}
+
+// FP64 PCG from the current x64.  Returns a DEC status.
+int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int64_t* iters_out,
+             dec_solve_stats* stats) {
+    Run<double> R = run64(m, c, o.precond);
+    const double tol2 = o.tol * o.tol;
+    int64_t total = 0;
+    for (int restart = 0;; ++restart) {
+        const int64_t left = o.max_iters - total;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left > 0 ? left : (int64_t)1);
+        // rr_stop = tol^2 b.b (absolute form of the relative test)
+        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, tol2, c->partials.p, R.st);
+        enqueue_start<double>(c, R, m->rhs.p, 0.0, 0);
+        PcgScalars s = read_state(c, R.st);
+        if (!s.done) {
+            if (left <= 0) {
+                *iters_out = total;
+                return DEC_ENOTCONV;
+            }
+            s = iterate(c, R, o, stats);
+        }
+        total += s.iter;
+        *iters_out = total;
+        if (s.done == PCG_BREAKDOWN) return DEC_EBREAKDOWN;
+        if (s.done == PCG_MAXITER) return DEC_ENOTCONV;
+        // converged on the recursive residual: confirm with the true one
+        const double rr = true_rr(m, c);
+        if (rr <= tol2 * bb) return DEC_OK;
+        if (stats) stats->restarts += 1;
+        if (restart >= 20) return DEC_ENOTCONV;
+    }
+}
+
+int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec_solve_stats* stats) {
+    Run<float> R = run32(m, c, o.precond);
+    PcgScalars* s2 = c->st.p + 2;
+    const double bn = sqrt(bb);
+    double rn_prev = INFINITY;
+    int64_t inner_total = 0;
+    for (int outer = 0; outer < 100; ++outer) {
+        // r64 = b - A x64 (FP64), ||r64||^2 into s2->rr
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
+        launch_sell<double, MODE_RESID>(c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p,
+                                                            m->sell.nslices, m->V},
+                                        c->x64.p, c->r64.p, m->rhs.p, s2);
+        const double rn = sqrt(read_state(c, s2).rr);
+        if (stats) stats->outer_iterations = outer;
+        if (rn <= o.tol * bn) return DEC_OK;
+        if (outer > 0 && rn > 0.5 * rn_prev) {
+            // refinement stagnates (FP32 cannot reduce the residual further): finish in FP64
+            if (stats) stats->fp64_fallback = 1;
+            int64_t it64 = 0;
+            dec_solve_opts o64 = o;
+            o64.max_iters = o.max_iters > inner_total ? o.max_iters - inner_total : 1;
+            const int st = pcg_fp64(m, c, o64, bb, &it64, stats);
+            if (stats) stats->iterations = inner_total + it64;
+            return st;
+        }
+        double itol = o.inner_tol;
+        if (o.adaptive_final_inner) itol = fmax(o.inner_tol, 0.5 * o.tol * bn / rn);
+        if (itol >= 1.0) itol = 0.5;
+        const int64_t left = o.max_iters - inner_total;
+        if (left <= 0) return DEC_ENOTCONV;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left);
+        hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s2, c->r32.p, c->x32.p,
+                           c->partials.p, R.st);
+        enqueue_start<float>(c, R, nullptr, itol * itol, 1);
+        PcgScalars s = read_state(c, R.st);
+        if (!s.done) s = iterate(c, R, o, stats);
+        inner_total += s.iter;
+        if (stats) stats->iterations = inner_total;
+        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, s2);
+        HIP_CHECK(hipGetLastError());
+        rn_prev = rn;
+    }
+    return DEC_ENOTCONV;
+}
+
+void ensure_vectors(dec_mesh* m, SolveCache* c, int precision) {
+    const int64_t V = m->V;
+    for (DBuf<double>* b : {&c->x64, &c->r64, &c->p64, &c->q64, &c->z64, &c->w64, &c->t64}) b->alloc(c->ctx, V);
+    if (precision == DEC_PREC_MIXED)
+        for (DBuf<float>* b : {&c->x32, &c->r32, &c->p32, &c->q32, &c->z32, &c->w32}) b->alloc(c->ctx, V);
+}
+
+}  // namespace
+
+void clear_graphs(SolveCache* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+void destroy_solve_cache(SolveCache* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    clear_graphs(c);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->t0) (void)hipEventDestroy(c->t0);
+    if (c->t1) (void)hipEventDestroy(c->t1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+SolveCache* get_solve_cache(dec_mesh* m) {
+    if (m->solve) return m->solve;
+    SolveCache* c = new SolveCache();
+    c->ctx = m->ctx;
+    try {
+        HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreate(&c->t0));
+        HIP_CHECK(hipEventCreate(&c->t1));
+        // one block per 256 rows up to 8 resident blocks per CU, multiple of 8
+        int64_t want = (m->V + BLOCK - 1) / BLOCK;
+        int64_t cap = 8 * (int64_t)m->ctx->num_cus;
+        int64_t G = want < cap ? want : cap;
+        G = ((G + 7) / 8) * 8;
+        c->G = (int)G;
+        c->partials.alloc(m->ctx, 2 * G);
+        c->st.alloc(m->ctx, 3);
+        HIP_CHECK(hipMemsetAsync(c->st.p, 0, 3 * sizeof(PcgScalars), c->stream));
+        (void)m->ctx->readback(c->st.p, 8);  // make sure the pinned staging area exists
+    } catch (...) {
+        destroy_solve_cache(c);
+        throw;
+    }
+    m->solve = c;
+    return c;
+}
+
+extern "C" {
+
+int dec_solve_opts_default(dec_solve_opts* o) {
+    if (!o) return DEC_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = DEC_PREC_FP64;
+    o->precond = DEC_PRECOND_JACOBI;
+    o->tol = 1e-10;
+    o->inner_tol = 1e-5;
+    o->adaptive_final_inner = 1;
+    o->warm_start = 0;
+    o->max_iters = 100000;
+    o->format = DEC_FMT_AUTO;
+    o->chunk = 32;
+    o->use_graph = 1;
+    o->profile = 0;
+    return DEC_OK;
+}
+
+int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats) {
+    if (!m || !opts || !T) return DEC_EINVAL;
+    dec_ctx* ctx = m->ctx;
+    try {
+        const dec_solve_opts& o = *opts;
+        DEC_REQUIRE(m->bc_ready, DEC_ESTATE, "dec_solve needs dec_apply_bc first");
+        DEC_REQUIRE(o.precision == DEC_PREC_FP64 || o.precision == DEC_PREC_MIXED, DEC_EINVAL, "bad precision");
+        DEC_REQUIRE(o.precond == DEC_PRECOND_JACOBI || o.precond == DEC_PRECOND_FSAI, DEC_EINVAL, "bad precond");
+        DEC_REQUIRE(o.tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0, DEC_EINVAL, "bad tolerance");
+        DEC_REQUIRE(o.max_iters > 0 && o.chunk >= 0 && o.chunk <= 4096, DEC_EINVAL, "bad iteration limits");
+        ctx->set_device();
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->spmv_bytes = (double)m->nnz * (8.0 + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * 8.0 * (double)m->V;
+            if (o.precision == DEC_PREC_MIXED)
+                stats->spmv_bytes = (double)m->nnz * (4.0 + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * 4.0 * (double)m->V;
+        }
+        SolveCache* c = get_solve_cache(m);
+        if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
+        ensure_vectors(m, c, o.precision);
+        ctx->sync();  // inputs written on the caller's stream are complete
+        HIP_CHECK(hipEventRecord(c->t0, c->stream));
+        hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
+                           m->bc_value.p, o.warm_start ? T : nullptr, c->x64.p);
+        // b.b
+        PcgScalars* s2 = c->st.p + 2;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
+        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, 0.0, c->partials.p, s2);
+        HIP_CHECK(hipGetLastError());
+        const double bb = read_state(c, s2).aux;
+        int status = DEC_OK;
+        if (bb == 0.0) {
+            HIP_CHECK(hipMemsetAsync(c->x64.p, 0, m->V * sizeof(double), c->stream));
+        } else if (o.precision == DEC_PREC_FP64) {
+            int64_t it = 0;
+            status = pcg_fp64(m, c, o, bb, &it, stats);
+            if (stats) stats->iterations = it;
+        } else {
+            status = ir_mixed(m, c, o, bb, stats);
+        }
+        HIP_CHECK(hipEventRecord(c->t1, c->stream));
+        HIP_CHECK(hipMemcpyAsync(T, c->x64.p, m->V * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        const double rr = bb == 0.0 ? 0.0 : true_rr(m, c);
+        HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (stats) {
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, c->t0, c->t1));
+            stats->solve_ms = ms;
+            stats->rel_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
+            stats->status = status;
+        }
+        if (status != DEC_OK) ctx->last_error = dec_status_string(status);
+        return status;
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+}
+
+int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void* y) {
+    if (!m || !x || !y) return DEC_EINVAL;
+    dec_ctx* ctx = m->ctx;
+    try {
+        DEC_REQUIRE(m->assembled, DEC_ESTATE, "dec_spmv needs dec_assemble first");
+        DEC_REQUIRE(precision == DEC_PREC_FP64 || precision == DEC_PREC_MIXED, DEC_EINVAL, "bad precision");
+        ctx->set_device();
+        SolveCache* c = get_solve_cache(m);
+        if (format == DEC_FMT_CSR) {
+            if (precision == DEC_PREC_FP64)
+                hipLaunchKernelGGL(k_csr_plain<double>, dim3(grid_for(m->V)), dim3(BLOCK), 0, ctx->stream,
+                                   CsrView<double>{m->row_ptr.p, m->col.p, m->val64.p, m->V},
+                                   static_cast<const double*>(x), static_cast<double*>(y));
+            else
+                hipLaunchKernelGGL(k_csr_plain<float>, dim3(grid_for(m->V)), dim3(BLOCK), 0, ctx->stream,
+                                   CsrView<float>{m->row_ptr.p, m->col.p, m->val32.p, m->V},
+                                   static_cast<const float*>(x), static_cast<float*>(y));
+        } else {
+            hipStream_t keep = c->stream;
+            c->stream = ctx->stream;
+            if (precision == DEC_PREC_FP64)
+                launch_sell<double, MODE_PLAIN>(
+                    c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V},
+                    static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr);
+            else
+                launch_sell<float, MODE_PLAIN>(
+                    c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V},
+                    static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr);
+            c->stream = keep;
+        }
+        HIP_CHECK(hipGetLastError());
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}
+
+}  // extern "C"

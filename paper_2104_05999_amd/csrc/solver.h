@@ -1,0 +1,130 @@
+// Device building blocks of the PCG solver: matrix views, the XCD-aware
+// block-to-rows mapping, the sliced-ELL row product and the scalar state
+// shared by the fused kernels.
+#pragma once
+
+#include <map>
+
+#include "common.h"
+
+// Scalar state of one PCG run, kept in device memory so that a batch of
+// iterations can be launched (or replayed from a graph) without the host.
+struct PcgScalars {
+    double rho;      // r.z of the current iterate
+    double pq;       // p.Ap
+    double alpha;
+    double beta;
+    double rr;       // r.r of the current iterate
+    double rr_stop;  // converged when rr <= rr_stop
+    double aux;      // b.b (FP64 solves) or the last reduction result
+    double pad0;
+    int64_t iter;
+    int64_t max_iter;
+    int32_t done;    // PCG_RUNNING / PCG_CONVERGED / PCG_MAXITER / PCG_BREAKDOWN
+    int32_t pad1;
+    unsigned counter;  // arrival counter of the last-block reductions
+    unsigned pad2;
+};
+
+enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXITER = 2, PCG_BREAKDOWN = 3 };
+
+template <class VT>
+struct SellView {
+    const int64_t* ptr;
+    const int32_t* col;
+    const VT* val;
+    int64_t nslices;
+    int64_t V;
+};
+
+template <class VT>
+struct CsrView {
+    const int32_t* ptr;
+    const int32_t* col;
+    const VT* val;
+    int64_t V;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that XCD x owns the contiguous x-th eighth of the
+// rows: neighbouring rows, which share x entries, then share an L2.
+// gridDim.x is a multiple of 8.
+__device__ __forceinline__ int logical_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ void block_range(int64_t n, int64_t* b0, int64_t* b1) {
+    const int64_t L = logical_block(), G = gridDim.x;
+    *b0 = n * L / G;
+    *b1 = n * (L + 1) / G;
+}
+
+// Row `lane` of the slice starting at `base` with `width` stored entries per
+// row: sum over the row's entries in stored (ascending column) order.
+template <class VT, int U>
+__device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
+                                       const VT* __restrict__ x) {
+    const int32_t* cp = A.col + base + lane;
+    const VT* vp = A.val + base + lane;
+    VT acc = 0;
+    int j = 0;
+    for (; j + U <= width; j += U) {
+        int32_t c[U];
+        VT v[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = __builtin_nontemporal_load(cp + u * SELL_C);
+            v[u] = __builtin_nontemporal_load(vp + u * SELL_C);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u] * xv[u];
+        cp += U * SELL_C;
+        vp += U * SELL_C;
+    }
+    for (; j < width; ++j) {
+        acc += __builtin_nontemporal_load(vp) * x[__builtin_nontemporal_load(cp)];
+        cp += SELL_C;
+        vp += SELL_C;
+    }
+    return acc;
+}
+
+template <class VT>
+__device__ __forceinline__ VT csr_row(const CsrView<VT>& A, int64_t row, const VT* __restrict__ x) {
+    VT acc = 0;
+    for (int32_t k = A.ptr[row]; k < A.ptr[row + 1]; ++k) acc += A.val[k] * x[A.col[k]];
+    return acc;
+}
+
+// ---------------------------------------------------------------- host side
+struct GraphKey {
+    int prec, precond, chunk, unroll;
+    bool operator<(const GraphKey& o) const {
+        if (prec != o.prec) return prec < o.prec;
+        if (precond != o.precond) return precond < o.precond;
+        if (chunk != o.chunk) return chunk < o.chunk;
+        return unroll < o.unroll;
+    }
+};
+
+struct SolveCache {
+    dec_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;  // internal stream (graph capture needs a non-null stream)
+    int G = 0;                     // blocks of the fused kernels (multiple of 8)
+    int unroll = 8;                // sliced-ELL unroll chosen by the tuner
+    bool tuned = false;
+    DBuf<double> x64, r64, p64, q64, z64, w64, t64;
+    DBuf<float> x32, r32, p32, q32, z32, w32;
+    DBuf<double> partials;  // [2G]
+    DBuf<PcgScalars> st;    // [3]: FP64 PCG, FP32 inner PCG, scratch reductions
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<hipEvent_t> events;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+SolveCache* get_solve_cache(dec_mesh* m);
+void clear_graphs(SolveCache* c);
+void fsai_setup(dec_mesh* m);

@@ -1,0 +1,424 @@
+// Topology of the tetrahedral complex (Section 2.1: cells, incidence, d0):
+// vertex -> tet lists, the edge set in lexicographic (lo, hi) order, the
+// edge -> tet incidence in ascending tet order, the static CSR pattern of
+// L = d0^T *1 d0 (full edge graph plus diagonal) and the boundary faces.
+//
+// Every list is built per vertex from that vertex's sorted tet list, so the
+// result is independent of thread scheduling: integer atomics only count
+// (deterministic totals) or claim slots whose order the per-vertex sort then
+// fixes.  Compiled without floating-point contraction: the zero-volume test
+// must take the same decision as the FP64 reference.
+#include <climits>
+
+#include "common.h"
+
+namespace {
+
+// local edge index of the local vertex pair (a, b), a < b:
+// (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+__device__ __forceinline__ int local_edge(int a, int b) {
+    return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+
+__device__ __forceinline__ int vget(const int4& q, int k) {
+    return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+}
+
+__global__ void k_tet_check(const int4* __restrict__ tets, int64_t T, int64_t V, const double* __restrict__ xyz,
+                            unsigned* __restrict__ err) {
+    GRID_STRIDE_LOOP(t, T) {
+        const int4 q = tets[t];
+        const int a[4] = {q.x, q.y, q.z, q.w};
+        bool oob = false;
+        for (int k = 0; k < 4; ++k) oob |= (a[k] < 0) | (static_cast<int64_t>(a[k]) >= V);
+        if (oob) {
+            atomicOr(err, 1u);
+            continue;
+        }
+        if (a[0] == a[1] || a[0] == a[2] || a[0] == a[3] || a[1] == a[2] || a[1] == a[3] || a[2] == a[3]) {
+            atomicOr(err, 2u);
+            continue;
+        }
+        const double* p0 = xyz + 3 * (int64_t)a[0];
+        const double* p1 = xyz + 3 * (int64_t)a[1];
+        const double* p2 = xyz + 3 * (int64_t)a[2];
+        const double* p3 = xyz + 3 * (int64_t)a[3];
+        const double ax = p1[0] - p0[0], ay = p1[1] - p0[1], az = p1[2] - p0[2];
+        const double bx = p2[0] - p0[0], by = p2[1] - p0[1], bz = p2[2] - p0[2];
+        const double cx = p3[0] - p0[0], cy = p3[1] - p0[1], cz = p3[2] - p0[2];
+        const double det = (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz)) + az * (bx * cy - by * cx);
+        if (det == 0.0) atomicOr(err, 4u);
+    }
+}
+
+__global__ void k_vt_count(const int32_t* __restrict__ tets, int64_t n4, int32_t* __restrict__ cnt) {
+    GRID_STRIDE_LOOP(i, n4) atomicAdd(&cnt[tets[i]], 1);
+}
+
+__global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const int64_t* __restrict__ vt_ptr,
+                          int32_t* __restrict__ fill, int32_t* __restrict__ vt_list) {
+    GRID_STRIDE_LOOP(i, n4) {
+        const int v = tets[i];
+        const int pos = atomicAdd(&fill[v], 1);
+        vt_list[vt_ptr[v] + pos] = static_cast<int32_t>(i >> 2);
+    }
+}
+
+// insertion sort of each vertex's tet list (short lists)
+__global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
+    GRID_STRIDE_LOOP(v, V) {
+        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
+        for (int64_t i = b + 1; i < e; ++i) {
+            const int32_t key = vt_list[i];
+            int64_t j = i - 1;
+            while (j >= b && vt_list[j] > key) {
+                vt_list[j + 1] = vt_list[j];
+                --j;
+            }
+            vt_list[j + 1] = key;
+        }
+    }
+}
+
+// Smallest neighbour w of v with w > cur over v's tets, and the number of
+// v's tets that contain it (each tet holds w at most once).  INT_MAX: none.
+__device__ __forceinline__ int next_neighbour(const int4* __restrict__ tets, const int32_t* __restrict__ list,
+                                              int64_t b, int64_t e, int v, int cur, int* count) {
+    int best = INT_MAX, c = 0;
+    for (int64_t k = b; k < e; ++k) {
+        const int4 q = tets[list[k]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int w = vget(q, r);
+            if (w != v && w > cur) {
+                if (w < best) {
+                    best = w;
+                    c = 1;
+                } else if (w == best) {
+                    ++c;
+                }
+            }
+        }
+    }
+    *count = c;
+    return best;
+}
+
+__global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
+                            const int32_t* __restrict__ vt_list, int64_t V, int32_t* __restrict__ n_up,
+                            int32_t* __restrict__ row_len) {
+    GRID_STRIDE_LOOP(v, V) {
+        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
+        int cur = -1, up = 0, all = 0, c;
+        while (true) {
+            const int w = next_neighbour(tets, vt_list, b, e, (int)v, cur, &c);
+            if (w == INT_MAX) break;
+            cur = w;
+            ++all;
+            up += (w > v);
+        }
+        n_up[v] = up;
+        row_len[v] = all + 1;
+    }
+}
+
+// Row v of the pattern: lower neighbours, the diagonal, upper neighbours,
+// ascending.  Upper neighbours define the edges (v, w) numbered from
+// up_ptr[v] in ascending w, i.e. lexicographic (lo, hi) order overall.
+__global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
+                           const int32_t* __restrict__ vt_list, int64_t V, const int64_t* __restrict__ up_ptr,
+                           const int64_t* __restrict__ row_ptr, int32_t* __restrict__ edges,
+                           int32_t* __restrict__ et_cnt, int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
+                           int32_t* __restrict__ diag_pos) {
+    GRID_STRIDE_LOOP(v, V) {
+        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
+        int64_t pos = row_ptr[v], ep = up_ptr[v];
+        bool diag = false;
+        int cur = -1, c;
+        while (true) {
+            const int w = next_neighbour(tets, vt_list, b, e, (int)v, cur, &c);
+            if (w == INT_MAX) break;
+            cur = w;
+            if (w > v && !diag) {
+                col[pos] = (int32_t)v;
+                nz_edge[pos] = -1;
+                diag_pos[v] = (int32_t)pos;
+                ++pos;
+                diag = true;
+            }
+            col[pos] = w;
+            if (w < v) {
+                nz_edge[pos] = -2;  // resolved by k_lower_edge_ids
+            } else {
+                nz_edge[pos] = (int32_t)ep;
+                edges[2 * ep] = (int32_t)v;
+                edges[2 * ep + 1] = w;
+                et_cnt[ep] = c;
+                ++ep;
+            }
+            ++pos;
+        }
+        if (!diag) {
+            col[pos] = (int32_t)v;
+            nz_edge[pos] = -1;
+            diag_pos[v] = (int32_t)pos;
+        }
+    }
+}
+
+// Entries (v, w) with w < v belong to edge (w, v), found by binary search in
+// w's upper edges (sorted by hi).
+__global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                 const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
+                                 int32_t* __restrict__ nz_edge, unsigned* __restrict__ err) {
+    GRID_STRIDE_LOOP(v, V) {
+        for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int w = col[k];
+            if (w >= v) break;
+            int64_t lo = up_ptr[w], hi = up_ptr[w + 1] - 1, found = -1;
+            while (lo <= hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int h = edges[2 * mid + 1];
+                if (h == v) {
+                    found = mid;
+                    break;
+                }
+                if (h < v)
+                    lo = mid + 1;
+                else
+                    hi = mid - 1;
+            }
+            if (found < 0) atomicOr(err, 8u);
+            nz_edge[k] = (int32_t)found;
+        }
+    }
+}
+
+// Incidences of edge (lo, hi): lo's tets that contain hi, ascending, as tet*6 + local edge.
+__global__ void k_et_fill(int64_t E, const int32_t* __restrict__ edges, const int4* __restrict__ tets,
+                          const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_list,
+                          const int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc) {
+    GRID_STRIDE_LOOP(e, E) {
+        const int lo = edges[2 * e], hi = edges[2 * e + 1];
+        int64_t out = et_ptr[e];
+        for (int64_t k = vt_ptr[lo]; k < vt_ptr[lo + 1]; ++k) {
+            const int t = vt_list[k];
+            const int4 q = tets[t];
+            int pl = -1, ph = -1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int w = vget(q, r);
+                if (w == lo) pl = r;
+                if (w == hi) ph = r;
+            }
+            if (ph >= 0) {
+                const int a = pl < ph ? pl : ph, bb = pl < ph ? ph : pl;
+                et_inc[out++] = t * 6 + local_edge(a, bb);
+            }
+        }
+    }
+}
+
+// Faces: face k of tet t is opposite local vertex k.  Its tets are found in
+// the sorted tet list of its smallest vertex; the first one found owns it.
+__global__ void k_faces(int64_t T, const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
+                        const int32_t* __restrict__ vt_list, uint8_t* __restrict__ bface,
+                        unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
+    GRID_STRIDE_LOOP(t, T) {
+        const int4 q = tets[t];
+        uint8_t mask = 0;
+        unsigned long long owned = 0, bnd = 0;
+        for (int k = 0; k < 4; ++k) {
+            int f[3], m = 0;
+            for (int r = 0; r < 4; ++r)
+                if (r != k) f[m++] = vget(q, r);
+            int a = f[0], b1 = f[1], c1 = f[2];
+            if (b1 < a) { int s = a; a = b1; b1 = s; }
+            if (c1 < a) { int s = a; a = c1; c1 = s; }
+            int cnt = 0, first = -1;
+            for (int64_t j = vt_ptr[a]; j < vt_ptr[a + 1]; ++j) {
+                const int u = vt_list[j];
+                const int4 o = tets[u];
+                bool hb = false, hc = false;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int w = vget(o, r);
+                    hb |= (w == b1);
+                    hc |= (w == c1);
+                }
+                if (hb && hc) {
+                    if (first < 0) first = u;
+                    ++cnt;
+                }
+            }
+            if (cnt > 2) atomicOr(err, 16u);
+            if (cnt == 1) {
+                mask |= (uint8_t)(1u << k);
+                ++bnd;
+            }
+            if (first == t) ++owned;
+        }
+        bface[t] = mask;
+        if (owned) atomicAdd(&counts[0], owned);
+        if (bnd) atomicAdd(&counts[1], bnd);
+    }
+}
+
+std::string topo_message(unsigned err) {
+    if (err & 1u) return "tet vertex index out of range";
+    if (err & 2u) return "tet repeats a vertex";
+    if (err & 4u) return "tet of zero volume";
+    if (err & 16u) return "face shared by more than two tets";
+    if (err & 8u) return "internal: lower edge not found";
+    return "invalid mesh";
+}
+
+void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
+    dec_ctx* ctx = m->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t V = m->V, T = m->T;
+    m->xyz.alloc(ctx, 3 * V);
+    m->tets.alloc(ctx, 4 * T);
+    HIP_CHECK(hipMemcpyAsync(m->xyz.p, xyz, 3 * V * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(m->tets.p, tets, 4 * T * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    const int4* tq = reinterpret_cast<const int4*>(m->tets.p);
+
+    DBuf<unsigned> err;
+    err.alloc(ctx, 1);
+    err.zero();
+    hipLaunchKernelGGL(k_tet_check, dim3(grid_for(T)), dim3(BLOCK), 0, s, tq, T, V, m->xyz.p, err.p);
+    HIP_CHECK(hipGetLastError());
+    unsigned e0 = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
+    if (e0) dec_fail(DEC_ETOPO, topo_message(e0));
+
+    // vertex -> tets
+    DBuf<int32_t> cnt;
+    cnt.alloc(ctx, V);
+    cnt.zero();
+    hipLaunchKernelGGL(k_vt_count, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, cnt.p);
+    m->vt_ptr.alloc(ctx, V + 1);
+    scan_exclusive_i32_to_i64(ctx, cnt.p, m->vt_ptr.p, V, false);
+    m->vt_list.alloc(ctx, 4 * T);
+    cnt.zero();
+    hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, m->vt_ptr.p, cnt.p,
+                       m->vt_list.p);
+    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
+    HIP_CHECK(hipGetLastError());
+
+    // neighbours: counts, then edges and the CSR pattern
+    DBuf<int32_t> n_up, row_len;
+    n_up.alloc(ctx, V);
+    row_len.alloc(ctx, V);
+    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V, n_up.p,
+                       row_len.p);
+    HIP_CHECK(hipGetLastError());
+    m->up_ptr.alloc(ctx, V + 1);
+    const int64_t E = scan_exclusive_i32_to_i64(ctx, n_up.p, m->up_ptr.p, V, true);
+    DBuf<int64_t> row_ptr64;
+    row_ptr64.alloc(ctx, V + 1);
+    const int64_t nnz = scan_exclusive_i32_to_i64(ctx, row_len.p, row_ptr64.p, V, true);
+    DEC_REQUIRE(nnz == V + 2 * E, DEC_ETOPO, "internal: pattern size mismatch");
+    DEC_REQUIRE(nnz < (int64_t(1) << 31) && 6 * T < (int64_t(1) << 31), DEC_EINVAL,
+                "mesh too large for int32 CSR indices");
+    m->E = E;
+    m->nnz = nnz;
+
+    m->edges.alloc(ctx, 2 * E);
+    DBuf<int32_t> et_cnt;
+    et_cnt.alloc(ctx, E);
+    m->col.alloc(ctx, nnz);
+    m->nz_edge.alloc(ctx, nnz);
+    m->diag_pos.alloc(ctx, V);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
+                       m->up_ptr.p, row_ptr64.p, m->edges.p, et_cnt.p, m->col.p, m->nz_edge.p, m->diag_pos.p);
+    err.zero();
+    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
+                       m->up_ptr.p, m->edges.p, m->nz_edge.p, err.p);
+    HIP_CHECK(hipGetLastError());
+    m->row_ptr.alloc(ctx, V + 1);
+    copy_i64_to_i32(ctx, row_ptr64.p, m->row_ptr.p, V + 1);
+
+    // edge -> tet incidences
+    m->et_ptr.alloc(ctx, E + 1);
+    const int64_t ninc = scan_exclusive_i32_to_i64(ctx, et_cnt.p, m->et_ptr.p, E, true);
+    DEC_REQUIRE(ninc == 6 * T, DEC_ETOPO, "internal: incidence count mismatch");
+    m->et_inc.alloc(ctx, 6 * T);
+    hipLaunchKernelGGL(k_et_fill, dim3(grid_for(E)), dim3(BLOCK), 0, s, E, m->edges.p, tq, m->vt_ptr.p,
+                       m->vt_list.p, m->et_ptr.p, m->et_inc.p);
+    HIP_CHECK(hipGetLastError());
+
+    // faces
+    m->tet_bface.alloc(ctx, T);
+    DBuf<unsigned long long> fc;
+    fc.alloc(ctx, 2);
+    fc.zero();
+    hipLaunchKernelGGL(k_faces, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tq, m->vt_ptr.p, m->vt_list.p,
+                       m->tet_bface.p, fc.p, err.p);
+    HIP_CHECK(hipGetLastError());
+    unsigned long long hc[2];
+    std::memcpy(hc, ctx->readback(fc.p, sizeof(hc)), sizeof(hc));
+    m->F = (int64_t)hc[0];
+    m->Fb = (int64_t)hc[1];
+    unsigned e1 = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
+    if (e1) dec_fail(DEC_ETOPO, topo_message(e1));
+}
+
+}  // namespace
+
+extern "C" {
+
+int dec_build_topology(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets, dec_mesh** out) {
+    if (!ctx || !out) return DEC_EINVAL;
+    *out = nullptr;
+    dec_mesh* m = new dec_mesh();
+    m->ctx = ctx;
+    try {
+        DEC_REQUIRE(V > 0 && T > 0 && xyz && tets, DEC_EINVAL, "empty mesh or NULL array");
+        DEC_REQUIRE(V < (int64_t(1) << 31), DEC_EINVAL, "too many vertices for int32 indices");
+        ctx->set_device();
+        m->V = V;
+        m->T = T;
+        build_topology(m, xyz, tets);
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        delete m;
+        return e.code;
+    }
+    *out = m;
+    return DEC_OK;
+}
+
+int dec_mesh_info(const dec_mesh* m, int64_t* V, int64_t* T, int64_t* E, int64_t* F, int64_t* Fb, int64_t* nnz) {
+    if (!m) return DEC_EINVAL;
+    if (V) *V = m->V;
+    if (T) *T = m->T;
+    if (E) *E = m->E;
+    if (F) *F = m->F;
+    if (Fb) *Fb = m->Fb;
+    if (nnz) *nnz = m->nnz;
+    return DEC_OK;
+}
+
+int dec_get_edges(const dec_mesh* m, int32_t* edges) {
+    if (!m || !edges) return DEC_EINVAL;
+    try {
+        HIP_CHECK(hipMemcpyAsync(edges, m->edges.p, 2 * m->E * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                 m->ctx->stream));
+    } catch (const DecError& e) {
+        m->ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}
+
+int dec_mesh_destroy(dec_mesh* m) {
+    if (!m) return DEC_EINVAL;
+    try {
+        m->ctx->sync();
+    } catch (const DecError&) {
+    }
+    delete m;
+    return DEC_OK;
+}
+
+}  // extern "C"

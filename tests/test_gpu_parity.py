@@ -1,0 +1,299 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on seeded inputs.
+
+Integer and index results (edges, CSR pattern, cut masks, pinned counts)
+must match bit for bit; floating-point results within the stated
+tolerances: *1 and the assembled values to 1e-13 relative (an h-scaled
+absolute floor for entries that are zero), SpMV to 1e-14 relative in FP64,
+solutions to 1e-10 relative against the oracle solved to 1e-14 (the GPU
+solve runs to 1e-12), k_eff to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    import paper_2104_05999_amd as dec
+    c = dec.Context(dev)
+    yield c
+    c.close()
+
+
+def _t(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def _shuffled_mesh(n, seed):
+    """Kuhn mesh with tets and each tet's vertex order shuffled (topology must not care)."""
+    xyz, tets = W.kuhn_cube(n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tets = tets[rng.permutation(len(tets))]
+    tets = np.take_along_axis(tets, np.argsort(rng.random(tets.shape), axis=1), axis=1).astype(np.int32)
+    return xyz, tets
+
+
+def _system(n, sigma=1.0, n_cracks=20, kseed=1, cseed=2, rmin=0.02, rmax=0.08, xyz=None, tets=None):
+    if xyz is None:
+        xyz, tets = W.kuhn_cube(n)
+    V = len(xyz)
+    E = O.edges_of(tets, V)
+    kap = W.lognormal_kappa(len(E), sigma, kseed) if sigma > 0 else np.ones(len(E))
+    cr = W.penny_cracks(n_cracks, cseed, rmin, rmax)
+    cut = O.crack_cut(xyz, E, cr)
+    star = O.hodge1(xyz, tets, E, kappa=kap, cut=cut)
+    L, _ = O.assemble(V, E, star)
+    bt, bv, side = W.x_sides(n)
+    A, b, pinned = O.apply_bc(L, bt, bv, E, star)
+    return dict(xyz=xyz, tets=tets, V=V, E=E, kap=kap, cr=cr, cut=cut, star=star, L=L, A=A, b=b, pinned=pinned,
+                bt=bt, bv=bv, side=side)
+
+
+def _gpu(ctx, s, dev):
+    m = ctx.mesh(_t(s["xyz"], dev), _t(s["tets"], dev))
+    cut, star = m.hodge1(_t(s["kap"], dev), _t(s["cr"], dev))
+    m.assemble()
+    npin, b = m.apply_bc(_t(s["bt"], dev), _t(s["bv"], dev))
+    return m, cut, star, npin, b
+
+
+# ---------------------------------------------------------------- topology
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16])
+def test_topology_bit_exact(ctx, dev, n):
+    xyz, tets = W.kuhn_cube(n)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    E = O.edges_of(tets, len(xyz))
+    F, count = O.faces_of(tets)
+    assert (m.E, m.F, m.F_boundary, m.nnz) == (len(E), len(F), int((count == 1).sum()), len(xyz) + 2 * len(E))
+    assert np.array_equal(m.edges().cpu().numpy(), E)
+    L, _ = O.assemble(len(xyz), E, np.ones(len(E)))
+    rp, col, _, _ = m.csr(values=False)
+    assert np.array_equal(rp.cpu().numpy(), L.indptr)
+    assert np.array_equal(col.cpu().numpy(), L.indices)
+
+
+def test_topology_independent_of_tet_order(ctx, dev):
+    xyz, tets = _shuffled_mesh(4, 3)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    assert np.array_equal(m.edges().cpu().numpy(), O.edges_of(tets, len(xyz)))
+
+
+@pytest.mark.parametrize("case", ["range", "repeat", "flat", "shared_face"])
+def test_invalid_mesh_rejected(ctx, dev, case):
+    import paper_2104_05999_amd as dec
+    xyz, tets = W.kuhn_cube(2)
+    if case == "range":
+        tets = tets.copy()
+        tets[3, 2] = len(xyz) + 5
+    elif case == "repeat":
+        tets = tets.copy()
+        tets[5, 1] = tets[5, 0]
+    elif case == "flat":
+        xyz = xyz.copy()
+        xyz[:, 2] = 0.0
+    else:
+        tets = np.concatenate([tets, tets[:1]])
+    with pytest.raises(dec.DecError) as ei:
+        ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    assert ei.value.code == -6
+    assert O.check_mesh(xyz, tets) is not None
+
+
+# ---------------------------------------------------------------- Hodge star and cracks
+@pytest.mark.parametrize("n,shuffle", [(3, False), (16, False), (24, False), (6, True)])
+def test_hodge1_and_cut(ctx, dev, n, shuffle):
+    xyz, tets = _shuffled_mesh(n, 5) if shuffle else W.kuhn_cube(n)
+    s = _system(n, n_cracks=30, rmin=0.05, rmax=0.2, xyz=xyz, tets=tets)
+    m, cut, star, _, _ = _gpu(ctx, s, dev)
+    assert np.array_equal(cut.cpu().numpy().astype(bool), s["cut"])
+    g = star.cpu().numpy()
+    h = 1.0 / n
+    assert np.all((g == 0) == (s["star"] == 0))
+    assert np.allclose(g, s["star"], rtol=1e-13, atol=1e-15 * h)
+
+
+def test_hodge1_jittered_geometry(ctx, dev):
+    n = 6
+    xyz, tets = W.kuhn_cube(n)
+    xyz = W.jitter_interior(xyz, n, 0.2, 7)
+    E = O.edges_of(tets, len(xyz))
+    want = O.hodge1(xyz, tets, E)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    _, star = m.hodge1()
+    assert np.allclose(star.cpu().numpy(), want, rtol=1e-12, atol=1e-15)
+
+
+def test_cut_mask_many_discs_over_lds_chunks(ctx, dev):
+    n = 10
+    xyz, tets = W.kuhn_cube(n)
+    E = O.edges_of(tets, len(xyz))
+    cr = W.penny_cracks(700, 9, 0.01, 0.06)  # more discs than one LDS chunk holds
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    cut, _ = m.hodge1(None, _t(cr, dev))
+    assert np.array_equal(cut.cpu().numpy().astype(bool), O.crack_cut(xyz, E, cr))
+
+
+# ---------------------------------------------------------------- assembly and boundary data
+@pytest.mark.parametrize("n", [4, 16])
+def test_assembly_and_bc(ctx, dev, n):
+    s = _system(n, n_cracks=25, rmin=0.05, rmax=0.25)
+    m = ctx.mesh(_t(s["xyz"], dev), _t(s["tets"], dev))
+    m.hodge1(_t(s["kap"], dev), _t(s["cr"], dev))
+    m.assemble()
+    _, _, v64, v32 = m.csr()
+    assert np.allclose(v64.cpu().numpy(), s["L"].data, rtol=1e-13, atol=1e-15 / n)
+    assert np.array_equal(v32.cpu().numpy(), v64.cpu().numpy().astype(np.float32))
+    npin, b = m.apply_bc(_t(s["bt"], dev), _t(s["bv"], dev))
+    assert npin == int(s["pinned"].sum())
+    _, _, a64, _ = m.csr()
+    assert np.allclose(a64.cpu().numpy(), s["A"].data, rtol=1e-13, atol=1e-15 / n)
+    assert np.allclose(b.cpu().numpy(), s["b"], rtol=1e-13, atol=1e-15 / n)
+
+
+def test_isolated_vertices_pinned(ctx, dev):
+    n = 6
+    xyz, tets = W.kuhn_cube(n)
+    E = O.edges_of(tets, len(xyz))
+    i, j, k = W.lattice_index(n)
+    # a small box of discs around two interior vertices cuts every edge at them
+    cr = []
+    for v in (3 + 7 * (3 + 7 * 3), 2 + 7 * (4 + 7 * 2)):
+        c = xyz[v]
+        for ax in range(3):
+            for sgn in (-1, 1):
+                nrm = np.zeros(3)
+                nrm[ax] = 1.0
+                cr.append([*(c + sgn * 0.4 / n * nrm), *nrm, 0.3])
+    cr = np.array(cr)
+    cut = O.crack_cut(xyz, E, cr)
+    star = O.hodge1(xyz, tets, E, cut=cut)
+    bt, bv, _ = W.x_sides(n)
+    _, _, pinned = O.apply_bc(O.assemble(len(xyz), E, star)[0], bt, bv, E, star)
+    assert pinned.sum() >= 2
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    m.hodge1(None, _t(cr, dev))
+    m.assemble()
+    npin, _ = m.apply_bc(_t(bt, dev), _t(bv, dev))
+    assert npin == int(pinned.sum())
+    T, st, _ = m.solve(tol=1e-12)
+    assert np.all(T.cpu().numpy()[pinned] == 0.0)
+
+
+def test_neumann_load(ctx, dev):
+    n = 5
+    xyz, tets = W.kuhn_cube(n)
+    V = len(xyz)
+    E = O.edges_of(tets, V)
+    i, j, _ = W.lattice_index(n)
+    bt = np.where(i == n, 1, np.where((i == 0) | (j == 0), 2, 0)).astype(np.int8)
+    f0 = np.where(i == 0, -2.5, np.where(j == 0, 0.7, 0.0))
+    g = O.neumann_load(xyz, tets, O.boundary_faces(tets), bt, f0)
+    star = O.hodge1(xyz, tets, E)
+    A, b, _ = O.apply_bc(O.assemble(V, E, star)[0], bt, np.zeros(V), E, star, neumann=g)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    m.hodge1()
+    m.assemble()
+    _, bg = m.apply_bc(_t(bt, dev), _t(np.zeros(V), dev), _t(f0, dev))
+    assert np.allclose(bg.cpu().numpy(), b, rtol=1e-13, atol=1e-16)
+
+
+# ---------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("n", [3, 16, 33])
+def test_spmv(ctx, dev, n):
+    import paper_2104_05999_amd as dec
+    s = _system(n)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    x = np.random.Generator(np.random.PCG64(n)).normal(size=s["V"])
+    want = s["A"] @ x
+    for fmt in (dec.DEC_FMT_SELL, dec.DEC_FMT_CSR):
+        y = m.spmv(_t(x, dev), fmt=fmt).cpu().numpy()
+        assert np.allclose(y, want, rtol=1e-14, atol=1e-14 * np.abs(want).max())
+        y32 = m.spmv(_t(x.astype(np.float32), dev), precision=dec.DEC_PREC_MIXED, fmt=fmt).cpu().numpy()
+        w32 = s["A"].astype(np.float32) @ x.astype(np.float32)
+        assert np.allclose(y32, w32, rtol=1e-5, atol=1e-5 * np.abs(w32).max())
+
+
+# ---------------------------------------------------------------- solves
+def test_homogeneous_16_linear_and_keff(ctx, dev):
+    n = 16
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, side = W.x_sides(n)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    m.hodge1()
+    m.assemble()
+    m.apply_bc(_t(bt, dev), _t(bv, dev))
+    T, st, rc = m.solve(tol=1e-10)
+    i, _, _ = W.lattice_index(n)
+    assert rc == 0 and st["rel_residual"] <= 1e-10
+    assert np.abs(T.cpu().numpy() - (1 - i / n)).max() < 1e-8
+    f = m.flux(T, _t(side, dev))
+    assert abs(f["k_eff"] - 1.0) < 1e-9 and abs(f["q_in"] - 1.0) < 1e-8 and abs(f["q_out"] - 1.0) < 1e-8
+
+
+def _reference(s):
+    return O.pcg(s["A"], s["b"], precond="jacobi", tol=1e-14, stagnation=50)
+
+
+@pytest.mark.parametrize("precision,precond", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_solve_against_oracle(ctx, dev, precision, precond):
+    n = 20
+    s = _system(n, n_cracks=40, rmin=0.03, rmax=0.12)
+    ref = _reference(s)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    T, st, rc = m.solve(tol=1e-12, precision=precision, precond=precond)
+    assert rc == 0, st
+    x = T.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    assert err <= 1e-10, (err, st)
+    assert st["rel_residual"] <= 1e-12
+    r = np.linalg.norm(s["b"] - s["A"] @ x) / np.linalg.norm(s["b"])
+    assert r <= 1.5e-12
+    f = m.flux(T, _t(s["side"], dev), want_edge_flux=True)
+    of = O.flux_effective_conductivity(ref.x, s["E"], s["star"], s["side"])
+    for key in ("k_eff", "q_in", "q_out", "energy"):
+        assert abs(f[key] - of[key]) <= 1e-9 * abs(of["energy"]), key
+    ef = f["edge_flux"].cpu().numpy()
+    assert np.allclose(ef, of["edge_flux"], rtol=1e-8, atol=1e-9 * np.abs(of["edge_flux"]).max())
+
+
+def test_fsai_factor_matches_oracle(ctx, dev):
+    n = 7
+    s = _system(n, n_cracks=15, rmin=0.05, rmax=0.2)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    ptr, col, val = m.fsai()
+    G = O.fsai_factor(s["A"])
+    assert np.array_equal(ptr.cpu().numpy(), G.indptr)
+    assert np.array_equal(col.cpu().numpy(), G.indices)
+    assert np.allclose(val.cpu().numpy(), G.data, rtol=1e-12, atol=1e-14 * np.abs(G.data).max())
+
+
+def test_solver_is_deterministic(ctx, dev):
+    s = _system(12, n_cracks=20)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    a, sa, _ = m.solve(tol=1e-11)
+    b, sb, _ = m.solve(tol=1e-11)
+    c, sc, _ = m.solve(tol=1e-11, use_graph=0)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert sa["iterations"] == sb["iterations"] == sc["iterations"]
+
+
+def test_warm_start_and_limits(ctx, dev):
+    s = _system(12, n_cracks=10)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    T, st, rc = m.solve(tol=1e-10)
+    T2, st2, rc2 = m.solve(T=T.clone(), tol=1e-10, warm_start=1)
+    assert rc2 == 0 and st2["iterations"] <= 1
+    _, st3, rc3 = m.solve(tol=1e-12, max_iters=3, check=False)
+    assert rc3 == -4 and st3["iterations"] == 3
+
+
+def test_profiled_solve_counts_spmv(ctx, dev):
+    s = _system(10, n_cracks=5)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    T, st, rc = m.solve(tol=1e-10, profile=1)
+    assert rc == 0 and st["spmv_launches"] == st["iterations"] and st["spmv_ms"] > 0
