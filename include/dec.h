@@ -107,8 +107,13 @@ int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, const double*
 /* ---- assembly of L = d0^T *1 d0 ---------------------------------------
  * L_ij = -*1_e for e = (i, j), L_ii = sum of *1_e over the row's edges in
  * ascending column order, pattern fixed (zeros kept), no atomics.  Fills the
- * FP64 and FP32 CSR and sliced-ELL copies.  flags: DEC_ASM_DEFAULT. */
+ * FP64 and FP32 CSR (full static pattern) and the sliced-ELL copies the
+ * solver multiplies with.  By default the sliced-ELL copy leaves out edges
+ * whose geometric dual area is exactly zero (L_ij = -0 for every kappa and
+ * crack set), which leaves every product bit-for-bit unchanged;
+ * DEC_ASM_FULL_PATTERN keeps them. */
 #define DEC_ASM_DEFAULT 0u
+#define DEC_ASM_FULL_PATTERN 1u
 int dec_assemble(dec_mesh* m, uint32_t flags);
 
 /* ---- boundary data (eqs. 3-4, 12-13) -----------------------------------
@@ -158,7 +163,9 @@ typedef struct dec_solve_stats {
     double solve_ms;          /* wall time of the call on the stream (HIP events)          */
     int64_t spmv_launches;    /* profile: SpMV launches timed                              */
     double spmv_ms;           /* profile: summed duration of those launches                */
-    double spmv_bytes;        /* algorithmic bytes of one SpMV launch (CSR definition)     */
+    double spmv_bytes;        /* bytes one SpMV must move: CSR definition over the entries
+                                 the product uses (nnz (s+4) + 4 (V+1) + 2 V s)            */
+    int64_t spmv_nnz;         /* entries the product uses (full pattern or pruned)       */
 } dec_solve_stats;
 
 /* Fill opts with the defaults: FP64, Jacobi, tol 1e-10, inner_tol 1e-5,

@@ -148,8 +148,9 @@ class Mesh:
         self.ctx.check(rc, "dec_hodge1")
         return cut, star
 
-    def assemble(self):
-        self.ctx.check(self.lib.dec_assemble(self.handle, 0), "dec_assemble")
+    def assemble(self, full_pattern=False):
+        """Assemble L; the solver's sliced-ELL copy drops zero-dual-area edges unless full_pattern."""
+        self.ctx.check(self.lib.dec_assemble(self.handle, 1 if full_pattern else 0), "dec_assemble")
 
     def apply_bc(self, bc_type, bc_value, neumann_f0=None, want_rhs=True):
         npin = ctypes.c_int64()

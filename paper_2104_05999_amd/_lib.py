@@ -55,6 +55,7 @@ class SolveStats(ctypes.Structure):
         ("spmv_launches", ctypes.c_int64),
         ("spmv_ms", ctypes.c_double),
         ("spmv_bytes", ctypes.c_double),
+        ("spmv_nnz", ctypes.c_int64),
     ]
 
     def as_dict(self):

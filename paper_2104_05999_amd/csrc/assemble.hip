@@ -6,6 +6,9 @@
 // from the FP64 CSR values.
 #include "common.h"
 
+struct SolveCache;
+void clear_graphs(SolveCache* c);
+
 namespace {
 
 __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nz_edge,
@@ -27,38 +30,66 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
     }
 }
 
+// Entries kept in the sliced-ELL copy: the diagonal and every edge whose
+// geometric factor |*e| / |e| is not exactly zero.  An edge with zero dual
+// area has L_ij = -kappa * 0 = -0 for every conductivity and crack set, and
+// adding its product to a row sum changes nothing, so the product y = A x is
+// bit-for-bit that of the full static pattern (which the CSR keeps).
+__device__ __forceinline__ bool kept(int32_t k, const int32_t* __restrict__ nz_edge, const double* __restrict__ geo) {
+    const int32_t e = nz_edge[k];
+    return e < 0 || geo == nullptr || geo[e] != 0.0;
+}
+
 __global__ void k_sell_width(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
+                             const int32_t* __restrict__ nz_edge, const double* __restrict__ geo,
                              int32_t* __restrict__ width64) {
     GRID_STRIDE_LOOP(s, nslices) {
         int w = 0;
         const int64_t r0 = s * SELL_C;
-        for (int64_t r = r0; r < r0 + SELL_C && r < V; ++r) w = max(w, row_ptr[r + 1] - row_ptr[r]);
+        for (int64_t r = r0; r < r0 + SELL_C && r < V; ++r) {
+            int len = 0;
+            for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) len += kept(k, nz_edge, geo);
+            w = max(w, len);
+        }
         width64[s] = w * SELL_C;  // entries in the slice
     }
 }
 
 __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
-                            const int32_t* __restrict__ col, const int64_t* __restrict__ sptr,
+                            const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
+                            const double* __restrict__ geo, const int64_t* __restrict__ sptr,
                             int32_t* __restrict__ scol, int32_t* __restrict__ ssrc) {
     GRID_STRIDE_LOOP(i, nslices * SELL_C) {
         const int64_t s = i / SELL_C;
         const int lane = static_cast<int>(i % SELL_C);
         const int64_t row = i;
         const int width = static_cast<int>((sptr[s + 1] - sptr[s]) / SELL_C);
-        const int32_t b = row < V ? row_ptr[row] : 0;
-        const int len = row < V ? row_ptr[row + 1] - b : 0;
         const int32_t pad_col = static_cast<int32_t>(row < V ? row : V - 1);
-        for (int j = 0; j < width; ++j) {
-            const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
-            if (j < len) {
-                scol[idx] = col[b + j];
-                ssrc[idx] = b + j;
-            } else {
-                scol[idx] = pad_col;
-                ssrc[idx] = -1;
+        int j = 0;
+        if (row < V) {
+            for (int32_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
+                if (!kept(k, nz_edge, geo)) continue;
+                const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+                scol[idx] = col[k];
+                ssrc[idx] = k;
+                ++j;
             }
         }
+        for (; j < width; ++j) {
+            const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+            scol[idx] = pad_col;
+            ssrc[idx] = -1;
+        }
     }
+}
+
+__global__ void k_count_kept(int64_t nnz, const int32_t* __restrict__ nz_edge, const double* __restrict__ geo,
+                             unsigned long long* __restrict__ count) {
+    __shared__ unsigned long long lds[BLOCK / 64];
+    unsigned long long c = 0;
+    GRID_STRIDE_LOOP(k, nnz) c += kept((int32_t)k, nz_edge, geo);
+    c = block_sum(c, lds);
+    if (threadIdx.x == 0 && c) atomicAdd(count, c);
 }
 
 __global__ void k_sell_values(int64_t n, const int32_t* __restrict__ ssrc, const double* __restrict__ v64,
@@ -78,16 +109,23 @@ void build_sell_pattern(dec_mesh* m) {
     S.nslices = (m->V + SELL_C - 1) / SELL_C;
     DBuf<int32_t> w;
     w.alloc(ctx, S.nslices);
+    const double* geo = m->prune_geometric_zeros ? m->geo.p : nullptr;
     hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices)), dim3(BLOCK), 0, ctx->stream, m->V, S.nslices,
-                       m->row_ptr.p, w.p);
+                       m->row_ptr.p, m->nz_edge.p, geo, w.p);
     S.ptr.alloc(ctx, S.nslices + 1);
     S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
+    DBuf<unsigned long long> cnt;
+    cnt.alloc(ctx, 1);
+    cnt.zero();
+    hipLaunchKernelGGL(k_count_kept, dim3(grid_for(m->nnz, BLOCK, 4096)), dim3(BLOCK), 0, ctx->stream, m->nnz,
+                       m->nz_edge.p, geo, cnt.p);
+    S.kept = (int64_t) * static_cast<unsigned long long*>(ctx->readback(cnt.p, sizeof(unsigned long long)));
     S.col.alloc(ctx, S.entries);
     S.src.alloc(ctx, S.entries);
     S.val64.alloc(ctx, S.entries);
     S.val32.alloc(ctx, S.entries);
     hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
-                       S.nslices, m->row_ptr.p, m->col.p, S.ptr.p, S.col.p, S.src.p);
+                       S.nslices, m->row_ptr.p, m->col.p, m->nz_edge.p, geo, S.ptr.p, S.col.p, S.src.p);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -119,8 +157,14 @@ void assemble_device(dec_mesh* m) {
 extern "C" int dec_assemble(dec_mesh* m, uint32_t flags) {
     if (!m) return DEC_EINVAL;
     try {
-        DEC_REQUIRE(flags == DEC_ASM_DEFAULT, DEC_EINVAL, "unknown assembly flags");
+        DEC_REQUIRE((flags & ~DEC_ASM_FULL_PATTERN) == 0, DEC_EINVAL, "unknown assembly flags");
         m->ctx->set_device();
+        const bool prune = !(flags & DEC_ASM_FULL_PATTERN);
+        if (m->sell.nslices && prune != m->prune_geometric_zeros) {
+            m->sell = SellMatrix();  // rebuild the sliced-ELL pattern for the other choice
+            if (m->solve) clear_graphs(m->solve);
+        }
+        m->prune_geometric_zeros = prune;
         assemble_device(m);
     } catch (const DecError& e) {
         m->ctx->last_error = e.msg;

@@ -2,8 +2,8 @@
 //
 // * Parts of the mesh that cracks cut off from every Dirichlet vertex
 //   (connected components of the graph of edges with *1 != 0) have no unique
-//   solution; they are found by monotone reachability sweeps from the
-//   Dirichlet set and pinned to T = 0.
+//   solution; they are found with a union-find over those edges and pinned
+//   to T = 0.
 // * Neumann faces load b_v -= f0_v A*_{v,f}, A*_{v,f} the circumcentric
 //   part of boundary face f belonging to vertex v.
 // * Dirichlet and pinned rows/columns are eliminated symmetrically: for a
@@ -52,43 +52,65 @@ __device__ __forceinline__ int vget(const int4& q, int k) {
 }
 
 __global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const double* __restrict__ bc_value,
-                          uint32_t* __restrict__ reach, double* __restrict__ dval, unsigned* __restrict__ err) {
+                          int32_t* __restrict__ parent, double* __restrict__ dval, unsigned* __restrict__ err) {
     GRID_STRIDE_LOOP(v, V) {
         const int8_t t = bc_type[v];
         if (t < 0 || t > 2) atomicOr(err, 1u);
-        reach[v] = (t == 1);
+        parent[v] = (int32_t)v;
         dval[v] = (t == 1) ? bc_value[v] : 0.0;
     }
 }
 
-// One monotone sweep: a vertex becomes reached when a neighbour across an
-// edge with *1 != 0 is reached.  Reads may see updates of the same sweep;
-// the fixed point (the set reachable from the Dirichlet vertices) is unique.
-__global__ void k_reach_sweep(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                              const int32_t* __restrict__ nz_edge, const double* __restrict__ star1,
-                              uint32_t* reach, unsigned* changed) {
-    GRID_STRIDE_LOOP(v, V) {
-        if (reach[v]) continue;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t e = nz_edge[k];
-            if (e < 0 || star1[e] == 0.0) continue;
-            if (__hip_atomic_load(reach + col[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __hip_atomic_store(reach + v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *changed = 1u;
-                break;
+// Connected components of the graph of edges with *1 != 0, by lock-free
+// union-find: the larger of two roots is hooked under the smaller with a
+// compare-and-swap, so parent[v] <= v always holds, every find ends, and the
+// root of a component is its smallest vertex (a label independent of
+// scheduling).  A failed swap means another thread hooked that root; the
+// loop then continues from the new root.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t v) {
+    while (true) {
+        const int32_t p = __hip_atomic_load(parent + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == v) return v;
+        v = p;
+    }
+}
+
+__global__ void k_uf_hook(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ star1,
+                          int32_t* parent) {
+    GRID_STRIDE_LOOP(e, E) {
+        if (star1[e] == 0.0) continue;
+        int32_t ra = uf_find(parent, edges[2 * e]);
+        int32_t rb = uf_find(parent, edges[2 * e + 1]);
+        while (ra != rb) {
+            if (ra > rb) {
+                const int32_t t = ra;
+                ra = rb;
+                rb = t;
             }
+            const int32_t old = atomicCAS(parent + rb, rb, ra);
+            if (old == rb) break;
+            rb = uf_find(parent, old);
+            ra = uf_find(parent, ra);
         }
     }
 }
 
-__global__ void k_mark_fixed(int64_t V, const int8_t* __restrict__ bc_type, const uint32_t* __restrict__ reach,
-                             uint8_t* __restrict__ fixed, unsigned long long* __restrict__ n_pinned) {
+__global__ void k_uf_anchor(int64_t V, const int8_t* __restrict__ bc_type, int32_t* parent,
+                            uint32_t* __restrict__ anchored) {
+    GRID_STRIDE_LOOP(v, V) {
+        if (bc_type[v] == 1) anchored[uf_find(parent, (int32_t)v)] = 1u;
+    }
+}
+
+__global__ void k_mark_fixed(int64_t V, const int8_t* __restrict__ bc_type, int32_t* parent,
+                             const uint32_t* __restrict__ anchored, uint8_t* __restrict__ fixed,
+                             unsigned long long* __restrict__ n_pinned) {
     unsigned long long local = 0;
     GRID_STRIDE_LOOP(v, V) {
         uint8_t f = 0;
         if (bc_type[v] == 1)
             f = 1;
-        else if (!reach[v]) {
+        else if (!anchored[uf_find(parent, (int32_t)v)]) {
             f = 2;
             ++local;
         }
@@ -190,34 +212,28 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     DBuf<unsigned> flags;
     flags.alloc(ctx, 16);
     flags.zero();
-    DBuf<uint32_t> reach;
-    reach.alloc(ctx, V);
+    DBuf<int32_t> parent;
+    parent.alloc(ctx, V);
     m->bc_value.alloc(ctx, V);
-    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, bc_value, reach.p,
+    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, bc_value, parent.p,
                        m->bc_value.p, flags.p);
     HIP_CHECK(hipGetLastError());
     unsigned e0 = *static_cast<unsigned*>(ctx->readback(flags.p, sizeof(unsigned)));
     DEC_REQUIRE(e0 == 0, DEC_EINVAL, "bc_type must be 0, 1 or 2");
 
-    // reachability from the Dirichlet set, 8 sweeps per host check; stop
-    // after a batch whose last sweep changed nothing
-    const unsigned g = grid_for(V);
-    for (int batch = 0;; ++batch) {
-        DEC_REQUIRE(batch < (int)(V / 8 + 16), DEC_EINVAL, "reachability did not settle");
-        HIP_CHECK(hipMemsetAsync(flags.p + 1, 0, 8 * sizeof(unsigned), s));
-        for (int k = 0; k < 8; ++k)
-            hipLaunchKernelGGL(k_reach_sweep, dim3(g), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
-                               m->star1.p, reach.p, flags.p + 1 + k);
-        HIP_CHECK(hipGetLastError());
-        unsigned ch[8];
-        std::memcpy(ch, ctx->readback(flags.p + 1, sizeof(ch)), sizeof(ch));
-        if (ch[7] == 0) break;
-    }
+    // parts of the graph of edges with *1 != 0 holding no Dirichlet vertex are pinned
+    hipLaunchKernelGGL(k_uf_hook, dim3(grid_for(m->E)), dim3(BLOCK), 0, s, m->E, m->edges.p, m->star1.p, parent.p);
+    DBuf<uint32_t> anchored;
+    anchored.alloc(ctx, V);
+    anchored.zero();
+    hipLaunchKernelGGL(k_uf_anchor, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, parent.p, anchored.p);
     m->fixed.alloc(ctx, V);
     DBuf<unsigned long long> npin;
     npin.alloc(ctx, 1);
     npin.zero();
-    hipLaunchKernelGGL(k_mark_fixed, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, reach.p, m->fixed.p, npin.p);
+    hipLaunchKernelGGL(k_mark_fixed, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, parent.p, anchored.p,
+                       m->fixed.p, npin.p);
+    HIP_CHECK(hipGetLastError());
     DBuf<double> gload;
     if (f0) {
         gload.alloc(ctx, V);

@@ -104,7 +104,8 @@ constexpr int SELL_C = 64;
 
 struct SellMatrix {
     int64_t nslices = 0;
-    int64_t entries = 0;
+    int64_t entries = 0;  // stored entries, padding included
+    int64_t kept = 0;     // entries of the pattern the product uses
     DBuf<int64_t> ptr;   // [nslices + 1]
     DBuf<int32_t> col;   // [entries]
     DBuf<int32_t> src;   // [entries]: CSR entry index, -1 for padding
@@ -146,6 +147,7 @@ struct dec_mesh {
     DBuf<double> val64;      // [nnz]
     DBuf<float> val32;       // [nnz]
     SellMatrix sell;
+    bool prune_geometric_zeros = true;  // sliced-ELL drops edges with |*e| = 0
 
     // Hodge star
     bool geo_ready = false;
@@ -211,7 +213,9 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
 
 // Called by every thread of a block after thread 0 has stored the block's
 // partial results.  Returns true in the block that finishes last; its loads
-// after this point see every other block's partials.
+// after this point see every other block's partials.  (Used only where one
+// launch per call is made; the solver's per-iteration kernels instead reduce
+// the previous kernel's partials redundantly, see reduce_bcast.)
 __device__ __forceinline__ bool last_block_arrived(unsigned* counter) {
     __shared__ int am_last;
     __syncthreads();
@@ -237,6 +241,18 @@ __device__ __forceinline__ T reduce_partials(const T* partials, int n, T* lds) {
     T acc = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) acc += coherent_load(partials + i);
     return block_sum(acc, lds);
+}
+
+// Fixed-order sum of `n` partials written by an earlier kernel, returned to
+// every thread of the block.  lds holds BLOCK/64 + 1 doubles.
+__device__ __forceinline__ double reduce_bcast(const double* __restrict__ partials, int n, double* lds) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
+    const double t = block_sum(acc, lds);
+    __syncthreads();
+    if (threadIdx.x == 0) lds[BLOCK / 64] = t;
+    __syncthreads();
+    return lds[BLOCK / 64];
 }
 
 // ---------------------------------------------------------------- host primitives

@@ -14,19 +14,25 @@
 // batches of iterations (optionally a captured hipGraph) and reads the
 // state once per batch.
 #include <cmath>
+#include <cstdlib>
 
 #include "solver.h"
 
 namespace {
 
 enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
+// regions of the partials array, G doubles each
+enum { R_PQ = 0, R_RR = 1, R_RZ = 2 };
+enum { FIN_NORM2 = 0, FIN_RR = 1, FIN_START = 2 };
 
 // ---------------------------------------------------------------- SpMV kernels
-template <class VT, int MODE, int U>
+// y = A x (PLAIN), y = A x with per-block partials of x.y (DOT), or
+// y = b - A x with per-block partials of y.y (RESID).
+template <class VT, int MODE, int U, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
-                                                PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
+                                                const PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64 + 1];
     if (MODE == MODE_DOT && st->done) return;
     int64_t s0, s1;
     block_range(A.nslices, &s0, &s1);
@@ -36,7 +42,7 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
         const int64_t base = A.ptr[s];
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;
-        const VT acc = sell_row<VT, U>(A, base, width, lane, x);
+        const VT acc = sell_row<VT, U, NT>(A, base, width, lane, x);
         if (row < A.V) {
             if (MODE == MODE_RESID) {
                 const VT ri = b[row] - acc;
@@ -51,22 +57,6 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
     if (MODE == MODE_PLAIN) return;
     const double bs = block_sum(static_cast<double>(d), lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_arrived(&st->counter)) {
-        const double tot = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            if (MODE == MODE_DOT) {
-                st->pq = tot;
-                if (!(tot > 0.0) || !isfinite(tot))
-                    st->done = PCG_BREAKDOWN;
-                else
-                    st->alpha = st->rho / tot;
-            } else {
-                st->rr = tot;
-                st->aux = tot;
-            }
-            st->counter = 0;
-        }
-    }
 }
 
 template <class VT>
@@ -74,25 +64,15 @@ __global__ void k_csr_plain(CsrView<VT> A, const VT* __restrict__ x, VT* __restr
     GRID_STRIDE_LOOP(row, A.V) y[row] = csr_row(A, row, x);
 }
 
-// ---------------------------------------------------------------- vector kernels
-// b.b into st->aux (and rr_stop = tol2 * b.b)
-__global__ void k_norm2(int64_t V, const double* __restrict__ b, double tol2, double* __restrict__ partials,
-                        PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
+// ---------------------------------------------------------------- start-up kernels
+__global__ void k_norm2(int64_t V, const double* __restrict__ b, double* __restrict__ partials) {
+    __shared__ double lds[BLOCK / 64 + 1];
     int64_t i0, i1;
     block_range(V, &i0, &i1);
     double s = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) s += b[i] * b[i];
     const double bs = block_sum(s, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_arrived(&st->counter)) {
-        const double tot = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            st->aux = tot;
-            st->rr_stop = tol2 * tot;
-            st->counter = 0;
-        }
-    }
 }
 
 __global__ void k_reset(PcgScalars* st, int64_t max_iter) {
@@ -100,8 +80,33 @@ __global__ void k_reset(PcgScalars* st, int64_t max_iter) {
         st->iter = 0;
         st->max_iter = max_iter;
         st->done = PCG_RUNNING;
-        st->counter = 0;
         st->rho = st->pq = st->alpha = st->beta = 0.0;
+    }
+}
+
+// One block: fold the partials of the previous kernel(s) into the state.
+//   FIN_NORM2: aux = sum(R_RR), rr_stop = factor * aux
+//   FIN_RR:    rr = aux = sum(R_RR)
+//   FIN_START: rr = sum(R_RR), rho = sum(R_RZ), iteration 0; rr_stop =
+//              factor * rr when `relative`, else kept; done when rr <= rr_stop
+__global__ void k_finalize(const double* __restrict__ partials, int P, int n_rr, int n_rz, int what, double factor,
+                           int relative, PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const double rr = reduce_bcast(partials + R_RR * P, n_rr, lds);
+    const double rz = what == FIN_START ? reduce_bcast(partials + R_RZ * P, n_rz, lds) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (what == FIN_NORM2) {
+        st->aux = rr;
+        st->rr_stop = factor * rr;
+    } else if (what == FIN_RR) {
+        st->rr = rr;
+        st->aux = rr;
+    } else {
+        st->rr = rr;
+        st->rho = rz;
+        if (relative) st->rr_stop = factor * rr;
+        st->iter = 0;
+        st->done = (rr <= st->rr_stop) ? PCG_CONVERGED : (isfinite(rz) ? PCG_RUNNING : PCG_BREAKDOWN);
     }
 }
 
@@ -115,12 +120,11 @@ __global__ void k_init_x(int64_t V, const uint8_t* __restrict__ fixed, const dou
     }
 }
 
-// Jacobi start: z = D^-1 r, p = z, rho = r.z; rr_stop = factor * (relative ? r.r : rr_stop_base)
+// Jacobi start: z = D^-1 r, p = z, partials of r.z
 template <class VT>
 __global__ void k_init_jacobi(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd, VT* __restrict__ p,
-                              double stop_factor, int relative, double* __restrict__ partials,
-                              PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
+                              double* __restrict__ partials) {
+    __shared__ double lds[BLOCK / 64 + 1];
     int64_t i0, i1;
     block_range(V, &i0, &i1);
     VT rz = 0;
@@ -132,28 +136,22 @@ __global__ void k_init_jacobi(int64_t V, const VT* __restrict__ r, const VT* __r
     }
     const double bs = block_sum(static_cast<double>(rz), lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_arrived(&st->counter)) {
-        const double tot = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            st->rho = tot;
-            if (relative) st->rr_stop = stop_factor * st->rr;
-            st->iter = 0;
-            st->done = (st->rr <= st->rr_stop) ? PCG_CONVERGED : PCG_RUNNING;
-            st->counter = 0;
-        }
-    }
 }
 
-// Jacobi iteration, part 2: x += alpha p, r -= alpha q, z = D^-1 r, r.z, r.r;
-// the last block decides convergence and forms beta.
-template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_update_jacobi(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
-                                                         const VT* __restrict__ p, const VT* __restrict__ q,
-                                                         const VT* __restrict__ invd, double* __restrict__ partials,
-                                                         PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
-    if (st->done) return;
-    const VT a = static_cast<VT>(st->alpha);
+// ---------------------------------------------------------------- iteration kernels
+// Every block folds the p.q partials of the SpMV in the same order, so all
+// blocks see the same alpha.  A non-positive p.q leaves x and r untouched;
+// the closing kernel reports the breakdown.
+template <class VT, bool JACOBI>
+__global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
+                                                  const VT* __restrict__ p, const VT* __restrict__ q,
+                                                  const VT* __restrict__ invd, double* __restrict__ partials,
+                                                  int P, int n_pq, const PcgScalars* __restrict__ S) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    if (S->done) return;
+    const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
+    if (!(pq > 0.0) || !isfinite(pq)) return;
+    const VT a = static_cast<VT>(S->rho / pq);
     int64_t i0, i1;
     block_range(V, &i0, &i1);
     VT rz = 0, rr = 0;
@@ -162,149 +160,98 @@ __global__ __launch_bounds__(BLOCK) void k_update_jacobi(int64_t V, VT* __restri
         const VT ri = r[i] - a * q[i];
         x[i] = xi;
         r[i] = ri;
-        rz += ri * (invd[i] * ri);
-        rr += ri * ri;
-    }
-    const int G = gridDim.x;
-    const double b1 = block_sum(static_cast<double>(rz), lds);
-    const double b2 = block_sum(static_cast<double>(rr), lds);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = b1;
-        partials[G + blockIdx.x] = b2;
-    }
-    if (last_block_arrived(&st->counter)) {
-        const double trz = reduce_partials(partials, G, lds);
-        const double trr = reduce_partials(partials + G, G, lds);
-        if (threadIdx.x == 0) {
-            st->rr = trr;
-            st->iter += 1;
-            if (!isfinite(trz) || !isfinite(trr))
-                st->done = PCG_BREAKDOWN;
-            else if (trr <= st->rr_stop)
-                st->done = PCG_CONVERGED;
-            else if (st->iter >= st->max_iter)
-                st->done = PCG_MAXITER;
-            else {
-                st->beta = trz / st->rho;
-                st->rho = trz;
-            }
-            st->counter = 0;
-        }
-    }
-}
-
-template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_p_jacobi(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
-                                                    VT* __restrict__ p, const PcgScalars* __restrict__ st) {
-    if (st->done) return;
-    const VT beta = static_cast<VT>(st->beta);
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) p[i] = invd[i] * r[i] + beta * p[i];
-}
-
-// FSAI iteration, part 2: x += alpha p, r -= alpha q, r.r and the convergence test
-template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_update_plain(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
-                                                        const VT* __restrict__ p, const VT* __restrict__ q,
-                                                        double* __restrict__ partials, PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
-    if (st->done) return;
-    const VT a = static_cast<VT>(st->alpha);
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
-    VT rr = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
-        const VT xi = x[i] + a * p[i];
-        const VT ri = r[i] - a * q[i];
-        x[i] = xi;
-        r[i] = ri;
+        if (JACOBI) rz += ri * (invd[i] * ri);
         rr += ri * ri;
     }
     const double b2 = block_sum(static_cast<double>(rr), lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = b2;
-    if (last_block_arrived(&st->counter)) {
-        const double trr = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            st->rr = trr;
-            st->iter += 1;
-            if (!isfinite(trr))
-                st->done = PCG_BREAKDOWN;
-            else if (trr <= st->rr_stop)
-                st->done = PCG_CONVERGED;
-            else if (st->iter >= st->max_iter)
-                st->done = PCG_MAXITER;
-            st->counter = 0;
-        }
+    if (threadIdx.x == 0) partials[R_RR * P + blockIdx.x] = b2;
+    if (JACOBI) {
+        const double b1 = block_sum(static_cast<double>(rz), lds);
+        if (threadIdx.x == 0) partials[R_RZ * P + blockIdx.x] = b1;
     }
 }
 
-// w = G r (rows of the lower-triangular factor)
+// w = G r (rows of the lower-triangular factor); S may be null (start-up)
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void k_fsai_g(CsrView<VT> G, const VT* __restrict__ r, VT* __restrict__ w,
-                                                  const PcgScalars* __restrict__ st) {
-    if (st->done) return;
+                                                  const PcgScalars* __restrict__ S) {
+    if (S && S->done) return;
     int64_t i0, i1;
     block_range(G.V, &i0, &i1);
     for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) w[i] = csr_row(G, i, r);
 }
 
-// z = G^T w and r.z.  init: p = z, rho = r.z, convergence test on the
-// current rr; iteration: beta = r.z / rho, rho = r.z.
+// z = G^T w (INIT: straight into p) and partials of r.z
 template <class VT, bool INIT>
 __global__ __launch_bounds__(BLOCK) void k_fsai_gt(CsrView<VT> GT, const VT* __restrict__ w, VT* __restrict__ z,
-                                                   const VT* __restrict__ r, VT* __restrict__ p, double stop_factor,
-                                                   int relative, double* __restrict__ partials,
-                                                   PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64];
-    if (!INIT && st->done) return;
+                                                   const VT* __restrict__ r, double* __restrict__ partials,
+                                                   int P, const PcgScalars* __restrict__ S) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    if (!INIT && S->done) return;
     int64_t i0, i1;
     block_range(GT.V, &i0, &i1);
     VT rz = 0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
         const VT zi = csr_row(GT, i, w);
-        if (INIT)
-            p[i] = zi;
-        else
-            z[i] = zi;
+        z[i] = zi;
         rz += r[i] * zi;
     }
     const double bs = block_sum(static_cast<double>(rz), lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_arrived(&st->counter)) {
-        const double tot = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            if (INIT) {
-                st->rho = tot;
-                if (relative) st->rr_stop = stop_factor * st->rr;
-                st->iter = 0;
-                st->done = (st->rr <= st->rr_stop) ? PCG_CONVERGED : PCG_RUNNING;
-            } else {
-                if (!isfinite(tot)) st->done = PCG_BREAKDOWN;
-                st->beta = tot / st->rho;
-                st->rho = tot;
-            }
-            st->counter = 0;
-        }
+    if (threadIdx.x == 0) partials[R_RZ * P + blockIdx.x] = bs;
+}
+
+// Close the iteration: fold p.q, r.r, r.z; decide breakdown / convergence /
+// iteration cap; p = z + beta p (z = D^-1 r for Jacobi); block 0 writes the
+// next state N.  A finished state is carried forward unchanged.
+template <class VT, bool JACOBI>
+__global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
+                                                 const VT* __restrict__ z, VT* __restrict__ p,
+                                                 const double* __restrict__ partials, int P, int n_pq,
+                                                 const PcgScalars* __restrict__ S, PcgScalars* __restrict__ N) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (S->done) {
+        if (lead) *N = *S;
+        return;
+    }
+    const int G = gridDim.x;
+    const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
+    const double rr = reduce_bcast(partials + R_RR * P, G, lds);
+    const double rz = reduce_bcast(partials + R_RZ * P, G, lds);
+    int done = PCG_RUNNING;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
+        done = PCG_BREAKDOWN;
+    else if (rr <= S->rr_stop)
+        done = PCG_CONVERGED;
+    else if (S->iter + 1 >= S->max_iter)
+        done = PCG_MAXITER;
+    const double beta = rz / S->rho;
+    if (done == PCG_RUNNING) {
+        const VT bt = static_cast<VT>(beta);
+        int64_t i0, i1;
+        block_range(V, &i0, &i1);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK)
+            p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * p[i];
+    }
+    if (lead) {
+        N->rho = rz;
+        N->rr = rr;
+        N->rr_stop = S->rr_stop;
+        N->aux = S->aux;
+        N->alpha = S->rho / pq;
+        N->beta = beta;
+        N->pq = pq;
+        N->iter = S->iter + (done == PCG_BREAKDOWN ? 0 : 1);
+        N->max_iter = S->max_iter;
+        N->done = done;
     }
 }
 
-template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_p_plain(int64_t V, const VT* __restrict__ z, VT* __restrict__ p,
-                                                   const PcgScalars* __restrict__ st) {
-    if (st->done) return;
-    const VT beta = static_cast<VT>(st->beta);
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) p[i] = z[i] + beta * p[i];
-}
-
 // ---------------------------------------------------------------- refinement kernels
-// r32 = r64 / ||r64|| (||r64||^2 in src->rr), x32 = 0, r32.r32 into dst->rr
+// r32 = r64 / ||r64|| (||r64||^2 in src->rr), x32 = 0, partials of r32.r32
 __global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgScalars* __restrict__ src,
-                         float* __restrict__ r32, float* __restrict__ x32, double* __restrict__ partials,
-                         PcgScalars* __restrict__ dst) {
-    __shared__ double lds[BLOCK / 64];
+                         float* __restrict__ r32, float* __restrict__ x32, double* __restrict__ partials) {
+    __shared__ double lds[BLOCK / 64 + 1];
     const double inv = 1.0 / sqrt(src->rr);
     int64_t i0, i1;
     block_range(V, &i0, &i1);
@@ -317,13 +264,6 @@ __global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgSca
     }
     const double bs = block_sum(static_cast<double>(s), lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-    if (last_block_arrived(&dst->counter)) {
-        const double tot = reduce_partials(partials, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            dst->rr = tot;
-            dst->counter = 0;
-        }
-    }
 }
 
 // x64 += ||r64|| * x32
@@ -340,60 +280,122 @@ struct Run {
     CsrView<VT> G, GT;
     VT *x, *r, *p, *q, *z, *w;
     const VT* invd;
-    PcgScalars* st;
+    PcgScalars* st;  // two parities
     int precond;
 };
 
-template <class VT, int MODE>
-void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, PcgScalars* st) {
-    double* part = c->partials.p;
-    switch (c->unroll) {
+template <class VT, int MODE, bool NT>
+void launch_sell_nt(SolveCache* c, int unroll, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                    const PcgScalars* st) {
+    const dim3 g(c->Gs), blk(BLOCK);
+    switch (unroll) {
         case 4:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 4>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            hipLaunchKernelGGL((k_sell<VT, MODE, 4, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
             break;
         case 16:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 16>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            hipLaunchKernelGGL((k_sell<VT, MODE, 16, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
             break;
         default:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 8>), dim3(c->G), dim3(BLOCK), 0, c->stream, A, x, y, b, part, st);
+            hipLaunchKernelGGL((k_sell<VT, MODE, 8, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
             break;
     }
 }
 
 template <class VT>
-void enqueue_iteration(SolveCache* c, const Run<VT>& R, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+constexpr int prec_index() {
+    return sizeof(VT) == 8 ? 0 : 1;
+}
+
+// SpMV launch on Gs blocks; MODE_DOT / MODE_RESID leave Gs partials in `part`
+template <class VT, int MODE>
+void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                 const PcgScalars* st) {
+    const int pi = prec_index<VT>();
+    if (c->nt[pi])
+        launch_sell_nt<VT, MODE, true>(c, c->unroll[pi], A, x, y, b, part, st);
+    else
+        launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st);
+}
+
+// Pick the sliced-ELL variant (unroll 4/8, non-temporal loads on/off) by
+// timing y = A x on this matrix.  All variants sum every row in the same
+// order, so the choice never changes a result.
+template <class VT>
+void autotune_spmv(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y) {
+    const int pi = prec_index<VT>();
+    if (c->tuned[pi] || c->pinned_variant) return;
+    const int cand[4][2] = {{8, 1}, {8, 0}, {4, 1}, {4, 0}};
+    float best = 1e30f;
+    int pick = 0;
+    for (int k = 0; k < 4; ++k) {
+        c->unroll[pi] = cand[k][0];
+        c->nt[pi] = cand[k][1];
+        launch_sell<VT, MODE_PLAIN>(c, A, x, y, nullptr, nullptr, nullptr);
+        HIP_CHECK(hipEventRecord(c->t0, c->stream));
+        for (int r = 0; r < 3; ++r) launch_sell<VT, MODE_PLAIN>(c, A, x, y, nullptr, nullptr, nullptr);
+        HIP_CHECK(hipEventRecord(c->t1, c->stream));
+        HIP_CHECK(hipEventSynchronize(c->t1));
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, c->t0, c->t1));
+        if (ms < best) {
+            best = ms;
+            pick = k;
+        }
+    }
+    c->unroll[pi] = cand[pick][0];
+    c->nt[pi] = cand[pick][1];
+    c->tuned[pi] = true;
+}
+
+int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
+double* region(SolveCache* c, int r) { return c->partials.p + (int64_t)r * stride(c); }
+
+// n_rr: blocks of the kernel that left the r.r partials; r.z partials always come from a G-block kernel
+void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, PcgScalars* st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, c->partials.p, stride(c), n_rr, c->G, what,
+                       factor, relative, st);
+}
+
+template <class VT>
+void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a = nullptr,
+                       hipEvent_t ev_b = nullptr) {
     const int64_t V = R.A.V;
+    const int G = c->G, P = stride(c), n_pq = c->Gs;
+    double* part = c->partials.p;
+    PcgScalars* S = R.st + par;
+    PcgScalars* N = R.st + (par ^ 1);
     if (ev_a) HIP_CHECK(hipEventRecord(ev_a, c->stream));
-    launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, R.st);
+    launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S);
     if (ev_b) HIP_CHECK(hipEventRecord(ev_b, c->stream));
     if (R.precond == DEC_PRECOND_JACOBI) {
-        hipLaunchKernelGGL(k_update_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
-                           c->partials.p, R.st);
-        hipLaunchKernelGGL(k_p_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p, R.st);
+        hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
+                           part, P, n_pq, S);
+        hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, (const VT*)nullptr,
+                           R.p, part, P, n_pq, S, N);
     } else {
-        hipLaunchKernelGGL(k_update_plain<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
-                           c->partials.p, R.st);
-        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w, R.st);
-        hipLaunchKernelGGL((k_fsai_gt<VT, false>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r,
-                           (VT*)nullptr, 0.0, 0, c->partials.p, R.st);
-        hipLaunchKernelGGL(k_p_plain<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.z, R.p, R.st);
+        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
+                           (const VT*)nullptr, part, P, n_pq, S);
+        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w, S);
+        hipLaunchKernelGGL((k_fsai_gt<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r, part, P,
+                           S);
+        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, (const VT*)nullptr, R.z,
+                           R.p, part, P, n_pq, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }
 
-// residual r = b - A x (r.r into st->rr), then the preconditioner start
+// preconditioner start from r (r.r partials already in R_RR): p = M^-1 r, partials of r.z
 template <class VT>
-void enqueue_start(SolveCache* c, const Run<VT>& R, const VT* b, double stop_factor, int relative) {
+void enqueue_precond_start(SolveCache* c, const Run<VT>& R) {
     const int64_t V = R.A.V;
-    if (b) launch_sell<VT, MODE_RESID>(c, R.A, R.x, R.r, b, R.st);
     if (R.precond == DEC_PRECOND_JACOBI) {
         hipLaunchKernelGGL(k_init_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
-                           stop_factor, relative, c->partials.p, R.st);
+                           region(c, R_RZ));
     } else {
         hipLaunchKernelGGL(k_fsai_g<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w,
-                           (const PcgScalars*)(c->st.p + 2));
-        hipLaunchKernelGGL((k_fsai_gt<VT, true>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r, R.p,
-                           stop_factor, relative, c->partials.p, R.st);
+                           (const PcgScalars*)nullptr);
+        hipLaunchKernelGGL((k_fsai_gt<VT, true>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.p, R.r,
+                           c->partials.p, stride(c), (const PcgScalars*)nullptr);
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -406,10 +408,16 @@ PcgScalars read_state(SolveCache* c, const PcgScalars* st) {
     return h;
 }
 
-// Run batches of iterations until the state says done.  Returns the final state.
+int even_chunk(const dec_solve_opts& o) {
+    int chunk = o.chunk > 0 ? o.chunk : 32;
+    return chunk < 2 ? 2 : (chunk + 1) / 2 * 2;
+}
+
+// Run batches of iterations (an even number each, so that the current state
+// is copy 0 after every batch) until the state says done.
 template <class VT>
 PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec_solve_stats* stats) {
-    const int chunk = o.chunk > 0 ? o.chunk : 32;
+    const int chunk = even_chunk(o);
     const int prec = sizeof(VT) == 8 ? 0 : 1;
     int64_t last_iter = -1;
     for (int64_t batch = 0;; ++batch) {
@@ -422,7 +430,7 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
                 c->events.push_back(e);
             }
             const PcgScalars before = read_state(c, R.st);
-            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, c->events[2 * k], c->events[2 * k + 1]);
+            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, k & 1, c->events[2 * k], c->events[2 * k + 1]);
             const PcgScalars after = read_state(c, R.st);
             const int64_t ran = after.iter - before.iter;
             for (int64_t k = 0; k < ran && k < chunk; ++k) {
@@ -439,13 +447,13 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             continue;
         }
         if (o.use_graph) {
-            GraphKey key{prec, R.precond, chunk, c->unroll};
+            GraphKey key{prec, R.precond, chunk, c->unroll[prec], c->nt[prec]};
             auto it = c->graphs.find(key);
             hipGraphExec_t exec = nullptr;
             if (it == c->graphs.end()) {
                 hipGraph_t g;
                 HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R);
+                for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, k & 1);
                 HIP_CHECK(hipStreamEndCapture(c->stream, &g));
                 HIP_CHECK(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
                 HIP_CHECK(hipGraphDestroy(g));
@@ -455,7 +463,7 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             }
             HIP_CHECK(hipGraphLaunch(exec, c->stream));
         } else {
-            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R);
+            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, k & 1);
         }
         const PcgScalars s = read_state(c, R.st);
         if (s.done) return s;
@@ -493,19 +501,22 @@ Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
     R.z = c->z32.p;
     R.w = c->w32.p;
     R.invd = m->invdiag32.p;
-    R.st = c->st.p + 1;
+    R.st = c->st.p + 2;
     R.precond = precond;
     return R;
 }
 
-// true FP64 residual of x64 against b: ||b - A x||^2 (via t64)
+SellView<double> sell64(dec_mesh* m) {
+    return SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V};
+}
+
+// ||b - A x64||^2 in FP64 (through t64), via the scratch state
 double true_rr(dec_mesh* m, SolveCache* c) {
-    Run<double> R = run64(m, c, DEC_PRECOND_JACOBI);
-    PcgScalars* s2 = c->st.p + 2;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
-    launch_sell<double, MODE_RESID>(c, R.A, c->x64.p, c->t64.p, m->rhs.p, s2);
+    PcgScalars* s4 = c->st.p + 4;
+    launch_sell<double, MODE_RESID>(c, sell64(m), c->x64.p, c->t64.p, m->rhs.p, region(c, R_RR), nullptr);
+    finalize(c, FIN_RR, c->Gs, 0.0, 0, s4);
     HIP_CHECK(hipGetLastError());
-    return read_state(c, s2).rr;
+    return read_state(c, s4).rr;
 }
 
 // FP64 PCG from the current x64.  Returns a DEC status.
@@ -517,9 +528,13 @@ int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int
     for (int restart = 0;; ++restart) {
         const int64_t left = o.max_iters - total;
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left > 0 ? left : (int64_t)1);
-        // rr_stop = tol^2 b.b (absolute form of the relative test)
-        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, tol2, c->partials.p, R.st);
-        enqueue_start<double>(c, R, m->rhs.p, 0.0, 0);
+        // rr_stop = tol^2 b.b (the relative test in absolute form)
+        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, region(c, R_RR));
+        finalize(c, FIN_NORM2, c->G, tol2, 0, R.st);
+        launch_sell<double, MODE_RESID>(c, R.A, R.x, R.r, m->rhs.p, region(c, R_RR), nullptr);
+        enqueue_precond_start<double>(c, R);
+        finalize(c, FIN_START, c->Gs, 0.0, 0, R.st);
+        HIP_CHECK(hipGetLastError());
         PcgScalars s = read_state(c, R.st);
         if (!s.done) {
             if (left <= 0) {
@@ -542,17 +557,15 @@ int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int
 
 int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec_solve_stats* stats) {
     Run<float> R = run32(m, c, o.precond);
-    PcgScalars* s2 = c->st.p + 2;
+    PcgScalars* s4 = c->st.p + 4;
     const double bn = sqrt(bb);
     double rn_prev = INFINITY;
     int64_t inner_total = 0;
     for (int outer = 0; outer < 100; ++outer) {
-        // r64 = b - A x64 (FP64), ||r64||^2 into s2->rr
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
-        launch_sell<double, MODE_RESID>(c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p,
-                                                            m->sell.nslices, m->V},
-                                        c->x64.p, c->r64.p, m->rhs.p, s2);
-        const double rn = sqrt(read_state(c, s2).rr);
+        // r64 = b - A x64 (FP64), ||r64||^2 into s4->rr
+        launch_sell<double, MODE_RESID>(c, sell64(m), c->x64.p, c->r64.p, m->rhs.p, region(c, R_RR), nullptr);
+        finalize(c, FIN_RR, c->Gs, 0.0, 0, s4);
+        const double rn = sqrt(read_state(c, s4).rr);
         if (stats) stats->outer_iterations = outer;
         if (rn <= o.tol * bn) return DEC_OK;
         if (outer > 0 && rn > 0.5 * rn_prev) {
@@ -571,14 +584,16 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         const int64_t left = o.max_iters - inner_total;
         if (left <= 0) return DEC_ENOTCONV;
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left);
-        hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s2, c->r32.p, c->x32.p,
-                           c->partials.p, R.st);
-        enqueue_start<float>(c, R, nullptr, itol * itol, 1);
+        hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s4, c->r32.p, c->x32.p,
+                           region(c, R_RR));
+        enqueue_precond_start<float>(c, R);
+        finalize(c, FIN_START, c->G, itol * itol, 1, R.st);
+        HIP_CHECK(hipGetLastError());
         PcgScalars s = read_state(c, R.st);
         if (!s.done) s = iterate(c, R, o, stats);
         inner_total += s.iter;
         if (stats) stats->iterations = inner_total;
-        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, s2);
+        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, s4);
         HIP_CHECK(hipGetLastError());
         rn_prev = rn;
     }
@@ -618,15 +633,30 @@ SolveCache* get_solve_cache(dec_mesh* m) {
         HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreate(&c->t0));
         HIP_CHECK(hipEventCreate(&c->t1));
-        // one block per 256 rows up to 8 resident blocks per CU, multiple of 8
-        int64_t want = (m->V + BLOCK - 1) / BLOCK;
-        int64_t cap = 8 * (int64_t)m->ctx->num_cus;
-        int64_t G = want < cap ? want : cap;
-        G = ((G + 7) / 8) * 8;
-        c->G = (int)G;
-        c->partials.alloc(m->ctx, 2 * G);
-        c->st.alloc(m->ctx, 3);
-        HIP_CHECK(hipMemsetAsync(c->st.p, 0, 3 * sizeof(PcgScalars), c->stream));
+        // one block per 256 rows (64 rows for the SpMV) up to a fixed number of
+        // blocks per CU, rounded to a multiple of 8 (one share per XCD)
+        int per_cu = 4, per_cu_s = 8;
+        if (const char* env = getenv("DEC_BLOCKS_PER_CU")) per_cu = atoi(env) > 0 ? atoi(env) : per_cu;
+        if (const char* env = getenv("DEC_SPMV_BLOCKS_PER_CU")) per_cu_s = atoi(env) > 0 ? atoi(env) : per_cu_s;
+        if (const char* env = getenv("DEC_SELL_UNROLL")) {
+            c->unroll[0] = c->unroll[1] = atoi(env);
+            c->pinned_variant = true;
+        }
+        if (const char* env = getenv("DEC_SELL_NT")) {
+            c->nt[0] = c->nt[1] = atoi(env);
+            c->pinned_variant = true;
+        }
+        auto blocks = [&](int64_t rows_per_block, int pc) {
+            const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
+            const int64_t cap = (int64_t)pc * m->ctx->num_cus;
+            const int64_t g = want < cap ? want : cap;
+            return (int)(((g + 7) / 8) * 8);
+        };
+        c->G = blocks(BLOCK, per_cu);
+        c->Gs = blocks(SELL_C * (BLOCK / 64), per_cu_s);
+        c->partials.alloc(m->ctx, 3 * (int64_t)stride(c));
+        c->st.alloc(m->ctx, 6);
+        HIP_CHECK(hipMemsetAsync(c->st.p, 0, 6 * sizeof(PcgScalars), c->stream));
         (void)m->ctx->readback(c->st.p, 8);  // make sure the pinned staging area exists
     } catch (...) {
         destroy_solve_cache(c);
@@ -668,23 +698,28 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         ctx->set_device();
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
-            stats->spmv_bytes = (double)m->nnz * (8.0 + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * 8.0 * (double)m->V;
-            if (o.precision == DEC_PREC_MIXED)
-                stats->spmv_bytes = (double)m->nnz * (4.0 + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * 4.0 * (double)m->V;
+            const double s = o.precision == DEC_PREC_MIXED ? 4.0 : 8.0, nz = (double)m->sell.kept;
+            stats->spmv_nnz = m->sell.kept;
+            stats->spmv_bytes = nz * (s + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
         }
         SolveCache* c = get_solve_cache(m);
         if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
         ensure_vectors(m, c, o.precision);
         ctx->sync();  // inputs written on the caller's stream are complete
+        autotune_spmv<double>(c, sell64(m), c->p64.p, c->q64.p);
+        if (o.precision == DEC_PREC_MIXED)
+            autotune_spmv<float>(c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices,
+                                                    m->V},
+                                 c->p32.p, c->q32.p);
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
                            m->bc_value.p, o.warm_start ? T : nullptr, c->x64.p);
         // b.b
-        PcgScalars* s2 = c->st.p + 2;
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, s2, (int64_t)0);
-        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, 0.0, c->partials.p, s2);
+        PcgScalars* s4 = c->st.p + 4;
+        hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, region(c, R_RR));
+        finalize(c, FIN_NORM2, c->G, 0.0, 0, s4);
         HIP_CHECK(hipGetLastError());
-        const double bb = read_state(c, s2).aux;
+        const double bb = read_state(c, s4).aux;
         int status = DEC_OK;
         if (bb == 0.0) {
             HIP_CHECK(hipMemsetAsync(c->x64.p, 0, m->V * sizeof(double), c->stream));
@@ -737,11 +772,11 @@ int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void
             if (precision == DEC_PREC_FP64)
                 launch_sell<double, MODE_PLAIN>(
                     c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V},
-                    static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr);
+                    static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr, nullptr);
             else
                 launch_sell<float, MODE_PLAIN>(
                     c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V},
-                    static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr);
+                    static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr, nullptr);
             c->stream = keep;
         }
         HIP_CHECK(hipGetLastError());

@@ -9,21 +9,19 @@
 
 // Scalar state of one PCG run, kept in device memory so that a batch of
 // iterations can be launched (or replayed from a graph) without the host.
+// Each run owns two copies: iteration k reads copy k&1 and the last kernel
+// of the iteration (block 0 only) writes copy (k+1)&1, so no kernel reads a
+// field that the same kernel writes.
 struct PcgScalars {
     double rho;      // r.z of the current iterate
-    double pq;       // p.Ap
-    double alpha;
-    double beta;
     double rr;       // r.r of the current iterate
     double rr_stop;  // converged when rr <= rr_stop
     double aux;      // b.b (FP64 solves) or the last reduction result
-    double pad0;
+    double alpha, beta, pq, pad0;
     int64_t iter;
     int64_t max_iter;
     int32_t done;    // PCG_RUNNING / PCG_CONVERGED / PCG_MAXITER / PCG_BREAKDOWN
-    int32_t pad1;
-    unsigned counter;  // arrival counter of the last-block reductions
-    unsigned pad2;
+    int32_t pad1[3];
 };
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXITER = 2, PCG_BREAKDOWN = 3 };
@@ -61,33 +59,38 @@ __device__ __forceinline__ void block_range(int64_t n, int64_t* b0, int64_t* b1)
 }
 
 // Row `lane` of the slice starting at `base` with `width` stored entries per
-// row: sum over the row's entries in stored (ascending column) order.
-template <class VT, int U>
+// row: sum over the row's entries in stored (ascending column) order.  The
+// entries go in groups of U: all column and value loads of a group are
+// issued before its x gathers, and the last group is predicated (the width
+// is uniform across the wavefront), so no entry waits on the one before.
+template <class T, bool NT>
+__device__ __forceinline__ T stream_load(const T* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <class VT, int U, bool NT = true>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
                                        const VT* __restrict__ x) {
     const int32_t* cp = A.col + base + lane;
     const VT* vp = A.val + base + lane;
     VT acc = 0;
-    int j = 0;
-    for (; j + U <= width; j += U) {
+    for (int j = 0; j < width; j += U) {
         int32_t c[U];
         VT v[U], xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c[u] = __builtin_nontemporal_load(cp + u * SELL_C);
-            v[u] = __builtin_nontemporal_load(vp + u * SELL_C);
+            const bool ok = j + u < width;
+            c[u] = ok ? stream_load<int32_t, NT>(cp + u * SELL_C) : 0;
+            v[u] = ok ? stream_load<VT, NT>(vp + u * SELL_C) : VT(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+        for (int u = 0; u < U; ++u) xv[u] = (j + u < width) ? x[c[u]] : VT(0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc += v[u] * xv[u];
+        for (int u = 0; u < U; ++u)
+            if (j + u < width) acc += v[u] * xv[u];
         cp += U * SELL_C;
         vp += U * SELL_C;
-    }
-    for (; j < width; ++j) {
-        acc += __builtin_nontemporal_load(vp) * x[__builtin_nontemporal_load(cp)];
-        cp += SELL_C;
-        vp += SELL_C;
     }
     return acc;
 }
@@ -101,25 +104,31 @@ __device__ __forceinline__ VT csr_row(const CsrView<VT>& A, int64_t row, const V
 
 // ---------------------------------------------------------------- host side
 struct GraphKey {
-    int prec, precond, chunk, unroll;
+    int prec, precond, chunk, unroll, nt;
     bool operator<(const GraphKey& o) const {
         if (prec != o.prec) return prec < o.prec;
         if (precond != o.precond) return precond < o.precond;
         if (chunk != o.chunk) return chunk < o.chunk;
-        return unroll < o.unroll;
+        if (unroll != o.unroll) return unroll < o.unroll;
+        return nt < o.nt;
     }
 };
 
 struct SolveCache {
     dec_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;  // internal stream (graph capture needs a non-null stream)
-    int G = 0;                     // blocks of the fused kernels (multiple of 8)
-    int unroll = 8;                // sliced-ELL unroll chosen by the tuner
-    bool tuned = false;
+    int G = 0;                     // blocks of the vector kernels (multiple of 8)
+    int Gs = 0;                    // blocks of the SpMV kernels (multiple of 8)
+    // sliced-ELL variant per precision ([0] FP64, [1] FP32), chosen by the
+    // tuner among variants whose products are bit-for-bit identical
+    int unroll[2] = {8, 8};
+    int nt[2] = {1, 0};  // non-temporal matrix loads
+    bool tuned[2] = {false, false};
+    bool pinned_variant = false;  // set through the environment: no tuning
     DBuf<double> x64, r64, p64, q64, z64, w64, t64;
     DBuf<float> x32, r32, p32, q32, z32, w32;
-    DBuf<double> partials;  // [2G]
-    DBuf<PcgScalars> st;    // [3]: FP64 PCG, FP32 inner PCG, scratch reductions
+    DBuf<double> partials;  // [3G]: per-block partial sums of p.q, r.r, r.z
+    DBuf<PcgScalars> st;    // [6]: FP64 PCG (2 parities), FP32 inner PCG (2), scratch (2)
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipEvent_t> events;
     hipEvent_t t0 = nullptr, t1 = nullptr;

@@ -80,45 +80,86 @@ __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restric
     }
 }
 
-// Smallest neighbour w of v with w > cur over v's tets, and the number of
-// v's tets that contain it (each tet holds w at most once).  INT_MAX: none.
-__device__ __forceinline__ int next_neighbour(const int4* __restrict__ tets, const int32_t* __restrict__ list,
-                                              int64_t b, int64_t e, int v, int cur, int* count) {
-    int best = INT_MAX, c = 0;
-    for (int64_t k = b; k < e; ++k) {
-        const int4 q = tets[list[k]];
+// One wavefront per vertex: lane k scans tets k, k+64, ... of the vertex's
+// sorted tet list.  Each round finds the smallest neighbour w > cur (wave
+// minimum) and, when asked, how many of the vertex's tets hold it (wave sum;
+// each tet holds w at most once).  INT_MAX: no neighbour left.
+__device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int w = vget(q, r);
-            if (w != v && w > cur) {
-                if (w < best) {
-                    best = w;
-                    c = 1;
-                } else if (w == best) {
-                    ++c;
-                }
-            }
-        }
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// The lane's first tet stays in registers across rounds; vertices in more
+// than 64 tets (rare) re-read the rest from memory.
+struct LaneTets {
+    int4 q0;
+    bool has0;
+};
+
+__device__ __forceinline__ LaneTets load_lane_tets(const int4* __restrict__ tets, const int32_t* __restrict__ list,
+                                                   int64_t b, int d, int lane) {
+    LaneTets t;
+    t.has0 = lane < d;
+    t.q0 = t.has0 ? tets[list[b + lane]] : make_int4(-1, -1, -1, -1);
+    return t;
+}
+
+__device__ __forceinline__ void scan_tet(const int4& q, int v, int cur, int* best) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int w = vget(q, r);
+        if (w != v && w > cur && w < *best) *best = w;
     }
-    *count = c;
+}
+
+template <bool COUNT>
+__device__ __forceinline__ int wave_next_neighbour(const int4* __restrict__ tets, const int32_t* __restrict__ list,
+                                                   int64_t b, int d, int v, int cur, int lane, const LaneTets& lt,
+                                                   int* count) {
+    int best = INT_MAX;
+    if (lt.has0) scan_tet(lt.q0, v, cur, &best);
+    for (int k = lane + 64; k < d; k += 64) scan_tet(tets[list[b + k]], v, cur, &best);
+    best = wave_min_i(best);
+    if (COUNT && best != INT_MAX) {
+        int c = 0;
+        if (lt.has0) c += (lt.q0.x == best) | (lt.q0.y == best) | (lt.q0.z == best) | (lt.q0.w == best);
+        for (int k = lane + 64; k < d; k += 64) {
+            const int4 q = tets[list[b + k]];
+            c += (q.x == best) | (q.y == best) | (q.z == best) | (q.w == best);
+        }
+        *count = wave_sum_i(c);
+    }
     return best;
 }
 
 __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
                             const int32_t* __restrict__ vt_list, int64_t V, int32_t* __restrict__ n_up,
                             int32_t* __restrict__ row_len) {
-    GRID_STRIDE_LOOP(v, V) {
-        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+        const int64_t b = vt_ptr[v];
+        const int d = (int)(vt_ptr[v + 1] - b);
         int cur = -1, up = 0, all = 0, c;
+        const LaneTets lt = load_lane_tets(tets, vt_list, b, d, lane);
         while (true) {
-            const int w = next_neighbour(tets, vt_list, b, e, (int)v, cur, &c);
+            const int w = wave_next_neighbour<false>(tets, vt_list, b, d, (int)v, cur, lane, lt, &c);
             if (w == INT_MAX) break;
             cur = w;
             ++all;
             up += (w > v);
         }
-        n_up[v] = up;
-        row_len[v] = all + 1;
+        if (lane == 0) {
+            n_up[v] = up;
+            row_len[v] = all + 1;
+        }
     }
 }
 
@@ -130,35 +171,43 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
                            const int64_t* __restrict__ row_ptr, int32_t* __restrict__ edges,
                            int32_t* __restrict__ et_cnt, int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
                            int32_t* __restrict__ diag_pos) {
-    GRID_STRIDE_LOOP(v, V) {
-        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+        const int64_t b = vt_ptr[v];
+        const int d = (int)(vt_ptr[v + 1] - b);
         int64_t pos = row_ptr[v], ep = up_ptr[v];
         bool diag = false;
-        int cur = -1, c;
+        int cur = -1, c = 0;
+        const LaneTets lt = load_lane_tets(tets, vt_list, b, d, lane);
         while (true) {
-            const int w = next_neighbour(tets, vt_list, b, e, (int)v, cur, &c);
+            const int w = wave_next_neighbour<true>(tets, vt_list, b, d, (int)v, cur, lane, lt, &c);
             if (w == INT_MAX) break;
             cur = w;
             if (w > v && !diag) {
-                col[pos] = (int32_t)v;
-                nz_edge[pos] = -1;
-                diag_pos[v] = (int32_t)pos;
+                if (lane == 0) {
+                    col[pos] = (int32_t)v;
+                    nz_edge[pos] = -1;
+                    diag_pos[v] = (int32_t)pos;
+                }
                 ++pos;
                 diag = true;
             }
-            col[pos] = w;
-            if (w < v) {
-                nz_edge[pos] = -2;  // resolved by k_lower_edge_ids
-            } else {
-                nz_edge[pos] = (int32_t)ep;
-                edges[2 * ep] = (int32_t)v;
-                edges[2 * ep + 1] = w;
-                et_cnt[ep] = c;
-                ++ep;
+            if (lane == 0) {
+                col[pos] = w;
+                if (w < v) {
+                    nz_edge[pos] = -2;  // resolved by k_lower_edge_ids
+                } else {
+                    nz_edge[pos] = (int32_t)ep;
+                    edges[2 * ep] = (int32_t)v;
+                    edges[2 * ep + 1] = w;
+                    et_cnt[ep] = c;
+                }
             }
+            if (w > v) ++ep;
             ++pos;
         }
-        if (!diag) {
+        if (!diag && lane == 0) {
             col[pos] = (int32_t)v;
             nz_edge[pos] = -1;
             diag_pos[v] = (int32_t)pos;
@@ -197,7 +246,8 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
 // Incidences of edge (lo, hi): lo's tets that contain hi, ascending, as tet*6 + local edge.
 __global__ void k_et_fill(int64_t E, const int32_t* __restrict__ edges, const int4* __restrict__ tets,
                           const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_list,
-                          const int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc) {
+                          const int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc,
+                          int32_t* __restrict__ tet_edge) {
     GRID_STRIDE_LOOP(e, E) {
         const int lo = edges[2 * e], hi = edges[2 * e + 1];
         int64_t out = et_ptr[e];
@@ -213,40 +263,37 @@ __global__ void k_et_fill(int64_t E, const int32_t* __restrict__ edges, const in
             }
             if (ph >= 0) {
                 const int a = pl < ph ? pl : ph, bb = pl < ph ? ph : pl;
-                et_inc[out++] = t * 6 + local_edge(a, bb);
+                const int slot = t * 6 + local_edge(a, bb);
+                et_inc[out++] = slot;
+                tet_edge[slot] = (int32_t)e;  // each (tet, local edge) has exactly one edge
             }
         }
     }
 }
 
-// Faces: face k of tet t is opposite local vertex k.  Its tets are found in
-// the sorted tet list of its smallest vertex; the first one found owns it.
-__global__ void k_faces(int64_t T, const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
-                        const int32_t* __restrict__ vt_list, uint8_t* __restrict__ bface,
-                        unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
+// Faces: face k of tet t is opposite local vertex k.  The tets holding it
+// are the tets of one of its edges (ascending tet order) that also hold its
+// third vertex; the first such tet owns the face.
+__global__ void k_faces(int64_t T, const int4* __restrict__ tets, const int32_t* __restrict__ tet_edge,
+                        const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
+                        uint8_t* __restrict__ bface, unsigned long long* __restrict__ counts,
+                        unsigned* __restrict__ err) {
+    __shared__ unsigned long long lds[BLOCK / 64];
+    unsigned long long owned = 0, bnd = 0;
     GRID_STRIDE_LOOP(t, T) {
         const int4 q = tets[t];
         uint8_t mask = 0;
-        unsigned long long owned = 0, bnd = 0;
         for (int k = 0; k < 4; ++k) {
-            int f[3], m = 0;
-            for (int r = 0; r < 4; ++r)
-                if (r != k) f[m++] = vget(q, r);
-            int a = f[0], b1 = f[1], c1 = f[2];
-            if (b1 < a) { int s = a; a = b1; b1 = s; }
-            if (c1 < a) { int s = a; a = c1; c1 = s; }
+            // the face's vertices are the local vertices other than k; use the edge of the
+            // first two and look for the third
+            const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
+            const int e = tet_edge[6 * t + local_edge(la, lb)];
+            const int c = vget(q, lc);
             int cnt = 0, first = -1;
-            for (int64_t j = vt_ptr[a]; j < vt_ptr[a + 1]; ++j) {
-                const int u = vt_list[j];
+            for (int64_t j = et_ptr[e]; j < et_ptr[e + 1]; ++j) {
+                const int u = et_inc[j] / 6;
                 const int4 o = tets[u];
-                bool hb = false, hc = false;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int w = vget(o, r);
-                    hb |= (w == b1);
-                    hc |= (w == c1);
-                }
-                if (hb && hc) {
+                if (o.x == c || o.y == c || o.z == c || o.w == c) {
                     if (first < 0) first = u;
                     ++cnt;
                 }
@@ -259,6 +306,10 @@ __global__ void k_faces(int64_t T, const int4* __restrict__ tets, const int64_t*
             if (first == t) ++owned;
         }
         bface[t] = mask;
+    }
+    owned = block_sum(owned, lds);
+    bnd = block_sum(bnd, lds);
+    if (threadIdx.x == 0) {
         if (owned) atomicAdd(&counts[0], owned);
         if (bnd) atomicAdd(&counts[1], bnd);
     }
@@ -309,8 +360,9 @@ void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
     DBuf<int32_t> n_up, row_len;
     n_up.alloc(ctx, V);
     row_len.alloc(ctx, V);
-    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V, n_up.p,
-                       row_len.p);
+    // one wavefront (64 lanes) per vertex
+    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
+                       n_up.p, row_len.p);
     HIP_CHECK(hipGetLastError());
     m->up_ptr.alloc(ctx, V + 1);
     const int64_t E = scan_exclusive_i32_to_i64(ctx, n_up.p, m->up_ptr.p, V, true);
@@ -329,7 +381,7 @@ void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
     m->col.alloc(ctx, nnz);
     m->nz_edge.alloc(ctx, nnz);
     m->diag_pos.alloc(ctx, V);
-    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
                        m->up_ptr.p, row_ptr64.p, m->edges.p, et_cnt.p, m->col.p, m->nz_edge.p, m->diag_pos.p);
     err.zero();
     hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
@@ -343,8 +395,10 @@ void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
     const int64_t ninc = scan_exclusive_i32_to_i64(ctx, et_cnt.p, m->et_ptr.p, E, true);
     DEC_REQUIRE(ninc == 6 * T, DEC_ETOPO, "internal: incidence count mismatch");
     m->et_inc.alloc(ctx, 6 * T);
+    DBuf<int32_t> tet_edge;
+    tet_edge.alloc(ctx, 6 * T);
     hipLaunchKernelGGL(k_et_fill, dim3(grid_for(E)), dim3(BLOCK), 0, s, E, m->edges.p, tq, m->vt_ptr.p,
-                       m->vt_list.p, m->et_ptr.p, m->et_inc.p);
+                       m->vt_list.p, m->et_ptr.p, m->et_inc.p, tet_edge.p);
     HIP_CHECK(hipGetLastError());
 
     // faces
@@ -352,8 +406,8 @@ void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
     DBuf<unsigned long long> fc;
     fc.alloc(ctx, 2);
     fc.zero();
-    hipLaunchKernelGGL(k_faces, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tq, m->vt_ptr.p, m->vt_list.p,
-                       m->tet_bface.p, fc.p, err.p);
+    hipLaunchKernelGGL(k_faces, dim3(grid_for(T, BLOCK, 8192)), dim3(BLOCK), 0, s, T, tq, tet_edge.p, m->et_ptr.p,
+                       m->et_inc.p, m->tet_bface.p, fc.p, err.p);
     HIP_CHECK(hipGetLastError());
     unsigned long long hc[2];
     std::memcpy(hc, ctx->readback(fc.p, sizeof(hc)), sizeof(hc));

@@ -297,3 +297,21 @@ def test_profiled_solve_counts_spmv(ctx, dev):
     m, _, _, _, _ = _gpu(ctx, s, dev)
     T, st, rc = m.solve(tol=1e-10, profile=1)
     assert rc == 0 and st["spmv_launches"] == st["iterations"] and st["spmv_ms"] > 0
+
+
+def test_pruned_pattern_products_are_bit_identical(ctx, dev):
+    import paper_2104_05999_amd as dec
+    n = 9
+    s = _system(n, n_cracks=20, rmin=0.05, rmax=0.2)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    x = torch.as_tensor(np.random.Generator(np.random.PCG64(4)).normal(size=s["V"]), device=dev)
+    y_pruned = m.spmv(x)
+    y_csr = m.spmv(x, fmt=dec.DEC_FMT_CSR)
+    T_pruned, st_p, _ = m.solve(tol=1e-11)
+    m.assemble(full_pattern=True)
+    m.apply_bc(_t(s["bt"], dev), _t(s["bv"], dev))
+    y_full = m.spmv(x)
+    T_full, st_f, _ = m.solve(tol=1e-11)
+    assert torch.equal(y_pruned, y_full) and torch.equal(y_full, y_csr)
+    assert torch.equal(T_pruned, T_full)
+    assert st_p["spmv_nnz"] < st_f["spmv_nnz"] == m.nnz
