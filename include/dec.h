@@ -52,6 +52,7 @@ extern "C" {
                                 zero-volume tet, face shared by more than two tets      */
 #define DEC_EBUDGET (-7)     /* request does not fit the server's HBM budget           */
 #define DEC_ESTATE (-8)      /* call out of order (e.g. solve before apply_bc)         */
+#define DEC_ECANCELED (-9)   /* a served request was cancelled                          */
 
 typedef struct dec_ctx dec_ctx;
 typedef struct dec_mesh dec_mesh;
@@ -202,6 +203,80 @@ int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* 
                                     double length, double area, double dT, double* k_eff,
                                     double* q_in, double* q_out, double* energy,
                                     double* edge_flux_out);
+
+/* ---- serving: many solves, batched on the device ----------------------
+ * A server admits requests (one full problem each: mesh, conductivity,
+ * cracks, boundary data) while the HBM budget allows, runs their setup on a
+ * side stream while the systems already admitted keep iterating, keeps each
+ * admitted system's matrix and Krylov state resident, and advances all of
+ * them together: one dec_server_step replays `chunk` PCG iterations of every
+ * admitted system in three batched kernels (captured in a hipGraph), then
+ * runs the FP64 refinement steps of systems whose inner solve ended, retires
+ * converged systems (solution copied to T_out, flux and k_eff computed) and
+ * admits new ones.  Each system's reductions depend only on that system, so
+ * its result is bit-for-bit the same alone and in any mix.  Not thread-safe:
+ * call from the context's thread. */
+typedef struct dec_server dec_server;
+
+typedef struct dec_request {
+    int64_t V;                 /* vertices                                              */
+    const double* xyz;         /* [V x 3] device                                        */
+    int64_t T;                 /* tets                                                  */
+    const int32_t* tets;       /* [T x 4] device                                        */
+    const double* kappa;       /* [E] device or NULL (kappa = 1), canonical edge order   */
+    int32_t n_cracks;
+    const double* cracks;      /* [n_cracks x 7] device or NULL                          */
+    const int8_t* bc_type;     /* [V] device, as dec_apply_bc                            */
+    const double* bc_value;    /* [V] device                                            */
+    const double* neumann_f0;  /* [V] device or NULL                                    */
+    const int8_t* side;        /* [V] device or NULL: faces for Q_in / Q_out             */
+    double length, area, dT;   /* k_eff scaling (0: 1)                                   */
+    double* T_out;             /* [V] device or NULL: receives the solution              */
+    uint64_t user_tag;
+} dec_request;
+/* The request's input arrays must stay valid until its result is polled
+ * (they are read when the request is admitted); T_out likewise. */
+
+typedef struct dec_result {
+    uint64_t ticket;
+    uint64_t user_tag;
+    int32_t status;             /* DEC_OK, DEC_ENOTCONV, DEC_ECANCELED, or a setup error   */
+    int32_t pad;
+    double k_eff, q_in, q_out, energy;
+    double rel_residual;        /* FP64 ||b - A T|| / ||b|| at retirement                  */
+    int64_t inner_iterations;   /* PCG iterations (FP32 inner, or FP64)                    */
+    int64_t outer_iterations;   /* refinement steps                                       */
+    double t_submit_ms, t_admit_ms, t_start_ms, t_finish_ms; /* host clock since creation  */
+} dec_result;
+
+typedef struct dec_server_opts {
+    int32_t precision;            /* DEC_PREC_MIXED (FP32 inner, FP64 refinement) or DEC_PREC_FP64 */
+    int32_t max_slots;            /* systems resident at once (<= 1024)                    */
+    double tol;                   /* ||b - A T|| <= tol ||b|| (FP64)                        */
+    double inner_tol;             /* mixed: relative tolerance of each FP32 solve            */
+    int32_t adaptive_final_inner; /* as dec_solve_opts                                      */
+    int32_t chunk;                /* iterations per batch step (even, 2..1024)              */
+    int64_t max_iters;            /* per request, inner iterations                          */
+} dec_server_opts;
+
+/* Defaults: mixed precision, 64 slots, tol 1e-10, inner_tol 1e-5, adaptive
+ * final inner tolerance, chunk 16, max_iters 100000. */
+int dec_server_opts_default(dec_server_opts* opts);
+/* hbm_budget_bytes bounds the estimated device memory of the admitted
+ * requests (setup peak included). */
+int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_opts* opts, dec_server** out);
+/* Queue a request (FIFO).  DEC_EBUDGET when it cannot fit the budget even alone. */
+int dec_server_submit(dec_server* s, const dec_request* req, uint64_t* ticket);
+/* Advance the server: one batch of iterations, refinement steps, retirements,
+ * admissions.  n_active / n_pending (host, NULL ok) receive the counts after
+ * the step.  Synchronises its streams. */
+int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending);
+/* Move up to max finished results (retirement order) into out; n_out receives the count. */
+int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out);
+/* Cancel a pending or admitted request; its result has status DEC_ECANCELED.
+ * DEC_EINVAL when the ticket is unknown or already finished. */
+int dec_server_cancel(dec_server* s, uint64_t ticket);
+int dec_server_destroy(dec_server* s);
 
 #ifdef __cplusplus
 }

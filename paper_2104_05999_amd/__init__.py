@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_PREC_FP64, DEC_PREC_MIXED, DEC_PRECOND_FSAI,
                    DEC_PRECOND_JACOBI, SolveOpts, SolveStats)
 
-__all__ = ["DecError", "Context", "Mesh", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
+__all__ = ["DecError", "Context", "Mesh", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
            "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL"]
 
 
@@ -210,3 +210,82 @@ class Mesh:
         self.ctx.check(rc, "dec_flux_effective_conductivity")
         k, qi, qo, en = (v.value for v in vals)
         return {"k_eff": k, "q_in": qi, "q_out": qo, "energy": en, "edge_flux": ef}
+
+
+class Server:
+    """dec_server: batched solves of many requests, admitted by HBM budget.
+
+    A request is a dict of device tensors: xyz [V,3] f64, tets [T,4] i32,
+    kappa [E] f64 (optional), cracks [n,7] f64 (optional), bc_type [V] i8,
+    bc_value [V] f64, neumann_f0 [V] f64 (optional), side [V] i8 (optional),
+    T_out [V] f64 (optional), and scalars length/area/dT.  The tensors are
+    kept referenced until the request's result has been polled.
+    """
+
+    def __init__(self, ctx, hbm_budget_bytes, **opts):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        o = _lib.ServerOpts()
+        self.lib.dec_server_opts_default(ctypes.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.dec_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(o), ctypes.byref(h)),
+                  "dec_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, req, user_tag=0):
+        V, T = int(req["xyz"].shape[0]), int(req["tets"].shape[0])
+        cracks = req.get("cracks")
+        n = 0 if cracks is None else int(cracks.shape[0])
+        r = _lib.Request()
+        r.V, r.T = V, T
+        r.xyz = _ptr(req["xyz"], torch.float64, 3 * V, "xyz")
+        r.tets = _ptr(req["tets"], torch.int32, 4 * T, "tets")
+        r.kappa = _ptr(req.get("kappa"), torch.float64, None, "kappa")
+        r.n_cracks = n
+        r.cracks = _ptr(cracks, torch.float64, 7 * n, "cracks") if n else None
+        r.bc_type = _ptr(req["bc_type"], torch.int8, V, "bc_type")
+        r.bc_value = _ptr(req["bc_value"], torch.float64, V, "bc_value")
+        r.neumann_f0 = _ptr(req.get("neumann_f0"), torch.float64, V, "neumann_f0")
+        r.side = _ptr(req.get("side"), torch.int8, V, "side")
+        r.length, r.area, r.dT = (float(req.get(k, 1.0)) for k in ("length", "area", "dT"))
+        r.T_out = _ptr(req.get("T_out"), torch.float64, V, "T_out")
+        r.user_tag = int(user_tag)
+        t = ctypes.c_uint64()
+        self.ctx.check(self.lib.dec_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "dec_server_submit")
+        self._keep[t.value] = req
+        return t.value
+
+    def step(self):
+        a, p = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(self.lib.dec_server_step(self.handle, ctypes.byref(a), ctypes.byref(p)), "dec_server_step")
+        return a.value, p.value
+
+    def poll(self, max_results=256):
+        buf = (_lib.Result * max_results)()
+        n = ctypes.c_int32()
+        self.ctx.check(self.lib.dec_server_poll(self.handle, buf, max_results, ctypes.byref(n)), "dec_server_poll")
+        out = []
+        for i in range(n.value):
+            d = buf[i].as_dict()
+            d["request"] = self._keep.pop(d["ticket"], None)
+            out.append(d)
+        return out
+
+    def cancel(self, ticket):
+        return self.lib.dec_server_cancel(self.handle, int(ticket))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.dec_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

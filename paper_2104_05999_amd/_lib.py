@@ -18,7 +18,7 @@ dp = ctypes.POINTER(ctypes.c_double)
 
 DEC_OK = 0
 STATUS = {0: "DEC_OK", -1: "DEC_EINVAL", -2: "DEC_ENOMEM", -3: "DEC_EHIP", -4: "DEC_ENOTCONV",
-          -5: "DEC_EBREAKDOWN", -6: "DEC_ETOPO", -7: "DEC_EBUDGET", -8: "DEC_ESTATE"}
+          -5: "DEC_EBREAKDOWN", -6: "DEC_ETOPO", -7: "DEC_EBUDGET", -8: "DEC_ESTATE", -9: "DEC_ECANCELED"}
 DEC_PREC_FP64, DEC_PREC_MIXED = 0, 1
 DEC_PRECOND_JACOBI, DEC_PRECOND_FSAI = 0, 1
 DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL = 0, 1, 2
@@ -62,6 +62,36 @@ class SolveStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("V", ctypes.c_int64), ("xyz", vp), ("T", ctypes.c_int64), ("tets", vp), ("kappa", vp),
+        ("n_cracks", ctypes.c_int32), ("cracks", vp), ("bc_type", vp), ("bc_value", vp), ("neumann_f0", vp),
+        ("side", vp), ("length", ctypes.c_double), ("area", ctypes.c_double), ("dT", ctypes.c_double),
+        ("T_out", vp), ("user_tag", ctypes.c_uint64),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64), ("user_tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+        ("pad", ctypes.c_int32), ("k_eff", ctypes.c_double), ("q_in", ctypes.c_double), ("q_out", ctypes.c_double),
+        ("energy", ctypes.c_double), ("rel_residual", ctypes.c_double), ("inner_iterations", ctypes.c_int64),
+        ("outer_iterations", ctypes.c_int64), ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+        ("t_start_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("tol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double), ("adaptive_final_inner", ctypes.c_int32), ("chunk", ctypes.c_int32),
+        ("max_iters", ctypes.c_int64),
+    ]
+
+
 # name -> (restype, argtypes); every entry point declared in include/dec.h
 SIGNATURES = {
     "dec_create": (c_int, [ctypes.POINTER(vp), c_int, vp, ALLOC_FN, FREE_FN, vp]),
@@ -82,6 +112,13 @@ SIGNATURES = {
     "dec_get_fsai": (c_int, [vp, i64p, vp, vp, vp]),
     "dec_flux_effective_conductivity": (c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 dp, dp, dp, dp, vp]),
+    "dec_server_opts_default": (c_int, [ctypes.POINTER(ServerOpts)]),
+    "dec_server_create": (c_int, [vp, ctypes.c_size_t, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]),
+    "dec_server_submit": (c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "dec_server_step": (c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "dec_server_poll": (c_int, [vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "dec_server_cancel": (c_int, [vp, ctypes.c_uint64]),
+    "dec_server_destroy": (c_int, [vp]),
 }
 
 _LIB = None

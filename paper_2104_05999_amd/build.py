@@ -28,6 +28,7 @@ SOURCES = {
     "pcg.hip": [],
     "fsai.hip": [],
     "flux.hip": [],
+    "serve.hip": [],
 }
 
 COMMON = [

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "solver.h"
 
 namespace {
@@ -284,19 +286,30 @@ struct Run {
     int precond;
 };
 
+// With events, the launch carries them (hipExtLaunchKernelGGL): the
+// timestamps are those of the dispatch itself, not of separate markers.
+template <class VT, int MODE, int U, bool NT>
+void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                   const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
+    const dim3 g(c->Gs), blk(BLOCK);
+    if (ev_a)
+        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b, part, st);
+    else
+        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
+}
+
 template <class VT, int MODE, bool NT>
 void launch_sell_nt(SolveCache* c, int unroll, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
-                    const PcgScalars* st) {
-    const dim3 g(c->Gs), blk(BLOCK);
+                    const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
     switch (unroll) {
         case 4:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 4, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
+            launch_sell_u<VT, MODE, 4, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
         case 16:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 16, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
+            launch_sell_u<VT, MODE, 16, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
         default:
-            hipLaunchKernelGGL((k_sell<VT, MODE, 8, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
+            launch_sell_u<VT, MODE, 8, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
     }
 }
@@ -309,12 +322,12 @@ constexpr int prec_index() {
 // SpMV launch on Gs blocks; MODE_DOT / MODE_RESID leave Gs partials in `part`
 template <class VT, int MODE>
 void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
-                 const PcgScalars* st) {
+                 const PcgScalars* st, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
     const int pi = prec_index<VT>();
     if (c->nt[pi])
-        launch_sell_nt<VT, MODE, true>(c, c->unroll[pi], A, x, y, b, part, st);
+        launch_sell_nt<VT, MODE, true>(c, c->unroll[pi], A, x, y, b, part, st, ev_a, ev_b);
     else
-        launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st);
+        launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st, ev_a, ev_b);
 }
 
 // Pick the sliced-ELL variant (unroll 4/8, non-temporal loads on/off) by
@@ -364,9 +377,7 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     double* part = c->partials.p;
     PcgScalars* S = R.st + par;
     PcgScalars* N = R.st + (par ^ 1);
-    if (ev_a) HIP_CHECK(hipEventRecord(ev_a, c->stream));
-    launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S);
-    if (ev_b) HIP_CHECK(hipEventRecord(ev_b, c->stream));
+    launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
     if (R.precond == DEC_PRECOND_JACOBI) {
         hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
                            part, P, n_pq, S);

@@ -1,0 +1,956 @@
+// Serving: many uneven systems solved together.
+//
+// Requests (mesh, conductivity, cracks, boundary data) are admitted while
+// the HBM budget allows; their setup (topology, *1, assembly, boundary
+// data) runs on a side stream while the batch already on the device keeps
+// iterating.  Every admitted system keeps its sliced-ELL matrix and Krylov
+// state resident.  One batch step replays a captured graph of `chunk`
+// iterations of three batched PCG kernels over a work table of
+// (system, 2048-row chunk) items; between replays the host retires
+// converged systems, runs the FP64 refinement steps of systems whose inner
+// solve ended, admits new systems and rewrites the tables.
+//
+// Each system's reductions are partitioned by its own chunks only and
+// folded in a fixed order, so its iterates do not depend on which other
+// systems share the batch: a result is bit-for-bit the same alone and in
+// any mix.
+#include <hip/hip_ext.h>
+
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <memory>
+
+#include "solver.h"
+
+void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets);
+void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const double* cracks);
+void assemble_device(dec_mesh* m);
+void apply_bc_internal(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* f0);
+
+namespace {
+
+constexpr int CHUNK_ROWS = 2048;
+constexpr int CHUNK_SLICES = CHUNK_ROWS / SELL_C;
+enum { Q_PQ = 0, Q_RR = 1, Q_RZ = 2, Q_OUT = 3 };  // partial regions, nchunks doubles each
+
+// Device descriptor of one admitted system.
+struct BSlot {
+    const int64_t* sptr;
+    const int32_t* scol;
+    const double* sval64;
+    const float* sval32;
+    const double* invd64;
+    const float* invd32;
+    const double* b;
+    const uint8_t* fixed;
+    const double* dval;
+    double *x64, *r64, *p64, *q64;
+    float *x32, *r32, *p32, *q32;
+    double* part;       // [4 * nchunks]
+    PcgScalars* st;     // [2] inner state (parity copies)
+    PcgScalars* outer;  // rr = ||r64||^2 of the last refinement residual, aux = b.b
+    int64_t V, nslices;
+    int32_t nchunks;
+    int32_t pad;
+    double stop_factor;  // inner rr_stop = stop_factor * (relative ? r.r : b.b)
+    int32_t relative;
+    int32_t pad2;
+    int64_t max_iter;
+};
+
+struct BItem {
+    int32_t slot, chunk;
+};
+
+template <class VT>
+struct SlotVec;
+template <>
+struct SlotVec<double> {
+    __device__ static const double* val(const BSlot& s) { return s.sval64; }
+    __device__ static const double* invd(const BSlot& s) { return s.invd64; }
+    __device__ static double* x(const BSlot& s) { return s.x64; }
+    __device__ static double* r(const BSlot& s) { return s.r64; }
+    __device__ static double* p(const BSlot& s) { return s.p64; }
+    __device__ static double* q(const BSlot& s) { return s.q64; }
+};
+template <>
+struct SlotVec<float> {
+    __device__ static const float* val(const BSlot& s) { return s.sval32; }
+    __device__ static const float* invd(const BSlot& s) { return s.invd32; }
+    __device__ static float* x(const BSlot& s) { return s.x32; }
+    __device__ static float* r(const BSlot& s) { return s.r32; }
+    __device__ static float* p(const BSlot& s) { return s.p32; }
+    __device__ static float* q(const BSlot& s) { return s.q32; }
+};
+
+__device__ __forceinline__ void chunk_rows(const BSlot& S, int c, int64_t* r0, int64_t* r1) {
+    *r0 = (int64_t)c * CHUNK_ROWS;
+    *r1 = *r0 + CHUNK_ROWS < S.V ? *r0 + CHUNK_ROWS : S.V;
+}
+
+// ---------------------------------------------------------------- batched inner PCG
+template <class VT, int U, bool NT>
+__global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
+                                                     const int32_t* __restrict__ n_items, int par) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const int n = *n_items;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        if (S.st[par].done) continue;
+        const SellView<VT> A{S.sptr, S.scol, SlotVec<VT>::val(S), S.nslices, S.V};
+        const VT* p = SlotVec<VT>::p(S);
+        VT* q = SlotVec<VT>::q(S);
+        const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
+        const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
+        VT d = 0;
+        for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+            const int64_t base = A.ptr[s];
+            const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
+            const int64_t row = s * SELL_C + lane;
+            const VT acc = sell_row<VT, U, NT>(A, base, width, lane, p);
+            if (row < A.V) {
+                q[row] = acc;
+                d += p[row] * acc;
+            }
+        }
+        const double bs = block_sum(static_cast<double>(d), lds);
+        if (threadIdx.x == 0) S.part[Q_PQ * S.nchunks + item.chunk] = bs;
+    }
+}
+
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
+                                                   const int32_t* __restrict__ n_items, int par) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const int n = *n_items;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        const PcgScalars* st = S.st + par;
+        if (st->done) continue;
+        const double pq = reduce_bcast(S.part + Q_PQ * S.nchunks, S.nchunks, lds);
+        if (!(pq > 0.0) || !isfinite(pq)) continue;
+        const VT a = static_cast<VT>(st->rho / pq);
+        VT *x = SlotVec<VT>::x(S), *r = SlotVec<VT>::r(S);
+        const VT *p = SlotVec<VT>::p(S), *q = SlotVec<VT>::q(S), *invd = SlotVec<VT>::invd(S);
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        VT rz = 0, rr = 0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+            const VT xi = x[i] + a * p[i];
+            const VT ri = r[i] - a * q[i];
+            x[i] = xi;
+            r[i] = ri;
+            rz += ri * (invd[i] * ri);
+            rr += ri * ri;
+        }
+        const double b1 = block_sum(static_cast<double>(rz), lds);
+        const double b2 = block_sum(static_cast<double>(rr), lds);
+        if (threadIdx.x == 0) {
+            S.part[Q_RZ * S.nchunks + item.chunk] = b1;
+            S.part[Q_RR * S.nchunks + item.chunk] = b2;
+        }
+    }
+}
+
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
+                                                  const int32_t* __restrict__ n_items, int par) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const int n = *n_items;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        const PcgScalars* Sp = S.st + par;
+        PcgScalars* N = S.st + (par ^ 1);
+        const bool lead = item.chunk == 0 && threadIdx.x == 0;
+        if (Sp->done) {
+            if (lead) *N = *Sp;
+            continue;
+        }
+        const int nc = S.nchunks;
+        const double pq = reduce_bcast(S.part + Q_PQ * nc, nc, lds);
+        const double rr = reduce_bcast(S.part + Q_RR * nc, nc, lds);
+        const double rz = reduce_bcast(S.part + Q_RZ * nc, nc, lds);
+        int done = PCG_RUNNING;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
+            done = PCG_BREAKDOWN;
+        else if (rr <= Sp->rr_stop)
+            done = PCG_CONVERGED;
+        else if (Sp->iter + 1 >= Sp->max_iter)
+            done = PCG_MAXITER;
+        const double beta = rz / Sp->rho;
+        if (done == PCG_RUNNING) {
+            const VT bt = static_cast<VT>(beta);
+            const VT *r = SlotVec<VT>::r(S), *invd = SlotVec<VT>::invd(S);
+            VT* p = SlotVec<VT>::p(S);
+            int64_t r0, r1;
+            chunk_rows(S, item.chunk, &r0, &r1);
+            for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) p[i] = invd[i] * r[i] + bt * p[i];
+        }
+        if (lead) {
+            N->rho = rz;
+            N->rr = rr;
+            N->rr_stop = Sp->rr_stop;
+            N->aux = Sp->aux;
+            N->alpha = Sp->rho / pq;
+            N->beta = beta;
+            N->pq = pq;
+            N->iter = Sp->iter + (done == PCG_BREAKDOWN ? 0 : 1);
+            N->max_iter = Sp->max_iter;
+            N->done = done;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- refinement steps (FP64)
+// x0 on admission: Dirichlet values, 0 elsewhere; FP32 correction zero
+__global__ void bk_admit_init(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        double bb = 0.0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+            S.x64[i] = S.fixed[i] == 1 ? S.dval[i] : 0.0;
+            if (S.x32) S.x32[i] = 0.0f;
+            bb += S.b[i] * S.b[i];
+        }
+        const double t = block_sum(bb, lds);
+        if (threadIdx.x == 0) S.part[Q_OUT * S.nchunks + item.chunk] = t;
+    }
+}
+
+// mixed: x64 += ||r_prev|| x32 (the correction of the inner solve just ended)
+__global__ void bk_correct(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        if (!S.x32) continue;
+        const double scale = sqrt(S.outer->rr);
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK)
+            S.x64[i] = S.x64[i] + scale * static_cast<double>(S.x32[i]);
+    }
+}
+
+// r64 = b - A64 x64, partials of r.r
+__global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
+                                                     int n) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        const SellView<double> A{S.sptr, S.scol, S.sval64, S.nslices, S.V};
+        const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
+        const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
+        double d = 0.0;
+        for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+            const int64_t base = A.ptr[s];
+            const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
+            const int64_t row = s * SELL_C + lane;
+            const double acc = sell_row<double, 8, true>(A, base, width, lane, S.x64);
+            if (row < A.V) {
+                const double ri = S.b[row] - acc;
+                S.r64[row] = ri;
+                d += ri * ri;
+            }
+        }
+        const double bs = block_sum(d, lds);
+        if (threadIdx.x == 0) S.part[Q_OUT * S.nchunks + item.chunk] = bs;
+    }
+}
+
+// one block per listed system: fold the Q_OUT partials into outer->rr (what 0) or outer->aux (what 1)
+__global__ void bk_fold_outer(const BSlot* __restrict__ slots, const int32_t* __restrict__ ids, int n, int what) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        const BSlot& S = slots[ids[k]];
+        const double t = reduce_bcast(S.part + Q_OUT * S.nchunks, S.nchunks, lds);
+        if (threadIdx.x == 0) {
+            if (what == 0)
+                S.outer->rr = t;
+            else {
+                S.outer->aux = t;
+                S.outer->rr = 0.0;
+            }
+        }
+    }
+}
+
+// Start an inner solve from the refinement residual r64.
+// mixed: r32 = r64 / ||r64||, x32 = 0, p32 = D^-1 r32.  FP64: p64 = D^-1 r64 (x64 continues).
+template <class VT>
+__global__ void bk_inner_start(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        const double inv = 1.0 / sqrt(S.outer->rr);
+        VT *r = SlotVec<VT>::r(S), *p = SlotVec<VT>::p(S);
+        const VT* invd = SlotVec<VT>::invd(S);
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        VT rr = 0, rz = 0;
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
+            VT ri;
+            if (sizeof(VT) == 4) {
+                ri = static_cast<VT>(S.r64[i] * inv);
+                r[i] = ri;
+                S.x32[i] = 0.0f;
+            } else {
+                ri = r[i];
+            }
+            const VT z = invd[i] * ri;
+            p[i] = z;
+            rr += ri * ri;
+            rz += ri * z;
+        }
+        const double b1 = block_sum(static_cast<double>(rr), lds);
+        const double b2 = block_sum(static_cast<double>(rz), lds);
+        if (threadIdx.x == 0) {
+            S.part[Q_RR * S.nchunks + item.chunk] = b1;
+            S.part[Q_RZ * S.nchunks + item.chunk] = b2;
+        }
+    }
+}
+
+// one block per listed system: inner state copy 0 from the start partials
+__global__ void bk_inner_fold(const BSlot* __restrict__ slots, const int32_t* __restrict__ ids, int n) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+        const BSlot& S = slots[ids[k]];
+        const double rr = reduce_bcast(S.part + Q_RR * S.nchunks, S.nchunks, lds);
+        const double rz = reduce_bcast(S.part + Q_RZ * S.nchunks, S.nchunks, lds);
+        if (threadIdx.x == 0) {
+            PcgScalars* st = S.st;
+            st->rr = rr;
+            st->rho = rz;
+            st->rr_stop = S.stop_factor * (S.relative ? rr : S.outer->aux);
+            st->aux = S.outer->aux;
+            st->iter = 0;
+            st->max_iter = S.max_iter;
+            st->alpha = st->beta = st->pq = 0.0;
+            st->done = (rr <= st->rr_stop) ? PCG_CONVERGED : (isfinite(rz) ? PCG_RUNNING : PCG_BREAKDOWN);
+        }
+    }
+}
+
+double now_ms(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+enum SlotPhase { PH_FREE = 0, PH_OUTER = 1, PH_INNER = 2 };
+
+struct ServeReq {
+    uint64_t ticket;
+    dec_request req;
+    double t_submit;
+};
+
+struct ServeSlot {
+    SlotPhase phase = PH_FREE;
+    int mode = DEC_PREC_MIXED;  // DEC_PREC_FP64 or DEC_PREC_MIXED (inner precision)
+    uint64_t ticket = 0;
+    dec_request req{};
+    dec_mesh* mesh = nullptr;
+    int64_t budget_bytes = 0;
+    int32_t nchunks = 0;
+    DBuf<double> x64, r64, p64, q64, part;
+    DBuf<float> x32, r32, p32, q32;
+    hipEvent_t ready = nullptr;  // setup finished on the setup stream
+    double t_submit = 0, t_admit = 0, t_start = 0;
+    double rn_prev = 0;
+    int64_t inner_total = 0, outer = 0;
+    bool fresh = true;  // no inner solve yet
+};
+
+struct dec_server {
+    dec_ctx* ctx = nullptr;
+    dec_ctx setup_ctx;  // same device and allocator, setup stream
+    hipStream_t solve_stream = nullptr, setup_stream = nullptr;
+    dec_server_opts opts{};
+    size_t budget = 0;
+    int64_t committed = 0;
+    std::chrono::steady_clock::time_point t0;
+    uint64_t next_ticket = 1;
+    std::deque<ServeReq> pending;
+    std::vector<ServeSlot> slots;
+    std::vector<dec_result> done;
+    int G = 0;
+    // device tables
+    DBuf<BSlot> d_slots;
+    DBuf<BItem> d_items32, d_items64, d_items_aux;
+    DBuf<int32_t> d_n;  // [2]: items in the FP32 and the FP64 inner tables
+    DBuf<int32_t> d_ids;
+    DBuf<PcgScalars> d_st;  // [3 * max_slots]: 2 inner parity copies + outer
+    BSlot* h_slots = nullptr;
+    BItem* h_items = nullptr;
+    int32_t* h_n = nullptr;
+    int32_t* h_ids = nullptr;
+    PcgScalars* h_st = nullptr;
+    int max_items = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] FP64 inner, [1] FP32 inner
+    hipEvent_t ev_chunk = nullptr;
+};
+
+namespace {
+
+int64_t estimate_bytes(int64_t V, int64_t T) {
+    // resident arrays plus the transient peak of the setup (elementary areas, tet-edge map)
+    return 300 * V + 220 * T + (int64_t(64) << 20);
+}
+
+void free_slot(dec_server* s, ServeSlot& sl) {
+    if (sl.mesh) {
+        delete sl.mesh;
+        sl.mesh = nullptr;
+    }
+    for (DBuf<double>* b : {&sl.x64, &sl.r64, &sl.p64, &sl.q64, &sl.part}) b->release();
+    for (DBuf<float>* b : {&sl.x32, &sl.r32, &sl.p32, &sl.q32}) b->release();
+    s->committed -= sl.budget_bytes;
+    sl.budget_bytes = 0;
+    sl.phase = PH_FREE;
+}
+
+// drop the setup-only arrays of an admitted mesh
+void compact_mesh(dec_mesh* m) {
+    m->tets.release();
+    m->vt_ptr.release();
+    m->vt_list.release();
+    m->et_ptr.release();
+    m->et_inc.release();
+    m->tet_bface.release();
+    m->xyz.release();
+    m->cut.release();
+    m->val64.release();
+    m->val32.release();
+    m->sell.src.release();
+    m->geo.release();
+}
+
+BSlot describe(dec_server* s, int k) {
+    ServeSlot& sl = s->slots[k];
+    dec_mesh* m = sl.mesh;
+    BSlot d{};
+    d.sptr = m->sell.ptr.p;
+    d.scol = m->sell.col.p;
+    d.sval64 = m->sell.val64.p;
+    d.sval32 = m->sell.val32.p;
+    d.invd64 = m->invdiag64.p;
+    d.invd32 = m->invdiag32.p;
+    d.b = m->rhs.p;
+    d.fixed = m->fixed.p;
+    d.dval = m->bc_value.p;
+    d.x64 = sl.x64.p;
+    d.r64 = sl.r64.p;
+    d.p64 = sl.p64.p;
+    d.q64 = sl.q64.p;
+    // FP32 vectors only while the system refines FP32 corrections (a system that
+    // fell back to FP64 must not apply its last FP32 correction again)
+    const bool mixed = sl.mode == DEC_PREC_MIXED;
+    d.x32 = mixed ? sl.x32.p : nullptr;
+    d.r32 = mixed ? sl.r32.p : nullptr;
+    d.p32 = mixed ? sl.p32.p : nullptr;
+    d.q32 = mixed ? sl.q32.p : nullptr;
+    d.part = sl.part.p;
+    d.st = s->d_st.p + 3 * k;
+    d.outer = s->d_st.p + 3 * k + 2;
+    d.V = m->V;
+    d.nslices = m->sell.nslices;
+    d.nchunks = sl.nchunks;
+    d.max_iter = s->opts.max_iters;
+    return d;
+}
+
+// Setup of one request on the setup stream.  Returns false when it failed (result recorded).
+bool admit(dec_server* s, const ServeReq& q, int k) {
+    ServeSlot& sl = s->slots[k];
+    hipEvent_t ev = sl.ready;  // events are kept across reuse of a slot
+    sl = ServeSlot();
+    sl.ready = ev;
+    sl.ticket = q.ticket;
+    sl.req = q.req;
+    sl.t_submit = q.t_submit;
+    sl.t_admit = now_ms(s->t0);
+    sl.mode = s->opts.precision;
+    sl.budget_bytes = estimate_bytes(q.req.V, q.req.T);
+    s->committed += sl.budget_bytes;
+    dec_mesh* m = new dec_mesh();
+    m->ctx = &s->setup_ctx;
+    m->V = q.req.V;
+    m->T = q.req.T;
+    sl.mesh = m;
+    try {
+        build_topology_device(m, q.req.xyz, q.req.tets);
+        hodge1_device(m, q.req.kappa, q.req.n_cracks, q.req.cracks);
+        assemble_device(m);
+        apply_bc_internal(m, q.req.bc_type, q.req.bc_value, q.req.neumann_f0);
+        compact_mesh(m);
+        const int64_t V = m->V;
+        sl.nchunks = (int32_t)((V + CHUNK_ROWS - 1) / CHUNK_ROWS);
+        dec_ctx* c = &s->setup_ctx;
+        sl.x64.alloc(c, V);
+        sl.r64.alloc(c, V);
+        sl.part.alloc(c, 4 * (int64_t)sl.nchunks);
+        if (sl.mode == DEC_PREC_MIXED) {
+            sl.x32.alloc(c, V);
+            sl.r32.alloc(c, V);
+            sl.p32.alloc(c, V);
+            sl.q32.alloc(c, V);
+        } else {
+            sl.p64.alloc(c, V);
+            sl.q64.alloc(c, V);
+        }
+        if (!sl.ready) HIP_CHECK(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(sl.ready, s->setup_stream));
+    } catch (const DecError& e) {
+        dec_result r{};
+        r.ticket = q.ticket;
+        r.user_tag = q.req.user_tag;
+        r.status = e.code;
+        r.t_submit_ms = q.t_submit;
+        r.t_admit_ms = sl.t_admit;
+        r.t_finish_ms = now_ms(s->t0);
+        s->done.push_back(r);
+        s->setup_ctx.last_error = e.msg;
+        free_slot(s, sl);
+        return false;
+    }
+    sl.phase = PH_OUTER;
+    sl.fresh = true;
+    return true;
+}
+
+// Upload descriptors and the item table for `ids` (all slots in the list), returning the item count.
+int build_items(dec_server* s, const std::vector<int>& ids, BItem* dst) {
+    int n = 0;
+    for (int k : ids)
+        for (int c = 0; c < s->slots[k].nchunks; ++c) dst[n++] = BItem{k, c};
+    return n;
+}
+
+void upload_slots(dec_server* s) {
+    const int ns = (int)s->slots.size();
+    for (int k = 0; k < ns; ++k)
+        if (s->slots[k].phase != PH_FREE) s->h_slots[k] = describe(s, k);
+    HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, ns * sizeof(BSlot), hipMemcpyHostToDevice, s->solve_stream));
+}
+
+template <class VT>
+void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t* n_items, int par) {
+    const dim3 g(s->G), b(BLOCK);
+    if (sizeof(VT) == 8)
+        hipLaunchKernelGGL((bk_spmv_dot<VT, 8, true>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+    else
+        hipLaunchKernelGGL((bk_spmv_dot<VT, 8, false>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+    hipLaunchKernelGGL(bk_update<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+    hipLaunchKernelGGL(bk_close<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+}
+
+hipGraphExec_t batched_graph(dec_server* s, int prec) {
+    if (s->graph[prec]) return s->graph[prec];
+    const int chunk = s->opts.chunk;
+    hipGraph_t g;
+    HIP_CHECK(hipStreamBeginCapture(s->solve_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) {
+        if (prec == 1)
+            enqueue_batched_iteration<float>(s, s->d_items32.p, s->d_n.p, k & 1);
+        else
+            enqueue_batched_iteration<double>(s, s->d_items64.p, s->d_n.p + 1, k & 1);
+    }
+    HIP_CHECK(hipStreamEndCapture(s->solve_stream, &g));
+    HIP_CHECK(hipGraphInstantiate(&s->graph[prec], g, nullptr, nullptr, 0));
+    HIP_CHECK(hipGraphDestroy(g));
+    return s->graph[prec];
+}
+
+void retire(dec_server* s, int k, int status, double rel) {
+    ServeSlot& sl = s->slots[k];
+    dec_mesh* m = sl.mesh;
+    m->ctx = s->ctx;  // flux on the caller's stream, after the solve stream
+    HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+    if (sl.req.T_out)
+        HIP_CHECK(hipMemcpyAsync(sl.req.T_out, sl.x64.p, m->V * sizeof(double), hipMemcpyDeviceToDevice,
+                                 s->ctx->stream));
+    dec_result r{};
+    r.ticket = sl.ticket;
+    r.user_tag = sl.req.user_tag;
+    r.status = status;
+    r.rel_residual = rel;
+    r.inner_iterations = sl.inner_total;
+    r.outer_iterations = sl.outer;
+    const int rc = dec_flux_effective_conductivity(m, sl.x64.p, sl.req.side, sl.req.length > 0 ? sl.req.length : 1.0,
+                                                   sl.req.area > 0 ? sl.req.area : 1.0, sl.req.dT != 0 ? sl.req.dT : 1.0,
+                                                   &r.k_eff, &r.q_in, &r.q_out, &r.energy, nullptr);
+    if (rc != DEC_OK && r.status == DEC_OK) r.status = rc;
+    r.t_submit_ms = sl.t_submit;
+    r.t_admit_ms = sl.t_admit;
+    r.t_start_ms = sl.t_start;
+    r.t_finish_ms = now_ms(s->t0);
+    s->done.push_back(r);
+    free_slot(s, sl);
+}
+
+// Refinement steps for the systems in `ids` (phase PH_OUTER): correction, FP64
+// residual, convergence decision, and the start of the next inner solve.
+void outer_steps(dec_server* s, const std::vector<int>& ids) {
+    if (ids.empty()) return;
+    const dim3 g(s->G), b(BLOCK);
+    for (int k : ids) HIP_CHECK(hipStreamWaitEvent(s->solve_stream, s->slots[k].ready, 0));
+    upload_slots(s);
+    const int n = build_items(s, ids, s->h_items);
+    DEC_REQUIRE(n <= s->max_items, DEC_EBUDGET, "work table full");
+    HIP_CHECK(hipMemcpyAsync(s->d_items_aux.p, s->h_items, n * sizeof(BItem), hipMemcpyHostToDevice, s->solve_stream));
+    for (size_t i = 0; i < ids.size(); ++i) s->h_ids[i] = ids[i];
+    HIP_CHECK(hipMemcpyAsync(s->d_ids.p, s->h_ids, ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s->solve_stream));
+    // fresh systems: x0 and b.b first
+    std::vector<int> fresh;
+    for (int k : ids)
+        if (s->slots[k].fresh) fresh.push_back(k);
+    if (!fresh.empty()) {
+        hipLaunchKernelGGL(bk_admit_init, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, n);
+        hipLaunchKernelGGL(bk_fold_outer, dim3((int)ids.size()), b, 0, s->solve_stream, s->d_slots.p, s->d_ids.p,
+                           (int)ids.size(), 1);
+    }
+    hipLaunchKernelGGL(bk_correct, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, n);
+    hipLaunchKernelGGL(bk_residual, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, n);
+    hipLaunchKernelGGL(bk_fold_outer, dim3((int)ids.size()), b, 0, s->solve_stream, s->d_slots.p, s->d_ids.p,
+                       (int)ids.size(), 0);
+    HIP_CHECK(hipGetLastError());
+    const int ns = (int)s->slots.size();
+    HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost,
+                             s->solve_stream));
+    HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+    std::vector<int> again;
+    for (int k : ids) {
+        ServeSlot& sl = s->slots[k];
+        const PcgScalars& out = s->h_st[3 * k + 2];
+        const double bn = sqrt(out.aux), rn = sqrt(out.rr);
+        const double rel = bn > 0 ? rn / bn : 0.0;
+        if (!sl.fresh) {
+            sl.inner_total += s->h_st[3 * k].iter;
+            ++sl.outer;
+        }
+        if (bn == 0.0 || rn <= s->opts.tol * bn) {
+            retire(s, k, DEC_OK, rel);
+            continue;
+        }
+        if (sl.inner_total >= s->opts.max_iters || sl.outer >= 100) {
+            retire(s, k, DEC_ENOTCONV, rel);
+            continue;
+        }
+        if (sl.mode == DEC_PREC_MIXED && !sl.fresh && rn > 0.5 * sl.rn_prev) {
+            // refinement stagnates in FP32: this system finishes in FP64
+            sl.mode = DEC_PREC_FP64;
+            sl.p64.alloc(&s->setup_ctx, sl.mesh->V);
+            sl.q64.alloc(&s->setup_ctx, sl.mesh->V);
+        }
+        sl.rn_prev = rn;
+        sl.fresh = false;
+        again.push_back(k);
+    }
+    if (again.empty()) return;
+    // start the next inner solves
+    upload_slots(s);
+    std::vector<int> by_mode[2];
+    for (int k : again) by_mode[s->slots[k].mode == DEC_PREC_MIXED ? 1 : 0].push_back(k);
+    for (int prec = 0; prec < 2; ++prec) {
+        if (by_mode[prec].empty()) continue;
+        for (int k : by_mode[prec]) {
+            ServeSlot& sl = s->slots[k];
+            const PcgScalars& out = s->h_st[3 * k + 2];
+            const double bn = sqrt(out.aux), rn = sqrt(out.rr);
+            if (prec == 1) {
+                double itol = s->opts.inner_tol;
+                if (s->opts.adaptive_final_inner) itol = fmax(itol, 0.5 * s->opts.tol * bn / rn);
+                if (itol >= 1.0) itol = 0.5;
+                s->h_slots[k].stop_factor = itol * itol;
+                s->h_slots[k].relative = 1;
+            } else {
+                s->h_slots[k].stop_factor = s->opts.tol * s->opts.tol;
+                s->h_slots[k].relative = 0;
+            }
+            (void)sl;
+        }
+        const int ns2 = (int)s->slots.size();
+        HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, ns2 * sizeof(BSlot), hipMemcpyHostToDevice,
+                                 s->solve_stream));
+        const int m = build_items(s, by_mode[prec], s->h_items);
+        HIP_CHECK(hipMemcpyAsync(s->d_items_aux.p, s->h_items, m * sizeof(BItem), hipMemcpyHostToDevice,
+                                 s->solve_stream));
+        for (size_t i = 0; i < by_mode[prec].size(); ++i) s->h_ids[i] = by_mode[prec][i];
+        HIP_CHECK(hipMemcpyAsync(s->d_ids.p, s->h_ids, by_mode[prec].size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s->solve_stream));
+        if (prec == 1)
+            hipLaunchKernelGGL(bk_inner_start<float>, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, m);
+        else
+            hipLaunchKernelGGL(bk_inner_start<double>, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, m);
+        hipLaunchKernelGGL(bk_inner_fold, dim3((int)by_mode[prec].size()), b, 0, s->solve_stream, s->d_slots.p,
+                           s->d_ids.p, (int)by_mode[prec].size());
+        HIP_CHECK(hipGetLastError());
+        // the host copies above reuse h_items / h_ids: wait before the next list overwrites them
+        HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+        for (int k : by_mode[prec]) {
+            ServeSlot& sl = s->slots[k];
+            if (sl.phase != PH_INNER) sl.t_start = sl.t_start > 0 ? sl.t_start : now_ms(s->t0);
+            sl.phase = PH_INNER;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dec_server_opts_default(dec_server_opts* o) {
+    if (!o) return DEC_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = DEC_PREC_MIXED;
+    o->tol = 1e-10;
+    o->inner_tol = 1e-5;
+    o->adaptive_final_inner = 1;
+    o->max_iters = 100000;
+    o->max_slots = 64;
+    o->chunk = 16;
+    return DEC_OK;
+}
+
+int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_opts* opts, dec_server** out) {
+    if (!ctx || !out) return DEC_EINVAL;
+    *out = nullptr;
+    dec_server* s = new dec_server();
+    try {
+        dec_server_opts o;
+        dec_server_opts_default(&o);
+        if (opts) o = *opts;
+        DEC_REQUIRE(o.precision == DEC_PREC_FP64 || o.precision == DEC_PREC_MIXED, DEC_EINVAL, "bad precision");
+        DEC_REQUIRE(o.max_slots > 0 && o.max_slots <= 1024, DEC_EINVAL, "max_slots must be in 1..1024");
+        DEC_REQUIRE(o.chunk >= 2 && o.chunk <= 1024 && o.chunk % 2 == 0, DEC_EINVAL, "chunk must be even, 2..1024");
+        DEC_REQUIRE(o.tol > 0 && o.inner_tol > 0 && o.inner_tol < 1 && o.max_iters > 0, DEC_EINVAL, "bad tolerances");
+        ctx->set_device();
+        s->ctx = ctx;
+        s->opts = o;
+        s->budget = hbm_budget_bytes;
+        s->t0 = std::chrono::steady_clock::now();
+        HIP_CHECK(hipStreamCreateWithFlags(&s->solve_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&s->ev_chunk, hipEventDisableTiming));
+        s->setup_ctx.device = ctx->device;
+        s->setup_ctx.stream = s->setup_stream;
+        s->setup_ctx.alloc = ctx->alloc;
+        s->setup_ctx.free_fn = ctx->free_fn;
+        s->setup_ctx.user = ctx->user;
+        s->setup_ctx.num_cus = ctx->num_cus;
+        s->G = 8 * ctx->num_cus;
+        s->slots.resize(o.max_slots);
+        s->max_items = 1 << 20;  // 2^20 chunks of 2048 rows: 2^31 rows in flight at most
+        s->d_slots.alloc(ctx, o.max_slots);
+        s->d_items32.alloc(ctx, s->max_items);
+        s->d_items64.alloc(ctx, s->max_items);
+        s->d_items_aux.alloc(ctx, s->max_items);
+        s->d_n.alloc(ctx, 2);
+        s->d_ids.alloc(ctx, o.max_slots);
+        s->d_st.alloc(ctx, 3 * (int64_t)o.max_slots);
+        HIP_CHECK(hipMemsetAsync(s->d_st.p, 0, 3 * o.max_slots * sizeof(PcgScalars), s->solve_stream));
+        HIP_CHECK(hipMemsetAsync(s->d_n.p, 0, 2 * sizeof(int32_t), s->solve_stream));
+        HIP_CHECK(hipHostMalloc((void**)&s->h_slots, o.max_slots * sizeof(BSlot), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&s->h_items, s->max_items * sizeof(BItem), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&s->h_n, 2 * sizeof(int32_t), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&s->h_ids, o.max_slots * sizeof(int32_t), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&s->h_st, 3 * o.max_slots * sizeof(PcgScalars), hipHostMallocDefault));
+        std::memset(s->h_slots, 0, o.max_slots * sizeof(BSlot));
+        HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        dec_server_destroy(s);
+        return e.code;
+    }
+    *out = s;
+    return DEC_OK;
+}
+
+int dec_server_submit(dec_server* s, const dec_request* req, uint64_t* ticket) {
+    if (!s || !req) return DEC_EINVAL;
+    try {
+        DEC_REQUIRE(req->V > 0 && req->T > 0 && req->xyz && req->tets && req->bc_type && req->bc_value,
+                    DEC_EINVAL, "request needs xyz, tets, bc_type and bc_value");
+        DEC_REQUIRE(req->n_cracks >= 0 && (req->n_cracks == 0 || req->cracks), DEC_EINVAL, "bad crack array");
+        DEC_REQUIRE(estimate_bytes(req->V, req->T) <= (int64_t)s->budget, DEC_EBUDGET,
+                    "request does not fit the HBM budget even alone");
+    } catch (const DecError& e) {
+        s->ctx->last_error = e.msg;
+        return e.code;
+    }
+    ServeReq q;
+    q.ticket = s->next_ticket++;
+    q.req = *req;
+    q.t_submit = now_ms(s->t0);
+    s->pending.push_back(q);
+    if (ticket) *ticket = q.ticket;
+    return DEC_OK;
+}
+
+int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
+    if (!s) return DEC_EINVAL;
+    try {
+        s->ctx->set_device();
+        const int ns = (int)s->slots.size();
+        // 1. one batch of inner iterations for every system in PH_INNER
+        std::vector<int> inner[2];
+        for (int k = 0; k < ns; ++k)
+            if (s->slots[k].phase == PH_INNER) inner[s->slots[k].mode == DEC_PREC_MIXED ? 1 : 0].push_back(k);
+        bool launched = false;
+        if (!inner[0].empty() || !inner[1].empty()) {
+            upload_slots(s);
+            const int n64 = build_items(s, inner[0], s->h_items);
+            HIP_CHECK(hipMemcpyAsync(s->d_items64.p, s->h_items, n64 * sizeof(BItem), hipMemcpyHostToDevice,
+                                     s->solve_stream));
+            const int n32 = build_items(s, inner[1], s->h_items + n64);
+            DEC_REQUIRE(n64 + n32 <= s->max_items, DEC_EBUDGET, "work table full");
+            HIP_CHECK(hipMemcpyAsync(s->d_items32.p, s->h_items + n64, n32 * sizeof(BItem), hipMemcpyHostToDevice,
+                                     s->solve_stream));
+            s->h_n[0] = n32;
+            s->h_n[1] = n64;
+            HIP_CHECK(hipMemcpyAsync(s->d_n.p, s->h_n, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s->solve_stream));
+            if (n32) HIP_CHECK(hipGraphLaunch(batched_graph(s, 1), s->solve_stream));
+            if (n64) HIP_CHECK(hipGraphLaunch(batched_graph(s, 0), s->solve_stream));
+            HIP_CHECK(hipEventRecord(s->ev_chunk, s->solve_stream));
+            launched = true;
+        }
+        // 2. admissions (setup overlaps the batch on the setup stream)
+        while (!s->pending.empty()) {
+            int free_k = -1;
+            for (int k = 0; k < ns; ++k)
+                if (s->slots[k].phase == PH_FREE) {
+                    free_k = k;
+                    break;
+                }
+            if (free_k < 0) break;
+            const ServeReq& q = s->pending.front();
+            if (s->committed + estimate_bytes(q.req.V, q.req.T) > (int64_t)s->budget) break;
+            ServeReq qq = q;
+            s->pending.pop_front();
+            admit(s, qq, free_k);
+        }
+        // 3. wait for the batch, then refinement steps for systems whose inner solve ended
+        if (launched) HIP_CHECK(hipEventSynchronize(s->ev_chunk));
+        HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost,
+                                 s->solve_stream));
+        HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+        std::vector<int> outer;
+        for (int k = 0; k < ns; ++k) {
+            ServeSlot& sl = s->slots[k];
+            if (sl.phase == PH_INNER && s->h_st[3 * k].done != PCG_RUNNING) sl.phase = PH_OUTER;
+            if (sl.phase == PH_OUTER) {
+                if (sl.fresh && hipEventQuery(sl.ready) != hipSuccess) continue;  // setup still running
+                outer.push_back(k);
+            }
+        }
+        // fresh systems (b.b, x0) first, then the others
+        std::vector<int> fresh, old;
+        for (int k : outer) (s->slots[k].fresh ? fresh : old).push_back(k);
+        outer_steps(s, fresh);
+        outer_steps(s, old);
+        int act = 0;
+        for (int k = 0; k < ns; ++k) act += s->slots[k].phase != PH_FREE;
+        if (n_active) *n_active = act;
+        if (n_pending) *n_pending = (int32_t)s->pending.size();
+    } catch (const DecError& e) {
+        s->ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}
+
+int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out) {
+    if (!s || (max > 0 && !out) || !n_out) return DEC_EINVAL;
+    const int n = (int)s->done.size() < max ? (int)s->done.size() : max;
+    for (int i = 0; i < n; ++i) out[i] = s->done[i];
+    s->done.erase(s->done.begin(), s->done.begin() + n);
+    *n_out = n;
+    return DEC_OK;
+}
+
+int dec_server_cancel(dec_server* s, uint64_t ticket) {
+    if (!s) return DEC_EINVAL;
+    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+        if (it->ticket == ticket) {
+            dec_result r{};
+            r.ticket = ticket;
+            r.user_tag = it->req.user_tag;
+            r.status = DEC_ECANCELED;
+            r.t_submit_ms = it->t_submit;
+            r.t_finish_ms = now_ms(s->t0);
+            s->done.push_back(r);
+            s->pending.erase(it);
+            return DEC_OK;
+        }
+    }
+    try {
+        for (size_t k = 0; k < s->slots.size(); ++k) {
+            ServeSlot& sl = s->slots[k];
+            if (sl.phase != PH_FREE && sl.ticket == ticket) {
+                HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+                HIP_CHECK(hipStreamSynchronize(s->setup_stream));
+                dec_result r{};
+                r.ticket = ticket;
+                r.user_tag = sl.req.user_tag;
+                r.status = DEC_ECANCELED;
+                r.t_submit_ms = sl.t_submit;
+                r.t_admit_ms = sl.t_admit;
+                r.t_finish_ms = now_ms(s->t0);
+                s->done.push_back(r);
+                free_slot(s, sl);
+                return DEC_OK;
+            }
+        }
+    } catch (const DecError& e) {
+        s->ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_EINVAL;
+}
+
+int dec_server_destroy(dec_server* s) {
+    if (!s) return DEC_EINVAL;
+    if (s->solve_stream) (void)hipStreamSynchronize(s->solve_stream);
+    if (s->setup_stream) (void)hipStreamSynchronize(s->setup_stream);
+    for (auto& sl : s->slots) {
+        if (sl.phase != PH_FREE) free_slot(s, sl);
+        if (sl.ready) (void)hipEventDestroy(sl.ready);
+    }
+    for (hipGraphExec_t g : s->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    s->d_slots.release();
+    s->d_items32.release();
+    s->d_items64.release();
+    s->d_items_aux.release();
+    s->d_n.release();
+    s->d_ids.release();
+    s->d_st.release();
+    if (s->h_slots) (void)hipHostFree(s->h_slots);
+    if (s->h_items) (void)hipHostFree(s->h_items);
+    if (s->h_n) (void)hipHostFree(s->h_n);
+    if (s->h_ids) (void)hipHostFree(s->h_ids);
+    if (s->h_st) (void)hipHostFree(s->h_st);
+    if (s->ev_chunk) (void)hipEventDestroy(s->ev_chunk);
+    if (s->setup_ctx.pinned) (void)hipHostFree(s->setup_ctx.pinned);
+    if (s->solve_stream) (void)hipStreamDestroy(s->solve_stream);
+    if (s->setup_stream) (void)hipStreamDestroy(s->setup_stream);
+    delete s;
+    return DEC_OK;
+}
+
+}  // extern "C"

@@ -324,7 +324,10 @@ std::string topo_message(unsigned err) {
     return "invalid mesh";
 }
 
-void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
+}  // namespace
+
+// Build every topology array of m (V, T set) from device xyz / tets.
+void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) {
     dec_ctx* ctx = m->ctx;
     hipStream_t s = ctx->stream;
     const int64_t V = m->V, T = m->T;
@@ -417,7 +420,6 @@ void build_topology(dec_mesh* m, const double* xyz, const int32_t* tets) {
     if (e1) dec_fail(DEC_ETOPO, topo_message(e1));
 }
 
-}  // namespace
 
 extern "C" {
 
@@ -432,7 +434,7 @@ int dec_build_topology(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, co
         ctx->set_device();
         m->V = V;
         m->T = T;
-        build_topology(m, xyz, tets);
+        build_topology_device(m, xyz, tets);
     } catch (const DecError& e) {
         ctx->last_error = e.msg;
         delete m;

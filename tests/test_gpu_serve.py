@@ -1,0 +1,136 @@
+"""Serving: batched solves of uneven requests through dec_server_* (GPU).
+
+Each result must match the FP64 oracle (solution to 1e-10 relative of the
+oracle's tight solve when the server runs to 1e-12, k_eff to 1e-9), and be
+bit-for-bit the same when the request is served alone as when it shares
+the device with others, including requests admitted while others iterate.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    import paper_2104_05999_amd as dec
+    c = dec.Context(dev)
+    yield c
+    c.close()
+
+
+def make_request(n, n_cracks, seed, dev, sigma=0.5):
+    xyz, tets = W.kuhn_cube(n)
+    E = W.kuhn_counts(n)["E"]
+    kappa = W.lognormal_kappa(E, sigma, 1000 + seed)
+    cracks = W.penny_cracks(n_cracks, 2000 + seed, 0.05, 0.2)
+    bt, bv, side = W.x_sides(n)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    req = dict(xyz=t(xyz), tets=t(tets), kappa=t(kappa), bc_type=t(bt), bc_value=t(bv), side=t(side),
+               T_out=torch.zeros(len(xyz), dtype=torch.float64, device=dev))
+    if n_cracks:
+        req["cracks"] = t(cracks)
+    host = dict(xyz=xyz, tets=tets, kappa=kappa, cracks=cracks if n_cracks else None, bt=bt, bv=bv, side=side)
+    return req, host
+
+
+def oracle_reference(h):
+    V = len(h["xyz"])
+    E = O.edges_of(h["tets"], V)
+    cut = O.crack_cut(h["xyz"], E, h["cracks"]) if h["cracks"] is not None else None
+    star = O.hodge1(h["xyz"], h["tets"], E, kappa=h["kappa"], cut=cut)
+    A, b, _ = O.apply_bc(O.assemble(V, E, star)[0], h["bt"], h["bv"], E, star)
+    ref = O.pcg(A, b, precond="jacobi", tol=1e-14, stagnation=50)
+    return ref.x, O.flux_effective_conductivity(ref.x, E, star, h["side"])
+
+
+def serve(ctx, reqs, budget=4 << 30, late=(), max_steps=20000, **opts):
+    """Submit reqs (late ones after the first steps); return results keyed by user tag and the peak activity."""
+    import paper_2104_05999_amd as dec
+    srv = dec.Server(ctx, budget, **opts)
+    for tag, r in enumerate(reqs):
+        if tag not in late:
+            srv.submit(r, user_tag=tag)
+    out, peak, steps = {}, 0, 0
+    late_left = list(late)
+    while len(out) < len(reqs):
+        assert steps < max_steps, "server did not finish"
+        active, pending = srv.step()
+        peak = max(peak, active)
+        steps += 1
+        if late_left and steps >= 2:
+            assert active > 0  # the late request joins a running batch
+            tag = late_left.pop(0)
+            srv.submit(reqs[tag], user_tag=tag)
+        for res in srv.poll():
+            out[res["user_tag"]] = res
+    srv.close()
+    return out, peak
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_served_results_match_oracle_and_are_the_same_alone(ctx, dev, precision):
+    specs = [(6, 5), (9, 12), (12, 20), (7, 0), (10, 8)]
+    built = [make_request(n, c, k, dev) for k, (n, c) in enumerate(specs)]
+    reqs = [b[0] for b in built]
+    mixed, peak = serve(ctx, reqs, late=(3, 4), tol=1e-12, precision=precision)
+    assert peak >= 2
+    for tag, (req, host) in enumerate(built):
+        res = mixed[tag]
+        assert res["status"] == 0, res
+        assert res["rel_residual"] <= 1e-12
+        x_ref, f_ref = oracle_reference(host)
+        T = req["T_out"].cpu().numpy()
+        assert np.linalg.norm(T - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+        assert abs(res["k_eff"] - f_ref["k_eff"]) <= 1e-9 * f_ref["k_eff"]
+        assert res["t_submit_ms"] <= res["t_admit_ms"] <= res["t_start_ms"] <= res["t_finish_ms"]
+    # each request alone in a fresh server: bit-for-bit the same
+    for tag in (0, 2, 4):
+        req, _ = built[tag]
+        T_mix = req["T_out"].clone()
+        req["T_out"].zero_()
+        alone, _ = serve(ctx, [req], tol=1e-12, precision=precision)
+        assert torch.equal(req["T_out"], T_mix)
+        assert alone[0]["k_eff"] == mixed[tag]["k_eff"]
+        assert alone[0]["inner_iterations"] == mixed[tag]["inner_iterations"]
+
+
+def test_budget_admits_one_at_a_time(ctx, dev):
+    import paper_2104_05999_amd as dec
+    reqs = [make_request(8, 4, 10 + k, dev)[0] for k in range(3)]
+    V, T = 9 ** 3, 6 * 8 ** 3
+    one = 300 * V + 220 * T + (64 << 20)
+    out, peak = serve(ctx, reqs, budget=one + 1000)
+    assert peak == 1 and all(r["status"] == 0 for r in out.values())
+    srv = dec.Server(ctx, one - 1)
+    with pytest.raises(dec.DecError) as ei:
+        srv.submit(reqs[0])
+    assert ei.value.code == -7
+    srv.close()
+
+
+def test_cancel_pending_and_admitted(ctx, dev):
+    import paper_2104_05999_amd as dec
+    built = [make_request(8, 6, 20 + k, dev) for k in range(3)]
+    reqs = [b[0] for b in built]
+    srv = dec.Server(ctx, 4 << 30, max_slots=1)
+    tickets = [srv.submit(r, user_tag=k) for k, r in enumerate(reqs)]
+    assert srv.cancel(tickets[2]) == 0          # still pending
+    srv.step()                                   # admits request 0
+    assert srv.cancel(tickets[0]) == 0          # admitted
+    assert srv.cancel(12345) == -1
+    out = {}
+    for _ in range(5000):
+        srv.step()
+        for r in srv.poll():
+            out[r["user_tag"]] = r
+        if len(out) == 3:
+            break
+    srv.close()
+    assert out[0]["status"] == -9 and out[2]["status"] == -9 and out[1]["status"] == 0
+    alone, _ = serve(ctx, [reqs[1]])
+    assert alone[0]["k_eff"] == out[1]["k_eff"]
