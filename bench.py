@@ -42,6 +42,24 @@ def spmv_bytes(V, nnz, s_v):
     return nnz * (s_v + 4) + 4 * (V + 1) + 2 * V * s_v
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_fp64_kuhn128_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("solver.h", "pcg.hip")]
+
+
+def measured_traffic(n):
+    """HBM bytes per SpMV launch from the committed counter summary, or None when the kernel
+    sources changed since the counters were taken (or for another mesh size)."""
+    import hashlib
+
+    if n != 128 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = dict(ln.strip().split("=", 1) for ln in open(TRAFFIC_FILE) if "=" in ln and not ln.startswith("#"))
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    if kv.get("source_sha256") != h:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def make_inputs(n, dev, sigma=1.0, kseed=1, n_cracks=200, cseed=2):
     import torch
 
@@ -65,6 +83,173 @@ def run_step(ctx, inp, precision=0, precond=0, profile=1, tol=1e-10):
     counts = dict(V=mesh.V, T=mesh.T, E=mesh.E, nnz=mesh.nnz, n_pinned=npin)
     mesh.close()
     return st, f, counts, rc
+
+
+def make_serve_inputs(count, dev, seed=3, rate=0.0):
+    """The serving stream: n ~ U{24..96}, 0..400 cracks, kappa sigma 0.5; meshes shared per n."""
+    import torch
+
+    trace = W.serving_trace(count, seed, rate)
+    meshes, reqs = {}, []
+    for spec in trace:
+        n = spec.n
+        if n not in meshes:
+            xyz, tets = W.kuhn_cube(n, device=dev)
+            bt, bv, side = W.x_sides(n)
+            meshes[n] = dict(xyz=xyz, tets=tets, bc_type=torch.as_tensor(bt, device=dev),
+                             bc_value=torch.as_tensor(bv, device=dev), side=torch.as_tensor(side, device=dev))
+        r = dict(meshes[n])
+        E = W.kuhn_counts(n)["E"]
+        r["kappa"] = torch.as_tensor(W.lognormal_kappa(E, 0.5, spec.kappa_seed), device=dev)
+        if spec.n_cracks:
+            r["cracks"] = torch.as_tensor(W.penny_cracks(spec.n_cracks, spec.crack_seed), device=dev)
+        r["T_out"] = torch.empty(r["xyz"].shape[0], dtype=torch.float64, device=dev)
+        r["n"] = n
+        reqs.append(r)
+    return trace, reqs
+
+
+def _percentiles(lat_s):
+    a = np.sort(np.asarray(lat_s)) * 1e3
+    return {"p50_ms": round(float(np.percentile(a, 50)), 3), "p99_ms": round(float(np.percentile(a, 99)), 3),
+            "mean_ms": round(float(a.mean()), 3)}
+
+
+def serve_fp64_sequential(ctx, reqs, arrivals):
+    """Plain FP64 Jacobi PCG, one request at a time in arrival order (the unbatched baseline)."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, keff, iters = [], [], 0
+    for q, r in enumerate(reqs):
+        wait = arrivals[q] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        mesh = ctx.mesh(r["xyz"], r["tets"])
+        mesh.hodge1(r["kappa"], r.get("cracks"), want_cut=False, want_star=False)
+        mesh.assemble()
+        mesh.apply_bc(r["bc_type"], r["bc_value"], want_rhs=False)
+        T, st, rc = mesh.solve(T=r["T_out"], tol=1e-10)
+        f = mesh.flux(T, r["side"])
+        mesh.close()
+        iters += st["iterations"]
+        keff.append(f["k_eff"])
+        lat.append(time.perf_counter() - t0 - arrivals[q])
+    total = time.perf_counter() - t0
+    return {"solves_per_sec": round(len(reqs) / (total - arrivals[0]), 3), **_percentiles(lat),
+            "seconds": round(total, 3), "iterations": iters}, keff
+
+
+def serve_batched(ctx, reqs, arrivals, precision, budget=16 << 30, max_slots=64, chunk=16):
+    """The server: requests submitted at their arrival time, stepped until all are done."""
+    import torch
+
+    import paper_2104_05999_amd as dec
+
+    srv = dec.Server(ctx, budget, precision=precision, max_slots=max_slots, chunk=chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nxt, done, lat, keff, steps, peak = 0, 0, [0.0] * len(reqs), [0.0] * len(reqs), 0, 0
+    inner = outer = 0
+    status_bad = 0
+    while done < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrivals[nxt] <= now:
+            srv.submit(reqs[nxt], user_tag=nxt)
+            nxt += 1
+        active, pending = srv.step()
+        steps += 1
+        peak = max(peak, active)
+        for res in srv.poll():
+            q = res["user_tag"]
+            lat[q] = time.perf_counter() - t0 - arrivals[q]
+            keff[q] = res["k_eff"]
+            inner += res["inner_iterations"]
+            outer += res["outer_iterations"]
+            status_bad += res["status"] != 0
+            done += 1
+        if active == 0 and pending == 0 and nxt < len(reqs):
+            wait = arrivals[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+    total = time.perf_counter() - t0
+    srv.close()
+    return {"solves_per_sec": round(len(reqs) / (total - arrivals[0]), 3), **_percentiles(lat),
+            "seconds": round(total, 3), "steps": steps, "peak_resident": peak, "inner_iterations": inner,
+            "outer_iterations": outer, "failed": status_bad}, keff
+
+
+def serving_benchmark(ctx, dev, count):
+    """Saturated throughput (all requests queued at t = 0) and latency under Poisson arrivals at
+    0.8 x the FP64 baseline's saturated rate, plain FP64 one-at-a-time vs mixed batched."""
+    import paper_2104_05999_amd as dec
+
+    trace, reqs = make_serve_inputs(count, dev)
+    zero = [0.0] * count
+    print(f"[bench] serving: {count} requests generated", file=sys.stderr, flush=True)
+    f64_sat, k64 = serve_fp64_sequential(ctx, reqs, zero)
+    print(f"[bench] serving fp64 saturated: {f64_sat}", file=sys.stderr, flush=True)
+    mix_sat, kmix = serve_batched(ctx, reqs, zero, dec.DEC_PREC_MIXED)
+    print(f"[bench] serving mixed saturated: {mix_sat}", file=sys.stderr, flush=True)
+    rate = 0.8 * f64_sat["solves_per_sec"]
+    arrivals = [spec.arrival_s for spec in W.serving_trace(count, 3, rate)]
+    f64_poi, _ = serve_fp64_sequential(ctx, reqs, arrivals)
+    mix_poi, _ = serve_batched(ctx, reqs, arrivals, dec.DEC_PREC_MIXED)
+    print(f"[bench] serving poisson: fp64 {f64_poi} mixed {mix_poi}", file=sys.stderr, flush=True)
+    dk = max(abs(a - b) / abs(b) for a, b in zip(kmix, k64))
+    ns = [spec.n for spec in trace]
+    return {
+        "workload": f"{count} requests, Kuhn n ~ U{{24..96}} (mean V {int(np.mean([(n + 1) ** 3 for n in ns]))}), "
+                    "0-400 penny cracks, lognormal kappa sigma 0.5, tol 1e-10",
+        "fp64_sequential": {"saturated": f64_sat, "poisson": f64_poi},
+        "mixed_batched": {"saturated": mix_sat, "poisson": mix_poi},
+        "poisson_rate_per_s": round(rate, 3),
+        "speedup_saturated_solves_per_sec": round(mix_sat["solves_per_sec"] / f64_sat["solves_per_sec"], 3),
+        "max_rel_keff_diff_mixed_vs_fp64": dk,
+    }
+
+
+def crack_growth(ctx, dev, n=256, steps=51, n_discs=1000, seed=4):
+    """Crack growth: discs grown by 2% per step, each solve warm-started from the previous step;
+    FP64 and mixed-precision chains on the same mesh.  Returns the k_eff curves and wall times."""
+    import torch
+
+    xyz, tets = W.kuhn_cube(n, device=dev)
+    c = W.kuhn_counts(n)
+    kappa = torch.as_tensor(W.lognormal_kappa(c["E"], 1.0, 1), device=dev)
+    bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
+    discs = W.penny_cracks(n_discs, seed)
+    grown = [torch.as_tensor(W.grown_radii(discs, s), device=dev) for s in range(steps)]
+    t0 = time.perf_counter()
+    mesh = ctx.mesh(xyz, tets)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    out = {"workload": f"kuhn{n}_growth_{n_discs}discs_{steps}steps", "V": mesh.V, "E": mesh.E,
+           "topology_s": round(setup_s, 3)}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        T = torch.zeros(mesh.V, dtype=torch.float64, device=dev)
+        curve, iters, cuts = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            cut, _ = mesh.hodge1(kappa, grown[s], want_star=False)
+            mesh.assemble()
+            mesh.apply_bc(bt, bv, want_rhs=False)
+            T, st, rc = mesh.solve(T=T, tol=1e-10, precision=prec, warm_start=1)
+            f = mesh.flux(T, side)
+            curve.append(f["k_eff"])
+            iters.append(st["iterations"])
+            cuts.append(int(cut.sum()))
+            print(f"[bench] growth {name} step {s}: k_eff {f['k_eff']:.9f} its {st['iterations']}",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "k_eff": curve, "iterations": iters}
+        out["n_cut"] = cuts
+    out["mixed_vs_fp64_speedup"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
+    out["max_abs_keff_diff"] = max(abs(a - b) for a, b in zip(out["fp64"]["k_eff"], out["mixed"]["k_eff"]))
+    mesh.close()
+    return out
 
 
 def cpu_baseline(n=80):
@@ -111,6 +296,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a plain device copy of this size")
+    ap.add_argument("--serve-requests", type=int, default=512, help="serving stream length (0: skip)")
+    ap.add_argument("--crack-growth", action="store_true",
+                    help="instead of the default line: the 256^3 crack-growth chains (FP64 and mixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -123,6 +311,10 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = dec.Context(dev)
+    if args.crack_growth:
+        print(json.dumps({"metric": "crack growth k_eff(step), mixed vs FP64 wall time", "n_gpus": 1,
+                          "data": "synthetic", **crack_growth(ctx, dev)}))
+        return
     inp = make_inputs(args.n, dev)
     precond = dec.DEC_PRECOND_FSAI if args.precond == "fsai" else dec.DEC_PRECOND_JACOBI
     profile = 0 if args.no_profile else 1
@@ -180,7 +372,7 @@ def main():
     if launches:
         achieved = per * launches / (spmv_ms / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(args.n),
                            "kernel": "k_sell<double, MODE_DOT> (sliced-ELL SpMV + p.Ap partials)",
                            "bytes_per_launch": per, "mean_launch_us": round(1e3 * spmv_ms / launches, 3),
                            "launches": launches}
@@ -209,6 +401,8 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         out["copy_probe"] = {"bytes": 2 * nb, "GBps": round(10 * 2 * nb / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)}
+    if args.serve_requests > 0:
+        out["serving"] = serving_benchmark(ctx, dev, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -151,6 +151,7 @@ struct dec_mesh {
 
     // Hodge star
     bool geo_ready = false;
+    double extent[7] = {0, 0, 0, 0, 0, 0, 0};  // bounding box (min xyz, max xyz) and longest half edge
     DBuf<double> geo;        // [E]  |*e| / |e| after the snap
     DBuf<double> star1;      // [E]
     DBuf<uint8_t> cut;       // [E]

@@ -109,6 +109,7 @@ __global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, co
 }
 
 constexpr int kMaxDiscsLds = 256;  // 256 * 7 doubles = 14 KiB of LDS per block
+constexpr int kBinnedFrom = 64;    // more discs than this: spatially binned cut
 
 __global__ void k_crack_cut(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
                             int32_t n_discs, const double* __restrict__ discs, uint8_t* __restrict__ cut) {
@@ -142,6 +143,124 @@ __global__ void k_crack_cut(int64_t E, const int32_t* __restrict__ edges, const 
     }
 }
 
+// ---- spatially binned cut for many discs
+// The mesh's bounding box is split into kBins^3 cells.  A disc is listed in
+// every cell its bounding box, inflated by the longest half edge, overlaps;
+// an edge can only cross a disc if its midpoint lies in that inflated box,
+// so each edge tests the discs of its midpoint's cell only.  The decision
+// per (edge, disc) is the same predicate, so the mask is unchanged.
+constexpr int kBins = 32;
+
+struct Bins {
+    double lo[3];
+    double inv[3];  // cells per unit length
+};
+
+__device__ __forceinline__ int bin_of(double x, double lo, double inv) {
+    const double t = (x - lo) * inv;
+    int b = t <= 0.0 ? 0 : (t >= (double)(kBins - 1) ? kBins - 1 : (int)t);
+    return b;
+}
+
+// per-block partial extents: [block][7] = min xyz, max xyz, longest half edge
+__global__ void k_geom_extent(int64_t V, const double* __restrict__ xyz, int64_t E, const int32_t* __restrict__ edges,
+                              double* __restrict__ part) {
+    __shared__ double red[7][BLOCK];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY}, he = 0.0;
+    GRID_STRIDE_LOOP(i, V) {
+        for (int a = 0; a < 3; ++a) {
+            const double v = xyz[3 * i + a];
+            mn[a] = fmin(mn[a], v);
+            mx[a] = fmax(mx[a], v);
+        }
+    }
+    GRID_STRIDE_LOOP(e, E) {
+        const d3 d = sub(load3(xyz + 3 * (int64_t)edges[2 * e + 1]), load3(xyz + 3 * (int64_t)edges[2 * e]));
+        he = fmax(he, 0.5 * sqrt(dot(d, d)));
+    }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = mn[a];
+        red[3 + a][threadIdx.x] = mx[a];
+    }
+    red[6][threadIdx.x] = he;
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double r = red[threadIdx.x][0];
+        for (int t = 1; t < BLOCK; ++t)
+            r = threadIdx.x < 3 ? fmin(r, red[threadIdx.x][t]) : fmax(r, red[threadIdx.x][t]);
+        part[7 * blockIdx.x + threadIdx.x] = r;
+    }
+}
+
+__global__ void k_geom_extent_fold(int nblocks, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x < 7) {
+        double r = part[threadIdx.x];
+        for (int b = 1; b < nblocks; ++b)
+            r = threadIdx.x < 3 ? fmin(r, part[7 * b + threadIdx.x]) : fmax(r, part[7 * b + threadIdx.x]);
+        out[threadIdx.x] = r;
+    }
+}
+
+__device__ __forceinline__ void disc_cells(const double* d, double reach, const Bins& B, int lo[3], int hi[3]) {
+    const double R = fabs(d[6]) + reach;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = bin_of(d[a] - R, B.lo[a], B.inv[a]);
+        hi[a] = bin_of(d[a] + R, B.lo[a], B.inv[a]);
+    }
+}
+
+__global__ void k_bin_count(int32_t n, const double* __restrict__ discs, double reach, Bins B, int32_t* __restrict__ cnt) {
+    GRID_STRIDE_LOOP(i, n) {
+        int lo[3], hi[3];
+        disc_cells(discs + 7 * i, reach, B, lo, hi);
+        for (int x = lo[0]; x <= hi[0]; ++x)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int z = lo[2]; z <= hi[2]; ++z) atomicAdd(&cnt[(x * kBins + y) * kBins + z], 1);
+    }
+}
+
+__global__ void k_bin_fill(int32_t n, const double* __restrict__ discs, double reach, Bins B,
+                           const int64_t* __restrict__ off, int32_t* __restrict__ fill, int32_t* __restrict__ list) {
+    GRID_STRIDE_LOOP(i, n) {
+        int lo[3], hi[3];
+        disc_cells(discs + 7 * i, reach, B, lo, hi);
+        for (int x = lo[0]; x <= hi[0]; ++x)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int z = lo[2]; z <= hi[2]; ++z) {
+                    const int c = (x * kBins + y) * kBins + z;
+                    list[off[c] + atomicAdd(&fill[c], 1)] = (int32_t)i;
+                }
+    }
+}
+
+__global__ void k_crack_cut_binned(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
+                                   const double* __restrict__ discs, Bins B, const int64_t* __restrict__ off,
+                                   const int32_t* __restrict__ list, uint8_t* __restrict__ cut) {
+    GRID_STRIDE_LOOP(e, E) {
+        const d3 p0 = load3(xyz + 3 * (int64_t)edges[2 * e]);
+        const d3 p1 = load3(xyz + 3 * (int64_t)edges[2 * e + 1]);
+        const int bx = bin_of(0.5 * (p0.x + p1.x), B.lo[0], B.inv[0]);
+        const int by = bin_of(0.5 * (p0.y + p1.y), B.lo[1], B.inv[1]);
+        const int bz = bin_of(0.5 * (p0.z + p1.z), B.lo[2], B.inv[2]);
+        const int c = (bx * kBins + by) * kBins + bz;
+        uint8_t hit = 0;
+        for (int64_t k = off[c]; k < off[c + 1] && !hit; ++k) {
+            const double* d = discs + 7 * (int64_t)list[k];
+            const double cx = d[0], cy = d[1], cz = d[2], nx = d[3], ny = d[4], nz = d[5], r = d[6];
+            const double s0 = ((p0.x - cx) * nx + (p0.y - cy) * ny) + (p0.z - cz) * nz;
+            const double s1 = ((p1.x - cx) * nx + (p1.y - cy) * ny) + (p1.z - cz) * nz;
+            if ((s0 < 0.0) == (s1 < 0.0)) continue;
+            const double t = s0 / (s0 - s1);
+            const double qx = p0.x + t * (p1.x - p0.x);
+            const double qy = p0.y + t * (p1.y - p0.y);
+            const double qz = p0.z + t * (p1.z - p0.z);
+            const double d2 = ((qx - cx) * (qx - cx) + (qy - cy) * (qy - cy)) + (qz - cz) * (qz - cz);
+            if (d2 <= r * r) hit = 1;
+        }
+        cut[e] = hit;
+    }
+}
+
 __global__ void k_star1(int64_t E, const double* __restrict__ geo, const double* __restrict__ kappa,
                         const uint8_t* __restrict__ cut, double* __restrict__ star1) {
     GRID_STRIDE_LOOP(e, E) {
@@ -153,6 +272,13 @@ __global__ void k_star1(int64_t E, const double* __restrict__ geo, const double*
 void ensure_geometry(dec_mesh* m) {
     if (m->geo_ready) return;
     dec_ctx* ctx = m->ctx;
+    DBuf<double> ext, part;
+    const int nb = (int)grid_for(m->E, BLOCK, 1024);
+    ext.alloc(ctx, 7);
+    part.alloc(ctx, 7 * (int64_t)nb);
+    hipLaunchKernelGGL(k_geom_extent, dim3(nb), dim3(BLOCK), 0, ctx->stream, m->V, m->xyz.p, m->E, m->edges.p, part.p);
+    hipLaunchKernelGGL(k_geom_extent_fold, dim3(1), dim3(64), 0, ctx->stream, nb, part.p, ext.p);
+    std::memcpy(m->extent, ctx->readback(ext.p, 7 * sizeof(double)), sizeof(m->extent));
     DBuf<double> elem;
     elem.alloc(ctx, 6 * m->T);
     hipLaunchKernelGGL(k_elementary_areas, dim3(grid_for(m->T)), dim3(BLOCK), 0, ctx->stream, m->T, m->tets.p,
@@ -173,9 +299,37 @@ void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const dou
     ensure_geometry(m);
     m->cut.alloc(ctx, m->E);
     m->star1.alloc(ctx, m->E);
-    const unsigned g = grid_for(m->E, BLOCK, 8 * (int64_t)ctx->num_cus);
-    hipLaunchKernelGGL(k_crack_cut, dim3(g), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p, m->xyz.p,
-                       n_cracks, cracks, m->cut.p);
+    if (n_cracks <= kBinnedFrom) {
+        const unsigned g = grid_for(m->E, BLOCK, 8 * (int64_t)ctx->num_cus);
+        hipLaunchKernelGGL(k_crack_cut, dim3(g), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p, m->xyz.p,
+                           n_cracks, cracks, m->cut.p);
+    } else {
+        Bins B;
+        for (int a = 0; a < 3; ++a) {
+            const double ext = m->extent[3 + a] - m->extent[a];
+            B.lo[a] = m->extent[a];
+            B.inv[a] = ext > 0.0 ? kBins / ext : 1.0;
+        }
+        // longest half edge, with a relative margin for the rounding of midpoints and cells
+        const double reach = m->extent[6] * (1.0 + 1e-9) + 1e-12;
+        const int64_t ncell = (int64_t)kBins * kBins * kBins;
+        DBuf<int32_t> cnt, fill, list;
+        DBuf<int64_t> off;
+        cnt.alloc(ctx, ncell);
+        cnt.zero();
+        hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n_cracks)), dim3(BLOCK), 0, ctx->stream, n_cracks, cracks, reach,
+                           B, cnt.p);
+        off.alloc(ctx, ncell + 1);
+        const int64_t total = scan_exclusive_i32_to_i64(ctx, cnt.p, off.p, ncell, true);
+        list.alloc(ctx, total > 0 ? total : 1);
+        cnt.zero();
+        hipLaunchKernelGGL(k_bin_fill, dim3(grid_for(n_cracks)), dim3(BLOCK), 0, ctx->stream, n_cracks, cracks, reach,
+                           B, off.p, cnt.p, list.p);
+        hipLaunchKernelGGL(k_crack_cut_binned, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
+                           m->xyz.p, cracks, B, off.p, list.p, m->cut.p);
+        HIP_CHECK(hipGetLastError());
+        ctx->sync();  // the bins are released on return
+    }
     hipLaunchKernelGGL(k_star1, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->geo.p, kappa,
                        m->cut.p, m->star1.p);
     HIP_CHECK(hipGetLastError());

@@ -64,50 +64,67 @@ __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const in
     }
 }
 
-// insertion sort of each vertex's tet list (short lists)
+// Sort each vertex's tet list (ascending tet id).  One wavefront per vertex:
+// a list of at most 64 distinct ids is ranked in registers (rank = number of
+// smaller ids) and written back; longer lists are insertion-sorted by lane 0.
 __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
-    GRID_STRIDE_LOOP(v, V) {
-        const int64_t b = vt_ptr[v], e = vt_ptr[v + 1];
-        for (int64_t i = b + 1; i < e; ++i) {
-            const int32_t key = vt_list[i];
-            int64_t j = i - 1;
-            while (j >= b && vt_list[j] > key) {
-                vt_list[j + 1] = vt_list[j];
-                --j;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+        const int64_t b = vt_ptr[v];
+        const int d = (int)(vt_ptr[v + 1] - b);
+        if (d <= 64) {
+            const int key = lane < d ? vt_list[b + lane] : INT_MAX;
+            int rank = 0;
+            for (int k = 0; k < 64; ++k) rank += __shfl(key, k, 64) < key;
+            if (lane < d) vt_list[b + rank] = key;
+        } else if (lane == 0) {
+            for (int64_t i = b + 1; i < b + d; ++i) {
+                const int32_t key = vt_list[i];
+                int64_t j = i - 1;
+                while (j >= b && vt_list[j] > key) {
+                    vt_list[j + 1] = vt_list[j];
+                    --j;
+                }
+                vt_list[j + 1] = key;
             }
-            vt_list[j + 1] = key;
         }
     }
 }
 
-// One wavefront per vertex: lane k scans tets k, k+64, ... of the vertex's
-// sorted tet list.  Each round finds the smallest neighbour w > cur (wave
-// minimum) and, when asked, how many of the vertex's tets hold it (wave sum;
-// each tet holds w at most once).  INT_MAX: no neighbour left.
-__device__ __forceinline__ int wave_min_i(int v) {
+// Neighbour enumeration with one 32-lane group per vertex (two vertices per
+// wavefront): lane k of the group holds tets k, k+32, ... of the vertex's
+// sorted tet list (the first in registers).  Each round finds the smallest
+// neighbour w > cur (group minimum) and the tets holding it (ballot; each
+// tet holds w at most once).  INT_MAX: no neighbour left.
+constexpr int NG = 32;
+
+__device__ __forceinline__ int group_min(int v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    for (int off = NG / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, NG));
     return v;
 }
 
-__device__ __forceinline__ int wave_sum_i(int v) {
+__device__ __forceinline__ int group_sum(int v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = NG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, NG);
     return v;
 }
 
-// The lane's first tet stays in registers across rounds; vertices in more
-// than 64 tets (rare) re-read the rest from memory.
-struct LaneTets {
+__device__ __forceinline__ int tet_pos(const int4& q, int w) {
+    return q.x == w ? 0 : (q.y == w ? 1 : (q.z == w ? 2 : (q.w == w ? 3 : -1)));
+}
+
+struct GroupTets {
     int4 q0;
     bool has0;
 };
 
-__device__ __forceinline__ LaneTets load_lane_tets(const int4* __restrict__ tets, const int32_t* __restrict__ list,
-                                                   int64_t b, int d, int lane) {
-    LaneTets t;
-    t.has0 = lane < d;
-    t.q0 = t.has0 ? tets[list[b + lane]] : make_int4(-1, -1, -1, -1);
+__device__ __forceinline__ GroupTets load_group_tets(const int4* __restrict__ tets, const int32_t* __restrict__ list,
+                                                     int64_t b, int d, int g) {
+    GroupTets t;
+    t.has0 = g < d;
+    t.q0 = t.has0 ? tets[list[b + g]] : make_int4(-1, -1, -1, -1);
     return t;
 }
 
@@ -119,73 +136,73 @@ __device__ __forceinline__ void scan_tet(const int4& q, int v, int cur, int* bes
     }
 }
 
-template <bool COUNT>
-__device__ __forceinline__ int wave_next_neighbour(const int4* __restrict__ tets, const int32_t* __restrict__ list,
-                                                   int64_t b, int d, int v, int cur, int lane, const LaneTets& lt,
-                                                   int* count) {
+__device__ __forceinline__ int group_next(const int4* __restrict__ tets, const int32_t* __restrict__ list, int64_t b,
+                                          int d, int v, int cur, int g, const GroupTets& gt) {
     int best = INT_MAX;
-    if (lt.has0) scan_tet(lt.q0, v, cur, &best);
-    for (int k = lane + 64; k < d; k += 64) scan_tet(tets[list[b + k]], v, cur, &best);
-    best = wave_min_i(best);
-    if (COUNT && best != INT_MAX) {
-        int c = 0;
-        if (lt.has0) c += (lt.q0.x == best) | (lt.q0.y == best) | (lt.q0.z == best) | (lt.q0.w == best);
-        for (int k = lane + 64; k < d; k += 64) {
-            const int4 q = tets[list[b + k]];
-            c += (q.x == best) | (q.y == best) | (q.z == best) | (q.w == best);
-        }
-        *count = wave_sum_i(c);
-    }
-    return best;
+    if (gt.has0) scan_tet(gt.q0, v, cur, &best);
+    for (int k = g + NG; k < d; k += NG) scan_tet(tets[list[b + k]], v, cur, &best);
+    return group_min(best);
 }
 
 __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
                             const int32_t* __restrict__ vt_list, int64_t V, int32_t* __restrict__ n_up,
-                            int32_t* __restrict__ row_len) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+                            int32_t* __restrict__ row_len, int32_t* __restrict__ n_inc) {
+    const int g = threadIdx.x & (NG - 1);
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / NG;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NG; v < V; v += ngroups) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
-        int cur = -1, up = 0, all = 0, c;
-        const LaneTets lt = load_lane_tets(tets, vt_list, b, d, lane);
+        const GroupTets gt = load_group_tets(tets, vt_list, b, d, g);
+        int cur = -1, up = 0, all = 0, inc = 0;
         while (true) {
-            const int w = wave_next_neighbour<false>(tets, vt_list, b, d, (int)v, cur, lane, lt, &c);
+            const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
             if (w == INT_MAX) break;
             cur = w;
             ++all;
-            up += (w > v);
+            if (w > v) {
+                ++up;
+                int c = gt.has0 ? (tet_pos(gt.q0, w) >= 0) : 0;
+                for (int k = g + NG; k < d; k += NG) c += tet_pos(tets[vt_list[b + k]], w) >= 0;
+                inc += group_sum(c);
+            }
         }
-        if (lane == 0) {
+        if (g == 0) {
             n_up[v] = up;
             row_len[v] = all + 1;
+            n_inc[v] = inc;
         }
     }
 }
 
-// Row v of the pattern: lower neighbours, the diagonal, upper neighbours,
-// ascending.  Upper neighbours define the edges (v, w) numbered from
-// up_ptr[v] in ascending w, i.e. lexicographic (lo, hi) order overall.
+// Row v of the pattern (lower neighbours, the diagonal, upper neighbours,
+// ascending).  Upper neighbours w define the edges (v, w), numbered from
+// up_ptr[v] in ascending w -- lexicographic (lo, hi) order overall -- and
+// their incidence lists: the tets of v holding w, in ascending tet order, as
+// tet * 6 + local edge, from inc_ptr[v] on.  Also the tet -> edge map.
 __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
                            const int32_t* __restrict__ vt_list, int64_t V, const int64_t* __restrict__ up_ptr,
-                           const int64_t* __restrict__ row_ptr, int32_t* __restrict__ edges,
-                           int32_t* __restrict__ et_cnt, int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
+                           const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ inc_ptr,
+                           int32_t* __restrict__ edges, int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc,
+                           int32_t* __restrict__ tet_edge, int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
                            int32_t* __restrict__ diag_pos) {
     const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+    const int g = threadIdx.x & (NG - 1);
+    const int gbase = lane & ~(NG - 1);  // first lane of this group in the wavefront
+    const uint64_t below = ((uint64_t)1 << g) - 1;
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / NG;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NG; v < V; v += ngroups) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
-        int64_t pos = row_ptr[v], ep = up_ptr[v];
+        const GroupTets gt = load_group_tets(tets, vt_list, b, d, g);
+        int64_t pos = row_ptr[v], ep = up_ptr[v], ip = inc_ptr[v];
         bool diag = false;
-        int cur = -1, c = 0;
-        const LaneTets lt = load_lane_tets(tets, vt_list, b, d, lane);
+        int cur = -1;
         while (true) {
-            const int w = wave_next_neighbour<true>(tets, vt_list, b, d, (int)v, cur, lane, lt, &c);
+            const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
             if (w == INT_MAX) break;
             cur = w;
             if (w > v && !diag) {
-                if (lane == 0) {
+                if (g == 0) {
                     col[pos] = (int32_t)v;
                     nz_edge[pos] = -1;
                     diag_pos[v] = (int32_t)pos;
@@ -193,26 +210,42 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
                 ++pos;
                 diag = true;
             }
-            if (lane == 0) {
+            if (g == 0) {
                 col[pos] = w;
-                if (w < v) {
-                    nz_edge[pos] = -2;  // resolved by k_lower_edge_ids
-                } else {
-                    nz_edge[pos] = (int32_t)ep;
-                    edges[2 * ep] = (int32_t)v;
-                    edges[2 * ep + 1] = w;
-                    et_cnt[ep] = c;
-                }
+                nz_edge[pos] = w < v ? -2 : (int32_t)ep;  // lower entries: k_lower_edge_ids
             }
-            if (w > v) ++ep;
             ++pos;
+            if (w < v) continue;
+            if (g == 0) {
+                edges[2 * ep] = (int32_t)v;
+                edges[2 * ep + 1] = w;
+                et_ptr[ep] = ip;
+            }
+            // incidences in ascending tet order: blocks of NG tets, lane order inside a block
+            for (int k0 = 0; k0 < d; k0 += NG) {
+                const int k = k0 + g;
+                int4 q = make_int4(-1, -1, -1, -1);
+                if (k < d) q = k0 == 0 ? gt.q0 : tets[vt_list[b + k]];
+                const int pw = tet_pos(q, w);
+                const uint64_t ball = (__ballot(pw >= 0) >> gbase) & 0xffffffffull;
+                if (pw >= 0) {
+                    const int t = vt_list[b + k];
+                    const int pv = tet_pos(q, (int)v);
+                    const int slot = t * 6 + local_edge(pv < pw ? pv : pw, pv < pw ? pw : pv);
+                    et_inc[ip + __popcll(ball & below)] = slot;
+                    tet_edge[slot] = (int32_t)ep;
+                }
+                ip += __popcll(ball);
+            }
+            ++ep;
         }
-        if (!diag && lane == 0) {
+        if (!diag && g == 0) {
             col[pos] = (int32_t)v;
             nz_edge[pos] = -1;
             diag_pos[v] = (int32_t)pos;
         }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) et_ptr[up_ptr[V]] = inc_ptr[V];
 }
 
 // Entries (v, w) with w < v belong to edge (w, v), found by binary search in
@@ -239,34 +272,6 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
             }
             if (found < 0) atomicOr(err, 8u);
             nz_edge[k] = (int32_t)found;
-        }
-    }
-}
-
-// Incidences of edge (lo, hi): lo's tets that contain hi, ascending, as tet*6 + local edge.
-__global__ void k_et_fill(int64_t E, const int32_t* __restrict__ edges, const int4* __restrict__ tets,
-                          const int64_t* __restrict__ vt_ptr, const int32_t* __restrict__ vt_list,
-                          const int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc,
-                          int32_t* __restrict__ tet_edge) {
-    GRID_STRIDE_LOOP(e, E) {
-        const int lo = edges[2 * e], hi = edges[2 * e + 1];
-        int64_t out = et_ptr[e];
-        for (int64_t k = vt_ptr[lo]; k < vt_ptr[lo + 1]; ++k) {
-            const int t = vt_list[k];
-            const int4 q = tets[t];
-            int pl = -1, ph = -1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int w = vget(q, r);
-                if (w == lo) pl = r;
-                if (w == hi) ph = r;
-            }
-            if (ph >= 0) {
-                const int a = pl < ph ? pl : ph, bb = pl < ph ? ph : pl;
-                const int slot = t * 6 + local_edge(a, bb);
-                et_inc[out++] = slot;
-                tet_edge[slot] = (int32_t)e;  // each (tet, local edge) has exactly one edge
-            }
         }
     }
 }
@@ -356,53 +361,48 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     cnt.zero();
     hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, m->vt_ptr.p, cnt.p,
                        m->vt_list.p);
-    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
+    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
     HIP_CHECK(hipGetLastError());
 
-    // neighbours: counts, then edges and the CSR pattern
-    DBuf<int32_t> n_up, row_len;
+    // neighbours: counts, then edges, incidences and the CSR pattern (one 32-lane group per vertex)
+    DBuf<int32_t> n_up, row_len, n_inc;
     n_up.alloc(ctx, V);
     row_len.alloc(ctx, V);
-    // one wavefront (64 lanes) per vertex
-    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
-                       n_up.p, row_len.p);
+    n_inc.alloc(ctx, V);
+    hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(NG * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
+                       n_up.p, row_len.p, n_inc.p);
     HIP_CHECK(hipGetLastError());
     m->up_ptr.alloc(ctx, V + 1);
     const int64_t E = scan_exclusive_i32_to_i64(ctx, n_up.p, m->up_ptr.p, V, true);
-    DBuf<int64_t> row_ptr64;
+    DBuf<int64_t> row_ptr64, inc_ptr;
     row_ptr64.alloc(ctx, V + 1);
+    inc_ptr.alloc(ctx, V + 1);
     const int64_t nnz = scan_exclusive_i32_to_i64(ctx, row_len.p, row_ptr64.p, V, true);
+    const int64_t ninc = scan_exclusive_i32_to_i64(ctx, n_inc.p, inc_ptr.p, V, true);
     DEC_REQUIRE(nnz == V + 2 * E, DEC_ETOPO, "internal: pattern size mismatch");
+    DEC_REQUIRE(ninc == 6 * T, DEC_ETOPO, "internal: incidence count mismatch");
     DEC_REQUIRE(nnz < (int64_t(1) << 31) && 6 * T < (int64_t(1) << 31), DEC_EINVAL,
                 "mesh too large for int32 CSR indices");
     m->E = E;
     m->nnz = nnz;
 
     m->edges.alloc(ctx, 2 * E);
-    DBuf<int32_t> et_cnt;
-    et_cnt.alloc(ctx, E);
+    m->et_ptr.alloc(ctx, E + 1);
+    m->et_inc.alloc(ctx, 6 * T);
+    DBuf<int32_t> tet_edge;
+    tet_edge.alloc(ctx, 6 * T);
     m->col.alloc(ctx, nnz);
     m->nz_edge.alloc(ctx, nnz);
     m->diag_pos.alloc(ctx, V);
-    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
-                       m->up_ptr.p, row_ptr64.p, m->edges.p, et_cnt.p, m->col.p, m->nz_edge.p, m->diag_pos.p);
+    hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(NG * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
+                       m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, tet_edge.p,
+                       m->col.p, m->nz_edge.p, m->diag_pos.p);
     err.zero();
     hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
                        m->up_ptr.p, m->edges.p, m->nz_edge.p, err.p);
     HIP_CHECK(hipGetLastError());
     m->row_ptr.alloc(ctx, V + 1);
     copy_i64_to_i32(ctx, row_ptr64.p, m->row_ptr.p, V + 1);
-
-    // edge -> tet incidences
-    m->et_ptr.alloc(ctx, E + 1);
-    const int64_t ninc = scan_exclusive_i32_to_i64(ctx, et_cnt.p, m->et_ptr.p, E, true);
-    DEC_REQUIRE(ninc == 6 * T, DEC_ETOPO, "internal: incidence count mismatch");
-    m->et_inc.alloc(ctx, 6 * T);
-    DBuf<int32_t> tet_edge;
-    tet_edge.alloc(ctx, 6 * T);
-    hipLaunchKernelGGL(k_et_fill, dim3(grid_for(E)), dim3(BLOCK), 0, s, E, m->edges.p, tq, m->vt_ptr.p,
-                       m->vt_list.p, m->et_ptr.p, m->et_inc.p, tet_edge.p);
-    HIP_CHECK(hipGetLastError());
 
     // faces
     m->tet_bface.alloc(ctx, T);
