@@ -65,6 +65,7 @@ typedef void (*dec_free_fn)(void* ptr, void* user);
  * the library's device memory (both NULL: hipMalloc/hipFree). */
 int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_free_fn free_fn,
                void* user);
+/* DEC_ESTATE while meshes or servers created on ctx are still alive. */
 int dec_destroy(dec_ctx* ctx);
 const char* dec_status_string(int status);
 const char* dec_last_error(const dec_ctx* ctx);

@@ -8,7 +8,9 @@ that library.  This module only checks and marshals arguments; PyTorch
 provides device memory (its caching allocator backs the library's
 allocations) and streams.
 """
+import atexit
 import ctypes
+import weakref
 
 import torch
 
@@ -18,6 +20,19 @@ from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_PREC_FP64, DEC_P
 
 __all__ = ["DecError", "Context", "Mesh", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
            "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL"]
+
+
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release every library object before torch (whose allocator backs them) shuts down."""
+    for ctx in list(_LIVE):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 class DecError(RuntimeError):
@@ -71,6 +86,8 @@ class Context:
         if rc != 0:
             raise DecError(rc, "dec_create failed")
         self.handle = h
+        self._children = weakref.WeakSet()  # meshes and servers: closed before the context
+        _LIVE.add(self)
 
     def check(self, rc, what):
         if rc != 0:
@@ -80,6 +97,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for child in list(self._children):
+                child.close()
             self.lib.dec_destroy(self.handle)
             self.handle = None
 
@@ -105,6 +124,7 @@ class Mesh:
                                          _ptr(tets, torch.int32, 4 * T, "tets"), ctypes.byref(h))
         ctx.check(rc, "dec_build_topology")
         self.handle = h
+        ctx._children.add(self)
         vals = [ctypes.c_int64() for _ in range(6)]
         ctx.check(self.lib.dec_mesh_info(h, *[ctypes.byref(v) for v in vals]), "dec_mesh_info")
         self.V, self.T, self.E, self.F, self.F_boundary, self.nnz = (v.value for v in vals)
@@ -235,6 +255,7 @@ class Server:
         ctx.check(self.lib.dec_server_create(ctx.handle, int(hbm_budget_bytes), ctypes.byref(o), ctypes.byref(h)),
                   "dec_server_create")
         self.handle = h
+        ctx._children.add(self)
         self._keep = {}
 
     def submit(self, req, user_tag=0):

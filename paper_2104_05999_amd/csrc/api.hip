@@ -45,6 +45,7 @@ void* dec_ctx::readback(const void* dptr, size_t bytes) {
 dec_mesh::~dec_mesh() {
     if (solve) destroy_solve_cache(solve);
     solve = nullptr;
+    if (owner) owner->live_children -= 1;
 }
 
 // ---------------------------------------------------------------- scan
@@ -200,6 +201,10 @@ int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_
 
 int dec_destroy(dec_ctx* ctx) {
     if (!ctx) return DEC_EINVAL;
+    if (ctx->live_children > 0) {
+        ctx->last_error = "context still owns meshes or servers";
+        return DEC_ESTATE;
+    }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return DEC_OK;

@@ -43,6 +43,7 @@ struct dec_ctx {
     std::string last_error;
     int num_cus = 256;
     int num_xcds = 8;
+    int live_children = 0;  // meshes and servers created on this context and not yet destroyed
     // small pinned staging area for scalar read-backs
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
@@ -127,6 +128,7 @@ struct SolveCache;  // Krylov vectors, reduction scratch and captured graphs
 // ---------------------------------------------------------------- mesh
 struct dec_mesh {
     dec_ctx* ctx = nullptr;
+    dec_ctx* owner = nullptr;  // the context counted in live_children (servers re-point ctx)
     int64_t V = 0, T = 0, E = 0, F = 0, Fb = 0, nnz = 0;
 
     DBuf<double> xyz;        // [V*3]

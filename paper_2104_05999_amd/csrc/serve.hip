@@ -741,6 +741,7 @@ int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_op
         DEC_REQUIRE(o.tol > 0 && o.inner_tol > 0 && o.inner_tol < 1 && o.max_iters > 0, DEC_EINVAL, "bad tolerances");
         ctx->set_device();
         s->ctx = ctx;
+        ctx->live_children += 1;
         s->opts = o;
         s->budget = hbm_budget_bytes;
         s->t0 = std::chrono::steady_clock::now();
@@ -949,6 +950,7 @@ int dec_server_destroy(dec_server* s) {
     if (s->setup_ctx.pinned) (void)hipHostFree(s->setup_ctx.pinned);
     if (s->solve_stream) (void)hipStreamDestroy(s->solve_stream);
     if (s->setup_stream) (void)hipStreamDestroy(s->setup_stream);
+    if (s->ctx) s->ctx->live_children -= 1;
     delete s;
     return DEC_OK;
 }

@@ -428,6 +428,8 @@ int dec_build_topology(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, co
     *out = nullptr;
     dec_mesh* m = new dec_mesh();
     m->ctx = ctx;
+    m->owner = ctx;
+    ctx->live_children += 1;
     try {
         DEC_REQUIRE(V > 0 && T > 0 && xyz && tets, DEC_EINVAL, "empty mesh or NULL array");
         DEC_REQUIRE(V < (int64_t(1) << 31), DEC_EINVAL, "too many vertices for int32 indices");

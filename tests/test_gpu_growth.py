@@ -1,0 +1,127 @@
+"""Crack growth: 1000 penny discs grown by 2% per step, each step warm-started from the last.
+
+64^3 replica: against stored oracle values (tests/golden/growth64.*, written
+by tests/golden/make_golden_growth.py from the oracle only) -- cut and
+pinned counts and the first/last cut sets bit-exact, solution samples to
+1e-10 ||x*|| (GPU to 1e-14), k_eff to 1e-9 of the uncracked value.
+
+256^3 (16,974,593 vertices): counts against the closed forms, the cut
+flags of 20,000 seeded lattice edges against the oracle predicate, and
+properties that hold at any size: the FP64 residual, Rayleigh monotonicity
+of k_eff as cracks grow, Q_in = Q_out = E, mixed precision agreeing with
+FP64.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    import paper_2104_05999_amd as dec
+    c = dec.Context(dev)
+    yield c
+    c.close()
+
+
+def _mesh(ctx, dev, n):
+    xyz, tets = W.kuhn_cube(n, device=dev)
+    m = ctx.mesh(xyz, tets)
+    c = W.kuhn_counts(n)
+    kappa = torch.as_tensor(W.lognormal_kappa(c["E"], 1.0, 1), device=dev)
+    bt, bv, side = W.x_sides(n)
+    t = lambda a: torch.as_tensor(a, device=dev)  # noqa: E731
+    return m, kappa, t(bt), t(bv), t(side)
+
+
+def _step(m, kappa, discs, s, dev, bt, bv):
+    cut, _ = m.hodge1(kappa, torch.as_tensor(W.grown_radii(discs, s), device=dev), want_star=False)
+    m.assemble()
+    npin, _ = m.apply_bc(bt, bv, want_rhs=False)
+    return cut, npin
+
+
+def test_growth64_against_oracle(ctx, dev):
+    meta = json.load(open(os.path.join(HERE, "golden", "growth64.json")))
+    arr = np.load(os.path.join(HERE, "golden", "growth64.npz"))
+    n = meta["n"]
+    m, kappa, bt, bv, side = _mesh(ctx, dev, n)
+    discs = W.penny_cracks(1000, 4)
+    vs = torch.as_tensor(arr["vertex_sample"], device=dev)
+    k0 = meta["steps"]["0"]["k_eff"]
+    T = torch.zeros(m.V, dtype=torch.float64, device=dev)
+    steps = sorted(int(s) for s in meta["steps"])
+    for s in steps:
+        ref = meta["steps"][str(s)]
+        cut, npin = _step(m, kappa, discs, s, dev, bt, bv)
+        assert int(cut.sum()) == ref["n_cut"] and npin == ref["n_pinned"], s
+        if f"cut_edges_{s}" in arr.files:
+            assert np.array_equal(torch.nonzero(cut).flatten().cpu().numpy(), arr[f"cut_edges_{s}"])
+        T, st, rc = m.solve(T=T, tol=1e-14, warm_start=1, check=False)
+        assert rc == 0, (s, st)
+        err = np.abs(T[vs].cpu().numpy() - arr[f"x_sample_{s}"]).max()
+        assert err <= 1e-10 * ref["x_norm"], (s, err)
+        f = m.flux(T, side)
+        assert abs(f["k_eff"] - ref["k_eff"]) <= 1e-9 * k0, s
+        assert abs(f["q_in"] - ref["q_in"]) <= 1e-9 * k0 and abs(f["q_out"] - ref["q_out"]) <= 1e-9 * k0
+    # the last step again in mixed precision, cold
+    Tm, st, rc = m.solve(tol=1e-14, precision=1, check=False)
+    assert rc == 0
+    err = np.abs(Tm[vs].cpu().numpy() - arr[f"x_sample_{steps[-1]}"]).max()
+    assert err <= 1e-10 * meta["steps"][str(steps[-1])]["x_norm"]
+    m.close()
+
+
+def _kuhn_edge_sample(n, count, seed):
+    """Seeded lattice edges (lo, hi) of the Kuhn split: v -> v + d for the seven directions it uses."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dirs = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [0, 1, 1], [1, 1, 1]])
+    ijk = rng.integers(0, n, size=(count, 3))
+    d = dirs[rng.integers(0, 7, size=count)]
+    m = n + 1
+    lo = ijk[:, 2] + m * (ijk[:, 1] + m * ijk[:, 0])
+    hj = ijk + d
+    hi = hj[:, 2] + m * (hj[:, 1] + m * hj[:, 0])
+    return np.stack([lo, hi], axis=1)
+
+
+def test_growth256_properties(ctx, dev):
+    n = 256
+    m, kappa, bt, bv, side = _mesh(ctx, dev, n)
+    c = W.kuhn_counts(n)
+    assert (m.V, m.T, m.E, m.F, m.nnz) == (c["V"], c["T"], c["E"], c["F"], c["nnz"])
+    discs = W.penny_cracks(1000, 4)
+    xyz = W.kuhn_cube(n)[0]
+    sample = _kuhn_edge_sample(n, 20000, 99)
+    edges = m.edges().cpu().numpy().astype(np.int64)
+    keys = edges[:, 0] * m.V + edges[:, 1]
+    ids = np.searchsorted(keys, sample[:, 0] * m.V + sample[:, 1])
+    assert np.array_equal(keys[ids], sample[:, 0] * m.V + sample[:, 1])
+    T = torch.zeros(m.V, dtype=torch.float64, device=dev)
+    prev, k0 = np.inf, None
+    for s in (0, 10, 20, 30, 40, 50):
+        cut, npin = _step(m, kappa, discs, s, dev, bt, bv)
+        want = O.crack_cut(xyz, sample, W.grown_radii(discs, s))
+        assert np.array_equal(cut.cpu().numpy()[ids].astype(bool), want), s
+        T, st, rc = m.solve(T=T, tol=1e-10, warm_start=1)
+        assert rc == 0 and st["rel_residual"] <= 1e-10
+        f = m.flux(T, side)
+        assert f["k_eff"] <= prev * (1 + 1e-9), (s, f["k_eff"], prev)
+        prev = f["k_eff"]
+        k0 = f["k_eff"] if k0 is None else k0
+        # the boundary fluxes are first-order in the residual; bound them on the uncracked flux scale
+        assert abs(f["q_in"] - f["energy"]) <= 1e-6 * k0, s
+        assert abs(f["q_out"] - f["energy"]) <= 1e-6 * k0, s
+    Tm, stm, rc = m.solve(tol=1e-10, precision=1)  # cold, mixed precision
+    fm = m.flux(Tm, side)
+    assert rc == 0 and abs(fm["k_eff"] - prev) <= 1e-9 * max(prev, 1e-12) + 1e-12
+    m.close()

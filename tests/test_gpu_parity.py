@@ -315,3 +315,64 @@ def test_pruned_pattern_products_are_bit_identical(ctx, dev):
     assert torch.equal(y_pruned, y_full) and torch.equal(y_full, y_csr)
     assert torch.equal(T_pruned, T_full)
     assert st_p["spmv_nnz"] < st_f["spmv_nnz"] == m.nnz
+
+
+def test_error_paths(ctx, dev):
+    import paper_2104_05999_amd as dec
+    n = 3
+    xyz, tets = W.kuhn_cube(n)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    try:
+        bt, bv, _ = W.x_sides(n)
+        with pytest.raises(dec.DecError) as ei:      # assembly before *1
+            m.assemble()
+        assert ei.value.code == -8
+        m.hodge1()
+        with pytest.raises(dec.DecError) as ei:      # solve before boundary data
+            m.assemble()
+            m.solve()
+        assert ei.value.code == -8
+        bad = bt.copy()
+        bad[0] = 7
+        with pytest.raises(dec.DecError) as ei:
+            m.apply_bc(_t(bad, dev), _t(bv, dev))
+        assert ei.value.code == -1
+        m.apply_bc(_t(bt, dev), _t(bv, dev))
+        for kw in ({"tol": 0.0}, {"inner_tol": 2.0}, {"precision": 5}, {"precond": 9}, {"max_iters": 0}):
+            with pytest.raises(dec.DecError) as ei:
+                m.solve(**kw)
+            assert ei.value.code == -1
+        with pytest.raises((ValueError, TypeError)):  # a crack record is 7 doubles
+            m.hodge1(None, torch.zeros(5, dtype=torch.float64, device=dev).reshape(1, 5))
+    finally:
+        m.close()
+
+
+def test_context_outlives_its_meshes(dev):
+    """A context that still owns a mesh refuses to go; closing it from Python closes the mesh first."""
+    import paper_2104_05999_amd as dec
+    c = dec.Context(dev)
+    xyz, tets = W.kuhn_cube(2)
+    m = c.mesh(_t(xyz, dev), _t(tets, dev))
+    assert c.lib.dec_destroy(c.handle) == -8   # DEC_ESTATE
+    c.close()
+    assert m.handle is None and c.handle is None
+
+
+def test_nonfinite_conductivity_breaks_down(ctx, dev):
+    n = 4
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, _ = W.x_sides(n)
+    edges = O.edges_of(tets, len(xyz))
+    interior = np.flatnonzero((bt[edges[:, 0]] == 0) & (bt[edges[:, 1]] == 0))
+    kap = np.ones(len(edges))
+    kap[interior[len(interior) // 2]] = np.nan   # an edge between two unknowns
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    try:
+        m.hodge1(_t(kap, dev))
+        m.assemble()
+        m.apply_bc(_t(bt, dev), _t(bv, dev))
+        _, st, rc = m.solve(check=False)
+        assert rc == -5  # DEC_EBREAKDOWN, reported rather than a silent NaN solution
+    finally:
+        m.close()
