@@ -268,22 +268,26 @@ def crack_growth(ctx, dev, n=256, steps=51, n_discs=1000, seed=4):
            "topology_s": round(setup_s, 3)}
     for name, prec in (("fp64", 0), ("mixed", 1)):
         T = torch.zeros(mesh.V, dtype=torch.float64, device=dev)
-        curve, iters, cuts = [], [], []
+        curve, iters, cuts, status, step_ms = [], [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(steps):
+            ts = time.perf_counter()
             cut, _ = mesh.hodge1(kappa, grown[s], want_star=False)
             mesh.assemble()
             mesh.apply_bc(bt, bv, want_rhs=False)
-            T, st, rc = mesh.solve(T=T, tol=1e-10, precision=prec, warm_start=1)
+            T, st, rc = mesh.solve(T=T, tol=1e-10, precision=prec, warm_start=1, check=False)
             f = mesh.flux(T, side)
             curve.append(f["k_eff"])
             iters.append(st["iterations"])
             cuts.append(int(cut.sum()))
-            print(f"[bench] growth {name} step {s}: k_eff {f['k_eff']:.9f} its {st['iterations']}",
-                  file=sys.stderr, flush=True)
+            status.append(rc)
+            step_ms.append(round(1e3 * (time.perf_counter() - ts), 2))
+            print(f"[bench] growth {name} step {s}: k_eff {f['k_eff']:.9f} its {st['iterations']} "
+                  f"rc {rc} {step_ms[-1]} ms", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "k_eff": curve, "iterations": iters}
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "k_eff": curve, "iterations": iters,
+                     "status": status, "step_ms": step_ms}
         out["n_cut"] = cuts
     out["mixed_vs_fp64_speedup"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 3)
     out["max_abs_keff_diff"] = max(abs(a - b) for a, b in zip(out["fp64"]["k_eff"], out["mixed"]["k_eff"]))
@@ -336,6 +340,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--serve-requests", type=int, default=512, help="serving stream length (0: skip)")
+    ap.add_argument("--growth-n", type=int, default=256)
+    ap.add_argument("--growth-steps", type=int, default=51)
     ap.add_argument("--crack-growth", action="store_true",
                     help="instead of the default line: the 256^3 crack-growth chains (FP64 and mixed)")
     args = ap.parse_args()
@@ -352,7 +358,7 @@ def main():
     ctx = dec.Context(dev)
     if args.crack_growth:
         print(json.dumps({"metric": "crack growth k_eff(step), mixed vs FP64 wall time", "n_gpus": 1,
-                          "data": "synthetic", **crack_growth(ctx, dev)}))
+                          "data": "synthetic", **crack_growth(ctx, dev, n=args.growth_n, steps=args.growth_steps)}))
         return
     inp = make_inputs(args.n, dev)
     precond = dec.DEC_PRECOND_FSAI if args.precond == "fsai" else dec.DEC_PRECOND_JACOBI
