@@ -336,6 +336,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--precond", choices=["jacobi", "fsai"], default="jacobi")
     ap.add_argument("--no-profile", action="store_true", help="time without per-SpMV events")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="carry HIP events on every k-th SpMV launch of the timed solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a plain device copy of this size")
@@ -362,7 +364,7 @@ def main():
         return
     inp = make_inputs(args.n, dev)
     precond = dec.DEC_PRECOND_FSAI if args.precond == "fsai" else dec.DEC_PRECOND_JACOBI
-    profile = 0 if args.no_profile else 1
+    profile = 0 if args.no_profile else args.profile_every
     print(f"[bench] n={args.n} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         st, f, counts, rc = run_step(ctx, inp, precond=precond, profile=profile)

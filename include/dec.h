@@ -152,7 +152,8 @@ typedef struct dec_solve_opts {
     int32_t format;              /* DEC_FMT_* for the SpMV                         */
     int32_t chunk;               /* iterations per launch batch (0: default)       */
     int32_t use_graph;           /* capture each batch in a hipGraph               */
-    int32_t profile;             /* time every SpMV launch with HIP events          */
+    int32_t profile;             /* 0: off; k > 0: time SpMV launches with HIP events,
+                                    every k-th one of each launch batch (1: all)   */
 } dec_solve_opts;
 
 typedef struct dec_solve_stats {

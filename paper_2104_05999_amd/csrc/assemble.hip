@@ -1,8 +1,7 @@
 // Assembly of L = d0^T *1 d0 on the static pattern (Section 2.1; the paper
 // keeps the system matrix's form fixed when cracks are inserted, Section
 // 2.3): L_ij = -*1_e, L_ii = sum of *1_e over the row's edges in ascending
-// column order.  One thread per row, no atomics, so the values are
-// deterministic.  The FP32 copy and the sliced-ELL copies are refreshed
+// column order.  No atomics, so the values are deterministic.  The FP32 copy and the sliced-ELL copies are refreshed
 // from the FP64 CSR values.
 #include "common.h"
 
@@ -11,22 +10,40 @@ void clear_graphs(SolveCache* c);
 
 namespace {
 
+// One ROWG-lane group per row: the group loads a run of ROWG entries at a
+// time (coalesced), writes the off-diagonal values, and every lane adds the
+// run's *1 values to the diagonal in ascending column order (shuffles), so
+// the diagonal is the same sequential sum as a one-thread-per-row loop.
+constexpr int ROWG = 16;
+
 __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nz_edge,
                                   const int32_t* __restrict__ diag_pos, const double* __restrict__ star1,
                                   double* __restrict__ val64, float* __restrict__ val32) {
-    GRID_STRIDE_LOOP(v, V) {
+    const int g = threadIdx.x & (ROWG - 1);
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / ROWG;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / ROWG; v < V; v += ngroups) {
+        const int32_t b = row_ptr[v], n = row_ptr[v + 1] - b;
         double sum = 0.0;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t e = nz_edge[k];
-            if (e < 0) continue;
-            const double s = star1[e];
-            val64[k] = -s;
-            val32[k] = static_cast<float>(-s);
-            sum += s;
+        for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
+            const int32_t k = k0 + g;
+            const int32_t e = k < n ? nz_edge[b + k] : -1;
+            const double s = e >= 0 ? star1[e] : 0.0;
+            if (e >= 0) {
+                val64[b + k] = -s;
+                val32[b + k] = static_cast<float>(-s);
+            }
+            const int run = min(ROWG, n - k0);
+            for (int j = 0; j < run; ++j) {
+                const double sj = __shfl(s, j, ROWG);
+                const int32_t ej = __shfl(e, j, ROWG);
+                if (ej >= 0) sum += sj;
+            }
         }
-        const int32_t d = diag_pos[v];
-        val64[d] = sum;
-        val32[d] = static_cast<float>(sum);
+        if (g == 0) {
+            const int32_t d = diag_pos[v];
+            val64[d] = sum;
+            val32[d] = static_cast<float>(sum);
+        }
     }
 }
 
@@ -40,19 +57,28 @@ __device__ __forceinline__ bool kept(int32_t k, const int32_t* __restrict__ nz_e
     return e < 0 || geo == nullptr || geo[e] != 0.0;
 }
 
-__global__ void k_sell_width(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
-                             const int32_t* __restrict__ nz_edge, const double* __restrict__ geo,
-                             int32_t* __restrict__ width64) {
-    GRID_STRIDE_LOOP(s, nslices) {
-        int w = 0;
-        const int64_t r0 = s * SELL_C;
-        for (int64_t r = r0; r < r0 + SELL_C && r < V; ++r) {
-            int len = 0;
+// Stored entries per slice: each thread counts its row's kept entries and the
+// wavefront -- the slice's 64 rows -- takes the maximum.  Also the number of
+// kept entries, per block.
+__global__ __launch_bounds__(BLOCK) void k_sell_width(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
+                                                      const int32_t* __restrict__ nz_edge,
+                                                      const double* __restrict__ geo, int32_t* __restrict__ width64,
+                                                      unsigned long long* __restrict__ kept_count) {
+    static_assert(SELL_C == 64, "one slice per wavefront");
+    __shared__ unsigned long long lds[BLOCK / 64];
+    unsigned long long total = 0;
+    GRID_STRIDE_LOOP(r, nslices * SELL_C) {
+        int len = 0;
+        if (r < V)
             for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) len += kept(k, nz_edge, geo);
-            w = max(w, len);
-        }
-        width64[s] = w * SELL_C;  // entries in the slice
+        total += len;
+        int w = len;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
+        if ((threadIdx.x & 63) == 0) width64[r / SELL_C] = w * SELL_C;  // entries in the slice
     }
+    total = block_sum(total, lds);
+    if (threadIdx.x == 0 && total) atomicAdd(kept_count, total);
 }
 
 __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
@@ -83,15 +109,6 @@ __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restric
     }
 }
 
-__global__ void k_count_kept(int64_t nnz, const int32_t* __restrict__ nz_edge, const double* __restrict__ geo,
-                             unsigned long long* __restrict__ count) {
-    __shared__ unsigned long long lds[BLOCK / 64];
-    unsigned long long c = 0;
-    GRID_STRIDE_LOOP(k, nnz) c += kept((int32_t)k, nz_edge, geo);
-    c = block_sum(c, lds);
-    if (threadIdx.x == 0 && c) atomicAdd(count, c);
-}
-
 __global__ void k_sell_values(int64_t n, const int32_t* __restrict__ ssrc, const double* __restrict__ v64,
                               double* __restrict__ s64, float* __restrict__ s32) {
     GRID_STRIDE_LOOP(i, n) {
@@ -109,16 +126,14 @@ void build_sell_pattern(dec_mesh* m) {
     S.nslices = (m->V + SELL_C - 1) / SELL_C;
     DBuf<int32_t> w;
     w.alloc(ctx, S.nslices);
-    const double* geo = m->prune_geometric_zeros ? m->geo.p : nullptr;
-    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices)), dim3(BLOCK), 0, ctx->stream, m->V, S.nslices,
-                       m->row_ptr.p, m->nz_edge.p, geo, w.p);
-    S.ptr.alloc(ctx, S.nslices + 1);
-    S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
     DBuf<unsigned long long> cnt;
     cnt.alloc(ctx, 1);
     cnt.zero();
-    hipLaunchKernelGGL(k_count_kept, dim3(grid_for(m->nnz, BLOCK, 4096)), dim3(BLOCK), 0, ctx->stream, m->nnz,
-                       m->nz_edge.p, geo, cnt.p);
+    const double* geo = m->prune_geometric_zeros ? m->geo.p : nullptr;
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
+                       S.nslices, m->row_ptr.p, m->nz_edge.p, geo, w.p, cnt.p);
+    S.ptr.alloc(ctx, S.nslices + 1);
+    S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
     S.kept = (int64_t) * static_cast<unsigned long long*>(ctx->readback(cnt.p, sizeof(unsigned long long)));
     S.col.alloc(ctx, S.entries);
     S.src.alloc(ctx, S.entries);
@@ -144,7 +159,7 @@ void assemble_device(dec_mesh* m) {
     DEC_REQUIRE(m->star_ready, DEC_ESTATE, "dec_assemble needs dec_hodge1 first");
     m->val64.alloc(ctx, m->nnz);
     m->val32.alloc(ctx, m->nnz);
-    hipLaunchKernelGGL(k_assemble_values, dim3(grid_for(m->V)), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p,
+    hipLaunchKernelGGL(k_assemble_values, dim3(grid_for(ROWG * m->V)), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p,
                        m->nz_edge.p, m->diag_pos.p, m->star1.p, m->val64.p, m->val32.p);
     HIP_CHECK(hipGetLastError());
     build_sell_pattern(m);

@@ -167,20 +167,34 @@ __global__ void k_neumann_load(int64_t V, const int8_t* __restrict__ bc_type, co
 }
 
 // b for free rows: (-g_v) - sum_k L_vk xd_k (all stored entries, ascending);
-// fixed rows: T0 (Dirichlet) or 0 (pinned).
+// fixed rows: T0 (Dirichlet) or 0 (pinned).  One ROWG-lane group per row
+// loads runs of ROWG entries (coalesced); the products are added in entry
+// order through shuffles, the same sequential sum as a one-thread loop.
+constexpr int ROWG = 16;
+
 __global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                       const double* __restrict__ val, const uint8_t* __restrict__ fixed,
                       const double* __restrict__ dval, const double* __restrict__ g, double* __restrict__ b) {
-    GRID_STRIDE_LOOP(v, V) {
+    const int gl = threadIdx.x & (ROWG - 1);
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / ROWG;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / ROWG; v < V; v += ngroups) {
         const uint8_t f = fixed[v];
         if (f) {
-            b[v] = (f == 1) ? dval[v] : 0.0;
+            if (gl == 0) b[v] = (f == 1) ? dval[v] : 0.0;
             continue;
         }
+        const int32_t r0 = row_ptr[v], n = row_ptr[v + 1] - r0;
         double acc = 0.0;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) acc += val[k] * dval[col[k]];
-        const double base = g ? (0.0 - g[v]) : 0.0;
-        b[v] = base - acc;
+        for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
+            const int32_t k = k0 + gl;
+            const double t = k < n ? val[r0 + k] * dval[col[r0 + k]] : 0.0;
+            const int run = min(ROWG, n - k0);
+            for (int j = 0; j < run; ++j) acc += __shfl(t, j, ROWG);
+        }
+        if (gl == 0) {
+            const double base = g ? (0.0 - g[v]) : 0.0;
+            b[v] = base - acc;
+        }
     }
 }
 
@@ -242,7 +256,7 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
                            m->xyz.p, gload.p);
     }
     m->rhs.alloc(ctx, V);
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->val64.p,
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(ROWG * V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->val64.p,
                        m->fixed.p, m->bc_value.p, f0 ? gload.p : nullptr, m->rhs.p);
     m->invdiag64.alloc(ctx, V);
     m->invdiag32.alloc(ctx, V);

@@ -7,6 +7,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <array>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -44,6 +46,8 @@ struct dec_ctx {
     int num_cus = 256;
     int num_xcds = 8;
     int live_children = 0;  // meshes and servers created on this context and not yet destroyed
+    // SpMV variant (unroll, non-temporal) chosen per (precision, V, slices, stored entries)
+    std::map<std::array<int64_t, 4>, std::pair<int, int>> spmv_tune;
     // small pinned staging area for scalar read-backs
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
@@ -246,16 +250,84 @@ __device__ __forceinline__ T reduce_partials(const T* partials, int n, T* lds) {
     return block_sum(acc, lds);
 }
 
+// Thread t's share of a fixed-order sum of n partials: p[t] + p[t + BLOCK] +
+// ... in that order.  The loads of a batch are issued together, so a block
+// waits for one memory latency per FOLD_BATCH * BLOCK partials, not one per
+// BLOCK (every block of a solver kernel folds the same partials at its start).
+constexpr int FOLD_BATCH = 8;
+
+struct FoldBatch {
+    double v[FOLD_BATCH];
+};
+
+__device__ __forceinline__ FoldBatch fold_load(const double* __restrict__ p, int n, int base) {
+    FoldBatch b;
+#pragma unroll
+    for (int k = 0; k < FOLD_BATCH; ++k) {
+        const int i = base + k * BLOCK + static_cast<int>(threadIdx.x);
+        b.v[k] = i < n ? p[i] : 0.0;
+    }
+    return b;
+}
+
+__device__ __forceinline__ double fold_add(double acc, const FoldBatch& b) {
+#pragma unroll
+    for (int k = 0; k < FOLD_BATCH; ++k) acc += b.v[k];
+    return acc;
+}
+
+__device__ __forceinline__ double thread_fold(const double* __restrict__ p, int n) {
+    double acc = 0.0;
+    for (int base = 0; base < n; base += FOLD_BATCH * BLOCK) acc = fold_add(acc, fold_load(p, n, base));
+    return acc;
+}
+
 // Fixed-order sum of `n` partials written by an earlier kernel, returned to
 // every thread of the block.  lds holds BLOCK/64 + 1 doubles.
 __device__ __forceinline__ double reduce_bcast(const double* __restrict__ partials, int n, double* lds) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
-    const double t = block_sum(acc, lds);
+    const double t = block_sum(thread_fold(partials, n), lds);
     __syncthreads();
     if (threadIdx.x == 0) lds[BLOCK / 64] = t;
     __syncthreads();
     return lds[BLOCK / 64];
+}
+
+// Three fixed-order sums (each as reduce_bcast computes it) with the loads of
+// all three in flight together and one set of barriers.  lds holds
+// 3 * (BLOCK/64 + 1) doubles.
+__device__ __forceinline__ void reduce_bcast3(const double* __restrict__ a, int na, const double* __restrict__ b,
+                                              int nb, const double* __restrict__ c, int nc, double* lds,
+                                              double* ra, double* rb, double* rc) {
+    constexpr int NW = BLOCK / 64;
+    const FoldBatch la = fold_load(a, na, 0), lb = fold_load(b, nb, 0), lc = fold_load(c, nc, 0);
+    double sa = fold_add(0.0, la), sb = fold_add(0.0, lb), sc = fold_add(0.0, lc);
+    for (int base = FOLD_BATCH * BLOCK; base < na; base += FOLD_BATCH * BLOCK) sa = fold_add(sa, fold_load(a, na, base));
+    for (int base = FOLD_BATCH * BLOCK; base < nb; base += FOLD_BATCH * BLOCK) sb = fold_add(sb, fold_load(b, nb, base));
+    for (int base = FOLD_BATCH * BLOCK; base < nc; base += FOLD_BATCH * BLOCK) sc = fold_add(sc, fold_load(c, nc, base));
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    sc = wave_sum(sc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[wid] = sa;
+        lds[NW + wid] = sb;
+        lds[2 * NW + wid] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0, tc = 0;
+        for (int w = 0; w < NW; ++w) ta += lds[w];
+        for (int w = 0; w < NW; ++w) tb += lds[NW + w];
+        for (int w = 0; w < NW; ++w) tc += lds[2 * NW + w];
+        lds[3 * NW] = ta;
+        lds[3 * NW + 1] = tb;
+        lds[3 * NW + 2] = tc;
+    }
+    __syncthreads();
+    *ra = lds[3 * NW];
+    *rb = lds[3 * NW + 1];
+    *rc = lds[3 * NW + 2];
 }
 
 // ---------------------------------------------------------------- host primitives

@@ -5,38 +5,51 @@
 //     Q_in = sum over inflow-face vertices of (L T)_v,
 //     Q_out = -sum over outflow-face vertices of (L T)_v,
 // and the dissipated energy E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at
-// the exact solution; k_eff = E length / (area dT^2).  One pass over the
-// rows, deterministic block partials.
+// the exact solution; k_eff = E length / (area dT^2).  Deterministic block
+// partials.
 #include "solver.h"
 
 namespace {
 
-__global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, const int32_t* __restrict__ row_ptr,
+// Q_in / Q_out from the rows of the two Dirichlet faces only (side != 0);
+// the energy edge by edge (coalesced over the edge arrays).  Partials per
+// block, folded in a fixed order by the last block.
+__global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, int64_t E, const int32_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
-                                                const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
-                                                const double* __restrict__ star1, const double* __restrict__ T,
-                                                const int8_t* __restrict__ side, double* __restrict__ edge_flux,
-                                                double* __restrict__ partials, double* __restrict__ out,
-                                                unsigned* __restrict__ counter) {
+                                                const int32_t* __restrict__ edges, const double* __restrict__ star1,
+                                                const double* __restrict__ T, const int8_t* __restrict__ side,
+                                                double* __restrict__ edge_flux, double* __restrict__ partials,
+                                                double* __restrict__ out, unsigned* __restrict__ counter) {
     __shared__ double lds[BLOCK / 64];
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
     double qin = 0.0, qout = 0.0, en = 0.0;
-    for (int64_t v = i0 + threadIdx.x; v < i1; v += BLOCK) {
-        const double tv = T[v];
-        double o = 0.0;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t e = nz_edge[k];
-            if (e < 0) continue;
-            o += star1[e] * (tv - T[col[k]]);
+    if (side) {
+        int64_t i0, i1;
+        block_range(V, &i0, &i1);
+        for (int64_t v = i0 + threadIdx.x; v < i1; v += BLOCK) {
+            const int8_t sd = side[v];
+            if (sd != 1 && sd != 2) continue;
+            const double tv = T[v];
+            double o = 0.0;
+            for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+                const int32_t e = nz_edge[k];
+                if (e < 0) continue;
+                o += star1[e] * (tv - T[col[k]]);
+            }
+            if (sd == 1) qin += o;
+            if (sd == 2) qout -= o;
         }
-        const int8_t sd = side ? side[v] : 0;
-        if (sd == 1) qin += o;
-        if (sd == 2) qout -= o;
-        for (int64_t e = up_ptr[v]; e < up_ptr[v + 1]; ++e) {
-            const double d = T[edges[2 * e + 1]] - tv;
-            en += star1[e] * d * d;
-            if (edge_flux) edge_flux[e] = star1[e] * (tv - T[edges[2 * e + 1]]);
+    }
+    {
+        int64_t e0, e1;
+        block_range(E, &e0, &e1);
+        const int2* ed = reinterpret_cast<const int2*>(edges);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+            const int2 lh = ed[e];
+            const double s = star1[e];
+            const double tl = T[lh.x], th = T[lh.y];
+            const double d = th - tl;
+            en += s * d * d;
+            if (edge_flux) edge_flux[e] = s * (tl - th);
         }
     }
     const int G = gridDim.x;
@@ -81,8 +94,8 @@ extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, con
         DBuf<unsigned> counter;
         counter.alloc(ctx, 1);
         counter.zero();
-        hipLaunchKernelGGL(k_flux, dim3(G), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p, m->col.p, m->nz_edge.p,
-                           m->up_ptr.p, m->edges.p, m->star1.p, T, side, edge_flux_out, part.p, out.p, counter.p);
+        hipLaunchKernelGGL(k_flux, dim3(G), dim3(BLOCK), 0, ctx->stream, m->V, m->E, m->row_ptr.p, m->col.p,
+                           m->nz_edge.p, m->edges.p, m->star1.p, T, side, edge_flux_out, part.p, out.p, counter.p);
         HIP_CHECK(hipGetLastError());
         double h[3];
         std::memcpy(h, ctx->readback(out.p, sizeof(h)), sizeof(h));

@@ -3,7 +3,9 @@
 // Geometry (once per mesh): every tet computes the signed area of the part
 // of each of its six edges' dual 2-cells that it holds -- the planar
 // quadrilateral (edge midpoint, circumcentre of face 1, tet circumcentre,
-// circumcentre of face 2) in the edge's bisector plane -- then every edge
+// circumcentre of face 2) in the edge's bisector plane, in a closed form
+// (cotangent of the face angles, distance of the tet circumcentre to the
+// face planes) -- then every edge
 // gathers its pieces in ascending tet order (no atomics), snaps near-zero
 // areas (|*e| <= 1e-12 |e|^2) to zero and stores |*e| / |e|.
 //
@@ -40,56 +42,49 @@ __device__ d3 tet_circumcentre(d3 p0, d3 p1, d3 p2, d3 p3) {
     return {p0.x + num.x / den, p0.y + num.y / den, p0.z + num.z / den};
 }
 
-// c_f = p0 + ((|a|^2 b - |b|^2 a) x (a x b)) / (2 |a x b|^2)
-__device__ d3 tri_circumcentre(d3 p0, d3 p1, d3 p2) {
-    const d3 a = sub(p1, p0), b = sub(p2, p0);
-    const d3 axb = cross(a, b);
-    const double sa = dot(a, a), sb = dot(b, b);
-    const d3 w = sub(scale(sa, b), scale(sb, a));
-    const d3 num = cross(w, axb);
-    const double den = 2.0 * dot(axb, axb);
-    return {p0.x + num.x / den, p0.y + num.y / den, p0.z + num.z / den};
-}
-
-// signed in-plane distance from the midpoint of (pi, pj) to cf, positive toward pk
-__device__ double edge_to_face(d3 pi, d3 pj, d3 pk, d3 cf) {
-    const d3 m = {0.5 * (pi.x + pj.x), 0.5 * (pi.y + pj.y), 0.5 * (pi.z + pj.z)};
-    const d3 e = sub(pj, pi), w = sub(pk, pi);
-    const double f = dot(w, e) / dot(e, e);
-    d3 u = sub(w, scale(f, e));
-    const double nu = sqrt(dot(u, u));
-    u = {u.x / nu, u.y / nu, u.z / nu};
-    return dot(sub(cf, m), u);
-}
-
-// signed distance from cf to ct along the normal of (pi, pj, pk), positive toward pl
-__device__ double face_to_tet(d3 pi, d3 pj, d3 pk, d3 pl, d3 cf, d3 ct) {
-    d3 n = cross(sub(pj, pi), sub(pk, pi));
-    const double sgn = dot(n, sub(pl, pi)) < 0.0 ? -1.0 : 1.0;
-    const double f = sgn / sqrt(dot(n, n));
-    n = scale(f, n);
-    return dot(sub(ct, cf), n);
-}
-
-__constant__ int kEdgeI[6] = {0, 0, 0, 1, 1, 2};
-__constant__ int kEdgeJ[6] = {1, 2, 3, 2, 3, 3};
-__constant__ int kEdgeK[6] = {2, 1, 1, 0, 0, 0};
-__constant__ int kEdgeL[6] = {3, 3, 2, 3, 2, 1};
-
+// Signed elementary dual area of edge (i, j) inside a tet with other vertices
+// k, l: the quad (edge midpoint, circumcentre of face ijk, tet circumcentre,
+// circumcentre of face ijl) in the edge's bisector plane has area
+//     A = 1/2 [ h(e -> f_ijk) h(f_ijk -> T) + h(e -> f_ijl) h(f_ijl -> T) ],
+// with h(e -> f) the in-plane signed distance from the edge midpoint to the
+// face circumcentre (positive toward the face's third vertex) and h(f -> T)
+// the signed distance from the face to the tet circumcentre along the face
+// normal (positive toward the opposite vertex).  Evaluated as:
+//  * h(e -> f_ijk) = |e|/2 cot(angle at k) = |e|/2 (p_i - p_k).(p_j - p_k) / |n_f|,
+//    |n_f| = twice the face area (the circumcentre sits |e|/2 cot from the
+//    edge midpoint on its perpendicular bisector);
+//  * h(f -> T) = sgn (c_T - p_a).n_f / |n_f| for any face vertex p_a (the face
+//    circumcentre lies in the face plane, so only the tet circumcentre's
+//    distance to that plane enters);
+// so A = |e|/4 [ dot_k H_l + dot_l H_k ] with H_f = sgn (c_T - p_a).n_f / |n_f|^2
+// for the face opposite vertex f.  Seven divisions and six square roots per
+// tet.
 __global__ void k_elementary_areas(int64_t T, const int32_t* __restrict__ tets, const double* __restrict__ xyz,
                                    double* __restrict__ elem) {
+    constexpr int FA[4] = {1, 0, 0, 0}, FB[4] = {2, 2, 1, 1}, FC[4] = {3, 3, 3, 2};  // face opposite vertex f
+    constexpr int EI[6] = {0, 0, 0, 1, 1, 2}, EJ[6] = {1, 2, 3, 2, 3, 3};
+    constexpr int EK[6] = {2, 1, 1, 0, 0, 0}, EL[6] = {3, 3, 2, 3, 2, 1};
     GRID_STRIDE_LOOP(t, T) {
         const int4 q = reinterpret_cast<const int4*>(tets)[t];
-        d3 p[4] = {load3(xyz + 3 * (int64_t)q.x), load3(xyz + 3 * (int64_t)q.y), load3(xyz + 3 * (int64_t)q.z),
-                   load3(xyz + 3 * (int64_t)q.w)};
+        const d3 p[4] = {load3(xyz + 3 * (int64_t)q.x), load3(xyz + 3 * (int64_t)q.y),
+                         load3(xyz + 3 * (int64_t)q.z), load3(xyz + 3 * (int64_t)q.w)};
         const d3 ct = tet_circumcentre(p[0], p[1], p[2], p[3]);
+        double H[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const d3 pa = p[FA[f]];
+            const d3 n = cross(sub(p[FB[f]], pa), sub(p[FC[f]], pa));
+            const double sgn = dot(n, sub(p[f], pa)) < 0.0 ? -1.0 : 1.0;
+            H[f] = sgn * dot(sub(ct, pa), n) / dot(n, n);
+        }
+#pragma unroll
         for (int e = 0; e < 6; ++e) {
-            const d3 pi = p[kEdgeI[e]], pj = p[kEdgeJ[e]], pk = p[kEdgeK[e]], pl = p[kEdgeL[e]];
-            const d3 cf1 = tri_circumcentre(pi, pj, pk);
-            const d3 cf2 = tri_circumcentre(pi, pj, pl);
-            const double t1 = edge_to_face(pi, pj, pk, cf1) * face_to_tet(pi, pj, pk, pl, cf1, ct);
-            const double t2 = edge_to_face(pi, pj, pl, cf2) * face_to_tet(pi, pj, pl, pk, cf2, ct);
-            elem[6 * t + e] = 0.5 * (t1 + t2);
+            const d3 pi = p[EI[e]], pj = p[EJ[e]], pk = p[EK[e]], pl = p[EL[e]];
+            const d3 d = sub(pj, pi);
+            const double le = sqrt(dot(d, d));
+            const double dk = dot(sub(pi, pk), sub(pj, pk));
+            const double dl = dot(sub(pi, pl), sub(pj, pl));
+            elem[6 * t + e] = 0.25 * le * (dk * H[EL[e]] + dl * H[EK[e]]);
         }
     }
 }
@@ -156,10 +151,12 @@ struct Bins {
     double inv[3];  // cells per unit length
 };
 
+// cell index along one axis, clamped to [0, kBins); NaN maps to 0
 __device__ __forceinline__ int bin_of(double x, double lo, double inv) {
     const double t = (x - lo) * inv;
-    int b = t <= 0.0 ? 0 : (t >= (double)(kBins - 1) ? kBins - 1 : (int)t);
-    return b;
+    if (!(t > 0.0)) return 0;
+    if (!(t < (double)(kBins - 1))) return kBins - 1;
+    return (int)t;
 }
 
 // per-block partial extents: [block][7] = min xyz, max xyz, longest half edge
@@ -192,13 +189,24 @@ __global__ void k_geom_extent(int64_t V, const double* __restrict__ xyz, int64_t
     }
 }
 
-__global__ void k_geom_extent_fold(int nblocks, const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x < 7) {
-        double r = part[threadIdx.x];
-        for (int b = 1; b < nblocks; ++b)
-            r = threadIdx.x < 3 ? fmin(r, part[7 * b + threadIdx.x]) : fmax(r, part[7 * b + threadIdx.x]);
-        out[threadIdx.x] = r;
+// min / max are exact, so the fold order does not matter
+__global__ __launch_bounds__(BLOCK) void k_geom_extent_fold(int nblocks, const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+    __shared__ double red[7][BLOCK];
+    double r[7];
+    for (int a = 0; a < 7; ++a) r[a] = a < 3 ? INFINITY : -INFINITY;
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK)
+        for (int a = 0; a < 7; ++a) r[a] = a < 3 ? fmin(r[a], part[7 * b + a]) : fmax(r[a], part[7 * b + a]);
+    for (int a = 0; a < 7; ++a) red[a][threadIdx.x] = r[a];
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 7; ++a)
+                red[a][threadIdx.x] = a < 3 ? fmin(red[a][threadIdx.x], red[a][threadIdx.x + w])
+                                            : fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+        __syncthreads();
     }
+    if (threadIdx.x < 7) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 __device__ __forceinline__ void disc_cells(const double* d, double reach, const Bins& B, int lo[3], int hi[3]) {
@@ -209,27 +217,32 @@ __device__ __forceinline__ void disc_cells(const double* d, double reach, const 
     }
 }
 
+// One block per disc (grid-stride over discs), its threads over the disc's
+// cells.  Counts are order-free; the order inside a cell's list is not
+// fixed, which the cut (an "any disc" test) does not see.
 __global__ void k_bin_count(int32_t n, const double* __restrict__ discs, double reach, Bins B, int32_t* __restrict__ cnt) {
-    GRID_STRIDE_LOOP(i, n) {
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         int lo[3], hi[3];
-        disc_cells(discs + 7 * i, reach, B, lo, hi);
-        for (int x = lo[0]; x <= hi[0]; ++x)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int z = lo[2]; z <= hi[2]; ++z) atomicAdd(&cnt[(x * kBins + y) * kBins + z], 1);
+        disc_cells(discs + 7 * (int64_t)i, reach, B, lo, hi);
+        const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+        for (int k = threadIdx.x; k < nx * ny * nz; k += blockDim.x) {
+            const int x = lo[0] + k / (ny * nz), y = lo[1] + (k / nz) % ny, z = lo[2] + k % nz;
+            atomicAdd(&cnt[(x * kBins + y) * kBins + z], 1);
+        }
     }
 }
 
 __global__ void k_bin_fill(int32_t n, const double* __restrict__ discs, double reach, Bins B,
                            const int64_t* __restrict__ off, int32_t* __restrict__ fill, int32_t* __restrict__ list) {
-    GRID_STRIDE_LOOP(i, n) {
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
         int lo[3], hi[3];
-        disc_cells(discs + 7 * i, reach, B, lo, hi);
-        for (int x = lo[0]; x <= hi[0]; ++x)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int z = lo[2]; z <= hi[2]; ++z) {
-                    const int c = (x * kBins + y) * kBins + z;
-                    list[off[c] + atomicAdd(&fill[c], 1)] = (int32_t)i;
-                }
+        disc_cells(discs + 7 * (int64_t)i, reach, B, lo, hi);
+        const int nx = hi[0] - lo[0] + 1, ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+        for (int k = threadIdx.x; k < nx * ny * nz; k += blockDim.x) {
+            const int x = lo[0] + k / (ny * nz), y = lo[1] + (k / nz) % ny, z = lo[2] + k % nz;
+            const int c = (x * kBins + y) * kBins + z;
+            list[off[c] + atomicAdd(&fill[c], 1)] = i;
+        }
     }
 }
 
@@ -277,7 +290,7 @@ void ensure_geometry(dec_mesh* m) {
     ext.alloc(ctx, 7);
     part.alloc(ctx, 7 * (int64_t)nb);
     hipLaunchKernelGGL(k_geom_extent, dim3(nb), dim3(BLOCK), 0, ctx->stream, m->V, m->xyz.p, m->E, m->edges.p, part.p);
-    hipLaunchKernelGGL(k_geom_extent_fold, dim3(1), dim3(64), 0, ctx->stream, nb, part.p, ext.p);
+    hipLaunchKernelGGL(k_geom_extent_fold, dim3(1), dim3(BLOCK), 0, ctx->stream, nb, part.p, ext.p);
     std::memcpy(m->extent, ctx->readback(ext.p, 7 * sizeof(double)), sizeof(m->extent));
     DBuf<double> elem;
     elem.alloc(ctx, 6 * m->T);
@@ -317,14 +330,14 @@ void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const dou
         DBuf<int64_t> off;
         cnt.alloc(ctx, ncell);
         cnt.zero();
-        hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n_cracks)), dim3(BLOCK), 0, ctx->stream, n_cracks, cracks, reach,
-                           B, cnt.p);
+        const dim3 disc_grid(n_cracks < 65536 ? n_cracks : 65536);
+        hipLaunchKernelGGL(k_bin_count, disc_grid, dim3(64), 0, ctx->stream, n_cracks, cracks, reach, B, cnt.p);
         off.alloc(ctx, ncell + 1);
         const int64_t total = scan_exclusive_i32_to_i64(ctx, cnt.p, off.p, ncell, true);
         list.alloc(ctx, total > 0 ? total : 1);
         cnt.zero();
-        hipLaunchKernelGGL(k_bin_fill, dim3(grid_for(n_cracks)), dim3(BLOCK), 0, ctx->stream, n_cracks, cracks, reach,
-                           B, off.p, cnt.p, list.p);
+        hipLaunchKernelGGL(k_bin_fill, disc_grid, dim3(64), 0, ctx->stream, n_cracks, cracks, reach, B, off.p, cnt.p,
+                           list.p);
         hipLaunchKernelGGL(k_crack_cut_binned, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
                            m->xyz.p, cracks, B, off.p, list.p, m->cut.p);
         HIP_CHECK(hipGetLastError());

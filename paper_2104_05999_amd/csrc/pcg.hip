@@ -23,6 +23,7 @@
 namespace {
 
 enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
+constexpr int PREFETCH = 4;  // rows per thread loaded ahead of a kernel's opening fold
 // regions of the partials array, G doubles each
 enum { R_PQ = 0, R_RR = 1, R_RZ = 2 };
 enum { FIN_NORM2 = 0, FIN_RR = 1, FIN_START = 2 };
@@ -151,13 +152,39 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
                                                   int P, int n_pq, const PcgScalars* __restrict__ S) {
     __shared__ double lds[BLOCK / 64 + 1];
     if (S->done) return;
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    // the first PREFETCH rows of each thread are loaded before the fold, so
+    // the fold's latency overlaps with their transfer
+    VT fx[PREFETCH], fp[PREFETCH], fr[PREFETCH], fq[PREFETCH], fd[PREFETCH];
+#pragma unroll
+    for (int k = 0; k < PREFETCH; ++k) {
+        const int64_t i = i0 + threadIdx.x + k * BLOCK;
+        if (i < i1) {
+            fx[k] = x[i];
+            fp[k] = p[i];
+            fr[k] = r[i];
+            fq[k] = q[i];
+            fd[k] = JACOBI ? invd[i] : VT(0);
+        }
+    }
     const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
     if (!(pq > 0.0) || !isfinite(pq)) return;
     const VT a = static_cast<VT>(S->rho / pq);
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
     VT rz = 0, rr = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+#pragma unroll
+    for (int k = 0; k < PREFETCH; ++k) {
+        const int64_t i = i0 + threadIdx.x + k * BLOCK;
+        if (i < i1) {
+            const VT xi = fx[k] + a * fp[k];
+            const VT ri = fr[k] - a * fq[k];
+            x[i] = xi;
+            r[i] = ri;
+            if (JACOBI) rz += ri * (fd[k] * ri);
+            rr += ri * ri;
+        }
+    }
+    for (int64_t i = i0 + threadIdx.x + PREFETCH * BLOCK; i < i1; i += BLOCK) {
         const VT xi = x[i] + a * p[i];
         const VT ri = r[i] - a * q[i];
         x[i] = xi;
@@ -210,16 +237,26 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
                                                  const VT* __restrict__ z, VT* __restrict__ p,
                                                  const double* __restrict__ partials, int P, int n_pq,
                                                  const PcgScalars* __restrict__ S, PcgScalars* __restrict__ N) {
-    __shared__ double lds[BLOCK / 64 + 1];
+    __shared__ double lds[3 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (S->done) {
         if (lead) *N = *S;
         return;
     }
     const int G = gridDim.x;
-    const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
-    const double rr = reduce_bcast(partials + R_RR * P, G, lds);
-    const double rz = reduce_bcast(partials + R_RZ * P, G, lds);
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    VT fz[PREFETCH], fp[PREFETCH];  // z (or D^-1 r) and p of the first rows, loaded before the fold
+#pragma unroll
+    for (int k = 0; k < PREFETCH; ++k) {
+        const int64_t i = i0 + threadIdx.x + k * BLOCK;
+        if (i < i1) {
+            fz[k] = JACOBI ? invd[i] * r[i] : z[i];
+            fp[k] = p[i];
+        }
+    }
+    double pq, rr, rz;
+    reduce_bcast3(partials + R_PQ * P, n_pq, partials + R_RR * P, G, partials + R_RZ * P, G, lds, &pq, &rr, &rz);
     int done = PCG_RUNNING;
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
         done = PCG_BREAKDOWN;
@@ -230,9 +267,12 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
     const double beta = rz / S->rho;
     if (done == PCG_RUNNING) {
         const VT bt = static_cast<VT>(beta);
-        int64_t i0, i1;
-        block_range(V, &i0, &i1);
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK)
+#pragma unroll
+        for (int k = 0; k < PREFETCH; ++k) {
+            const int64_t i = i0 + threadIdx.x + k * BLOCK;
+            if (i < i1) p[i] = fz[k] + bt * fp[k];
+        }
+        for (int64_t i = i0 + threadIdx.x + PREFETCH * BLOCK; i < i1; i += BLOCK)
             p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * p[i];
     }
     if (lead) {
@@ -334,9 +374,17 @@ void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const
 // timing y = A x on this matrix.  All variants sum every row in the same
 // order, so the choice never changes a result.
 template <class VT>
-void autotune_spmv(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y) {
+void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const VT* x, VT* y) {
     const int pi = prec_index<VT>();
     if (c->tuned[pi] || c->pinned_variant) return;
+    const std::array<int64_t, 4> shape{pi, A.V, A.nslices, entries};
+    auto known = c->ctx->spmv_tune.find(shape);
+    if (known != c->ctx->spmv_tune.end()) {  // a matrix of this shape was timed before on this context
+        c->unroll[pi] = known->second.first;
+        c->nt[pi] = known->second.second;
+        c->tuned[pi] = true;
+        return;
+    }
     const int cand[4][2] = {{8, 1}, {8, 0}, {4, 1}, {4, 0}};
     float best = 1e30f;
     int pick = 0;
@@ -358,6 +406,7 @@ void autotune_spmv(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y) {
     c->unroll[pi] = cand[pick][0];
     c->nt[pi] = cand[pick][1];
     c->tuned[pi] = true;
+    c->ctx->spmv_tune[shape] = {c->unroll[pi], c->nt[pi]};
 }
 
 int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
@@ -435,16 +484,22 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
         // every batch must advance the iteration count until the state says done
         DEC_REQUIRE(batch <= o.max_iters / chunk + 4, DEC_EHIP, "PCG batches exceed the iteration cap");
         if (o.profile) {
+            // SpMV k of the batch carries events when k is a multiple of the sampling stride
+            const int every = o.profile;
             while ((int)c->events.size() < 2 * chunk) {
                 hipEvent_t e;
                 HIP_CHECK(hipEventCreate(&e));
                 c->events.push_back(e);
             }
-            const PcgScalars before = read_state(c, R.st);
-            for (int k = 0; k < chunk; ++k) enqueue_iteration(c, R, k & 1, c->events[2 * k], c->events[2 * k + 1]);
+            if (batch == 0) last_iter = read_state(c, R.st).iter;
+            for (int k = 0; k < chunk; ++k) {
+                const bool timed = k % every == 0;
+                enqueue_iteration(c, R, k & 1, timed ? c->events[2 * k] : nullptr,
+                                  timed ? c->events[2 * k + 1] : nullptr);
+            }
             const PcgScalars after = read_state(c, R.st);
-            const int64_t ran = after.iter - before.iter;
-            for (int64_t k = 0; k < ran && k < chunk; ++k) {
+            const int64_t ran = after.iter - last_iter;  // SpMVs 0 .. ran-1 did work; later ones returned at once
+            for (int64_t k = 0; k < ran && k < chunk; k += every) {
                 float ms = 0.0f;
                 HIP_CHECK(hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
                 if (stats) {
@@ -453,7 +508,7 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
                 }
             }
             if (after.done) return after;
-            DEC_REQUIRE(after.iter > last_iter, DEC_EHIP, "PCG made no progress in a batch");
+            DEC_REQUIRE(ran > 0, DEC_EHIP, "PCG made no progress in a batch");
             last_iter = after.iter;
             continue;
         }
@@ -706,6 +761,7 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         DEC_REQUIRE(o.precond == DEC_PRECOND_JACOBI || o.precond == DEC_PRECOND_FSAI, DEC_EINVAL, "bad precond");
         DEC_REQUIRE(o.tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0, DEC_EINVAL, "bad tolerance");
         DEC_REQUIRE(o.max_iters > 0 && o.chunk >= 0 && o.chunk <= 4096, DEC_EINVAL, "bad iteration limits");
+        DEC_REQUIRE(o.profile >= 0, DEC_EINVAL, "profile is a sampling stride, 0 for off");
         ctx->set_device();
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
@@ -717,11 +773,12 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
         ensure_vectors(m, c, o.precision);
         ctx->sync();  // inputs written on the caller's stream are complete
-        autotune_spmv<double>(c, sell64(m), c->p64.p, c->q64.p);
+        autotune_spmv<double>(c, sell64(m), m->sell.entries, c->p64.p, c->q64.p);
         if (o.precision == DEC_PREC_MIXED)
-            autotune_spmv<float>(c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices,
-                                                    m->V},
-                                 c->p32.p, c->q32.p);
+            autotune_spmv<float>(c,
+                                 SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices,
+                                                 m->V},
+                                 m->sell.entries, c->p32.p, c->q32.p);
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
                            m->bc_value.p, o.warm_start ? T : nullptr, c->x64.p);

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slo
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                   const int32_t* __restrict__ n_items, int par) {
-    __shared__ double lds[BLOCK / 64 + 1];
+    __shared__ double lds[3 * (BLOCK / 64 + 1)];
     const int n = *n_items;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const BItem item = items[it];
@@ -172,9 +172,8 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
             continue;
         }
         const int nc = S.nchunks;
-        const double pq = reduce_bcast(S.part + Q_PQ * nc, nc, lds);
-        const double rr = reduce_bcast(S.part + Q_RR * nc, nc, lds);
-        const double rz = reduce_bcast(S.part + Q_RZ * nc, nc, lds);
+        double pq, rr, rz;
+        reduce_bcast3(S.part + Q_PQ * nc, nc, S.part + Q_RR * nc, nc, S.part + Q_RZ * nc, nc, lds, &pq, &rr, &rz);
         int done = PCG_RUNNING;
         if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
             done = PCG_BREAKDOWN;

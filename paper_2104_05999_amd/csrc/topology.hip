@@ -64,19 +64,22 @@ __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const in
     }
 }
 
-// Sort each vertex's tet list (ascending tet id).  One wavefront per vertex:
-// a list of at most 64 distinct ids is ranked in registers (rank = number of
-// smaller ids) and written back; longer lists are insertion-sorted by lane 0.
+// Sort each vertex's tet list (ascending tet id).  One 32-lane group per
+// vertex: a list of at most 32 distinct ids is ranked in registers (rank =
+// number of smaller ids) and written back; longer lists are insertion-sorted
+// by the group's first lane.
 __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < V; v += nwaves) {
+    constexpr int W = 32;
+    const int lane = threadIdx.x & (W - 1);
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / W;
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / W; v < V; v += ngroups) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
-        if (d <= 64) {
+        if (d <= W) {
             const int key = lane < d ? vt_list[b + lane] : INT_MAX;
             int rank = 0;
-            for (int k = 0; k < 64; ++k) rank += __shfl(key, k, 64) < key;
+#pragma unroll
+            for (int k = 0; k < W; ++k) rank += __shfl(key, k, W) < key;
             if (lane < d) vt_list[b + rank] = key;
         } else if (lane == 0) {
             for (int64_t i = b + 1; i < b + d; ++i) {
@@ -276,31 +279,35 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
     }
 }
 
-// Faces: face k of tet t is opposite local vertex k.  The tets holding it
-// are the tets of one of its edges (ascending tet order) that also hold its
-// third vertex; the first such tet owns the face.
-__global__ void k_faces(int64_t T, const int4* __restrict__ tets, const int32_t* __restrict__ tet_edge,
-                        const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
-                        uint8_t* __restrict__ bface, unsigned long long* __restrict__ counts,
-                        unsigned* __restrict__ err) {
+// Faces: face k of tet t is opposite local vertex k.  The tets holding face
+// (a, b, c) are those holding both edges (a, b) and (a, c): the intersection
+// of two incidence lists, both in ascending tet order (a merge over ~10
+// contiguous integers).  The first such tet owns the face.
+__global__ void k_faces(int64_t T, const int32_t* __restrict__ tet_edge, const int64_t* __restrict__ et_ptr,
+                        const int32_t* __restrict__ et_inc, uint8_t* __restrict__ bface,
+                        unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
     __shared__ unsigned long long lds[BLOCK / 64];
     unsigned long long owned = 0, bnd = 0;
     GRID_STRIDE_LOOP(t, T) {
-        const int4 q = tets[t];
         uint8_t mask = 0;
         for (int k = 0; k < 4; ++k) {
-            // the face's vertices are the local vertices other than k; use the edge of the
-            // first two and look for the third
             const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
-            const int e = tet_edge[6 * t + local_edge(la, lb)];
-            const int c = vget(q, lc);
+            const int e1 = tet_edge[6 * t + local_edge(la, lb)];
+            const int e2 = tet_edge[6 * t + local_edge(la, lc)];
+            int64_t i = et_ptr[e1], j = et_ptr[e2];
+            const int64_t i1 = et_ptr[e1 + 1], j1 = et_ptr[e2 + 1];
             int cnt = 0, first = -1;
-            for (int64_t j = et_ptr[e]; j < et_ptr[e + 1]; ++j) {
-                const int u = et_inc[j] / 6;
-                const int4 o = tets[u];
-                if (o.x == c || o.y == c || o.z == c || o.w == c) {
+            while (i < i1 && j < j1) {
+                const int u = et_inc[i] / 6, w = et_inc[j] / 6;
+                if (u == w) {
                     if (first < 0) first = u;
                     ++cnt;
+                    ++i;
+                    ++j;
+                } else if (u < w) {
+                    ++i;
+                } else {
+                    ++j;
                 }
             }
             if (cnt > 2) atomicOr(err, 16u);
@@ -361,7 +368,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     cnt.zero();
     hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, m->vt_ptr.p, cnt.p,
                        m->vt_list.p);
-    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(64 * V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
+    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(32 * V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
     HIP_CHECK(hipGetLastError());
 
     // neighbours: counts, then edges, incidences and the CSR pattern (one 32-lane group per vertex)
@@ -409,7 +416,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     DBuf<unsigned long long> fc;
     fc.alloc(ctx, 2);
     fc.zero();
-    hipLaunchKernelGGL(k_faces, dim3(grid_for(T, BLOCK, 8192)), dim3(BLOCK), 0, s, T, tq, tet_edge.p, m->et_ptr.p,
+    hipLaunchKernelGGL(k_faces, dim3(grid_for(T, BLOCK, 8192)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
                        m->et_inc.p, m->tet_bface.p, fc.p, err.p);
     HIP_CHECK(hipGetLastError());
     unsigned long long hc[2];

@@ -77,6 +77,39 @@ def test_topology_bit_exact(ctx, dev, n):
     assert np.array_equal(col.cpu().numpy(), L.indices)
 
 
+def _double_cone(k, seed):
+    """Centre, two apexes and a ring of k vertices: the centre lies in 2k tets and the
+    centre-apex edges in k each (beyond one 32-lane group); tets in seeded random order."""
+    th = 2 * np.pi * np.arange(k) / k
+    xyz = np.concatenate([[[0.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, -1.0]],
+                          np.stack([np.cos(th), np.sin(th), np.zeros(k)], axis=1)])
+    ring = 3 + np.arange(k)
+    nxt = 3 + (np.arange(k) + 1) % k
+    tets = np.concatenate([np.stack([np.zeros(k, int), np.full(k, 1), ring, nxt], axis=1),
+                           np.stack([np.zeros(k, int), np.full(k, 2), ring, nxt], axis=1)])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tets = tets[rng.permutation(len(tets))]
+    tets = np.take_along_axis(tets, rng.permuted(np.tile(np.arange(4), (len(tets), 1)), axis=1), axis=1)
+    return xyz, tets.astype(np.int32)
+
+
+@pytest.mark.parametrize("k", [12, 20, 40])
+def test_topology_high_degree_vertices(ctx, dev, k):
+    xyz, tets = _double_cone(k, k)
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    E = O.edges_of(tets, len(xyz))
+    F, count = O.faces_of(tets)
+    assert (m.E, m.F, m.F_boundary) == (len(E), len(F), int((count == 1).sum()))
+    assert np.array_equal(m.edges().cpu().numpy(), E)
+    L, _ = O.assemble(len(xyz), E, np.ones(len(E)))
+    rp, col, _, _ = m.csr(values=False)
+    assert np.array_equal(rp.cpu().numpy(), L.indptr) and np.array_equal(col.cpu().numpy(), L.indices)
+    _, star = m.hodge1()
+    ref = O.hodge1(xyz, tets, E)
+    assert np.allclose(star.cpu().numpy(), ref, rtol=1e-13, atol=1e-15)
+    m.close()
+
+
 def test_topology_independent_of_tet_order(ctx, dev):
     xyz, tets = _shuffled_mesh(4, 3)
     m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
@@ -297,6 +330,14 @@ def test_profiled_solve_counts_spmv(ctx, dev):
     m, _, _, _, _ = _gpu(ctx, s, dev)
     T, st, rc = m.solve(tol=1e-10, profile=1)
     assert rc == 0 and st["spmv_launches"] == st["iterations"] and st["spmv_ms"] > 0
+    T4, st4, rc4 = m.solve(tol=1e-10, profile=4)  # SpMV k of each 32-iteration batch timed when 4 | k
+    n = st4["iterations"]
+    assert rc4 == 0 and n == st["iterations"] and torch.equal(T4, T)
+    if st4["restarts"] == 0:  # one run of batches from iteration 0
+        assert st4["spmv_launches"] == 8 * (n // 32) + (n % 32 + 3) // 4
+    assert 0 < st4["spmv_launches"] <= n
+    T0, st0, _ = m.solve(tol=1e-10)
+    assert torch.equal(T0, T) and st0["spmv_launches"] == 0
 
 
 def test_pruned_pattern_products_are_bit_identical(ctx, dev):
