@@ -292,6 +292,37 @@ __device__ __forceinline__ double reduce_bcast(const double* __restrict__ partia
     return lds[BLOCK / 64];
 }
 
+// Two fixed-order sums (each as reduce_bcast computes it) with the loads of
+// both in flight together and one set of barriers.  lds holds
+// 2 * (BLOCK/64 + 1) doubles.
+__device__ __forceinline__ void reduce_bcast2(const double* __restrict__ a, int na, const double* __restrict__ b,
+                                              int nb, double* lds, double* ra, double* rb) {
+    constexpr int NW = BLOCK / 64;
+    const FoldBatch la = fold_load(a, na, 0), lb = fold_load(b, nb, 0);
+    double sa = fold_add(0.0, la), sb = fold_add(0.0, lb);
+    for (int base = FOLD_BATCH * BLOCK; base < na; base += FOLD_BATCH * BLOCK) sa = fold_add(sa, fold_load(a, na, base));
+    for (int base = FOLD_BATCH * BLOCK; base < nb; base += FOLD_BATCH * BLOCK) sb = fold_add(sb, fold_load(b, nb, base));
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[wid] = sa;
+        lds[NW + wid] = sb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0;
+        for (int w = 0; w < NW; ++w) ta += lds[w];
+        for (int w = 0; w < NW; ++w) tb += lds[NW + w];
+        lds[2 * NW] = ta;
+        lds[2 * NW + 1] = tb;
+    }
+    __syncthreads();
+    *ra = lds[2 * NW];
+    *rb = lds[2 * NW + 1];
+}
+
 // Three fixed-order sums (each as reduce_bcast computes it) with the loads of
 // all three in flight together and one set of barriers.  lds holds
 // 3 * (BLOCK/64 + 1) doubles.

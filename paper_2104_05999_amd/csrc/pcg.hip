@@ -23,7 +23,8 @@
 namespace {
 
 enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
-constexpr int PREFETCH = 4;  // rows per thread loaded ahead of a kernel's opening fold
+constexpr int PREFETCH = 4;        // rows per thread the update kernel loads ahead of its opening fold
+constexpr int CLOSE_PREFETCH = 8;  // the same for the closing kernel (two vectors per row)
 // regions of the partials array, G doubles each
 enum { R_PQ = 0, R_RR = 1, R_RZ = 2 };
 enum { FIN_NORM2 = 0, FIN_RR = 1, FIN_START = 2 };
@@ -149,7 +150,7 @@ template <class VT, bool JACOBI>
 __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
                                                   const VT* __restrict__ p, const VT* __restrict__ q,
                                                   const VT* __restrict__ invd, double* __restrict__ partials,
-                                                  int P, int n_pq, const PcgScalars* __restrict__ S) {
+                                                  int P, int n_pq, PcgScalars* __restrict__ S) {
     __shared__ double lds[BLOCK / 64 + 1];
     if (S->done) return;
     int64_t i0, i1;
@@ -169,6 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
         }
     }
     const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) S->pq_now = pq;  // for the closing kernel (no other reader here)
     if (!(pq > 0.0) || !isfinite(pq)) return;
     const VT a = static_cast<VT>(S->rho / pq);
     VT rz = 0, rr = 0;
@@ -229,15 +231,16 @@ __global__ __launch_bounds__(BLOCK) void k_fsai_gt(CsrView<VT> GT, const VT* __r
     if (threadIdx.x == 0) partials[R_RZ * P + blockIdx.x] = bs;
 }
 
-// Close the iteration: fold p.q, r.r, r.z; decide breakdown / convergence /
+// Close the iteration: p.q as the update kernel folded it, fold r.r and r.z;
+// decide breakdown / convergence /
 // iteration cap; p = z + beta p (z = D^-1 r for Jacobi); block 0 writes the
 // next state N.  A finished state is carried forward unchanged.
 template <class VT, bool JACOBI>
 __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
                                                  const VT* __restrict__ z, VT* __restrict__ p,
-                                                 const double* __restrict__ partials, int P, int n_pq,
+                                                 const double* __restrict__ partials, int P,
                                                  const PcgScalars* __restrict__ S, PcgScalars* __restrict__ N) {
-    __shared__ double lds[3 * (BLOCK / 64 + 1)];
+    __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (S->done) {
         if (lead) *N = *S;
@@ -246,17 +249,18 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
     const int G = gridDim.x;
     int64_t i0, i1;
     block_range(V, &i0, &i1);
-    VT fz[PREFETCH], fp[PREFETCH];  // z (or D^-1 r) and p of the first rows, loaded before the fold
+    VT fz[CLOSE_PREFETCH], fp[CLOSE_PREFETCH];  // z (or D^-1 r) and p of the first rows, loaded before the fold
 #pragma unroll
-    for (int k = 0; k < PREFETCH; ++k) {
+    for (int k = 0; k < CLOSE_PREFETCH; ++k) {
         const int64_t i = i0 + threadIdx.x + k * BLOCK;
         if (i < i1) {
             fz[k] = JACOBI ? invd[i] * r[i] : z[i];
             fp[k] = p[i];
         }
     }
-    double pq, rr, rz;
-    reduce_bcast3(partials + R_PQ * P, n_pq, partials + R_RR * P, G, partials + R_RZ * P, G, lds, &pq, &rr, &rz);
+    const double pq = S->pq_now;
+    double rr, rz;
+    reduce_bcast2(partials + R_RR * P, G, partials + R_RZ * P, G, lds, &rr, &rz);
     int done = PCG_RUNNING;
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
         done = PCG_BREAKDOWN;
@@ -268,11 +272,11 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
     if (done == PCG_RUNNING) {
         const VT bt = static_cast<VT>(beta);
 #pragma unroll
-        for (int k = 0; k < PREFETCH; ++k) {
+        for (int k = 0; k < CLOSE_PREFETCH; ++k) {
             const int64_t i = i0 + threadIdx.x + k * BLOCK;
             if (i < i1) p[i] = fz[k] + bt * fp[k];
         }
-        for (int64_t i = i0 + threadIdx.x + PREFETCH * BLOCK; i < i1; i += BLOCK)
+        for (int64_t i = i0 + threadIdx.x + CLOSE_PREFETCH * BLOCK; i < i1; i += BLOCK)
             p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * p[i];
     }
     if (lead) {
@@ -431,7 +435,7 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
         hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
                            part, P, n_pq, S);
         hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, (const VT*)nullptr,
-                           R.p, part, P, n_pq, S, N);
+                           R.p, part, P, S, N);
     } else {
         hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
                            (const VT*)nullptr, part, P, n_pq, S);
@@ -439,7 +443,7 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
         hipLaunchKernelGGL((k_fsai_gt<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r, part, P,
                            S);
         hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, (const VT*)nullptr, R.z,
-                           R.p, part, P, n_pq, S, N);
+                           R.p, part, P, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }

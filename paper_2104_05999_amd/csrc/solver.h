@@ -17,7 +17,8 @@ struct PcgScalars {
     double rr;       // r.r of the current iterate
     double rr_stop;  // converged when rr <= rr_stop
     double aux;      // b.b (FP64 solves) or the last reduction result
-    double alpha, beta, pq, pad0;
+    double alpha, beta, pq;
+    double pq_now;   // p.q of the iteration in progress, folded by the update kernel
     int64_t iter;
     int64_t max_iter;
     int32_t done;    // PCG_RUNNING / PCG_CONVERGED / PCG_MAXITER / PCG_BREAKDOWN
