@@ -20,8 +20,9 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
                                   const int32_t* __restrict__ diag_pos, const double* __restrict__ star1,
                                   double* __restrict__ val64, float* __restrict__ val32) {
     const int g = threadIdx.x & (ROWG - 1);
-    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / ROWG;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / ROWG; v < V; v += ngroups) {
+    int64_t v0, v1;
+    block_range(V, &v0, &v1);
+    for (int64_t v = v0 + threadIdx.x / ROWG; v < v1; v += blockDim.x / ROWG) {
         const int32_t b = row_ptr[v], n = row_ptr[v + 1] - b;
         double sum = 0.0;
         for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
@@ -57,8 +58,8 @@ __device__ __forceinline__ bool kept(int32_t k, const int32_t* __restrict__ nz_e
     return e < 0 || geo == nullptr || geo[e] != 0.0;
 }
 
-// Stored entries per slice: each thread counts its row's kept entries and the
-// wavefront -- the slice's 64 rows -- takes the maximum.  Also the number of
+// Stored entries per slice: one wavefront per slice, each lane counts its
+// row's kept entries and the wavefront takes the maximum.  Also the number of
 // kept entries, per block.
 __global__ __launch_bounds__(BLOCK) void k_sell_width(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ nz_edge,
@@ -66,16 +67,20 @@ __global__ __launch_bounds__(BLOCK) void k_sell_width(int64_t V, int64_t nslices
                                                       unsigned long long* __restrict__ kept_count) {
     static_assert(SELL_C == 64, "one slice per wavefront");
     __shared__ unsigned long long lds[BLOCK / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long total = 0;
-    GRID_STRIDE_LOOP(r, nslices * SELL_C) {
+    int64_t s0, s1;
+    block_range(nslices, &s0, &s1);
+    for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+        const int64_t r = s * SELL_C + lane;
         int len = 0;
         if (r < V)
             for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) len += kept(k, nz_edge, geo);
         total += len;
-        int w = len;
+        int wmax = len;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
-        if ((threadIdx.x & 63) == 0) width64[r / SELL_C] = w * SELL_C;  // entries in the slice
+        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        if (lane == 0) width64[s] = wmax * SELL_C;  // entries in the slice
     }
     total = block_sum(total, lds);
     if (threadIdx.x == 0 && total) atomicAdd(kept_count, total);
@@ -85,7 +90,7 @@ __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restric
                             const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
                             const double* __restrict__ geo, const int64_t* __restrict__ sptr,
                             int32_t* __restrict__ scol, int32_t* __restrict__ ssrc) {
-    GRID_STRIDE_LOOP(i, nslices * SELL_C) {
+    RANGE_LOOP(i, nslices * SELL_C) {
         const int64_t s = i / SELL_C;
         const int lane = static_cast<int>(i % SELL_C);
         const int64_t row = i;
@@ -130,7 +135,7 @@ void build_sell_pattern(dec_mesh* m) {
     cnt.alloc(ctx, 1);
     cnt.zero();
     const double* geo = m->prune_geometric_zeros ? m->geo.p : nullptr;
-    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_xcd(S.nslices, BLOCK / 64)), dim3(BLOCK), 0, ctx->stream, m->V,
                        S.nslices, m->row_ptr.p, m->nz_edge.p, geo, w.p, cnt.p);
     S.ptr.alloc(ctx, S.nslices + 1);
     S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
@@ -139,7 +144,7 @@ void build_sell_pattern(dec_mesh* m) {
     S.src.alloc(ctx, S.entries);
     S.val64.alloc(ctx, S.entries);
     S.val32.alloc(ctx, S.entries);
-    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
                        S.nslices, m->row_ptr.p, m->col.p, m->nz_edge.p, geo, S.ptr.p, S.col.p, S.src.p);
     HIP_CHECK(hipGetLastError());
 }
@@ -159,7 +164,7 @@ void assemble_device(dec_mesh* m) {
     DEC_REQUIRE(m->star_ready, DEC_ESTATE, "dec_assemble needs dec_hodge1 first");
     m->val64.alloc(ctx, m->nnz);
     m->val32.alloc(ctx, m->nnz);
-    hipLaunchKernelGGL(k_assemble_values, dim3(grid_for(ROWG * m->V)), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p,
+    hipLaunchKernelGGL(k_assemble_values, dim3(grid_xcd(m->V, BLOCK / ROWG)), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p,
                        m->nz_edge.p, m->diag_pos.p, m->star1.p, m->val64.p, m->val32.p);
     HIP_CHECK(hipGetLastError());
     build_sell_pattern(m);

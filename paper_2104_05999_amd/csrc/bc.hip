@@ -176,8 +176,9 @@ __global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int3
                       const double* __restrict__ val, const uint8_t* __restrict__ fixed,
                       const double* __restrict__ dval, const double* __restrict__ g, double* __restrict__ b) {
     const int gl = threadIdx.x & (ROWG - 1);
-    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / ROWG;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / ROWG; v < V; v += ngroups) {
+    int64_t v0, v1;
+    block_range(V, &v0, &v1);
+    for (int64_t v = v0 + threadIdx.x / ROWG; v < v1; v += blockDim.x / ROWG) {
         const uint8_t f = fixed[v];
         if (f) {
             if (gl == 0) b[v] = (f == 1) ? dval[v] : 0.0;
@@ -202,7 +203,7 @@ __global__ void k_eliminate(int64_t V, const int32_t* __restrict__ row_ptr, cons
                             const uint8_t* __restrict__ fixed, double* __restrict__ val64, float* __restrict__ val32,
                             const int32_t* __restrict__ diag_pos, double* __restrict__ inv64,
                             float* __restrict__ inv32) {
-    GRID_STRIDE_LOOP(v, V) {
+    RANGE_LOOP(v, V) {
         const bool fv = fixed[v] != 0;
         for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
             const int32_t c = col[k];
@@ -256,11 +257,11 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
                            m->xyz.p, gload.p);
     }
     m->rhs.alloc(ctx, V);
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(ROWG * V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->val64.p,
+    hipLaunchKernelGGL(k_rhs, dim3(grid_xcd(V, BLOCK / ROWG)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->val64.p,
                        m->fixed.p, m->bc_value.p, f0 ? gload.p : nullptr, m->rhs.p);
     m->invdiag64.alloc(ctx, V);
     m->invdiag32.alloc(ctx, V);
-    hipLaunchKernelGGL(k_eliminate, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->fixed.p,
+    hipLaunchKernelGGL(k_eliminate, dim3(grid_xcd(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->fixed.p,
                        m->val64.p, m->val32.p, m->diag_pos.p, m->invdiag64.p, m->invdiag32.p);
     HIP_CHECK(hipGetLastError());
     refresh_sell_values(m);

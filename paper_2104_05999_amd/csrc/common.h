@@ -189,6 +189,39 @@ inline unsigned grid_for(int64_t n, int block = BLOCK, int64_t cap = 1 << 20) {
     return static_cast<unsigned>(g);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that XCD x owns the contiguous x-th eighth of the
+// work: neighbouring items, which gather the same data, then share an L2.
+// gridDim.x must be a multiple of 8 (grid_xcd).
+__device__ __forceinline__ int logical_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+// This block's contiguous share [b0, b1) of n items.
+__device__ __forceinline__ void block_range(int64_t n, int64_t* b0, int64_t* b1) {
+    const int64_t L = logical_block(), G = gridDim.x;
+    *b0 = n * L / G;
+    *b1 = n * (L + 1) / G;
+}
+
+// Grid for block_range: about `per_block` items per block, at most `cap`
+// blocks (32 per CU on 256 CUs: long-lived blocks, each walking a
+// contiguous range), a multiple of 8.
+inline unsigned grid_xcd(int64_t n, int64_t per_block = BLOCK, int64_t cap = 8192) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g > cap) g = cap;
+    g = (g + 7) / 8 * 8;
+    if (g < 8) g = 8;
+    return static_cast<unsigned>(g);
+}
+
+// Loop over this block's contiguous share of n items (launch with grid_xcd).
+#define RANGE_LOOP(i, n)                                      \
+    int64_t i##_lo, i##_hi;                                   \
+    block_range((n), &i##_lo, &i##_hi);                       \
+    for (int64_t i = i##_lo + threadIdx.x; i < i##_hi; i += blockDim.x)
+
 #define GRID_STRIDE_LOOP(i, n)                                                     \
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; \
          i < (n); i += static_cast<int64_t>(gridDim.x) * blockDim.x)

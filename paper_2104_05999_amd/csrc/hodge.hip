@@ -93,7 +93,7 @@ __global__ void k_elementary_areas(int64_t T, const int32_t* __restrict__ tets, 
 __global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
                                 const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
                                 const double* __restrict__ elem, double* __restrict__ geo) {
-    GRID_STRIDE_LOOP(e, E) {
+    RANGE_LOOP(e, E) {
         double area = 0.0;
         for (int64_t k = et_ptr[e]; k < et_ptr[e + 1]; ++k) area += elem[et_inc[k]];
         const d3 d = sub(load3(xyz + 3 * (int64_t)edges[2 * e + 1]), load3(xyz + 3 * (int64_t)edges[2 * e]));
@@ -249,7 +249,7 @@ __global__ void k_bin_fill(int32_t n, const double* __restrict__ discs, double r
 __global__ void k_crack_cut_binned(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
                                    const double* __restrict__ discs, Bins B, const int64_t* __restrict__ off,
                                    const int32_t* __restrict__ list, uint8_t* __restrict__ cut) {
-    GRID_STRIDE_LOOP(e, E) {
+    RANGE_LOOP(e, E) {
         const d3 p0 = load3(xyz + 3 * (int64_t)edges[2 * e]);
         const d3 p1 = load3(xyz + 3 * (int64_t)edges[2 * e + 1]);
         const int bx = bin_of(0.5 * (p0.x + p1.x), B.lo[0], B.inv[0]);
@@ -297,7 +297,7 @@ void ensure_geometry(dec_mesh* m) {
     hipLaunchKernelGGL(k_elementary_areas, dim3(grid_for(m->T)), dim3(BLOCK), 0, ctx->stream, m->T, m->tets.p,
                        m->xyz.p, elem.p);
     m->geo.alloc(ctx, m->E);
-    hipLaunchKernelGGL(k_edge_geometry, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
+    hipLaunchKernelGGL(k_edge_geometry, dim3(grid_xcd(m->E, BLOCK, 1 << 20)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
                        m->xyz.p, m->et_ptr.p, m->et_inc.p, elem.p, m->geo.p);
     HIP_CHECK(hipGetLastError());
     ctx->sync();  // elem is released on return
@@ -338,7 +338,7 @@ void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const dou
         cnt.zero();
         hipLaunchKernelGGL(k_bin_fill, disc_grid, dim3(64), 0, ctx->stream, n_cracks, cracks, reach, B, off.p, cnt.p,
                            list.p);
-        hipLaunchKernelGGL(k_crack_cut_binned, dim3(grid_for(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
+        hipLaunchKernelGGL(k_crack_cut_binned, dim3(grid_xcd(m->E)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
                            m->xyz.p, cracks, B, off.p, list.p, m->cut.p);
         HIP_CHECK(hipGetLastError());
         ctx->sync();  // the bins are released on return

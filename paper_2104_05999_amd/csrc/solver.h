@@ -44,21 +44,6 @@ struct CsrView {
     int64_t V;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Renumber them so that XCD x owns the contiguous x-th eighth of the
-// rows: neighbouring rows, which share x entries, then share an L2.
-// gridDim.x is a multiple of 8.
-__device__ __forceinline__ int logical_block() {
-    const int G = gridDim.x, b = blockIdx.x;
-    return (b & 7) * (G >> 3) + (b >> 3);
-}
-
-__device__ __forceinline__ void block_range(int64_t n, int64_t* b0, int64_t* b1) {
-    const int64_t L = logical_block(), G = gridDim.x;
-    *b0 = n * L / G;
-    *b1 = n * (L + 1) / G;
-}
-
 // Row `lane` of the slice starting at `base` with `width` stored entries per
 // row: sum over the row's entries in stored (ascending column) order.  The
 // entries go in groups of U: all column and value loads of a group are

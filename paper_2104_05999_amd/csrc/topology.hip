@@ -71,8 +71,9 @@ __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const in
 __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
     constexpr int W = 32;
     const int lane = threadIdx.x & (W - 1);
-    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / W;
-    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / W; v < V; v += ngroups) {
+    int64_t v0, v1;
+    block_range(V, &v0, &v1);
+    for (int64_t v = v0 + threadIdx.x / W; v < v1; v += blockDim.x / W) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
         if (d <= W) {
@@ -256,7 +257,7 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
 __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
                                  int32_t* __restrict__ nz_edge, unsigned* __restrict__ err) {
-    GRID_STRIDE_LOOP(v, V) {
+    RANGE_LOOP(v, V) {
         for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
             const int w = col[k];
             if (w >= v) break;
@@ -288,7 +289,7 @@ __global__ void k_faces(int64_t T, const int32_t* __restrict__ tet_edge, const i
                         unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
     __shared__ unsigned long long lds[BLOCK / 64];
     unsigned long long owned = 0, bnd = 0;
-    GRID_STRIDE_LOOP(t, T) {
+    RANGE_LOOP(t, T) {
         uint8_t mask = 0;
         for (int k = 0; k < 4; ++k) {
             const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
@@ -368,7 +369,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     cnt.zero();
     hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, m->vt_ptr.p, cnt.p,
                        m->vt_list.p);
-    hipLaunchKernelGGL(k_vt_sort, dim3(grid_for(32 * V)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
+    hipLaunchKernelGGL(k_vt_sort, dim3(grid_xcd(V, BLOCK / 32)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
     HIP_CHECK(hipGetLastError());
 
     // neighbours: counts, then edges, incidences and the CSR pattern (one 32-lane group per vertex)
@@ -405,7 +406,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
                        m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, tet_edge.p,
                        m->col.p, m->nz_edge.p, m->diag_pos.p);
     err.zero();
-    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
+    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
                        m->up_ptr.p, m->edges.p, m->nz_edge.p, err.p);
     HIP_CHECK(hipGetLastError());
     m->row_ptr.alloc(ctx, V + 1);
@@ -416,7 +417,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     DBuf<unsigned long long> fc;
     fc.alloc(ctx, 2);
     fc.zero();
-    hipLaunchKernelGGL(k_faces, dim3(grid_for(T, BLOCK, 8192)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
+    hipLaunchKernelGGL(k_faces, dim3(grid_xcd(T)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
                        m->et_inc.p, m->tet_bface.p, fc.p, err.p);
     HIP_CHECK(hipGetLastError());
     unsigned long long hc[2];
