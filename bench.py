@@ -43,7 +43,7 @@ def spmv_bytes(V, nnz, s_v):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_fp64_kuhn128_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("solver.h", "pcg.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("sell.h", "common.h")]
 
 
 def measured_traffic(n):

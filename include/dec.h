@@ -153,7 +153,8 @@ typedef struct dec_solve_opts {
     int32_t chunk;               /* iterations per launch batch (0: default)       */
     int32_t use_graph;           /* capture each batch in a hipGraph               */
     int32_t profile;             /* 0: off; k > 0: time SpMV launches with HIP events,
-                                    every k-th one of each launch batch (1: all)   */
+                                    every k-th one of each launch batch, the batch's
+                                    launches k-1, 2k-1, ... (1: all)               */
 } dec_solve_opts;
 
 typedef struct dec_solve_stats {

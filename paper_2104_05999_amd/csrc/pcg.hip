@@ -22,7 +22,6 @@
 
 namespace {
 
-enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
 constexpr int PREFETCH = 4;        // rows per thread the update kernel loads ahead of its opening fold
 constexpr int CLOSE_PREFETCH = 8;  // the same for the closing kernel (two vectors per row)
 // regions of the partials array, G doubles each
@@ -30,39 +29,7 @@ enum { R_PQ = 0, R_RR = 1, R_RZ = 2 };
 enum { FIN_NORM2 = 0, FIN_RR = 1, FIN_START = 2 };
 
 // ---------------------------------------------------------------- SpMV kernels
-// y = A x (PLAIN), y = A x with per-block partials of x.y (DOT), or
-// y = b - A x with per-block partials of y.y (RESID).
-template <class VT, int MODE, int U, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
-                                                const VT* __restrict__ b, double* __restrict__ partials,
-                                                const PcgScalars* __restrict__ st) {
-    __shared__ double lds[BLOCK / 64 + 1];
-    if (MODE == MODE_DOT && st->done) return;
-    int64_t s0, s1;
-    block_range(A.nslices, &s0, &s1);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    VT d = 0;
-    for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
-        const int64_t base = A.ptr[s];
-        const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
-        const int64_t row = s * SELL_C + lane;
-        const VT acc = sell_row<VT, U, NT>(A, base, width, lane, x);
-        if (row < A.V) {
-            if (MODE == MODE_RESID) {
-                const VT ri = b[row] - acc;
-                y[row] = ri;
-                d += ri * ri;
-            } else {
-                y[row] = acc;
-                if (MODE == MODE_DOT) d += x[row] * acc;
-            }
-        }
-    }
-    if (MODE == MODE_PLAIN) return;
-    const double bs = block_sum(static_cast<double>(d), lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-}
-
+// k_sell (sliced ELL) is in sell.h.
 template <class VT>
 __global__ void k_csr_plain(CsrView<VT> A, const VT* __restrict__ x, VT* __restrict__ y) {
     GRID_STRIDE_LOOP(row, A.V) y[row] = csr_row(A, row, x);
@@ -336,10 +303,12 @@ template <class VT, int MODE, int U, bool NT>
 void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
     const dim3 g(c->Gs), blk(BLOCK);
+    const int32_t* done = st ? &st->done : nullptr;
     if (ev_a)
-        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b, part, st);
+        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b, part,
+                              done);
     else
-        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, A, x, y, b, part, st);
+        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, A, x, y, b, part, done);
 }
 
 template <class VT, int MODE, bool NT>
@@ -488,7 +457,9 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
         // every batch must advance the iteration count until the state says done
         DEC_REQUIRE(batch <= o.max_iters / chunk + 4, DEC_EHIP, "PCG batches exceed the iteration cap");
         if (o.profile) {
-            // SpMV k of the batch carries events when k is a multiple of the sampling stride
+            // SpMV k of the batch carries events when k % every == every - 1: mid-batch launches,
+            // queued behind other work like the untimed ones (the first launch of a batch follows
+            // the host's read of the state and starts on an idle device)
             const int every = o.profile;
             while ((int)c->events.size() < 2 * chunk) {
                 hipEvent_t e;
@@ -497,13 +468,13 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             }
             if (batch == 0) last_iter = read_state(c, R.st).iter;
             for (int k = 0; k < chunk; ++k) {
-                const bool timed = k % every == 0;
+                const bool timed = k % every == every - 1;
                 enqueue_iteration(c, R, k & 1, timed ? c->events[2 * k] : nullptr,
                                   timed ? c->events[2 * k + 1] : nullptr);
             }
             const PcgScalars after = read_state(c, R.st);
             const int64_t ran = after.iter - last_iter;  // SpMVs 0 .. ran-1 did work; later ones returned at once
-            for (int64_t k = 0; k < ran && k < chunk; k += every) {
+            for (int64_t k = every - 1; k < ran && k < chunk; k += every) {
                 float ms = 0.0f;
                 HIP_CHECK(hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
                 if (stats) {

@@ -1,11 +1,12 @@
-// Device building blocks of the PCG solver: matrix views, the XCD-aware
-// block-to-rows mapping, the sliced-ELL row product and the scalar state
-// shared by the fused kernels.
+// Device building blocks of the PCG solver: the scalar state shared by the
+// fused kernels, the CSR view and the host-side solve cache.  The sliced-ELL
+// product lives in sell.h.
 #pragma once
 
 #include <map>
 
 #include "common.h"
+#include "sell.h"
 
 // Scalar state of one PCG run, kept in device memory so that a batch of
 // iterations can be launched (or replayed from a graph) without the host.
@@ -28,58 +29,12 @@ struct PcgScalars {
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXITER = 2, PCG_BREAKDOWN = 3 };
 
 template <class VT>
-struct SellView {
-    const int64_t* ptr;
-    const int32_t* col;
-    const VT* val;
-    int64_t nslices;
-    int64_t V;
-};
-
-template <class VT>
 struct CsrView {
     const int32_t* ptr;
     const int32_t* col;
     const VT* val;
     int64_t V;
 };
-
-// Row `lane` of the slice starting at `base` with `width` stored entries per
-// row: sum over the row's entries in stored (ascending column) order.  The
-// entries go in groups of U: all column and value loads of a group are
-// issued before its x gathers, and the last group is predicated (the width
-// is uniform across the wavefront), so no entry waits on the one before.
-template <class T, bool NT>
-__device__ __forceinline__ T stream_load(const T* p) {
-    if (NT) return __builtin_nontemporal_load(p);
-    return *p;
-}
-
-template <class VT, int U, bool NT = true>
-__device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
-                                       const VT* __restrict__ x) {
-    const int32_t* cp = A.col + base + lane;
-    const VT* vp = A.val + base + lane;
-    VT acc = 0;
-    for (int j = 0; j < width; j += U) {
-        int32_t c[U];
-        VT v[U], xv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool ok = j + u < width;
-            c[u] = ok ? stream_load<int32_t, NT>(cp + u * SELL_C) : 0;
-            v[u] = ok ? stream_load<VT, NT>(vp + u * SELL_C) : VT(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (j + u < width) ? x[c[u]] : VT(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (j + u < width) acc += v[u] * xv[u];
-        cp += U * SELL_C;
-        vp += U * SELL_C;
-    }
-    return acc;
-}
 
 template <class VT>
 __device__ __forceinline__ VT csr_row(const CsrView<VT>& A, int64_t row, const VT* __restrict__ x) {
