@@ -125,6 +125,7 @@ struct FsaiFactor {
     DBuf<int32_t> g_ptr, g_col, gt_ptr, gt_col, gt_src;
     DBuf<double> g_val64, gt_val64;
     DBuf<float> g_val32, gt_val32;
+    SellMatrix g_sell, gt_sell;  // sliced-ELL copies that the solver applies (same entry order per row)
 };
 
 struct SolveCache;  // Krylov vectors, reduction scratch and captured graphs

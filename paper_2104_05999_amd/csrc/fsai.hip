@@ -125,6 +125,71 @@ __global__ void k_fsai_transpose_values(int64_t n, const int32_t* __restrict__ s
     }
 }
 
+// Sliced-ELL copy of a CSR matrix: per-slice width (one wavefront per slice,
+// the maximum of its 64 row lengths), then the entries of each row in CSR
+// order, column-major inside the slice; padding repeats the row's own column
+// with value 0.
+__global__ __launch_bounds__(BLOCK) void k_csr_sell_width(int64_t V, int64_t nslices, const int32_t* __restrict__ ptr,
+                                                          int32_t* __restrict__ width64) {
+    static_assert(SELL_C == 64, "one slice per wavefront");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t s0, s1;
+    block_range(nslices, &s0, &s1);
+    for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+        const int64_t r = s * SELL_C + lane;
+        int wmax = r < V ? ptr[r + 1] - ptr[r] : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+        if (lane == 0) width64[s] = wmax * SELL_C;
+    }
+}
+
+__global__ void k_csr_sell_fill(int64_t V, int64_t nslices, const int32_t* __restrict__ ptr,
+                                const int32_t* __restrict__ col, const double* __restrict__ v64,
+                                const float* __restrict__ v32, const int64_t* __restrict__ sptr,
+                                int32_t* __restrict__ scol, double* __restrict__ s64, float* __restrict__ s32) {
+    RANGE_LOOP(r, nslices * SELL_C) {
+        const int64_t s = r / SELL_C;
+        const int lane = static_cast<int>(r % SELL_C);
+        const int width = static_cast<int>((sptr[s + 1] - sptr[s]) / SELL_C);
+        const int32_t pad = static_cast<int32_t>(r < V ? r : V - 1);
+        int j = 0;
+        if (r < V) {
+            for (int32_t k = ptr[r]; k < ptr[r + 1]; ++k, ++j) {
+                const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+                scol[idx] = col[k];
+                s64[idx] = v64[k];
+                s32[idx] = v32[k];
+            }
+        }
+        for (; j < width; ++j) {
+            const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+            scol[idx] = pad;
+            s64[idx] = 0.0;
+            s32[idx] = 0.0f;
+        }
+    }
+}
+
+void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, const int32_t* col, const double* v64,
+                     const float* v32, SellMatrix& S) {
+    hipStream_t s = ctx->stream;
+    S.nslices = (V + SELL_C - 1) / SELL_C;
+    DBuf<int32_t> w;
+    w.alloc(ctx, S.nslices);
+    hipLaunchKernelGGL(k_csr_sell_width, dim3(grid_xcd(S.nslices, BLOCK / 64)), dim3(BLOCK), 0, s, V, S.nslices, ptr,
+                       w.p);
+    S.ptr.alloc(ctx, S.nslices + 1);
+    S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
+    S.kept = nnz;
+    S.col.alloc(ctx, S.entries);
+    S.val64.alloc(ctx, S.entries);
+    S.val32.alloc(ctx, S.entries);
+    hipLaunchKernelGGL(k_csr_sell_fill, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, s, V, S.nslices, ptr, col,
+                       v64, v32, S.ptr.p, S.col.p, S.val64.p, S.val32.p);
+    HIP_CHECK(hipGetLastError());
+}
+
 }  // namespace
 
 void fsai_setup(dec_mesh* m) {
@@ -174,6 +239,11 @@ void fsai_setup(dec_mesh* m) {
     HIP_CHECK(hipGetLastError());
     const unsigned e = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
     DEC_REQUIRE(e == 0, DEC_EBREAKDOWN, "FSAI: a local system is not positive definite");
+    F.g_sell = SellMatrix();
+    F.gt_sell = SellMatrix();
+    build_sell_copy(ctx, V, ng, F.g_ptr.p, F.g_col.p, F.g_val64.p, F.g_val32.p, F.g_sell);
+    build_sell_copy(ctx, V, ng, F.gt_ptr.p, F.gt_col.p, F.gt_val64.p, F.gt_val32.p, F.gt_sell);
+    ctx->sync();  // the width scratch is released on return
     F.ready = true;
     if (m->solve) clear_graphs(m->solve);
 }

@@ -169,35 +169,6 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
     }
 }
 
-// w = G r (rows of the lower-triangular factor); S may be null (start-up)
-template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_fsai_g(CsrView<VT> G, const VT* __restrict__ r, VT* __restrict__ w,
-                                                  const PcgScalars* __restrict__ S) {
-    if (S && S->done) return;
-    int64_t i0, i1;
-    block_range(G.V, &i0, &i1);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) w[i] = csr_row(G, i, r);
-}
-
-// z = G^T w (INIT: straight into p) and partials of r.z
-template <class VT, bool INIT>
-__global__ __launch_bounds__(BLOCK) void k_fsai_gt(CsrView<VT> GT, const VT* __restrict__ w, VT* __restrict__ z,
-                                                   const VT* __restrict__ r, double* __restrict__ partials,
-                                                   int P, const PcgScalars* __restrict__ S) {
-    __shared__ double lds[BLOCK / 64 + 1];
-    if (!INIT && S->done) return;
-    int64_t i0, i1;
-    block_range(GT.V, &i0, &i1);
-    VT rz = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
-        const VT zi = csr_row(GT, i, w);
-        z[i] = zi;
-        rz += r[i] * zi;
-    }
-    const double bs = block_sum(static_cast<double>(rz), lds);
-    if (threadIdx.x == 0) partials[R_RZ * P + blockIdx.x] = bs;
-}
-
 // Close the iteration: p.q as the update kernel folded it, fold r.r and r.z;
 // decide breakdown / convergence /
 // iteration cap; p = z + beta p (z = D^-1 r for Jacobi); block 0 writes the
@@ -205,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_fsai_gt(CsrView<VT> GT, const VT* __r
 template <class VT, bool JACOBI>
 __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
                                                  const VT* __restrict__ z, VT* __restrict__ p,
-                                                 const double* __restrict__ partials, int P,
+                                                 const double* __restrict__ partials, int P, int n_rz,
                                                  const PcgScalars* __restrict__ S, PcgScalars* __restrict__ N) {
     __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -227,7 +198,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
     }
     const double pq = S->pq_now;
     double rr, rz;
-    reduce_bcast2(partials + R_RR * P, G, partials + R_RZ * P, G, lds, &rr, &rz);
+    reduce_bcast2(partials + R_RR * P, G, partials + R_RZ * P, n_rz, lds, &rr, &rz);
     int done = PCG_RUNNING;
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
         done = PCG_BREAKDOWN;
@@ -290,7 +261,7 @@ __global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __re
 template <class VT>
 struct Run {
     SellView<VT> A;
-    CsrView<VT> G, GT;
+    SellView<VT> G, GT;  // FSAI factor and its transpose (sliced ELL)
     VT *x, *r, *p, *q, *z, *w;
     const VT* invd;
     PcgScalars* st;  // two parities
@@ -386,10 +357,14 @@ int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
 double* region(SolveCache* c, int r) { return c->partials.p + (int64_t)r * stride(c); }
 
 // n_rr: blocks of the kernel that left the r.r partials; r.z partials always come from a G-block kernel
-void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, PcgScalars* st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, c->partials.p, stride(c), n_rr, c->G, what,
-                       factor, relative, st);
+void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, PcgScalars* st, int n_rz = 0) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, c->partials.p, stride(c), n_rr,
+                       n_rz ? n_rz : c->G, what, factor, relative, st);
 }
+
+// blocks that leave the r.z partials: the Jacobi kernels run on G blocks, the
+// FSAI product G^T w on the SpMV's Gs blocks
+int rz_parts(const SolveCache* c, int precond) { return precond == DEC_PRECOND_FSAI ? c->Gs : c->G; }
 
 template <class VT>
 void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a = nullptr,
@@ -404,15 +379,14 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
         hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
                            part, P, n_pq, S);
         hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, (const VT*)nullptr,
-                           R.p, part, P, S, N);
+                           R.p, part, P, G, S, N);
     } else {
         hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
                            (const VT*)nullptr, part, P, n_pq, S);
-        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w, S);
-        hipLaunchKernelGGL((k_fsai_gt<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.z, R.r, part, P,
-                           S);
+        launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
+        launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
         hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, (const VT*)nullptr, R.z,
-                           R.p, part, P, S, N);
+                           R.p, part, P, c->Gs, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -425,10 +399,8 @@ void enqueue_precond_start(SolveCache* c, const Run<VT>& R) {
         hipLaunchKernelGGL(k_init_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
                            region(c, R_RZ));
     } else {
-        hipLaunchKernelGGL(k_fsai_g<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, R.G, R.r, R.w,
-                           (const PcgScalars*)nullptr);
-        hipLaunchKernelGGL((k_fsai_gt<VT, true>), dim3(c->G), dim3(BLOCK), 0, c->stream, R.GT, R.w, R.p, R.r,
-                           c->partials.p, stride(c), (const PcgScalars*)nullptr);
+        launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, nullptr);       // w = G r
+        launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.p, R.r, region(c, R_RZ), nullptr);   // p = G^T w, r.z partials
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -516,8 +488,8 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
 Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
     Run<double> R{};
     R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V};
-    R.G = {m->fsai.g_ptr.p, m->fsai.g_col.p, m->fsai.g_val64.p, m->V};
-    R.GT = {m->fsai.gt_ptr.p, m->fsai.gt_col.p, m->fsai.gt_val64.p, m->V};
+    R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val64.p, m->fsai.g_sell.nslices, m->V};
+    R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val64.p, m->fsai.gt_sell.nslices, m->V};
     R.x = c->x64.p;
     R.r = c->r64.p;
     R.p = c->p64.p;
@@ -533,8 +505,8 @@ Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
 Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
     Run<float> R{};
     R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V};
-    R.G = {m->fsai.g_ptr.p, m->fsai.g_col.p, m->fsai.g_val32.p, m->V};
-    R.GT = {m->fsai.gt_ptr.p, m->fsai.gt_col.p, m->fsai.gt_val32.p, m->V};
+    R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val32.p, m->fsai.g_sell.nslices, m->V};
+    R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val32.p, m->fsai.gt_sell.nslices, m->V};
     R.x = c->x32.p;
     R.r = c->r32.p;
     R.p = c->p32.p;
@@ -574,7 +546,7 @@ int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int
         finalize(c, FIN_NORM2, c->G, tol2, 0, R.st);
         launch_sell<double, MODE_RESID>(c, R.A, R.x, R.r, m->rhs.p, region(c, R_RR), nullptr);
         enqueue_precond_start<double>(c, R);
-        finalize(c, FIN_START, c->Gs, 0.0, 0, R.st);
+        finalize(c, FIN_START, c->Gs, 0.0, 0, R.st, rz_parts(c, R.precond));
         HIP_CHECK(hipGetLastError());
         PcgScalars s = read_state(c, R.st);
         if (!s.done) {
@@ -628,7 +600,7 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s4, c->r32.p, c->x32.p,
                            region(c, R_RR));
         enqueue_precond_start<float>(c, R);
-        finalize(c, FIN_START, c->G, itol * itol, 1, R.st);
+        finalize(c, FIN_START, c->G, itol * itol, 1, R.st, rz_parts(c, R.precond));
         HIP_CHECK(hipGetLastError());
         PcgScalars s = read_state(c, R.st);
         if (!s.done) s = iterate(c, R, o, stats);

@@ -57,16 +57,19 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
     return acc;
 }
 
-enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2 };
+enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 
-// y = A x (PLAIN), y = A x with per-block partials of x.y (DOT), or
-// y = b - A x with per-block partials of y.y (RESID).
+// y = A x (PLAIN), y = A x with per-block partials of x.y (DOT),
+// y = b - A x with per-block partials of y.y (RESID), or y = A x with
+// per-block partials of b.y (DOTB).  A launch whose `done` flag (if given)
+// is set returns at once: inside a batch of PCG iterations that has
+// converged, the remaining launches do nothing.
 template <class VT, int MODE, int U, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
                                                 const int32_t* __restrict__ done) {
     __shared__ double lds[BLOCK / 64 + 1];
-    if (MODE == MODE_DOT && *done) return;
+    if (done != nullptr && *done) return;
     int64_t s0, s1;
     block_range(A.nslices, &s0, &s1);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
             } else {
                 y[row] = acc;
                 if (MODE == MODE_DOT) d += x[row] * acc;
+                if (MODE == MODE_DOTB) d += b[row] * acc;
             }
         }
     }

@@ -171,6 +171,43 @@ def test_cut_mask_many_discs_over_lds_chunks(ctx, dev):
     assert np.array_equal(cut.cpu().numpy().astype(bool), O.crack_cut(xyz, E, cr))
 
 
+def _odd_discs():
+    """Degenerate discs: zero radius, negative radius, a disc larger than the domain, a zero
+    normal, NaN and infinite centres."""
+    nan, inf = float("nan"), float("inf")
+    return np.array([
+        [0.5, 0.5, 0.5, 0.0, 0.0, 1.0, 0.0],
+        [0.31, 0.42, 0.53, 0.0, 1.0, 0.0, -0.2],
+        [0.5, 0.5, 0.37, 0.3, 0.4, 0.866, 10.0],
+        [0.2, 0.2, 0.2, 0.0, 0.0, 0.0, 0.3],
+        [nan, 0.5, 0.5, 1.0, 0.0, 0.0, 0.3],
+        [0.5, 0.5, 0.5, nan, 0.0, 1.0, 0.3],
+        [inf, 0.5, 0.5, 1.0, 0.0, 0.0, 0.3],
+        [0.5, 0.5, 0.5, 1.0, 0.0, 0.0, nan],
+    ])
+
+
+@pytest.mark.parametrize("many", [False, True])
+def test_cut_mask_degenerate_discs(ctx, dev, many):
+    """Both cut paths (at most 64 discs: every disc against every edge; more: spatial bins)
+    agree with the oracle predicate on degenerate discs."""
+    n = 7
+    xyz, tets = W.kuhn_cube(n)
+    E = O.edges_of(tets, len(xyz))
+    cr = _odd_discs()
+    if many:
+        cr = np.concatenate([W.penny_cracks(80, 11, 0.02, 0.1), cr])
+    m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
+    try:
+        cut, star = m.hodge1(None, _t(cr, dev))
+        want = O.crack_cut(xyz, E, cr)
+        assert want.any()
+        assert np.array_equal(cut.cpu().numpy().astype(bool), want)
+        assert np.all(np.isfinite(star.cpu().numpy()))
+    finally:
+        m.close()
+
+
 # ---------------------------------------------------------------- assembly and boundary data
 @pytest.mark.parametrize("n", [4, 16])
 def test_assembly_and_bc(ctx, dev, n):
