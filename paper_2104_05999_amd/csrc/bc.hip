@@ -66,12 +66,18 @@ __global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const d
 // compare-and-swap, so parent[v] <= v always holds, every find ends, and the
 // root of a component is its smallest vertex (a label independent of
 // scheduling).  A failed swap means another thread hooked that root; the
-// loop then continues from the new root.
+// loop then continues from the new root.  Finds halve the path they walk:
+// a vertex that is not a root is re-pointed to its grandparent, which is an
+// ancestor in the same tree (a non-root never becomes a root again, and the
+// swaps only ever change roots), so the halving races with nothing.
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t v) {
     while (true) {
         const int32_t p = __hip_atomic_load(parent + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (p == v) return v;
-        v = p;
+        const int32_t gp = __hip_atomic_load(parent + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp == p) return p;
+        __hip_atomic_store(parent + v, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = gp;
     }
 }
 
