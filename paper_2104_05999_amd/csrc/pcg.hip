@@ -111,11 +111,12 @@ __global__ void k_init_jacobi(int64_t V, const VT* __restrict__ r, const VT* __r
 
 // ---------------------------------------------------------------- iteration kernels
 // Every block folds the p.q partials of the SpMV in the same order, so all
-// blocks see the same alpha.  A non-positive p.q leaves x and r untouched;
-// the closing kernel reports the breakdown.
+// blocks see the same alpha.  The update kernel moves r only (r -= alpha q);
+// the closing kernel moves x (x += alpha p) together with p, so p is read
+// once per iteration.  A non-positive p.q leaves x and r untouched; the
+// closing kernel reports the breakdown.
 template <class VT, bool JACOBI>
-__global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x, VT* __restrict__ r,
-                                                  const VT* __restrict__ p, const VT* __restrict__ q,
+__global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r, const VT* __restrict__ q,
                                                   const VT* __restrict__ invd, double* __restrict__ partials,
                                                   int P, int n_pq, PcgScalars* __restrict__ S) {
     __shared__ double lds[BLOCK / 64 + 1];
@@ -124,13 +125,11 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
     block_range(V, &i0, &i1);
     // the first PREFETCH rows of each thread are loaded before the fold, so
     // the fold's latency overlaps with their transfer
-    VT fx[PREFETCH], fp[PREFETCH], fr[PREFETCH], fq[PREFETCH], fd[PREFETCH];
+    VT fr[PREFETCH], fq[PREFETCH], fd[PREFETCH];
 #pragma unroll
     for (int k = 0; k < PREFETCH; ++k) {
         const int64_t i = i0 + threadIdx.x + k * BLOCK;
         if (i < i1) {
-            fx[k] = x[i];
-            fp[k] = p[i];
             fr[k] = r[i];
             fq[k] = q[i];
             fd[k] = JACOBI ? invd[i] : VT(0);
@@ -145,18 +144,14 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
     for (int k = 0; k < PREFETCH; ++k) {
         const int64_t i = i0 + threadIdx.x + k * BLOCK;
         if (i < i1) {
-            const VT xi = fx[k] + a * fp[k];
             const VT ri = fr[k] - a * fq[k];
-            x[i] = xi;
             r[i] = ri;
             if (JACOBI) rz += ri * (fd[k] * ri);
             rr += ri * ri;
         }
     }
     for (int64_t i = i0 + threadIdx.x + PREFETCH * BLOCK; i < i1; i += BLOCK) {
-        const VT xi = x[i] + a * p[i];
         const VT ri = r[i] - a * q[i];
-        x[i] = xi;
         r[i] = ri;
         if (JACOBI) rz += ri * (invd[i] * ri);
         rr += ri * ri;
@@ -170,14 +165,16 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ x,
 }
 
 // Close the iteration: p.q as the update kernel folded it, fold r.r and r.z;
-// decide breakdown / convergence /
-// iteration cap; p = z + beta p (z = D^-1 r for Jacobi); block 0 writes the
-// next state N.  A finished state is carried forward unchanged.
+// decide breakdown / convergence / iteration cap; x += alpha p (unless p.q
+// broke down), then p = z + beta p while running (z = D^-1 r for Jacobi);
+// block 0 writes the next state N.  A finished state is carried forward
+// unchanged.
 template <class VT, bool JACOBI>
-__global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict__ r, const VT* __restrict__ invd,
-                                                 const VT* __restrict__ z, VT* __restrict__ p,
-                                                 const double* __restrict__ partials, int P, int n_rz,
-                                                 const PcgScalars* __restrict__ S, PcgScalars* __restrict__ N) {
+__global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, const VT* __restrict__ r,
+                                                 const VT* __restrict__ invd, const VT* __restrict__ z,
+                                                 VT* __restrict__ p, const double* __restrict__ partials, int P,
+                                                 int n_rz, const PcgScalars* __restrict__ S,
+                                                 PcgScalars* __restrict__ N) {
     __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (S->done) {
@@ -187,35 +184,46 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, const VT* __restrict
     const int G = gridDim.x;
     int64_t i0, i1;
     block_range(V, &i0, &i1);
-    VT fz[CLOSE_PREFETCH], fp[CLOSE_PREFETCH];  // z (or D^-1 r) and p of the first rows, loaded before the fold
+    // z (or D^-1 r), p and x of the first rows, loaded before the fold
+    VT fz[CLOSE_PREFETCH], fp[CLOSE_PREFETCH], fx[CLOSE_PREFETCH];
 #pragma unroll
     for (int k = 0; k < CLOSE_PREFETCH; ++k) {
         const int64_t i = i0 + threadIdx.x + k * BLOCK;
         if (i < i1) {
             fz[k] = JACOBI ? invd[i] * r[i] : z[i];
             fp[k] = p[i];
+            fx[k] = x[i];
         }
     }
     const double pq = S->pq_now;
     double rr, rz;
     reduce_bcast2(partials + R_RR * P, G, partials + R_RZ * P, n_rz, lds, &rr, &rz);
+    const bool pq_ok = pq > 0.0 && isfinite(pq);
     int done = PCG_RUNNING;
-    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
+    if (!pq_ok || !isfinite(rr) || !isfinite(rz))
         done = PCG_BREAKDOWN;
     else if (rr <= S->rr_stop)
         done = PCG_CONVERGED;
     else if (S->iter + 1 >= S->max_iter)
         done = PCG_MAXITER;
     const double beta = rz / S->rho;
-    if (done == PCG_RUNNING) {
+    if (pq_ok) {
+        const VT a = static_cast<VT>(S->rho / pq);
         const VT bt = static_cast<VT>(beta);
+        const bool run = done == PCG_RUNNING;
 #pragma unroll
         for (int k = 0; k < CLOSE_PREFETCH; ++k) {
             const int64_t i = i0 + threadIdx.x + k * BLOCK;
-            if (i < i1) p[i] = fz[k] + bt * fp[k];
+            if (i < i1) {
+                x[i] = fx[k] + a * fp[k];
+                if (run) p[i] = fz[k] + bt * fp[k];
+            }
         }
-        for (int64_t i = i0 + threadIdx.x + CLOSE_PREFETCH * BLOCK; i < i1; i += BLOCK)
-            p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * p[i];
+        for (int64_t i = i0 + threadIdx.x + CLOSE_PREFETCH * BLOCK; i < i1; i += BLOCK) {
+            const VT pi = p[i];
+            x[i] = x[i] + a * pi;
+            if (run) p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * pi;
+        }
     }
     if (lead) {
         N->rho = rz;
@@ -376,17 +384,17 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     PcgScalars* N = R.st + (par ^ 1);
     launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
     if (R.precond == DEC_PRECOND_JACOBI) {
-        hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q, R.invd,
-                           part, P, n_pq, S);
-        hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, (const VT*)nullptr,
-                           R.p, part, P, G, S, N);
+        hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part, P,
+                           n_pq, S);
+        hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
+                           (const VT*)nullptr, R.p, part, P, G, S, N);
     } else {
-        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.p, R.q,
-                           (const VT*)nullptr, part, P, n_pq, S);
+        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, (const VT*)nullptr,
+                           part, P, n_pq, S);
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
-        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, (const VT*)nullptr, R.z,
-                           R.p, part, P, c->Gs, S, N);
+        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, (const VT*)nullptr,
+                           R.z, R.p, part, P, c->Gs, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }
