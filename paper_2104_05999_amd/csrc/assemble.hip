@@ -100,14 +100,14 @@ __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restric
         if (row < V) {
             for (int32_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
                 if (!kept(k, nz_edge, geo)) continue;
-                const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+                const int64_t idx = sell_index(sptr[s], width, j, lane);
                 scol[idx] = col[k];
                 ssrc[idx] = k;
                 ++j;
             }
         }
         for (; j < width; ++j) {
-            const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+            const int64_t idx = sell_index(sptr[s], width, j, lane);
             scol[idx] = pad_col;
             ssrc[idx] = -1;
         }

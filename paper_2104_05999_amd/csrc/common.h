@@ -101,11 +101,20 @@ struct DBuf {
 };
 
 // ---------------------------------------------------------------- matrices
-// Sliced ELLPACK with slice height SELL_C (one row per lane of a wavefront),
-// entries stored column-major inside a slice: entry j of row r of slice s is
-// at ptr[s] + j * SELL_C + (r - s * SELL_C).  Padding entries repeat the row's
-// own column with value 0.
+// Sliced ELLPACK with slice height SELL_C (one row per lane of a wavefront)
+// and `width` stored entries per row in the slice, paired: entries 2t and
+// 2t + 1 of lane l sit side by side at ptr[s] + 2 SELL_C t + 2 l (+1), and an
+// odd last entry at ptr[s] + 2 SELL_C (width / 2) + l.  A wavefront then
+// reads two entries of every row with one 8 B (column) or 16 B (FP64 value)
+// load per lane, over one contiguous segment.  Padding entries repeat the
+// row's own column with value 0.
 constexpr int SELL_C = 64;
+
+__host__ __device__ inline int64_t sell_index(int64_t base, int width, int j, int lane) {
+    const int np = width >> 1;
+    return j < 2 * np ? base + static_cast<int64_t>(j >> 1) * (2 * SELL_C) + 2 * lane + (j & 1)
+                      : base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
+}
 
 struct SellMatrix {
     int64_t nslices = 0;

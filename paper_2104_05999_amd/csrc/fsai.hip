@@ -156,14 +156,14 @@ __global__ void k_csr_sell_fill(int64_t V, int64_t nslices, const int32_t* __res
         int j = 0;
         if (r < V) {
             for (int32_t k = ptr[r]; k < ptr[r + 1]; ++k, ++j) {
-                const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+                const int64_t idx = sell_index(sptr[s], width, j, lane);
                 scol[idx] = col[k];
                 s64[idx] = v64[k];
                 s32[idx] = v32[k];
             }
         }
         for (; j < width; ++j) {
-            const int64_t idx = sptr[s] + static_cast<int64_t>(j) * SELL_C + lane;
+            const int64_t idx = sell_index(sptr[s], width, j, lane);
             scol[idx] = pad;
             s64[idx] = 0.0;
             s32[idx] = 0.0f;

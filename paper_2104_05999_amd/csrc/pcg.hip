@@ -293,15 +293,13 @@ void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, con
 template <class VT, int MODE, bool NT>
 void launch_sell_nt(SolveCache* c, int unroll, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                     const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
+    // unroll = pairs of entries in flight per lane
     switch (unroll) {
-        case 4:
-            launch_sell_u<VT, MODE, 4, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
-            break;
-        case 16:
-            launch_sell_u<VT, MODE, 16, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
+        case 2:
+            launch_sell_u<VT, MODE, 2, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
         default:
-            launch_sell_u<VT, MODE, 8, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
+            launch_sell_u<VT, MODE, 4, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
     }
 }
@@ -322,7 +320,7 @@ void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const
         launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st, ev_a, ev_b);
 }
 
-// Pick the sliced-ELL variant (unroll 4/8, non-temporal loads on/off) by
+// Pick the sliced-ELL variant (2 or 4 entry pairs in flight, non-temporal loads on/off) by
 // timing y = A x on this matrix.  All variants sum every row in the same
 // order, so the choice never changes a result.
 template <class VT>
@@ -337,7 +335,7 @@ void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const 
         c->tuned[pi] = true;
         return;
     }
-    const int cand[4][2] = {{8, 1}, {8, 0}, {4, 1}, {4, 0}};
+    const int cand[4][2] = {{4, 1}, {4, 0}, {2, 1}, {2, 0}};
     float best = 1e30f;
     int pick = 0;
     for (int k = 0; k < 4; ++k) {

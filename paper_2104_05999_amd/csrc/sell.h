@@ -2,11 +2,10 @@
 // product), the dominant kernel of every solve.  Kept on its own so that the
 // HBM counters recorded for it can be tied to exactly this source.
 //
-// Layout: slices of SELL_C = 64 consecutive rows, one row per lane of a
-// wavefront; entry j of row r of slice s sits at ptr[s] + j * 64 + (r - 64 s),
-// so each load instruction of a wavefront reads one contiguous 256 B (column)
-// or 512 B (FP64 value) segment.  Padding entries repeat the row's own column
-// with value 0.
+// Layout (see sell_index): slices of SELL_C = 64 consecutive rows, one row
+// per lane of a wavefront, consecutive entries of a row stored in pairs, so
+// each load instruction of a wavefront reads two entries of every row from one
+// contiguous 512 B (column) or 1 KiB (FP64 value) segment.
 #pragma once
 
 #include "common.h"
@@ -20,39 +19,73 @@ struct SellView {
     int64_t V;
 };
 
-// Row `lane` of the slice starting at `base` with `width` stored entries per
-// row: sum over the row's entries in stored (ascending column) order.  The
-// entries go in groups of U: all column and value loads of a group are
-// issued before its x gathers, and the last group is predicated (the width
-// is uniform across the wavefront), so no entry waits on the one before.
+// Native two-element vectors for the paired loads.
+template <class T>
+struct Pair;
+template <>
+struct Pair<int32_t> {
+    typedef int32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+
 template <class T, bool NT>
 __device__ __forceinline__ T stream_load(const T* p) {
     if (NT) return __builtin_nontemporal_load(p);
     return *p;
 }
 
+// Row `lane` of the slice starting at `base` with `width` stored entries per
+// row: sum over the row's entries in stored (ascending column) order.  The
+// pairs go in groups of U: all column and value loads of a group are issued
+// before its x gathers, and the last group is predicated (the width is
+// uniform across the wavefront), so no entry waits on the one before; an odd
+// last entry follows.  The terms are added in entry order, so every layout
+// and unroll gives the same sum.
 template <class VT, int U, bool NT = true>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
                                        const VT* __restrict__ x) {
-    const int32_t* cp = A.col + base + lane;
-    const VT* vp = A.val + base + lane;
+    typedef typename Pair<int32_t>::type C2;
+    typedef typename Pair<VT>::type V2;
+    const int np = width >> 1;
+    const C2* cp = reinterpret_cast<const C2*>(A.col + base) + lane;
+    const V2* vp = reinterpret_cast<const V2*>(A.val + base) + lane;
     VT acc = 0;
-    for (int j = 0; j < width; j += U) {
-        int32_t c[U];
-        VT v[U], xv[U];
+    for (int t = 0; t < np; t += U) {
+        C2 c[U];
+        V2 v[U];
+        VT x0[U], x1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool ok = j + u < width;
-            c[u] = ok ? stream_load<int32_t, NT>(cp + u * SELL_C) : 0;
-            v[u] = ok ? stream_load<VT, NT>(vp + u * SELL_C) : VT(0);
+            const bool ok = t + u < np;
+            c[u] = ok ? stream_load<C2, NT>(cp + u * SELL_C) : C2(0);
+            v[u] = ok ? stream_load<V2, NT>(vp + u * SELL_C) : V2(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = (j + u < width) ? x[c[u]] : VT(0);
+        for (int u = 0; u < U; ++u) {
+            const bool ok = t + u < np;
+            x0[u] = ok ? x[c[u].x] : VT(0);
+            x1[u] = ok ? x[c[u].y] : VT(0);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j + u < width) acc += v[u] * xv[u];
+            if (t + u < np) {
+                acc += v[u].x * x0[u];
+                acc += v[u].y * x1[u];
+            }
         cp += U * SELL_C;
         vp += U * SELL_C;
+    }
+    if (width & 1) {
+        const int64_t k = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
+        const int32_t c = stream_load<int32_t, NT>(A.col + k);
+        acc += stream_load<VT, NT>(A.val + k) * x[c];
     }
     return acc;
 }

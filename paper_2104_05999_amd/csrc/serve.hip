@@ -255,7 +255,7 @@ __global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ s
             const int64_t base = A.ptr[s];
             const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
             const int64_t row = s * SELL_C + lane;
-            const double acc = sell_row<double, 8, true>(A, base, width, lane, S.x64);
+            const double acc = sell_row<double, 4, true>(A, base, width, lane, S.x64);
             if (row < A.V) {
                 const double ri = S.b[row] - acc;
                 S.r64[row] = ri;
@@ -550,9 +550,9 @@ template <class VT>
 void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t* n_items, int par) {
     const dim3 g(s->G), b(BLOCK);
     if (sizeof(VT) == 8)
-        hipLaunchKernelGGL((bk_spmv_dot<VT, 8, true>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+        hipLaunchKernelGGL((bk_spmv_dot<VT, 4, true>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
     else
-        hipLaunchKernelGGL((bk_spmv_dot<VT, 8, false>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+        hipLaunchKernelGGL((bk_spmv_dot<VT, 4, false>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
     hipLaunchKernelGGL(bk_update<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
     hipLaunchKernelGGL(bk_close<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
 }

@@ -62,7 +62,7 @@ struct SolveCache {
     int Gs = 0;                    // blocks of the SpMV kernels (multiple of 8)
     // sliced-ELL variant per precision ([0] FP64, [1] FP32), chosen by the
     // tuner among variants whose products are bit-for-bit identical
-    int unroll[2] = {8, 8};
+    int unroll[2] = {4, 4};
     int nt[2] = {1, 0};  // non-temporal matrix loads
     bool tuned[2] = {false, false};
     bool pinned_variant = false;  // set through the environment: no tuning
