@@ -298,6 +298,9 @@ void launch_sell_nt(SolveCache* c, int unroll, const SellView<VT>& A, const VT* 
         case 2:
             launch_sell_u<VT, MODE, 2, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
+        case 3:
+            launch_sell_u<VT, MODE, 3, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
+            break;
         default:
             launch_sell_u<VT, MODE, 4, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
@@ -320,7 +323,7 @@ void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const
         launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st, ev_a, ev_b);
 }
 
-// Pick the sliced-ELL variant (2 or 4 entry pairs in flight, non-temporal loads on/off) by
+// Pick the sliced-ELL variant (2, 3 or 4 entry pairs in flight, non-temporal loads on/off) by
 // timing y = A x on this matrix.  All variants sum every row in the same
 // order, so the choice never changes a result.
 template <class VT>
@@ -335,10 +338,10 @@ void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const 
         c->tuned[pi] = true;
         return;
     }
-    const int cand[4][2] = {{4, 1}, {4, 0}, {2, 1}, {2, 0}};
+    const int cand[6][2] = {{4, 1}, {4, 0}, {3, 1}, {3, 0}, {2, 1}, {2, 0}};
     float best = 1e30f;
     int pick = 0;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 6; ++k) {
         c->unroll[pi] = cand[k][0];
         c->nt[pi] = cand[k][1];
         launch_sell<VT, MODE_PLAIN>(c, A, x, y, nullptr, nullptr, nullptr);
