@@ -22,7 +22,8 @@
  *    outputs (k_eff, counts, stats) are HOST pointers.
  *  - Work is ordered on the context's HIP stream.  Calls that return a
  *    count or a scalar to the host synchronise that stream before returning.
- *    Input buffers only need to stay valid until the call returns.
+ *    Input buffers only need to stay valid until the call returns (the
+ *    server, dec_server_submit, is the exception).
  *  - The caller owns every buffer it passes; the library copies what it
  *    keeps.  The library's own device memory comes from the alloc/free
  *    callbacks given to dec_create (hipMalloc/hipFree when they are NULL).
@@ -268,7 +269,12 @@ int dec_server_opts_default(dec_server_opts* opts);
 /* hbm_budget_bytes bounds the estimated device memory of the admitted
  * requests (setup peak included). */
 int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_opts* opts, dec_server** out);
-/* Queue a request (FIFO).  DEC_EBUDGET when it cannot fit the budget even alone. */
+/* Queue a request (FIFO).  DEC_EBUDGET when it cannot fit the budget even alone.
+ * Unlike the other calls, the request's arrays are read later, when a
+ * dec_server_step admits it (its setup runs on a stream of the server, after
+ * the work queued on the context's stream before this call), and T_out is
+ * written when it retires: the caller keeps every array of the request valid
+ * and unchanged until its result has been polled or it was cancelled. */
 int dec_server_submit(dec_server* s, const dec_request* req, uint64_t* ticket);
 /* Advance the server: one batch of iterations, refinement steps, retirements,
  * admissions.  n_active / n_pending (host, NULL ok) receive the counts after

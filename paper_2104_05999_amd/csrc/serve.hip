@@ -355,6 +355,7 @@ struct ServeReq {
     uint64_t ticket;
     dec_request req;
     double t_submit;
+    hipEvent_t inputs;  // recorded on the caller's stream at submit; the setup waits for it
 };
 
 struct ServeSlot {
@@ -363,6 +364,7 @@ struct ServeSlot {
     uint64_t ticket = 0;
     dec_request req{};
     dec_mesh* mesh = nullptr;
+    hipEvent_t inputs = nullptr;  // the request's input event, released with the slot
     int64_t budget_bytes = 0;
     int32_t nchunks = 0;
     DBuf<double> x64, r64, p64, q64, part;
@@ -414,6 +416,10 @@ void free_slot(dec_server* s, ServeSlot& sl) {
     if (sl.mesh) {
         delete sl.mesh;
         sl.mesh = nullptr;
+    }
+    if (sl.inputs) {
+        (void)hipEventDestroy(sl.inputs);
+        sl.inputs = nullptr;
     }
     for (DBuf<double>* b : {&sl.x64, &sl.r64, &sl.p64, &sl.q64, &sl.part}) b->release();
     for (DBuf<float>* b : {&sl.x32, &sl.r32, &sl.p32, &sl.q32}) b->release();
@@ -483,6 +489,7 @@ bool admit(dec_server* s, const ServeReq& q, int k) {
     sl.t_submit = q.t_submit;
     sl.t_admit = now_ms(s->t0);
     sl.mode = s->opts.precision;
+    sl.inputs = q.inputs;
     sl.budget_bytes = estimate_bytes(q.req.V, q.req.T);
     s->committed += sl.budget_bytes;
     dec_mesh* m = new dec_mesh();
@@ -491,6 +498,8 @@ bool admit(dec_server* s, const ServeReq& q, int k) {
     m->T = q.req.T;
     sl.mesh = m;
     try {
+        // the caller's writes to the request arrays (on its stream, before submit) come first
+        HIP_CHECK(hipStreamWaitEvent(s->setup_stream, q.inputs, 0));
         build_topology_device(m, q.req.xyz, q.req.tets);
         hodge1_device(m, q.req.kappa, q.req.n_cracks, q.req.cracks);
         assemble_device(m);
@@ -523,6 +532,7 @@ bool admit(dec_server* s, const ServeReq& q, int k) {
         r.t_finish_ms = now_ms(s->t0);
         s->done.push_back(r);
         s->setup_ctx.last_error = e.msg;
+        (void)hipStreamSynchronize(s->setup_stream);  // no setup kernel may still use what free_slot returns
         free_slot(s, sl);
         return false;
     }
@@ -794,6 +804,14 @@ int dec_server_submit(dec_server* s, const dec_request* req, uint64_t* ticket) {
         return e.code;
     }
     ServeReq q;
+    try {
+        s->ctx->set_device();
+        HIP_CHECK(hipEventCreateWithFlags(&q.inputs, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(q.inputs, s->ctx->stream));
+    } catch (const DecError& e) {
+        s->ctx->last_error = e.msg;
+        return e.code;
+    }
     q.ticket = s->next_ticket++;
     q.req = *req;
     q.t_submit = now_ms(s->t0);
@@ -894,6 +912,7 @@ int dec_server_cancel(dec_server* s, uint64_t ticket) {
             r.t_submit_ms = it->t_submit;
             r.t_finish_ms = now_ms(s->t0);
             s->done.push_back(r);
+            (void)hipEventDestroy(it->inputs);
             s->pending.erase(it);
             return DEC_OK;
         }
@@ -931,6 +950,7 @@ int dec_server_destroy(dec_server* s) {
         if (sl.phase != PH_FREE) free_slot(s, sl);
         if (sl.ready) (void)hipEventDestroy(sl.ready);
     }
+    for (ServeReq& q : s->pending) (void)hipEventDestroy(q.inputs);
     for (hipGraphExec_t g : s->graph)
         if (g) (void)hipGraphExecDestroy(g);
     s->d_slots.release();
