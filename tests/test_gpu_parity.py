@@ -342,14 +342,19 @@ def test_fsai_factor_matches_oracle(ctx, dev):
     assert np.allclose(val.cpu().numpy(), G.data, rtol=1e-12, atol=1e-14 * np.abs(G.data).max())
 
 
-def test_solver_is_deterministic(ctx, dev):
+@pytest.mark.parametrize("precision,precond", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_solver_is_deterministic(ctx, dev, precision, precond):
+    """Fixed-order folds: repeated solves, graph replay or plain launches, and sampled timing
+    all give the same bits."""
     s = _system(12, n_cracks=20)
     m, _, _, _, _ = _gpu(ctx, s, dev)
-    a, sa, _ = m.solve(tol=1e-11)
-    b, sb, _ = m.solve(tol=1e-11)
-    c, sc, _ = m.solve(tol=1e-11, use_graph=0)
-    assert torch.equal(a, b) and torch.equal(a, c)
-    assert sa["iterations"] == sb["iterations"] == sc["iterations"]
+    kw = dict(tol=1e-11, precision=precision, precond=precond)
+    a, sa, _ = m.solve(**kw)
+    b, sb, _ = m.solve(**kw)
+    c, sc, _ = m.solve(use_graph=0, **kw)
+    d, sd, _ = m.solve(profile=3, **kw)
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, d)
+    assert sa["iterations"] == sb["iterations"] == sc["iterations"] == sd["iterations"]
 
 
 def test_warm_start_and_limits(ctx, dev):
