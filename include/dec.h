@@ -208,6 +208,19 @@ int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* 
                                     double* q_in, double* q_out, double* energy,
                                     double* edge_flux_out);
 
+/* ---- cracking (Section 3, deterministic cracking process) --------------
+ * The face with the largest heat-flux density: over the edges e with
+ * eligible[e] != 0 (eligible [E] uint8 device, or NULL for every edge whose
+ * dual cell has nonzero area and whose *1_e is not zero, i.e. the faces not
+ * cracked yet), the largest |*1_e (T_hi - T_lo)| / |*e| for the solution
+ * T [V] float64 device, |*e| the edge's dual area.  Ties go to the smallest
+ * edge id.  *edge_out (host) receives the edge, -1 when no eligible edge has
+ * a finite density; *density_out (host, NULL ok) its density.  A crack is
+ * then a zero in the conductivity given to dec_hodge1.  Needs dec_hodge1.
+ * Synchronises the stream. */
+int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int64_t* edge_out,
+                      double* density_out);
+
 /* ---- serving: many solves, batched on the device ----------------------
  * A server admits requests (one full problem each: mesh, conductivity,
  * cracks, boundary data) while the HBM budget allows, runs their setup on a

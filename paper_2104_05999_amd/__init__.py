@@ -231,6 +231,15 @@ class Mesh:
         k, qi, qo, en = (v.value for v in vals)
         return {"k_eff": k, "q_in": qi, "q_out": qo, "energy": en, "edge_flux": ef}
 
+    def max_flux_edge(self, T, eligible=None):
+        """(edge, density) of the face with the largest heat-flux density (-1 when none)."""
+        e, d = ctypes.c_int64(), ctypes.c_double()
+        rc = self.lib.dec_max_flux_edge(self.handle, _ptr(T, torch.float64, self.V, "T"),
+                                        _ptr(eligible, torch.uint8, self.E, "eligible"), ctypes.byref(e),
+                                        ctypes.byref(d))
+        self.ctx.check(rc, "dec_max_flux_edge")
+        return e.value, d.value
+
 
 class Server:
     """dec_server: batched solves of many requests, admitted by HBM budget.

@@ -112,6 +112,7 @@ SIGNATURES = {
     "dec_get_fsai": (c_int, [vp, i64p, vp, vp, vp]),
     "dec_flux_effective_conductivity": (c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 dp, dp, dp, dp, vp]),
+    "dec_max_flux_edge": (c_int, [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), dp]),
     "dec_server_opts_default": (c_int, [ctypes.POINTER(ServerOpts)]),
     "dec_server_create": (c_int, [vp, ctypes.c_size_t, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]),
     "dec_server_submit": (c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),

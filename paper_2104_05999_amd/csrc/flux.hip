@@ -7,6 +7,9 @@
 // and the dissipated energy E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at
 // the exact solution; k_eff = E length / (area dT^2).  Deterministic block
 // partials.
+#include <climits>
+#include <cmath>
+
 #include "solver.h"
 
 namespace {
@@ -74,7 +77,117 @@ __global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, int64_t E, const int3
     }
 }
 
+// Largest heat-flux density over the eligible faces (Section 3, deterministic
+// cracking): density_e = |*1_e (T_hi - T_lo)| / |*e| with |*e| = geo_e |e|
+// the dual area.  Pairs (density, edge) are ordered by density, then by the
+// smaller edge id; that order is total, so the block partials and their fold
+// give the same pair whatever the schedule.
+__device__ __forceinline__ bool flux_better(double v, int64_t e, double bv, int64_t be) {
+    return v > bv || (v == bv && e < be);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_max_flux_partial(int64_t E, const int32_t* __restrict__ edges,
+                                                            const double* __restrict__ xyz,
+                                                            const double* __restrict__ geo,
+                                                            const double* __restrict__ star1,
+                                                            const double* __restrict__ T,
+                                                            const uint8_t* __restrict__ eligible,
+                                                            double* __restrict__ pv, int64_t* __restrict__ pe) {
+    __shared__ double sv[BLOCK];
+    __shared__ int64_t se[BLOCK];
+    double bv = -1.0;
+    int64_t be = INT64_MAX;
+    RANGE_LOOP(e, E) {
+        const double g = geo[e], s1 = star1[e];
+        if (eligible ? eligible[e] == 0 : (g == 0.0 || s1 == 0.0)) continue;
+        const int32_t lo = edges[2 * e], hi = edges[2 * e + 1];
+        const double dx = xyz[3 * (int64_t)hi] - xyz[3 * (int64_t)lo];
+        const double dy = xyz[3 * (int64_t)hi + 1] - xyz[3 * (int64_t)lo + 1];
+        const double dz = xyz[3 * (int64_t)hi + 2] - xyz[3 * (int64_t)lo + 2];
+        const double area = fabs(g * sqrt((dx * dx + dy * dy) + dz * dz));
+        const double v = fabs(s1 * (T[hi] - T[lo])) / area;
+        if (!(v >= 0.0) || isinf(v)) continue;  // no face (zero area) or a non-finite solution
+        if (flux_better(v, e, bv, be)) {
+            bv = v;
+            be = e;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    se[threadIdx.x] = be;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w && flux_better(sv[threadIdx.x + w], se[threadIdx.x + w], sv[threadIdx.x], se[threadIdx.x])) {
+            sv[threadIdx.x] = sv[threadIdx.x + w];
+            se[threadIdx.x] = se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pv[blockIdx.x] = sv[0];
+        pe[blockIdx.x] = se[0];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_max_flux_final(int nb, const double* __restrict__ pv,
+                                                          const int64_t* __restrict__ pe, double* __restrict__ out_v,
+                                                          int64_t* __restrict__ out_e) {
+    __shared__ double sv[BLOCK];
+    __shared__ int64_t se[BLOCK];
+    double bv = -1.0;
+    int64_t be = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+        if (flux_better(pv[b], pe[b], bv, be)) {
+            bv = pv[b];
+            be = pe[b];
+        }
+    sv[threadIdx.x] = bv;
+    se[threadIdx.x] = be;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w && flux_better(sv[threadIdx.x + w], se[threadIdx.x + w], sv[threadIdx.x], se[threadIdx.x])) {
+            sv[threadIdx.x] = sv[threadIdx.x + w];
+            se[threadIdx.x] = se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out_v[0] = sv[0];
+        out_e[0] = se[0] == INT64_MAX ? -1 : se[0];
+    }
+}
+
 }  // namespace
+
+extern "C" int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int64_t* edge_out,
+                                 double* density_out) {
+    if (!m || !T || !edge_out) return DEC_EINVAL;
+    dec_ctx* ctx = m->ctx;
+    try {
+        DEC_REQUIRE(m->star_ready && m->geo_ready && m->xyz.p, DEC_ESTATE, "max flux edge needs dec_hodge1 first");
+        ctx->set_device();
+        const unsigned G = grid_xcd(m->E);
+        DBuf<double> pv, ov;
+        DBuf<int64_t> pe, oe;
+        pv.alloc(ctx, G);
+        pe.alloc(ctx, G);
+        ov.alloc(ctx, 1);
+        oe.alloc(ctx, 1);
+        hipLaunchKernelGGL(k_max_flux_partial, dim3(G), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p, m->xyz.p,
+                           m->geo.p, m->star1.p, T, eligible, pv.p, pe.p);
+        hipLaunchKernelGGL(k_max_flux_final, dim3(1), dim3(BLOCK), 0, ctx->stream, (int)G, pv.p, pe.p, ov.p, oe.p);
+        HIP_CHECK(hipGetLastError());
+        int64_t e = 0;
+        std::memcpy(&e, ctx->readback(oe.p, sizeof(int64_t)), sizeof(int64_t));
+        double v = 0.0;
+        std::memcpy(&v, ctx->readback(ov.p, sizeof(double)), sizeof(double));
+        *edge_out = e;
+        if (density_out) *density_out = e >= 0 ? v : NAN;
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}
 
 extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* side, double length,
                                                double area, double dT, double* k_eff, double* q_in, double* q_out,

@@ -1,0 +1,122 @@
+"""Cracking processes (Section 3) on the GPU against the oracle.
+
+The largest-flux-density face must be a valid arg max of the oracle's flux
+densities (several faces may tie up to rounding; ties go to the smallest edge
+id on both sides, so away from ties the edges agree exactly).  Along a path,
+both sides crack the same face, and k_eff after every crack agrees to 1e-9 of
+the uncracked value.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from oracle import cracking as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    import paper_2104_05999_amd as dec
+    c = dec.Context(dev)
+    yield c
+    c.close()
+
+
+def _setup(ctx, dev, n, sigma, seed):
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, side = W.x_sides(n)
+    E = W.kuhn_counts(n)["E"]
+    kappa = W.lognormal_kappa(E, sigma, seed) if sigma > 0 else np.ones(E)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    m = ctx.mesh(t(xyz), t(tets))
+    sysm = C.CrackingSystem(xyz, tets, kappa, bt, bv, side)
+    return m, sysm, t(kappa), t(bt), t(bv), t(side)
+
+
+def _gpu_solve(m, kappa, bt, bv, side, T=None):
+    m.hodge1(kappa, want_cut=False, want_star=False)
+    m.assemble()
+    m.apply_bc(bt, bv, want_rhs=False)
+    T, st, rc = m.solve(T=T, tol=1e-13, warm_start=T is not None, check=False)
+    assert rc == 0, st
+    return T, m.flux(T, side)
+
+
+def _valid_argmax(e, dens, eligible, rel=1e-9):
+    ok = eligible & ~np.isnan(dens)
+    return bool(ok[e]) and dens[e] >= dens[ok].max() * (1.0 - rel)
+
+
+def test_max_flux_edge_matches_oracle(ctx, dev):
+    m, s, kappa, bt, bv, side = _setup(ctx, dev, 6, 1.0, 3)
+    try:
+        T, _ = _gpu_solve(m, kappa, bt, bv, side)
+        Th = T.cpu().numpy()
+        dens = C.flux_density(Th, s.edges, s.star1, s.area)
+        faces = C.faces(s.area) & (s.star1 != 0)
+        e, d = m.max_flux_edge(T)
+        eo, do = C.max_flux_edge(Th, s.edges, s.star1, s.area)
+        assert e == eo and abs(d - do) <= 1e-13 * do
+        # an explicit candidate set, and a temperature field with no ties at all
+        rng = np.random.Generator(np.random.PCG64(8))
+        elig = faces & (rng.random(len(faces)) < 0.3)
+        e2, _ = m.max_flux_edge(T, torch.as_tensor(elig.astype(np.uint8), device=dev))
+        assert e2 == C.max_flux_edge(Th, s.edges, s.star1, s.area, eligible=elig)[0]
+        Tr = rng.random(s.V)
+        e3, d3 = m.max_flux_edge(torch.as_tensor(Tr, device=dev))
+        e3o, d3o = C.max_flux_edge(Tr, s.edges, s.star1, s.area)
+        assert e3 == e3o and abs(d3 - d3o) <= 1e-13 * d3o
+        assert _valid_argmax(e, dens, faces)
+        assert m.max_flux_edge(T, torch.zeros(m.E, dtype=torch.uint8, device=dev))[0] == -1
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("n,sigma", [(3, 0.0), (5, 1.0)])
+def test_deterministic_process_against_oracle(ctx, dev, n, sigma):
+    m, s, kappa, bt, bv, side = _setup(ctx, dev, n, sigma, 5)
+    try:
+        T, f = _gpu_solve(m, kappa, bt, bv, side)
+        To, fo = s.solve()
+        k0 = fo["k_eff"]
+        steps = 0
+        while fo["k_eff"] > C.ZERO_REL * k0 and steps < 60:
+            assert abs(f["k_eff"] - fo["k_eff"]) <= 1e-9 * k0, steps
+            e, _ = m.max_flux_edge(T)
+            dens = C.flux_density(To, s.edges, s.star1, s.area)
+            assert _valid_argmax(e, dens, C.faces(s.area) & (s.star1 != 0)), steps
+            kappa[e] = 0.0
+            s.crack(e)
+            T, f = _gpu_solve(m, kappa, bt, bv, side, T)
+            To, fo = s.solve()
+            steps += 1
+        assert abs(f["k_eff"] - fo["k_eff"]) <= 1e-9 * k0
+        if sigma == 0.0:  # homogeneous: at least one full cross-section, then no conduction
+            assert steps >= (n + 1) ** 2 and f["k_eff"] <= 1e-9 * k0
+    finally:
+        m.close()
+
+
+def test_stochastic_path_against_oracle(ctx, dev):
+    n = 4
+    m, s, kappa, bt, bv, side = _setup(ctx, dev, n, 0.5, 6)
+    try:
+        rng = np.random.Generator(np.random.PCG64(21))
+        order = rng.permutation(np.flatnonzero(C.faces(s.area)))[:40]
+        T, f = _gpu_solve(m, kappa, bt, bv, side)
+        _, fo = s.solve()
+        k0 = fo["k_eff"]
+        ks = [f["k_eff"]]
+        for e in order:
+            kappa[int(e)] = 0.0
+            s.crack(int(e))
+            T, f = _gpu_solve(m, kappa, bt, bv, side, T)
+            _, fo = s.solve()
+            assert abs(f["k_eff"] - fo["k_eff"]) <= 1e-9 * k0
+            ks.append(f["k_eff"])
+        assert all(a >= b - 1e-12 * k0 for a, b in zip(ks, ks[1:]))
+    finally:
+        m.close()
