@@ -295,6 +295,68 @@ def crack_growth(ctx, dev, n=256, steps=51, n_discs=1000, seed=4):
     return out
 
 
+def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
+    """Section 3's cracking processes on homogeneous Kuhn cubes: the deterministic one (crack the
+    face of largest flux density) on n_det^3, and `paths` Monte Carlo paths (faces in seeded random
+    orders) on n_mc^3, each until the domain stops conducting (k_eff <= 1e-12 of its start).
+    Every step: conductivity with the new zero, *1, assembly, boundary data, a warm-started FP64
+    solve to 1e-10, flux (and, deterministic, the largest-flux-density face)."""
+    import torch
+
+    def run(n, order=None, max_steps=100000):
+        xyz, tets = W.kuhn_cube(n, device=dev)
+        bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
+        mesh = ctx.mesh(xyz, tets)
+        kappa = torch.ones(mesh.E, dtype=torch.float64, device=dev)
+        _, star = mesh.hodge1(kappa, want_cut=False)
+        n_faces = int((star != 0).sum())
+        T, ks, steps = None, [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            mesh.hodge1(kappa, want_cut=False, want_star=False)
+            mesh.assemble()
+            mesh.apply_bc(bt, bv, want_rhs=False)
+            T, st, rc = mesh.solve(T=T, tol=1e-10, warm_start=T is not None, check=False)
+            k = mesh.flux(T, side)["k_eff"]
+            ks.append(k)
+            if rc != 0 or k <= 1e-12 * ks[0] or steps >= max_steps:
+                break
+            if order is None:
+                e, _ = mesh.max_flux_edge(T)
+            else:
+                e = int(order[steps]) if steps < len(order) else -1
+            if e < 0:
+                break
+            kappa[e] = 0.0
+            steps += 1
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        mesh.close()
+        print(f"[bench] cracking n={n} {'deterministic' if order is None else 'stochastic'}: {steps} cracks, "
+              f"k_eff {ks[0]:.6f} -> {ks[-1]:.3e}, {sec:.2f} s", file=sys.stderr, flush=True)
+        return {"steps": steps, "faces": n_faces, "D_n_at_separation": steps / n_faces, "seconds": round(sec, 3),
+                "steps_per_sec": round((steps + 1) / sec, 1), "status": rc,
+                "k_eff_curve": [round(ks[i], 6) for i in range(0, len(ks), max(1, len(ks) // 40))]}
+
+    out = {"deterministic": {"workload": f"kuhn{n_det}_homogeneous", **run(n_det)}}
+    xyz, tets = W.kuhn_cube(n_mc)
+    probe = ctx.mesh(torch.as_tensor(xyz, device=dev), torch.as_tensor(tets, device=dev))
+    _, star = probe.hodge1(torch.ones(probe.E, dtype=torch.float64, device=dev), want_cut=False)
+    face_ids = torch.nonzero(star != 0).flatten().cpu().numpy()
+    probe.close()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mc = [run(n_mc, order=rng.permutation(face_ids)) for _ in range(paths)]
+    dn = [p["D_n_at_separation"] for p in mc]
+    out["stochastic"] = {"workload": f"kuhn{n_mc}_homogeneous_{paths}paths_seed{seed}", "paths": paths,
+                         "D_n_at_separation": {"mean": round(float(np.mean(dn)), 4), "min": round(min(dn), 4),
+                                               "max": round(max(dn), 4)},
+                         "steps": sum(p["steps"] for p in mc), "seconds": round(sum(p["seconds"] for p in mc), 3),
+                         "steps_per_sec": round(sum(p["steps"] + 1 for p in mc) / sum(p["seconds"] for p in mc), 1),
+                         "k_eff_curve_path0": mc[0]["k_eff_curve"]}
+    return out
+
+
 def cpu_baseline(n=80):
     """The oracle, single-threaded, on the full path of a smaller instance of the same recipe."""
     from threadpoolctl import threadpool_limits
@@ -342,6 +404,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--serve-requests", type=int, default=512, help="serving stream length (0: skip)")
+    ap.add_argument("--cracking", action="store_true",
+                    help="instead of the default line: the deterministic and Monte Carlo cracking processes")
     ap.add_argument("--growth-n", type=int, default=256)
     ap.add_argument("--growth-steps", type=int, default=51)
     ap.add_argument("--crack-growth", action="store_true",
@@ -358,6 +422,10 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = dec.Context(dev)
+    if args.cracking:
+        print(json.dumps({"metric": "cracking processes: k_eff vs damage D_n, steps/s", "n_gpus": 1,
+                          "data": "synthetic", **cracking_processes(ctx, dev)}))
+        return
     if args.crack_growth:
         print(json.dumps({"metric": "crack growth k_eff(step), mixed vs FP64 wall time", "n_gpus": 1,
                           "data": "synthetic", **crack_growth(ctx, dev, n=args.growth_n, steps=args.growth_steps)}))
