@@ -25,6 +25,7 @@ from .laplacian import (assemble, isolated_components, apply_bc, lumped_vertex_v
 from .krylov import pcg, fsai_factor, fsai_pattern, iterative_refinement, PCGResult
 from .flux import flux_effective_conductivity
 from .cracking import (flux_density, max_flux_edge, CrackingSystem, cracking_process)
+from . import dual
 
 __all__ = [
     "LOCAL_EDGES", "edges_of", "tet_edge_ids", "faces_of", "d0_matrix", "d1_matrix",
@@ -36,4 +37,5 @@ __all__ = [
     "pcg", "fsai_factor", "fsai_pattern", "iterative_refinement", "PCGResult",
     "flux_effective_conductivity",
     "flux_density", "max_flux_edge", "CrackingSystem", "cracking_process",
+    "dual",
 ]

@@ -1,0 +1,96 @@
+"""Pins of the oracle of the paper's own unknowns (temperature on the tets, flux through the
+triangles; Section 2.3, eq. 11-13; the 1e-8 Hodge limiter of Section 3.1).  CPU only."""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import workloads as W
+from oracle import dual as D
+
+
+def _kuhn(n):
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, side = W.x_sides(n)
+    return xyz, tets, bt, bv, side
+
+
+def test_faces_by_owner():
+    for n in (1, 2, 3):
+        xyz, tets, *_ = _kuhn(n)
+        t1, k1, t2, k2, verts = D.faces_by_owner(tets)
+        assert len(t1) == W.kuhn_counts(n)["F"] and int((t2 < 0).sum()) == 12 * n * n
+        inner = t2 >= 0
+        assert (t1[inner] < t2[inner]).all()
+        for f in np.flatnonzero(inner)[:50]:
+            a = set(tets[t1[f]]) - {tets[t1[f], k1[f]]}
+            b = set(tets[t2[f]]) - {tets[t2[f], k2[f]]}
+            assert a == b == set(verts[f])
+        assert sorted(zip(t1, k1)) == list(zip(t1, k1))  # owner order
+
+
+def test_kuhn_dual_edge_lengths_and_the_limited_faces():
+    """Kuhn cubes: the six tets of a cube share its centre as circumcentre, so exactly the 6 n^3
+    faces inside the cubes have zero Voronoi length (and are limited); the others measure the
+    lattice spacing h between cube centres, h/2 from a cube centre to a boundary face."""
+    for n in (2, 3, 5):
+        xyz, tets, bt, bv, side = _kuhn(n)
+        s = D.dual_system(xyz, tets, bt, bv, side)
+        h, area, t2 = s["geo"]["h"], s["geo"]["area"], s["faces"][2]
+        limited = h / area < D.LIMITER
+        assert limited.sum() == 6 * n ** 3 and np.abs(h[limited]).max() < 1e-14
+        assert np.allclose(h[~limited & (t2 >= 0)], 1.0 / n, rtol=1e-12)
+        assert np.allclose(h[t2 < 0], 0.5 / n, rtol=1e-12)
+        assert np.array_equal(s["geo"]["star"][limited], np.full(limited.sum(), D.LIMITER))
+
+
+def test_schur_complement_of_the_mixed_system():
+    """Eliminating the face fluxes from eq. 11-13 (the (1,1) block is diagonal) gives exactly
+    the tet operator and right-hand side: S = -L, r = -b (jittered mesh, lognormal
+    conductivity, cracks, Dirichlet and Neumann faces, limited entries)."""
+    n = 3
+    xyz, tets, bt, bv, side = _kuhn(n)
+    xj = W.jitter_interior(xyz, n, 0.2, 3)
+    cr = W.penny_cracks(6, 2, 0.1, 0.3)
+    F = W.kuhn_counts(n)["F"]
+    kap = np.random.Generator(np.random.PCG64(1)).lognormal(0.0, 1.0, F)
+    K, rhs, s = D.mixed_system(xj, tets, bt, bv, side, kappa=kap, cracks=cr)
+    assert (s["kappa"] == 0).any() and (s["geo"]["h"] < 0).any()
+    K = K.tocsr()
+    A, B, C = K[:F, :F], K[:F, F:], K[F:, F:]
+    Ainv = sp.diags(1.0 / A.diagonal())
+    S = (C - B.T @ Ainv @ B).toarray()
+    L = s["L"].toarray()
+    assert np.abs(S + L).max() <= 1e-14 * np.abs(L).max()
+    assert np.abs(rhs[F:] - B.T @ (Ainv @ rhs[:F]) + s["b"]).max() <= 1e-14 * np.abs(s["b"]).max()
+    assert np.allclose(L, L.T, rtol=0, atol=1e-15 * np.abs(L).max())
+
+
+def test_limiter_sets_the_error_of_the_linear_solution():
+    """Homogeneous Kuhn cube: with the limited Voronoi lengths the saddle system's solution
+    deviates from the exact linear field by an amount proportional to the limit (the paper's
+    non-machine-zero error), and k_eff = 1 up to the same order."""
+    n = 3
+    xyz, tets, bt, bv, side = _kuhn(n)
+    errs = []
+    for lim in (1e-6, 1e-8, 1e-10):
+        K, rhs, s = D.mixed_system(xyz, tets, bt, bv, side, limiter=lim)
+        T = spla.spsolve(K.tocsc(), rhs)[len(s["W"]):]
+        err = np.abs(T - (1.0 - s["geo"]["ct"][:, 0])).max()
+        errs.append(err)
+        assert 0.05 * lim < err < 0.5 * lim
+        assert abs(D.flux(T, s)["k_eff"] - 1.0) < 3.0 * lim
+    assert 80 < errs[0] / errs[1] < 120 and 80 < errs[1] / errs[2] < 120
+
+
+def test_energy_identity_and_cracks_lower_the_conductivity():
+    n = 4
+    xyz, tets, bt, bv, side = _kuhn(n)
+    xj = W.jitter_interior(xyz, n, 0.15, 5)
+    K, rhs, s = D.mixed_system(xj, tets, bt, bv, side)
+    T = spla.spsolve(K.tocsc(), rhs)[len(s["W"]):]
+    f = D.flux(T, s)
+    assert abs(f["q_in"] - f["energy"]) < 1e-6 * f["energy"] and abs(f["q_out"] - f["energy"]) < 1e-6 * f["energy"]
+    K2, rhs2, s2 = D.mixed_system(xj, tets, bt, bv, side, cracks=W.penny_cracks(5, 4, 0.15, 0.3))
+    T2 = spla.spsolve(K2.tocsc(), rhs2)[len(s2["W"]):]
+    assert (s2["kappa"] == 0).any() and D.flux(T2, s2)["k_eff"] < f["k_eff"]
