@@ -138,44 +138,66 @@ int dec_apply_bc(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
 #define DEC_PREC_MIXED 1  /* FP32 PCG inner solves inside FP64 iterative refinement */
 #define DEC_PRECOND_JACOBI 0
 #define DEC_PRECOND_FSAI 1 /* factored sparse approximate inverse, pattern lower(L)  */
+#define DEC_PRECOND_BLOCK 2 /* tet systems only: block Jacobi, the exact inverse of A on
+                               each cluster of <= 16 tets joined by limited faces
+                               (conducting interior faces whose *_f the limiter set),
+                               1 / a_ii on every other tet                          */
 #define DEC_FMT_AUTO 0
 #define DEC_FMT_CSR 1
 #define DEC_FMT_SELL 2
+#define DEC_NORM_RESIDUAL 0 /* stop on ||b - A T||_2 <= tol ||b||_2                      */
+#define DEC_NORM_ENERGY 1   /* FP64 only: stop when the error in the A-norm,
+                               ||T* - T||_A <= tol ||T*||_A, by the Hestenes-Stiefel
+                               estimate: PCG step j removes alpha_j rho_j from
+                               ||T* - T||_A^2, so the sum over a window of 16 steps
+                               bounds the error of the iterate 15 steps back from
+                               below, and ||T*||_A^2 = T0.(b + r0) + all steps.  For
+                               systems whose weights span many orders (the tet
+                               system's limited faces): there rounding T to FP64
+                               alone leaves ||b - A T||_2 near eps ||A|| ||T||, far
+                               above a useful tolerance, while CG keeps reducing the
+                               A-norm error                                          */
 
 typedef struct dec_solve_opts {
     int32_t precision;           /* DEC_PREC_*                                     */
     int32_t precond;             /* DEC_PRECOND_*                                  */
-    double tol;                  /* stop at ||b - A T||_2 <= tol ||b||_2 (FP64)    */
+    double tol;                  /* stop at ||b - A T|| <= tol ||b|| (FP64), norm below */
     double inner_tol;            /* mixed: relative tolerance of each FP32 solve   */
     int32_t adaptive_final_inner;/* mixed: inner tol max(inner_tol, 0.5 tol||b||/||r||) */
     int32_t warm_start;          /* T holds the initial guess (Dirichlet values are imposed) */
-    int64_t max_iters;           /* cap on PCG iterations (FP64) / inner iterations (mixed) */
+    int64_t max_iters;           /* cap on PCG iterations (FP64) / inner iterations (mixed;
+                                    one FP32 solve gets at most max_iters / 8)      */
     int32_t format;              /* DEC_FMT_* for the SpMV                         */
     int32_t chunk;               /* iterations per launch batch (0: default)       */
     int32_t use_graph;           /* capture each batch in a hipGraph               */
     int32_t profile;             /* 0: off; k > 0: time SpMV launches with HIP events,
                                     every k-th one of each launch batch, the batch's
                                     launches k-1, 2k-1, ... (1: all)               */
+    int32_t norm;                /* DEC_NORM_* of the stopping test                */
 } dec_solve_opts;
 
 typedef struct dec_solve_stats {
     int64_t iterations;       /* FP64: PCG iterations. mixed: sum of inner iterations    */
     int64_t outer_iterations; /* mixed: refinement steps (FP64 residuals)                */
     int64_t restarts;         /* FP64: restarts from the true residual                    */
-    int32_t fp64_fallback;    /* mixed: 1 when refinement stagnated and FP64 PCG finished */
+    int32_t fp64_fallback;    /* mixed: 1 when FP64 PCG finished: refinement stagnated (a
+                                 correction that raised the residual is undone first) or an
+                                 FP32 solve broke down or hit its cap (it is not applied)   */
     int32_t status;           /* DEC_OK / DEC_ENOTCONV / DEC_EBREAKDOWN                   */
-    double rel_residual;      /* true FP64 ||b - A T|| / ||b|| at exit                     */
+    double rel_residual;      /* true FP64 ||b - A T|| / ||b|| at exit; with DEC_NORM_ENERGY
+                                 and DEC_OK, the final A-norm error estimate instead       */
     double solve_ms;          /* wall time of the call on the stream (HIP events)          */
     int64_t spmv_launches;    /* profile: SpMV launches timed                              */
     double spmv_ms;           /* profile: summed duration of those launches                */
     double spmv_bytes;        /* bytes one SpMV must move: CSR definition over the entries
                                  the product uses (nnz (s+4) + 4 (V+1) + 2 V s)            */
     int64_t spmv_nnz;         /* entries the product uses (full pattern or pruned)       */
+    double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
 } dec_solve_stats;
 
 /* Fill opts with the defaults: FP64, Jacobi, tol 1e-10, inner_tol 1e-5,
  * adaptive final inner tolerance on, cold start, max_iters 100000, auto
- * format, chunk 32, graphs on, profiling off. */
+ * format, chunk 32, graphs on, profiling off, plain residual norm. */
 int dec_solve_opts_default(dec_solve_opts* opts);
 /* Solve A T = b (after dec_apply_bc).  T [V] float64 device: initial guess
  * when opts->warm_start, solution on return.  stats (host) may be NULL.
@@ -220,6 +242,68 @@ int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* 
  * Synchronises the stream. */
 int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int64_t* edge_out,
                       double* density_out);
+
+/* ---- temperature on the tets, flux through the triangles ---------------
+ * The paper's own unknowns (Section 2.3, eq. 11-13): one temperature per tet
+ * (the Voronoi vertex at its circumcentre), one flux per triangle (the dual
+ * of a Voronoi edge).  The flux block (1/kappa) * is diagonal, so it is
+ * eliminated and the Schur complement on the tets is assembled: a face f
+ * between tets t1 and t2 couples them with W_f = kappa_f / *_f, a Dirichlet
+ * face adds W_f to its tet's diagonal and W_f T0_f to its right-hand side,
+ * insulated and cracked faces carry nothing.  *_f = max(h_f / |f|, limiter):
+ * h_f the signed length of the Voronoi edge through f (t1's circumcentre to
+ * t2's, or to the face's circumcentre on the boundary, positive along the
+ * normal out of t1), |f| the face area; the limiter is Section 3.1's (1e-8
+ * when limiter <= 0).
+ *
+ * Faces are numbered by owner tet (the lowest tet holding the face), then by
+ * local index (the tet's vertex opposite the face).  A boundary face is
+ * Dirichlet when its three vertices have bc_type 1, with T0 their mean
+ * bc_value, and inflow/outflow when all three vertices carry side 1/2.
+ * A face is cracked when its Voronoi edge crosses a disc (cracks as in
+ * dec_hodge1) or kappa_face is 0.
+ *
+ * m: a mesh from dec_build_topology.  kappa_face [F] float64 device (NULL
+ * for 1), cracks [n_cracks x 7] device, bc_type/bc_value/side [V] device
+ * (side NULL ok), all read during the call.  *dual_out receives a new mesh
+ * whose rows are the tets (V = T of m, F the faces), assembled and with its
+ * boundary data applied: dec_solve, dec_spmv, dec_get_csr, dec_get_fsai and
+ * dec_mesh_info apply to it; the vertex calls (dec_hodge1, dec_assemble,
+ * dec_apply_bc, dec_flux_effective_conductivity, dec_max_flux_edge) return
+ * DEC_ESTATE.  Tets in parts joined to no Dirichlet face over conducting
+ * faces are pinned to 0 (*n_pinned_out, host, NULL ok).  The limiter puts
+ * weights up to kappa / limiter beside weights of order |f| / h, so the
+ * solver's (sliced-ELL) product of this system takes the difference form
+ * (L x)_i = e_i x_i + sum_j L_ij (x_j - x_i), with e_i the exact sum of the
+ * tet's Dirichlet-face weights (1 on pinned rows): the diagonal never cancels
+ * against the limited couplings, so residuals keep full FP64 (and FP32)
+ * relative accuracy; dec_spmv with DEC_FMT_CSR applies the stored matrix
+ * as is.  Free it with
+ * dec_mesh_destroy; it does not refer to m.  Synchronises the stream.
+ * DEC_ETOPO if a face is shared by more than two tets. */
+int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, const double* cracks,
+                   const int8_t* bc_type, const double* bc_value, const int8_t* side, double limiter,
+                   dec_mesh** dual_out, int64_t* n_pinned_out);
+
+/* Counts of a tet system (host outputs, each NULL ok): faces, limited faces,
+ * clusters inverted as blocks by DEC_PRECOND_BLOCK, the largest of them. */
+int dec_dual_info(const dec_mesh* d, int64_t* n_faces, int64_t* n_limited, int64_t* n_blocks,
+                  int64_t* max_block);
+
+/* Face records of a tet system, device outputs (each NULL ok):
+ * face_tets [F x 2] int32 (t1, t2 or -1), face_local [F x 2] int32 (local
+ * index of the face in t1 and t2, or -1), weight [F] float64 (W_f, 0 on
+ * insulated and cracked faces), cut [F] uint8.  Stream-ordered. */
+int dec_dual_faces(const dec_mesh* d, int32_t* face_tets, int32_t* face_local, double* weight,
+                   uint8_t* cut);
+
+/* Flux of a tet solution T [T] float64 device: energy
+ * E = sum_f W_f (T_t1 - T_t2)^2 over interior faces plus W_f (T_t1 - T0_f)^2
+ * over Dirichlet faces, k_eff = E length / (area dT^2), Q_in = sum of
+ * W_f (T0_f - T_t1) over inflow faces, Q_out = sum of W_f (T_t1 - T0_f) over
+ * outflow faces.  Host outputs (NULL ok).  Synchronises the stream. */
+int dec_dual_flux(dec_mesh* d, const double* T, double length, double area, double dT, double* k_eff,
+                  double* q_in, double* q_out, double* energy);
 
 /* ---- serving: many solves, batched on the device ----------------------
  * A server admits requests (one full problem each: mesh, conductivity,

@@ -15,11 +15,13 @@ import weakref
 import torch
 
 from . import _lib
-from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_PREC_FP64, DEC_PREC_MIXED, DEC_PRECOND_FSAI,
-                   DEC_PRECOND_JACOBI, SolveOpts, SolveStats)
+from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_NORM_ENERGY, DEC_NORM_RESIDUAL, DEC_PREC_FP64,
+                   DEC_PREC_MIXED, DEC_PRECOND_BLOCK, DEC_PRECOND_FSAI, DEC_PRECOND_JACOBI, SolveOpts,
+                   SolveStats)
 
-__all__ = ["DecError", "Context", "Mesh", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
-           "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL"]
+__all__ = ["DecError", "Context", "Mesh", "DualMesh", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
+           "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL",
+           "DEC_NORM_RESIDUAL", "DEC_NORM_ENERGY", "DEC_PRECOND_BLOCK"]
 
 
 _LIVE = weakref.WeakSet()
@@ -123,10 +125,13 @@ class Mesh:
         rc = self.lib.dec_build_topology(ctx.handle, V, _ptr(xyz, torch.float64, 3 * V, "xyz"), T,
                                          _ptr(tets, torch.int32, 4 * T, "tets"), ctypes.byref(h))
         ctx.check(rc, "dec_build_topology")
+        self._adopt(h)
+
+    def _adopt(self, h):
         self.handle = h
-        ctx._children.add(self)
+        self.ctx._children.add(self)
         vals = [ctypes.c_int64() for _ in range(6)]
-        ctx.check(self.lib.dec_mesh_info(h, *[ctypes.byref(v) for v in vals]), "dec_mesh_info")
+        self.ctx.check(self.lib.dec_mesh_info(h, *[ctypes.byref(v) for v in vals]), "dec_mesh_info")
         self.V, self.T, self.E, self.F, self.F_boundary, self.nnz = (v.value for v in vals)
 
     @property
@@ -239,6 +244,64 @@ class Mesh:
                                         ctypes.byref(d))
         self.ctx.check(rc, "dec_max_flux_edge")
         return e.value, d.value
+
+    def dual(self, bc_type, bc_value, side=None, kappa_face=None, cracks=None, limiter=0.0):
+        """The system of the paper's own unknowns (temperature per tet, flux per triangle) as a
+        DualMesh, assembled and with its boundary data applied; see dec_dual_build."""
+        return DualMesh(self, bc_type, bc_value, side, kappa_face, cracks, limiter)
+
+
+class DualMesh(Mesh):
+    """A dec_mesh whose rows are the tets of a mesh (dec_dual_build): solve, spmv, csr and fsai
+    apply as for vertex meshes; V is the tet count of the source mesh, F its face count."""
+
+    def __init__(self, mesh, bc_type, bc_value, side=None, kappa_face=None, cracks=None, limiter=0.0):
+        self.ctx = mesh.ctx
+        self.lib = mesh.lib
+        n = 0 if cracks is None else int(cracks.shape[0])
+        h = ctypes.c_void_p()
+        npin = ctypes.c_int64()
+        rc = self.lib.dec_dual_build(
+            mesh.handle, _ptr(kappa_face, torch.float64, mesh.F, "kappa_face"), n,
+            _ptr(cracks, torch.float64, 7 * n, "cracks") if n else None,
+            _ptr(bc_type, torch.int8, mesh.V, "bc_type"), _ptr(bc_value, torch.float64, mesh.V, "bc_value"),
+            _ptr(side, torch.int8, mesh.V, "side"), float(limiter), ctypes.byref(h), ctypes.byref(npin))
+        self.ctx.check(rc, "dec_dual_build")
+        self._adopt(h)
+        self.n_pinned = npin.value
+
+    def solve(self, T=None, opts=None, check=True, **kw):
+        """As Mesh.solve, with the block-Jacobi preconditioner and the A-norm error test unless
+        `precond` / `norm` are given: limited faces couple their tets with kappa / limiter, which
+        leaves the plain residual of any FP64 vector near eps * kappa / limiter."""
+        if opts is None:
+            kw.setdefault("precond", DEC_PRECOND_BLOCK)
+            kw.setdefault("norm", DEC_NORM_ENERGY)
+        return super().solve(T, opts, check, **kw)
+
+    def info(self):
+        """dict(faces, limited, blocks, max_block) of dec_dual_info."""
+        vals = [ctypes.c_int64() for _ in range(4)]
+        self.ctx.check(self.lib.dec_dual_info(self.handle, *[ctypes.byref(v) for v in vals]), "dec_dual_info")
+        return dict(zip(("faces", "limited", "blocks", "max_block"), (v.value for v in vals)))
+
+    def faces(self):
+        """Device tensors: face_tets [F,2] i32, face_local [F,2] i32, weight [F] f64, cut [F] u8."""
+        ft = torch.empty((self.F, 2), dtype=torch.int32, device=self.dev)
+        fl = torch.empty((self.F, 2), dtype=torch.int32, device=self.dev)
+        w = torch.empty(self.F, dtype=torch.float64, device=self.dev)
+        cut = torch.empty(self.F, dtype=torch.uint8, device=self.dev)
+        self.ctx.check(self.lib.dec_dual_faces(self.handle, _ptr(ft, torch.int32), _ptr(fl, torch.int32),
+                                               _ptr(w, torch.float64), _ptr(cut, torch.uint8)), "dec_dual_faces")
+        return ft, fl, w, cut
+
+    def flux(self, T, length=1.0, area=1.0, dT=1.0):
+        vals = [ctypes.c_double() for _ in range(4)]
+        rc = self.lib.dec_dual_flux(self.handle, _ptr(T, torch.float64, self.V, "T"), length, area, dT,
+                                    *[ctypes.byref(v) for v in vals])
+        self.ctx.check(rc, "dec_dual_flux")
+        k, qi, qo, en = (v.value for v in vals)
+        return {"k_eff": k, "q_in": qi, "q_out": qo, "energy": en}
 
 
 class Server:

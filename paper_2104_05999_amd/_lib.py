@@ -20,8 +20,9 @@ DEC_OK = 0
 STATUS = {0: "DEC_OK", -1: "DEC_EINVAL", -2: "DEC_ENOMEM", -3: "DEC_EHIP", -4: "DEC_ENOTCONV",
           -5: "DEC_EBREAKDOWN", -6: "DEC_ETOPO", -7: "DEC_EBUDGET", -8: "DEC_ESTATE", -9: "DEC_ECANCELED"}
 DEC_PREC_FP64, DEC_PREC_MIXED = 0, 1
-DEC_PRECOND_JACOBI, DEC_PRECOND_FSAI = 0, 1
+DEC_PRECOND_JACOBI, DEC_PRECOND_FSAI, DEC_PRECOND_BLOCK = 0, 1, 2
 DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL = 0, 1, 2
+DEC_NORM_RESIDUAL, DEC_NORM_ENERGY = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -40,6 +41,7 @@ class SolveOpts(ctypes.Structure):
         ("chunk", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("profile", ctypes.c_int32),
+        ("norm", ctypes.c_int32),
     ]
 
 
@@ -56,6 +58,7 @@ class SolveStats(ctypes.Structure):
         ("spmv_ms", ctypes.c_double),
         ("spmv_bytes", ctypes.c_double),
         ("spmv_nnz", ctypes.c_int64),
+        ("plain_residual", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -113,6 +116,11 @@ SIGNATURES = {
     "dec_flux_effective_conductivity": (c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                 dp, dp, dp, dp, vp]),
     "dec_max_flux_edge": (c_int, [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), dp]),
+    "dec_dual_build": (c_int, [vp, vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(vp),
+                               ctypes.POINTER(ctypes.c_int64)]),
+    "dec_dual_faces": (c_int, [vp, vp, vp, vp, vp]),
+    "dec_dual_info": (c_int, [vp] + [ctypes.POINTER(ctypes.c_int64)] * 4),
+    "dec_dual_flux": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]),
     "dec_server_opts_default": (c_int, [ctypes.POINTER(ServerOpts)]),
     "dec_server_create": (c_int, [vp, ctypes.c_size_t, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]),
     "dec_server_submit": (c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),

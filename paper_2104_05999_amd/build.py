@@ -29,6 +29,7 @@ SOURCES = {
     "fsai.hip": [],
     "flux.hip": [],
     "serve.hip": [],
+    "dual.hip": NO_CONTRACT,
 }
 
 COMMON = [

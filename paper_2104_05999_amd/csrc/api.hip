@@ -45,6 +45,8 @@ void* dec_ctx::readback(const void* dptr, size_t bytes) {
 dec_mesh::~dec_mesh() {
     if (solve) destroy_solve_cache(solve);
     solve = nullptr;
+    delete dual;
+    dual = nullptr;
     if (owner) owner->live_children -= 1;
 }
 

@@ -177,6 +177,7 @@ void assemble_device(dec_mesh* m) {
 extern "C" int dec_assemble(dec_mesh* m, uint32_t flags) {
     if (!m) return DEC_EINVAL;
     try {
+        DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_assemble is for meshes of vertex unknowns");
         DEC_REQUIRE((flags & ~DEC_ASM_FULL_PATTERN) == 0, DEC_EINVAL, "unknown assembly flags");
         m->ctx->set_device();
         const bool prune = !(flags & DEC_ASM_FULL_PATTERN);

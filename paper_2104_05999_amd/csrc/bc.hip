@@ -12,6 +12,7 @@
 //
 // Compiled without floating-point contraction (fixed operation order).
 #include "common.h"
+#include "uf.h"
 
 void refresh_sell_values(dec_mesh* m);
 
@@ -61,43 +62,11 @@ __global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const d
     }
 }
 
-// Connected components of the graph of edges with *1 != 0, by lock-free
-// union-find: the larger of two roots is hooked under the smaller with a
-// compare-and-swap, so parent[v] <= v always holds, every find ends, and the
-// root of a component is its smallest vertex (a label independent of
-// scheduling).  A failed swap means another thread hooked that root; the
-// loop then continues from the new root.  Finds halve the path they walk:
-// a vertex that is not a root is re-pointed to its grandparent, which is an
-// ancestor in the same tree (a non-root never becomes a root again, and the
-// swaps only ever change roots), so the halving races with nothing.
-__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t v) {
-    while (true) {
-        const int32_t p = __hip_atomic_load(parent + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (p == v) return v;
-        const int32_t gp = __hip_atomic_load(parent + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (gp == p) return p;
-        __hip_atomic_store(parent + v, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        v = gp;
-    }
-}
-
 __global__ void k_uf_hook(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ star1,
                           int32_t* parent) {
     GRID_STRIDE_LOOP(e, E) {
         if (star1[e] == 0.0) continue;
-        int32_t ra = uf_find(parent, edges[2 * e]);
-        int32_t rb = uf_find(parent, edges[2 * e + 1]);
-        while (ra != rb) {
-            if (ra > rb) {
-                const int32_t t = ra;
-                ra = rb;
-                rb = t;
-            }
-            const int32_t old = atomicCAS(parent + rb, rb, ra);
-            if (old == rb) break;
-            rb = uf_find(parent, old);
-            ra = uf_find(parent, ra);
-        }
+        uf_union(parent, edges[2 * e], edges[2 * e + 1]);
     }
 }
 
@@ -286,6 +255,7 @@ extern "C" int dec_apply_bc(dec_mesh* m, const int8_t* bc_type, const double* bc
                             int64_t* n_pinned_out, double* b_out) {
     if (!m) return DEC_EINVAL;
     try {
+        DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_apply_bc is for meshes of vertex unknowns");
         DEC_REQUIRE(bc_type && bc_value, DEC_EINVAL, "NULL bc_type or bc_value");
         m->ctx->set_device();
         apply_bc_device(m, bc_type, bc_value, neumann_f0);

@@ -125,6 +125,8 @@ struct SellMatrix {
     DBuf<int32_t> src;   // [entries]: CSR entry index, -1 for padding
     DBuf<double> val64;  // [entries]
     DBuf<float> val32;   // [entries]
+    DBuf<double> excess64;  // [V] row excess for the difference-form product (empty: plain form)
+    DBuf<float> excess32;   // [V]
 };
 
 // Lower-triangular FSAI factor G (CSR) and its transpose (CSR of G^T).
@@ -135,6 +137,22 @@ struct FsaiFactor {
     DBuf<double> g_val64, gt_val64;
     DBuf<float> g_val32, gt_val32;
     SellMatrix g_sell, gt_sell;  // sliced-ELL copies that the solver applies (same entry order per row)
+};
+
+// The paper's own unknowns: a system whose rows are the tets of a mesh, with
+// the face data its flux and queries need (see dual.hip).
+struct DualData {
+    int64_t F = 0;
+    DBuf<int32_t> t1, k1, t2, k2;  // [F] owner tet, local face index, other tet (-1), its index (-1)
+    DBuf<double> W;                // [F] kappa_f / *_f on interior and Dirichlet faces, else 0
+    DBuf<double> T0;               // [F] Dirichlet value (0 elsewhere)
+    DBuf<int8_t> kind;             // [F] 0 interior, 1 Dirichlet, 2 insulated boundary
+    DBuf<int8_t> side;             // [F] 1 inflow, 2 outflow, 0 other
+    DBuf<uint8_t> cut;             // [F] cut by a disc
+    DBuf<uint8_t> limited;         // [F] *_f set by the limiter
+    int64_t n_limited = 0;         // limited faces
+    int64_t n_blocks = 0;          // clusters of >= 2 tets inverted as one block
+    int64_t max_block = 0;         // largest such cluster
 };
 
 struct SolveCache;  // Krylov vectors, reduction scratch and captured graphs
@@ -185,6 +203,9 @@ struct dec_mesh {
 
     FsaiFactor fsai;
     SolveCache* solve = nullptr;
+    DualData* dual = nullptr;  // set for a system of tet unknowns (dec_dual_build)
+    SellMatrix blockinv;       // tet systems: inverse of the diagonal blocks over the
+                               // clusters of tets joined by limited faces (block Jacobi)
 
     ~dec_mesh();
 };

@@ -163,6 +163,7 @@ extern "C" int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* el
     if (!m || !T || !edge_out) return DEC_EINVAL;
     dec_ctx* ctx = m->ctx;
     try {
+        DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_max_flux_edge is for meshes of vertex unknowns");
         DEC_REQUIRE(m->star_ready && m->geo_ready && m->xyz.p, DEC_ESTATE, "max flux edge needs dec_hodge1 first");
         ctx->set_device();
         const unsigned G = grid_xcd(m->E);
@@ -195,6 +196,7 @@ extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, con
     if (!m || !T) return DEC_EINVAL;
     dec_ctx* ctx = m->ctx;
     try {
+        DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_flux_effective_conductivity is for meshes of vertex unknowns");
         DEC_REQUIRE(m->star_ready, DEC_ESTATE, "flux needs dec_hodge1 first");
         DEC_REQUIRE(area > 0.0 && length > 0.0 && dT != 0.0, DEC_EINVAL, "bad length/area/dT");
         ctx->set_device();

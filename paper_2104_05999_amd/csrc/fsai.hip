@@ -171,6 +171,9 @@ __global__ void k_csr_sell_fill(int64_t V, int64_t nslices, const int32_t* __res
     }
 }
 
+}  // namespace
+
+// Sliced-ELL copy of a CSR matrix (also used for the tet systems).
 void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, const int32_t* col, const double* v64,
                      const float* v32, SellMatrix& S) {
     hipStream_t s = ctx->stream;
@@ -189,8 +192,6 @@ void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, c
                        v64, v32, S.ptr.p, S.col.p, S.val64.p, S.val32.p);
     HIP_CHECK(hipGetLastError());
 }
-
-}  // namespace
 
 void fsai_setup(dec_mesh* m) {
     FsaiFactor& F = m->fsai;

@@ -356,6 +356,7 @@ extern "C" int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, co
     if (!m) return DEC_EINVAL;
     dec_ctx* ctx = m->ctx;
     try {
+        DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_hodge1 is for meshes of vertex unknowns");
         DEC_REQUIRE(n_cracks >= 0, DEC_EINVAL, "negative crack count");
         DEC_REQUIRE(n_cracks == 0 || cracks, DEC_EINVAL, "NULL crack array");
         ctx->set_device();

@@ -46,10 +46,34 @@ __global__ void k_norm2(int64_t V, const double* __restrict__ b, double* __restr
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
-__global__ void k_reset(PcgScalars* st, int64_t max_iter) {
+// partials of x.(b + r): the A-norm squared of x when r = b - A x
+__global__ void k_xbr(int64_t V, const double* __restrict__ x, const double* __restrict__ b,
+                      const double* __restrict__ r, double* __restrict__ partials) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) s += x[i] * (b[i] + r[i]);
+    const double bs = block_sum(s, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// energy-norm state: cum = sum of the partials, window cleared, rr_stop = tol^2
+__global__ void k_energy_start(const double* __restrict__ partials, int n, double tol2, PcgScalars* __restrict__ st) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    const double s = reduce_bcast(partials, n, lds);
+    if (threadIdx.x == 0) {
+        st->cum = s;
+        st->rr_stop = tol2;
+        for (int j = 0; j < ENERGY_DELAY; ++j) st->hist[j] = 0.0;
+    }
+}
+
+__global__ void k_reset(PcgScalars* st, int64_t max_iter, int32_t use_energy) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->iter = 0;
         st->max_iter = max_iter;
+        st->use_energy = use_energy;
         st->done = PCG_RUNNING;
         st->rho = st->pq = st->alpha = st->beta = 0.0;
     }
@@ -60,6 +84,7 @@ __global__ void k_reset(PcgScalars* st, int64_t max_iter) {
 //   FIN_RR:    rr = aux = sum(R_RR)
 //   FIN_START: rr = sum(R_RR), rho = sum(R_RZ), iteration 0; rr_stop =
 //              factor * rr when `relative`, else kept; done when rr <= rr_stop
+//              (energy-norm state: done only when rho is 0, x is the solution)
 __global__ void k_finalize(const double* __restrict__ partials, int P, int n_rr, int n_rz, int what, double factor,
                            int relative, PcgScalars* __restrict__ st) {
     __shared__ double lds[BLOCK / 64 + 1];
@@ -77,7 +102,8 @@ __global__ void k_finalize(const double* __restrict__ partials, int P, int n_rr,
         st->rho = rz;
         if (relative) st->rr_stop = factor * rr;
         st->iter = 0;
-        st->done = (rr <= st->rr_stop) ? PCG_CONVERGED : (isfinite(rz) ? PCG_RUNNING : PCG_BREAKDOWN);
+        const bool conv = st->use_energy ? rz == 0.0 : rr <= st->rr_stop;
+        st->done = conv ? PCG_CONVERGED : (isfinite(rz) ? PCG_RUNNING : PCG_BREAKDOWN);
     }
 }
 
@@ -164,6 +190,19 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
     }
 }
 
+// Energy-norm test of the iteration being closed (k = S->iter): the window of
+// the last ENERGY_DELAY terms alpha_j rho_j, this one included, against
+// tol^2 times cum (summed in slot order, as on the host).
+__device__ __forceinline__ bool energy_converged(const PcgScalars* S, double pq) {
+    const int64_t k = S->iter;
+    if (k + 1 < ENERGY_DELAY) return false;
+    const double term = S->rho * (S->rho / pq);
+    const int slot = static_cast<int>(k % ENERGY_DELAY);
+    double win = 0.0;
+    for (int j = 0; j < ENERGY_DELAY; ++j) win += j == slot ? term : S->hist[j];
+    return win <= S->rr_stop * (S->cum + term);
+}
+
 // Close the iteration: p.q as the update kernel folded it, fold r.r and r.z;
 // decide breakdown / convergence / iteration cap; x += alpha p (unless p.q
 // broke down), then p = z + beta p while running (z = D^-1 r for Jacobi);
@@ -202,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
     int done = PCG_RUNNING;
     if (!pq_ok || !isfinite(rr) || !isfinite(rz))
         done = PCG_BREAKDOWN;
-    else if (rr <= S->rr_stop)
+    else if (S->use_energy ? energy_converged(S, pq) : rr <= S->rr_stop)
         done = PCG_CONVERGED;
     else if (S->iter + 1 >= S->max_iter)
         done = PCG_MAXITER;
@@ -235,7 +274,14 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         N->pq = pq;
         N->iter = S->iter + (done == PCG_BREAKDOWN ? 0 : 1);
         N->max_iter = S->max_iter;
+        N->use_energy = S->use_energy;
         N->done = done;
+        if (S->use_energy) {
+            const double term = S->rho * (S->rho / pq);
+            N->cum = S->cum + term;
+            for (int j = 0; j < ENERGY_DELAY; ++j) N->hist[j] = S->hist[j];
+            N->hist[S->iter % ENERGY_DELAY] = term;
+        }
     }
 }
 
@@ -258,10 +304,8 @@ __global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgSca
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
-// x64 += ||r64|| * x32
-__global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __restrict__ x32,
-                          const PcgScalars* __restrict__ src) {
-    const double scale = sqrt(src->rr);
+// x64 += scale * x32 (scale = ||r64|| of the refinement step, or its negative to undo it)
+__global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __restrict__ x32, double scale) {
     GRID_STRIDE_LOOP(i, V) x64[i] = x64[i] + scale * static_cast<double>(x32[i]);
 }
 
@@ -270,6 +314,7 @@ template <class VT>
 struct Run {
     SellView<VT> A;
     SellView<VT> G, GT;  // FSAI factor and its transpose (sliced ELL)
+    SellView<VT> M;      // block-Jacobi inverse (tet systems)
     VT *x, *r, *p, *q, *z, *w;
     const VT* invd;
     PcgScalars* st;  // two parities
@@ -283,11 +328,18 @@ void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, con
                    const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
     const dim3 g(c->Gs), blk(BLOCK);
     const int32_t* done = st ? &st->done : nullptr;
-    if (ev_a)
+    if (A.excess) {
+        if (ev_a)
+            hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, true>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
+                                  part, done);
+        else
+            hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, true>), g, blk, 0, c->stream, A, x, y, b, part, done);
+    } else if (ev_a) {
         hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b, part,
                               done);
-    else
+    } else {
         hipLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, A, x, y, b, part, done);
+    }
 }
 
 template <class VT, int MODE, bool NT>
@@ -330,7 +382,7 @@ template <class VT>
 void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const VT* x, VT* y) {
     const int pi = prec_index<VT>();
     if (c->tuned[pi] || c->pinned_variant) return;
-    const std::array<int64_t, 4> shape{pi, A.V, A.nslices, entries};
+    const std::array<int64_t, 4> shape{pi + (A.excess ? 2 : 0), A.V, A.nslices, entries};
     auto known = c->ctx->spmv_tune.find(shape);
     if (known != c->ctx->spmv_tune.end()) {  // a matrix of this shape was timed before on this context
         c->unroll[pi] = known->second.first;
@@ -372,8 +424,8 @@ void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, Pc
 }
 
 // blocks that leave the r.z partials: the Jacobi kernels run on G blocks, the
-// FSAI product G^T w on the SpMV's Gs blocks
-int rz_parts(const SolveCache* c, int precond) { return precond == DEC_PRECOND_FSAI ? c->Gs : c->G; }
+// FSAI product G^T w and the block-Jacobi product on the SpMV's Gs blocks
+int rz_parts(const SolveCache* c, int precond) { return precond == DEC_PRECOND_JACOBI ? c->G : c->Gs; }
 
 template <class VT>
 void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a = nullptr,
@@ -389,6 +441,12 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
                            n_pq, S);
         hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
                            (const VT*)nullptr, R.p, part, P, G, S, N);
+    } else if (R.precond == DEC_PRECOND_BLOCK) {
+        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, (const VT*)nullptr,
+                           part, P, n_pq, S);
+        launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.z, R.r, region(c, R_RZ), S);       // z = M r, r.z partials
+        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, (const VT*)nullptr,
+                           R.z, R.p, part, P, c->Gs, S, N);
     } else {
         hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, (const VT*)nullptr,
                            part, P, n_pq, S);
@@ -407,6 +465,8 @@ void enqueue_precond_start(SolveCache* c, const Run<VT>& R) {
     if (R.precond == DEC_PRECOND_JACOBI) {
         hipLaunchKernelGGL(k_init_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
                            region(c, R_RZ));
+    } else if (R.precond == DEC_PRECOND_BLOCK) {
+        launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.p, R.r, region(c, R_RZ), nullptr);    // p = M r, r.z partials
     } else {
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, nullptr);       // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.p, R.r, region(c, R_RZ), nullptr);   // p = G^T w, r.z partials
@@ -496,9 +556,10 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
 
 Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
     Run<double> R{};
-    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V};
+    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V, m->sell.excess64.p};
     R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val64.p, m->fsai.g_sell.nslices, m->V};
     R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val64.p, m->fsai.gt_sell.nslices, m->V};
+    R.M = {m->blockinv.ptr.p, m->blockinv.col.p, m->blockinv.val64.p, m->blockinv.nslices, m->V};
     R.x = c->x64.p;
     R.r = c->r64.p;
     R.p = c->p64.p;
@@ -513,9 +574,10 @@ Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
 
 Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
     Run<float> R{};
-    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V};
+    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V, m->sell.excess32.p};
     R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val32.p, m->fsai.g_sell.nslices, m->V};
     R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val32.p, m->fsai.gt_sell.nslices, m->V};
+    R.M = {m->blockinv.ptr.p, m->blockinv.col.p, m->blockinv.val32.p, m->blockinv.nslices, m->V};
     R.x = c->x32.p;
     R.r = c->r32.p;
     R.p = c->p32.p;
@@ -529,7 +591,8 @@ Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
 }
 
 SellView<double> sell64(dec_mesh* m) {
-    return SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V};
+    return SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V,
+                            m->sell.excess64.p};
 }
 
 // ||b - A x64||^2 in FP64 (through t64), via the scratch state
@@ -541,19 +604,36 @@ double true_rr(dec_mesh* m, SolveCache* c) {
     return read_state(c, s4).rr;
 }
 
-// FP64 PCG from the current x64.  Returns a DEC status.
+// The energy-norm estimate of a finished state: sqrt(window / cum).
+double energy_estimate(const PcgScalars& s) {
+    double win = 0.0;
+    for (int j = 0; j < ENERGY_DELAY; ++j) win += s.hist[j];
+    return s.cum > 0.0 ? sqrt(win / s.cum) : 0.0;
+}
+
+// FP64 PCG from the current x64.  Returns a DEC status.  With the energy
+// norm, the state's estimate is the test and no true residual is taken (the
+// plain residual of such systems can sit far above tol at full accuracy).
 int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int64_t* iters_out,
              dec_solve_stats* stats) {
     Run<double> R = run64(m, c, o.precond);
     const double tol2 = o.tol * o.tol;
+    const bool en = o.norm == DEC_NORM_ENERGY;
     int64_t total = 0;
     for (int restart = 0;; ++restart) {
         const int64_t left = o.max_iters - total;
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left > 0 ? left : (int64_t)1);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left > 0 ? left : (int64_t)1, (int32_t)en);
         // rr_stop = tol^2 b.b (the relative test in absolute form)
         hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, region(c, R_RR));
         finalize(c, FIN_NORM2, c->G, tol2, 0, R.st);
         launch_sell<double, MODE_RESID>(c, R.A, R.x, R.r, m->rhs.p, region(c, R_RR), nullptr);
+        if (en) {
+            // ||x0||_A^2 = x0.(b + r0) seeds cum; rr_stop = tol^2
+            hipLaunchKernelGGL(k_xbr, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, R.x, m->rhs.p, R.r,
+                               region(c, R_PQ));
+            hipLaunchKernelGGL(k_energy_start, dim3(1), dim3(BLOCK), 0, c->stream, region(c, R_PQ), c->G, tol2,
+                               R.st);
+        }
         enqueue_precond_start<double>(c, R);
         finalize(c, FIN_START, c->Gs, 0.0, 0, R.st, rz_parts(c, R.precond));
         HIP_CHECK(hipGetLastError());
@@ -569,6 +649,10 @@ int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int
         *iters_out = total;
         if (s.done == PCG_BREAKDOWN) return DEC_EBREAKDOWN;
         if (s.done == PCG_MAXITER) return DEC_ENOTCONV;
+        if (en) {
+            if (stats) stats->rel_residual = energy_estimate(s);
+            return DEC_OK;
+        }
         // converged on the recursive residual: confirm with the true one
         const double rr = true_rr(m, c);
         if (rr <= tol2 * bb) return DEC_OK;
@@ -583,6 +667,19 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
     const double bn = sqrt(bb);
     double rn_prev = INFINITY;
     int64_t inner_total = 0;
+    // FP64 PCG from the current x64 with the iterations left
+    auto finish_fp64 = [&]() {
+        if (stats) stats->fp64_fallback = 1;
+        int64_t it64 = 0;
+        dec_solve_opts o64 = o;
+        o64.max_iters = o.max_iters > inner_total ? o.max_iters - inner_total : 1;
+        const int st = pcg_fp64(m, c, o64, bb, &it64, stats);
+        if (stats) stats->iterations = inner_total + it64;
+        return st;
+    };
+    // one inner solve gets at most an eighth of the budget, so that a stalled FP32
+    // solve leaves FP64 the rest
+    const int64_t inner_cap = o.max_iters / 8 > 64 ? o.max_iters / 8 : 64;
     for (int outer = 0; outer < 100; ++outer) {
         // r64 = b - A x64 (FP64), ||r64||^2 into s4->rr
         launch_sell<double, MODE_RESID>(c, sell64(m), c->x64.p, c->r64.p, m->rhs.p, region(c, R_RR), nullptr);
@@ -591,21 +688,22 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         if (stats) stats->outer_iterations = outer;
         if (rn <= o.tol * bn) return DEC_OK;
         if (outer > 0 && rn > 0.5 * rn_prev) {
-            // refinement stagnates (FP32 cannot reduce the residual further): finish in FP64
-            if (stats) stats->fp64_fallback = 1;
-            int64_t it64 = 0;
-            dec_solve_opts o64 = o;
-            o64.max_iters = o.max_iters > inner_total ? o.max_iters - inner_total : 1;
-            const int st = pcg_fp64(m, c, o64, bb, &it64, stats);
-            if (stats) stats->iterations = inner_total + it64;
-            return st;
+            // refinement stagnates (FP32 cannot reduce the residual further): finish in FP64,
+            // from the previous iterate when the last correction made the residual larger
+            // (an FP32 solve below its own rounding floor can return nonsense)
+            if (rn > rn_prev) {
+                hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p,
+                                   c->x32.p, -rn_prev);
+                HIP_CHECK(hipGetLastError());
+            }
+            return finish_fp64();
         }
         double itol = o.inner_tol;
         if (o.adaptive_final_inner) itol = fmax(o.inner_tol, 0.5 * o.tol * bn / rn);
         if (itol >= 1.0) itol = 0.5;
         const int64_t left = o.max_iters - inner_total;
         if (left <= 0) return DEC_ENOTCONV;
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left < inner_cap ? left : inner_cap, 0);
         hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s4, c->r32.p, c->x32.p,
                            region(c, R_RR));
         enqueue_precond_start<float>(c, R);
@@ -615,7 +713,9 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         if (!s.done) s = iterate(c, R, o, stats);
         inner_total += s.iter;
         if (stats) stats->iterations = inner_total;
-        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, s4);
+        // an FP32 solve that broke down or ran out of iterations is not applied
+        if (s.done != PCG_CONVERGED) return finish_fp64();
+        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, rn);
         HIP_CHECK(hipGetLastError());
         rn_prev = rn;
     }
@@ -704,6 +804,7 @@ int dec_solve_opts_default(dec_solve_opts* o) {
     o->chunk = 32;
     o->use_graph = 1;
     o->profile = 0;
+    o->norm = DEC_NORM_RESIDUAL;
     return DEC_OK;
 }
 
@@ -714,10 +815,16 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         const dec_solve_opts& o = *opts;
         DEC_REQUIRE(m->bc_ready, DEC_ESTATE, "dec_solve needs dec_apply_bc first");
         DEC_REQUIRE(o.precision == DEC_PREC_FP64 || o.precision == DEC_PREC_MIXED, DEC_EINVAL, "bad precision");
-        DEC_REQUIRE(o.precond == DEC_PRECOND_JACOBI || o.precond == DEC_PRECOND_FSAI, DEC_EINVAL, "bad precond");
+        DEC_REQUIRE(o.precond == DEC_PRECOND_JACOBI || o.precond == DEC_PRECOND_FSAI || o.precond == DEC_PRECOND_BLOCK,
+                    DEC_EINVAL, "bad precond");
+        DEC_REQUIRE(o.precond != DEC_PRECOND_BLOCK || m->blockinv.nslices > 0, DEC_EINVAL,
+                    "the block preconditioner is built for tet systems (dec_dual_build)");
         DEC_REQUIRE(o.tol > 0.0 && o.inner_tol > 0.0 && o.inner_tol < 1.0, DEC_EINVAL, "bad tolerance");
         DEC_REQUIRE(o.max_iters > 0 && o.chunk >= 0 && o.chunk <= 4096, DEC_EINVAL, "bad iteration limits");
         DEC_REQUIRE(o.profile >= 0, DEC_EINVAL, "profile is a sampling stride, 0 for off");
+        DEC_REQUIRE(o.norm == DEC_NORM_RESIDUAL || o.norm == DEC_NORM_ENERGY, DEC_EINVAL, "bad stopping norm");
+        DEC_REQUIRE(o.norm == DEC_NORM_RESIDUAL || o.precision == DEC_PREC_FP64, DEC_EINVAL,
+                    "the energy-norm test is for FP64 solves");
         ctx->set_device();
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
@@ -733,7 +840,7 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         if (o.precision == DEC_PREC_MIXED)
             autotune_spmv<float>(c,
                                  SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices,
-                                                 m->V},
+                                                 m->V, m->sell.excess32.p},
                                  m->sell.entries, c->p32.p, c->q32.p);
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
@@ -762,7 +869,10 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
             float ms = 0.0f;
             HIP_CHECK(hipEventElapsedTime(&ms, c->t0, c->t1));
             stats->solve_ms = ms;
-            stats->rel_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
+            // the energy-norm test leaves its own estimate (when it converged)
+            const bool keep = o.norm == DEC_NORM_ENERGY && status == DEC_OK && bb != 0.0;
+            if (!keep) stats->rel_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
+            stats->plain_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
             stats->status = status;
         }
         if (status != DEC_OK) ctx->last_error = dec_status_string(status);
@@ -795,11 +905,13 @@ int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void
             c->stream = ctx->stream;
             if (precision == DEC_PREC_FP64)
                 launch_sell<double, MODE_PLAIN>(
-                    c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V},
+                    c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V,
+                                        m->sell.excess64.p},
                     static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr, nullptr);
             else
                 launch_sell<float, MODE_PLAIN>(
-                    c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V},
+                    c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V,
+                                       m->sell.excess32.p},
                     static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr, nullptr);
             c->stream = keep;
         }

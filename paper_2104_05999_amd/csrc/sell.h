@@ -10,6 +10,13 @@
 
 #include "common.h"
 
+// With `excess` set, the product is taken in difference form,
+//     (A x)_i = excess_i x_i + sum_{j != i} a_ij (x_j - x_i),
+// where excess_i = a_ii + sum_{j != i} a_ij is kept exactly (from the weights
+// that make it up, never as that difference).  For a Laplacian-like matrix
+// with weights of very different size this avoids the cancellation of
+// a_ii x_i against its neighbours, so the product keeps full relative accuracy
+// in the smooth components; the stored diagonal then multiplies x_i - x_i = 0.
 template <class VT>
 struct SellView {
     const int64_t* ptr;
@@ -17,6 +24,7 @@ struct SellView {
     const VT* val;
     int64_t nslices;
     int64_t V;
+    const VT* excess = nullptr;  // [V], or null for the plain product
 };
 
 // Native two-element vectors for the paired loads.
@@ -47,10 +55,10 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // before its x gathers, and the last group is predicated (the width is
 // uniform across the wavefront), so no entry waits on the one before; an odd
 // last entry follows.  The terms are added in entry order, so every layout
-// and unroll gives the same sum.
-template <class VT, int U, bool NT = true>
+// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).
+template <class VT, int U, bool NT = true, bool DIFF = false>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
-                                       const VT* __restrict__ x) {
+                                       const VT* __restrict__ x, VT xi = 0) {
     typedef typename Pair<int32_t>::type C2;
     typedef typename Pair<VT>::type V2;
     const int np = width >> 1;
@@ -72,6 +80,10 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
             const bool ok = t + u < np;
             x0[u] = ok ? x[c[u].x] : VT(0);
             x1[u] = ok ? x[c[u].y] : VT(0);
+            if (DIFF) {
+                x0[u] -= xi;
+                x1[u] -= xi;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -85,7 +97,7 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
     if (width & 1) {
         const int64_t k = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
         const int32_t c = stream_load<int32_t, NT>(A.col + k);
-        acc += stream_load<VT, NT>(A.val + k) * x[c];
+        acc += stream_load<VT, NT>(A.val + k) * (DIFF ? x[c] - xi : x[c]);
     }
     return acc;
 }
@@ -96,8 +108,9 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // y = b - A x with per-block partials of y.y (RESID), or y = A x with
 // per-block partials of b.y (DOTB).  A launch whose `done` flag (if given)
 // is set returns at once: inside a batch of PCG iterations that has
-// converged, the remaining launches do nothing.
-template <class VT, int MODE, int U, bool NT>
+// converged, the remaining launches do nothing.  DIFF: the difference form
+// (A.excess set).
+template <class VT, int MODE, int U, bool NT, bool DIFF = false>
 __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
                                                 const int32_t* __restrict__ done) {
@@ -111,7 +124,14 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
         const int64_t base = A.ptr[s];
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;
-        const VT acc = sell_row<VT, U, NT>(A, base, width, lane, x);
+        VT acc;
+        if (DIFF) {
+            const VT xi = row < A.V ? x[row] : VT(0);
+            acc = sell_row<VT, U, NT, true>(A, base, width, lane, x, xi);
+            if (row < A.V) acc += A.excess[row] * xi;
+        } else {
+            acc = sell_row<VT, U, NT>(A, base, width, lane, x);
+        }
         if (row < A.V) {
             if (MODE == MODE_RESID) {
                 const VT ri = b[row] - acc;

@@ -23,8 +23,19 @@ struct PcgScalars {
     int64_t iter;
     int64_t max_iter;
     int32_t done;    // PCG_RUNNING / PCG_CONVERGED / PCG_MAXITER / PCG_BREAKDOWN
-    int32_t pad1[3];
+    int32_t use_energy;  // stop on the estimate of the A-norm error instead of r.r
+    int32_t pad1[2];
+    // Energy-norm stopping test (Hestenes-Stiefel): iteration j adds
+    // alpha_j rho_j = ||x* - x_j||_A^2 - ||x* - x_{j+1}||_A^2, so the sum of the
+    // last ENERGY_DELAY terms is a lower bound of the A-norm error squared of
+    // the iterate ENERGY_DELAY - 1 steps back; `cum` is x0^T (b + r0) plus all
+    // terms so far (tending to ||x*||_A^2).  Converged when the window sum is
+    // <= rr_stop * cum (rr_stop = tol^2).
+    double cum;
+    double hist[16];  // the last ENERGY_DELAY terms, term j in slot j % ENERGY_DELAY
 };
+
+constexpr int ENERGY_DELAY = 16;
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXITER = 2, PCG_BREAKDOWN = 3 };
 

@@ -26,6 +26,8 @@ __all__ = [
     "lattice_index",
     "jitter_interior",
     "x_sides",
+    "delaunay_cube",
+    "x_faces",
     "lognormal_kappa",
     "penny_cracks",
     "grown_radii",
@@ -108,6 +110,47 @@ def x_sides(n: int):
     bc_type = ((i == 0) | (i == n)).astype(np.int8)
     bc_value = (i == 0).astype(np.float64)
     side = np.where(i == 0, 1, np.where(i == n, 2, 0)).astype(np.int8)
+    return bc_type, bc_value, side
+
+
+def delaunay_cube(n_interior: int, n_face: int, seed: int):
+    """Delaunay tetrahedralisation of random points in the unit cube (stand-in
+    for the paper's TetGen Delaunay meshes, Section 2.2).
+
+    Points: the 8 corners, ``n_face`` uniform points on each of the 6 faces
+    (coordinates exactly 0 or 1 on the face's axis) and ``n_interior`` uniform
+    interior points, from PCG64(seed).  Tets from scipy's Qhull Delaunay;
+    simplices of volume <= 1e-12 (flat ones Qhull can leave on coplanar hull
+    points) are dropped, and every tet is ordered to positive volume.
+    Returns ``xyz`` float64 [V,3] and ``tets`` int32 [T,4].
+    """
+    import scipy.spatial
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = [np.array(list(itertools.product((0.0, 1.0), repeat=3)))]
+    for ax in range(3):
+        for side in (0.0, 1.0):
+            p = rng.random((n_face, 3))
+            p[:, ax] = side
+            pts.append(p)
+    pts.append(rng.random((n_interior, 3)))
+    xyz = np.concatenate(pts)
+    tets = scipy.spatial.Delaunay(xyz).simplices.astype(np.int64)
+    p = xyz[tets]
+    vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0]) / 6.0
+    keep = np.abs(vol) > 1e-12
+    tets, vol = tets[keep], vol[keep]
+    tets[vol < 0] = tets[vol < 0][:, [0, 2, 1, 3]]
+    return xyz, np.ascontiguousarray(tets, dtype=np.int32)
+
+
+def x_faces(xyz: np.ndarray):
+    """The conduction test's Dirichlet data on any mesh of the unit cube: T = 1 on
+    x = 0 and T = 0 on x = 1 (vertices exactly on those planes); same outputs as
+    ``x_sides``."""
+    x = np.asarray(xyz)[:, 0]
+    bc_type = ((x == 0.0) | (x == 1.0)).astype(np.int8)
+    bc_value = (x == 0.0).astype(np.float64)
+    side = np.where(x == 0.0, 1, np.where(x == 1.0, 2, 0)).astype(np.int8)
     return bc_type, bc_value, side
 
 
