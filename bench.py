@@ -43,17 +43,18 @@ def spmv_bytes(V, nnz, s_v):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_fp64_kuhn128_traffic.txt")
+DUAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_diff_fp64_kuhn128_tets_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("sell.h", "common.h")]
 
 
-def measured_traffic(n):
+def measured_traffic(n, path=TRAFFIC_FILE):
     """HBM bytes per SpMV launch from the committed counter summary, or None when the kernel
     sources changed since the counters were taken (or for another mesh size)."""
     import hashlib
 
-    if n != 128 or not os.path.exists(TRAFFIC_FILE):
+    if n != 128 or not os.path.exists(path):
         return None
-    kv = dict(ln.strip().split("=", 1) for ln in open(TRAFFIC_FILE) if "=" in ln and not ln.startswith("#"))
+    kv = dict(ln.strip().split("=", 1) for ln in open(path) if "=" in ln and not ln.startswith("#"))
     h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     if kv.get("source_sha256") != h:
         return None
@@ -357,6 +358,96 @@ def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
     return out
 
 
+def dual_inputs(n, dev, sigma=1.0, kseed=1, n_cracks=200, cseed=2):
+    """The tet-unknown workload: the default recipe with the conductivity on the faces."""
+    import torch
+
+    xyz, tets = W.kuhn_cube(n, device=dev)
+    F = W.kuhn_counts(n)["F"]
+    bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
+    return dict(n=n, xyz=xyz, tets=tets, kappa=torch.as_tensor(W.lognormal_kappa(F, sigma, kseed), device=dev),
+                cracks=torch.as_tensor(W.penny_cracks(n_cracks, cseed), device=dev), bt=bt, bv=bv, side=side)
+
+
+def dual_step(ctx, inp, profile=8, tol=1e-10):
+    """Topology, tet system (faces, limited Hodge entries, cuts, Dirichlet faces, blocks), block-Jacobi
+    PCG to tol in the A-norm, flux; returns (stats, flux, info, build_ms)."""
+    import torch
+
+    t0 = time.perf_counter()
+    mesh = ctx.mesh(inp["xyz"], inp["tets"])
+    d = mesh.dual(inp["bt"], inp["bv"], inp["side"], inp["kappa"], inp["cracks"])
+    mesh.close()
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    T, st, rc = d.solve(tol=tol, profile=profile, check=False)
+    f = d.flux(T)
+    info = dict(d.info(), V=d.V, nnz=d.nnz, n_pinned=d.n_pinned, status=rc)
+    d.close()
+    return st, f, info, build_ms
+
+
+def dual_cpu_baseline(n=20):
+    """The oracle on the tet-unknown path (faces, geometry, cuts, Schur system, direct solve, flux) on an
+    n^3 instance of the same recipe, single-threaded: tets per second."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dual as D
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        xyz, tets = W.kuhn_cube(n)
+        F = W.kuhn_counts(n)["F"]
+        bt, bv, side = W.x_sides(n)
+        s = D.dual_system(xyz, tets, bt, bv, side, kappa=W.lognormal_kappa(F, 1.0, 1), cracks=W.penny_cracks(200, 2))
+        D.flux(D.solve(s), s)
+        dt = time.perf_counter() - t0
+    return {"value": len(tets) / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle tet-unknown path on the {n}^3 instance of the same recipe ({len(tets)} tets, "
+                      f"sparse LU for the solve) in {dt:.1f} s", "seconds": dt}
+
+
+def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True):
+    import torch
+
+    inp = dual_inputs(n, dev)
+    for _ in range(warmup):
+        st, f, info, bms = dual_step(ctx, inp)
+        print(f"[bench] dual warmup: build {bms:.1f} ms, {st['iterations']} its, {st['solve_ms']:.1f} ms solve",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [dual_step(ctx, inp) for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st, f, info, bms = runs[-1]
+    launches = sum(r[0]["spmv_launches"] for r in runs)
+    spmv_ms = sum(r[0]["spmv_ms"] for r in runs)
+    per = st["spmv_bytes"]
+    out = {"metric": "tet-unknown system (eq. 11-13): tets/s through topology, build, solve, flux",
+           "value": round(info["V"] * steps / elapsed, 1), "unit": "tets/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(1e3 * elapsed / steps, 3), "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"kuhn{n}_face_lognormal1_cracks200_fp64_block_energy", "n": n, "tets": info["V"],
+                      "faces": info["faces"], "limited": info["limited"], "blocks": info["blocks"],
+                      "max_block": info["max_block"], "nnz": info["nnz"], "tol": 1e-10,
+                      "stopping": "A-norm error estimate (Hestenes-Stiefel, window 16)"},
+           "build_ms": round(bms, 3), "solve_ms": round(st["solve_ms"], 3), "pcg_iterations": st["iterations"],
+           "error_estimate": st["rel_residual"], "plain_residual": st["plain_residual"], "k_eff": f["k_eff"],
+           "q_in": f["q_in"], "q_out": f["q_out"], "n_pinned": info["n_pinned"], "status": info["status"]}
+    if launches:
+        achieved = per * launches / (spmv_ms / 1e3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                           "traffic": measured_traffic(n, DUAL_TRAFFIC_FILE),
+                           "kernel": "k_sell<double, MODE_DOT, difference form> (tet system SpMV + p.Ap partials)",
+                           "bytes_per_launch": per, "mean_launch_us": round(1e3 * spmv_ms / launches, 3),
+                           "launches": launches}
+    if cpu:
+        out["cpu_baseline"] = dual_cpu_baseline()
+    return out
+
+
 def cpu_baseline(n=80):
     """The oracle, single-threaded, on the full path of a smaller instance of the same recipe."""
     from threadpoolctl import threadpool_limits
@@ -408,6 +499,9 @@ def main():
                     help="instead of the default line: the deterministic and Monte Carlo cracking processes")
     ap.add_argument("--growth-n", type=int, default=256)
     ap.add_argument("--growth-steps", type=int, default=51)
+    ap.add_argument("--dual", action="store_true",
+                    help="instead of the default line: the tet-unknown system (temperature per tet, flux per face)")
+    ap.add_argument("--dual-n", type=int, default=128)
     ap.add_argument("--crack-growth", action="store_true",
                     help="instead of the default line: the 256^3 crack-growth chains (FP64 and mixed)")
     args = ap.parse_args()
@@ -425,6 +519,9 @@ def main():
     if args.cracking:
         print(json.dumps({"metric": "cracking processes: k_eff vs damage D_n, steps/s", "n_gpus": 1,
                           "data": "synthetic", **cracking_processes(ctx, dev)}))
+        return
+    if args.dual:
+        print(json.dumps(dual_benchmark(ctx, dev, args.dual_n, args.steps, args.warmup, not args.no_cpu_baseline)))
         return
     if args.crack_growth:
         print(json.dumps({"metric": "crack growth k_eff(step), mixed vs FP64 wall time", "n_gpus": 1,

@@ -190,7 +190,8 @@ typedef struct dec_solve_stats {
     int64_t spmv_launches;    /* profile: SpMV launches timed                              */
     double spmv_ms;           /* profile: summed duration of those launches                */
     double spmv_bytes;        /* bytes one SpMV must move: CSR definition over the entries
-                                 the product uses (nnz (s+4) + 4 (V+1) + 2 V s)            */
+                                 the product uses (nnz (s+4) + 4 (V+1) + 2 V s, plus V s
+                                 for the row excess of a difference-form product)          */
     int64_t spmv_nnz;         /* entries the product uses (full pattern or pruned)       */
     double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
 } dec_solve_stats;

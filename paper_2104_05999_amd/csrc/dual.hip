@@ -271,7 +271,8 @@ __global__ void k_dual_rows(int64_t T, const int32_t* __restrict__ nbr, const in
                             const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                             int32_t* __restrict__ diag_pos, double* __restrict__ v64, float* __restrict__ v32,
                             double* __restrict__ rhs, double* __restrict__ invd64, float* __restrict__ invd32,
-                            double* __restrict__ ex64, float* __restrict__ ex32) {
+                            double* __restrict__ ex64, float* __restrict__ ex32, int32_t* __restrict__ o_col,
+                            double* __restrict__ o64, float* __restrict__ o32) {
     GRID_STRIDE_LOOP(t, T) {
         const bool pin = fixed[t] != 0;
         int cc[5], ff[5], n = 0;
@@ -303,6 +304,7 @@ __global__ void k_dual_rows(int64_t T, const int32_t* __restrict__ nbr, const in
             }
         }
         const int32_t p = row_ptr[t];
+        int32_t q = p - (int32_t)t;  // the row in the off-diagonal copy (one diagonal per row before it)
         for (int i = 0; i < n; ++i) {
             const double v = ff[i] < 0 ? (pin ? 1.0 : diag) : (pin ? 0.0 : -W[ff[i]]);
             col[p + i] = cc[i];
@@ -312,6 +314,11 @@ __global__ void k_dual_rows(int64_t T, const int32_t* __restrict__ nbr, const in
                 diag_pos[t] = p + i;
                 invd64[t] = 1.0 / v;
                 invd32[t] = 1.0f / static_cast<float>(v);
+            } else {
+                o_col[q] = cc[i];
+                o64[q] = v;
+                o32[q] = static_cast<float>(v);
+                ++q;
             }
         }
         rhs[t] = pin ? 0.0 : b;
@@ -391,9 +398,10 @@ __global__ void k_dual_block_single(int64_t T, const int32_t* __restrict__ root,
 }
 
 // One thread per block cluster: gather A restricted to the cluster (members
-// ascending), Cholesky A = L L^T, inverse (L^-1)^T L^-1, rows written in member
-// order.  A pivot that is not positive (not expected: the block of an SPD
-// matrix) leaves the cluster's rows diagonal (Jacobi).
+// ascending), Cholesky A = L L^T, then column b of the inverse from
+// L y = e_b, L^T x = y; its entries a >= b go to (a, b) and (b, a).  A pivot
+// that is not positive (not expected: the block of an SPD matrix) leaves the
+// cluster's rows diagonal (Jacobi).
 __global__ void k_dual_block_inv(int64_t T, const int32_t* __restrict__ root, const int32_t* __restrict__ size,
                                  const int64_t* __restrict__ slot_off, const int32_t* __restrict__ members,
                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -411,7 +419,7 @@ __global__ void k_dual_block_inv(int64_t T, const int32_t* __restrict__ root, co
                 mem[b] = mem[b - 1];
                 mem[b - 1] = x;
             }
-        double A[MAX_BLOCK][MAX_BLOCK], Li[MAX_BLOCK][MAX_BLOCK], dg[MAX_BLOCK];
+        double A[MAX_BLOCK][MAX_BLOCK], dg[MAX_BLOCK], y[MAX_BLOCK];
         for (int a = 0; a < s; ++a)
             for (int b = 0; b < s; ++b) A[a][b] = 0.0;
         for (int a = 0; a < s; ++a)
@@ -436,31 +444,37 @@ __global__ void k_dual_block_inv(int64_t T, const int32_t* __restrict__ root, co
                 A[i][j] = v / A[j][j];
             }
         }
-        if (ok)
-            for (int j = 0; j < s; ++j) {
-                Li[j][j] = 1.0 / A[j][j];
-                for (int i = j + 1; i < s; ++i) {
-                    double v = 0.0;
-                    for (int k = j; k < i; ++k) v += A[i][k] * Li[k][j];
-                    Li[i][j] = -v / A[i][i];
-                }
-            }
         for (int a = 0; a < s; ++a) {
             const int32_t p = m_ptr[mem[a]];
-            for (int b = 0; b < s; ++b) {
-                double v;
-                if (ok) {
-                    v = 0.0;
-                    for (int k = a > b ? a : b; k < s; ++k) v += Li[k][a] * Li[k][b];
-                } else {
-                    v = a == b ? 1.0 / dg[a] : 0.0;
+            for (int b = 0; b < s; ++b) m_col[p + b] = mem[b];
+        }
+        for (int b = 0; b < s; ++b) {
+            if (ok) {
+                for (int i = 0; i < s; ++i) {  // L y = e_b
+                    double v = i == b ? 1.0 : 0.0;
+                    for (int k = 0; k < i; ++k) v -= A[i][k] * y[k];
+                    y[i] = v / A[i][i];
                 }
-                m_col[p + b] = mem[b];
-                m64[p + b] = v;
-                m32[p + b] = static_cast<float>(v);
+                for (int i = s - 1; i >= 0; --i) {  // L^T x = y, in place
+                    double v = y[i];
+                    for (int k = i + 1; k < s; ++k) v -= A[k][i] * y[k];
+                    y[i] = v / A[i][i];
+                }
+            } else {
+                for (int i = 0; i < s; ++i) y[i] = i == b ? 1.0 / dg[b] : 0.0;
+            }
+            for (int a = b; a < s; ++a) {  // the lower triangle, mirrored: M is exactly symmetric
+                const int32_t pa = m_ptr[mem[a]] + b, pb = m_ptr[mem[b]] + a;
+                m64[pa] = m64[pb] = y[a];
+                m32[pa] = m32[pb] = static_cast<float>(y[a]);
             }
         }
     }
+}
+
+// Row pointer of the off-diagonal copy: row t starts after t diagonals fewer.
+__global__ void k_offdiag_ptr(int64_t T, const int32_t* __restrict__ row_ptr, int32_t* __restrict__ o_ptr) {
+    GRID_STRIDE_LOOP(t, T + 1) o_ptr[t] = row_ptr[t] - (int32_t)t;
 }
 
 // Flux of a tet solution: energy, Q_in, Q_out as per-block partials.
@@ -604,15 +618,23 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
         d->invdiag32.alloc(ctx, T);
         d->bc_value.alloc(ctx, T);
         d->bc_value.zero();
-        DBuf<double> ex64;
-        DBuf<float> ex32;
+        // the solver's copy holds the off-diagonal entries only: in the difference form the
+        // diagonal multiplies x_i - x_i = 0
+        DBuf<double> ex64, o64;
+        DBuf<float> ex32, o32;
+        DBuf<int32_t> o_ptr, o_col;
         ex64.alloc(ctx, T);
         ex32.alloc(ctx, T);
+        o_ptr.alloc(ctx, T + 1);
+        o_col.alloc(ctx, nnz - T > 0 ? nnz - T : 1);
+        o64.alloc(ctx, nnz - T > 0 ? nnz - T : 1);
+        o32.alloc(ctx, nnz - T > 0 ? nnz - T : 1);
         hipLaunchKernelGGL(k_dual_rows, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, nbr.p, tet_face.p, D.W.p, D.T0.p,
                            D.kind.p, d->fixed.p, d->row_ptr.p, d->col.p, d->diag_pos.p, d->val64.p, d->val32.p,
-                           d->rhs.p, d->invdiag64.p, d->invdiag32.p, ex64.p, ex32.p);
+                           d->rhs.p, d->invdiag64.p, d->invdiag32.p, ex64.p, ex32.p, o_col.p, o64.p, o32.p);
+        hipLaunchKernelGGL(k_offdiag_ptr, dim3(grid_for(T + 1)), dim3(BLOCK), 0, s, T, d->row_ptr.p, o_ptr.p);
         HIP_CHECK(hipGetLastError());
-        build_sell_copy(ctx, T, nnz, d->row_ptr.p, d->col.p, d->val64.p, d->val32.p, d->sell);
+        build_sell_copy(ctx, T, nnz - T, o_ptr.p, o_col.p, o64.p, o32.p, d->sell);
         d->sell.excess64 = std::move(ex64);
         d->sell.excess32 = std::move(ex32);
 

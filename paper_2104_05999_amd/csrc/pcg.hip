@@ -831,6 +831,7 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
             const double s = o.precision == DEC_PREC_MIXED ? 4.0 : 8.0, nz = (double)m->sell.kept;
             stats->spmv_nnz = m->sell.kept;
             stats->spmv_bytes = nz * (s + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
+            if (m->sell.excess64.p) stats->spmv_bytes += s * (double)m->V;  // difference form: the row excess
         }
         SolveCache* c = get_solve_cache(m);
         if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
