@@ -448,6 +448,104 @@ def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True):
     return out
 
 
+def _max_tet_volume(xyz, tets):
+    p = xyz[tets.astype(np.int64)]
+    return float(np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]),
+                                  p[:, 3] - p[:, 0])).max() / 6.0)
+
+
+def _verify_mesh(ctx, dev, xyz, tets, tol=1e-12):
+    """The pristine cube (Section 3.1): T = 1 / 0 on x = 0 / 1, kappa = 1, both unknown placements;
+    eq. 15 RMS errors against 1 - x, k_eff, limited faces."""
+    import torch
+
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    bt, bv, side = (t(a) for a in W.x_faces(xyz))
+    m = ctx.mesh(t(xyz), t(tets))
+    m.hodge1(want_cut=False, want_star=False)
+    m.assemble()
+    m.apply_bc(bt, bv, want_rhs=False)
+    Tv, sv, rcv = m.solve(tol=tol, check=False)
+    fv = m.flux(Tv, side)
+    row = {"V": m.V, "T": m.T, "max_tet_volume": _max_tet_volume(xyz, tets),
+           "vertex": {"rms": m.rms_error(Tv), "k_eff": fv["k_eff"], "iterations": sv["iterations"], "status": rcv}}
+    d = m.dual(bt, bv, side)
+    Tt, st, rct = d.solve(tol=tol, check=False)
+    ft = d.flux(Tt)
+    info = d.info()
+    row["tets"] = {"rms": m.rms_error(Tt), "k_eff": ft["k_eff"], "iterations": st["iterations"], "status": rct,
+                   "limited_fraction": info["limited"] / info["faces"], "blocks": info["blocks"]}
+    d.close()
+    m.close()
+    return row
+
+
+def _spmv_rate(ctx, dev, xyz, tets, steps=2):
+    """Mean SpMV launch time and rate (profiled solves) of the vertex path on this numbering."""
+    import torch
+
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    bt, bv, _ = (t(a) for a in W.x_faces(xyz))
+    m = ctx.mesh(t(xyz), t(tets))
+    m.hodge1(want_cut=False, want_star=False)
+    m.assemble()
+    m.apply_bc(bt, bv, want_rhs=False)
+    m.solve(tol=1e-10, profile=8)  # tuning outside the timing
+    ms = launches = 0
+    solve = []
+    for _ in range(steps):
+        _, st, _ = m.solve(tol=1e-10, profile=8)
+        ms += st["spmv_ms"]
+        launches += st["spmv_launches"]
+        solve.append(st["solve_ms"])
+    per = st["spmv_bytes"]
+    m.close()
+    us = 1e3 * ms / launches
+    return {"spmv_us": round(us, 3), "GBps": round(per / (us * 1e-6) / 1e9, 1), "solve_ms": round(min(solve), 3),
+            "iterations": st["iterations"]}
+
+
+def meshes_benchmark(ctx, dev, kuhn=(8, 16, 32, 64), delaunay=(2000, 8000, 32000, 128000), shuffle_n=128):
+    """General meshes: the eq. 15 convergence study over Kuhn cubes and Delaunay meshes of random
+    points (the TetGen stand-in), and the SpMV on a scrambled numbering before and after the
+    spatial numbering of Section 2.2."""
+    import torch
+
+    out = {"metric": "eq. 15 RMS error vs max tet volume; SpMV GB/s before / after spatial numbering",
+           "n_gpus": 1, "data": "synthetic", "convergence": {"kuhn": [], "delaunay": []}}
+    for n in kuhn:
+        xyz, tets = W.kuhn_cube(n)
+        out["convergence"]["kuhn"].append({"n": n, **_verify_mesh(ctx, dev, xyz, tets)})
+        print(f"[bench] kuhn {n}: {out['convergence']['kuhn'][-1]}", file=sys.stderr, flush=True)
+    for npts in delaunay:
+        t0 = time.perf_counter()
+        xyz, tets = W.delaunay_cube(npts, int(2 * npts ** (2.0 / 3.0)), 1)
+        gen = time.perf_counter() - t0
+        xr, tr, _, _ = ctx.reorder(torch.as_tensor(xyz, device=dev), torch.as_tensor(tets, device=dev))
+        row = {"points": npts, "mesh_s": round(gen, 1),
+               **_verify_mesh(ctx, dev, xr.cpu().numpy(), tr.cpu().numpy())}
+        out["convergence"]["delaunay"].append(row)
+        print(f"[bench] delaunay {npts}: {row}", file=sys.stderr, flush=True)
+    # numbering: a Kuhn cube with scrambled vertex and tet numbers (a mesh file in no useful order)
+    xyz, tets = W.kuhn_cube(shuffle_n)
+    rng = np.random.Generator(np.random.PCG64(5))
+    p = rng.permutation(len(xyz))
+    xs = np.ascontiguousarray(xyz[np.argsort(p)])
+    ts = np.ascontiguousarray(p[tets][rng.permutation(len(tets))].astype(np.int32))
+    before = _spmv_rate(ctx, dev, xs, ts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr, tr, _, _ = ctx.reorder(torch.as_tensor(xs, device=dev), torch.as_tensor(ts, device=dev))
+    torch.cuda.synchronize()
+    reorder_ms = 1e3 * (time.perf_counter() - t0)
+    after = _spmv_rate(ctx, dev, xr.cpu().numpy(), tr.cpu().numpy())
+    out["numbering"] = {"workload": f"kuhn{shuffle_n}_homogeneous_scrambled_numbering", "scrambled": before,
+                        "spatial": after, "reorder_ms": round(reorder_ms, 3),
+                        "spmv_speedup": round(before["spmv_us"] / after["spmv_us"], 2)}
+    print(f"[bench] numbering: {out['numbering']}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(n=80):
     """The oracle, single-threaded, on the full path of a smaller instance of the same recipe."""
     from threadpoolctl import threadpool_limits
@@ -502,6 +600,8 @@ def main():
     ap.add_argument("--dual", action="store_true",
                     help="instead of the default line: the tet-unknown system (temperature per tet, flux per face)")
     ap.add_argument("--dual-n", type=int, default=128)
+    ap.add_argument("--meshes", action="store_true",
+                    help="instead of the default line: eq. 15 convergence study and the spatial numbering")
     ap.add_argument("--crack-growth", action="store_true",
                     help="instead of the default line: the 256^3 crack-growth chains (FP64 and mixed)")
     args = ap.parse_args()
@@ -519,6 +619,9 @@ def main():
     if args.cracking:
         print(json.dumps({"metric": "cracking processes: k_eff vs damage D_n, steps/s", "n_gpus": 1,
                           "data": "synthetic", **cracking_processes(ctx, dev)}))
+        return
+    if args.meshes:
+        print(json.dumps(meshes_benchmark(ctx, dev)))
         return
     if args.dual:
         print(json.dumps(dual_benchmark(ctx, dev, args.dual_n, args.steps, args.warmup, not args.no_cpu_baseline)))

@@ -69,6 +69,8 @@ int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_
 /* DEC_ESTATE while meshes or servers created on ctx are still alive. */
 int dec_destroy(dec_ctx* ctx);
 const char* dec_status_string(int status);
+/* Message of the last failure on ctx; with ctx NULL, of the last failed call
+ * that takes no context on this thread (dec_tetgen_read). */
 const char* dec_last_error(const dec_ctx* ctx);
 
 /* ---- topology (Section 2.1: cells, incidence, coboundary d) ------------
@@ -91,6 +93,39 @@ int dec_get_edges(const dec_mesh* m, int32_t* edges);
  * dec_apply_bc the values are those of L; after, those of the eliminated system A. */
 int dec_get_csr(const dec_mesh* m, int32_t* row_ptr, int32_t* col, double* val64, float* val32);
 int dec_mesh_destroy(dec_mesh* m);
+
+/* ---- TetGen mesh files (Section 2.2: the input is TetGen's Delaunay mesh) --
+ * Host only (no GPU call, no context).  node_path: the .node file (header
+ * "<points> 3 <attributes> <marker flag>", then "<index> x y z [attributes]
+ * [marker]" per point); ele_path: the .ele file (header "<tets> <4|10>
+ * <attributes>", then "<index> n1 .. n4 [n5 .. n10] [attributes]" per tet).
+ * '#' starts a comment.  The first point index (0 or 1) is the numbering
+ * base; points and tets must be numbered consecutively from it; ten-node tets
+ * keep their corners.  *V_out, *T_out (host, NULL ok) receive the counts;
+ * with xyz, tets and node_marker all NULL only the headers are read.
+ * Otherwise xyz [V x 3] float64, tets [T x 4] int32 (0-based) and node_marker
+ * [V] int32 (0 without markers) are HOST buffers the caller sized from a first
+ * call (any may be NULL).  DEC_EINVAL on a missing file or a malformed line;
+ * dec_last_error(NULL) names the file and line. */
+int dec_tetgen_read(const char* node_path, const char* ele_path, int64_t* V_out, int64_t* T_out,
+                    double* xyz, int32_t* tets, int32_t* node_marker);
+
+/* ---- spatial numbering (Section 2.2: nodes numbered by location, z first,
+ * then y, then x) ------------------------------------------------------------
+ * For points off a lattice the order is taken on cells: the bounding box is
+ * cut into B^3 cells, B the smallest integer with B^3 >= V; a point's cell on
+ * axis a is floor((x_a - lo_a) * (B / (hi_a - lo_a))) clamped to [0, B-1]
+ * (0 on a flat axis); points go by (x cell, y cell, z cell), z cell fastest,
+ * ties by original index.  Tets then go by their smallest new vertex number,
+ * ties by original index, keeping their vertex order.  On a lattice with one
+ * point per cell (a Kuhn cube) this is the lattice order.
+ * xyz [V x 3] float64, tets [T x 4] int32 device inputs; xyz_out, tets_out
+ * device outputs of the same shapes (not aliasing the inputs), tets_out
+ * renumbered; vperm_out [V] (new -> old vertex) and tperm_out [T] (new -> old
+ * tet) int32 device outputs, NULL ok.  DEC_ETOPO for a vertex index out of
+ * range, DEC_EINVAL for non-finite coordinates.  Synchronises the stream. */
+int dec_reorder(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets, double* xyz_out,
+                int32_t* tets_out, int32_t* vperm_out, int32_t* tperm_out);
 
 /* ---- Hodge star *1 with conductivity and cracks (Sections 2.1, 2.5) ----
  * |*e| = sum over the edge's tets (ascending tet id) of the signed area of
@@ -230,6 +265,15 @@ int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* 
                                     double length, double area, double dT, double* k_eff,
                                     double* q_in, double* q_out, double* energy,
                                     double* edge_flux_out);
+
+/* ---- verification error (eq. 15) ----------------------------------------
+ * RMS = sqrt(sum_i w_i (T_i - a - g.p_i)^2) against the linear field with
+ * field = {a, g_x, g_y, g_z} (HOST array of 4).  m: the mesh of vertices and
+ * tets (not a tet system).  on_tets = 1: T [T] float64 device holds one
+ * value per tet (a tet system's solution), p_i the tet's circumcentre, w_i
+ * its volume, as in the paper; on_tets = 0: T [V] per vertex, p_i the vertex,
+ * w_i = sum over its tets of vol / 4.  *rms host.  Synchronises the stream. */
+int dec_rms_error(dec_mesh* m, int32_t on_tets, const double* T, const double* field, double* rms);
 
 /* ---- cracking (Section 3, deterministic cracking process) --------------
  * The face with the largest heat-flux density: over the edges e with

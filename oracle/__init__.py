@@ -26,6 +26,7 @@ from .krylov import pcg, fsai_factor, fsai_pattern, iterative_refinement, PCGRes
 from .flux import flux_effective_conductivity
 from .cracking import (flux_density, max_flux_edge, CrackingSystem, cracking_process)
 from . import dual
+from .reorder import spatial_order
 
 __all__ = [
     "LOCAL_EDGES", "edges_of", "tet_edge_ids", "faces_of", "d0_matrix", "d1_matrix",
@@ -37,5 +38,5 @@ __all__ = [
     "pcg", "fsai_factor", "fsai_pattern", "iterative_refinement", "PCGResult",
     "flux_effective_conductivity",
     "flux_density", "max_flux_edge", "CrackingSystem", "cracking_process",
-    "dual",
+    "dual", "spatial_order",
 ]

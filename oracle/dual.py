@@ -203,3 +203,15 @@ def flux(T, s, length=1.0, area=1.0, dT=1.0):
     q_in = float((W * (T0 - T[t1]))[dirichlet & (side == 1)].sum())
     q_out = float((W * (T[t1] - T0))[dirichlet & (side == 2)].sum())
     return {"k_eff": energy * length / (area * dT * dT), "q_in": q_in, "q_out": q_out, "energy": energy}
+
+
+def rms_error_tets(xyz, tets, T, field=(1.0, -1.0, 0.0, 0.0)):
+    """Eq. 15, the paper's verification error: sqrt(sum over tets of V_t (T_t - T_exact)^2), T_exact
+    the linear field a + g.p at the tet's circumcentre (its Voronoi vertex), V_t its volume."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    p = xyz[np.asarray(tets, dtype=np.int64)]
+    c = circumcenter_tet(p[:, 0], p[:, 1], p[:, 2], p[:, 3])
+    vol = np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])) / 6.0
+    a, g = field[0], np.asarray(field[1:], dtype=np.float64)
+    d = np.asarray(T, dtype=np.float64) - (a + c @ g)
+    return float(np.sqrt((vol * d * d).sum()))

@@ -10,6 +10,7 @@ allocations) and streams.
 """
 import atexit
 import ctypes
+import os
 import weakref
 
 import torch
@@ -19,7 +20,7 @@ from ._lib import (DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL, DEC_NORM_ENERGY, DEC
                    DEC_PREC_MIXED, DEC_PRECOND_BLOCK, DEC_PRECOND_FSAI, DEC_PRECOND_JACOBI, SolveOpts,
                    SolveStats)
 
-__all__ = ["DecError", "Context", "Mesh", "DualMesh", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
+__all__ = ["DecError", "Context", "Mesh", "DualMesh", "read_tetgen", "Server", "SolveOpts", "SolveStats", "DEC_PREC_FP64", "DEC_PREC_MIXED",
            "DEC_PRECOND_JACOBI", "DEC_PRECOND_FSAI", "DEC_FMT_AUTO", "DEC_FMT_CSR", "DEC_FMT_SELL",
            "DEC_NORM_RESIDUAL", "DEC_NORM_ENERGY", "DEC_PRECOND_BLOCK"]
 
@@ -41,6 +42,27 @@ class DecError(RuntimeError):
     def __init__(self, code, message):
         super().__init__(f"{_lib.STATUS.get(code, code)}: {message}")
         self.code = code
+
+
+def read_tetgen(node_path, ele_path):
+    """TetGen .node / .ele files (dec_tetgen_read, host only): returns numpy arrays xyz [V,3]
+    float64, tets [T,4] int32 (0-based) and the node boundary markers [V] int32."""
+    import numpy as np
+
+    lib = _lib.load()
+    V, T = ctypes.c_int64(), ctypes.c_int64()
+    args = (os.fsencode(node_path), os.fsencode(ele_path))
+    rc = lib.dec_tetgen_read(*args, ctypes.byref(V), ctypes.byref(T), None, None, None)
+    if rc != 0:
+        raise DecError(rc, "dec_tetgen_read: " + lib.dec_last_error(None).decode(errors="replace"))
+    xyz = np.empty((V.value, 3), dtype=np.float64)
+    tets = np.empty((T.value, 4), dtype=np.int32)
+    mark = np.empty(V.value, dtype=np.int32)
+    rc = lib.dec_tetgen_read(*args, None, None, xyz.ctypes.data_as(ctypes.c_void_p),
+                             tets.ctypes.data_as(ctypes.c_void_p), mark.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise DecError(rc, "dec_tetgen_read: " + lib.dec_last_error(None).decode(errors="replace"))
+    return xyz, tets, mark
 
 
 def _ptr(t, dtype, n=None, name="array"):
@@ -112,6 +134,20 @@ class Context:
 
     def mesh(self, xyz, tets):
         return Mesh(self, xyz, tets)
+
+    def reorder(self, xyz, tets):
+        """Spatial numbering (dec_reorder): returns (xyz, tets, vperm, tperm) device tensors, the
+        permutations mapping new to old indices."""
+        V, T = int(xyz.shape[0]), int(tets.shape[0])
+        xo = torch.empty((V, 3), dtype=torch.float64, device=self.device)
+        to = torch.empty((T, 4), dtype=torch.int32, device=self.device)
+        vp = torch.empty(V, dtype=torch.int32, device=self.device)
+        tp = torch.empty(T, dtype=torch.int32, device=self.device)
+        rc = self.lib.dec_reorder(self.handle, V, _ptr(xyz, torch.float64, 3 * V, "xyz"), T,
+                                  _ptr(tets, torch.int32, 4 * T, "tets"), _ptr(xo, torch.float64),
+                                  _ptr(to, torch.int32), _ptr(vp, torch.int32), _ptr(tp, torch.int32))
+        self.check(rc, "dec_reorder")
+        return xo, to, vp, tp
 
 
 class Mesh:
@@ -244,6 +280,19 @@ class Mesh:
                                         ctypes.byref(d))
         self.ctx.check(rc, "dec_max_flux_edge")
         return e.value, d.value
+
+    def rms_error(self, T, field=(1.0, -1.0, 0.0, 0.0)):
+        """Eq. 15 against the linear field a + g.p, field = (a, gx, gy, gz): T per vertex
+        (length V) or per tet (length T, tet systems' solutions)."""
+        n = int(T.numel())
+        if n not in (self.V, self.T):
+            raise ValueError(f"T must have {self.V} (vertex) or {self.T} (tet) values")
+        on_tets = 1 if n == self.T and n != self.V else 0
+        f = (ctypes.c_double * 4)(*[float(v) for v in field])
+        out = ctypes.c_double()
+        self.ctx.check(self.lib.dec_rms_error(self.handle, on_tets, _ptr(T, torch.float64, n, "T"), f,
+                                              ctypes.byref(out)), "dec_rms_error")
+        return out.value
 
     def dual(self, bc_type, bc_value, side=None, kappa_face=None, cracks=None, limiter=0.0):
         """The system of the paper's own unknowns (temperature per tet, flux per triangle) as a

@@ -30,6 +30,9 @@ SOURCES = {
     "flux.hip": [],
     "serve.hip": [],
     "dual.hip": NO_CONTRACT,
+    "tetgen.hip": [],
+    "reorder.hip": [],
+    "rms.hip": [],
 }
 
 COMMON = [

@@ -155,6 +155,11 @@ void copy_i64_to_i32(dec_ctx* ctx, const int64_t* in, int32_t* out, int64_t n) {
 }
 
 // ---------------------------------------------------------------- C ABI
+std::string& free_error() {
+    thread_local std::string msg;
+    return msg;
+}
+
 extern "C" {
 
 const char* dec_status_string(int status) {
@@ -172,7 +177,10 @@ const char* dec_status_string(int status) {
     }
 }
 
-const char* dec_last_error(const dec_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+const char* dec_last_error(const dec_ctx* ctx) {
+    if (ctx) return ctx->last_error.c_str();
+    return free_error().empty() ? "no context" : free_error().c_str();
+}
 
 int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_free_fn free_fn, void* user) {
     if (!out) return DEC_EINVAL;

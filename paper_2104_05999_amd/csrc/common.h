@@ -23,6 +23,9 @@ struct DecError {
 
 [[noreturn]] inline void dec_fail(int code, const std::string& msg) { throw DecError{code, msg}; }
 
+// Message of the last failed call that takes no context (this thread); dec_last_error(NULL).
+std::string& free_error();
+
 #define HIP_CHECK(expr)                                                                    \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \

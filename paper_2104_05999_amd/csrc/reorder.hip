@@ -1,0 +1,219 @@
+// Spatial numbering of a mesh (Section 2.2: a pre-processing step numbers the
+// Delaunay nodes by their location in space, z first, then y, then x, so that
+// blocks of consecutive nodes are compact; here it also makes the gathers of
+// the SpMV and the assembly local).  For points off a lattice the sort is
+// taken on cells: the bounding box is cut into B^3 cells, B^3 the first cube >= V,
+// a point's cell on each axis is floor((x - lo) * (B / (hi - lo))) clamped to
+// [0, B-1], and points are ordered by (x cell, y cell, z cell) with the z cell
+// fastest, ties by original index.  Tets are then ordered by their smallest
+// new vertex number, ties by original index, and keep their vertex order.
+// Counting sorts on the cell and on the smallest vertex, then a sort by
+// original index inside each cell or bucket, so the result is unique.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+__global__ void k_bbox(int64_t V, const double* __restrict__ xyz, double* __restrict__ part) {
+    __shared__ double red[6][BLOCK];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    GRID_STRIDE_LOOP(i, V) {
+        for (int a = 0; a < 3; ++a) {
+            const double v = xyz[3 * i + a];
+            mn[a] = fmin(mn[a], v);
+            mx[a] = fmax(mx[a], v);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = mn[a];
+        red[3 + a][threadIdx.x] = mx[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double r = red[threadIdx.x][0];
+        for (int t = 1; t < BLOCK; ++t) r = threadIdx.x < 3 ? fmin(r, red[threadIdx.x][t]) : fmax(r, red[threadIdx.x][t]);
+        part[6 * blockIdx.x + threadIdx.x] = r;
+    }
+}
+
+__global__ void k_bbox_fold(int nb, const double* __restrict__ part, double* __restrict__ out) {
+    if (threadIdx.x < 6) {
+        double r = part[threadIdx.x];
+        for (int b = 1; b < nb; ++b)
+            r = threadIdx.x < 3 ? fmin(r, part[6 * b + threadIdx.x]) : fmax(r, part[6 * b + threadIdx.x]);
+        out[threadIdx.x] = r;
+    }
+}
+
+struct Grid {
+    double lo[3], s[3];
+    int64_t B;
+};
+
+__device__ __forceinline__ int64_t axis_cell(double x, double lo, double s, int64_t B) {
+    const double c = floor((x - lo) * s);
+    if (!(c > 0.0)) return 0;  // also NaN
+    return c >= static_cast<double>(B - 1) ? B - 1 : static_cast<int64_t>(c);
+}
+
+__global__ void k_point_cell(int64_t V, const double* __restrict__ xyz, Grid g, int64_t* __restrict__ cell,
+                             int32_t* __restrict__ count) {
+    GRID_STRIDE_LOOP(i, V) {
+        const int64_t bx = axis_cell(xyz[3 * i], g.lo[0], g.s[0], g.B);
+        const int64_t by = axis_cell(xyz[3 * i + 1], g.lo[1], g.s[1], g.B);
+        const int64_t bz = axis_cell(xyz[3 * i + 2], g.lo[2], g.s[2], g.B);
+        const int64_t c = (bx * g.B + by) * g.B + bz;
+        cell[i] = c;
+        atomicAdd(count + c, 1);
+    }
+}
+
+// items i = 0..n-1 with bucket key[i] go to off[key] + (arrival slot); sorted per bucket afterwards
+__global__ void k_bucket_scatter(int64_t n, const int64_t* __restrict__ key, const int64_t* __restrict__ off,
+                                 int32_t* __restrict__ fill, int32_t* __restrict__ out) {
+    GRID_STRIDE_LOOP(i, n) {
+        const int64_t k = key[i];
+        out[off[k] + atomicAdd(fill + k, 1)] = (int32_t)i;
+    }
+}
+
+// each bucket's items ascending (original index): the order no longer depends on the atomics
+__global__ void k_bucket_sort(int64_t nb, const int64_t* __restrict__ off, int32_t* __restrict__ items) {
+    GRID_STRIDE_LOOP(b, nb) {
+        const int64_t a = off[b], e = off[b + 1];
+        for (int64_t i = a + 1; i < e; ++i) {
+            const int32_t v = items[i];
+            int64_t j = i;
+            while (j > a && items[j - 1] > v) {
+                items[j] = items[j - 1];
+                --j;
+            }
+            items[j] = v;
+        }
+    }
+}
+
+__global__ void k_apply_vperm(int64_t V, const int32_t* __restrict__ perm, const double* __restrict__ xyz,
+                              double* __restrict__ xyz_out, int32_t* __restrict__ inv) {
+    GRID_STRIDE_LOOP(i, V) {
+        const int32_t o = perm[i];
+        inv[o] = (int32_t)i;
+        xyz_out[3 * i] = xyz[3 * (int64_t)o];
+        xyz_out[3 * i + 1] = xyz[3 * (int64_t)o + 1];
+        xyz_out[3 * i + 2] = xyz[3 * (int64_t)o + 2];
+    }
+}
+
+// tet key: its smallest new vertex number; flags a vertex index out of range
+__global__ void k_tet_key(int64_t T, int64_t V, const int32_t* __restrict__ tets, const int32_t* __restrict__ inv,
+                          int64_t* __restrict__ key, int32_t* __restrict__ count, unsigned* __restrict__ err) {
+    GRID_STRIDE_LOOP(t, T) {
+        int32_t m = INT32_MAX;
+        bool ok = true;
+        for (int k = 0; k < 4; ++k) {
+            const int32_t v = tets[4 * t + k];
+            if (v < 0 || v >= V) {
+                ok = false;
+                break;
+            }
+            m = min(m, inv[v]);
+        }
+        if (!ok) {
+            atomicOr(err, 1u);
+            m = 0;
+        }
+        key[t] = m;
+        atomicAdd(count + m, 1);
+    }
+}
+
+__global__ void k_apply_tperm(int64_t T, const int32_t* __restrict__ tperm, const int32_t* __restrict__ tets,
+                              const int32_t* __restrict__ inv, int32_t* __restrict__ tets_out) {
+    GRID_STRIDE_LOOP(i, T) {
+        const int64_t o = tperm[i];
+        for (int k = 0; k < 4; ++k) tets_out[4 * i + k] = inv[tets[4 * o + k]];
+    }
+}
+
+}  // namespace
+
+extern "C" int dec_reorder(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets,
+                           double* xyz_out, int32_t* tets_out, int32_t* vperm_out, int32_t* tperm_out) {
+    if (!ctx) return DEC_EINVAL;
+    try {
+        DEC_REQUIRE(V > 0 && T > 0 && V < (int64_t(1) << 31) && T < (int64_t(1) << 31), DEC_EINVAL, "bad sizes");
+        DEC_REQUIRE(xyz && tets && xyz_out && tets_out, DEC_EINVAL, "NULL array");
+        DEC_REQUIRE(xyz_out != xyz && tets_out != tets, DEC_EINVAL, "outputs must not alias the inputs");
+        ctx->set_device();
+        hipStream_t s = ctx->stream;
+        // bounding box and the cell grid
+        const unsigned nb = grid_for(V, BLOCK, 1024);
+        DBuf<double> part, box;
+        part.alloc(ctx, 6 * (int64_t)nb);
+        box.alloc(ctx, 6);
+        hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(BLOCK), 0, s, V, xyz, part.p);
+        hipLaunchKernelGGL(k_bbox_fold, dim3(1), dim3(64), 0, s, (int)nb, part.p, box.p);
+        double bb[6];
+        std::memcpy(bb, ctx->readback(box.p, sizeof(bb)), sizeof(bb));
+        for (int a = 0; a < 3; ++a)
+            DEC_REQUIRE(std::isfinite(bb[a]) && std::isfinite(bb[3 + a]), DEC_EINVAL, "non-finite coordinates");
+        Grid g;
+        // B = the smallest integer with B^3 >= V (found exactly, whatever cbrt rounds to)
+        g.B = std::llround(std::cbrt(static_cast<double>(V)));
+        if (g.B < 1) g.B = 1;
+        while (g.B * g.B * g.B < V) ++g.B;
+        while (g.B > 1 && (g.B - 1) * (g.B - 1) * (g.B - 1) >= V) --g.B;
+        for (int a = 0; a < 3; ++a) {
+            g.lo[a] = bb[a];
+            const double ext = bb[3 + a] - bb[a];
+            g.s[a] = ext > 0.0 ? static_cast<double>(g.B) / ext : 0.0;
+        }
+        const int64_t ncell = g.B * g.B * g.B;
+        // vertices: counting sort on the cell, then by original index inside each cell
+        DBuf<int64_t> cell, coff;
+        DBuf<int32_t> ccount, cfill, perm, inv;
+        cell.alloc(ctx, V);
+        ccount.alloc(ctx, ncell);
+        ccount.zero();
+        hipLaunchKernelGGL(k_point_cell, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, xyz, g, cell.p, ccount.p);
+        coff.alloc(ctx, ncell + 1);
+        scan_exclusive_i32_to_i64(ctx, ccount.p, coff.p, ncell, false);
+        cfill.alloc(ctx, ncell);
+        cfill.zero();
+        perm.alloc(ctx, V);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, cell.p, coff.p, cfill.p, perm.p);
+        hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(ncell)), dim3(BLOCK), 0, s, ncell, coff.p, perm.p);
+        inv.alloc(ctx, V);
+        hipLaunchKernelGGL(k_apply_vperm, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, perm.p, xyz, xyz_out, inv.p);
+        // tets: counting sort on the smallest new vertex, then by original index
+        DBuf<int64_t> tkey, toff;
+        DBuf<int32_t> tcount, tfill, tperm;
+        DBuf<unsigned> err;
+        tkey.alloc(ctx, T);
+        tcount.alloc(ctx, V);
+        tcount.zero();
+        err.alloc(ctx, 1);
+        err.zero();
+        hipLaunchKernelGGL(k_tet_key, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, V, tets, inv.p, tkey.p, tcount.p, err.p);
+        const unsigned e = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
+        DEC_REQUIRE(e == 0, DEC_ETOPO, "tet vertex index out of range");
+        toff.alloc(ctx, V + 1);
+        scan_exclusive_i32_to_i64(ctx, tcount.p, toff.p, V, false);
+        tfill.alloc(ctx, V);
+        tfill.zero();
+        tperm.alloc(ctx, T);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tkey.p, toff.p, tfill.p, tperm.p);
+        hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, toff.p, tperm.p);
+        hipLaunchKernelGGL(k_apply_tperm, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tperm.p, tets, inv.p, tets_out);
+        HIP_CHECK(hipGetLastError());
+        if (vperm_out) HIP_CHECK(hipMemcpyAsync(vperm_out, perm.p, V * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (tperm_out) HIP_CHECK(hipMemcpyAsync(tperm_out, tperm.p, T * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        ctx->sync();  // the temporaries are released on return
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+    return DEC_OK;
+}

@@ -94,3 +94,17 @@ def test_energy_identity_and_cracks_lower_the_conductivity():
     K2, rhs2, s2 = D.mixed_system(xj, tets, bt, bv, side, cracks=W.penny_cracks(5, 4, 0.15, 0.3))
     T2 = spla.spsolve(K2.tocsc(), rhs2)[len(s2["W"]):]
     assert (s2["kappa"] == 0).any() and D.flux(T2, s2)["k_eff"] < f["k_eff"]
+
+
+def test_rms_error_of_eq15():
+    """Zero on the exact linear values, |delta| for a constant shift on the unit cube (the
+    volumes sum to 1), and one tet by hand."""
+    xyz, tets, *_ = _kuhn(3)
+    p = xyz[tets]
+    ct = O.circumcenter_tet(p[:, 0], p[:, 1], p[:, 2], p[:, 3])
+    exact = 1.0 - ct[:, 0]
+    assert D.rms_error_tets(xyz, tets, exact) == 0.0
+    assert abs(D.rms_error_tets(xyz, tets, exact + 1e-3) - 1e-3) < 1e-15
+    one = np.array([[0.0, 0, 0], [2, 0, 0], [0, 2, 0], [0, 0, 2]])
+    # circumcentre (1, 1, 1), volume 8/6; field 2x + 3y: exact 5 there, T = 7
+    assert abs(D.rms_error_tets(one, [[0, 1, 2, 3]], [7.0], (0.0, 2.0, 3.0, 0.0)) - 2.0 * np.sqrt(8 / 6)) < 1e-14
