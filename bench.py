@@ -358,11 +358,14 @@ def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
     return out
 
 
-def dual_inputs(n, dev, sigma=1.0, kseed=1, n_cracks=200, cseed=2):
-    """The tet-unknown workload: the default recipe with the conductivity on the faces."""
+def dual_inputs(n, dev, sigma=1.0, kseed=1, n_cracks=200, cseed=2, order=None, ctx=None):
+    """The tet-unknown workload: the default recipe with the conductivity on the faces (per face of
+    the lattice numbering; with `order`, the mesh is renumbered first and the faces follow)."""
     import torch
 
     xyz, tets = W.kuhn_cube(n, device=dev)
+    if order:
+        xyz, tets, _, _ = ctx.reorder(xyz, tets, order)
     F = W.kuhn_counts(n)["F"]
     bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
     return dict(n=n, xyz=xyz, tets=tets, kappa=torch.as_tensor(W.lognormal_kappa(F, sigma, kseed), device=dev),
@@ -407,10 +410,10 @@ def dual_cpu_baseline(n=20):
                       f"sparse LU for the solve) in {dt:.1f} s", "seconds": dt}
 
 
-def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True):
+def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True, order=None):
     import torch
 
-    inp = dual_inputs(n, dev)
+    inp = dual_inputs(n, dev, order=order, ctx=ctx)
     for _ in range(warmup):
         st, f, info, bms = dual_step(ctx, inp)
         print(f"[bench] dual warmup: build {bms:.1f} ms, {st['iterations']} its, {st['solve_ms']:.1f} ms solve",
@@ -428,7 +431,8 @@ def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True):
            "value": round(info["V"] * steps / elapsed, 1), "unit": "tets/s", "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": round(1e3 * elapsed / steps, 3), "higher_is_better": True,
            "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"kuhn{n}_face_lognormal1_cracks200_fp64_block_energy", "n": n, "tets": info["V"],
+           "config": {"workload": f"kuhn{n}_face_lognormal1_cracks200_fp64_block_energy"
+                                  + (f"_{order}_numbering" if order else ""), "n": n, "tets": info["V"],
                       "faces": info["faces"], "limited": info["limited"], "blocks": info["blocks"],
                       "max_block": info["max_block"], "nnz": info["nnz"], "tol": 1e-10,
                       "stopping": "A-norm error estimate (Hestenes-Stiefel, window 16)"},
@@ -454,7 +458,7 @@ def _max_tet_volume(xyz, tets):
                                   p[:, 3] - p[:, 0])).max() / 6.0)
 
 
-def _verify_mesh(ctx, dev, xyz, tets, tol=1e-12):
+def _verify_mesh(ctx, dev, xyz, tets, tol=1e-12, dual=True):
     """The pristine cube (Section 3.1): T = 1 / 0 on x = 0 / 1, kappa = 1, both unknown placements;
     eq. 15 RMS errors against 1 - x, k_eff, limited faces."""
     import torch
@@ -462,13 +466,20 @@ def _verify_mesh(ctx, dev, xyz, tets, tol=1e-12):
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
     bt, bv, side = (t(a) for a in W.x_faces(xyz))
     m = ctx.mesh(t(xyz), t(tets))
-    m.hodge1(want_cut=False, want_star=False)
+    _, star = m.hodge1(want_cut=False)
     m.assemble()
     m.apply_bc(bt, bv, want_rhs=False)
     Tv, sv, rcv = m.solve(tol=tol, check=False)
     fv = m.flux(Tv, side)
-    row = {"V": m.V, "T": m.T, "max_tet_volume": _max_tet_volume(xyz, tets),
-           "vertex": {"rms": m.rms_error(Tv), "k_eff": fv["k_eff"], "iterations": sv["iterations"], "status": rcv}}
+    # negative circumcentric dual areas (random Delaunay meshes) make the vertex operator indefinite:
+    # the solve then breaks down and has no error to report
+    vert = {"negative_dual_areas": int((star < 0).sum()), "iterations": sv["iterations"], "status": rcv}
+    if rcv == 0:
+        vert.update(rms=m.rms_error(Tv), k_eff=fv["k_eff"])
+    row = {"V": m.V, "T": m.T, "max_tet_volume": _max_tet_volume(xyz, tets), "vertex": vert}
+    if not dual:
+        m.close()
+        return row
     d = m.dual(bt, bv, side)
     Tt, st, rct = d.solve(tol=tol, check=False)
     ft = d.flux(Tt)
@@ -505,18 +516,31 @@ def _spmv_rate(ctx, dev, xyz, tets, steps=2):
             "iterations": st["iterations"]}
 
 
-def meshes_benchmark(ctx, dev, kuhn=(8, 16, 32, 64), delaunay=(2000, 8000, 32000, 128000), shuffle_n=128):
+def meshes_benchmark(ctx, dev, kuhn=(8, 16, 32, 64), lattice=(8, 16, 24, 32, 48), delaunay=(2000, 8000, 32000, 128000),
+                     shuffle_n=128):
     """General meshes: the eq. 15 convergence study over Kuhn cubes and Delaunay meshes of random
     points (the TetGen stand-in), and the SpMV on a scrambled numbering before and after the
     spatial numbering of Section 2.2."""
     import torch
 
     out = {"metric": "eq. 15 RMS error vs max tet volume; SpMV GB/s before / after spatial numbering",
-           "n_gpus": 1, "data": "synthetic", "convergence": {"kuhn": [], "delaunay": []}}
+           "n_gpus": 1, "data": "synthetic", "convergence": {"kuhn": [], "kuhn_jittered": [], "delaunay_lattice": [], "delaunay": []}}
     for n in kuhn:
         xyz, tets = W.kuhn_cube(n)
         out["convergence"]["kuhn"].append({"n": n, **_verify_mesh(ctx, dev, xyz, tets)})
         print(f"[bench] kuhn {n}: {out['convergence']['kuhn'][-1]}", file=sys.stderr, flush=True)
+        # interior nodes moved by up to 0.15 h: not Delaunay, so only the vertex unknowns apply
+        xj = W.jitter_interior(xyz, n, 0.15, n)
+        row = _verify_mesh(ctx, dev, xj, tets, dual=False)
+        out["convergence"]["kuhn_jittered"].append({"n": n, **row})
+        print(f"[bench] kuhn {n} jittered: {row}", file=sys.stderr, flush=True)
+    for n in lattice:
+        t0 = time.perf_counter()
+        xyz, tets = W.delaunay_lattice(n, 0.2, 3)
+        gen = time.perf_counter() - t0
+        row = {"n": n, "mesh_s": round(gen, 1), **_verify_mesh(ctx, dev, xyz, tets)}
+        out["convergence"]["delaunay_lattice"].append(row)
+        print(f"[bench] delaunay lattice {n}: {row}", file=sys.stderr, flush=True)
     for npts in delaunay:
         t0 = time.perf_counter()
         xyz, tets = W.delaunay_cube(npts, int(2 * npts ** (2.0 / 3.0)), 1)
@@ -539,8 +563,10 @@ def meshes_benchmark(ctx, dev, kuhn=(8, 16, 32, 64), delaunay=(2000, 8000, 32000
     torch.cuda.synchronize()
     reorder_ms = 1e3 * (time.perf_counter() - t0)
     after = _spmv_rate(ctx, dev, xr.cpu().numpy(), tr.cpu().numpy())
+    xm, tm, _, _ = ctx.reorder(torch.as_tensor(xs, device=dev), torch.as_tensor(ts, device=dev), "morton")
+    morton = _spmv_rate(ctx, dev, xm.cpu().numpy(), tm.cpu().numpy())
     out["numbering"] = {"workload": f"kuhn{shuffle_n}_homogeneous_scrambled_numbering", "scrambled": before,
-                        "spatial": after, "reorder_ms": round(reorder_ms, 3),
+                        "spatial": after, "morton": morton, "reorder_ms": round(reorder_ms, 3),
                         "spmv_speedup": round(before["spmv_us"] / after["spmv_us"], 2)}
     print(f"[bench] numbering: {out['numbering']}", file=sys.stderr, flush=True)
     return out
@@ -600,6 +626,8 @@ def main():
     ap.add_argument("--dual", action="store_true",
                     help="instead of the default line: the tet-unknown system (temperature per tet, flux per face)")
     ap.add_argument("--dual-n", type=int, default=128)
+    ap.add_argument("--dual-order", choices=["lexicographic", "morton"], default=None,
+                    help="renumber the tet workload first (dec_reorder)")
     ap.add_argument("--meshes", action="store_true",
                     help="instead of the default line: eq. 15 convergence study and the spatial numbering")
     ap.add_argument("--crack-growth", action="store_true",
@@ -624,7 +652,8 @@ def main():
         print(json.dumps(meshes_benchmark(ctx, dev)))
         return
     if args.dual:
-        print(json.dumps(dual_benchmark(ctx, dev, args.dual_n, args.steps, args.warmup, not args.no_cpu_baseline)))
+        print(json.dumps(dual_benchmark(ctx, dev, args.dual_n, args.steps, args.warmup, not args.no_cpu_baseline,
+                                        args.dual_order)))
         return
     if args.crack_growth:
         print(json.dumps({"metric": "crack growth k_eff(step), mixed vs FP64 wall time", "n_gpus": 1,

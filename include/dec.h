@@ -119,13 +119,19 @@ int dec_tetgen_read(const char* node_path, const char* ele_path, int64_t* V_out,
  * ties by original index.  Tets then go by their smallest new vertex number,
  * ties by original index, keeping their vertex order.  On a lattice with one
  * point per cell (a Kuhn cube) this is the lattice order.
+ * order: DEC_ORDER_LEXICOGRAPHIC (the above, the paper's) or DEC_ORDER_MORTON
+ * (cells by the interleaved bits of (x cell, y cell, z cell), z in the lowest
+ * bit, which keeps neighbours in all three directions close in memory; ties
+ * and tets as above).
  * xyz [V x 3] float64, tets [T x 4] int32 device inputs; xyz_out, tets_out
  * device outputs of the same shapes (not aliasing the inputs), tets_out
  * renumbered; vperm_out [V] (new -> old vertex) and tperm_out [T] (new -> old
  * tet) int32 device outputs, NULL ok.  DEC_ETOPO for a vertex index out of
  * range, DEC_EINVAL for non-finite coordinates.  Synchronises the stream. */
-int dec_reorder(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets, double* xyz_out,
-                int32_t* tets_out, int32_t* vperm_out, int32_t* tperm_out);
+#define DEC_ORDER_LEXICOGRAPHIC 0
+#define DEC_ORDER_MORTON 1
+int dec_reorder(dec_ctx* ctx, int32_t order, int64_t V, const double* xyz, int64_t T, const int32_t* tets,
+                double* xyz_out, int32_t* tets_out, int32_t* vperm_out, int32_t* tperm_out);
 
 /* ---- Hodge star *1 with conductivity and cracks (Sections 2.1, 2.5) ----
  * |*e| = sum over the edge's tets (ascending tet id) of the signed area of

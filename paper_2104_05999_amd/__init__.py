@@ -135,15 +135,16 @@ class Context:
     def mesh(self, xyz, tets):
         return Mesh(self, xyz, tets)
 
-    def reorder(self, xyz, tets):
-        """Spatial numbering (dec_reorder): returns (xyz, tets, vperm, tperm) device tensors, the
-        permutations mapping new to old indices."""
+    def reorder(self, xyz, tets, order="lexicographic"):
+        """Spatial numbering (dec_reorder), order "lexicographic" (the paper's z, y, x) or "morton":
+        returns (xyz, tets, vperm, tperm) device tensors, the permutations mapping new to old."""
+        code = {"lexicographic": 0, "morton": 1}[order]
         V, T = int(xyz.shape[0]), int(tets.shape[0])
         xo = torch.empty((V, 3), dtype=torch.float64, device=self.device)
         to = torch.empty((T, 4), dtype=torch.int32, device=self.device)
         vp = torch.empty(V, dtype=torch.int32, device=self.device)
         tp = torch.empty(T, dtype=torch.int32, device=self.device)
-        rc = self.lib.dec_reorder(self.handle, V, _ptr(xyz, torch.float64, 3 * V, "xyz"), T,
+        rc = self.lib.dec_reorder(self.handle, code, V, _ptr(xyz, torch.float64, 3 * V, "xyz"), T,
                                   _ptr(tets, torch.int32, 4 * T, "tets"), _ptr(xo, torch.float64),
                                   _ptr(to, torch.int32), _ptr(vp, torch.int32), _ptr(tp, torch.int32))
         self.check(rc, "dec_reorder")

@@ -121,7 +121,7 @@ SIGNATURES = {
     "dec_dual_faces": (c_int, [vp, vp, vp, vp, vp]),
     "dec_dual_info": (c_int, [vp] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     "dec_rms_error": (c_int, [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double), dp]),
-    "dec_reorder": (c_int, [vp, ctypes.c_int64, vp, ctypes.c_int64, vp, vp, vp, vp, vp]),
+    "dec_reorder": (c_int, [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_int64, vp, vp, vp, vp, vp]),
     "dec_tetgen_read": (c_int, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_int64), vp, vp, vp]),
     "dec_dual_flux": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]),

@@ -12,8 +12,10 @@
 // local index of the opposite vertex.  A boundary face is Dirichlet when its
 // three vertices carry Dirichlet data, with T0 their mean.  Tets in parts
 // joined to no Dirichlet face over conducting faces are pinned to 0.  The
-// system is returned as a mesh whose rows are the tets, so the solver, the
-// SpMV and FSAI apply unchanged.
+// system is returned as a mesh whose rows are the tets, so the solver applies
+// to it; its solver copy is built for the difference-form product (the
+// limited weights are many orders above the rest) and carries the block-Jacobi
+// inverse over the clusters of tets that limited faces join.
 //
 // Compiled without floating-point contraction: the Voronoi-edge end points
 // enter the crack predicate, which decides integers.
@@ -124,9 +126,9 @@ __global__ void k_dual_faces(int64_t F, const int4* __restrict__ tets, const dou
                              const int8_t* __restrict__ bc_type, const double* __restrict__ bc_value,
                              const int8_t* __restrict__ side, double* __restrict__ W, double* __restrict__ T0,
                              int8_t* __restrict__ kind, int8_t* __restrict__ fside, uint8_t* __restrict__ cut,
-                             uint8_t* __restrict__ limited, unsigned long long* __restrict__ n_limited) {
+                             uint8_t* __restrict__ limited, unsigned long long* __restrict__ counts) {
     __shared__ int lds[BLOCK / 64];
-    int nlim = 0;
+    int nlim = 0, nbnd = 0;
     RANGE_LOOP(f, F) {
         const int t = t1[f], k = k1[f], o = t2[f];
         const int4 q = tets[t];
@@ -164,6 +166,7 @@ __global__ void k_dual_faces(int64_t F, const int4* __restrict__ tets, const dou
         int8_t kd = 0, sd = 0;
         double t0 = 0.0;
         if (o < 0) {
+            ++nbnd;
             kd = 2;
             if (bc_type[va] == 1 && bc_type[vb] == 1 && bc_type[vc] == 1) {
                 kd = 1;
@@ -183,7 +186,9 @@ __global__ void k_dual_faces(int64_t F, const int4* __restrict__ tets, const dou
         limited[f] = lim;
     }
     const int total = block_sum(nlim, lds);
-    if (threadIdx.x == 0 && total) atomicAdd(n_limited, (unsigned long long)total);
+    if (threadIdx.x == 0 && total) atomicAdd(counts, (unsigned long long)total);
+    const int bnd = block_sum(nbnd, lds);
+    if (threadIdx.x == 0 && bnd) atomicAdd(counts + 3, (unsigned long long)bnd);
 }
 
 __global__ void k_dual_uf_init(int64_t T, int32_t* __restrict__ parent) {
@@ -537,8 +542,8 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
         D.side.alloc(ctx, F);
         D.cut.alloc(ctx, F);
         D.limited.alloc(ctx, F);
-        DBuf<unsigned long long> counts;  // limited faces, block clusters, largest block
-        counts.alloc(ctx, 3);
+        DBuf<unsigned long long> counts;  // limited faces, block clusters, largest block, boundary faces
+        counts.alloc(ctx, 4);
         counts.zero();
         hipLaunchKernelGGL(k_dual_faces, dim3(grid_xcd(F)), dim3(BLOCK), 0, s, F, tq, m->xyz.p, ct.p, D.t1.p, D.k1.p,
                            D.t2.p, limiter > 0.0 ? limiter : 1e-8, n_cracks, cracks, kappa_face, bc_type, bc_value,
@@ -636,22 +641,14 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
             HIP_CHECK(hipGetLastError());
             build_sell_copy(ctx, T, mnnz, m_ptr.p, m_col.p, m64.p, m32.p, d->blockinv);
             ctx->sync();  // the temporaries above are released on return
-            unsigned long long h[3];
+            unsigned long long h[4];
             std::memcpy(h, ctx->readback(counts.p, sizeof(h)), sizeof(h));
             D.n_limited = (int64_t)h[0];
             D.n_blocks = (int64_t)h[1];
             D.max_block = (int64_t)h[2];
+            d->Fb = (int64_t)h[3];
         }
         d->n_pinned = (int64_t) * static_cast<unsigned long long*>(ctx->readback(npin.p, sizeof(unsigned long long)));
-        int64_t nb = 0;
-        {
-            // boundary faces: read the kinds back once (a small count for dec_mesh_info)
-            std::vector<int8_t> kinds(F);
-            HIP_CHECK(hipMemcpyAsync(kinds.data(), D.kind.p, F, hipMemcpyDeviceToHost, s));
-            ctx->sync();
-            for (int8_t k : kinds) nb += k != 0;
-        }
-        d->Fb = nb;
         d->assembled = true;
         d->bc_ready = true;
         if (n_pinned_out) *n_pinned_out = d->n_pinned;

@@ -9,6 +9,9 @@
 // new vertex number, ties by original index, and keep their vertex order.
 // Counting sorts on the cell and on the smallest vertex, then a sort by
 // original index inside each cell or bucket, so the result is unique.
+// The Z (Morton) order is offered beside it: cells by the interleaved bits of
+// (x cell, y cell, z cell) (z in the lowest bit), which keeps neighbours in
+// all three directions close in memory.
 #include <cmath>
 #include <cstring>
 
@@ -58,13 +61,25 @@ __device__ __forceinline__ int64_t axis_cell(double x, double lo, double s, int6
     return c >= static_cast<double>(B - 1) ? B - 1 : static_cast<int64_t>(c);
 }
 
-__global__ void k_point_cell(int64_t V, const double* __restrict__ xyz, Grid g, int64_t* __restrict__ cell,
-                             int32_t* __restrict__ count) {
+// the bits of v (< 2^21) spread to every third position
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_point_cell(int64_t V, const double* __restrict__ xyz, Grid g, int morton,
+                             int64_t* __restrict__ cell, int32_t* __restrict__ count) {
     GRID_STRIDE_LOOP(i, V) {
         const int64_t bx = axis_cell(xyz[3 * i], g.lo[0], g.s[0], g.B);
         const int64_t by = axis_cell(xyz[3 * i + 1], g.lo[1], g.s[1], g.B);
         const int64_t bz = axis_cell(xyz[3 * i + 2], g.lo[2], g.s[2], g.B);
-        const int64_t c = (bx * g.B + by) * g.B + bz;
+        const int64_t c = morton ? (int64_t)((spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz))
+                                 : (bx * g.B + by) * g.B + bz;
         cell[i] = c;
         atomicAdd(count + c, 1);
     }
@@ -139,10 +154,12 @@ __global__ void k_apply_tperm(int64_t T, const int32_t* __restrict__ tperm, cons
 
 }  // namespace
 
-extern "C" int dec_reorder(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets,
-                           double* xyz_out, int32_t* tets_out, int32_t* vperm_out, int32_t* tperm_out) {
+extern "C" int dec_reorder(dec_ctx* ctx, int32_t order, int64_t V, const double* xyz, int64_t T,
+                           const int32_t* tets, double* xyz_out, int32_t* tets_out, int32_t* vperm_out,
+                           int32_t* tperm_out) {
     if (!ctx) return DEC_EINVAL;
     try {
+        DEC_REQUIRE(order == DEC_ORDER_LEXICOGRAPHIC || order == DEC_ORDER_MORTON, DEC_EINVAL, "unknown order");
         DEC_REQUIRE(V > 0 && T > 0 && V < (int64_t(1) << 31) && T < (int64_t(1) << 31), DEC_EINVAL, "bad sizes");
         DEC_REQUIRE(xyz && tets && xyz_out && tets_out, DEC_EINVAL, "NULL array");
         DEC_REQUIRE(xyz_out != xyz && tets_out != tets, DEC_EINVAL, "outputs must not alias the inputs");
@@ -170,14 +187,18 @@ extern "C" int dec_reorder(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T
             const double ext = bb[3 + a] - bb[a];
             g.s[a] = ext > 0.0 ? static_cast<double>(g.B) / ext : 0.0;
         }
-        const int64_t ncell = g.B * g.B * g.B;
+        // cell keys: lexicographic in [0, B^3), or Morton in [0, 2^(3k)) with 2^k >= B
+        int kbits = 0;
+        while ((int64_t(1) << kbits) < g.B) ++kbits;
+        const int64_t ncell = order == DEC_ORDER_MORTON ? int64_t(1) << (3 * kbits) : g.B * g.B * g.B;
         // vertices: counting sort on the cell, then by original index inside each cell
         DBuf<int64_t> cell, coff;
         DBuf<int32_t> ccount, cfill, perm, inv;
         cell.alloc(ctx, V);
         ccount.alloc(ctx, ncell);
         ccount.zero();
-        hipLaunchKernelGGL(k_point_cell, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, xyz, g, cell.p, ccount.p);
+        hipLaunchKernelGGL(k_point_cell, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, xyz, g,
+                           (int)(order == DEC_ORDER_MORTON), cell.p, ccount.p);
         coff.alloc(ctx, ncell + 1);
         scan_exclusive_i32_to_i64(ctx, ccount.p, coff.p, ncell, false);
         cfill.alloc(ctx, ncell);

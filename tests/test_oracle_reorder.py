@@ -59,3 +59,26 @@ def test_flat_and_degenerate_boxes():
     xyz = np.array([[0.0, 0.0, 0.5], [1.0, 0.0, 0.5], [0.0, 1.0, 0.5], [1.0, 1.0, 0.5]])
     c = point_cells(xyz, 2)
     assert (c[:, 2] == 0).all() and np.array_equal(c[:, 0], [0, 1, 0, 1])
+
+
+def test_morton_keys_and_octants():
+    """The interleave against bit-by-bit Python arithmetic; on a 4^3 lattice the Z order visits
+    each 2x2x2 octant as one run of 8 points, octants in Z order themselves."""
+    from oracle.reorder import morton_key
+    rng = np.random.Generator(np.random.PCG64(2))
+    c = rng.integers(0, 1 << 20, size=(50, 3))
+    for row, k in zip(c, morton_key(c)):
+        want = 0
+        for b in range(21):
+            want |= ((int(row[0]) >> b) & 1) << (3 * b + 2)
+            want |= ((int(row[1]) >> b) & 1) << (3 * b + 1)
+            want |= ((int(row[2]) >> b) & 1) << (3 * b)
+        assert int(k) == want
+    xyz, tets = W.kuhn_cube(3)
+    x2, t2, vp, tp = O.spatial_order(xyz, tets, order="morton")
+    cells = np.rint(x2 * 3).astype(int)  # lattice coordinates in the new order
+    octant = (cells // 2) @ np.array([4, 2, 1])
+    assert np.array_equal(octant, np.repeat(np.arange(8), 8))
+    assert np.array_equal(np.sort(vp), np.arange(len(xyz)))
+    m = t2.min(axis=1)
+    assert (np.diff(m) >= 0).all() and np.array_equal(t2, np.argsort(vp)[tets[tp]])

@@ -27,6 +27,7 @@ __all__ = [
     "jitter_interior",
     "x_sides",
     "delaunay_cube",
+    "delaunay_lattice",
     "x_faces",
     "lognormal_kappa",
     "penny_cracks",
@@ -134,6 +135,27 @@ def delaunay_cube(n_interior: int, n_face: int, seed: int):
             pts.append(p)
     pts.append(rng.random((n_interior, 3)))
     xyz = np.concatenate(pts)
+    tets = scipy.spatial.Delaunay(xyz).simplices.astype(np.int64)
+    p = xyz[tets]
+    vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0]) / 6.0
+    keep = np.abs(vol) > 1e-12
+    tets, vol = tets[keep], vol[keep]
+    tets[vol < 0] = tets[vol < 0][:, [0, 2, 1, 3]]
+    return xyz, np.ascontiguousarray(tets, dtype=np.int32)
+
+
+def delaunay_lattice(n: int, jitter: float, seed: int):
+    """Delaunay tetrahedralisation of a jittered lattice of the unit cube (a quality mesh, the
+    closer stand-in for the paper's TetGen meshes: few slivers, near-uniform sizes).
+
+    Points: the (n+1)^3 lattice x = (i, j, k)/n with interior points moved as in
+    ``jitter_interior(..., n, jitter, seed)`` (boundary points stay on the lattice, so the cube's
+    faces are planes of points).  Tets from scipy's Qhull Delaunay; simplices of volume <= 1e-12
+    (flat ones on coplanar hull points) dropped, every tet ordered to positive volume.
+    Returns ``xyz`` float64 [V,3] and ``tets`` int32 [T,4].
+    """
+    import scipy.spatial
+    xyz = jitter_interior(kuhn_cube(n)[0], n, jitter, seed)
     tets = scipy.spatial.Delaunay(xyz).simplices.astype(np.int64)
     p = xyz[tets]
     vol = np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0]) / 6.0
