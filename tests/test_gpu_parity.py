@@ -459,3 +459,38 @@ def test_nonfinite_conductivity_breaks_down(ctx, dev):
         assert rc == -5  # DEC_EBREAKDOWN, reported rather than a silent NaN solution
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("unroll,nt", [(2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1)])
+def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt):
+    """The autotuner's variants (pairs in flight, non-temporal loads) sum every row in the same
+    order and fold the partials in the same order: pinned through the environment, each gives
+    the tuned solve's bits, on a vertex system and on a tet system, in FP64 and with FP32 inner
+    solves."""
+    import os
+    import paper_2104_05999_amd as dec
+    s = _system(12, n_cracks=20)
+    m, _, _, _, _ = _gpu(ctx, s, dev)
+    ref = [m.solve(tol=1e-11, precision=p)[0] for p in (0, 1)]
+    xyz, tets = W.kuhn_cube(7)
+    bt, bv, side = W.x_sides(7)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    kap = t(W.lognormal_kappa(W.kuhn_counts(7)["F"], 1.0, 3))
+    mt = ctx.mesh(t(xyz), t(tets))
+    d = mt.dual(t(bt), t(bv), t(side), kap, t(W.penny_cracks(5, 9, 0.1, 0.3)))
+    mt.close()
+    ref_d = d.solve(tol=1e-11)[0]
+    d.close()
+    os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"] = str(unroll), str(nt)
+    try:
+        m2, _, _, _, _ = _gpu(ctx, s, dev)
+        for p, r in zip((0, 1), ref):
+            T, st, rc = m2.solve(tol=1e-11, precision=p)
+            assert rc == 0 and torch.equal(T, r), p
+        mt = ctx.mesh(t(xyz), t(tets))
+        d = mt.dual(t(bt), t(bv), t(side), kap, t(W.penny_cracks(5, 9, 0.1, 0.3)))
+        mt.close()
+        assert torch.equal(d.solve(tol=1e-11)[0], ref_d)
+        d.close()
+    finally:
+        del os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"]
