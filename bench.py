@@ -296,15 +296,14 @@ def crack_growth(ctx, dev, n=256, steps=51, n_discs=1000, seed=4):
     return out
 
 
-def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
-    """Section 3's cracking processes on homogeneous Kuhn cubes: the deterministic one (crack the
-    face of largest flux density) on n_det^3, and `paths` Monte Carlo paths (faces in seeded random
-    orders) on n_mc^3, each until the domain stops conducting (k_eff <= 1e-12 of its start).
+def _cracking_path(ctx, dev, n, order=None, max_steps=100000):
+    """One cracking process on a homogeneous Kuhn n^3 cube, on ctx's stream: crack a face per step
+    (largest flux density, or the next of `order`), re-solve, until k_eff <= 1e-12 of its start.
     Every step: conductivity with the new zero, *1, assembly, boundary data, a warm-started FP64
     solve to 1e-10, flux (and, deterministic, the largest-flux-density face)."""
     import torch
 
-    def run(n, order=None, max_steps=100000):
+    with torch.cuda.stream(ctx.stream):
         xyz, tets = W.kuhn_cube(n, device=dev)
         bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
         mesh = ctx.mesh(xyz, tets)
@@ -312,7 +311,6 @@ def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
         _, star = mesh.hodge1(kappa, want_cut=False)
         n_faces = int((star != 0).sum())
         T, ks, steps = None, [], 0
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         while True:
             mesh.hodge1(kappa, want_cut=False, want_star=False)
@@ -331,30 +329,87 @@ def cracking_processes(ctx, dev, n_det=16, n_mc=8, paths=8, seed=7):
                 break
             kappa[e] = 0.0
             steps += 1
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         sec = time.perf_counter() - t0
         mesh.close()
-        print(f"[bench] cracking n={n} {'deterministic' if order is None else 'stochastic'}: {steps} cracks, "
-              f"k_eff {ks[0]:.6f} -> {ks[-1]:.3e}, {sec:.2f} s", file=sys.stderr, flush=True)
-        return {"steps": steps, "faces": n_faces, "D_n_at_separation": steps / n_faces, "seconds": round(sec, 3),
-                "steps_per_sec": round((steps + 1) / sec, 1), "status": rc,
-                "k_eff_curve": [round(ks[i], 6) for i in range(0, len(ks), max(1, len(ks) // 40))]}
+    return {"steps": steps, "faces": n_faces, "D_n_at_separation": steps / n_faces, "seconds": round(sec, 3),
+            "steps_per_sec": round((steps + 1) / sec, 1), "status": rc,
+            "k_eff_curve": [round(ks[i], 6) for i in range(0, len(ks), max(1, len(ks) // 40))]}
 
-    out = {"deterministic": {"workload": f"kuhn{n_det}_homogeneous", **run(n_det)}}
-    xyz, tets = W.kuhn_cube(n_mc)
+
+def _faces_of(ctx, dev, n):
+    import torch
+
+    xyz, tets = W.kuhn_cube(n)
     probe = ctx.mesh(torch.as_tensor(xyz, device=dev), torch.as_tensor(tets, device=dev))
     _, star = probe.hodge1(torch.ones(probe.E, dtype=torch.float64, device=dev), want_cut=False)
-    face_ids = torch.nonzero(star != 0).flatten().cpu().numpy()
+    ids = torch.nonzero(star != 0).flatten().cpu().numpy()
     probe.close()
-    rng = np.random.Generator(np.random.PCG64(seed))
-    mc = [run(n_mc, order=rng.permutation(face_ids)) for _ in range(paths)]
-    dn = [p["D_n_at_separation"] for p in mc]
-    out["stochastic"] = {"workload": f"kuhn{n_mc}_homogeneous_{paths}paths_seed{seed}", "paths": paths,
-                         "D_n_at_separation": {"mean": round(float(np.mean(dn)), 4), "min": round(min(dn), 4),
-                                               "max": round(max(dn), 4)},
-                         "steps": sum(p["steps"] for p in mc), "seconds": round(sum(p["seconds"] for p in mc), 3),
-                         "steps_per_sec": round(sum(p["steps"] + 1 for p in mc) / sum(p["seconds"] for p in mc), 1),
-                         "k_eff_curve_path0": mc[0]["k_eff_curve"]}
+    return ids
+
+
+def _parallel_paths(dev, n, orders, threads):
+    """Monte Carlo paths driven from `threads` host threads, each with its own context on its own
+    stream (the library's calls release the interpreter lock), so the paths' small kernels overlap."""
+    import threading
+
+    import torch
+
+    import paper_2104_05999_amd as dec
+
+    ctxs = [dec.Context(dev, stream=torch.cuda.Stream(dev)) for _ in range(threads)]
+    out = [None] * len(orders)
+    errors = []
+
+    def worker(tid):
+        try:
+            for i in range(tid, len(orders), threads):
+                out[i] = _cracking_path(ctxs[tid], dev, n, order=orders[i])
+                print(f"[bench] cracking n={n} stochastic path {i}: {out[i]['steps']} cracks, "
+                      f"{out[i]['seconds']:.2f} s", file=sys.stderr, flush=True)
+        except Exception as exc:  # reported after the join
+            errors.append(exc)
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    if errors:
+        raise errors[0]
+    return out, wall
+
+
+def cracking_processes(ctx, dev, n_det=(16, 24), n_mc=(8, 16), paths=8, threads=8, seed=7):
+    """Section 3's cracking processes on homogeneous Kuhn cubes: the deterministic one (crack the
+    face of largest flux density) on each n_det^3 (24^3 has 45,000 faces, the size of the paper's
+    mesh), and `paths` Monte Carlo paths (faces in seeded random orders) on each n_mc^3, run
+    concurrently from `threads` host threads, each until the domain stops conducting."""
+    out = {"deterministic": [], "stochastic": []}
+    for n in n_det:
+        r = _cracking_path(ctx, dev, n)
+        print(f"[bench] cracking n={n} deterministic: {r['steps']} cracks, D_n {r['D_n_at_separation']:.4f}, "
+              f"{r['seconds']:.2f} s", file=sys.stderr, flush=True)
+        out["deterministic"].append({"workload": f"kuhn{n}_homogeneous", **r})
+    for n in n_mc:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        faces = _faces_of(ctx, dev, n)
+        orders = [rng.permutation(faces) for _ in range(paths)]
+        mc, wall = _parallel_paths(dev, n, orders, threads)
+        dn = [p["D_n_at_separation"] for p in mc]
+        steps = sum(p["steps"] + 1 for p in mc)
+        out["stochastic"].append({
+            "workload": f"kuhn{n}_homogeneous_{paths}paths_seed{seed}", "paths": paths, "threads": threads,
+            "faces": mc[0]["faces"],
+            "D_n_at_separation": {"mean": round(float(np.mean(dn)), 4), "min": round(min(dn), 4),
+                                  "max": round(max(dn), 4)},
+            "steps": steps, "wall_seconds": round(wall, 3), "steps_per_sec": round(steps / wall, 1),
+            "k_eff_curve_path0": mc[0]["k_eff_curve"]})
     return out
 
 

@@ -120,3 +120,54 @@ def test_stochastic_path_against_oracle(ctx, dev):
         assert all(a >= b - 1e-12 * k0 for a, b in zip(ks, ks[1:]))
     finally:
         m.close()
+
+
+def test_paths_from_parallel_threads_match_sequential(dev):
+    """Cracking paths driven from several host threads, each with its own context and stream (as
+    the benchmark runs its Monte Carlo paths), give the same k_eff after every crack, bit for bit,
+    as the same paths run one after another."""
+    import threading
+
+    import paper_2104_05999_amd as dec
+    n, paths, steps = 4, 4, 25
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, side = W.x_sides(n)
+    E = W.kuhn_counts(n)["E"]
+    rng = np.random.Generator(np.random.PCG64(12))
+    orders = [rng.permutation(E)[:steps] for _ in range(paths)]
+
+    def run(ctx, order):
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+        with torch.cuda.stream(ctx.stream):
+            m = ctx.mesh(t(xyz), t(tets))
+            kappa = torch.ones(m.E, dtype=torch.float64, device=dev)
+            T, ks = None, []
+            for e in order:
+                kappa[int(e)] = 0.0
+                m.hodge1(kappa, want_cut=False, want_star=False)
+                m.assemble()
+                m.apply_bc(t(bt), t(bv), want_rhs=False)
+                T, st, rc = m.solve(T=T, tol=1e-10, warm_start=T is not None, check=False)
+                ks.append(m.flux(T, t(side))["k_eff"] if rc == 0 else rc)
+            m.close()
+            torch.cuda.current_stream().synchronize()
+        return ks
+
+    c0 = dec.Context(dev, stream=torch.cuda.Stream(dev))
+    seq = [run(c0, o) for o in orders]
+    c0.close()
+    ctxs = [dec.Context(dev, stream=torch.cuda.Stream(dev)) for _ in range(2)]
+    par = [None] * paths
+
+    def worker(tid):
+        for i in range(tid, paths, 2):
+            par[i] = run(ctxs[tid], orders[i])
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    for c in ctxs:
+        c.close()
+    assert par == seq
