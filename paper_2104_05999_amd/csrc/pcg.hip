@@ -502,9 +502,12 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             // queued behind other work like the untimed ones (the first launch of a batch follows
             // the host's read of the state and starts on an idle device)
             const int every = o.profile;
+            // timing-only events: no system-scope fence (its cache writeback and invalidation
+            // would lengthen the timed launch and slow the work after it); the elapsed times
+            // are read after the batch's stream synchronisation
             while ((int)c->events.size() < 2 * chunk) {
                 hipEvent_t e;
-                HIP_CHECK(hipEventCreate(&e));
+                HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                 c->events.push_back(e);
             }
             if (batch == 0) last_iter = read_state(c, R.st).iter;
