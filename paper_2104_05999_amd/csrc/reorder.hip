@@ -73,8 +73,10 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
 }
 
 __global__ void k_point_cell(int64_t V, const double* __restrict__ xyz, Grid g, int morton,
-                             int64_t* __restrict__ cell, int32_t* __restrict__ count) {
+                             int64_t* __restrict__ cell, int32_t* __restrict__ count, unsigned* __restrict__ err) {
     GRID_STRIDE_LOOP(i, V) {
+        // the box ignores NaN (fmin / fmax), so a NaN coordinate is caught here
+        if (!(isfinite(xyz[3 * i]) && isfinite(xyz[3 * i + 1]) && isfinite(xyz[3 * i + 2]))) atomicOr(err, 1u);
         const int64_t bx = axis_cell(xyz[3 * i], g.lo[0], g.s[0], g.B);
         const int64_t by = axis_cell(xyz[3 * i + 1], g.lo[1], g.s[1], g.B);
         const int64_t bz = axis_cell(xyz[3 * i + 2], g.lo[2], g.s[2], g.B);
@@ -194,11 +196,16 @@ extern "C" int dec_reorder(dec_ctx* ctx, int32_t order, int64_t V, const double*
         // vertices: counting sort on the cell, then by original index inside each cell
         DBuf<int64_t> cell, coff;
         DBuf<int32_t> ccount, cfill, perm, inv;
+        DBuf<unsigned> bad;
         cell.alloc(ctx, V);
         ccount.alloc(ctx, ncell);
         ccount.zero();
+        bad.alloc(ctx, 1);
+        bad.zero();
         hipLaunchKernelGGL(k_point_cell, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, xyz, g,
-                           (int)(order == DEC_ORDER_MORTON), cell.p, ccount.p);
+                           (int)(order == DEC_ORDER_MORTON), cell.p, ccount.p, bad.p);
+        DEC_REQUIRE(*static_cast<unsigned*>(ctx->readback(bad.p, sizeof(unsigned))) == 0, DEC_EINVAL,
+                    "non-finite coordinates");
         coff.alloc(ctx, ncell + 1);
         scan_exclusive_i32_to_i64(ctx, ccount.p, coff.p, ncell, false);
         cfill.alloc(ctx, ncell);

@@ -188,3 +188,51 @@ def test_linear_solution_verification(ctx, dev):
     ro = D.rms_error_tets(xyz, tets, To)
     print("rms vertex", rms_v, "tets", rms_t, "oracle tets", ro, flush=True)
     assert abs(rms_t - ro) <= 1e-6 * ro + 1e-12
+
+
+def test_error_paths_of_the_mesh_calls(ctx, dev):
+    """Bad arguments and calls on the wrong kind of mesh return status codes, and the context keeps
+    working after each."""
+    import ctypes
+    import paper_2104_05999_amd as dec
+    from paper_2104_05999_amd import _lib
+    L = _lib.load()
+    xyz, tets = W.kuhn_cube(3)
+    x, t = _t(xyz, dev), _t(tets, dev)
+    out_x = torch.empty_like(x)
+    out_t = torch.empty_like(t)
+    vp = lambda a: ctypes.c_void_p(a.data_ptr())  # noqa: E731
+    EINVAL, ESTATE = -1, -8
+    assert L.dec_reorder(ctx.handle, 0, 0, vp(x), len(tets), vp(t), vp(out_x), vp(out_t), None, None) == EINVAL
+    assert L.dec_reorder(ctx.handle, 5, len(xyz), vp(x), len(tets), vp(t), vp(out_x), vp(out_t), None,
+                         None) == EINVAL
+    assert L.dec_reorder(ctx.handle, 0, len(xyz), vp(x), len(tets), vp(t), vp(x), vp(out_t), None, None) == EINVAL
+    assert L.dec_reorder(None, 0, len(xyz), vp(x), len(tets), vp(t), vp(out_x), vp(out_t), None, None) == EINVAL
+    bad = x.clone()
+    bad[3, 1] = float("nan")
+    with pytest.raises(dec.DecError):
+        ctx.reorder(bad, t)
+    m = ctx.mesh(x, t)
+    try:
+        f = (ctypes.c_double * 4)(1.0, -1.0, 0.0, 0.0)
+        r = ctypes.c_double()
+        T = torch.zeros(m.V, dtype=torch.float64, device=dev)
+        assert L.dec_rms_error(m.handle, 2, vp(T), f, ctypes.byref(r)) == EINVAL
+        assert L.dec_rms_error(m.handle, 0, None, f, ctypes.byref(r)) == EINVAL
+        bt, bv, side = W.x_sides(3)
+        d = m.dual(_t(bt, dev), _t(bv, dev), _t(side, dev))
+        try:
+            Td = torch.zeros(d.V, dtype=torch.float64, device=dev)
+            assert L.dec_rms_error(d.handle, 1, vp(Td), f, ctypes.byref(r)) == ESTATE
+            assert L.dec_dual_flux(d.handle, vp(Td), 1.0, 0.0, 1.0, None, None, None, None) == EINVAL
+            assert L.dec_dual_faces(m.handle, None, None, None, None) == EINVAL  # not a tet system
+            assert L.dec_dual_info(m.handle, None, None, None, None) == EINVAL
+            assert L.dec_dual_build(None, None, 0, None, None, None, None, 0.0, None, None) == EINVAL
+            assert L.dec_dual_build(m.handle, None, -1, None, vp(_t(bt, dev)), vp(_t(bv, dev)), None, 0.0,
+                                    ctypes.byref(ctypes.c_void_p()), None) == EINVAL
+        finally:
+            d.close()
+        # still working
+        assert abs(m.rms_error(_t(1.0 - xyz[:, 0], dev))) < 1e-15
+    finally:
+        m.close()
