@@ -50,7 +50,8 @@ extern "C" {
 #define DEC_ENOTCONV (-4)    /* max_iters reached before the tolerance                 */
 #define DEC_EBREAKDOWN (-5)  /* CG breakdown: p.Ap <= 0 or a non-finite scalar         */
 #define DEC_ETOPO (-6)       /* invalid mesh: index out of range, repeated vertex,
-                                zero-volume tet, face shared by more than two tets      */
+                                non-finite coordinate, zero-volume tet, face shared by
+                                more than two tets                                       */
 #define DEC_EBUDGET (-7)     /* request does not fit the server's HBM budget           */
 #define DEC_ESTATE (-8)      /* call out of order (e.g. solve before apply_bc)         */
 #define DEC_ECANCELED (-9)   /* a served request was cancelled                          */

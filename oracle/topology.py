@@ -92,8 +92,9 @@ def check_mesh(xyz, tets):
     """Validity of a tet mesh as the path requires it.
 
     Returns a string naming the first problem found, or None: an index out of
-    [0, V), a tet repeating a vertex, a tet of zero volume, or a face shared
-    by more than two tets (not a 3-manifold with boundary).
+    [0, V), a tet repeating a vertex, a tet with a non-finite vertex
+    coordinate, a tet of zero volume, or a face shared by more than two tets
+    (not a 3-manifold with boundary).
     """
     xyz = np.asarray(xyz, dtype=np.float64)
     tets = np.asarray(tets, dtype=np.int64)
@@ -104,8 +105,11 @@ def check_mesh(xyz, tets):
     if np.any(s[:, 1:] == s[:, :-1]):
         return "repeated vertex"
     p = xyz[tets]
-    a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
-    det = (a * np.cross(b, c)).sum(axis=1)
+    with np.errstate(invalid="ignore"):  # inf - inf in a tet with an infinite coordinate
+        a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
+        det = (a * np.cross(b, c)).sum(axis=1)
+    if not np.all(np.isfinite(det)):
+        return "non-finite coordinate"
     if np.any(det == 0.0):
         return "zero volume"
     if len(tets):

@@ -48,6 +48,7 @@ __global__ void k_tet_check(const int4* __restrict__ tets, int64_t T, int64_t V,
         const double cx = p3[0] - p0[0], cy = p3[1] - p0[1], cz = p3[2] - p0[2];
         const double det = (ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz)) + az * (bx * cy - by * cx);
         if (det == 0.0) atomicOr(err, 4u);
+        if (!isfinite(det)) atomicOr(err, 32u);  // a NaN or infinite coordinate
     }
 }
 
@@ -331,6 +332,7 @@ __global__ void k_faces(int64_t T, const int32_t* __restrict__ tet_edge, const i
 std::string topo_message(unsigned err) {
     if (err & 1u) return "tet vertex index out of range";
     if (err & 2u) return "tet repeats a vertex";
+    if (err & 32u) return "non-finite vertex coordinate";
     if (err & 4u) return "tet of zero volume";
     if (err & 16u) return "face shared by more than two tets";
     if (err & 8u) return "internal: lower edge not found";

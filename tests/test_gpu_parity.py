@@ -116,7 +116,7 @@ def test_topology_independent_of_tet_order(ctx, dev):
     assert np.array_equal(m.edges().cpu().numpy(), O.edges_of(tets, len(xyz)))
 
 
-@pytest.mark.parametrize("case", ["range", "repeat", "flat", "shared_face"])
+@pytest.mark.parametrize("case", ["range", "repeat", "flat", "shared_face", "nan"])
 def test_invalid_mesh_rejected(ctx, dev, case):
     import paper_2104_05999_amd as dec
     xyz, tets = W.kuhn_cube(2)
@@ -129,6 +129,9 @@ def test_invalid_mesh_rejected(ctx, dev, case):
     elif case == "flat":
         xyz = xyz.copy()
         xyz[:, 2] = 0.0
+    elif case == "nan":
+        xyz = xyz.copy()
+        xyz[7, 1] = np.nan
     else:
         tets = np.concatenate([tets, tets[:1]])
     with pytest.raises(dec.DecError) as ei:

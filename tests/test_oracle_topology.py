@@ -96,6 +96,10 @@ def test_check_mesh_errors():
     assert O.check_mesh(flat, tets) == "zero volume"
     dup = np.concatenate([tets, tets[:1]])
     assert O.check_mesh(xyz, dup) == "face shared by more than two tets"
+    for v in (np.nan, np.inf):
+        odd = xyz.copy()
+        odd[7, 1] = v
+        assert O.check_mesh(odd, tets) == "non-finite coordinate"
 
 
 def test_boundary_faces_match_face_counts():
