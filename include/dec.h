@@ -338,7 +338,9 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
                    dec_mesh** dual_out, int64_t* n_pinned_out);
 
 /* Counts of a tet system (host outputs, each NULL ok): faces, limited faces,
- * clusters inverted as blocks by DEC_PRECOND_BLOCK, the largest of them. */
+ * clusters inverted as blocks by DEC_PRECOND_BLOCK, the largest of them.
+ * This call, dec_dual_faces and dec_dual_flux return DEC_ESTATE for a mesh
+ * of vertex unknowns. */
 int dec_dual_info(const dec_mesh* d, int64_t* n_faces, int64_t* n_limited, int64_t* n_blocks,
                   int64_t* max_block);
 

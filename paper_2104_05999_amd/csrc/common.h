@@ -63,6 +63,13 @@ struct dec_ctx {
     void* readback(const void* dptr, size_t bytes);
 };
 
+// A required pointer argument was NULL: record which call on the context (when
+// one is reachable) and return DEC_EINVAL.
+inline int null_argument(dec_ctx* ctx, const char* call) {
+    if (ctx) ctx->last_error = std::string(call) + ": a required pointer argument is NULL";
+    return DEC_EINVAL;
+}
+
 // Device buffer owned through the context's allocator.
 template <class T>
 struct DBuf {

@@ -484,6 +484,12 @@ __global__ void k_dual_flux_fold(int G, const double* __restrict__ partials, dou
     }
 }
 
+// A call for tet systems was given a mesh of vertex unknowns.
+int not_dual(dec_ctx* ctx, const char* call) {
+    ctx->last_error = std::string(call) + " takes a tet system from dec_dual_build";
+    return DEC_ESTATE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -491,7 +497,8 @@ extern "C" {
 int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, const double* cracks,
                    const int8_t* bc_type, const double* bc_value, const int8_t* side, double limiter,
                    dec_mesh** dual_out, int64_t* n_pinned_out) {
-    if (!m || !dual_out || !bc_type || !bc_value) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!dual_out || !bc_type || !bc_value) return null_argument(m->ctx, "dec_dual_build");
     *dual_out = nullptr;
     dec_ctx* ctx = m->ctx;
     dec_mesh* d = nullptr;
@@ -665,7 +672,8 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
 }
 
 int dec_dual_faces(const dec_mesh* d, int32_t* face_tets, int32_t* face_local, double* weight, uint8_t* cut) {
-    if (!d || !d->dual) return DEC_EINVAL;
+    if (!d) return DEC_EINVAL;
+    if (!d->dual) return not_dual(d->ctx, "dec_dual_faces");
     try {
         const DualData& D = *d->dual;
         hipStream_t s = d->ctx->stream;
@@ -692,7 +700,8 @@ int dec_dual_faces(const dec_mesh* d, int32_t* face_tets, int32_t* face_local, d
 }
 
 int dec_dual_info(const dec_mesh* d, int64_t* n_faces, int64_t* n_limited, int64_t* n_blocks, int64_t* max_block) {
-    if (!d || !d->dual) return DEC_EINVAL;
+    if (!d) return DEC_EINVAL;
+    if (!d->dual) return not_dual(d->ctx, "dec_dual_info");
     const DualData& D = *d->dual;
     if (n_faces) *n_faces = D.F;
     if (n_limited) *n_limited = D.n_limited;
@@ -703,7 +712,9 @@ int dec_dual_info(const dec_mesh* d, int64_t* n_faces, int64_t* n_limited, int64
 
 int dec_dual_flux(dec_mesh* d, const double* T, double length, double area, double dT, double* k_eff, double* q_in,
                   double* q_out, double* energy) {
-    if (!d || !d->dual || !T) return DEC_EINVAL;
+    if (!d) return DEC_EINVAL;
+    if (!d->dual) return not_dual(d->ctx, "dec_dual_flux");
+    if (!T) return null_argument(d->ctx, "dec_dual_flux");
     dec_ctx* ctx = d->ctx;
     try {
         DEC_REQUIRE(area > 0.0 && length > 0.0 && dT != 0.0, DEC_EINVAL, "bad length/area/dT");

@@ -160,7 +160,8 @@ __global__ __launch_bounds__(BLOCK) void k_max_flux_final(int nb, const double* 
 
 extern "C" int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int64_t* edge_out,
                                  double* density_out) {
-    if (!m || !T || !edge_out) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!T || !edge_out) return null_argument(m->ctx, "dec_max_flux_edge");
     dec_ctx* ctx = m->ctx;
     try {
         DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_max_flux_edge is for meshes of vertex unknowns");
@@ -193,7 +194,8 @@ extern "C" int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* el
 extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* side, double length,
                                                double area, double dT, double* k_eff, double* q_in, double* q_out,
                                                double* energy, double* edge_flux_out) {
-    if (!m || !T) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!T) return null_argument(m->ctx, "dec_flux_effective_conductivity");
     dec_ctx* ctx = m->ctx;
     try {
         DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_flux_effective_conductivity is for meshes of vertex unknowns");

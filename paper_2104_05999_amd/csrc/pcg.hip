@@ -812,7 +812,8 @@ int dec_solve_opts_default(dec_solve_opts* o) {
 }
 
 int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats) {
-    if (!m || !opts || !T) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!opts || !T) return null_argument(m->ctx, "dec_solve");
     dec_ctx* ctx = m->ctx;
     try {
         const dec_solve_opts& o = *opts;
@@ -888,7 +889,8 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
 }
 
 int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void* y) {
-    if (!m || !x || !y) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!x || !y) return null_argument(m->ctx, "dec_spmv");
     dec_ctx* ctx = m->ctx;
     try {
         DEC_REQUIRE(m->assembled, DEC_ESTATE, "dec_spmv needs dec_assemble first");

@@ -7,13 +7,17 @@
 // [0, B-1], and points are ordered by (x cell, y cell, z cell) with the z cell
 // fastest, ties by original index.  Tets are then ordered by their smallest
 // new vertex number, ties by original index, and keep their vertex order.
-// Counting sorts on the cell and on the smallest vertex, then a sort by
-// original index inside each cell or bucket, so the result is unique.
+// Both orders come from a stable radix sort of (key, original index) pairs
+// with the indices in ascending order, so the result is unique, and its cost
+// is linear however unevenly the points fill the cells.
 // The Z (Morton) order is offered beside it: cells by the interleaved bits of
 // (x cell, y cell, z cell) (z in the lowest bit), which keeps neighbours in
 // all three directions close in memory.
 #include <cmath>
 #include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "common.h"
 
@@ -73,42 +77,15 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {
 }
 
 __global__ void k_point_cell(int64_t V, const double* __restrict__ xyz, Grid g, int morton,
-                             int64_t* __restrict__ cell, int32_t* __restrict__ count, unsigned* __restrict__ err) {
+                             uint64_t* __restrict__ cell, unsigned* __restrict__ err) {
     GRID_STRIDE_LOOP(i, V) {
         // the box ignores NaN (fmin / fmax), so a NaN coordinate is caught here
         if (!(isfinite(xyz[3 * i]) && isfinite(xyz[3 * i + 1]) && isfinite(xyz[3 * i + 2]))) atomicOr(err, 1u);
         const int64_t bx = axis_cell(xyz[3 * i], g.lo[0], g.s[0], g.B);
         const int64_t by = axis_cell(xyz[3 * i + 1], g.lo[1], g.s[1], g.B);
         const int64_t bz = axis_cell(xyz[3 * i + 2], g.lo[2], g.s[2], g.B);
-        const int64_t c = morton ? (int64_t)((spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz))
-                                 : (bx * g.B + by) * g.B + bz;
-        cell[i] = c;
-        atomicAdd(count + c, 1);
-    }
-}
-
-// items i = 0..n-1 with bucket key[i] go to off[key] + (arrival slot); sorted per bucket afterwards
-__global__ void k_bucket_scatter(int64_t n, const int64_t* __restrict__ key, const int64_t* __restrict__ off,
-                                 int32_t* __restrict__ fill, int32_t* __restrict__ out) {
-    GRID_STRIDE_LOOP(i, n) {
-        const int64_t k = key[i];
-        out[off[k] + atomicAdd(fill + k, 1)] = (int32_t)i;
-    }
-}
-
-// each bucket's items ascending (original index): the order no longer depends on the atomics
-__global__ void k_bucket_sort(int64_t nb, const int64_t* __restrict__ off, int32_t* __restrict__ items) {
-    GRID_STRIDE_LOOP(b, nb) {
-        const int64_t a = off[b], e = off[b + 1];
-        for (int64_t i = a + 1; i < e; ++i) {
-            const int32_t v = items[i];
-            int64_t j = i;
-            while (j > a && items[j - 1] > v) {
-                items[j] = items[j - 1];
-                --j;
-            }
-            items[j] = v;
-        }
+        cell[i] = morton ? (spread3(bx) << 2) | (spread3(by) << 1) | spread3(bz)
+                         : static_cast<uint64_t>((bx * g.B + by) * g.B + bz);
     }
 }
 
@@ -125,7 +102,7 @@ __global__ void k_apply_vperm(int64_t V, const int32_t* __restrict__ perm, const
 
 // tet key: its smallest new vertex number; flags a vertex index out of range
 __global__ void k_tet_key(int64_t T, int64_t V, const int32_t* __restrict__ tets, const int32_t* __restrict__ inv,
-                          int64_t* __restrict__ key, int32_t* __restrict__ count, unsigned* __restrict__ err) {
+                          uint32_t* __restrict__ key, unsigned* __restrict__ err) {
     GRID_STRIDE_LOOP(t, T) {
         int32_t m = INT32_MAX;
         bool ok = true;
@@ -141,8 +118,7 @@ __global__ void k_tet_key(int64_t T, int64_t V, const int32_t* __restrict__ tets
             atomicOr(err, 1u);
             m = 0;
         }
-        key[t] = m;
-        atomicAdd(count + m, 1);
+        key[t] = static_cast<uint32_t>(m);
     }
 }
 
@@ -152,6 +128,30 @@ __global__ void k_apply_tperm(int64_t T, const int32_t* __restrict__ tperm, cons
         const int64_t o = tperm[i];
         for (int k = 0; k < 4; ++k) tets_out[4 * i + k] = inv[tets[4 * o + k]];
     }
+}
+
+// perm = the indices 0..n-1 ordered by key, ties in index order (a stable
+// radix sort over the low `bits` bits of the keys); keys are left sorted.
+template <class K>
+void sort_indices(dec_ctx* ctx, DBuf<K>& key, int64_t n, int bits, DBuf<int32_t>& perm) {
+    DBuf<K> key_out;
+    key_out.alloc(ctx, n);
+    perm.alloc(ctx, n);
+    const rocprim::counting_iterator<int32_t> idx(0);
+    size_t bytes = 0;
+    HIP_CHECK(rocprim::radix_sort_pairs(nullptr, bytes, key.p, key_out.p, idx, perm.p, static_cast<size_t>(n), 0,
+                                        static_cast<unsigned>(bits), ctx->stream));
+    DBuf<uint8_t> tmp;
+    tmp.alloc(ctx, bytes ? bytes : 1);
+    HIP_CHECK(rocprim::radix_sort_pairs(tmp.p, bytes, key.p, key_out.p, idx, perm.p, static_cast<size_t>(n), 0,
+                                        static_cast<unsigned>(bits), ctx->stream));
+    ctx->sync();  // tmp and key_out are released on return
+}
+
+int bits_for(uint64_t n) {  // bits of the largest key below n
+    int b = 1;
+    while (b < 64 && (uint64_t(1) << b) < n) ++b;
+    return b;
 }
 
 }  // namespace
@@ -192,48 +192,33 @@ extern "C" int dec_reorder(dec_ctx* ctx, int32_t order, int64_t V, const double*
         // cell keys: lexicographic in [0, B^3), or Morton in [0, 2^(3k)) with 2^k >= B
         int kbits = 0;
         while ((int64_t(1) << kbits) < g.B) ++kbits;
-        const int64_t ncell = order == DEC_ORDER_MORTON ? int64_t(1) << (3 * kbits) : g.B * g.B * g.B;
-        // vertices: counting sort on the cell, then by original index inside each cell
-        DBuf<int64_t> cell, coff;
-        DBuf<int32_t> ccount, cfill, perm, inv;
+        const int cbits = order == DEC_ORDER_MORTON ? (3 * kbits > 0 ? 3 * kbits : 1)
+                                                    : bits_for(static_cast<uint64_t>(g.B * g.B * g.B));
+        // vertices: by cell, then original index
+        DBuf<uint64_t> cell;
+        DBuf<int32_t> perm, inv;
         DBuf<unsigned> bad;
         cell.alloc(ctx, V);
-        ccount.alloc(ctx, ncell);
-        ccount.zero();
         bad.alloc(ctx, 1);
         bad.zero();
         hipLaunchKernelGGL(k_point_cell, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, xyz, g,
-                           (int)(order == DEC_ORDER_MORTON), cell.p, ccount.p, bad.p);
+                           (int)(order == DEC_ORDER_MORTON), cell.p, bad.p);
         DEC_REQUIRE(*static_cast<unsigned*>(ctx->readback(bad.p, sizeof(unsigned))) == 0, DEC_EINVAL,
                     "non-finite coordinates");
-        coff.alloc(ctx, ncell + 1);
-        scan_exclusive_i32_to_i64(ctx, ccount.p, coff.p, ncell, false);
-        cfill.alloc(ctx, ncell);
-        cfill.zero();
-        perm.alloc(ctx, V);
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, cell.p, coff.p, cfill.p, perm.p);
-        hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(ncell)), dim3(BLOCK), 0, s, ncell, coff.p, perm.p);
+        sort_indices(ctx, cell, V, cbits, perm);
         inv.alloc(ctx, V);
         hipLaunchKernelGGL(k_apply_vperm, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, perm.p, xyz, xyz_out, inv.p);
-        // tets: counting sort on the smallest new vertex, then by original index
-        DBuf<int64_t> tkey, toff;
-        DBuf<int32_t> tcount, tfill, tperm;
+        // tets: by smallest new vertex, then original index
+        DBuf<uint32_t> tkey;
+        DBuf<int32_t> tperm;
         DBuf<unsigned> err;
         tkey.alloc(ctx, T);
-        tcount.alloc(ctx, V);
-        tcount.zero();
         err.alloc(ctx, 1);
         err.zero();
-        hipLaunchKernelGGL(k_tet_key, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, V, tets, inv.p, tkey.p, tcount.p, err.p);
+        hipLaunchKernelGGL(k_tet_key, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, V, tets, inv.p, tkey.p, err.p);
         const unsigned e = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
         DEC_REQUIRE(e == 0, DEC_ETOPO, "tet vertex index out of range");
-        toff.alloc(ctx, V + 1);
-        scan_exclusive_i32_to_i64(ctx, tcount.p, toff.p, V, false);
-        tfill.alloc(ctx, V);
-        tfill.zero();
-        tperm.alloc(ctx, T);
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tkey.p, toff.p, tfill.p, tperm.p);
-        hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, toff.p, tperm.p);
+        sort_indices(ctx, tkey, T, bits_for(static_cast<uint64_t>(V)), tperm);
         hipLaunchKernelGGL(k_apply_tperm, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tperm.p, tets, inv.p, tets_out);
         HIP_CHECK(hipGetLastError());
         if (vperm_out) HIP_CHECK(hipMemcpyAsync(vperm_out, perm.p, V * sizeof(int32_t), hipMemcpyDeviceToDevice, s));

@@ -50,7 +50,8 @@ __global__ void k_rms_fold(int n, const double* __restrict__ partials, double* _
 }  // namespace
 
 extern "C" int dec_rms_error(dec_mesh* m, int32_t on_tets, const double* T, const double* field, double* rms) {
-    if (!m || !T || !field || !rms) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!T || !field || !rms) return null_argument(m->ctx, "dec_rms_error");
     dec_ctx* ctx = m->ctx;
     try {
         DEC_REQUIRE(!m->dual && m->tets.p && m->xyz.p, DEC_ESTATE,

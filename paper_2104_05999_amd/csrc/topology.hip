@@ -468,7 +468,8 @@ int dec_mesh_info(const dec_mesh* m, int64_t* V, int64_t* T, int64_t* E, int64_t
 }
 
 int dec_get_edges(const dec_mesh* m, int32_t* edges) {
-    if (!m || !edges) return DEC_EINVAL;
+    if (!m) return DEC_EINVAL;
+    if (!edges) return null_argument(m->ctx, "dec_get_edges");
     try {
         HIP_CHECK(hipMemcpyAsync(edges, m->edges.p, 2 * m->E * sizeof(int32_t), hipMemcpyDeviceToDevice,
                                  m->ctx->stream));

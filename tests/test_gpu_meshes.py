@@ -44,6 +44,9 @@ CASES = {
     "kuhn6_shuffled": lambda: _shuffled_kuhn(6, 3),
     "kuhn6_jittered": lambda: (W.jitter_interior(W.kuhn_cube(6)[0], 6, 0.2, 1), W.kuhn_cube(6)[1]),
     "delaunay": lambda: W.delaunay_cube(1500, 80, 7),
+    # strongly graded towards one corner: 44% of the points share the first cell, so the ties by
+    # original index decide most of the order
+    "graded": lambda: (W.kuhn_cube(20)[0] ** 12, W.kuhn_cube(20)[1]),
 }
 
 
@@ -225,8 +228,11 @@ def test_error_paths_of_the_mesh_calls(ctx, dev):
             Td = torch.zeros(d.V, dtype=torch.float64, device=dev)
             assert L.dec_rms_error(d.handle, 1, vp(Td), f, ctypes.byref(r)) == ESTATE
             assert L.dec_dual_flux(d.handle, vp(Td), 1.0, 0.0, 1.0, None, None, None, None) == EINVAL
-            assert L.dec_dual_faces(m.handle, None, None, None, None) == EINVAL  # not a tet system
-            assert L.dec_dual_info(m.handle, None, None, None, None) == EINVAL
+            assert L.dec_dual_faces(m.handle, None, None, None, None) == ESTATE  # not a tet system
+            assert L.dec_dual_info(m.handle, None, None, None, None) == ESTATE
+            assert b"dec_dual_build" in L.dec_last_error(ctx.handle)
+            assert L.dec_dual_flux(d.handle, None, 1.0, 1.0, 1.0, None, None, None, None) == EINVAL
+            assert b"NULL" in L.dec_last_error(ctx.handle)
             assert L.dec_dual_build(None, None, 0, None, None, None, None, 0.0, None, None) == EINVAL
             assert L.dec_dual_build(m.handle, None, -1, None, vp(_t(bt, dev)), vp(_t(bv, dev)), None, 0.0,
                                     ctypes.byref(ctypes.c_void_p()), None) == EINVAL
