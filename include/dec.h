@@ -156,7 +156,10 @@ int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, const double*
  * solver multiplies with.  By default the sliced-ELL copy leaves out edges
  * whose geometric dual area is exactly zero (L_ij = -0 for every kappa and
  * crack set), which leaves every product bit-for-bit unchanged;
- * DEC_ASM_FULL_PATTERN keeps them. */
+ * DEC_ASM_FULL_PATTERN keeps them.  When every stored column lies within
+ * 2^15 of its row (a spatially numbered mesh), the sliced-ELL copy also
+ * holds the columns as 16-bit offsets from the row, which the solver's
+ * product reads instead of the int32 columns (same entries, same sums). */
 #define DEC_ASM_DEFAULT 0u
 #define DEC_ASM_FULL_PATTERN 1u
 int dec_assemble(dec_mesh* m, uint32_t flags);
@@ -232,8 +235,9 @@ typedef struct dec_solve_stats {
     int64_t spmv_launches;    /* profile: SpMV launches timed                              */
     double spmv_ms;           /* profile: summed duration of those launches                */
     double spmv_bytes;        /* bytes one SpMV must move: CSR definition over the entries
-                                 the product uses (nnz (s+4) + 4 (V+1) + 2 V s, plus V s
-                                 for the row excess of a difference-form product)          */
+                                 the product uses (nnz (s+c) + 4 (V+1) + 2 V s, plus V s
+                                 for the row excess of a difference-form product; c = 2
+                                 with 16-bit column offsets, else 4)                       */
     int64_t spmv_nnz;         /* entries the product uses (full pattern or pruned)       */
     double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
 } dec_solve_stats;

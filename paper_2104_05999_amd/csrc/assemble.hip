@@ -124,6 +124,24 @@ __global__ void k_sell_values(int64_t n, const int32_t* __restrict__ ssrc, const
     }
 }
 
+// Column offsets col - row as int16 in the same slots; flags an offset that does not fit.
+__global__ void k_sell_offsets(int64_t nslices, const int64_t* __restrict__ sptr, const int32_t* __restrict__ scol,
+                               int16_t* __restrict__ dcol, unsigned* __restrict__ wide) {
+    bool over = false;
+    RANGE_LOOP(i, nslices * SELL_C) {
+        const int64_t s = i / SELL_C;
+        const int lane = static_cast<int>(i % SELL_C);
+        const int width = static_cast<int>((sptr[s + 1] - sptr[s]) / SELL_C);
+        for (int j = 0; j < width; ++j) {
+            const int64_t idx = sell_index(sptr[s], width, j, lane);
+            const int64_t d = static_cast<int64_t>(scol[idx]) - i;  // row i = s * SELL_C + lane
+            over |= d < INT16_MIN || d > INT16_MAX;
+            dcol[idx] = static_cast<int16_t>(d);  // unused when any offset is out of range
+        }
+    }
+    if (over) atomicOr(wide, 1u);
+}
+
 void build_sell_pattern(dec_mesh* m) {
     dec_ctx* ctx = m->ctx;
     SellMatrix& S = m->sell;
@@ -147,9 +165,24 @@ void build_sell_pattern(dec_mesh* m) {
     hipLaunchKernelGGL(k_sell_fill, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
                        S.nslices, m->row_ptr.p, m->col.p, m->nz_edge.p, geo, S.ptr.p, S.col.p, S.src.p);
     HIP_CHECK(hipGetLastError());
+    build_sell_offsets(ctx, S);
 }
 
 }  // namespace
+
+void build_sell_offsets(dec_ctx* ctx, SellMatrix& S) {
+    S.dcol = DBuf<int16_t>();
+    if (S.entries == 0) return;
+    DBuf<int16_t> d;
+    d.alloc(ctx, S.entries);
+    DBuf<unsigned> wide;
+    wide.alloc(ctx, 1);
+    wide.zero();
+    hipLaunchKernelGGL(k_sell_offsets, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, S.nslices,
+                       S.ptr.p, S.col.p, d.p, wide.p);
+    HIP_CHECK(hipGetLastError());
+    if (*static_cast<unsigned*>(ctx->readback(wide.p, sizeof(unsigned))) == 0) S.dcol = std::move(d);
+}
 
 // Copy the CSR values into the sliced-ELL layout (after assembly or boundary edits).
 void refresh_sell_values(dec_mesh* m) {

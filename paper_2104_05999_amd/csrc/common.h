@@ -137,7 +137,12 @@ struct SellMatrix {
     DBuf<float> val32;   // [entries]
     DBuf<double> excess64;  // [V] row excess for the difference-form product (empty: plain form)
     DBuf<float> excess32;   // [V]
+    DBuf<int16_t> dcol;     // [entries] col - row, kept only when every offset fits in 16 bits
 };
+
+// Fill S.dcol from S.col (rows of V, padding included), or leave it empty when
+// some column lies 2^15 or more from its row.  Synchronises the stream.
+void build_sell_offsets(dec_ctx* ctx, SellMatrix& S);
 
 // Lower-triangular FSAI factor G (CSR) and its transpose (CSR of G^T).
 struct FsaiFactor {

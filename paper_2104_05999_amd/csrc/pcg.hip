@@ -323,22 +323,30 @@ struct Run {
 
 // With events, the launch carries them (hipExtLaunchKernelGGL): the
 // timestamps are those of the dispatch itself, not of separate markers.
+template <class VT, int MODE, int U, bool NT, bool DIFF, bool D16>
+void launch_sell_k(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                   const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
+    const dim3 g(c->Gs), blk(BLOCK);
+    if (ev_a)
+        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, D16>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
+                              part, done);
+    else
+        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, D16>), g, blk, 0, c->stream, A, x, y, b, part, done);
+}
+
 template <class VT, int MODE, int U, bool NT>
 void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
-    const dim3 g(c->Gs), blk(BLOCK);
     const int32_t* done = st ? &st->done : nullptr;
     if (A.excess) {
-        if (ev_a)
-            hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, true>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
-                                  part, done);
+        if (A.dcol)
+            launch_sell_k<VT, MODE, U, NT, true, true>(c, A, x, y, b, part, done, ev_a, ev_b);
         else
-            hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, true>), g, blk, 0, c->stream, A, x, y, b, part, done);
-    } else if (ev_a) {
-        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b, part,
-                              done);
+            launch_sell_k<VT, MODE, U, NT, true, false>(c, A, x, y, b, part, done, ev_a, ev_b);
+    } else if (A.dcol) {
+        launch_sell_k<VT, MODE, U, NT, false, true>(c, A, x, y, b, part, done, ev_a, ev_b);
     } else {
-        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT>), g, blk, 0, c->stream, A, x, y, b, part, done);
+        launch_sell_k<VT, MODE, U, NT, false, false>(c, A, x, y, b, part, done, ev_a, ev_b);
     }
 }
 
@@ -382,7 +390,7 @@ template <class VT>
 void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const VT* x, VT* y) {
     const int pi = prec_index<VT>();
     if (c->tuned[pi] || c->pinned_variant) return;
-    const std::array<int64_t, 4> shape{pi + (A.excess ? 2 : 0), A.V, A.nslices, entries};
+    const std::array<int64_t, 4> shape{pi + (A.excess ? 2 : 0) + (A.dcol ? 4 : 0), A.V, A.nslices, entries};
     auto known = c->ctx->spmv_tune.find(shape);
     if (known != c->ctx->spmv_tune.end()) {  // a matrix of this shape was timed before on this context
         c->unroll[pi] = known->second.first;
@@ -557,12 +565,46 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
     }
 }
 
-Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
+template <class VT>
+const VT* values(const SellMatrix& S);
+template <>
+const double* values<double>(const SellMatrix& S) {
+    return S.val64.p;
+}
+template <>
+const float* values<float>(const SellMatrix& S) {
+    return S.val32.p;
+}
+template <class VT>
+const VT* excess(const SellMatrix& S);
+template <>
+const double* excess<double>(const SellMatrix& S) {
+    return S.excess64.p;
+}
+template <>
+const float* excess<float>(const SellMatrix& S) {
+    return S.excess32.p;
+}
+
+// The solver's view of a sliced-ELL matrix with V rows: its 16-bit column
+// offsets where it has them (unless switched off), its row excess if any.
+template <class VT>
+SellView<VT> view(const SolveCache* c, const SellMatrix& S, int64_t V) {
+    SellView<VT> v{S.ptr.p, S.col.p, values<VT>(S), S.nslices, V, excess<VT>(S)};
+    if (!c->wide_cols) v.dcol = S.dcol.p;
+    return v;
+}
+
+template <class VT>
+Run<VT> make_run(dec_mesh* m, SolveCache* c, int precond);
+
+template <>
+Run<double> make_run<double>(dec_mesh* m, SolveCache* c, int precond) {
     Run<double> R{};
-    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V, m->sell.excess64.p};
-    R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val64.p, m->fsai.g_sell.nslices, m->V};
-    R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val64.p, m->fsai.gt_sell.nslices, m->V};
-    R.M = {m->blockinv.ptr.p, m->blockinv.col.p, m->blockinv.val64.p, m->blockinv.nslices, m->V};
+    R.A = view<double>(c, m->sell, m->V);
+    R.G = view<double>(c, m->fsai.g_sell, m->V);
+    R.GT = view<double>(c, m->fsai.gt_sell, m->V);
+    R.M = view<double>(c, m->blockinv, m->V);
     R.x = c->x64.p;
     R.r = c->r64.p;
     R.p = c->p64.p;
@@ -575,12 +617,13 @@ Run<double> run64(dec_mesh* m, SolveCache* c, int precond) {
     return R;
 }
 
-Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
+template <>
+Run<float> make_run<float>(dec_mesh* m, SolveCache* c, int precond) {
     Run<float> R{};
-    R.A = {m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V, m->sell.excess32.p};
-    R.G = {m->fsai.g_sell.ptr.p, m->fsai.g_sell.col.p, m->fsai.g_sell.val32.p, m->fsai.g_sell.nslices, m->V};
-    R.GT = {m->fsai.gt_sell.ptr.p, m->fsai.gt_sell.col.p, m->fsai.gt_sell.val32.p, m->fsai.gt_sell.nslices, m->V};
-    R.M = {m->blockinv.ptr.p, m->blockinv.col.p, m->blockinv.val32.p, m->blockinv.nslices, m->V};
+    R.A = view<float>(c, m->sell, m->V);
+    R.G = view<float>(c, m->fsai.g_sell, m->V);
+    R.GT = view<float>(c, m->fsai.gt_sell, m->V);
+    R.M = view<float>(c, m->blockinv, m->V);
     R.x = c->x32.p;
     R.r = c->r32.p;
     R.p = c->p32.p;
@@ -593,15 +636,15 @@ Run<float> run32(dec_mesh* m, SolveCache* c, int precond) {
     return R;
 }
 
-SellView<double> sell64(dec_mesh* m) {
-    return SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V,
-                            m->sell.excess64.p};
-}
+Run<double> run64(dec_mesh* m, SolveCache* c, int precond) { return make_run<double>(m, c, precond); }
+Run<float> run32(dec_mesh* m, SolveCache* c, int precond) { return make_run<float>(m, c, precond); }
+
+SellView<double> sell64(dec_mesh* m, const SolveCache* c) { return view<double>(c, m->sell, m->V); }
 
 // ||b - A x64||^2 in FP64 (through t64), via the scratch state
 double true_rr(dec_mesh* m, SolveCache* c) {
     PcgScalars* s4 = c->st.p + 4;
-    launch_sell<double, MODE_RESID>(c, sell64(m), c->x64.p, c->t64.p, m->rhs.p, region(c, R_RR), nullptr);
+    launch_sell<double, MODE_RESID>(c, sell64(m, c), c->x64.p, c->t64.p, m->rhs.p, region(c, R_RR), nullptr);
     finalize(c, FIN_RR, c->Gs, 0.0, 0, s4);
     HIP_CHECK(hipGetLastError());
     return read_state(c, s4).rr;
@@ -685,7 +728,7 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
     const int64_t inner_cap = o.max_iters / 8 > 64 ? o.max_iters / 8 : 64;
     for (int outer = 0; outer < 100; ++outer) {
         // r64 = b - A x64 (FP64), ||r64||^2 into s4->rr
-        launch_sell<double, MODE_RESID>(c, sell64(m), c->x64.p, c->r64.p, m->rhs.p, region(c, R_RR), nullptr);
+        launch_sell<double, MODE_RESID>(c, sell64(m, c), c->x64.p, c->r64.p, m->rhs.p, region(c, R_RR), nullptr);
         finalize(c, FIN_RR, c->Gs, 0.0, 0, s4);
         const double rn = sqrt(read_state(c, s4).rr);
         if (stats) stats->outer_iterations = outer;
@@ -771,6 +814,7 @@ SolveCache* get_solve_cache(dec_mesh* m) {
             c->nt[0] = c->nt[1] = atoi(env);
             c->pinned_variant = true;
         }
+        if (const char* env = getenv("DEC_SELL_COLS")) c->wide_cols = atoi(env) == 32;
         auto blocks = [&](int64_t rows_per_block, int pc) {
             const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
             const int64_t cap = (int64_t)pc * m->ctx->num_cus;
@@ -830,23 +874,21 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
         DEC_REQUIRE(o.norm == DEC_NORM_RESIDUAL || o.precision == DEC_PREC_FP64, DEC_EINVAL,
                     "the energy-norm test is for FP64 solves");
         ctx->set_device();
+        SolveCache* c = get_solve_cache(m);
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
             const double s = o.precision == DEC_PREC_MIXED ? 4.0 : 8.0, nz = (double)m->sell.kept;
+            const double cb = view<double>(c, m->sell, m->V).dcol ? 2.0 : 4.0;  // bytes per column
             stats->spmv_nnz = m->sell.kept;
-            stats->spmv_bytes = nz * (s + 4.0) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
+            stats->spmv_bytes = nz * (s + cb) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
             if (m->sell.excess64.p) stats->spmv_bytes += s * (double)m->V;  // difference form: the row excess
         }
-        SolveCache* c = get_solve_cache(m);
         if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
         ensure_vectors(m, c, o.precision);
         ctx->sync();  // inputs written on the caller's stream are complete
-        autotune_spmv<double>(c, sell64(m), m->sell.entries, c->p64.p, c->q64.p);
+        autotune_spmv<double>(c, sell64(m, c), m->sell.entries, c->p64.p, c->q64.p);
         if (o.precision == DEC_PREC_MIXED)
-            autotune_spmv<float>(c,
-                                 SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices,
-                                                 m->V, m->sell.excess32.p},
-                                 m->sell.entries, c->p32.p, c->q32.p);
+            autotune_spmv<float>(c, view<float>(c, m->sell, m->V), m->sell.entries, c->p32.p, c->q32.p);
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
                            m->bc_value.p, o.warm_start ? T : nullptr, c->x64.p);
@@ -910,15 +952,11 @@ int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void
             hipStream_t keep = c->stream;
             c->stream = ctx->stream;
             if (precision == DEC_PREC_FP64)
-                launch_sell<double, MODE_PLAIN>(
-                    c, SellView<double>{m->sell.ptr.p, m->sell.col.p, m->sell.val64.p, m->sell.nslices, m->V,
-                                        m->sell.excess64.p},
-                    static_cast<const double*>(x), static_cast<double*>(y), nullptr, nullptr, nullptr);
+                launch_sell<double, MODE_PLAIN>(c, view<double>(c, m->sell, m->V), static_cast<const double*>(x),
+                                                static_cast<double*>(y), nullptr, nullptr, nullptr);
             else
-                launch_sell<float, MODE_PLAIN>(
-                    c, SellView<float>{m->sell.ptr.p, m->sell.col.p, m->sell.val32.p, m->sell.nslices, m->V,
-                                       m->sell.excess32.p},
-                    static_cast<const float*>(x), static_cast<float*>(y), nullptr, nullptr, nullptr);
+                launch_sell<float, MODE_PLAIN>(c, view<float>(c, m->sell, m->V), static_cast<const float*>(x),
+                                               static_cast<float*>(y), nullptr, nullptr, nullptr);
             c->stream = keep;
         }
         HIP_CHECK(hipGetLastError());

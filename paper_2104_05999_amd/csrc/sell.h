@@ -5,7 +5,11 @@
 // Layout (see sell_index): slices of SELL_C = 64 consecutive rows, one row
 // per lane of a wavefront, consecutive entries of a row stored in pairs, so
 // each load instruction of a wavefront reads two entries of every row from one
-// contiguous 512 B (column) or 1 KiB (FP64 value) segment.
+// contiguous 512 B (column) or 1 KiB (FP64 value) segment.  Where every
+// entry's column lies within 2^15 of its row, the columns are read as 16-bit
+// offsets from the row instead (one 256 B segment per pair): a spatially
+// numbered mesh keeps its neighbours that close, and the bytes per stored
+// entry fall from 12 to 10 (FP64) and from 8 to 6 (FP32).
 #pragma once
 
 #include "common.h"
@@ -25,6 +29,7 @@ struct SellView {
     int64_t nslices;
     int64_t V;
     const VT* excess = nullptr;  // [V], or null for the plain product
+    const int16_t* dcol = nullptr;  // [entries] col - row, or null: the int32 columns
 };
 
 // Native two-element vectors for the paired loads.
@@ -33,6 +38,10 @@ struct Pair;
 template <>
 struct Pair<int32_t> {
     typedef int32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<int16_t> {
+    typedef int16_t type __attribute__((ext_vector_type(2)));
 };
 template <>
 struct Pair<double> {
@@ -55,14 +64,17 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // before its x gathers, and the last group is predicated (the width is
 // uniform across the wavefront), so no entry waits on the one before; an odd
 // last entry follows.  The terms are added in entry order, so every layout
-// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).
-template <class VT, int U, bool NT = true, bool DIFF = false>
+// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).  D16:
+// the columns come from the 16-bit offsets (A.dcol) added to `row`.
+template <class VT, int U, bool NT = true, bool DIFF = false, bool D16 = false>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
-                                       const VT* __restrict__ x, VT xi = 0) {
+                                       const VT* __restrict__ x, VT xi = 0, int32_t row = 0) {
     typedef typename Pair<int32_t>::type C2;
+    typedef typename Pair<int16_t>::type D2;
     typedef typename Pair<VT>::type V2;
     const int np = width >> 1;
     const C2* cp = reinterpret_cast<const C2*>(A.col + base) + lane;
+    const D2* dp = reinterpret_cast<const D2*>(A.dcol + base) + lane;
     const V2* vp = reinterpret_cast<const V2*>(A.val + base) + lane;
     VT acc = 0;
     for (int t = 0; t < np; t += U) {
@@ -72,7 +84,13 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = t + u < np;
-            c[u] = ok ? stream_load<C2, NT>(cp + u * SELL_C) : C2(0);
+            if (D16) {
+                const D2 d = ok ? stream_load<D2, NT>(dp + u * SELL_C) : D2(0);
+                c[u].x = row + d.x;
+                c[u].y = row + d.y;
+            } else {
+                c[u] = ok ? stream_load<C2, NT>(cp + u * SELL_C) : C2(0);
+            }
             v[u] = ok ? stream_load<V2, NT>(vp + u * SELL_C) : V2(0);
         }
 #pragma unroll
@@ -92,11 +110,12 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
                 acc += v[u].y * x1[u];
             }
         cp += U * SELL_C;
+        dp += U * SELL_C;
         vp += U * SELL_C;
     }
     if (width & 1) {
         const int64_t k = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
-        const int32_t c = stream_load<int32_t, NT>(A.col + k);
+        const int32_t c = D16 ? row + stream_load<int16_t, NT>(A.dcol + k) : stream_load<int32_t, NT>(A.col + k);
         acc += stream_load<VT, NT>(A.val + k) * (DIFF ? x[c] - xi : x[c]);
     }
     return acc;
@@ -109,8 +128,8 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // per-block partials of b.y (DOTB).  A launch whose `done` flag (if given)
 // is set returns at once: inside a batch of PCG iterations that has
 // converged, the remaining launches do nothing.  DIFF: the difference form
-// (A.excess set).
-template <class VT, int MODE, int U, bool NT, bool DIFF = false>
+// (A.excess set).  D16: the 16-bit column offsets (A.dcol set).
+template <class VT, int MODE, int U, bool NT, bool DIFF = false, bool D16 = false>
 __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
                                                 const int32_t* __restrict__ done) {
@@ -127,10 +146,10 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
         VT acc;
         if (DIFF) {
             const VT xi = row < A.V ? x[row] : VT(0);
-            acc = sell_row<VT, U, NT, true>(A, base, width, lane, x, xi);
+            acc = sell_row<VT, U, NT, true, D16>(A, base, width, lane, x, xi, static_cast<int32_t>(row));
             if (row < A.V) acc += A.excess[row] * xi;
         } else {
-            acc = sell_row<VT, U, NT>(A, base, width, lane, x);
+            acc = sell_row<VT, U, NT, false, D16>(A, base, width, lane, x, VT(0), static_cast<int32_t>(row));
         }
         if (row < A.V) {
             if (MODE == MODE_RESID) {

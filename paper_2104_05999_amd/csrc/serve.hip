@@ -37,7 +37,8 @@ enum { Q_PQ = 0, Q_RR = 1, Q_RZ = 2, Q_OUT = 3 };  // partial regions, nchunks d
 // Device descriptor of one admitted system.
 struct BSlot {
     const int64_t* sptr;
-    const int32_t* scol;
+    const int32_t* scol;   // int32 columns, null when the 16-bit offsets are kept instead
+    const int16_t* sdcol;  // 16-bit column offsets, or null
     const double* sval64;
     const float* sval32;
     const double* invd64;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         if (S.st[par].done) continue;
-        const SellView<VT> A{S.sptr, S.scol, SlotVec<VT>::val(S), S.nslices, S.V};
+        const SellView<VT> A{S.sptr, S.scol, SlotVec<VT>::val(S), S.nslices, S.V, nullptr, S.sdcol};
         const VT* p = SlotVec<VT>::p(S);
         VT* q = SlotVec<VT>::q(S);
         const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
@@ -110,7 +111,8 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
             const int64_t base = A.ptr[s];
             const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
             const int64_t row = s * SELL_C + lane;
-            const VT acc = sell_row<VT, U, NT>(A, base, width, lane, p);
+            const VT acc = A.dcol ? sell_row<VT, U, NT, false, true>(A, base, width, lane, p, VT(0), (int32_t)row)
+                                  : sell_row<VT, U, NT>(A, base, width, lane, p);
             if (row < A.V) {
                 q[row] = acc;
                 d += p[row] * acc;
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ s
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
-        const SellView<double> A{S.sptr, S.scol, S.sval64, S.nslices, S.V};
+        const SellView<double> A{S.sptr, S.scol, S.sval64, S.nslices, S.V, nullptr, S.sdcol};
         const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
         const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
         double d = 0.0;
@@ -255,7 +257,9 @@ __global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ s
             const int64_t base = A.ptr[s];
             const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
             const int64_t row = s * SELL_C + lane;
-            const double acc = sell_row<double, 4, true>(A, base, width, lane, S.x64);
+            const double acc = A.dcol ? sell_row<double, 4, true, false, true>(A, base, width, lane, S.x64, 0.0,
+                                                                              (int32_t)row)
+                                      : sell_row<double, 4, true>(A, base, width, lane, S.x64);
             if (row < A.V) {
                 const double ri = S.b[row] - acc;
                 S.r64[row] = ri;
@@ -441,6 +445,7 @@ void compact_mesh(dec_mesh* m) {
     m->val64.release();
     m->val32.release();
     m->sell.src.release();
+    if (m->sell.dcol.p) m->sell.col.release();  // the product reads the 16-bit offsets
     m->geo.release();
 }
 
@@ -450,6 +455,7 @@ BSlot describe(dec_server* s, int k) {
     BSlot d{};
     d.sptr = m->sell.ptr.p;
     d.scol = m->sell.col.p;
+    d.sdcol = m->sell.dcol.p;
     d.sval64 = m->sell.val64.p;
     d.sval32 = m->sell.val32.p;
     d.invd64 = m->invdiag64.p;

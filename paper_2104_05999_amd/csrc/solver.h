@@ -77,6 +77,7 @@ struct SolveCache {
     int nt[2] = {1, 0};  // non-temporal matrix loads
     bool tuned[2] = {false, false};
     bool pinned_variant = false;  // set through the environment: no tuning
+    bool wide_cols = false;       // int32 columns even where 16-bit offsets exist (environment)
     DBuf<double> x64, r64, p64, q64, z64, w64, t64;
     DBuf<float> x32, r32, p32, q32, z32, w32;
     DBuf<double> partials;  // [3G]: per-block partial sums of p.q, r.r, r.z

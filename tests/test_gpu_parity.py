@@ -464,12 +464,13 @@ def test_nonfinite_conductivity_breaks_down(ctx, dev):
         m.close()
 
 
+@pytest.mark.parametrize("cols", [16, 32])
 @pytest.mark.parametrize("unroll,nt", [(2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1)])
-def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt):
+def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt, cols):
     """The autotuner's variants (pairs in flight, non-temporal loads) sum every row in the same
-    order and fold the partials in the same order: pinned through the environment, each gives
-    the tuned solve's bits, on a vertex system and on a tet system, in FP64 and with FP32 inner
-    solves."""
+    order and fold the partials in the same order, and the 16-bit column offsets name the same
+    columns as the int32 columns: pinned through the environment, each gives the tuned solve's
+    bits, on a vertex system and on a tet system, in FP64 and with FP32 inner solves."""
     import os
     import paper_2104_05999_amd as dec
     s = _system(12, n_cracks=20)
@@ -485,6 +486,7 @@ def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt):
     ref_d = d.solve(tol=1e-11)[0]
     d.close()
     os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"] = str(unroll), str(nt)
+    os.environ["DEC_SELL_COLS"] = str(cols)
     try:
         m2, _, _, _, _ = _gpu(ctx, s, dev)
         for p, r in zip((0, 1), ref):
@@ -496,4 +498,4 @@ def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt):
         assert torch.equal(d.solve(tol=1e-11)[0], ref_d)
         d.close()
     finally:
-        del os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"]
+        del os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"], os.environ["DEC_SELL_COLS"]
