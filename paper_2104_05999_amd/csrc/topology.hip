@@ -97,12 +97,14 @@ __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restric
     }
 }
 
-// Neighbour enumeration with one 32-lane group per vertex (two vertices per
-// wavefront): lane k of the group holds tets k, k+32, ... of the vertex's
-// sorted tet list (the first in registers).  Each round finds the smallest
-// neighbour w > cur (group minimum) and the tets holding it (ballot; each
-// tet holds w at most once).  INT_MAX: no neighbour left.
-constexpr int NG = 32;
+// Neighbour enumeration with one 16-lane group per vertex (four vertices per
+// wavefront, so the group reductions stay inside a row of 16 lanes): lane g
+// of the group holds tets g and g + 16 of the vertex's sorted tet list in
+// registers (entries -1 past the end), tets g + 32, g + 48, ... are read as
+// needed.  Each round finds the smallest neighbour w > cur (group minimum)
+// and the tets holding it (ballot; each tet holds w at most once).
+// INT_MAX: no neighbour left.
+constexpr int NG = 16;
 
 __device__ __forceinline__ int group_min(int v) {
 #pragma unroll
@@ -120,16 +122,24 @@ __device__ __forceinline__ int tet_pos(const int4& q, int w) {
     return q.x == w ? 0 : (q.y == w ? 1 : (q.z == w ? 2 : (q.w == w ? 3 : -1)));
 }
 
+// vertices of q above v (-1 entries never are)
+__device__ __forceinline__ int above(const int4& q, int v) {
+    return (q.x > v) + (q.y > v) + (q.z > v) + (q.w > v);
+}
+
 struct GroupTets {
-    int4 q0;
-    bool has0;
+    int4 q0, q1;  // tets g and g + NG of the list
+    int t0, t1;   // their ids
 };
 
 __device__ __forceinline__ GroupTets load_group_tets(const int4* __restrict__ tets, const int32_t* __restrict__ list,
                                                      int64_t b, int d, int g) {
     GroupTets t;
-    t.has0 = g < d;
-    t.q0 = t.has0 ? tets[list[b + g]] : make_int4(-1, -1, -1, -1);
+    const int4 none = make_int4(-1, -1, -1, -1);
+    t.t0 = g < d ? list[b + g] : -1;
+    t.t1 = g + NG < d ? list[b + g + NG] : -1;
+    t.q0 = t.t0 >= 0 ? tets[t.t0] : none;
+    t.q1 = t.t1 >= 0 ? tets[t.t1] : none;
     return t;
 }
 
@@ -144,11 +154,15 @@ __device__ __forceinline__ void scan_tet(const int4& q, int v, int cur, int* bes
 __device__ __forceinline__ int group_next(const int4* __restrict__ tets, const int32_t* __restrict__ list, int64_t b,
                                           int d, int v, int cur, int g, const GroupTets& gt) {
     int best = INT_MAX;
-    if (gt.has0) scan_tet(gt.q0, v, cur, &best);
-    for (int k = g + NG; k < d; k += NG) scan_tet(tets[list[b + k]], v, cur, &best);
+    scan_tet(gt.q0, v, cur, &best);
+    scan_tet(gt.q1, v, cur, &best);
+    for (int k = g + 2 * NG; k < d; k += NG) scan_tet(tets[list[b + k]], v, cur, &best);
     return group_min(best);
 }
 
+// Per vertex: upper neighbours (edges it is the low end of), pattern row
+// length, and the incidences of its upper edges -- each tet of v adds one per
+// vertex above v, so that count needs no enumeration.
 __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
                             const int32_t* __restrict__ vt_list, int64_t V, int32_t* __restrict__ n_up,
                             int32_t* __restrict__ row_len, int32_t* __restrict__ n_inc) {
@@ -158,18 +172,16 @@ __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __rest
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
         const GroupTets gt = load_group_tets(tets, vt_list, b, d, g);
-        int cur = -1, up = 0, all = 0, inc = 0;
+        int inc = above(gt.q0, (int)v) + above(gt.q1, (int)v);
+        for (int k = g + 2 * NG; k < d; k += NG) inc += above(tets[vt_list[b + k]], (int)v);
+        inc = group_sum(inc);
+        int cur = -1, up = 0, all = 0;
         while (true) {
             const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
             if (w == INT_MAX) break;
             cur = w;
             ++all;
-            if (w > v) {
-                ++up;
-                int c = gt.has0 ? (tet_pos(gt.q0, w) >= 0) : 0;
-                for (int k = g + NG; k < d; k += NG) c += tet_pos(tets[vt_list[b + k]], w) >= 0;
-                inc += group_sum(c);
-            }
+            up += w > v;
         }
         if (g == 0) {
             n_up[v] = up;
@@ -230,11 +242,20 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
             for (int k0 = 0; k0 < d; k0 += NG) {
                 const int k = k0 + g;
                 int4 q = make_int4(-1, -1, -1, -1);
-                if (k < d) q = k0 == 0 ? gt.q0 : tets[vt_list[b + k]];
+                int t = -1;
+                if (k0 == 0) {
+                    q = gt.q0;
+                    t = gt.t0;
+                } else if (k0 == NG) {
+                    q = gt.q1;
+                    t = gt.t1;
+                } else if (k < d) {
+                    t = vt_list[b + k];
+                    q = tets[t];
+                }
                 const int pw = tet_pos(q, w);
-                const uint64_t ball = (__ballot(pw >= 0) >> gbase) & 0xffffffffull;
+                const uint64_t ball = (__ballot(pw >= 0) >> gbase) & ((uint64_t(1) << NG) - 1);
                 if (pw >= 0) {
-                    const int t = vt_list[b + k];
                     const int pv = tet_pos(q, (int)v);
                     const int slot = t * 6 + local_edge(pv < pw ? pv : pw, pv < pw ? pw : pv);
                     et_inc[ip + __popcll(ball & below)] = slot;
@@ -374,7 +395,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     hipLaunchKernelGGL(k_vt_sort, dim3(grid_xcd(V, BLOCK / 32)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
     HIP_CHECK(hipGetLastError());
 
-    // neighbours: counts, then edges, incidences and the CSR pattern (one 32-lane group per vertex)
+    // neighbours: counts, then edges, incidences and the CSR pattern (one 16-lane group per vertex)
     DBuf<int32_t> n_up, row_len, n_inc;
     n_up.alloc(ctx, V);
     row_len.alloc(ctx, V);

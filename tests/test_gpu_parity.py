@@ -79,7 +79,8 @@ def test_topology_bit_exact(ctx, dev, n):
 
 def _double_cone(k, seed):
     """Centre, two apexes and a ring of k vertices: the centre lies in 2k tets and the
-    centre-apex edges in k each (beyond one 32-lane group); tets in seeded random order."""
+    centre-apex edges in k each (2k = 16 and 32 fill exactly the one and two tets per lane that a
+    16-lane group holds in registers; 40 and 80 go past them); tets in seeded random order."""
     th = 2 * np.pi * np.arange(k) / k
     xyz = np.concatenate([[[0.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, -1.0]],
                           np.stack([np.cos(th), np.sin(th), np.zeros(k)], axis=1)])
@@ -93,7 +94,7 @@ def _double_cone(k, seed):
     return xyz, tets.astype(np.int32)
 
 
-@pytest.mark.parametrize("k", [12, 20, 40])
+@pytest.mark.parametrize("k", [8, 12, 16, 20, 40])
 def test_topology_high_degree_vertices(ctx, dev, k):
     xyz, tets = _double_cone(k, k)
     m = ctx.mesh(_t(xyz, dev), _t(tets, dev))
