@@ -404,6 +404,44 @@ def test_pruned_pattern_products_are_bit_identical(ctx, dev):
     assert st_p["spmv_nnz"] < st_f["spmv_nnz"] == m.nnz
 
 
+def test_column_offsets_and_their_fallback(ctx, dev):
+    """The sliced-ELL copy reads 16-bit column offsets when every column lies within 2^15 of its
+    row (the 41^3-vertex lattice: neighbours within 41^2 + 42 rows) and the int32 columns when
+    not (the same mesh with its vertices scrambled).  Either way the product equals the CSR
+    product bit for bit, the solve's byte count states which columns it read, and the two
+    numberings give the same temperatures."""
+    import paper_2104_05999_amd as dec
+    n = 40
+    xyz, tets = W.kuhn_cube(n)
+    rng = np.random.Generator(np.random.PCG64(11))
+    perm = rng.permutation(len(xyz))            # new number of old vertex i: perm[i]
+    xyz_s = np.empty_like(xyz)
+    xyz_s[perm] = xyz
+    tets_s = perm[tets].astype(np.int32)
+    bt, bv, _ = W.x_sides(n)
+    bt_s, bv_s = np.empty_like(bt), np.empty_like(bv)
+    bt_s[perm], bv_s[perm] = bt, bv
+    out = {}
+    for name, (x3, tt, b_t, b_v, col_bytes) in {"lattice": (xyz, tets, bt, bv, 2),
+                                                  "scrambled": (xyz_s, tets_s, bt_s, bv_s, 4)}.items():
+        m = ctx.mesh(_t(x3, dev), _t(tt, dev))
+        try:
+            m.hodge1()
+            m.assemble()
+            m.apply_bc(_t(b_t, dev), _t(b_v, dev))
+            x = torch.as_tensor(rng.normal(size=len(x3)), device=dev)
+            assert torch.equal(m.spmv(x), m.spmv(x, fmt=dec.DEC_FMT_CSR)), name
+            T, st, rc = m.solve(tol=1e-12)
+            assert rc == 0, (name, st)
+            V, nz = len(x3), st["spmv_nnz"]
+            assert st["spmv_bytes"] == nz * (8 + col_bytes) + 4 * (V + 1) + 16 * V, name
+            out[name] = T.cpu().numpy()
+        finally:
+            m.close()
+    Tl, Ts = out["lattice"], out["scrambled"][perm]
+    assert np.abs(Tl - Ts).max() <= 1e-10 * np.abs(Tl).max()
+
+
 def test_error_paths(ctx, dev):
     import paper_2104_05999_amd as dec
     n = 3
