@@ -251,6 +251,24 @@ __device__ __forceinline__ void block_range(int64_t n, int64_t* b0, int64_t* b1)
     *b1 = n * (L + 1) / G;
 }
 
+// Front order for streaming kernels: XCD x owns the contiguous x-th eighth
+// [x0, x1) of n items, and its blocks sweep it together, block j taking rows
+// x0 + (j + k * per) * blockDim.x + threadIdx.x, k = 0, 1, ... (per = blocks
+// of one XCD), so that at any moment an XCD streams one contiguous stretch of
+// memory.  gridDim.x must be a multiple of 8.
+struct FrontRange {
+    int64_t first, step, end;
+};
+
+__device__ __forceinline__ FrontRange front_range(int64_t n) {
+    const int64_t xcd = blockIdx.x & 7, j = blockIdx.x >> 3, per = gridDim.x >> 3;
+    FrontRange r;
+    r.first = n * xcd / 8 + j * blockDim.x + threadIdx.x;
+    r.step = per * blockDim.x;
+    r.end = n * (xcd + 1) / 8;
+    return r;
+}
+
 // Grid for block_range: about `per_block` items per block, at most `cap`
 // blocks (32 per CU on 256 CUs: long-lived blocks, each walking a
 // contiguous range), a multiple of 8.

@@ -147,15 +147,14 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
                                                   int P, int n_pq, PcgScalars* __restrict__ S) {
     __shared__ double lds[BLOCK / 64 + 1];
     if (S->done) return;
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
+    const FrontRange R = front_range(V);
     // the first PREFETCH rows of each thread are loaded before the fold, so
     // the fold's latency overlaps with their transfer
     VT fr[PREFETCH], fq[PREFETCH], fd[PREFETCH];
 #pragma unroll
     for (int k = 0; k < PREFETCH; ++k) {
-        const int64_t i = i0 + threadIdx.x + k * BLOCK;
-        if (i < i1) {
+        const int64_t i = R.first + k * R.step;
+        if (i < R.end) {
             fr[k] = r[i];
             fq[k] = q[i];
             fd[k] = JACOBI ? invd[i] : VT(0);
@@ -168,15 +167,15 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
     VT rz = 0, rr = 0;
 #pragma unroll
     for (int k = 0; k < PREFETCH; ++k) {
-        const int64_t i = i0 + threadIdx.x + k * BLOCK;
-        if (i < i1) {
+        const int64_t i = R.first + k * R.step;
+        if (i < R.end) {
             const VT ri = fr[k] - a * fq[k];
             r[i] = ri;
             if (JACOBI) rz += ri * (fd[k] * ri);
             rr += ri * ri;
         }
     }
-    for (int64_t i = i0 + threadIdx.x + PREFETCH * BLOCK; i < i1; i += BLOCK) {
+    for (int64_t i = R.first + PREFETCH * R.step; i < R.end; i += R.step) {
         const VT ri = r[i] - a * q[i];
         r[i] = ri;
         if (JACOBI) rz += ri * (invd[i] * ri);
@@ -221,14 +220,13 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         return;
     }
     const int G = gridDim.x;
-    int64_t i0, i1;
-    block_range(V, &i0, &i1);
+    const FrontRange R = front_range(V);
     // z (or D^-1 r), p and x of the first rows, loaded before the fold
     VT fz[CLOSE_PREFETCH], fp[CLOSE_PREFETCH], fx[CLOSE_PREFETCH];
 #pragma unroll
     for (int k = 0; k < CLOSE_PREFETCH; ++k) {
-        const int64_t i = i0 + threadIdx.x + k * BLOCK;
-        if (i < i1) {
+        const int64_t i = R.first + k * R.step;
+        if (i < R.end) {
             fz[k] = JACOBI ? invd[i] * r[i] : z[i];
             fp[k] = p[i];
             fx[k] = x[i];
@@ -252,13 +250,13 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         const bool run = done == PCG_RUNNING;
 #pragma unroll
         for (int k = 0; k < CLOSE_PREFETCH; ++k) {
-            const int64_t i = i0 + threadIdx.x + k * BLOCK;
-            if (i < i1) {
+            const int64_t i = R.first + k * R.step;
+            if (i < R.end) {
                 x[i] = fx[k] + a * fp[k];
                 if (run) p[i] = fz[k] + bt * fp[k];
             }
         }
-        for (int64_t i = i0 + threadIdx.x + CLOSE_PREFETCH * BLOCK; i < i1; i += BLOCK) {
+        for (int64_t i = R.first + CLOSE_PREFETCH * R.step; i < R.end; i += R.step) {
             const VT pi = p[i];
             x[i] = x[i] + a * pi;
             if (run) p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * pi;

@@ -85,6 +85,17 @@ struct SlotVec<float> {
     __device__ static float* q(const BSlot& s) { return s.q32; }
 };
 
+// Work items in XCD order: XCD x (blockIdx.x & 7) takes the contiguous x-th
+// eighth of the n items, its blocks in turn, so that the neighbouring chunks
+// of one system, which gather the same parts of its vectors, share an L2.
+// Each item's work and partial sums do not depend on which block takes it.
+// gridDim.x must be a multiple of 8.
+#define ITEM_LOOP(it, n)                                                          \
+    const int it##_step = static_cast<int>(gridDim.x >> 3);                       \
+    const int it##_end = static_cast<int>((int64_t)(n) * ((blockIdx.x & 7) + 1) / 8); \
+    for (int it = static_cast<int>((int64_t)(n) * (blockIdx.x & 7) / 8) + static_cast<int>(blockIdx.x >> 3); \
+         it < it##_end; it += it##_step)
+
 __device__ __forceinline__ void chunk_rows(const BSlot& S, int c, int64_t* r0, int64_t* r1) {
     *r0 = (int64_t)c * CHUNK_ROWS;
     *r1 = *r0 + CHUNK_ROWS < S.V ? *r0 + CHUNK_ROWS : S.V;
@@ -97,7 +108,7 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
     __shared__ double lds[BLOCK / 64 + 1];
     const int n = *n_items;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         if (S.st[par].done) continue;
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slo
                                                    const int32_t* __restrict__ n_items, int par) {
     __shared__ double lds[BLOCK / 64 + 1];
     const int n = *n_items;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         const PcgScalars* st = S.st + par;
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
                                                   const int32_t* __restrict__ n_items, int par) {
     __shared__ double lds[3 * (BLOCK / 64 + 1)];
     const int n = *n_items;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         const PcgScalars* Sp = S.st + par;
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
 // x0 on admission: Dirichlet values, 0 elsewhere; FP32 correction zero
 __global__ void bk_admit_init(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
     __shared__ double lds[BLOCK / 64 + 1];
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         int64_t r0, r1;
@@ -229,7 +240,7 @@ __global__ void bk_admit_init(const BSlot* __restrict__ slots, const BItem* __re
 
 // mixed: x64 += ||r_prev|| x32 (the correction of the inner solve just ended)
 __global__ void bk_correct(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         if (!S.x32) continue;
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ s
                                                      int n) {
     __shared__ double lds[BLOCK / 64 + 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         const SellView<double> A{S.sptr, S.scol, S.sval64, S.nslices, S.V, nullptr, S.sdcol};
@@ -293,7 +304,7 @@ __global__ void bk_fold_outer(const BSlot* __restrict__ slots, const int32_t* __
 template <class VT>
 __global__ void bk_inner_start(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
     __shared__ double lds[BLOCK / 64 + 1];
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         const double inv = 1.0 / sqrt(S.outer->rr);
