@@ -205,6 +205,7 @@ void assemble_device(dec_mesh* m) {
     m->assembled = true;
     m->bc_ready = false;
     m->fsai.ready = false;
+    m->jsplit.ready = false;
 }
 
 extern "C" int dec_assemble(dec_mesh* m, uint32_t flags) {

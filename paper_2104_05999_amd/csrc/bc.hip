@@ -243,6 +243,7 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     m->n_pinned = (int64_t) * static_cast<unsigned long long*>(ctx->readback(npin.p, sizeof(unsigned long long)));
     m->bc_ready = true;
     m->fsai.ready = false;
+    m->jsplit.ready = false;
 }
 
 }  // namespace

@@ -154,6 +154,21 @@ struct FsaiFactor {
     SellMatrix g_sell, gt_sell;  // sliced-ELL copies that the solver applies (same entry order per row)
 };
 
+// Jacobi in split form: CG on D^-1/2 A D^-1/2 with x = D^-1/2 x^, the same
+// iterates as Jacobi-preconditioned CG on A, one vector fewer per iteration.
+// Built by the solver from the sliced-ELL copy when every diagonal entry is
+// positive; stale after assembly or new boundary data.
+struct JacobiSplit {
+    bool ready = false;   // built for the current values
+    bool usable = false;  // every diagonal entry positive and finite
+    DBuf<double> v64;     // [entries] a_ij s_i s_j, s = D^-1/2
+    DBuf<float> v32;      // [entries]
+    DBuf<double> s64;     // [V] s
+    DBuf<double> b64;     // [V] s * b
+    DBuf<double> d64;     // [V] a_ii (r.r of the unscaled residual is sum d r^2)
+    DBuf<float> d32;      // [V]
+};
+
 // The paper's own unknowns: a system whose rows are the tets of a mesh, with
 // the face data its flux and queries need (see dual.hip).
 struct DualData {
@@ -217,6 +232,7 @@ struct dec_mesh {
     int64_t n_pinned = 0;
 
     FsaiFactor fsai;
+    JacobiSplit jsplit;
     SolveCache* solve = nullptr;
     DualData* dual = nullptr;  // set for a system of tet unknowns (dec_dual_build)
     SellMatrix blockinv;       // tet systems: inverse of the diagonal blocks over the

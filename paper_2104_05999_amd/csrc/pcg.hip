@@ -135,13 +135,78 @@ __global__ void k_init_jacobi(int64_t V, const VT* __restrict__ r, const VT* __r
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
+// Split-Jacobi start (CG on D^-1/2 A D^-1/2): p = r^, partials of r^.r^ (= r.D^-1 r)
+// and of r^.D r^ (= r.r, for the stopping test on the residual of A); dg = diag(A).
+template <class VT>
+__global__ void k_init_split(int64_t V, const VT* __restrict__ r, const VT* __restrict__ dg, VT* __restrict__ p,
+                             double* __restrict__ rz_part, double* __restrict__ rr_part) {
+    __shared__ double lds[BLOCK / 64 + 1];
+    int64_t i0, i1;
+    block_range(V, &i0, &i1);
+    VT rz = 0, rr = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+        const VT ri = r[i];
+        p[i] = ri;
+        rz += ri * ri;
+        rr += (ri * ri) * dg[i];
+    }
+    const double a = block_sum(static_cast<double>(rz), lds);
+    if (threadIdx.x == 0) rz_part[blockIdx.x] = a;
+    const double b = block_sum(static_cast<double>(rr), lds);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = b;
+}
+
+// Split-Jacobi values: a_ij (s_i s_j) in every stored slot (the product s_i s_j
+// is the same for (i, j) and (j, i), so the scaled matrix stays exactly
+// symmetric; padding stays 0), s = sqrt(1 / a_ii), s b and a_ii = 1 / invd_i.
+// Flags a diagonal entry that is not positive and finite.
+__global__ void k_jacobi_split(int64_t V, int64_t nslices, const int64_t* __restrict__ sptr,
+                               const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                               const double* __restrict__ invd, const double* __restrict__ rhs, double* __restrict__ v64,
+                               float* __restrict__ v32, double* __restrict__ s64, double* __restrict__ b64,
+                               double* __restrict__ d64, float* __restrict__ d32, unsigned* __restrict__ bad) {
+    bool neg = false;
+    RANGE_LOOP(i, nslices * SELL_C) {
+        const int64_t sl = i / SELL_C;
+        const int lane = static_cast<int>(i % SELL_C);
+        const int width = static_cast<int>((sptr[sl + 1] - sptr[sl]) / SELL_C);
+        const double si = i < V ? sqrt(invd[i]) : 0.0;
+        if (i < V) {
+            neg |= !(invd[i] > 0.0) || !isfinite(invd[i]);
+            s64[i] = si;
+            b64[i] = si * rhs[i];
+            d64[i] = 1.0 / invd[i];
+            d32[i] = static_cast<float>(1.0 / invd[i]);
+        }
+        for (int j = 0; j < width; ++j) {
+            const int64_t idx = sell_index(sptr[sl], width, j, lane);
+            const double v = sval[idx] * (si * sqrt(invd[scol[idx]]));
+            v64[idx] = v;
+            v32[idx] = static_cast<float>(v);
+        }
+    }
+    if (neg) atomicOr(bad, 1u);
+}
+
+// x *= s (to_hat = 0) or x /= s (to_hat = 1): between x and x^ = D^1/2 x
+__global__ void k_split_x(int64_t V, double* __restrict__ x, const double* __restrict__ s, int to_hat) {
+    GRID_STRIDE_LOOP(i, V) x[i] = to_hat ? x[i] / s[i] : x[i] * s[i];
+}
+
 // ---------------------------------------------------------------- iteration kernels
 // Every block folds the p.q partials of the SpMV in the same order, so all
 // blocks see the same alpha.  The update kernel moves r only (r -= alpha q);
 // the closing kernel moves x (x += alpha p) together with p, so p is read
 // once per iteration.  A non-positive p.q leaves x and r untouched; the
 // closing kernel reports the breakdown.
-template <class VT, bool JACOBI>
+// PJ: the preconditioner's part in these kernels.  PJ_NONE: z comes from
+// another kernel (FSAI, block Jacobi); PJ_JACOBI: z = D^-1 r (`invd` is
+// D^-1); PJ_SPLIT: the system is D^-1/2 A D^-1/2 and z = r (the vectors are
+// the hatted ones), with r.r of the unscaled residual taken as sum d_i r_i^2
+// (`invd` is then D itself).
+enum { PJ_NONE = 0, PJ_JACOBI = 1, PJ_SPLIT = 2 };
+
+template <class VT, int PJ>
 __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r, const VT* __restrict__ q,
                                                   const VT* __restrict__ invd, double* __restrict__ partials,
                                                   int P, int n_pq, PcgScalars* __restrict__ S) {
@@ -157,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
         if (i < R.end) {
             fr[k] = r[i];
             fq[k] = q[i];
-            fd[k] = JACOBI ? invd[i] : VT(0);
+            fd[k] = PJ != PJ_NONE ? invd[i] : VT(0);
         }
     }
     const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
@@ -171,19 +236,21 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
         if (i < R.end) {
             const VT ri = fr[k] - a * fq[k];
             r[i] = ri;
-            if (JACOBI) rz += ri * (fd[k] * ri);
-            rr += ri * ri;
+            if (PJ == PJ_JACOBI) rz += ri * (fd[k] * ri);
+            if (PJ == PJ_SPLIT) rz += ri * ri;
+            rr += PJ == PJ_SPLIT ? (ri * ri) * fd[k] : ri * ri;
         }
     }
     for (int64_t i = R.first + PREFETCH * R.step; i < R.end; i += R.step) {
         const VT ri = r[i] - a * q[i];
         r[i] = ri;
-        if (JACOBI) rz += ri * (invd[i] * ri);
-        rr += ri * ri;
+        if (PJ == PJ_JACOBI) rz += ri * (invd[i] * ri);
+        if (PJ == PJ_SPLIT) rz += ri * ri;
+        rr += PJ == PJ_SPLIT ? (ri * ri) * invd[i] : ri * ri;
     }
     const double b2 = block_sum(static_cast<double>(rr), lds);
     if (threadIdx.x == 0) partials[R_RR * P + blockIdx.x] = b2;
-    if (JACOBI) {
+    if (PJ != PJ_NONE) {
         const double b1 = block_sum(static_cast<double>(rz), lds);
         if (threadIdx.x == 0) partials[R_RZ * P + blockIdx.x] = b1;
     }
@@ -207,7 +274,7 @@ __device__ __forceinline__ bool energy_converged(const PcgScalars* S, double pq)
 // broke down), then p = z + beta p while running (z = D^-1 r for Jacobi);
 // block 0 writes the next state N.  A finished state is carried forward
 // unchanged.
-template <class VT, bool JACOBI>
+template <class VT, int PJ>
 __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, const VT* __restrict__ r,
                                                  const VT* __restrict__ invd, const VT* __restrict__ z,
                                                  VT* __restrict__ p, const double* __restrict__ partials, int P,
@@ -227,7 +294,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
     for (int k = 0; k < CLOSE_PREFETCH; ++k) {
         const int64_t i = R.first + k * R.step;
         if (i < R.end) {
-            fz[k] = JACOBI ? invd[i] * r[i] : z[i];
+            fz[k] = PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i]);
             fp[k] = p[i];
             fx[k] = x[i];
         }
@@ -259,7 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         for (int64_t i = R.first + CLOSE_PREFETCH * R.step; i < R.end; i += R.step) {
             const VT pi = p[i];
             x[i] = x[i] + a * pi;
-            if (run) p[i] = (JACOBI ? invd[i] * r[i] : z[i]) + bt * pi;
+            if (run) p[i] = (PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i])) + bt * pi;
         }
     }
     if (lead) {
@@ -284,16 +351,18 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
 }
 
 // ---------------------------------------------------------------- refinement kernels
-// r32 = r64 / ||r64|| (||r64||^2 in src->rr), x32 = 0, partials of r32.r32
+// r32 = r64 / ||r64|| (||r64||^2 in src->rr), x32 = 0, partials of r32.r32;
+// with split Jacobi (sc set) r32 = sc * r64 / ||r64||, the hatted residual
 __global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgScalars* __restrict__ src,
-                         float* __restrict__ r32, float* __restrict__ x32, double* __restrict__ partials) {
+                         const double* __restrict__ sc, float* __restrict__ r32, float* __restrict__ x32,
+                         double* __restrict__ partials) {
     __shared__ double lds[BLOCK / 64 + 1];
     const double inv = 1.0 / sqrt(src->rr);
     int64_t i0, i1;
     block_range(V, &i0, &i1);
     float s = 0.0f;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += BLOCK) {
-        const float ri = static_cast<float>(r64[i] * inv);
+        const float ri = static_cast<float>(sc ? sc[i] * (r64[i] * inv) : r64[i] * inv);
         r32[i] = ri;
         x32[i] = 0.0f;
         s += ri * ri;
@@ -302,9 +371,14 @@ __global__ void k_to_f32(int64_t V, const double* __restrict__ r64, const PcgSca
     if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
-// x64 += scale * x32 (scale = ||r64|| of the refinement step, or its negative to undo it)
-__global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __restrict__ x32, double scale) {
-    GRID_STRIDE_LOOP(i, V) x64[i] = x64[i] + scale * static_cast<double>(x32[i]);
+// x64 += scale * x32 (scale = ||r64|| of the refinement step, or its negative to undo it);
+// with split Jacobi (sc set) x32 is hatted: x64 += scale * sc * x32
+__global__ void k_correct(int64_t V, double* __restrict__ x64, const float* __restrict__ x32, const double* __restrict__ sc,
+                          double scale) {
+    GRID_STRIDE_LOOP(i, V) {
+        const double c = static_cast<double>(x32[i]);
+        x64[i] = x64[i] + scale * (sc ? sc[i] * c : c);
+    }
 }
 
 // ---------------------------------------------------------------- host driver
@@ -314,9 +388,12 @@ struct Run {
     SellView<VT> G, GT;  // FSAI factor and its transpose (sliced ELL)
     SellView<VT> M;      // block-Jacobi inverse (tet systems)
     VT *x, *r, *p, *q, *z, *w;
-    const VT* invd;
+    const VT* invd;  // D^-1 (Jacobi), D (split Jacobi)
     PcgScalars* st;  // two parities
     int precond;
+    bool split;          // Jacobi in split form: A is D^-1/2 A D^-1/2, the vectors are hatted
+    const double* b;     // right-hand side of the system A is (s b with split Jacobi)
+    const double* sc;    // split Jacobi: s = D^-1/2 (null otherwise)
 };
 
 // With events, the launch carries them (hipExtLaunchKernelGGL): the
@@ -442,33 +519,42 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     PcgScalars* S = R.st + par;
     PcgScalars* N = R.st + (par ^ 1);
     launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
-    if (R.precond == DEC_PRECOND_JACOBI) {
-        hipLaunchKernelGGL((k_update<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part, P,
+    if (R.precond == DEC_PRECOND_JACOBI && R.split) {
+        hipLaunchKernelGGL((k_update<VT, PJ_SPLIT>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part, P,
                            n_pq, S);
-        hipLaunchKernelGGL((k_close<VT, true>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
+        hipLaunchKernelGGL((k_close<VT, PJ_SPLIT>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
+                           (const VT*)nullptr, (const VT*)nullptr, R.p, part, P, G, S, N);
+    } else if (R.precond == DEC_PRECOND_JACOBI) {
+        hipLaunchKernelGGL((k_update<VT, PJ_JACOBI>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part,
+                           P, n_pq, S);
+        hipLaunchKernelGGL((k_close<VT, PJ_JACOBI>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
                            (const VT*)nullptr, R.p, part, P, G, S, N);
     } else if (R.precond == DEC_PRECOND_BLOCK) {
-        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, (const VT*)nullptr,
-                           part, P, n_pq, S);
+        hipLaunchKernelGGL((k_update<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q,
+                           (const VT*)nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.z, R.r, region(c, R_RZ), S);       // z = M r, r.z partials
-        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, (const VT*)nullptr,
-                           R.z, R.p, part, P, c->Gs, S, N);
+        hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
+                           (const VT*)nullptr, R.z, R.p, part, P, c->Gs, S, N);
     } else {
-        hipLaunchKernelGGL((k_update<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, (const VT*)nullptr,
-                           part, P, n_pq, S);
+        hipLaunchKernelGGL((k_update<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q,
+                           (const VT*)nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
-        hipLaunchKernelGGL((k_close<VT, false>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, (const VT*)nullptr,
-                           R.z, R.p, part, P, c->Gs, S, N);
+        hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
+                           (const VT*)nullptr, R.z, R.p, part, P, c->Gs, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }
 
-// preconditioner start from r (r.r partials already in R_RR): p = M^-1 r, partials of r.z
+// preconditioner start from r (r.r partials already in R_RR): p = M^-1 r, partials of r.z;
+// split Jacobi also rewrites the R_RR partials (G blocks) with r.r of the unscaled residual
 template <class VT>
 void enqueue_precond_start(SolveCache* c, const Run<VT>& R) {
     const int64_t V = R.A.V;
-    if (R.precond == DEC_PRECOND_JACOBI) {
+    if (R.precond == DEC_PRECOND_JACOBI && R.split) {
+        hipLaunchKernelGGL(k_init_split<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
+                           region(c, R_RZ), region(c, R_RR));
+    } else if (R.precond == DEC_PRECOND_JACOBI) {
         hipLaunchKernelGGL(k_init_jacobi<VT>, dim3(c->G), dim3(BLOCK), 0, c->stream, V, R.r, R.invd, R.p,
                            region(c, R_RZ));
     } else if (R.precond == DEC_PRECOND_BLOCK) {
@@ -538,7 +624,7 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             continue;
         }
         if (o.use_graph) {
-            GraphKey key{prec, R.precond, chunk, c->unroll[prec], c->nt[prec]};
+            GraphKey key{prec, R.precond + (R.split ? 8 : 0), chunk, c->unroll[prec], c->nt[prec]};
             auto it = c->graphs.find(key);
             hipGraphExec_t exec = nullptr;
             if (it == c->graphs.end()) {
@@ -596,10 +682,45 @@ SellView<VT> view(const SolveCache* c, const SellMatrix& S, int64_t V) {
 template <class VT>
 Run<VT> make_run(dec_mesh* m, SolveCache* c, int precond);
 
+// Split Jacobi for a Jacobi solve of a plain (not difference-form) system:
+// builds the scaled values once per assembly and boundary data, unless
+// DEC_JACOBI_SPLIT=0.  Returns whether the solve takes it.
+bool use_split(dec_mesh* m, SolveCache* c, int precond) {
+    if (precond != DEC_PRECOND_JACOBI || m->sell.excess64.p || c->no_split) return false;
+    JacobiSplit& J = m->jsplit;
+    if (J.ready) return J.usable;
+    dec_ctx* ctx = m->ctx;
+    const SellMatrix& S = m->sell;
+    J.v64.alloc(ctx, S.entries);
+    J.v32.alloc(ctx, S.entries);
+    J.s64.alloc(ctx, m->V);
+    J.b64.alloc(ctx, m->V);
+    DBuf<unsigned> bad;
+    bad.alloc(ctx, 1);
+    bad.zero();
+    J.d64.alloc(ctx, m->V);
+    J.d32.alloc(ctx, m->V);
+    hipLaunchKernelGGL(k_jacobi_split, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
+                       S.nslices, S.ptr.p, S.col.p, S.val64.p, m->invdiag64.p, m->rhs.p, J.v64.p, J.v32.p, J.s64.p,
+                       J.b64.p, J.d64.p, J.d32.p, bad.p);
+    HIP_CHECK(hipGetLastError());
+    J.usable = *static_cast<unsigned*>(ctx->readback(bad.p, sizeof(unsigned))) == 0;
+    J.ready = true;
+    clear_graphs(c);  // graphs hold the pointers of the previous values
+    return J.usable;
+}
+
 template <>
 Run<double> make_run<double>(dec_mesh* m, SolveCache* c, int precond) {
     Run<double> R{};
     R.A = view<double>(c, m->sell, m->V);
+    R.split = use_split(m, c, precond);
+    R.b = m->rhs.p;
+    if (R.split) {
+        R.A.val = m->jsplit.v64.p;
+        R.b = m->jsplit.b64.p;
+        R.sc = m->jsplit.s64.p;
+    }
     R.G = view<double>(c, m->fsai.g_sell, m->V);
     R.GT = view<double>(c, m->fsai.gt_sell, m->V);
     R.M = view<double>(c, m->blockinv, m->V);
@@ -609,7 +730,7 @@ Run<double> make_run<double>(dec_mesh* m, SolveCache* c, int precond) {
     R.q = c->q64.p;
     R.z = c->z64.p;
     R.w = c->w64.p;
-    R.invd = m->invdiag64.p;
+    R.invd = R.split ? m->jsplit.d64.p : m->invdiag64.p;  // split Jacobi: the diagonal itself
     R.st = c->st.p;
     R.precond = precond;
     return R;
@@ -619,6 +740,11 @@ template <>
 Run<float> make_run<float>(dec_mesh* m, SolveCache* c, int precond) {
     Run<float> R{};
     R.A = view<float>(c, m->sell, m->V);
+    R.split = use_split(m, c, precond);
+    if (R.split) {
+        R.A.val = m->jsplit.v32.p;
+        R.sc = m->jsplit.s64.p;
+    }
     R.G = view<float>(c, m->fsai.g_sell, m->V);
     R.GT = view<float>(c, m->fsai.gt_sell, m->V);
     R.M = view<float>(c, m->blockinv, m->V);
@@ -628,7 +754,7 @@ Run<float> make_run<float>(dec_mesh* m, SolveCache* c, int precond) {
     R.q = c->q32.p;
     R.z = c->z32.p;
     R.w = c->w32.p;
-    R.invd = m->invdiag32.p;
+    R.invd = R.split ? m->jsplit.d32.p : m->invdiag32.p;
     R.st = c->st.p + 2;
     R.precond = precond;
     return R;
@@ -664,31 +790,38 @@ int pcg_fp64(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, int
     const double tol2 = o.tol * o.tol;
     const bool en = o.norm == DEC_NORM_ENERGY;
     int64_t total = 0;
+    // split Jacobi iterates on x^ = D^1/2 x, in x64 between these two calls
+    auto hat = [&](int to_hat) {
+        if (R.split)
+            hipLaunchKernelGGL(k_split_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, R.x, R.sc, to_hat);
+    };
     for (int restart = 0;; ++restart) {
         const int64_t left = o.max_iters - total;
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left > 0 ? left : (int64_t)1, (int32_t)en);
         // rr_stop = tol^2 b.b (the relative test in absolute form)
         hipLaunchKernelGGL(k_norm2, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, m->rhs.p, region(c, R_RR));
         finalize(c, FIN_NORM2, c->G, tol2, 0, R.st);
-        launch_sell<double, MODE_RESID>(c, R.A, R.x, R.r, m->rhs.p, region(c, R_RR), nullptr);
+        hat(1);
+        launch_sell<double, MODE_RESID>(c, R.A, R.x, R.r, R.b, region(c, R_RR), nullptr);
         if (en) {
-            // ||x0||_A^2 = x0.(b + r0) seeds cum; rr_stop = tol^2
-            hipLaunchKernelGGL(k_xbr, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, R.x, m->rhs.p, R.r,
-                               region(c, R_PQ));
+            // ||x0||_A^2 = x0.(b + r0) seeds cum (the same on the split system); rr_stop = tol^2
+            hipLaunchKernelGGL(k_xbr, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, R.x, R.b, R.r, region(c, R_PQ));
             hipLaunchKernelGGL(k_energy_start, dim3(1), dim3(BLOCK), 0, c->stream, region(c, R_PQ), c->G, tol2,
                                R.st);
         }
         enqueue_precond_start<double>(c, R);
-        finalize(c, FIN_START, c->Gs, 0.0, 0, R.st, rz_parts(c, R.precond));
+        finalize(c, FIN_START, R.split ? c->G : c->Gs, 0.0, 0, R.st, rz_parts(c, R.precond));
         HIP_CHECK(hipGetLastError());
         PcgScalars s = read_state(c, R.st);
         if (!s.done) {
             if (left <= 0) {
+                hat(0);
                 *iters_out = total;
                 return DEC_ENOTCONV;
             }
             s = iterate(c, R, o, stats);
         }
+        hat(0);
         total += s.iter;
         *iters_out = total;
         if (s.done == PCG_BREAKDOWN) return DEC_EBREAKDOWN;
@@ -737,7 +870,7 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
             // (an FP32 solve below its own rounding floor can return nonsense)
             if (rn > rn_prev) {
                 hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p,
-                                   c->x32.p, -rn_prev);
+                                   c->x32.p, R.sc, -rn_prev);
                 HIP_CHECK(hipGetLastError());
             }
             return finish_fp64();
@@ -748,8 +881,8 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         const int64_t left = o.max_iters - inner_total;
         if (left <= 0) return DEC_ENOTCONV;
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c->stream, R.st, left < inner_cap ? left : inner_cap, 0);
-        hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s4, c->r32.p, c->x32.p,
-                           region(c, R_RR));
+        hipLaunchKernelGGL(k_to_f32, dim3(c->G), dim3(BLOCK), 0, c->stream, m->V, c->r64.p, s4, R.sc, c->r32.p,
+                           c->x32.p, region(c, R_RR));
         enqueue_precond_start<float>(c, R);
         finalize(c, FIN_START, c->G, itol * itol, 1, R.st, rz_parts(c, R.precond));
         HIP_CHECK(hipGetLastError());
@@ -759,7 +892,8 @@ int ir_mixed(dec_mesh* m, SolveCache* c, const dec_solve_opts& o, double bb, dec
         if (stats) stats->iterations = inner_total;
         // an FP32 solve that broke down or ran out of iterations is not applied
         if (s.done != PCG_CONVERGED) return finish_fp64();
-        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, rn);
+        hipLaunchKernelGGL(k_correct, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, c->x64.p, c->x32.p, R.sc,
+                           rn);
         HIP_CHECK(hipGetLastError());
         rn_prev = rn;
     }
@@ -813,6 +947,7 @@ SolveCache* get_solve_cache(dec_mesh* m) {
             c->pinned_variant = true;
         }
         if (const char* env = getenv("DEC_SELL_COLS")) c->wide_cols = atoi(env) == 32;
+        if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->no_split = atoi(env) == 0;
         auto blocks = [&](int64_t rows_per_block, int pc) {
             const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
             const int64_t cap = (int64_t)pc * m->ctx->num_cus;

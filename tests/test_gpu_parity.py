@@ -404,6 +404,33 @@ def test_pruned_pattern_products_are_bit_identical(ctx, dev):
     assert st_p["spmv_nnz"] < st_f["spmv_nnz"] == m.nnz
 
 
+@pytest.mark.parametrize("precision,norm", [(0, 0), (1, 0), (0, 1)])
+def test_split_jacobi_matches_jacobi(ctx, dev, precision, norm):
+    """Jacobi in split form (CG on D^-1/2 A D^-1/2, the solver's default) takes the iterates of
+    Jacobi-preconditioned CG on A up to rounding: the same solution to the tolerance's accuracy,
+    the same iteration count within a few, in FP64, with FP32 inner solves, and with the A-norm
+    test; the oracle's solution bounds both."""
+    import os
+    s = _system(12, n_cracks=30)
+    xs = _reference(s).x
+    out = {}
+    for split in ("1", "0"):
+        os.environ["DEC_JACOBI_SPLIT"] = split
+        try:
+            m, _, _, _, _ = _gpu(ctx, s, dev)
+            T, st, rc = m.solve(tol=1e-12, precision=precision, norm=norm)
+            assert rc == 0, (split, st)
+            m.close()
+        finally:
+            del os.environ["DEC_JACOBI_SPLIT"]
+        out[split] = (T.cpu().numpy(), st)
+    (Ts, ss), (Tp, sp) = out["1"], out["0"]
+    scale = np.abs(xs).max()
+    assert np.abs(Ts - xs).max() <= 1e-9 * scale and np.abs(Tp - xs).max() <= 1e-9 * scale
+    assert np.abs(Ts - Tp).max() <= 1e-9 * scale
+    assert abs(ss["iterations"] - sp["iterations"]) <= max(3, sp["iterations"] // 50), (ss, sp)
+
+
 def test_column_offsets_and_their_fallback(ctx, dev):
     """The sliced-ELL copy reads 16-bit column offsets when every column lies within 2^15 of its
     row (the 41^3-vertex lattice: neighbours within 41^2 + 42 rows) and the int32 columns when
