@@ -242,6 +242,18 @@ typedef struct dec_solve_stats {
     double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
 } dec_solve_stats;
 
+/* Solver knobs read from the environment when a mesh's solver state is
+ * first created (first dec_solve or dec_spmv on it), for tests and timing;
+ * none changes a result except DEC_JACOBI_SPLIT, which changes rounding:
+ *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1  pin the sliced-ELL variant the
+ *       autotuner would pick (entry pairs in flight, non-temporal loads);
+ *   DEC_SELL_COLS=32      read int32 columns even where 16-bit offsets exist;
+ *   DEC_JACOBI_SPLIT=0    run Jacobi PCG on A rather than in split form
+ *       (CG on D^-1/2 A D^-1/2, the default for plain systems with a
+ *       positive diagonal);
+ *   DEC_BLOCKS_PER_CU, DEC_SPMV_BLOCKS_PER_CU  workgroups per CU of the
+ *       vector kernels (default 4) and of the SpMV (default 8). */
+
 /* Fill opts with the defaults: FP64, Jacobi, tol 1e-10, inner_tol 1e-5,
  * adaptive final inner tolerance on, cold start, max_iters 100000, auto
  * format, chunk 32, graphs on, profiling off, plain residual norm. */
