@@ -243,8 +243,9 @@ typedef struct dec_solve_stats {
 } dec_solve_stats;
 
 /* Solver knobs read from the environment when a mesh's solver state is
- * first created (first dec_solve or dec_spmv on it), for tests and timing;
- * none changes a result except DEC_JACOBI_SPLIT, which changes rounding:
+ * first created (first dec_solve or dec_spmv on it), for tests and timing.
+ * The first three change no result; the others change rounding (the split
+ * form's arithmetic, or how the reductions are partitioned):
  *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1  pin the sliced-ELL variant the
  *       autotuner would pick (entry pairs in flight, non-temporal loads);
  *   DEC_SELL_COLS=32      read int32 columns even where 16-bit offsets exist;
