@@ -249,9 +249,9 @@ typedef struct dec_solve_stats {
  *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1  pin the sliced-ELL variant the
  *       autotuner would pick (entry pairs in flight, non-temporal loads);
  *   DEC_SELL_COLS=32      read int32 columns even where 16-bit offsets exist;
- *   DEC_JACOBI_SPLIT=0    run Jacobi PCG on A rather than in split form
- *       (CG on D^-1/2 A D^-1/2, the default for plain systems with a
- *       positive diagonal);
+ *   DEC_JACOBI_SPLIT=0|1  run Jacobi PCG on A, or always in split form (CG
+ *       on D^-1/2 A D^-1/2); unset, the split form is taken for plain
+ *       systems of 65,536 rows or more with a positive diagonal;
  *   DEC_BLOCKS_PER_CU, DEC_SPMV_BLOCKS_PER_CU  workgroups per CU of the
  *       vector kernels (default 4) and of the SpMV (default 8). */
 

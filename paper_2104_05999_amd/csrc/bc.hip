@@ -177,7 +177,8 @@ __global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int3
 __global__ void k_eliminate(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                             const uint8_t* __restrict__ fixed, double* __restrict__ val64, float* __restrict__ val32,
                             const int32_t* __restrict__ diag_pos, double* __restrict__ inv64,
-                            float* __restrict__ inv32) {
+                            float* __restrict__ inv32, unsigned long long* __restrict__ nonpos) {
+    unsigned long long bad = 0;
     RANGE_LOOP(v, V) {
         const bool fv = fixed[v] != 0;
         for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
@@ -191,7 +192,9 @@ __global__ void k_eliminate(int64_t V, const int32_t* __restrict__ row_ptr, cons
         const int32_t d = diag_pos[v];
         inv64[v] = 1.0 / val64[d];
         inv32[v] = 1.0f / val32[d];
+        bad += !(val64[d] > 0.0) || !isfinite(val64[d]);
     }
+    if (bad) atomicAdd(nonpos, bad);  // rows whose diagonal is not positive and finite
 }
 
 void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* f0) {
@@ -218,8 +221,8 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     anchored.zero();
     hipLaunchKernelGGL(k_uf_anchor, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, parent.p, anchored.p);
     m->fixed.alloc(ctx, V);
-    DBuf<unsigned long long> npin;
-    npin.alloc(ctx, 1);
+    DBuf<unsigned long long> npin;  // pinned vertices, rows with a diagonal that is not positive
+    npin.alloc(ctx, 2);
     npin.zero();
     hipLaunchKernelGGL(k_mark_fixed, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, parent.p, anchored.p,
                        m->fixed.p, npin.p);
@@ -237,10 +240,13 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     m->invdiag64.alloc(ctx, V);
     m->invdiag32.alloc(ctx, V);
     hipLaunchKernelGGL(k_eliminate, dim3(grid_xcd(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->fixed.p,
-                       m->val64.p, m->val32.p, m->diag_pos.p, m->invdiag64.p, m->invdiag32.p);
+                       m->val64.p, m->val32.p, m->diag_pos.p, m->invdiag64.p, m->invdiag32.p, npin.p + 1);
     HIP_CHECK(hipGetLastError());
     refresh_sell_values(m);
-    m->n_pinned = (int64_t) * static_cast<unsigned long long*>(ctx->readback(npin.p, sizeof(unsigned long long)));
+    unsigned long long h[2];
+    std::memcpy(h, ctx->readback(npin.p, sizeof(h)), sizeof(h));
+    m->n_pinned = (int64_t)h[0];
+    m->diag_positive = h[1] == 0;
     m->bc_ready = true;
     m->fsai.ready = false;
     m->jsplit.ready = false;

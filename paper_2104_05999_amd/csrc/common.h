@@ -160,7 +160,6 @@ struct FsaiFactor {
 // positive; stale after assembly or new boundary data.
 struct JacobiSplit {
     bool ready = false;   // built for the current values
-    bool usable = false;  // every diagonal entry positive and finite
     DBuf<double> v64;     // [entries] a_ij s_i s_j, s = D^-1/2
     DBuf<float> v32;      // [entries]
     DBuf<double> s64;     // [V] s
@@ -233,6 +232,7 @@ struct dec_mesh {
 
     FsaiFactor fsai;
     JacobiSplit jsplit;
+    bool diag_positive = false;  // every diagonal entry positive and finite (set with the boundary data)
     SolveCache* solve = nullptr;
     DualData* dual = nullptr;  // set for a system of tet unknowns (dec_dual_build)
     SellMatrix blockinv;       // tet systems: inverse of the diagonal blocks over the

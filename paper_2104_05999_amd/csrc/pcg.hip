@@ -159,20 +159,18 @@ __global__ void k_init_split(int64_t V, const VT* __restrict__ r, const VT* __re
 // Split-Jacobi values: a_ij (s_i s_j) in every stored slot (the product s_i s_j
 // is the same for (i, j) and (j, i), so the scaled matrix stays exactly
 // symmetric; padding stays 0), s = sqrt(1 / a_ii), s b and a_ii = 1 / invd_i.
-// Flags a diagonal entry that is not positive and finite.
+// Every diagonal entry is positive (checked with the boundary data).
 __global__ void k_jacobi_split(int64_t V, int64_t nslices, const int64_t* __restrict__ sptr,
                                const int32_t* __restrict__ scol, const double* __restrict__ sval,
                                const double* __restrict__ invd, const double* __restrict__ rhs, double* __restrict__ v64,
                                float* __restrict__ v32, double* __restrict__ s64, double* __restrict__ b64,
-                               double* __restrict__ d64, float* __restrict__ d32, unsigned* __restrict__ bad) {
-    bool neg = false;
+                               double* __restrict__ d64, float* __restrict__ d32) {
     RANGE_LOOP(i, nslices * SELL_C) {
         const int64_t sl = i / SELL_C;
         const int lane = static_cast<int>(i % SELL_C);
         const int width = static_cast<int>((sptr[sl + 1] - sptr[sl]) / SELL_C);
         const double si = i < V ? sqrt(invd[i]) : 0.0;
         if (i < V) {
-            neg |= !(invd[i] > 0.0) || !isfinite(invd[i]);
             s64[i] = si;
             b64[i] = si * rhs[i];
             d64[i] = 1.0 / invd[i];
@@ -185,7 +183,6 @@ __global__ void k_jacobi_split(int64_t V, int64_t nslices, const int64_t* __rest
             v32[idx] = static_cast<float>(v);
         }
     }
-    if (neg) atomicOr(bad, 1u);
 }
 
 // x *= s (to_hat = 0) or x /= s (to_hat = 1): between x and x^ = D^1/2 x
@@ -682,32 +679,41 @@ SellView<VT> view(const SolveCache* c, const SellMatrix& S, int64_t V) {
 template <class VT>
 Run<VT> make_run(dec_mesh* m, SolveCache* c, int precond);
 
-// Split Jacobi for a Jacobi solve of a plain (not difference-form) system:
-// builds the scaled values once per assembly and boundary data, unless
-// DEC_JACOBI_SPLIT=0.  Returns whether the solve takes it.
+// Rows from which the split form pays: it saves one vector per iteration but
+// adds three small kernels per solve, which on systems this small (short,
+// launch-bound iterations, often warm-started) cost more than they save.
+constexpr int64_t SPLIT_MIN_ROWS = int64_t(1) << 16;
+
+// Split Jacobi for a Jacobi solve of a plain (not difference-form) system
+// whose diagonal is positive (checked with the boundary data), from
+// SPLIT_MIN_ROWS rows (DEC_JACOBI_SPLIT=1: always, 0: never): builds the
+// scaled values once per assembly and boundary data.  Returns whether the
+// solve takes it.
 bool use_split(dec_mesh* m, SolveCache* c, int precond) {
-    if (precond != DEC_PRECOND_JACOBI || m->sell.excess64.p || c->no_split) return false;
+    if (precond != DEC_PRECOND_JACOBI || m->sell.excess64.p || !m->diag_positive) return false;
+    if (c->split == 0 || (c->split < 0 && m->V < SPLIT_MIN_ROWS)) return false;
     JacobiSplit& J = m->jsplit;
-    if (J.ready) return J.usable;
+    if (J.ready) return true;
     dec_ctx* ctx = m->ctx;
     const SellMatrix& S = m->sell;
-    J.v64.alloc(ctx, S.entries);
+    const void* before[4] = {J.v64.p, J.v32.p, J.d64.p, J.d32.p};
+    J.v64.alloc(ctx, S.entries);  // kept when large enough, so graphs stay valid
     J.v32.alloc(ctx, S.entries);
     J.s64.alloc(ctx, m->V);
     J.b64.alloc(ctx, m->V);
-    DBuf<unsigned> bad;
-    bad.alloc(ctx, 1);
-    bad.zero();
     J.d64.alloc(ctx, m->V);
     J.d32.alloc(ctx, m->V);
-    hipLaunchKernelGGL(k_jacobi_split, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
+    // on the solve's stream, so the iterations that read the values follow it (its inputs are
+    // complete: the solve waited for the caller's stream)
+    hipLaunchKernelGGL(k_jacobi_split, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, c->stream, m->V,
                        S.nslices, S.ptr.p, S.col.p, S.val64.p, m->invdiag64.p, m->rhs.p, J.v64.p, J.v32.p, J.s64.p,
-                       J.b64.p, J.d64.p, J.d32.p, bad.p);
+                       J.b64.p, J.d64.p, J.d32.p);
     HIP_CHECK(hipGetLastError());
-    J.usable = *static_cast<unsigned*>(ctx->readback(bad.p, sizeof(unsigned))) == 0;
     J.ready = true;
-    clear_graphs(c);  // graphs hold the pointers of the previous values
-    return J.usable;
+    // graphs hold the scaled values' and the diagonal's pointers
+    if (before[0] != J.v64.p || before[1] != J.v32.p || before[2] != J.d64.p || before[3] != J.d32.p)
+        clear_graphs(c);
+    return true;
 }
 
 template <>
@@ -947,7 +953,7 @@ SolveCache* get_solve_cache(dec_mesh* m) {
             c->pinned_variant = true;
         }
         if (const char* env = getenv("DEC_SELL_COLS")) c->wide_cols = atoi(env) == 32;
-        if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->no_split = atoi(env) == 0;
+        if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->split = atoi(env) != 0;
         auto blocks = [&](int64_t rows_per_block, int pc) {
             const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
             const int64_t cap = (int64_t)pc * m->ctx->num_cus;

@@ -78,7 +78,7 @@ struct SolveCache {
     bool tuned[2] = {false, false};
     bool pinned_variant = false;  // set through the environment: no tuning
     bool wide_cols = false;       // int32 columns even where 16-bit offsets exist (environment)
-    bool no_split = false;        // Jacobi on A itself rather than in split form (environment)
+    int split = -1;               // Jacobi in split form: 1 always, 0 never, -1 by size (environment)
     DBuf<double> x64, r64, p64, q64, z64, w64, t64;
     DBuf<float> x32, r32, p32, q32, z32, w32;
     DBuf<double> partials;  // [3G]: per-block partial sums of p.q, r.r, r.z
