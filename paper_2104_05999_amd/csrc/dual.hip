@@ -19,6 +19,7 @@
 //
 // Compiled without floating-point contraction: the Voronoi-edge end points
 // enter the crack predicate, which decides integers.
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -322,19 +323,37 @@ __global__ void k_dual_cluster_size(int64_t T, int32_t* parent, int32_t* __restr
 
 __device__ __forceinline__ bool is_block(int s) { return s >= 2 && s <= MAX_BLOCK; }
 
-// Row lengths of the block inverse; member slots per block cluster (at its root)
-__global__ void k_dual_block_len(int64_t T, const int32_t* __restrict__ root, const int32_t* __restrict__ size,
-                                 int32_t* __restrict__ len, int32_t* __restrict__ slots,
-                                 unsigned long long* __restrict__ counts) {
+// Row lengths of the block inverse; member slots per block cluster (at its
+// root); the number of block clusters and the largest, reduced per workgroup
+// before one atomic each (one per cluster would serialise on two words).
+__global__ __launch_bounds__(BLOCK) void k_dual_block_len(int64_t T, const int32_t* __restrict__ root,
+                                                          const int32_t* __restrict__ size, int32_t* __restrict__ len,
+                                                          int32_t* __restrict__ slots,
+                                                          unsigned long long* __restrict__ counts) {
+    __shared__ unsigned long long lds[BLOCK / 64];
+    __shared__ int wmax[BLOCK / 64];
+    unsigned long long leads = 0;
+    int smax = 0;
     GRID_STRIDE_LOOP(t, T) {
         const int s = size[root[t]];
         const bool lead = is_block(s) && root[t] == (int32_t)t;
         len[t] = is_block(s) ? s : 1;
         slots[t] = lead ? s : 0;
         if (lead) {
-            atomicAdd(counts, 1ull);
-            atomicMax(counts + 1, (unsigned long long)s);
+            ++leads;
+            smax = max(smax, s);
         }
+    }
+    const unsigned long long total = block_sum(leads, lds);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = smax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) m = max(m, wmax[w]);
+        if (total) atomicAdd(counts, total);
+        if (m) atomicMax(counts + 1, (unsigned long long)m);
     }
 }
 
@@ -368,8 +387,12 @@ __global__ void k_dual_block_single(int64_t T, const int32_t* __restrict__ root,
 // ascending), Cholesky A = L L^T, then column b of the inverse from
 // L y = e_b, L^T x = y; its entries a >= b go to (a, b) and (b, a).  A pivot
 // that is not positive (not expected: the block of an SPD matrix) leaves the
-// cluster's rows diagonal (Jacobi).
-__global__ void k_dual_block_inv(int64_t T, const int32_t* __restrict__ root, const int32_t* __restrict__ size,
+// cluster's rows diagonal (Jacobi).  N bounds the cluster size the launch
+// handles (clusters of other sizes are skipped): every loop runs to N with
+// the cluster's own size s as a guard, so for N = 8 the matrix stays in
+// registers; the operations and their order are those of a loop to s.
+template <int N>
+__global__ void k_dual_block_inv(int64_t T, int lo, const int32_t* __restrict__ root, const int32_t* __restrict__ size,
                                  const int64_t* __restrict__ slot_off, const int32_t* __restrict__ members,
                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  const double* __restrict__ v64, const int32_t* __restrict__ m_ptr,
@@ -377,60 +400,94 @@ __global__ void k_dual_block_inv(int64_t T, const int32_t* __restrict__ root, co
     GRID_STRIDE_LOOP(t, T) {
         if (root[t] != (int32_t)t) continue;
         const int s = size[t];
-        if (!is_block(s)) continue;
-        int mem[MAX_BLOCK];
-        for (int a = 0; a < s; ++a) mem[a] = members[slot_off[t] + a];
-        for (int a = 1; a < s; ++a)
-            for (int b = a; b > 0 && mem[b - 1] > mem[b]; --b) {
-                const int x = mem[b];
-                mem[b] = mem[b - 1];
-                mem[b - 1] = x;
-            }
-        double A[MAX_BLOCK][MAX_BLOCK], dg[MAX_BLOCK], y[MAX_BLOCK];
-        for (int a = 0; a < s; ++a)
-            for (int b = 0; b < s; ++b) A[a][b] = 0.0;
-        for (int a = 0; a < s; ++a)
+        if (!is_block(s) || s < lo || s > N) continue;
+        int mem[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) mem[a] = a < s ? members[slot_off[t] + a] : INT_MAX;
+#pragma unroll
+        for (int a = 1; a < N; ++a)  // insertion sort; the INT_MAX tail stays in place
+#pragma unroll
+            for (int b = a; b > 0; --b)
+                if (mem[b - 1] > mem[b]) {
+                    const int x = mem[b];
+                    mem[b] = mem[b - 1];
+                    mem[b - 1] = x;
+                }
+        double A[N][N], dg[N], y[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) A[a][b] = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            if (a >= s) continue;
             for (int32_t e = row_ptr[mem[a]]; e < row_ptr[mem[a] + 1]; ++e) {
                 const int c = col[e];
-                for (int b = 0; b < s; ++b)
-                    if (mem[b] == c) A[a][b] = v64[e];
+                const double v = v64[e];
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    if (mem[b] == c) A[a][b] = v;
             }
-        for (int a = 0; a < s; ++a) dg[a] = A[a][a];
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a) dg[a] = A[a][a];
         bool ok = true;
-        for (int j = 0; j < s && ok; ++j) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j >= s || !ok) continue;
             double d = A[j][j];
+#pragma unroll
             for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
             if (!(d > 0.0) || !isfinite(d)) {
                 ok = false;
-                break;
+                continue;
             }
             A[j][j] = sqrt(d);
-            for (int i = j + 1; i < s; ++i) {
+#pragma unroll
+            for (int i = j + 1; i < N; ++i) {
+                if (i >= s) continue;
                 double v = A[i][j];
+#pragma unroll
                 for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
                 A[i][j] = v / A[j][j];
             }
         }
-        for (int a = 0; a < s; ++a) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            if (a >= s) continue;
             const int32_t p = m_ptr[mem[a]];
-            for (int b = 0; b < s; ++b) m_col[p + b] = mem[b];
+#pragma unroll
+            for (int b = 0; b < N; ++b)
+                if (b < s) m_col[p + b] = mem[b];
         }
-        for (int b = 0; b < s; ++b) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            if (b >= s) continue;
             if (ok) {
-                for (int i = 0; i < s; ++i) {  // L y = e_b
+#pragma unroll
+                for (int i = 0; i < N; ++i) {  // L y = e_b
+                    if (i >= s) continue;
                     double v = i == b ? 1.0 : 0.0;
+#pragma unroll
                     for (int k = 0; k < i; ++k) v -= A[i][k] * y[k];
                     y[i] = v / A[i][i];
                 }
-                for (int i = s - 1; i >= 0; --i) {  // L^T x = y, in place
+#pragma unroll
+                for (int i = N - 1; i >= 0; --i) {  // L^T x = y, in place
+                    if (i >= s) continue;
                     double v = y[i];
-                    for (int k = i + 1; k < s; ++k) v -= A[k][i] * y[k];
+#pragma unroll
+                    for (int k = i + 1; k < N; ++k)
+                        if (k < s) v -= A[k][i] * y[k];
                     y[i] = v / A[i][i];
                 }
             } else {
-                for (int i = 0; i < s; ++i) y[i] = i == b ? 1.0 / dg[b] : 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) y[i] = i == b ? 1.0 / dg[b] : 0.0;
             }
-            for (int a = b; a < s; ++a) {  // the lower triangle, mirrored: M is exactly symmetric
+#pragma unroll
+            for (int a = 0; a < N; ++a) {  // the lower triangle, mirrored: M is exactly symmetric
+                if (a < b || a >= s) continue;
                 const int32_t pa = m_ptr[mem[a]] + b, pb = m_ptr[mem[b]] + a;
                 m64[pa] = m64[pb] = y[a];
                 m32[pa] = m32[pb] = static_cast<float>(y[a]);
@@ -622,7 +679,7 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
             hipLaunchKernelGGL(k_dual_cluster_hook, dim3(grid_for(F)), dim3(BLOCK), 0, s, F, D.t1.p, D.t2.p, D.W.p,
                                D.limited.p, cpar.p);
             hipLaunchKernelGGL(k_dual_cluster_size, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, cpar.p, root.p, size.p);
-            hipLaunchKernelGGL(k_dual_block_len, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, root.p, size.p, len.p,
+            hipLaunchKernelGGL(k_dual_block_len, dim3(grid_for(T, BLOCK, 1024)), dim3(BLOCK), 0, s, T, root.p, size.p, len.p,
                                slots.p, counts.p + 1);
             DBuf<int64_t> mp64, slot_off;
             mp64.alloc(ctx, T + 1);
@@ -643,8 +700,13 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
                                slot_off.p, fill.p, members.p);
             hipLaunchKernelGGL(k_dual_block_single, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, root.p, size.p,
                                d->diag_pos.p, d->val64.p, m_ptr.p, m_col.p, m64.p, m32.p);
-            hipLaunchKernelGGL(k_dual_block_inv, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, root.p, size.p, slot_off.p,
-                               members.p, d->row_ptr.p, d->col.p, d->val64.p, m_ptr.p, m_col.p, m64.p, m32.p);
+            // clusters of up to 8 tets (the Kuhn cube's 6) in registers, larger ones apart
+            hipLaunchKernelGGL(k_dual_block_inv<8>, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, 2, root.p, size.p,
+                               slot_off.p, members.p, d->row_ptr.p, d->col.p, d->val64.p, m_ptr.p, m_col.p, m64.p,
+                               m32.p);
+            hipLaunchKernelGGL(k_dual_block_inv<MAX_BLOCK>, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, 9, root.p,
+                               size.p, slot_off.p, members.p, d->row_ptr.p, d->col.p, d->val64.p, m_ptr.p, m_col.p,
+                               m64.p, m32.p);
             HIP_CHECK(hipGetLastError());
             build_sell_copy(ctx, T, mnnz, m_ptr.p, m_col.p, m64.p, m32.p, d->blockinv);
             ctx->sync();  // the temporaries above are released on return
