@@ -455,9 +455,12 @@ void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const
         launch_sell_nt<VT, MODE, false>(c, c->unroll[pi], A, x, y, b, part, st, ev_a, ev_b);
 }
 
+int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
+double* region(SolveCache* c, int r) { return c->partials.p + (int64_t)r * stride(c); }
+
 // Pick the sliced-ELL variant (2, 3 or 4 entry pairs in flight, non-temporal loads on/off) by
-// timing y = A x on this matrix.  All variants sum every row in the same
-// order, so the choice never changes a result.
+// timing the iteration's product (y = A x with the partials of x.y) on this matrix.  All
+// variants sum every row in the same order, so the choice never changes a result.
 template <class VT>
 void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const VT* x, VT* y) {
     const int pi = prec_index<VT>();
@@ -471,31 +474,35 @@ void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const 
         return;
     }
     const int cand[6][2] = {{4, 1}, {4, 0}, {3, 1}, {3, 0}, {2, 1}, {2, 0}};
-    float best = 1e30f;
-    int pick = 0;
-    for (int k = 0; k < 6; ++k) {
-        c->unroll[pi] = cand[k][0];
-        c->nt[pi] = cand[k][1];
-        launch_sell<VT, MODE_PLAIN>(c, A, x, y, nullptr, nullptr, nullptr);
-        HIP_CHECK(hipEventRecord(c->t0, c->stream));
-        for (int r = 0; r < 3; ++r) launch_sell<VT, MODE_PLAIN>(c, A, x, y, nullptr, nullptr, nullptr);
-        HIP_CHECK(hipEventRecord(c->t1, c->stream));
-        HIP_CHECK(hipEventSynchronize(c->t1));
-        float ms = 0.0f;
-        HIP_CHECK(hipEventElapsedTime(&ms, c->t0, c->t1));
-        if (ms < best) {
-            best = ms;
-            pick = k;
+    // four rounds over the variants, each timing three launches; a variant's
+    // figure is its best round, so that one slow round (clock or
+    // neighbouring-work noise) does not decide the pick
+    float best[6];
+    for (int k = 0; k < 6; ++k) best[k] = 1e30f;
+    for (int round = 0; round < 4; ++round) {
+        for (int k = 0; k < 6; ++k) {
+            c->unroll[pi] = cand[k][0];
+            c->nt[pi] = cand[k][1];
+            // the iteration's own mode (y = A x with the partials of x.y)
+            launch_sell<VT, MODE_DOT>(c, A, x, y, nullptr, region(c, R_PQ), nullptr);
+            HIP_CHECK(hipEventRecord(c->t0, c->stream));
+            for (int r = 0; r < 3; ++r) launch_sell<VT, MODE_DOT>(c, A, x, y, nullptr, region(c, R_PQ), nullptr);
+            HIP_CHECK(hipEventRecord(c->t1, c->stream));
+            HIP_CHECK(hipEventSynchronize(c->t1));
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, c->t0, c->t1));
+            if (ms < best[k]) best[k] = ms;
         }
     }
+    int pick = 0;
+    for (int k = 1; k < 6; ++k)
+        if (best[k] < best[pick]) pick = k;
     c->unroll[pi] = cand[pick][0];
     c->nt[pi] = cand[pick][1];
     c->tuned[pi] = true;
     c->ctx->spmv_tune[shape] = {c->unroll[pi], c->nt[pi]};
 }
 
-int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
-double* region(SolveCache* c, int r) { return c->partials.p + (int64_t)r * stride(c); }
 
 // n_rr: blocks of the kernel that left the r.r partials; r.z partials always come from a G-block kernel
 void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, PcgScalars* st, int n_rz = 0) {
