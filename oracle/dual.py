@@ -14,16 +14,19 @@ with * the diagonal Hodge star of the triangles, *_f = |f*| / |f| (length of
 the Voronoi edge through f over the triangle's area).  Dirichlet faces (eq. 12)
 keep the incomplete Voronoi edge from the tet's circumcentre to the face's
 circumcentre and move kappa-weighted T0 to the right-hand side; Neumann faces
-(eq. 13, zero flux here) and cracked faces (kappa = 0) have their rows and
-columns replaced by a unit diagonal, so their flux is zero.  Section 3.1 limits
+(eq. 13) prescribe their flux: the face's row fixes omega_f and the known
+flux moves to its tet's balance; insulated faces (zero flux) and cracked faces
+(kappa = 0) have their rows and columns replaced by a unit diagonal, so their
+flux is zero.  Section 3.1 limits
 Hodge entries at 1e-8 (zero-length Voronoi edges occur wherever tets share a
 circumcentre).
 
 Eliminating omega (the (1,1) block is diagonal) leaves the Schur complement on
 the tets: L = d diag(kappa_f / *_f) d^T, i.e. every face f between tets t1, t2
-contributes W_f (T_t1 - T_t2) to both balances, with W_f = kappa_f / *_f, and a
-Dirichlet face W_f (T_t - T0).  `mixed_system` writes eq. 11-13 out literally
-(used to pin `dual_system`).
+contributes W_f (T_t1 - T_t2) to both balances, with W_f = kappa_f / *_f, a
+Dirichlet face W_f (T_t - T0), and a Neumann face its prescribed outward flux
+g_f = f0 |f| (moved to the right-hand side).  `mixed_system` writes eq. 11-13
+out literally (used to pin `dual_system`).
 
 Readings (where the paper is silent): faces are numbered by their owner tet
 (the lowest-numbered tet holding them), then by the local index of the
@@ -31,7 +34,10 @@ opposite vertex; a signed Voronoi-edge length (positive along the normal from
 t1 to t2) and the limiter *_f := max(*_f, 1e-8) (negative entries included); a
 boundary face is Dirichlet when all three vertices carry Dirichlet data, with
 T0 the mean of the three vertex values, and its side (inflow / outflow) is the
-vertices' common side.
+vertices' common side; a boundary face is Neumann when all three vertices
+carry Neumann data (type 2), the vertices' values being outward flux
+densities, with f0 their mean; tets in parts joined to no Dirichlet face are
+pinned to 0 and their Neumann data ignored.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -109,15 +115,19 @@ def face_cut(xyz, tets, faces, geo, cracks):
 
 
 def face_bc(faces, bc_type, bc_value, side):
-    """Per boundary face: Dirichlet flag, T0 (mean of the vertex values), side (1/2/0)."""
+    """Per boundary face: Dirichlet flag, T0 (mean of the vertex values), side (1/2/0),
+    Neumann flag and f0 (mean of the vertices' outward flux densities)."""
     t2, verts = faces[2], faces[4]
     bt = np.asarray(bc_type)[verts]
     bv = np.asarray(bc_value, dtype=np.float64)[verts]
     sd = np.asarray(side)[verts] if side is not None else np.zeros_like(bt)
     dirichlet = (t2 < 0) & (bt == 1).all(axis=1)
-    T0 = np.where(dirichlet, ((bv[:, 0] + bv[:, 1]) + bv[:, 2]) / 3.0, 0.0)
+    mean = ((bv[:, 0] + bv[:, 1]) + bv[:, 2]) / 3.0
+    T0 = np.where(dirichlet, mean, 0.0)
     fside = np.where(dirichlet & (sd == 1).all(axis=1), 1, np.where(dirichlet & (sd == 2).all(axis=1), 2, 0))
-    return dirichlet, T0, fside
+    neumann = (t2 < 0) & (bt == 2).all(axis=1)
+    f0 = np.where(neumann, mean, 0.0)
+    return dirichlet, T0, fside, neumann, f0
 
 
 def dual_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=None, limiter=LIMITER):
@@ -130,7 +140,8 @@ def dual_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=None
     geo = face_geometry(xyz, tets, faces, limiter)
     kap = np.ones(len(t1)) if kappa is None else np.asarray(kappa, dtype=np.float64)
     kap = np.where(face_cut(xyz, tets, faces, geo, cracks), 0.0, kap)
-    dirichlet, T0, fside = face_bc(faces, bc_type, bc_value, side)
+    dirichlet, T0, fside, neumann, f0 = face_bc(faces, bc_type, bc_value, side)
+    g = f0 * geo["area"]  # prescribed outward flux of the Neumann faces
     inner = t2 >= 0
     W = np.where(inner | dirichlet, kap * geo["gw"], 0.0)
     # pinning over the faces that conduct
@@ -142,6 +153,7 @@ def dual_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=None
     vals = np.concatenate([-W[inner], -W[inner], W[inner], W[inner], W[dirichlet]])
     L = sp.csr_matrix((vals, (rows, cols)), shape=(T, T))
     b = np.bincount(t1[dirichlet], weights=W[dirichlet] * T0[dirichlet], minlength=T)
+    b = b - np.bincount(t1[neumann], weights=g[neumann], minlength=T)
     # pinned parts: unit rows, zero right-hand side (they touch no conducting face)
     L = L.tolil()
     for t in np.flatnonzero(pinned):
@@ -149,14 +161,16 @@ def dual_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=None
     L = L.tocsr()
     b[pinned] = 0.0
     return {"L": L, "b": b, "W": W, "pinned": pinned, "faces": faces, "geo": geo, "dirichlet": dirichlet,
-            "T0": T0, "side": fside, "kappa": kap}
+            "T0": T0, "side": fside, "kappa": kap, "neumann": neumann, "g": g}
 
 
 def mixed_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=None, limiter=LIMITER):
     """Eq. 11-13 written out: unknowns [omega (faces); alpha (tets)], the (1,1) block
     (1/kappa_f) *_f, d the tet-face incidence (+1 for the owner t1, -1 for t2), Dirichlet
-    faces moving T0 to the right-hand side, Neumann and cracked faces replaced by unit
-    rows and columns (zero flux).  Pinned tets (as in dual_system) get unit rows."""
+    faces moving T0 to the right-hand side, Neumann faces fixing omega_f = -g_f (omega
+    is the flux into t1) in their own row and keeping their entry in t1's balance,
+    insulated and cracked faces replaced by unit rows and columns (zero flux).  Pinned
+    tets (as in dual_system) get unit rows, and their Neumann faces count as insulated."""
     s = dual_system(xyz, tets, bc_type, bc_value, side, kappa, cracks, limiter)
     t1, _, t2, _, _ = s["faces"]
     F, T = len(t1), len(tets)
@@ -166,6 +180,12 @@ def mixed_system(xyz, tets, bc_type, bc_value, side=None, kappa=None, cracks=Non
     rows, cols, vals = [], [], []
     rhs = np.zeros(F + T)
     for f in range(F):
+        if s["neumann"][f] and not s["pinned"][t1[f]]:
+            rows += [f, F + t1[f]]
+            cols += [f, f]
+            vals += [1.0, 1.0]
+            rhs[f] = -s["g"][f]
+            continue
         if not live[f]:
             rows.append(f), cols.append(f), vals.append(1.0)
             continue

@@ -85,7 +85,7 @@ def test_sampled_weights_and_cuts(tets128):
     geo = D.face_geometry(xyz, sub, faces)
     ocut = D.face_cut(xyz, sub, faces, geo, tets128["cracks"])
     assert np.array_equal(cut[sample].astype(bool), ocut) and ocut.sum() >= 100
-    dirichlet, _, _ = D.face_bc(faces, tets128["bt"], tets128["bv"], tets128["side"])
+    dirichlet = D.face_bc(faces, tets128["bt"], tets128["bv"], tets128["side"])[0]
     kap = np.where(ocut, 0.0, tets128["kappa"][sample])
     wo = np.where((r2 >= 0) | dirichlet, kap * geo["gw"], 0.0)
     assert np.array_equal(w[sample] == 0.0, wo == 0.0)

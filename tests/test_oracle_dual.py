@@ -15,6 +15,27 @@ def _kuhn(n):
     return xyz, tets, bt, bv, side
 
 
+def _with_neumann(xyz, bt, bv, seed):
+    """Neumann data (type 2, outward flux densities) on the vertices of the face y = 0 that carry
+    no Dirichlet data."""
+    bt, bv = bt.copy(), bv.copy()
+    on = (np.abs(xyz[:, 1]) < 1e-12) & (bt != 1)
+    bt[on] = 2
+    bv[on] = np.random.Generator(np.random.PCG64(seed)).normal(0.0, 1.0, on.sum())
+    return bt, bv
+
+
+def _neumann_inflow(n):
+    """T = 0 on x = 1 (Dirichlet), outward flux density -1 on x = 0 (an inflow of 1 through the
+    unit face), insulated elsewhere: the continuous solution is 1 - x."""
+    xyz, tets = W.kuhn_cube(n)
+    i = W.lattice_index(n)[0]
+    bt = np.where(i == n, 1, np.where(i == 0, 2, 0)).astype(np.int8)
+    bv = np.where(i == 0, -1.0, 0.0)
+    side = np.where(i == n, 2, 0).astype(np.int8)
+    return xyz, tets, bt, bv, side
+
+
 def test_faces_by_owner():
     for n in (1, 2, 3):
         xyz, tets, *_ = _kuhn(n)
@@ -54,15 +75,18 @@ def test_schur_complement_of_the_mixed_system():
     cr = W.penny_cracks(6, 2, 0.1, 0.3)
     F = W.kuhn_counts(n)["F"]
     kap = np.random.Generator(np.random.PCG64(1)).lognormal(0.0, 1.0, F)
+    bt, bv = _with_neumann(xj, bt, bv, 4)
     K, rhs, s = D.mixed_system(xj, tets, bt, bv, side, kappa=kap, cracks=cr)
-    assert (s["kappa"] == 0).any() and (s["geo"]["h"] < 0).any()
+    assert (s["kappa"] == 0).any() and (s["geo"]["h"] < 0).any() and s["neumann"].sum() == 2 * (n - 2) * n
     K = K.tocsr()
-    A, B, C = K[:F, :F], K[:F, F:], K[F:, F:]
+    # a Neumann face's row fixes its flux and has no tet column, so the tets' rows are
+    # taken as they stand (B2) rather than as the transpose of the faces' columns
+    A, B, B2, C = K[:F, :F], K[:F, F:], K[F:, :F], K[F:, F:]
     Ainv = sp.diags(1.0 / A.diagonal())
-    S = (C - B.T @ Ainv @ B).toarray()
+    S = (C - B2 @ Ainv @ B).toarray()
     L = s["L"].toarray()
     assert np.abs(S + L).max() <= 1e-14 * np.abs(L).max()
-    assert np.abs(rhs[F:] - B.T @ (Ainv @ rhs[:F]) + s["b"]).max() <= 1e-14 * np.abs(s["b"]).max()
+    assert np.abs(rhs[F:] - B2 @ (Ainv @ rhs[:F]) + s["b"]).max() <= 1e-14 * np.abs(s["b"]).max()
     assert np.allclose(L, L.T, rtol=0, atol=1e-15 * np.abs(L).max())
 
 
@@ -81,6 +105,33 @@ def test_limiter_sets_the_error_of_the_linear_solution():
         assert 0.05 * lim < err < 0.5 * lim
         assert abs(D.flux(T, s)["k_eff"] - 1.0) < 3.0 * lim
     assert 80 < errs[0] / errs[1] < 120 and 80 < errs[1] / errs[2] < 120
+
+
+def test_neumann_inflow_is_conserved_and_gives_the_linear_field():
+    """A prescribed inflow (outward flux density -1 on x = 0) with T = 0 on x = 1: summing the
+    tet balances, the interior faces cancel, so the Dirichlet outflow equals the inflow, 1, on
+    any mesh and conductivity (jittered, lognormal, cracked), up to the direct solve's
+    residual (the limited weights, ~kappa / 1e-8, leave it near 1e-8 of the inflow); on the
+    homogeneous cube the solution is the linear field 1 - x up to the limiter's error."""
+    n = 4
+    xyz, tets, bt, bv, side = _neumann_inflow(n)
+    s = D.dual_system(xyz, tets, bt, bv, side)
+    assert s["neumann"].sum() == 2 * n * n and abs(s["g"][s["neumann"]].sum() + 1.0) < 1e-14
+    T = D.solve(s)
+    assert np.abs(T - (1.0 - s["geo"]["ct"][:, 0])).max() < 1e-6
+    assert abs(D.flux(T, s)["q_out"] - 1.0) < 1e-6
+    xj = W.jitter_interior(xyz, n, 0.2, 8)
+    kap = np.random.Generator(np.random.PCG64(2)).lognormal(0.0, 1.0, W.kuhn_counts(n)["F"])
+    s2 = D.dual_system(xj, tets, bt, bv, side, kappa=kap, cracks=W.penny_cracks(3, 5, 0.05, 0.15))
+    assert not s2["pinned"].any()
+    T2 = D.solve(s2)
+    assert abs(D.flux(T2, s2)["q_out"] - 1.0) < 1e-6
+    # the literal saddle system gives the same solution, up to what rounding leaves of two
+    # direct solves beside weights near kappa / 1e-8 (about 1e-7 here, as with Dirichlet data
+    # on both sides; the matrices themselves agree to 1e-14, test_schur_complement_...)
+    K, rhs, s3 = D.mixed_system(xj, tets, bt, bv, side, kappa=kap, cracks=W.penny_cracks(3, 5, 0.05, 0.15))
+    T3 = spla.spsolve(K.tocsc(), rhs)[len(s3["W"]):]
+    assert np.abs(T3 - T2).max() < 1e-5 * np.abs(T2).max()
 
 
 def test_energy_identity_and_cracks_lower_the_conductivity():
