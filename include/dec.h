@@ -319,7 +319,8 @@ int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int
  * eliminated and the Schur complement on the tets is assembled: a face f
  * between tets t1 and t2 couples them with W_f = kappa_f / *_f, a Dirichlet
  * face adds W_f to its tet's diagonal and W_f T0_f to its right-hand side,
- * insulated and cracked faces carry nothing.  *_f = max(h_f / |f|, limiter):
+ * a Neumann face subtracts its prescribed outward flux from it, insulated and
+ * cracked faces carry nothing.  *_f = max(h_f / |f|, limiter):
  * h_f the signed length of the Voronoi edge through f (t1's circumcentre to
  * t2's, or to the face's circumcentre on the boundary, positive along the
  * normal out of t1), |f| the face area; the limiter is Section 3.1's (1e-8
@@ -328,7 +329,10 @@ int dec_max_flux_edge(dec_mesh* m, const double* T, const uint8_t* eligible, int
  * Faces are numbered by owner tet (the lowest tet holding the face), then by
  * local index (the tet's vertex opposite the face).  A boundary face is
  * Dirichlet when its three vertices have bc_type 1, with T0 their mean
- * bc_value, and inflow/outflow when all three vertices carry side 1/2.
+ * bc_value, and inflow/outflow when all three vertices carry side 1/2; it is
+ * Neumann (eq. 13) when all three have bc_type 2, whose bc_value is then an
+ * outward flux density: the face's outward flux f0 |f|, f0 their mean, moves
+ * to its tet's right-hand side.  Other boundary faces are insulated.
  * A face is cracked when its Voronoi edge crosses a disc (cracks as in
  * dec_hodge1) or kappa_face is 0.
  *

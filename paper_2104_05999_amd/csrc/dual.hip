@@ -10,7 +10,10 @@
 //
 // Faces are numbered by owner tet (the lowest tet holding them), then by the
 // local index of the opposite vertex.  A boundary face is Dirichlet when its
-// three vertices carry Dirichlet data, with T0 their mean.  Tets in parts
+// three vertices carry Dirichlet data, with T0 their mean, and Neumann (eq. 13:
+// its flux is given) when they carry Neumann data, the vertices' values being
+// outward flux densities: its outward flux f0 |f|, f0 their mean, moves to the
+// right-hand side.  Tets in parts
 // joined to no Dirichlet face over conducting faces are pinned to 0.  The
 // system is returned as a mesh whose rows are the tets, so the solver applies
 // to it; its solver copy is built for the difference-form product (the
@@ -119,7 +122,9 @@ __global__ void k_dual_circ(int64_t T, const int4* __restrict__ tets, const doub
 }
 
 // Per face: the limited Hodge entry, the cut flag (Voronoi edge against the
-// discs), boundary kind, Dirichlet value, side and the weight W_f.
+// discs), boundary kind (0 interior, 1 Dirichlet, 2 insulated, 3 Neumann), the
+// Dirichlet value (T0) or the prescribed outward flux of a Neumann face (in
+// T0 as well), side and the weight W_f (0 on insulated and Neumann faces).
 __global__ void k_dual_faces(int64_t F, const int4* __restrict__ tets, const double* __restrict__ xyz,
                              const double* __restrict__ ct, const int32_t* __restrict__ t1,
                              const int32_t* __restrict__ k1, const int32_t* __restrict__ t2, double limiter,
@@ -176,10 +181,13 @@ __global__ void k_dual_faces(int64_t F, const int4* __restrict__ tets, const dou
                     const int8_t sa = side[va];
                     if ((sa == 1 || sa == 2) && side[vb] == sa && side[vc] == sa) sd = sa;
                 }
+            } else if (bc_type[va] == 2 && bc_type[vb] == 2 && bc_type[vc] == 2) {
+                kd = 3;
+                t0 = (((bc_value[va] + bc_value[vb]) + bc_value[vc]) / 3.0) * area;
             }
         }
         const double kap = hit ? 0.0 : (kappa ? kappa[f] : 1.0);
-        W[f] = kd == 2 ? 0.0 : kap * (1.0 / star);
+        W[f] = kd >= 2 ? 0.0 : kap * (1.0 / star);
         T0[f] = t0;
         kind[f] = kd;
         fside[f] = sd;
@@ -228,7 +236,8 @@ __global__ void k_dual_pin(int64_t T, int32_t* parent, const uint32_t* __restric
 
 // Row t: the diagonal and the tets across its interior faces, ascending;
 // off-diagonal -W_f, diagonal the sum of W over its conducting faces in local
-// face order, right-hand side the Dirichlet faces' W_f T0_f; pinned rows
+// face order, right-hand side the Dirichlet faces' W_f T0_f less the Neumann
+// faces' outward flux (in local face order); pinned rows
 // become unit rows with a zero right-hand side.  The row excess (diagonal
 // minus the off-diagonal weights) is the sum of the Dirichlet faces' W_f, 1 on
 // pinned rows: the solver's product takes the difference form with it, so
@@ -249,11 +258,12 @@ __global__ void k_dual_rows(int64_t T, const int32_t* __restrict__ nbr, const in
         double diag = 0.0, b = 0.0, ex = 0.0;
         for (int k = 0; k < 4; ++k) {
             const int f = tet_face[4 * t + k];
-            if (kind[f] != 2) diag += W[f];
+            if (kind[f] <= 1) diag += W[f];
             if (kind[f] == 1) {
                 b += W[f] * T0[f];
                 ex += W[f];
             }
+            if (kind[f] == 3) b -= T0[f];
             const int o = nbr[4 * t + k];
             if (o >= 0) {
                 cc[n] = o;
@@ -511,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_dual_flux(int64_t F, const int32_t* _
     double en = 0.0, qi = 0.0, qo = 0.0;
     RANGE_LOOP(f, F) {
         const int8_t kd = kind[f];
-        if (kd == 2) continue;
+        if (kd >= 2) continue;  // insulated and Neumann faces (W = 0)
         const double w = W[f], ta = T[t1[f]];
         const double d = kd == 0 ? ta - T[t2[f]] : ta - T0[f];
         en += w * d * d;

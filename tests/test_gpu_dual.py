@@ -56,7 +56,7 @@ def _t(a, dev):
     return torch.as_tensor(np.ascontiguousarray(a), device=dev)
 
 
-def _case(n=None, delaunay=None, lattice=None, jitter=0.0, n_cracks=0, sigma=0.0, seed=1, rmax=0.3):
+def _case(n=None, delaunay=None, lattice=None, jitter=0.0, n_cracks=0, sigma=0.0, seed=1, rmax=0.3, neumann=None):
     if lattice is not None:
         xyz, tets = W.delaunay_lattice(lattice, 0.2, seed)
         bt, bv, side = W.x_faces(xyz)
@@ -68,6 +68,15 @@ def _case(n=None, delaunay=None, lattice=None, jitter=0.0, n_cracks=0, sigma=0.0
         if jitter:
             xyz = W.jitter_interior(xyz, n, jitter, seed)
         bt, bv, side = W.x_sides(n)
+    if neumann == "y0":  # seeded outward flux densities on the face y = 0 (off the Dirichlet faces)
+        bt, bv = bt.copy(), bv.copy()
+        on = (np.abs(xyz[:, 1]) < 1e-12) & (bt != 1)
+        bt[on] = 2
+        bv[on] = np.random.Generator(np.random.PCG64(seed + 50)).normal(0.0, 1.0, int(on.sum()))
+    elif neumann == "inflow":  # an inflow of 1 through x = 0 (outward density -1), T = 0 on x = 1
+        bt, bv, side = bt.copy(), bv.copy(), side.copy()
+        on = np.abs(xyz[:, 0]) < 1e-12
+        bt[on], bv[on], side[on] = 2, -1.0, 0
     F = len(D.faces_by_owner(tets)[0]) if n is None else W.kuhn_counts(n)["F"]
     kap = np.random.Generator(np.random.PCG64(seed + 100)).lognormal(0.0, sigma, F) if sigma else None
     cr = W.penny_cracks(n_cracks, seed + 7, 0.1, rmax) if n_cracks else None
@@ -104,6 +113,8 @@ OP_CASES = {
     "jit11_cracks": dict(n=11, jitter=0.15, n_cracks=10, sigma=0.5, seed=3),
     "delaunay_cracks": dict(delaunay=(600, 60), n_cracks=5, sigma=1.0, seed=4),
     "lattice8": dict(lattice=8, seed=2),
+    "jit6_neumann": dict(n=6, jitter=0.2, n_cracks=4, sigma=1.0, seed=2, neumann="y0"),
+    "delaunay_inflow": dict(delaunay=(600, 60), sigma=0.5, seed=4, neumann="inflow"),
 }
 
 SOLVE_CASES = {
@@ -113,6 +124,8 @@ SOLVE_CASES = {
     "delaunay_small": dict(delaunay=(200, 30), seed=1),
     "delaunay_cracks": dict(delaunay=(2000, 150), n_cracks=8, sigma=0.5, seed=6),
     "lattice12_cracks": dict(lattice=12, n_cracks=6, sigma=1.0, seed=7),
+    "kuhn9_neumann": dict(n=9, n_cracks=6, sigma=1.0, seed=5, neumann="y0"),
+    "kuhn8_inflow": dict(n=8, n_cracks=4, sigma=1.0, seed=6, neumann="inflow"),
 }
 
 # (case, preconditioner): 0 Jacobi, 1 FSAI, 2 block Jacobi over limited clusters.  On Kuhn
@@ -122,7 +135,8 @@ SOLVE_CASES = {
 # the block preconditioner is the one that meets the bar there.
 SOLVE_RUNS = [("kuhn3", 2), ("kuhn3", 0), ("kuhn9_cracks", 2), ("kuhn16_cracks", 2),
               ("delaunay_small", 2), ("delaunay_small", 0), ("delaunay_small", 1),
-              ("delaunay_cracks", 2), ("delaunay_cracks", 1), ("lattice12_cracks", 2)]
+              ("delaunay_cracks", 2), ("delaunay_cracks", 1), ("lattice12_cracks", 2),
+              ("kuhn9_neumann", 2), ("kuhn8_inflow", 2)]
 
 
 def _clusters(s):
@@ -216,6 +230,34 @@ def test_solution_against_the_saddle_system(ctx, dev, name, precond):
         assert abs(f["q_in"] - fh["q_in"]) <= 1e-12 * fh["energy"]
     finally:
         d.close()
+
+
+def test_neumann_inflow_leaves_the_same_outflow(ctx, dev):
+    """An inflow of 1 through x = 0 (Neumann data, outward flux density -1) with T = 0 on
+    x = 1: the tet balances sum to outflow = inflow for the exact discrete solution, so the
+    solve's outflow is 1 within the bound its A-norm error implies (Cauchy-Schwarz), on a
+    cracked lognormal Kuhn cube and a Delaunay mesh."""
+    tol = 1e-10
+    for case in (_case(n=8, n_cracks=4, sigma=1.0, seed=6, neumann="inflow"),
+                 _case(delaunay=(600, 60), sigma=0.5, seed=4, neumann="inflow")):
+        xyz, tets, bt, bv, side, kap, cr = case
+        s = D.dual_system(xyz, tets, bt, bv, side, kappa=kap, cracks=cr)
+        assert s["neumann"].any() and abs(s["g"][s["neumann"]].sum() + 1.0) < 1e-12
+        assert not s["pinned"].any()
+        d = _build(ctx, dev, case)
+        try:
+            T, st, rc = d.solve(tol=tol, check=False)
+            assert rc == 0, st
+            Th = T.cpu().numpy()
+            f = d.flux(T)
+            # |Q_out(T) - Q_out(T*)| <= sqrt(sum of the outflow faces' W) ||T - T*||_A, and the
+            # A-norm test bounds ||T - T*||_A by 10 tol ||T*||_A (T* ~ T)
+            w_side = s["W"][s["dirichlet"] & (s["side"] == 2)].sum()
+            bound = 1.01 * np.sqrt(w_side) * 10.0 * tol * np.sqrt(_energy(Th, s)) + 1e-12
+            assert abs(f["q_out"] - 1.0) <= bound, (f, bound)
+            assert f["q_in"] == 0.0
+        finally:
+            d.close()
 
 
 def test_block_preconditioner_removes_the_limited_stiffness(ctx, dev):
