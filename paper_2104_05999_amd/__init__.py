@@ -297,7 +297,10 @@ class Mesh:
 
     def dual(self, bc_type, bc_value, side=None, kappa_face=None, cracks=None, limiter=0.0):
         """The system of the paper's own unknowns (temperature per tet, flux per triangle) as a
-        DualMesh, assembled and with its boundary data applied; see dec_dual_build."""
+        DualMesh, assembled and with its boundary data applied; see dec_dual_build.  bc_type per
+        vertex: 1 Dirichlet (bc_value the temperature), 2 Neumann (bc_value the outward flux
+        density), 0 free; a boundary face takes the kind its three vertices share, else it is
+        insulated."""
         return DualMesh(self, bc_type, bc_value, side, kappa_face, cracks, limiter)
 
 
