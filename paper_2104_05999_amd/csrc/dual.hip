@@ -30,6 +30,7 @@
 #include "geom.h"
 #include "solver.h"
 #include "uf.h"
+#include "wave_atomic.h"
 
 void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, const int32_t* col, const double* v64,
                      const float* v32, SellMatrix& S);
@@ -327,7 +328,7 @@ __global__ void k_dual_cluster_size(int64_t T, int32_t* parent, int32_t* __restr
     GRID_STRIDE_LOOP(t, T) {
         const int32_t r = uf_find(parent, (int32_t)t);
         root[t] = r;
-        atomicAdd(size + r, 1);
+        (void)wave_claim(size, r);  // a cluster's tets are mostly neighbours
     }
 }
 
@@ -373,7 +374,7 @@ __global__ void k_dual_block_members(int64_t T, const int32_t* __restrict__ root
     GRID_STRIDE_LOOP(t, T) {
         const int32_t r = root[t];
         if (!is_block(size[r])) continue;
-        const int k = atomicAdd(fill + r, 1);
+        const int k = wave_claim(fill, r);
         members[slot_off[r] + k] = (int32_t)t;
     }
 }

@@ -11,6 +11,7 @@
 #include <climits>
 
 #include "common.h"
+#include "wave_atomic.h"
 
 namespace {
 
@@ -52,15 +53,17 @@ __global__ void k_tet_check(const int4* __restrict__ tets, int64_t T, int64_t V,
     }
 }
 
+// Vertex-to-tet counts and slots, one atomic per distinct vertex of a
+// wavefront (wave_claim): the 16 tets of a wavefront share most vertices.
 __global__ void k_vt_count(const int32_t* __restrict__ tets, int64_t n4, int32_t* __restrict__ cnt) {
-    GRID_STRIDE_LOOP(i, n4) atomicAdd(&cnt[tets[i]], 1);
+    GRID_STRIDE_LOOP(i, n4) (void)wave_claim(cnt, tets[i]);
 }
 
 __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const int64_t* __restrict__ vt_ptr,
                           int32_t* __restrict__ fill, int32_t* __restrict__ vt_list) {
     GRID_STRIDE_LOOP(i, n4) {
         const int v = tets[i];
-        const int pos = atomicAdd(&fill[v], 1);
+        const int pos = wave_claim(fill, v);
         vt_list[vt_ptr[v] + pos] = static_cast<int32_t>(i >> 2);
     }
 }
