@@ -134,6 +134,17 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
     }
 }
 
+// The update and closing kernels split the vector work as the single-system
+// solver does: the update moves r only (r -= alpha q, partials of r.z and
+// r.r), the closing kernel moves x together with p (x += alpha p, p = D^-1 r
+// + beta p), so p is read once per iteration.  The update's first item
+// stores its fold of p.q in the system's scalars, where the closing kernel
+// reads it instead of folding the partials again.  A thread loads its rows of
+// the chunk (eight of them) before folding the system's partials, so the
+// fold's latency overlaps with their transfer.
+constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
+static_assert(ROWS_PER_THREAD * BLOCK == CHUNK_ROWS, "a chunk is a whole number of rows per thread");
+
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                    const int32_t* __restrict__ n_items, int par) {
@@ -142,23 +153,36 @@ __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slo
     ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
-        const PcgScalars* st = S.st + par;
+        PcgScalars* st = S.st + par;
         if (st->done) continue;
-        const double pq = reduce_bcast(S.part + Q_PQ * S.nchunks, S.nchunks, lds);
-        if (!(pq > 0.0) || !isfinite(pq)) continue;
-        const VT a = static_cast<VT>(st->rho / pq);
-        VT *x = SlotVec<VT>::x(S), *r = SlotVec<VT>::r(S);
-        const VT *p = SlotVec<VT>::p(S), *q = SlotVec<VT>::q(S), *invd = SlotVec<VT>::invd(S);
+        VT* r = SlotVec<VT>::r(S);
+        const VT *q = SlotVec<VT>::q(S), *invd = SlotVec<VT>::invd(S);
         int64_t r0, r1;
         chunk_rows(S, item.chunk, &r0, &r1);
+        VT fr[ROWS_PER_THREAD], fq[ROWS_PER_THREAD], fd[ROWS_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t i = r0 + threadIdx.x + k * BLOCK;
+            if (i < r1) {
+                fr[k] = r[i];
+                fq[k] = q[i];
+                fd[k] = invd[i];
+            }
+        }
+        const double pq = reduce_bcast(S.part + Q_PQ * S.nchunks, S.nchunks, lds);
+        if (item.chunk == 0 && threadIdx.x == 0) st->pq_now = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) continue;
+        const VT a = static_cast<VT>(st->rho / pq);
         VT rz = 0, rr = 0;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
-            const VT xi = x[i] + a * p[i];
-            const VT ri = r[i] - a * q[i];
-            x[i] = xi;
-            r[i] = ri;
-            rz += ri * (invd[i] * ri);
-            rr += ri * ri;
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t i = r0 + threadIdx.x + k * BLOCK;
+            if (i < r1) {
+                const VT ri = fr[k] - a * fq[k];
+                r[i] = ri;
+                rz += ri * (fd[k] * ri);
+                rr += ri * ri;
+            }
         }
         const double b1 = block_sum(static_cast<double>(rz), lds);
         const double b2 = block_sum(static_cast<double>(rr), lds);
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slo
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                   const int32_t* __restrict__ n_items, int par) {
-    __shared__ double lds[3 * (BLOCK / 64 + 1)];
+    __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const int n = *n_items;
     ITEM_LOOP(it, n) {
         const BItem item = items[it];
@@ -184,24 +208,45 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
             if (lead) *N = *Sp;
             continue;
         }
+        VT *x = SlotVec<VT>::x(S), *p = SlotVec<VT>::p(S);
+        const VT *r = SlotVec<VT>::r(S), *invd = SlotVec<VT>::invd(S);
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        VT fz[ROWS_PER_THREAD], fp[ROWS_PER_THREAD], fx[ROWS_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t i = r0 + threadIdx.x + k * BLOCK;
+            if (i < r1) {
+                fz[k] = invd[i] * r[i];
+                fp[k] = p[i];
+                fx[k] = x[i];
+            }
+        }
         const int nc = S.nchunks;
-        double pq, rr, rz;
-        reduce_bcast3(S.part + Q_PQ * nc, nc, S.part + Q_RR * nc, nc, S.part + Q_RZ * nc, nc, lds, &pq, &rr, &rz);
+        const double pq = Sp->pq_now;
+        double rr, rz;
+        reduce_bcast2(S.part + Q_RR * nc, nc, S.part + Q_RZ * nc, nc, lds, &rr, &rz);
+        const bool pq_ok = pq > 0.0 && isfinite(pq);
         int done = PCG_RUNNING;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr) || !isfinite(rz))
+        if (!pq_ok || !isfinite(rr) || !isfinite(rz))
             done = PCG_BREAKDOWN;
         else if (rr <= Sp->rr_stop)
             done = PCG_CONVERGED;
         else if (Sp->iter + 1 >= Sp->max_iter)
             done = PCG_MAXITER;
         const double beta = rz / Sp->rho;
-        if (done == PCG_RUNNING) {
+        if (pq_ok) {
+            const VT a = static_cast<VT>(Sp->rho / pq);
             const VT bt = static_cast<VT>(beta);
-            const VT *r = SlotVec<VT>::r(S), *invd = SlotVec<VT>::invd(S);
-            VT* p = SlotVec<VT>::p(S);
-            int64_t r0, r1;
-            chunk_rows(S, item.chunk, &r0, &r1);
-            for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) p[i] = invd[i] * r[i] + bt * p[i];
+            const bool run = done == PCG_RUNNING;
+#pragma unroll
+            for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+                const int64_t i = r0 + threadIdx.x + k * BLOCK;
+                if (i < r1) {
+                    x[i] = fx[k] + a * fp[k];
+                    if (run) p[i] = fz[k] + bt * fp[k];
+                }
+            }
         }
         if (lead) {
             N->rho = rz;
