@@ -108,6 +108,7 @@ def _energy(e, s):
 
 
 OP_CASES = {
+    "kuhn1": dict(n=1),  # one cube: six tets, one limited cluster holding every unknown
     "kuhn3": dict(n=3),
     "jit6_cracks": dict(n=6, jitter=0.2, n_cracks=4, sigma=1.0, seed=2),
     "jit11_cracks": dict(n=11, jitter=0.15, n_cracks=10, sigma=0.5, seed=3),
@@ -118,6 +119,7 @@ OP_CASES = {
 }
 
 SOLVE_CASES = {
+    "kuhn1": dict(n=1),
     "kuhn3": dict(n=3),
     "kuhn9_cracks": dict(n=9, n_cracks=6, sigma=1.0, seed=5),
     "kuhn16_cracks": dict(n=16, n_cracks=20, sigma=1.0, seed=3),
@@ -133,7 +135,7 @@ SOLVE_CASES = {
 # then stalls for thousands of steps (and a windowed error estimate cannot see a stall; the
 # Delaunay meshes of a jittered lattice have such clusters too);
 # the block preconditioner is the one that meets the bar there.
-SOLVE_RUNS = [("kuhn3", 2), ("kuhn3", 0), ("kuhn9_cracks", 2), ("kuhn16_cracks", 2),
+SOLVE_RUNS = [("kuhn1", 2), ("kuhn3", 2), ("kuhn3", 0), ("kuhn9_cracks", 2), ("kuhn16_cracks", 2),
               ("delaunay_small", 2), ("delaunay_small", 0), ("delaunay_small", 1),
               ("delaunay_cracks", 2), ("delaunay_cracks", 1), ("lattice12_cracks", 2),
               ("kuhn9_neumann", 2), ("kuhn8_inflow", 2)]
