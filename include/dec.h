@@ -174,7 +174,10 @@ int dec_assemble(dec_mesh* m, uint32_t flags);
  * part of the face); connected parts of the graph of edges with *1 != 0
  * that hold no Dirichlet vertex are pinned to T = 0.  n_pinned_out (host,
  * NULL ok) receives their vertex count; b_out [V] float64 device (NULL ok)
- * the right-hand side.  Synchronises the stream. */
+ * the right-hand side.  A later call on the same assembly replaces the
+ * earlier boundary data (the operator is rebuilt from *1 first); after a
+ * failed call the mesh has no system until a call succeeds.
+ * Synchronises the stream. */
 int dec_apply_bc(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
                  const double* neumann_f0, int64_t* n_pinned_out, double* b_out);
 

@@ -192,14 +192,19 @@ void refresh_sell_values(dec_mesh* m) {
     HIP_CHECK(hipGetLastError());
 }
 
+// L = d0^T *1 d0 into the CSR values (FP64 and FP32) from the current *1.
+void assemble_values(dec_mesh* m) {
+    hipLaunchKernelGGL(k_assemble_values, dim3(grid_xcd(m->V, BLOCK / ROWG)), dim3(BLOCK), 0, m->ctx->stream, m->V,
+                       m->row_ptr.p, m->nz_edge.p, m->diag_pos.p, m->star1.p, m->val64.p, m->val32.p);
+    HIP_CHECK(hipGetLastError());
+}
+
 void assemble_device(dec_mesh* m) {
     dec_ctx* ctx = m->ctx;
     DEC_REQUIRE(m->star_ready, DEC_ESTATE, "dec_assemble needs dec_hodge1 first");
     m->val64.alloc(ctx, m->nnz);
     m->val32.alloc(ctx, m->nnz);
-    hipLaunchKernelGGL(k_assemble_values, dim3(grid_xcd(m->V, BLOCK / ROWG)), dim3(BLOCK), 0, ctx->stream, m->V, m->row_ptr.p,
-                       m->nz_edge.p, m->diag_pos.p, m->star1.p, m->val64.p, m->val32.p);
-    HIP_CHECK(hipGetLastError());
+    assemble_values(m);
     build_sell_pattern(m);
     refresh_sell_values(m);
     m->assembled = true;

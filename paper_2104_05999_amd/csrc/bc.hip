@@ -15,6 +15,7 @@
 #include "uf.h"
 
 void refresh_sell_values(dec_mesh* m);
+void assemble_values(dec_mesh* m);
 
 namespace {
 
@@ -202,6 +203,10 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     hipStream_t s = ctx->stream;
     const int64_t V = m->V;
     DEC_REQUIRE(m->assembled, DEC_ESTATE, "dec_apply_bc needs dec_assemble first");
+    // boundary data applied before to this assembly overwrote the rows and columns it
+    // fixed: start again from L (and until this call completes, there is no system to solve)
+    if (m->bc_ready) assemble_values(m);
+    m->bc_ready = false;
     DBuf<unsigned> flags;
     flags.alloc(ctx, 16);
     flags.zero();

@@ -258,6 +258,34 @@ def test_isolated_vertices_pinned(ctx, dev):
     assert np.all(T.cpu().numpy()[pinned] == 0.0)
 
 
+def test_boundary_data_applied_again_to_one_assembly(ctx, dev):
+    """dec_apply_bc twice on one assembly: the second system is the oracle's for the second data
+    (the first call's elimination is undone), and applying the first data again gives the first
+    solution bit for bit."""
+    n = 8
+    s = _system(n, n_cracks=10)
+    i, j, k = W.lattice_index(n)
+    bt2 = ((j == 0) | (j == n)).astype(np.int8)
+    bv2 = np.where(j == 0, 2.0, -1.0) * bt2 + 0.1 * k / n * bt2
+    A2, b2, _ = O.apply_bc(s["L"], bt2, bv2, s["E"], s["star"])
+    ref2 = O.pcg(A2, b2, precond="jacobi", tol=1e-14, stagnation=50)
+    m, _, _, _, b1 = _gpu(ctx, s, dev)
+    try:
+        T1, _, rc1 = m.solve(tol=1e-12)
+        T1 = T1.clone()
+        _, b = m.apply_bc(_t(bt2, dev), _t(bv2, dev))
+        assert np.abs(b.cpu().numpy() - b2).max() <= 1e-13 * np.abs(b2).max()
+        T2, st, rc2 = m.solve(tol=1e-12)
+        assert rc1 == 0 and rc2 == 0, st
+        x = T2.cpu().numpy()
+        assert np.linalg.norm(x - ref2.x) <= 1e-10 * np.linalg.norm(ref2.x)
+        m.apply_bc(_t(s["bt"], dev), _t(s["bv"], dev))
+        T3, _, _ = m.solve(tol=1e-12)
+        assert torch.equal(T3, T1)
+    finally:
+        m.close()
+
+
 def test_neumann_load(ctx, dev):
     n = 5
     xyz, tets = W.kuhn_cube(n)
