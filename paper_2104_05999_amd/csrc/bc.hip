@@ -54,20 +54,61 @@ __device__ __forceinline__ int vget(const int4& q, int k) {
 }
 
 __global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const double* __restrict__ bc_value,
-                          int32_t* __restrict__ parent, double* __restrict__ dval, unsigned* __restrict__ err) {
+                          double* __restrict__ dval, unsigned* __restrict__ err) {
     GRID_STRIDE_LOOP(v, V) {
         const int8_t t = bc_type[v];
         if (t < 0 || t > 2) atomicOr(err, 1u);
-        parent[v] = (int32_t)v;
         dval[v] = (t == 1) ? bc_value[v] : 0.0;
     }
 }
 
-__global__ void k_uf_hook(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ star1,
-                          int32_t* parent) {
-    GRID_STRIDE_LOOP(e, E) {
-        if (star1[e] == 0.0) continue;
-        uf_union(parent, edges[2 * e], edges[2 * e + 1]);
+// Components of the graph of edges with *1 != 0, in two passes over the rows.
+// k_uf_tiles: each workgroup joins, in LDS, the edges between vertices of its
+// own tile of UF_TILE consecutive vertices, then stores as every vertex's
+// parent the root of its part of the tile (that part's smallest vertex).
+// k_uf_cross: the edges between tiles, each from its lower end, through the
+// global union-find.  The forest that results has the same components and
+// the same roots (each component's smallest vertex) as one global pass over
+// all edges, but only the edges whose ends lie in different tiles meet the
+// device-scope atomics: on a lattice numbered plane by plane, with planes
+// larger than a tile, the edges between planes and a few more.
+constexpr int UF_TILE = 2048;
+
+__global__ __launch_bounds__(BLOCK) void k_uf_tiles(int64_t V, const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ nz_edge,
+                                                    const double* __restrict__ star1, int32_t* __restrict__ parent) {
+    __shared__ int32_t lp[UF_TILE];
+    const int64_t v0 = (int64_t)blockIdx.x * UF_TILE;
+    const int n = (int)(V - v0 < UF_TILE ? V - v0 : UF_TILE);
+    for (int i = threadIdx.x; i < n; i += BLOCK) lp[i] = i;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BLOCK) {
+        const int64_t v = v0 + i;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t c = col[k];
+            if (c <= v || c >= v0 + n) continue;
+            const int32_t e = nz_edge[k];
+            if (e < 0 || star1[e] == 0.0) continue;
+            uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i, (int32_t)(c - v0));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BLOCK)
+        parent[v0 + i] = (int32_t)(v0 + uf_find<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i));
+}
+
+__global__ void k_uf_cross(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                           const int32_t* __restrict__ nz_edge, const double* __restrict__ star1, int32_t* parent) {
+    GRID_STRIDE_LOOP(v, V) {
+        const int64_t tile_end = (v / UF_TILE + 1) * UF_TILE;
+        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+            const int32_t c = col[k];
+            if (c < tile_end) continue;  // a lower neighbour, or one in v's own tile
+            const int32_t e = nz_edge[k];
+            if (e < 0 || star1[e] == 0.0) continue;
+            uf_union(parent, (int32_t)v, c);
+        }
     }
 }
 
@@ -213,14 +254,17 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     DBuf<int32_t> parent;
     parent.alloc(ctx, V);
     m->bc_value.alloc(ctx, V);
-    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, bc_value, parent.p,
-                       m->bc_value.p, flags.p);
+    hipLaunchKernelGGL(k_bc_init, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, bc_type, bc_value, m->bc_value.p,
+                       flags.p);
     HIP_CHECK(hipGetLastError());
     unsigned e0 = *static_cast<unsigned*>(ctx->readback(flags.p, sizeof(unsigned)));
     DEC_REQUIRE(e0 == 0, DEC_EINVAL, "bc_type must be 0, 1 or 2");
 
     // parts of the graph of edges with *1 != 0 holding no Dirichlet vertex are pinned
-    hipLaunchKernelGGL(k_uf_hook, dim3(grid_for(m->E)), dim3(BLOCK), 0, s, m->E, m->edges.p, m->star1.p, parent.p);
+    hipLaunchKernelGGL(k_uf_tiles, dim3((unsigned)((V + UF_TILE - 1) / UF_TILE)), dim3(BLOCK), 0, s, V, m->row_ptr.p,
+                       m->col.p, m->nz_edge.p, m->star1.p, parent.p);
+    hipLaunchKernelGGL(k_uf_cross, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
+                       m->star1.p, parent.p);
     DBuf<uint32_t> anchored;
     anchored.alloc(ctx, V);
     anchored.zero();
