@@ -72,18 +72,22 @@ __global__ void k_bc_init(int64_t V, const int8_t* __restrict__ bc_type, const d
 // all edges, but only the edges whose ends lie in different tiles meet the
 // device-scope atomics: on a lattice numbered plane by plane, with planes
 // larger than a tile, the edges between planes and a few more.
+// NT threads per tile: a mesh of few tiles takes 1024 (two rows per thread, as
+// the rows' dependent loads are the latency), one of many takes 256 (more
+// tiles resident per CU).
 constexpr int UF_TILE = 2048;
 
-__global__ __launch_bounds__(BLOCK) void k_uf_tiles(int64_t V, const int32_t* __restrict__ row_ptr,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_uf_tiles(int64_t V, const int32_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col,
                                                     const int32_t* __restrict__ nz_edge,
                                                     const double* __restrict__ star1, int32_t* __restrict__ parent) {
     __shared__ int32_t lp[UF_TILE];
     const int64_t v0 = (int64_t)blockIdx.x * UF_TILE;
     const int n = (int)(V - v0 < UF_TILE ? V - v0 : UF_TILE);
-    for (int i = threadIdx.x; i < n; i += BLOCK) lp[i] = i;
+    for (int i = threadIdx.x; i < n; i += NT) lp[i] = i;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += BLOCK) {
+    for (int i = threadIdx.x; i < n; i += NT) {
         const int64_t v = v0 + i;
         for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
             const int32_t c = col[k];
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(BLOCK) void k_uf_tiles(int64_t V, const int32_t* __
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += BLOCK)
+    for (int i = threadIdx.x; i < n; i += NT)
         parent[v0 + i] = (int32_t)(v0 + uf_find<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i));
 }
 
@@ -261,8 +265,13 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     DEC_REQUIRE(e0 == 0, DEC_EINVAL, "bc_type must be 0, 1 or 2");
 
     // parts of the graph of edges with *1 != 0 holding no Dirichlet vertex are pinned
-    hipLaunchKernelGGL(k_uf_tiles, dim3((unsigned)((V + UF_TILE - 1) / UF_TILE)), dim3(BLOCK), 0, s, V, m->row_ptr.p,
-                       m->col.p, m->nz_edge.p, m->star1.p, parent.p);
+    const unsigned tiles = (unsigned)((V + UF_TILE - 1) / UF_TILE);
+    if (tiles < 512)
+        hipLaunchKernelGGL(k_uf_tiles<1024>, dim3(tiles), dim3(1024), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
+                           m->star1.p, parent.p);
+    else
+        hipLaunchKernelGGL(k_uf_tiles<256>, dim3(tiles), dim3(256), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
+                           m->star1.p, parent.p);
     hipLaunchKernelGGL(k_uf_cross, dim3(grid_for(V)), dim3(BLOCK), 0, s, V, m->row_ptr.p, m->col.p, m->nz_edge.p,
                        m->star1.p, parent.p);
     DBuf<uint32_t> anchored;
