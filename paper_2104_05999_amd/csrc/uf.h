@@ -5,13 +5,15 @@
 
 // Connected components by lock-free union-find (used for the parts that
 // cracks cut off from every Dirichlet vertex or face): the larger of two
-// roots is hooked under the smaller with a compare-and-swap, so parent[v] <= v always holds, every find ends, and the
-// root of a component is its smallest vertex (a label independent of
-// scheduling).  A failed swap means another thread hooked that root; the
-// loop then continues from the new root.  Finds halve the path they walk:
-// a vertex that is not a root is re-pointed to its grandparent, which is an
-// ancestor in the same tree (a non-root never becomes a root again, and the
-// swaps only ever change roots), so the halving races with nothing.
+// roots is hooked under the smaller with a compare-and-swap, so
+// parent[v] <= v always holds, every find ends, and the root of a component
+// is its smallest vertex (a label independent of scheduling).  A failed swap
+// means another thread hooked that root; the loop then continues from the
+// new root.  Finds halve the path they walk: a vertex that is not a root is
+// re-pointed to its grandparent, which is an ancestor in the same tree (a
+// non-root never becomes a root again, and the swaps only ever change
+// roots), so the halving races with nothing.  The same code serves a parent
+// array in LDS (SCOPE = workgroup) and one in global memory (the device).
 template <int SCOPE = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t v) {
     while (true) {
