@@ -181,7 +181,7 @@ def serve_fp64_sequential(ctx, reqs, arrivals):
             "seconds": round(total, 3), "iterations": iters}, keff
 
 
-def serve_batched(ctx, reqs, arrivals, precision, budget=16 << 30, max_slots=64, chunk=16):
+def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96, chunk=24):
     """The server: requests submitted at their arrival time, stepped until all are done."""
     import torch
 
