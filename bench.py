@@ -222,7 +222,8 @@ def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96,
 
 def serving_benchmark(ctx, dev, count):
     """Saturated throughput (all requests queued at t = 0) and latency under Poisson arrivals at
-    0.8 x the FP64 baseline's saturated rate, plain FP64 one-at-a-time vs mixed batched."""
+    0.8 x the FP64 baseline's saturated rate, plain FP64 one-at-a-time vs mixed batched (and, saturated,
+    the same server in FP64)."""
     import paper_2104_05999_amd as dec
 
     trace, reqs = make_serve_inputs(count, dev)
@@ -232,6 +233,9 @@ def serving_benchmark(ctx, dev, count):
     print(f"[bench] serving fp64 saturated: {f64_sat}", file=sys.stderr, flush=True)
     mix_sat, kmix = serve_batched(ctx, reqs, zero, dec.DEC_PREC_MIXED)
     print(f"[bench] serving mixed saturated: {mix_sat}", file=sys.stderr, flush=True)
+    # the same server in FP64: separates what batching gives from what FP32 inner solves give
+    b64_sat, kb64 = serve_batched(ctx, reqs, zero, dec.DEC_PREC_FP64)
+    print(f"[bench] serving fp64 batched saturated: {b64_sat}", file=sys.stderr, flush=True)
     rate = 0.8 * f64_sat["solves_per_sec"]
     arrivals = [spec.arrival_s for spec in W.serving_trace(count, 3, rate)]
     f64_poi, _ = serve_fp64_sequential(ctx, reqs, arrivals)
@@ -244,8 +248,11 @@ def serving_benchmark(ctx, dev, count):
                     "0-400 penny cracks, lognormal kappa sigma 0.5, tol 1e-10",
         "fp64_sequential": {"saturated": f64_sat, "poisson": f64_poi},
         "mixed_batched": {"saturated": mix_sat, "poisson": mix_poi},
+        "fp64_batched": {"saturated": b64_sat},
         "poisson_rate_per_s": round(rate, 3),
         "speedup_saturated_solves_per_sec": round(mix_sat["solves_per_sec"] / f64_sat["solves_per_sec"], 3),
+        "speedup_mixed_vs_fp64_batched": round(mix_sat["solves_per_sec"] / b64_sat["solves_per_sec"], 3),
+        "max_rel_keff_diff_fp64_batched_vs_sequential": max(abs(a - b) / abs(b) for a, b in zip(kb64, k64)),
         "max_rel_keff_diff_mixed_vs_fp64": dk,
     }
 
