@@ -134,3 +134,28 @@ def test_cancel_pending_and_admitted(ctx, dev):
     assert out[0]["status"] == -9 and out[2]["status"] == -9 and out[1]["status"] == 0
     alone, _ = serve(ctx, [reqs[1]])
     assert alone[0]["k_eff"] == out[1]["k_eff"]
+
+
+def test_a_bad_request_fails_alone(ctx, dev):
+    """A request whose boundary data is invalid (a bc_type of 7) or whose mesh is not a valid
+    tetrahedralisation (a repeated vertex) ends with its own error status; the requests around it
+    are served as if it had not been there, bit for bit."""
+    built = [make_request(7, 5, 30 + k, dev) for k in range(4)]
+    reqs = [b[0] for b in built]
+    bad_bc = dict(reqs[1])
+    bt = bad_bc["bc_type"].clone()
+    bt[3] = 7
+    bad_bc["bc_type"] = bt
+    bad_mesh = dict(reqs[2])
+    tets = bad_mesh["tets"].clone()
+    tets[5, 1] = tets[5, 0]
+    bad_mesh["tets"] = tets
+    bad_bc["T_out"] = torch.zeros_like(reqs[1]["T_out"])
+    bad_mesh["T_out"] = torch.zeros_like(reqs[2]["T_out"])
+    out, _ = serve(ctx, [reqs[0], bad_bc, bad_mesh, reqs[3]], tol=1e-12)
+    assert out[1]["status"] == -1 and out[2]["status"] == -6
+    assert out[0]["status"] == 0 and out[3]["status"] == 0
+    T0, T3 = reqs[0]["T_out"].clone(), reqs[3]["T_out"].clone()
+    alone, _ = serve(ctx, [reqs[0], reqs[3]], tol=1e-12)
+    assert torch.equal(reqs[0]["T_out"], T0) and torch.equal(reqs[3]["T_out"], T3)
+    assert alone[0]["k_eff"] == out[0]["k_eff"] and alone[1]["k_eff"] == out[3]["k_eff"]
