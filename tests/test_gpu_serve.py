@@ -159,3 +159,32 @@ def test_a_bad_request_fails_alone(ctx, dev):
     alone, _ = serve(ctx, [reqs[0], reqs[3]], tol=1e-12)
     assert torch.equal(reqs[0]["T_out"], T0) and torch.equal(reqs[3]["T_out"], T3)
     assert alone[0]["k_eff"] == out[0]["k_eff"] and alone[1]["k_eff"] == out[3]["k_eff"]
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_served_neumann_request_matches_oracle(ctx, dev, precision):
+    """A request with Neumann data (outward flux densities on two faces of the cube, T = 0 on the
+    opposite x face) beside a plain one: the served solution is the oracle's solve of the system
+    with the Neumann load (eqs. 3-4), to 1e-10 of its norm."""
+    n = 9
+    xyz, tets = W.kuhn_cube(n)
+    V = len(xyz)
+    E = O.edges_of(tets, V)
+    i, j, _ = W.lattice_index(n)
+    bt = np.where(i == n, 1, np.where((i == 0) | (j == 0), 2, 0)).astype(np.int8)
+    f0 = np.where(i == 0, -2.5, np.where(j == 0, 0.7, 0.0))
+    kappa = W.lognormal_kappa(len(E), 0.5, 77)
+    cracks = W.penny_cracks(6, 78, 0.05, 0.2)
+    cut = O.crack_cut(xyz, E, cracks)
+    star = O.hodge1(xyz, tets, E, kappa=kappa, cut=cut)
+    g = O.neumann_load(xyz, tets, O.boundary_faces(tets), bt, f0)
+    A, b, _ = O.apply_bc(O.assemble(V, E, star)[0], bt, np.zeros(V), E, star, neumann=g)
+    ref = O.pcg(A, b, precond="jacobi", tol=1e-14, stagnation=50)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    req = dict(xyz=t(xyz), tets=t(tets), kappa=t(kappa), cracks=t(cracks), bc_type=t(bt), bc_value=t(np.zeros(V)),
+               neumann_f0=t(f0), T_out=torch.zeros(V, dtype=torch.float64, device=dev))
+    other, _ = make_request(6, 3, 40, dev)
+    out, _ = serve(ctx, [other, req], tol=1e-12, precision=precision)
+    assert out[1]["status"] == 0 and out[0]["status"] == 0
+    T = req["T_out"].cpu().numpy()
+    assert np.linalg.norm(T - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
