@@ -102,17 +102,37 @@ __global__ __launch_bounds__(NT) void k_uf_tiles(int64_t V, const int32_t* __res
         parent[v0 + i] = (int32_t)(v0 + uf_find<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i));
 }
 
-__global__ void k_uf_cross(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                           const int32_t* __restrict__ nz_edge, const double* __restrict__ star1, int32_t* parent) {
-    GRID_STRIDE_LOOP(v, V) {
-        const int64_t tile_end = (v / UF_TILE + 1) * UF_TILE;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t c = col[k];
-            if (c < tile_end) continue;  // a lower neighbour, or one in v's own tile
-            const int32_t e = nz_edge[k];
-            if (e < 0 || star1[e] == 0.0) continue;
-            uf_union(parent, (int32_t)v, c);
+// A wavefront takes 64 consecutive rows, one per lane.  A lane's first edge
+// between tiles joins the sets holding parent[v] and parent[c]; when the lane
+// before it names the same two values, the two edges join the same two sets
+// (values of parent[] are always ancestors within a set), so only the first
+// lane of such a run makes the device-scope union.  On a lattice that leaves
+// about one union per wavefront for the edges between planes.
+__global__ __launch_bounds__(BLOCK) void k_uf_cross(int64_t V, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
+                                                   const double* __restrict__ star1, int32_t* parent) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63); base < V; base += stride) {
+        const int64_t v = base + lane;
+        int32_t c1 = -1;
+        if (v < V) {
+            const int64_t tile_end = (v / UF_TILE + 1) * UF_TILE;
+            for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+                const int32_t c = col[k];
+                if (c < tile_end) continue;  // a lower neighbour, or one in v's own tile
+                const int32_t e = nz_edge[k];
+                if (e < 0 || star1[e] == 0.0) continue;
+                if (c1 < 0)
+                    c1 = c;
+                else
+                    uf_union(parent, (int32_t)v, c);
+            }
         }
+        const int32_t a = c1 >= 0 ? __hip_atomic_load(parent + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+        const int32_t b = c1 >= 0 ? __hip_atomic_load(parent + c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+        const int32_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+        if (c1 >= 0 && !(lane > 0 && pa == a && pb == b)) uf_union(parent, (int32_t)v, c1);
     }
 }
 
