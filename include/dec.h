@@ -258,19 +258,32 @@ typedef struct dec_solve_stats {
  *   DEC_BLOCKS_PER_CU, DEC_SPMV_BLOCKS_PER_CU  workgroups per CU of the
  *       vector kernels (default 4) and of the SpMV (default 8). */
 
-/* Fill opts with the defaults: FP64, Jacobi, tol 1e-10, inner_tol 1e-5,
- * adaptive final inner tolerance on, cold start, max_iters 100000, auto
- * format, chunk 32, graphs on, profiling off, plain residual norm. */
+/* Fill opts (host) with the defaults: FP64, Jacobi, tol 1e-10 (the relative
+ * tolerance of Section 3.1's solves), inner_tol 1e-5, adaptive final inner
+ * tolerance on, cold start, max_iters 100000, auto format, chunk 32, graphs
+ * on, profiling off, plain residual norm.  DEC_EINVAL when opts is NULL. */
 int dec_solve_opts_default(dec_solve_opts* opts);
-/* Solve A T = b (after dec_apply_bc).  T [V] float64 device: initial guess
- * when opts->warm_start, solution on return.  stats (host) may be NULL.
- * Returns DEC_OK, DEC_ENOTCONV or DEC_EBREAKDOWN (T then holds the last
- * iterate).  Synchronises the stream. */
+/* The iterative solve of the assembled system (Section 2.3: the paper solves
+ * its system with a preconditioned Krylov method, FGMRES with a
+ * sparse-approximate-inverse preconditioner; the vertex system here is
+ * symmetric positive definite, so the method is preconditioned conjugate
+ * gradients with Jacobi, FSAI or block-Jacobi preconditioning, in FP64 or as
+ * FP32 inner solves inside FP64 iterative refinement).  Solves A T = b after
+ * dec_apply_bc.  opts (host, read during the call).  T [V] float64 device,
+ * owned by the caller: initial guess when opts->warm_start, solution on
+ * return.  stats (host) may be NULL.  Returns DEC_OK, DEC_ENOTCONV or
+ * DEC_EBREAKDOWN (T then holds the last iterate), DEC_ESTATE before
+ * dec_apply_bc, DEC_EINVAL for a bad option.  The solver keeps its Krylov
+ * vectors with the mesh (allocated on first use).  Synchronises the stream. */
 int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats);
 
-/* y = A x with the current system matrix.  precision DEC_PREC_FP64 (x, y
- * float64) or DEC_PREC_MIXED (x, y float32), format DEC_FMT_*.  Device
- * vectors of length V.  Asynchronous. */
+/* y = A x with the current system matrix: the solver's matrix-vector product
+ * (Section 2.3), the dominant kernel of every solve.  precision DEC_PREC_FP64
+ * (x, y float64) or DEC_PREC_MIXED (x, y float32), format DEC_FMT_CSR (the
+ * full static pattern) or DEC_FMT_SELL / DEC_FMT_AUTO (the solver's
+ * sliced-ELL copy; the same sums).  x, y: device vectors of length V owned
+ * by the caller, not aliasing.  DEC_ESTATE before dec_assemble, DEC_EINVAL
+ * for a NULL vector or a bad precision.  Asynchronous on the stream. */
 int dec_spmv(dec_mesh* m, int32_t precision, int32_t format, const void* x, void* y);
 
 /* The FSAI factor G of the current system (built on first use): nnz_out
