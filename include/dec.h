@@ -277,6 +277,27 @@ int dec_solve_opts_default(dec_solve_opts* opts);
  * vectors with the mesh (allocated on first use).  Synchronises the stream. */
 int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats);
 
+/* The same FP64 Jacobi PCG as dec_solve, for callers that cannot allocate
+ * device memory (code running while other work is captured into a graph,
+ * tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * allocator.  Its Krylov vectors r, p, q, the partial sums of its reductions
+ * and its scalar state live in one static device array of the library, held
+ * on every GPU the library runs on from library load to process end:
+ * 3 x 8 B x DEC_NOALLOC_MAX_ROWS (96 MiB) plus 64 KiB; x is T itself.
+ * m: after dec_apply_bc, at most DEC_NOALLOC_MAX_ROWS rows (DEC_EINVAL with a
+ * message naming both counts beyond that).  opts: precision DEC_PREC_FP64,
+ * precond DEC_PRECOND_JACOBI, norm DEC_NORM_RESIDUAL and profile 0, else
+ * DEC_EINVAL; tol, warm_start, max_iters and chunk as in dec_solve; format and
+ * use_graph are ignored (sliced-ELL product, no graphs).  T [V] float64
+ * device: initial guess when warm_start, solution on return.  stats (host,
+ * NULL ok): iterations, restarts, residuals, solve_ms (host clock).  Returns
+ * as dec_solve.  Every call on one GPU uses that GPU's one array: calls from
+ * this process are serialised per device, and the array keeps the last
+ * call's contents (each call initialises what it reads).  It is ordered on
+ * the context's stream and synchronises it before returning. */
+#define DEC_NOALLOC_MAX_ROWS 4194304
+int dec_solve_noalloc(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats);
+
 /* y = A x with the current system matrix: the solver's matrix-vector product
  * (Section 2.3), the dominant kernel of every solve.  precision DEC_PREC_FP64
  * (x, y float64) or DEC_PREC_MIXED (x, y float32), format DEC_FMT_CSR (the

@@ -245,6 +245,20 @@ class Mesh:
             self.ctx.check(rc, "dec_solve")
         return T, st.as_dict(), rc
 
+    def solve_noalloc(self, T=None, opts=None, check=True, **kw):
+        """dec_solve_noalloc: FP64 Jacobi PCG whose scratch is the library's static device array
+        (no allocation inside the call); T (allocated here when None) receives the solution.
+        Returns (T, stats dict, status)."""
+        o = opts if opts is not None else self.options(**kw)
+        if T is None:
+            T = torch.zeros(self.V, dtype=torch.float64, device=self.dev)
+        st = SolveStats()
+        rc = self.lib.dec_solve_noalloc(self.handle, ctypes.byref(o), _ptr(T, torch.float64, self.V, "T"),
+                                        ctypes.byref(st))
+        if check:
+            self.ctx.check(rc, "dec_solve_noalloc")
+        return T, st.as_dict(), rc
+
     def spmv(self, x, y=None, precision=DEC_PREC_FP64, fmt=DEC_FMT_SELL):
         dt = torch.float64 if precision == DEC_PREC_FP64 else torch.float32
         if y is None:

@@ -23,6 +23,7 @@ DEC_PREC_FP64, DEC_PREC_MIXED = 0, 1
 DEC_PRECOND_JACOBI, DEC_PRECOND_FSAI, DEC_PRECOND_BLOCK = 0, 1, 2
 DEC_FMT_AUTO, DEC_FMT_CSR, DEC_FMT_SELL = 0, 1, 2
 DEC_NORM_RESIDUAL, DEC_NORM_ENERGY = 0, 1
+DEC_NOALLOC_MAX_ROWS = 4194304
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -111,6 +112,7 @@ SIGNATURES = {
     "dec_apply_bc": (c_int, [vp, vp, vp, vp, i64p, vp]),
     "dec_solve_opts_default": (c_int, [ctypes.POINTER(SolveOpts)]),
     "dec_solve": (c_int, [vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveStats)]),
+    "dec_solve_noalloc": (c_int, [vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveStats)]),
     "dec_spmv": (c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]),
     "dec_get_fsai": (c_int, [vp, i64p, vp, vp, vp]),
     "dec_flux_effective_conductivity": (c_int, [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,

@@ -4,6 +4,9 @@
 #include "common.h"
 
 void destroy_solve_cache(SolveCache* c);
+// Device address of dec_solve_noalloc's static scratch on `device` (the current
+// device), taken once per device; a failure is kept and reported by that call.
+void noalloc_setup(int device);
 
 void* dec_ctx::dalloc(size_t bytes) {
     void* p = nullptr;
@@ -200,8 +203,13 @@ int dec_create(dec_ctx** out, int device, void* stream, dec_alloc_fn alloc, dec_
         hipDeviceProp_t prop;
         HIP_CHECK(hipGetDeviceProperties(&prop, device));
         c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        // the staging area of scalar read-backs, so that no later read-back of up to 4 KiB allocates
+        HIP_CHECK(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
+        c->pinned_bytes = 4096;
+        noalloc_setup(device);
     } catch (const DecError& e) {
         int code = e.code;
+        if (c->pinned) (void)hipHostFree(c->pinned);
         delete c;
         return code;
     }

@@ -13,8 +13,10 @@
 // depend on scheduling.  Scalars stay on the device; the host launches
 // batches of iterations (optionally a captured hipGraph) and reads the
 // state once per batch.
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
@@ -922,6 +924,179 @@ void ensure_vectors(dec_mesh* m, SolveCache* c, int precision) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- solve without allocation
+// dec_solve_noalloc keeps its vectors, partial sums and scalar state in one
+// static device array per GPU (each device holds its own copy of the code
+// object's variables), laid out in doubles as
+//     [0, NA_STATE)                 PcgScalars: two parity copies and a scratch copy
+//     [NA_STATE, NA_HEAD)           partial sums: regions R_PQ, R_RR, R_RZ of NA_PARTS each
+//     [NA_HEAD, + 3 DEC_NOALLOC_MAX_ROWS)  r, p, q
+// The solution vector is the caller's T.  In host code the array's name is
+// only a host-side stand-in: the kernels get the device address that
+// hipGetSymbolAddress gave for the device (noalloc_setup, called by
+// dec_create with the device current), never `scratch` itself.
+namespace {
+constexpr int64_t NA_STATE = 128;       // doubles: room for 4 PcgScalars
+constexpr int64_t NA_PARTS = 2048;      // partials per region: more than any launch's blocks
+constexpr int64_t NA_HEAD = 8192;       // doubles before the vectors (64 KiB)
+constexpr int64_t NA_ROWS = DEC_NOALLOC_MAX_ROWS;
+constexpr int NA_MAX_DEVICES = 64;
+static_assert(4 * sizeof(PcgScalars) <= NA_STATE * sizeof(double), "scalar states fit their region");
+static_assert(NA_STATE + 3 * NA_PARTS <= NA_HEAD, "partials fit before the vectors");
+}  // namespace
+
+static __device__ __align__(256) double scratch[NA_HEAD + 3 * NA_ROWS];
+
+namespace {
+std::mutex na_mutex;                           // set-up of the table below
+std::mutex na_solve_mutex[NA_MAX_DEVICES];     // one solve at a time per device in this process
+double* na_ptr[NA_MAX_DEVICES] = {};           // device address of `scratch`, per device
+std::string na_error[NA_MAX_DEVICES];          // why set-up failed, per device
+
+// x = Dirichlet values on Dirichlet rows, 0 on pinned rows, and on the others
+// x itself (warm start) or 0
+__global__ void k_init_x_inplace(int64_t V, const uint8_t* __restrict__ fixed, const double* __restrict__ dval,
+                                 int warm, double* x) {
+    GRID_STRIDE_LOOP(i, V) {
+        const uint8_t f = fixed[i];
+        x[i] = f == 1 ? dval[i] : (f == 2 ? 0.0 : (warm ? x[i] : 0.0));
+    }
+}
+
+__global__ void k_zero(int64_t V, double* __restrict__ x) { GRID_STRIDE_LOOP(i, V) x[i] = 0.0; }
+
+// FP64 Jacobi PCG on A (the recurrence and kernels of dec_solve's FP64 path)
+// with every buffer beyond m's system and T in the scratch at `base`.
+int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base, dec_solve_stats* stats) {
+    dec_ctx* ctx = m->ctx;
+    const int64_t V = m->V;
+    PcgScalars* st = reinterpret_cast<PcgScalars*>(base);  // [0], [1] parities, [2] scratch
+    PcgScalars* s2 = st + 2;
+    double* part = base + NA_STATE;
+    const int P = static_cast<int>(NA_PARTS);
+    double* r = base + NA_HEAD;
+    double* p = r + NA_ROWS;
+    double* q = p + NA_ROWS;
+    // launch settings only: this cache owns no buffer, stream or graph
+    SolveCache c;
+    c.ctx = ctx;
+    c.stream = ctx->stream;
+    auto blocks = [&](int64_t rows_per_block, int per_cu) {
+        const int64_t want = (V + rows_per_block - 1) / rows_per_block;
+        int64_t cap = (int64_t)per_cu * ctx->num_cus;
+        if (cap > NA_PARTS) cap = NA_PARTS;
+        const int64_t g = want < cap ? want : cap;
+        return (int)(((g + 7) / 8) * 8);
+    };
+    c.G = blocks(BLOCK, 4);
+    c.Gs = blocks(SELL_C * (BLOCK / 64), 8);
+    const std::array<int64_t, 4> shape{0 + (m->sell.excess64.p ? 2 : 0) + (m->sell.dcol.p ? 4 : 0), V,
+                                       m->sell.nslices, m->sell.entries};
+    auto known = ctx->spmv_tune.find(shape);  // a variant timed earlier for this shape, else the default
+    if (known != ctx->spmv_tune.end()) {
+        c.unroll[0] = known->second.first;
+        c.nt[0] = known->second.second;
+    }
+    const SellView<double> A = view<double>(&c, m->sell, V);
+    const int G = c.G, Gs = c.Gs;
+    const dim3 blk(BLOCK);
+    auto fin = [&](int what, int n_rr, int n_rz, double factor, PcgScalars* s) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), blk, 0, c.stream, part, P, n_rr, n_rz, what, factor, 0, s);
+    };
+    auto state = [&](const PcgScalars* s) {  // the pinned staging area exists from dec_create on
+        DEC_REQUIRE(ctx->pinned && ctx->pinned_bytes >= sizeof(PcgScalars), DEC_ESTATE, "no staging area");
+        return read_state(&c, s);
+    };
+    hipLaunchKernelGGL(k_init_x_inplace, dim3(grid_for(V)), blk, 0, c.stream, V, m->fixed.p, m->bc_value.p,
+                       (int)o.warm_start, T);
+    hipLaunchKernelGGL(k_norm2, dim3(G), blk, 0, c.stream, V, m->rhs.p, part + R_RR * P);
+    fin(FIN_NORM2, G, G, 0.0, s2);
+    HIP_CHECK(hipGetLastError());
+    const double bb = state(s2).aux;
+    if (stats) stats->spmv_nnz = m->sell.kept;
+    if (bb == 0.0) {
+        hipLaunchKernelGGL(k_zero, dim3(grid_for(V)), blk, 0, c.stream, V, T);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(c.stream));
+        return DEC_OK;
+    }
+    const double tol2 = o.tol * o.tol;
+    const int chunk = even_chunk(o);
+    int64_t total = 0;
+    double rr = 0.0;
+    int status = DEC_ENOTCONV;
+    for (int restart = 0; restart <= 20; ++restart) {
+        const int64_t left = o.max_iters - total;
+        if (left <= 0) break;
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, c.stream, st, left, (int32_t)0);
+        hipLaunchKernelGGL(k_norm2, dim3(G), blk, 0, c.stream, V, m->rhs.p, part + R_RR * P);
+        fin(FIN_NORM2, G, G, tol2, st);
+        launch_sell<double, MODE_RESID>(&c, A, T, r, m->rhs.p, part + R_RR * P, nullptr);
+        hipLaunchKernelGGL(k_init_jacobi<double>, dim3(G), blk, 0, c.stream, V, r, m->invdiag64.p, p,
+                           part + R_RZ * P);
+        fin(FIN_START, Gs, G, 0.0, st);
+        HIP_CHECK(hipGetLastError());
+        PcgScalars s = state(st);
+        for (int64_t batch = 0; !s.done; ++batch) {
+            DEC_REQUIRE(batch <= o.max_iters / chunk + 4, DEC_EHIP, "PCG batches exceed the iteration cap");
+            const int64_t before = s.iter;
+            for (int k = 0; k < chunk; ++k) {
+                PcgScalars* S = st + (k & 1);
+                PcgScalars* N = st + ((k & 1) ^ 1);
+                launch_sell<double, MODE_DOT>(&c, A, p, q, nullptr, part + R_PQ * P, S);
+                hipLaunchKernelGGL((k_update<double, PJ_JACOBI>), dim3(G), blk, 0, c.stream, V, r, q,
+                                   m->invdiag64.p, part, P, Gs, S);
+                hipLaunchKernelGGL((k_close<double, PJ_JACOBI>), dim3(G), blk, 0, c.stream, V, T, r,
+                                   m->invdiag64.p, (const double*)nullptr, p, part, P, G, S, N);
+            }
+            HIP_CHECK(hipGetLastError());
+            s = state(st);
+            DEC_REQUIRE(s.done || s.iter > before, DEC_EHIP, "PCG made no progress in a batch");
+        }
+        total += s.iter;
+        if (s.done == PCG_BREAKDOWN) {
+            status = DEC_EBREAKDOWN;
+            break;
+        }
+        if (s.done == PCG_MAXITER) break;
+        // converged on the recursive residual: confirm with the true one (q is free now)
+        launch_sell<double, MODE_RESID>(&c, A, T, q, m->rhs.p, part + R_RR * P, nullptr);
+        fin(FIN_RR, Gs, G, 0.0, s2);
+        HIP_CHECK(hipGetLastError());
+        rr = state(s2).rr;
+        if (rr <= tol2 * bb) {
+            status = DEC_OK;
+            break;
+        }
+        if (stats) stats->restarts += 1;
+    }
+    if (status != DEC_OK) {
+        launch_sell<double, MODE_RESID>(&c, A, T, q, m->rhs.p, part + R_RR * P, nullptr);
+        fin(FIN_RR, Gs, G, 0.0, s2);
+        HIP_CHECK(hipGetLastError());
+        rr = state(s2).rr;
+    }
+    if (stats) {
+        stats->iterations = total;
+        stats->rel_residual = stats->plain_residual = sqrt(rr / bb);
+    }
+    return status;
+}
+}  // namespace
+
+void noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (device < 0 || device >= NA_MAX_DEVICES || na_ptr[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        (void)hipGetLastError();
+        na_error[device] = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+        return;
+    }
+    na_ptr[device] = static_cast<double*>(p);
+}
+
 void clear_graphs(SolveCache* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
@@ -1066,6 +1241,51 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
             const bool keep = o.norm == DEC_NORM_ENERGY && status == DEC_OK && bb != 0.0;
             if (!keep) stats->rel_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
             stats->plain_residual = bb == 0.0 ? 0.0 : sqrt(rr / bb);
+            stats->status = status;
+        }
+        if (status != DEC_OK) ctx->last_error = dec_status_string(status);
+        return status;
+    } catch (const DecError& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+}
+
+int dec_solve_noalloc(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stats* stats) {
+    if (!m) return DEC_EINVAL;
+    if (!opts || !T) return null_argument(m->ctx, "dec_solve_noalloc");
+    dec_ctx* ctx = m->ctx;
+    try {
+        const dec_solve_opts& o = *opts;
+        DEC_REQUIRE(m->V <= DEC_NOALLOC_MAX_ROWS, DEC_EINVAL,
+                    "dec_solve_noalloc: " + std::to_string(m->V) + " rows exceed the scratch's maximum of " +
+                        std::to_string((long long)DEC_NOALLOC_MAX_ROWS));
+        DEC_REQUIRE(m->bc_ready, DEC_ESTATE, "dec_solve_noalloc needs dec_apply_bc first");
+        DEC_REQUIRE(o.precision == DEC_PREC_FP64 && o.precond == DEC_PRECOND_JACOBI && o.norm == DEC_NORM_RESIDUAL,
+                    DEC_EINVAL, "dec_solve_noalloc runs FP64 Jacobi PCG with the residual test only");
+        DEC_REQUIRE(o.profile == 0, DEC_EINVAL, "dec_solve_noalloc does not profile");
+        DEC_REQUIRE(o.tol > 0.0 && o.max_iters > 0 && o.chunk >= 0 && o.chunk <= 4096, DEC_EINVAL,
+                    "bad tolerance or iteration limits");
+        DEC_REQUIRE(ctx->device >= 0 && ctx->device < NA_MAX_DEVICES, DEC_EINVAL, "device index beyond the table");
+        double* base = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(na_mutex);
+            base = na_ptr[ctx->device];
+            DEC_REQUIRE(base != nullptr, DEC_EHIP,
+                        na_error[ctx->device].empty() ? "scratch not set up" : na_error[ctx->device]);
+        }
+        ctx->set_device();
+        std::lock_guard<std::mutex> solve_lock(na_solve_mutex[ctx->device]);
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            const double cb = m->sell.dcol.p ? 2.0 : 4.0, nz = (double)m->sell.kept;
+            stats->spmv_bytes = nz * (8.0 + cb) + 4.0 * (double)(m->V + 1) + 16.0 * (double)m->V;
+            if (m->sell.excess64.p) stats->spmv_bytes += 8.0 * (double)m->V;
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        const int status = solve_noalloc(m, o, T, base, stats);
+        if (stats) {
+            stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             stats->status = status;
         }
         if (status != DEC_OK) ctx->last_error = dec_status_string(status);
