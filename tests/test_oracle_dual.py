@@ -159,3 +159,62 @@ def test_rms_error_of_eq15():
     one = np.array([[0.0, 0, 0], [2, 0, 0], [0, 2, 0], [0, 0, 2]])
     # circumcentre (1, 1, 1), volume 8/6; field 2x + 3y: exact 5 there, T = 7
     assert abs(D.rms_error_tets(one, [[0, 1, 2, 3]], [7.0], (0.0, 2.0, 3.0, 0.0)) - 2.0 * np.sqrt(8 / 6)) < 1e-14
+
+
+def _linear_residual(xyz, tets, g=(0.3, -0.7, 0.55), a=0.2):
+    """(L u)_t for u = a + g.c_t (the linear field at the Voronoi nodes) over the tets whose four
+    faces are interior and unlimited, with the scale sum_f W_f |u_t - u_t'|, and that count."""
+    bt, bv, side = W.x_faces(xyz)
+    s = D.dual_system(xyz, tets, bt, bv, side)
+    t1, _, t2, _, _ = s["faces"]
+    geo = s["geo"]
+    lim = geo["h"] / geo["area"] <= D.LIMITER
+    excluded = np.zeros(len(tets), dtype=bool)
+    excluded[t1[(t2 < 0) | lim]] = True
+    excluded[t2[(t2 >= 0) & lim]] = True
+    u = a + geo["ct"] @ np.asarray(g)
+    Lu = s["L"] @ u
+    inner = t2 >= 0
+    d = np.abs(u[t1[inner]] - u[t2[inner]]) * s["W"][inner]
+    scale = np.zeros(len(tets))
+    np.add.at(scale, t1[inner], d)
+    np.add.at(scale, t2[inner], d)
+    keep = ~excluded
+    return Lu[keep], scale[keep], int(keep.sum())
+
+
+def test_linear_fields_are_exact_at_interior_voronoi_nodes():
+    """Off the lattice (Delaunay meshes of a jittered lattice and of random points): for a tet
+    whose four faces are interior and unlimited, the flux balance of a linear field u = a + g.x
+    taken at the circumcentres vanishes, (L u)_t = sum_f (|f| / h_f)(u_t - u_t') = -g . sum_f |f| n_f
+    = 0, because the Voronoi edge through a face is orthogonal to it (c_t' - c_t = h_f n_f with n_f
+    the unit normal out of t) and the outward area vectors of a closed surface sum to zero
+    (Section 3.1: exact for linear solutions where nothing is limited).  A wrong normal sign
+    limits almost every face (the count below), a wrong area or length breaks the balance."""
+    for xyz, tets in (W.delaunay_lattice(8, 0.2, 1), W.delaunay_lattice(8, 0.2, 2), W.delaunay_cube(600, 60, 3)):
+        Lu, scale, count = _linear_residual(xyz, tets)
+        assert count >= 0.7 * len(tets), (count, len(tets))
+        assert (np.abs(Lu) <= 1e-9 * scale).all(), np.max(np.abs(Lu) / scale)
+        assert np.median(np.abs(Lu) / scale) <= 1e-13
+
+
+def test_one_interior_face_by_hand():
+    """Two tets sharing the face (1,0,0), (0,1,0), (0,0,1): t1 has the origin as its fourth vertex
+    and circumcentre (1/2, 1/2, 1/2); t2 has (2,2,2), and its circumcentre s(1,1,1) satisfies
+    (s - 1)^2 + 2 s^2 = 3 (s - 2)^2, s = 11/10.  Face area sqrt(3)/2; the unit normal out of t1 is
+    (1,1,1)/sqrt(3), so h = 0.6 sqrt(3) and *_f = h / |f| = 1.2.  A boundary face of t1, the one in
+    the plane x = 0: area 1/2, circumcentre (0, 1/2, 1/2), h = 1/2 along (-1, 0, 0), *_f = 1."""
+    xyz = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [2, 2, 2]])
+    tets = np.array([[0, 1, 2, 3], [1, 2, 3, 4]])
+    faces = D.faces_by_owner(tets)
+    geo = D.face_geometry(xyz, tets, faces)
+    t1, k1, t2, _, verts = faces
+    assert np.allclose(geo["ct"], [[0.5, 0.5, 0.5], [1.1, 1.1, 1.1]], rtol=0, atol=1e-15)
+    f = int(np.flatnonzero(t2 >= 0)[0])
+    assert (t1[f], t2[f], set(verts[f])) == (0, 1, {1, 2, 3})
+    assert abs(geo["area"][f] - np.sqrt(3) / 2) <= 1e-15
+    assert abs(geo["h"][f] - 0.6 * np.sqrt(3)) <= 1e-15
+    assert abs(geo["star"][f] - 1.2) <= 1e-15
+    b = [i for i in np.flatnonzero(t2 < 0) if t1[i] == 0 and set(verts[i]) == {0, 2, 3}][0]
+    assert abs(geo["area"][b] - 0.5) <= 1e-16 and abs(geo["h"][b] - 0.5) <= 1e-16
+    assert np.allclose(geo["cf"][b], [0.0, 0.5, 0.5], rtol=0, atol=1e-16) and abs(geo["star"][b] - 1.0) <= 1e-15
