@@ -7,8 +7,12 @@ kappa = exp(Z) (sigma 1, seed 1, canonical edge order), 200 penny cracks
 Stored: mesh counts, the full set of cut edges and pinned vertices
 (bit-exact targets), *1 on a seeded sample of edges, the reference
 solution x* (oracle PCG to 1e-14 relative residual or stagnation) on a
-seeded sample of vertices with its norm, k_eff / Q_in / Q_out / energy at
-x*, and the error against x* of the oracle's own solve stopped at 1e-10.
+seeded sample S of 65,536 vertices with its norms, k_eff / Q_in / Q_out /
+energy at x*, and the error against x* of the oracle's own solves stopped at
+1e-10 (Jacobi PCG in FP64, and FP64 iterative refinement around FP32 Jacobi
+PCG, the mixed-precision method), over the whole vector and on S
+(||x_S - x*_S||_2 / ||x*_S||_2, the measure the parity tests apply to the
+GPU's solution).
 
     python tests/golden/make_golden.py [n]      (n = 128 by default; minutes of CPU)
 """
@@ -48,10 +52,15 @@ def main(n=128):
     loose = O.pcg(A, b, precond="jacobi", tol=1e-10)
     err_loose = float(np.linalg.norm(loose.x - ref.x) / np.linalg.norm(ref.x))
     print(f"[{time.time()-t0:.0f}s] 1e-10 solve: {loose.iterations} its, error vs x* {err_loose:.2e}", flush=True)
+    x_ir, ir_outer, ir_inner, ir_res = O.iterative_refinement(A, b, tol=1e-10, inner_tol=1e-5, precond="jacobi",
+                                                              adaptive_final=True)
+    print(f"[{time.time()-t0:.0f}s] mixed refinement: inner {ir_inner}, residual {ir_res:.2e}", flush=True)
     f = O.flux_effective_conductivity(ref.x, E, star, side)
     rng = np.random.Generator(np.random.PCG64(12345))
     e_sample = np.sort(rng.choice(len(E), size=4096, replace=False))
-    v_sample = np.sort(rng.choice(V, size=4096, replace=False))
+    v_sample = np.sort(rng.choice(V, size=min(V, 65536), replace=False))
+    x_s = ref.x[v_sample]
+    err_loose_s = float(np.linalg.norm(loose.x[v_sample] - x_s) / np.linalg.norm(x_s))
     np.savez_compressed(
         os.path.join(HERE, f"{name}.npz"),
         cut_edges=np.nonzero(cut)[0].astype(np.int64),
@@ -60,7 +69,7 @@ def main(n=128):
         edge_sample_lohi=E[e_sample],
         star1_sample=star[e_sample],
         vertex_sample=v_sample,
-        x_sample=ref.x[v_sample],
+        x_sample=x_s,
         b_sample=b[v_sample],
     )
     meta = {
@@ -78,6 +87,11 @@ def main(n=128):
         "ref_rel_residual": float(ref.rel_residual),
         "loose_iterations": int(loose.iterations),
         "loose_error_vs_ref": err_loose,
+        "x_sample_norm": float(np.linalg.norm(x_s)),
+        "loose_sample_error_vs_ref": err_loose_s,
+        "ir_inner_iterations": [int(k) for k in ir_inner],
+        "ir_rel_residual": float(ir_res),
+        "ir_sample_error_vs_ref": float(np.linalg.norm(x_ir[v_sample] - x_s) / np.linalg.norm(x_s)),
         "k_eff": f["k_eff"],
         "q_in": f["q_in"],
         "q_out": f["q_out"],

@@ -3,11 +3,12 @@
 The stored values (tests/golden/kuhn128_lognormal1_cracks200.*) come from
 tests/golden/make_golden.py, which calls only the oracle.  Bit-exact: mesh
 counts, the whole set of cut edges, the pinned vertices.  Floating point:
-*1 on a seeded edge sample to 1e-13; the solution on a seeded vertex sample
-to 1e-10 ||x*|| (the GPU solves to 1e-14, as the oracle's reference did:
-on this conditioning a 1e-10 residual leaves ~1e-7 relative error); k_eff
-to 1e-9 relative.  The throughput configuration (tol 1e-10) is held to
-twice the oracle's own 1e-10 solve error on the sample.
+*1 on a seeded edge sample to 1e-13; the solution on a seeded sample S of
+65,536 vertices in the 2-norm, ||x_S - x*_S||_2 <= 1e-10 ||x*_S||_2 (the GPU
+solves to 1e-14, as the oracle's reference did: on this conditioning a 1e-10
+residual leaves ~1e-7 relative error); k_eff to 1e-9 relative.  The
+throughput configuration (tol 1e-10) is held, in the same measure on the same
+sample, to twice the error of the oracle's own 1e-10 solve.
 """
 import json
 import os
@@ -22,6 +23,13 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 NAME = "kuhn128_lognormal1_cracks200"
+
+
+def sample_error(T, arr):
+    """||x_S - x*_S||_2 / ||x*_S||_2 on the stored vertex sample S."""
+    vs = torch.as_tensor(arr["vertex_sample"], device=T.device)
+    xs = arr["x_sample"]
+    return float(np.linalg.norm(T[vs].cpu().numpy() - xs) / np.linalg.norm(xs))
 
 
 @pytest.fixture(scope="module")
@@ -75,9 +83,8 @@ def test_solution_against_reference(mesh128, golden, precision, precond):
     m = mesh128["m"]
     T, st, rc = m.solve(tol=1e-14, precision=precision, precond=precond, check=False)
     assert rc == 0, st
-    vs = torch.as_tensor(arr["vertex_sample"], device=T.device)
-    err = np.abs(T[vs].cpu().numpy() - arr["x_sample"]).max()
-    assert err <= 1e-10 * meta["x_norm"], (err, st)
+    err = sample_error(T, arr)
+    assert err <= 1e-10, (err, st)
     assert abs(float(torch.linalg.norm(T)) - meta["x_norm"]) <= 1e-10 * meta["x_norm"]
     f = m.flux(T, mesh128["side"])
     assert abs(f["k_eff"] - meta["k_eff"]) <= 1e-9 * meta["k_eff"]
@@ -90,9 +97,8 @@ def test_throughput_tolerance_error(mesh128, golden):
     m = mesh128["m"]
     T, st, rc = m.solve(tol=1e-10)
     assert rc == 0 and st["rel_residual"] <= 1e-10
-    vs = torch.as_tensor(arr["vertex_sample"], device=T.device)
-    err = np.abs(T[vs].cpu().numpy() - arr["x_sample"]).max() / meta["x_norm"]
-    assert err <= 2 * meta["loose_error_vs_ref"]
+    err = sample_error(T, arr)
+    assert err <= 2 * meta["loose_sample_error_vs_ref"], (err, meta["loose_sample_error_vs_ref"])
     f = m.flux(T, mesh128["side"])
     assert abs(f["k_eff"] - meta["k_eff"]) <= 1e-9 * meta["k_eff"]
     assert abs(f["energy"] - f["q_in"]) <= 1e-7 * f["energy"]

@@ -2,8 +2,9 @@
 
 64^3 replica: against stored oracle values (tests/golden/growth64.*, written
 by tests/golden/make_golden_growth.py from the oracle only) -- cut and
-pinned counts and the first/last cut sets bit-exact, solution samples to
-1e-10 ||x*|| (GPU to 1e-14), k_eff to 1e-9 of the uncracked value.
+pinned counts and the first/last cut sets bit-exact, the solution on a seeded
+sample S of 65,536 vertices to ||x_S - x*_S||_2 <= 1e-10 ||x*_S||_2 (GPU to
+1e-14), k_eff to 1e-9 of the uncracked value.
 
 256^3 (16,974,593 vertices): counts against the closed forms, the cut
 flags of 20,000 seeded lattice edges against the oracle predicate, and
@@ -68,16 +69,21 @@ def test_growth64_against_oracle(ctx, dev):
             assert np.array_equal(torch.nonzero(cut).flatten().cpu().numpy(), arr[f"cut_edges_{s}"])
         T, st, rc = m.solve(T=T, tol=1e-14, warm_start=1, check=False)
         assert rc == 0, (s, st)
-        err = np.abs(T[vs].cpu().numpy() - arr[f"x_sample_{s}"]).max()
-        assert err <= 1e-10 * ref["x_norm"], (s, err)
+        xs = arr[f"x_sample_{s}"]
+        err = np.linalg.norm(T[vs].cpu().numpy() - xs) / np.linalg.norm(xs)
+        print(f"step {s}: sample error {err:.3e} (oracle 1e-10 solve {ref['loose_sample_error_vs_ref']:.3e})",
+              flush=True)
+        assert err <= 1e-10, (s, err)
         f = m.flux(T, side)
         assert abs(f["k_eff"] - ref["k_eff"]) <= 1e-9 * k0, s
         assert abs(f["q_in"] - ref["q_in"]) <= 1e-9 * k0 and abs(f["q_out"] - ref["q_out"]) <= 1e-9 * k0
     # the last step again in mixed precision, cold
     Tm, st, rc = m.solve(tol=1e-14, precision=1, check=False)
     assert rc == 0
-    err = np.abs(Tm[vs].cpu().numpy() - arr[f"x_sample_{steps[-1]}"]).max()
-    assert err <= 1e-10 * meta["steps"][str(steps[-1])]["x_norm"]
+    xs = arr[f"x_sample_{steps[-1]}"]
+    err = np.linalg.norm(Tm[vs].cpu().numpy() - xs) / np.linalg.norm(xs)
+    print(f"step {steps[-1]} mixed: sample error {err:.3e}", flush=True)
+    assert err <= 1e-10, err
     m.close()
 
 

@@ -1,0 +1,105 @@
+"""Served results at serving sizes against the oracle: requests 0, 16, ..., 496 of the
+512-request stream (Kuhn cubes n ~ U{24..96}, i.e. 8 to 446 work-table chunks per system,
+0-400 penny cracks, kappa sigma 0.5), served together by one mixed-precision server.
+
+Stored values: tests/golden/serve512_every16.*, written by tests/golden/make_golden_serve.py
+from the oracle only (x* to 1e-14 on a seeded sample S of up to 4096 vertices per request,
+k_eff at x*, and the error on S of the oracle's own solves stopped at 1e-10).  Gates, per
+request, in ||x_S - x*_S||_2 / ||x*_S||_2: <= 1e-10 with the mixed server at 1e-14.  At the
+throughput tolerance 1e-10: the FP64 server runs the oracle's recurrence (Jacobi PCG stopped at
+the first residual below the tolerance) and stays within 2x the oracle's FP64 error (measured:
+1.00x).  A refinement stops wherever its last FP32 inner solve ends below the tolerance, so two
+refinements of one system leave errors a factor of ~2.5 apart either way (the oracle's own
+refinement: 0.4x to 2.3x its FP64 error); the mixed server is held to 2x the larger of the
+oracle's two errors at this tolerance.  k_eff within 1e-9 relative throughout.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+NAME = "serve512_every16"
+
+
+@pytest.fixture(scope="module")
+def stream(dev):
+    import paper_2104_05999_amd as dec
+    meta = json.load(open(os.path.join(HERE, "golden", NAME + ".json")))
+    arr = np.load(os.path.join(HERE, "golden", NAME + ".npz"))
+    trace = {spec.index: spec for spec in W.serving_trace(meta["count"], meta["seed"], 0.0)}
+    reqs = []
+    for r in meta["requests"]:
+        spec = trace[r["index"]]
+        assert (spec.n, spec.n_cracks) == (r["n"], r["n_cracks"])
+        xyz, tets = W.kuhn_cube(spec.n, device=dev)
+        bt, bv, side = W.x_sides(spec.n)
+        t = lambda a: torch.as_tensor(a, device=dev)  # noqa: E731
+        req = dict(xyz=xyz, tets=tets, bc_type=t(bt), bc_value=t(bv), side=t(side),
+                   kappa=t(W.lognormal_kappa(W.kuhn_counts(spec.n)["E"], 0.5, spec.kappa_seed)))
+        if spec.n_cracks:
+            req["cracks"] = t(W.penny_cracks(spec.n_cracks, spec.crack_seed))
+        reqs.append(req)
+    ctx = dec.Context(dev)
+    yield ctx, meta, arr, reqs
+    ctx.close()
+
+
+def _serve_all(ctx, reqs, tol, precision=1):
+    import paper_2104_05999_amd as dec
+    srv = dec.Server(ctx, 48 << 30, precision=precision, max_slots=64, chunk=24, tol=tol)
+    for k, r in enumerate(reqs):
+        r["T_out"] = torch.zeros(r["xyz"].shape[0], dtype=torch.float64, device=r["xyz"].device)
+        srv.submit(r, user_tag=k)
+    out, peak = {}, 0
+    for _ in range(100000):
+        active, pending = srv.step()
+        peak = max(peak, active)
+        for res in srv.poll():
+            out[res["user_tag"]] = res
+        if len(out) == len(reqs):
+            break
+    srv.close()
+    assert len(out) == len(reqs)
+    return out, peak
+
+
+def _errors(meta, arr, reqs, out):
+    errs = []
+    for k, r in enumerate(meta["requests"]):
+        q = r["index"]
+        vs = torch.as_tensor(arr[f"vertex_sample_{q}"], device=reqs[k]["T_out"].device)
+        xs = arr[f"x_sample_{q}"]
+        e = float(np.linalg.norm(reqs[k]["T_out"][vs].cpu().numpy() - xs) / np.linalg.norm(xs))
+        dk = abs(out[k]["k_eff"] - r["k_eff"]) / r["k_eff"]
+        errs.append((q, e, dk, r["loose_sample_error_vs_ref"], r["ir_sample_error_vs_ref"]))
+    return errs
+
+
+def test_stream_sample_at_tight_tolerance(stream):
+    ctx, meta, arr, reqs = stream
+    out, peak = _serve_all(ctx, reqs, 1e-14)
+    assert peak >= 8
+    assert all(res["status"] == 0 for res in out.values()), [r for r in out.values() if r["status"]]
+    for q, e, dk, _, _ in _errors(meta, arr, reqs, out):
+        print(f"request {q}: sample error {e:.2e}, k_eff {dk:.2e}", flush=True)
+        assert e <= 1e-10, (q, e)
+        assert dk <= 1e-9, (q, dk)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stream_sample_at_throughput_tolerance(stream, precision):
+    ctx, meta, arr, reqs = stream
+    out, _ = _serve_all(ctx, reqs, 1e-10, precision)
+    assert all(res["status"] == 0 and res["rel_residual"] <= 1e-10 for res in out.values())
+    for q, e, dk, loose, ir in _errors(meta, arr, reqs, out):
+        ref = loose if precision == 0 else max(loose, ir)
+        print(f"request {q}: sample error {e:.2e} = {e / loose:.2f} x the oracle's FP64 error, "
+              f"{e / ir:.2f} x its mixed-precision error", flush=True)
+        assert e <= 2 * ref, (q, e, loose, ir)
+        assert dk <= 1e-9, (q, dk)
