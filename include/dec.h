@@ -318,8 +318,15 @@ int dec_get_fsai(dec_mesh* m, int64_t* nnz_out, int32_t* g_ptr, int32_t* g_col, 
 /* ---- flux and effective conductivity (Section 2.5) ---------------------
  * T [V] float64, side [V] int8 (1 inflow face, 2 outflow face, 0 other).
  * Q_in = sum over side 1 of (L T)_v, Q_out = -sum over side 2, with L before
- * boundary elimination; energy E = sum_e *1_e (T_hi - T_lo)^2 and
- * k_eff = E length / (area dT^2).  Host scalar outputs (NULL ok);
+ * boundary elimination; energy E = sum_e *1_e (T_hi - T_lo)^2.  k_eff is the
+ * flux density through the inflow face over the gradient, Section 2.5's
+ * definition: without a Neumann load (the last dec_apply_bc had neumann_f0
+ * NULL) it is taken in the energy form k_eff = E length / (area dT^2), equal
+ * to Q_in length / (area dT) at the exact solution and second order in the
+ * solution's error; with a Neumann load k_eff = Q length / (area dT), Q the
+ * flux through a Dirichlet side: Q_in when side marks inflow vertices, else
+ * Q_out, NaN when it marks neither.
+ * Host scalar outputs (NULL ok);
  * edge_flux_out [E] float64 device (NULL ok): *1_e (T_lo - T_hi).
  * Synchronises the stream. */
 int dec_flux_effective_conductivity(dec_mesh* m, const double* T, const int8_t* side,
@@ -446,6 +453,9 @@ typedef struct dec_request {
     double length, area, dT;   /* k_eff scaling (0: 1)                                   */
     double* T_out;             /* [V] device or NULL: receives the solution              */
     uint64_t user_tag;
+    const double* T0;          /* [V] device or NULL: initial guess (warm start, e.g. the
+                                  previous step of a cracking path); Dirichlet values and
+                                  pinned zeros are imposed on it                          */
 } dec_request;
 /* The request's input arrays must stay valid until its result is polled
  * (they are read when the request is admitted); T_out likewise. */
@@ -453,8 +463,13 @@ typedef struct dec_request {
 typedef struct dec_result {
     uint64_t ticket;
     uint64_t user_tag;
-    int32_t status;             /* DEC_OK, DEC_ENOTCONV, DEC_ECANCELED, or a setup error   */
-    int32_t pad;
+    int32_t status;             /* DEC_OK, DEC_ENOTCONV, DEC_EBREAKDOWN (an FP64 inner
+                                   solve broke down or the residual is not finite),
+                                   DEC_ECANCELED, or a setup error                         */
+    int32_t fp64_fallback;      /* mixed: 1 when FP64 PCG finished (an FP32 solve broke down
+                                   or reached its cap of max(max_iters / 8, 64) iterations and
+                                   was not applied, or refinement stagnated: a correction that
+                                   raised the residual is taken back first), as dec_solve  */
     double k_eff, q_in, q_out, energy;
     double rel_residual;        /* FP64 ||b - A T|| / ||b|| at retirement                  */
     int64_t inner_iterations;   /* PCG iterations (FP32 inner, or FP64)                    */
@@ -469,7 +484,8 @@ typedef struct dec_server_opts {
     double inner_tol;             /* mixed: relative tolerance of each FP32 solve            */
     int32_t adaptive_final_inner; /* as dec_solve_opts                                      */
     int32_t chunk;                /* iterations per batch step (even, 2..1024)              */
-    int64_t max_iters;            /* per request, inner iterations                          */
+    int64_t max_iters;            /* per request, inner iterations; one FP32 solve gets at
+                                     most max(max_iters / 8, 64)                            */
 } dec_server_opts;
 
 /* Defaults: mixed precision, 64 slots, tol 1e-10, inner_tol 1e-5, adaptive

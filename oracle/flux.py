@@ -7,15 +7,22 @@ leaving vertex v through its dual cell is (L_full T)_v, L_full the operator
 before any boundary elimination, so
     Q_in  =  sum over inflow-face vertices of (L_full T)_v,
     Q_out = -sum over outflow-face vertices of (L_full T)_v,
-and the dissipated energy E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at
-the exact discrete solution.  The reported conductivity is the energy form
-k_eff = E length / (area dT^2) (Q_in and Q_out are reported beside it).
+and, when no Neumann flux is prescribed, the dissipated energy
+E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at the exact discrete
+solution.  The reported conductivity is the flux density through a Dirichlet
+side over the gradient, k_eff = Q length / (area dT), with Q = Q_in (or
+Q_out when no inflow face is marked: the paper allows either side); without
+a Neumann load it is taken in the energy form k_eff = E length / (area dT^2),
+the same number at the exact solution and second order in the solution's
+error (with a Neumann load the energy also holds the work of the prescribed
+fluxes).
 """
 import numpy as np
 
 
-def flux_effective_conductivity(T, edges, star1, side, length=1.0, area=1.0, dT=1.0):
-    """Return dict(k_eff, q_in, q_out, energy, edge_flux) with edge_flux_e = *1_e (T_lo - T_hi)."""
+def flux_effective_conductivity(T, edges, star1, side, length=1.0, area=1.0, dT=1.0, neumann=False):
+    """Return dict(k_eff, q_in, q_out, energy, edge_flux) with edge_flux_e = *1_e (T_lo - T_hi);
+    ``neumann``: the system carries a Neumann load (k_eff from Q_in, else from E)."""
     T = np.asarray(T, dtype=np.float64)
     edges = np.asarray(edges, dtype=np.int64)
     star1 = np.asarray(star1, dtype=np.float64)
@@ -29,7 +36,8 @@ def flux_effective_conductivity(T, edges, star1, side, length=1.0, area=1.0, dT=
     dTe = T[hi] - T[lo]
     energy = float((star1 * dTe * dTe).sum())
     return {
-        "k_eff": energy * length / (area * dT * dT),
+        "k_eff": energy * length / (area * dT * dT) if not neumann else
+                 (q_in if (side == 1).any() else q_out if (side == 2).any() else np.nan) * length / (area * dT),
         "q_in": q_in,
         "q_out": q_out,
         "energy": energy,

@@ -377,7 +377,8 @@ class Server:
     A request is a dict of device tensors: xyz [V,3] f64, tets [T,4] i32,
     kappa [E] f64 (optional), cracks [n,7] f64 (optional), bc_type [V] i8,
     bc_value [V] f64, neumann_f0 [V] f64 (optional), side [V] i8 (optional),
-    T_out [V] f64 (optional), and scalars length/area/dT.  The tensors are
+    T_out [V] f64 (optional), T0 [V] f64 (optional warm start), and scalars
+    length/area/dT.  The tensors are
     kept referenced until the request's result has been polled.
     """
 
@@ -414,6 +415,7 @@ class Server:
         r.side = _ptr(req.get("side"), torch.int8, V, "side")
         r.length, r.area, r.dT = (float(req.get(k, 1.0)) for k in ("length", "area", "dT"))
         r.T_out = _ptr(req.get("T_out"), torch.float64, V, "T_out")
+        r.T0 = _ptr(req.get("T0"), torch.float64, V, "T0")
         r.user_tag = int(user_tag)
         t = ctypes.c_uint64()
         self.ctx.check(self.lib.dec_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "dec_server_submit")

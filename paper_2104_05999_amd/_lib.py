@@ -71,21 +71,21 @@ class Request(ctypes.Structure):
         ("V", ctypes.c_int64), ("xyz", vp), ("T", ctypes.c_int64), ("tets", vp), ("kappa", vp),
         ("n_cracks", ctypes.c_int32), ("cracks", vp), ("bc_type", vp), ("bc_value", vp), ("neumann_f0", vp),
         ("side", vp), ("length", ctypes.c_double), ("area", ctypes.c_double), ("dT", ctypes.c_double),
-        ("T_out", vp), ("user_tag", ctypes.c_uint64),
+        ("T_out", vp), ("user_tag", ctypes.c_uint64), ("T0", vp),
     ]
 
 
 class Result(ctypes.Structure):
     _fields_ = [
         ("ticket", ctypes.c_uint64), ("user_tag", ctypes.c_uint64), ("status", ctypes.c_int32),
-        ("pad", ctypes.c_int32), ("k_eff", ctypes.c_double), ("q_in", ctypes.c_double), ("q_out", ctypes.c_double),
+        ("fp64_fallback", ctypes.c_int32), ("k_eff", ctypes.c_double), ("q_in", ctypes.c_double), ("q_out", ctypes.c_double),
         ("energy", ctypes.c_double), ("rel_residual", ctypes.c_double), ("inner_iterations", ctypes.c_int64),
         ("outer_iterations", ctypes.c_int64), ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
         ("t_start_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class ServerOpts(ctypes.Structure):

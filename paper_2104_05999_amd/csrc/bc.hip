@@ -324,6 +324,7 @@ void apply_bc_device(dec_mesh* m, const int8_t* bc_type, const double* bc_value,
     unsigned long long h[2];
     std::memcpy(h, ctx->readback(npin.p, sizeof(h)), sizeof(h));
     m->n_pinned = (int64_t)h[0];
+    m->neumann = f0 != nullptr;
     m->diag_positive = h[1] == 0;
     m->bc_ready = true;
     m->fsai.ready = false;

@@ -4,15 +4,22 @@
 // elimination is the heat leaving v's dual cell, so
 //     Q_in = sum over inflow-face vertices of (L T)_v,
 //     Q_out = -sum over outflow-face vertices of (L T)_v,
-// and the dissipated energy E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at
-// the exact solution; k_eff = E length / (area dT^2).  Deterministic block
-// partials.
+// and, without a Neumann load, the dissipated energy
+// E = sum_e *1_e (T_hi - T_lo)^2 equals Q_in dT at the exact solution, so
+// k_eff = E length / (area dT^2), which is second order in the solution's
+// error; with a Neumann load the energy also holds the work of the
+// prescribed fluxes, and k_eff = Q length / (area dT), the flux density
+// itself through a Dirichlet side: Q = Q_in when inflow vertices are marked,
+// else Q_out.  Deterministic block partials.
 #include <climits>
 #include <cmath>
 
 #include "solver.h"
 
 namespace {
+
+// Sums of k_flux: Q_in, Q_out, energy, inflow vertices, outflow vertices.
+constexpr int FLUX_SUMS = 5;
 
 // Q_in / Q_out from the rows of the two Dirichlet faces only (side != 0);
 // the energy edge by edge (coalesced over the edge arrays).  Partials per
@@ -24,13 +31,15 @@ __global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, int64_t E, const int3
                                                 double* __restrict__ edge_flux, double* __restrict__ partials,
                                                 double* __restrict__ out, unsigned* __restrict__ counter) {
     __shared__ double lds[BLOCK / 64];
-    double qin = 0.0, qout = 0.0, en = 0.0;
+    double qin = 0.0, qout = 0.0, en = 0.0, nin = 0.0, nout = 0.0;
     if (side) {
         int64_t i0, i1;
         block_range(V, &i0, &i1);
         for (int64_t v = i0 + threadIdx.x; v < i1; v += BLOCK) {
             const int8_t sd = side[v];
             if (sd != 1 && sd != 2) continue;
+            nin += sd == 1;
+            nout += sd == 2;
             const double tv = T[v];
             double o = 0.0;
             for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
@@ -56,24 +65,17 @@ __global__ __launch_bounds__(BLOCK) void k_flux(int64_t V, int64_t E, const int3
         }
     }
     const int G = gridDim.x;
-    const double a = block_sum(qin, lds);
-    const double b = block_sum(qout, lds);
-    const double c = block_sum(en, lds);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = a;
-        partials[G + blockIdx.x] = b;
-        partials[2 * G + blockIdx.x] = c;
+    const double in[FLUX_SUMS] = {qin, qout, en, nin, nout};
+    for (int k = 0; k < FLUX_SUMS; ++k) {
+        const double t = block_sum(in[k], lds);
+        if (threadIdx.x == 0) partials[k * G + blockIdx.x] = t;
     }
     if (last_block_arrived(counter)) {
-        const double ta = reduce_partials(partials, G, lds);
-        const double tb = reduce_partials(partials + G, G, lds);
-        const double tc = reduce_partials(partials + 2 * G, G, lds);
-        if (threadIdx.x == 0) {
-            out[0] = ta;
-            out[1] = tb;
-            out[2] = tc;
-            *counter = 0;
+        for (int k = 0; k < FLUX_SUMS; ++k) {
+            const double t = reduce_partials(partials + k * G, G, lds);
+            if (threadIdx.x == 0) out[k] = t;
         }
+        if (threadIdx.x == 0) *counter = 0;
     }
 }
 
@@ -206,20 +208,25 @@ extern "C" int dec_flux_effective_conductivity(dec_mesh* m, const double* T, con
         const int64_t want = ((m->V + BLOCK - 1) / BLOCK + 7) / 8 * 8;
         if (want < G) G = want;
         DBuf<double> part, out;
-        part.alloc(ctx, 3 * G);
-        out.alloc(ctx, 4);
+        part.alloc(ctx, FLUX_SUMS * G);
+        out.alloc(ctx, FLUX_SUMS);
         DBuf<unsigned> counter;
         counter.alloc(ctx, 1);
         counter.zero();
         hipLaunchKernelGGL(k_flux, dim3(G), dim3(BLOCK), 0, ctx->stream, m->V, m->E, m->row_ptr.p, m->col.p,
                            m->nz_edge.p, m->edges.p, m->star1.p, T, side, edge_flux_out, part.p, out.p, counter.p);
         HIP_CHECK(hipGetLastError());
-        double h[3];
+        double h[FLUX_SUMS];
         std::memcpy(h, ctx->readback(out.p, sizeof(h)), sizeof(h));
         if (q_in) *q_in = h[0];
         if (q_out) *q_out = h[1];
         if (energy) *energy = h[2];
-        if (k_eff) *k_eff = h[2] * length / (area * dT * dT);
+        if (k_eff) {
+            if (!m->neumann)
+                *k_eff = h[2] * length / (area * dT * dT);
+            else  // the flux density through a Dirichlet side given in `side`
+                *k_eff = (h[3] > 0 ? h[0] : h[4] > 0 ? h[1] : NAN) * length / (area * dT);
+        }
     } catch (const DecError& e) {
         ctx->last_error = e.msg;
         return e.code;

@@ -46,6 +46,7 @@ struct BSlot {
     const double* b;
     const uint8_t* fixed;
     const double* dval;
+    const double* x0;      // warm start of the request, or null
     double *x64, *r64, *p64, *q64;
     float *x32, *r32, *p32, *q32;
     double* part;       // [4 * nchunks]
@@ -57,7 +58,8 @@ struct BSlot {
     double stop_factor;  // inner rr_stop = stop_factor * (relative ? r.r : b.b)
     int32_t relative;
     int32_t pad2;
-    int64_t max_iter;
+    int64_t max_iter;    // iterations of the next inner solve
+    double undo_scale;   // bk_undo: x64 -= undo_scale * x32
 };
 
 struct BItem {
@@ -264,7 +266,8 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
 }
 
 // ---------------------------------------------------------------- refinement steps (FP64)
-// x0 on admission: Dirichlet values, 0 elsewhere; FP32 correction zero
+// x0 on admission: Dirichlet values on Dirichlet rows, 0 on pinned rows, the
+// request's warm start (or 0) elsewhere; FP32 correction zero
 __global__ void bk_admit_init(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
     __shared__ double lds[BLOCK / 64 + 1];
     ITEM_LOOP(it, n) {
@@ -274,7 +277,8 @@ __global__ void bk_admit_init(const BSlot* __restrict__ slots, const BItem* __re
         chunk_rows(S, item.chunk, &r0, &r1);
         double bb = 0.0;
         for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK) {
-            S.x64[i] = S.fixed[i] == 1 ? S.dval[i] : 0.0;
+            const uint8_t f = S.fixed[i];
+            S.x64[i] = f == 1 ? S.dval[i] : (f == 2 || !S.x0 ? 0.0 : S.x0[i]);
             if (S.x32) S.x32[i] = 0.0f;
             bb += S.b[i] * S.b[i];
         }
@@ -294,6 +298,19 @@ __global__ void bk_correct(const BSlot* __restrict__ slots, const BItem* __restr
         chunk_rows(S, item.chunk, &r0, &r1);
         for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK)
             S.x64[i] = S.x64[i] + scale * static_cast<double>(S.x32[i]);
+    }
+}
+
+// x64 -= undo_scale * x32: takes back a refinement correction that raised the residual
+__global__ void bk_undo(const BSlot* __restrict__ slots, const BItem* __restrict__ items, int n) {
+    ITEM_LOOP(it, n) {
+        const BItem item = items[it];
+        const BSlot& S = slots[item.slot];
+        if (!S.x32) continue;
+        int64_t r0, r1;
+        chunk_rows(S, item.chunk, &r0, &r1);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += BLOCK)
+            S.x64[i] = S.x64[i] - S.undo_scale * static_cast<double>(S.x32[i]);
     }
 }
 
@@ -433,7 +450,9 @@ struct ServeSlot {
     double t_submit = 0, t_admit = 0, t_start = 0;
     double rn_prev = 0;
     int64_t inner_total = 0, outer = 0;
-    bool fresh = true;  // no inner solve yet
+    bool fresh = true;      // no inner solve yet
+    bool fallback = false;  // a mixed-precision system that went on in FP64
+    bool broke = false;     // its last FP64 inner solve broke down
 };
 
 struct dec_server {
@@ -519,6 +538,7 @@ BSlot describe(dec_server* s, int k) {
     d.b = m->rhs.p;
     d.fixed = m->fixed.p;
     d.dval = m->bc_value.p;
+    d.x0 = sl.req.T0;
     d.x64 = sl.x64.p;
     d.r64 = sl.r64.p;
     d.p64 = sl.p64.p;
@@ -603,8 +623,12 @@ bool admit(dec_server* s, const ServeReq& q, int k) {
     return true;
 }
 
-// Upload descriptors and the item table for `ids` (all slots in the list), returning the item count.
-int build_items(dec_server* s, const std::vector<int>& ids, BItem* dst) {
+// The item table of the slots in `ids` into dst (room for `cap` items), returning the item
+// count; DEC_EBUDGET before anything is written when the table would not fit.
+int build_items(dec_server* s, const std::vector<int>& ids, BItem* dst, int64_t cap) {
+    int64_t total = 0;
+    for (int k : ids) total += s->slots[k].nchunks;
+    DEC_REQUIRE(total <= cap, DEC_EBUDGET, "work table full");
     int n = 0;
     for (int k : ids)
         for (int c = 0; c < s->slots[k].nchunks; ++c) dst[n++] = BItem{k, c};
@@ -661,6 +685,7 @@ void retire(dec_server* s, int k, int status, double rel) {
     r.rel_residual = rel;
     r.inner_iterations = sl.inner_total;
     r.outer_iterations = sl.outer;
+    r.fp64_fallback = sl.fallback ? 1 : 0;
     const int rc = dec_flux_effective_conductivity(m, sl.x64.p, sl.req.side, sl.req.length > 0 ? sl.req.length : 1.0,
                                                    sl.req.area > 0 ? sl.req.area : 1.0, sl.req.dT != 0 ? sl.req.dT : 1.0,
                                                    &r.k_eff, &r.q_in, &r.q_out, &r.energy, nullptr);
@@ -673,23 +698,60 @@ void retire(dec_server* s, int k, int status, double rel) {
     free_slot(s, sl);
 }
 
-// Refinement steps for the systems in `ids` (phase PH_OUTER): correction, FP64
-// residual, convergence decision, and the start of the next inner solve.
-void outer_steps(dec_server* s, const std::vector<int>& ids) {
-    if (ids.empty()) return;
-    const dim3 g(s->G), b(BLOCK);
-    for (int k : ids) HIP_CHECK(hipStreamWaitEvent(s->solve_stream, s->slots[k].ready, 0));
-    upload_slots(s);
-    const int n = build_items(s, ids, s->h_items);
-    DEC_REQUIRE(n <= s->max_items, DEC_EBUDGET, "work table full");
+// Items of `ids` into the auxiliary table and the ids into d_ids (host staging reused: the
+// caller synchronises the stream before building the next list).  Returns the item count.
+int stage_items(dec_server* s, const std::vector<int>& ids) {
+    const int n = build_items(s, ids, s->h_items, s->max_items);
     HIP_CHECK(hipMemcpyAsync(s->d_items_aux.p, s->h_items, n * sizeof(BItem), hipMemcpyHostToDevice, s->solve_stream));
     for (size_t i = 0; i < ids.size(); ++i) s->h_ids[i] = ids[i];
     HIP_CHECK(hipMemcpyAsync(s->d_ids.p, s->h_ids, ids.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                              s->solve_stream));
-    // fresh systems: x0 and b.b first
+    return n;
+}
+
+void read_states(dec_server* s) {
+    const int ns = (int)s->slots.size();
+    HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost, s->solve_stream));
+    HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+}
+
+void to_fp64(dec_server* s, ServeSlot& sl) {
+    sl.mode = DEC_PREC_FP64;
+    sl.fallback = true;
+    sl.p64.alloc(&s->setup_ctx, sl.mesh->V);
+    sl.q64.alloc(&s->setup_ctx, sl.mesh->V);
+}
+
+// Refinement steps for the systems in `ids` (phase PH_OUTER), the steps of the
+// single-system refinement loop: an FP32 inner solve that did not converge is
+// not applied and the system goes on in FP64; otherwise its correction is
+// applied, the FP64 residual taken, and the system retires when it meets the
+// tolerance, fails on a non-finite residual, a broken-down FP64 solve or the
+// iteration budget, or, when refinement stagnates (the residual not halved),
+// goes on in FP64 after taking back a correction that raised the residual.
+// Each system then starts its next inner solve: FP32 with at most
+// max(max_iters / 8, 64) iterations, FP64 with what is left.
+void outer_steps(dec_server* s, const std::vector<int>& ids) {
+    if (ids.empty()) return;
+    const dim3 g(s->G), b(BLOCK);
+    for (int k : ids) HIP_CHECK(hipStreamWaitEvent(s->solve_stream, s->slots[k].ready, 0));
     std::vector<int> fresh;
-    for (int k : ids)
-        if (s->slots[k].fresh) fresh.push_back(k);
+    for (int k : ids) {
+        ServeSlot& sl = s->slots[k];
+        if (sl.fresh) {
+            fresh.push_back(k);
+            continue;
+        }
+        const PcgScalars& in = s->h_st[3 * k];
+        sl.inner_total += in.iter;
+        ++sl.outer;
+        if (sl.mode == DEC_PREC_MIXED && in.done != PCG_CONVERGED)
+            to_fp64(s, sl);  // its correction is not applied (describe() drops the FP32 vectors)
+        else if (sl.mode == DEC_PREC_FP64)
+            sl.broke = in.done == PCG_BREAKDOWN;
+    }
+    upload_slots(s);
+    const int n = stage_items(s, ids);
     if (!fresh.empty()) {
         hipLaunchKernelGGL(bk_admit_init, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, n);
         hipLaunchKernelGGL(bk_fold_outer, dim3((int)ids.size()), b, 0, s->solve_stream, s->d_slots.p, s->d_ids.p,
@@ -700,70 +762,90 @@ void outer_steps(dec_server* s, const std::vector<int>& ids) {
     hipLaunchKernelGGL(bk_fold_outer, dim3((int)ids.size()), b, 0, s->solve_stream, s->d_slots.p, s->d_ids.p,
                        (int)ids.size(), 0);
     HIP_CHECK(hipGetLastError());
-    const int ns = (int)s->slots.size();
-    HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost,
-                             s->solve_stream));
-    HIP_CHECK(hipStreamSynchronize(s->solve_stream));
-    std::vector<int> again;
+    read_states(s);
+    std::vector<int> again, undo;
     for (int k : ids) {
         ServeSlot& sl = s->slots[k];
         const PcgScalars& out = s->h_st[3 * k + 2];
         const double bn = sqrt(out.aux), rn = sqrt(out.rr);
         const double rel = bn > 0 ? rn / bn : 0.0;
-        if (!sl.fresh) {
-            sl.inner_total += s->h_st[3 * k].iter;
-            ++sl.outer;
+        const bool was_fresh = sl.fresh;
+        sl.fresh = false;
+        if (!std::isfinite(rn) || !std::isfinite(bn)) {
+            retire(s, k, DEC_EBREAKDOWN, rel);
+            continue;
         }
         if (bn == 0.0 || rn <= s->opts.tol * bn) {
             retire(s, k, DEC_OK, rel);
+            continue;
+        }
+        if (sl.broke) {
+            retire(s, k, DEC_EBREAKDOWN, rel);
             continue;
         }
         if (sl.inner_total >= s->opts.max_iters || sl.outer >= 100) {
             retire(s, k, DEC_ENOTCONV, rel);
             continue;
         }
-        if (sl.mode == DEC_PREC_MIXED && !sl.fresh && rn > 0.5 * sl.rn_prev) {
-            // refinement stagnates in FP32: this system finishes in FP64
-            sl.mode = DEC_PREC_FP64;
-            sl.p64.alloc(&s->setup_ctx, sl.mesh->V);
-            sl.q64.alloc(&s->setup_ctx, sl.mesh->V);
+        if (sl.mode == DEC_PREC_MIXED && !was_fresh && rn > 0.5 * sl.rn_prev) {
+            // refinement stagnates in FP32: FP64 finishes, from the previous iterate when the
+            // last correction raised the residual
+            if (rn > sl.rn_prev) {
+                undo.push_back(k);
+                continue;  // rn_prev stays the residual of the restored iterate
+            }
+            to_fp64(s, sl);
         }
         sl.rn_prev = rn;
-        sl.fresh = false;
         again.push_back(k);
+    }
+    if (!undo.empty()) {
+        upload_slots(s);  // still mixed: the FP32 correction is in place
+        for (int k : undo) s->h_slots[k].undo_scale = s->slots[k].rn_prev;
+        HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, s->slots.size() * sizeof(BSlot), hipMemcpyHostToDevice,
+                                 s->solve_stream));
+        const int m = stage_items(s, undo);
+        hipLaunchKernelGGL(bk_undo, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, m);
+        hipLaunchKernelGGL(bk_residual, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, m);
+        hipLaunchKernelGGL(bk_fold_outer, dim3((int)undo.size()), b, 0, s->solve_stream, s->d_slots.p, s->d_ids.p,
+                           (int)undo.size(), 0);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipStreamSynchronize(s->solve_stream));  // before the staging area is reused
+        for (int k : undo) {
+            to_fp64(s, s->slots[k]);
+            again.push_back(k);
+        }
     }
     if (again.empty()) return;
     // start the next inner solves
     upload_slots(s);
     std::vector<int> by_mode[2];
     for (int k : again) by_mode[s->slots[k].mode == DEC_PREC_MIXED ? 1 : 0].push_back(k);
+    const int64_t cap32 = s->opts.max_iters / 8 > 64 ? s->opts.max_iters / 8 : 64;
     for (int prec = 0; prec < 2; ++prec) {
         if (by_mode[prec].empty()) continue;
         for (int k : by_mode[prec]) {
             ServeSlot& sl = s->slots[k];
             const PcgScalars& out = s->h_st[3 * k + 2];
-            const double bn = sqrt(out.aux), rn = sqrt(out.rr);
+            const double bn = sqrt(out.aux), rn = sl.rn_prev;
+            const int64_t left = s->opts.max_iters - sl.inner_total;
             if (prec == 1) {
                 double itol = s->opts.inner_tol;
                 if (s->opts.adaptive_final_inner) itol = fmax(itol, 0.5 * s->opts.tol * bn / rn);
                 if (itol >= 1.0) itol = 0.5;
                 s->h_slots[k].stop_factor = itol * itol;
                 s->h_slots[k].relative = 1;
+                s->h_slots[k].max_iter = left < cap32 ? left : cap32;
             } else {
                 s->h_slots[k].stop_factor = s->opts.tol * s->opts.tol;
                 s->h_slots[k].relative = 0;
+                s->h_slots[k].max_iter = left;
             }
-            (void)sl;
         }
         const int ns2 = (int)s->slots.size();
         HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, ns2 * sizeof(BSlot), hipMemcpyHostToDevice,
                                  s->solve_stream));
-        const int m = build_items(s, by_mode[prec], s->h_items);
-        HIP_CHECK(hipMemcpyAsync(s->d_items_aux.p, s->h_items, m * sizeof(BItem), hipMemcpyHostToDevice,
-                                 s->solve_stream));
-        for (size_t i = 0; i < by_mode[prec].size(); ++i) s->h_ids[i] = by_mode[prec][i];
-        HIP_CHECK(hipMemcpyAsync(s->d_ids.p, s->h_ids, by_mode[prec].size() * sizeof(int32_t),
-                                 hipMemcpyHostToDevice, s->solve_stream));
+        const int m = stage_items(s, by_mode[prec]);
         if (prec == 1)
             hipLaunchKernelGGL(bk_inner_start<float>, g, b, 0, s->solve_stream, s->d_slots.p, s->d_items_aux.p, m);
         else
@@ -894,11 +976,10 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
         bool launched = false;
         if (!inner[0].empty() || !inner[1].empty()) {
             upload_slots(s);
-            const int n64 = build_items(s, inner[0], s->h_items);
+            const int n64 = build_items(s, inner[0], s->h_items, s->max_items);
             HIP_CHECK(hipMemcpyAsync(s->d_items64.p, s->h_items, n64 * sizeof(BItem), hipMemcpyHostToDevice,
                                      s->solve_stream));
-            const int n32 = build_items(s, inner[1], s->h_items + n64);
-            DEC_REQUIRE(n64 + n32 <= s->max_items, DEC_EBUDGET, "work table full");
+            const int n32 = build_items(s, inner[1], s->h_items + n64, s->max_items - n64);
             HIP_CHECK(hipMemcpyAsync(s->d_items32.p, s->h_items + n64, n32 * sizeof(BItem), hipMemcpyHostToDevice,
                                      s->solve_stream));
             s->h_n[0] = n32;

@@ -74,7 +74,8 @@ def serve(ctx, reqs, budget=4 << 30, late=(), max_steps=20000, **opts):
 
 @pytest.mark.parametrize("precision", [1, 0])
 def test_served_results_match_oracle_and_are_the_same_alone(ctx, dev, precision):
-    specs = [(6, 5), (9, 12), (12, 20), (7, 0), (10, 8)]
+    # sizes from 1 to 18 work-table chunks of 2048 rows (n = 24: 8 chunks, n = 32: 18)
+    specs = [(6, 5), (9, 12), (12, 20), (7, 0), (10, 8), (24, 30), (32, 40)]
     built = [make_request(n, c, k, dev) for k, (n, c) in enumerate(specs)]
     reqs = [b[0] for b in built]
     mixed, peak = serve(ctx, reqs, late=(3, 4), tol=1e-12, precision=precision)
@@ -85,11 +86,11 @@ def test_served_results_match_oracle_and_are_the_same_alone(ctx, dev, precision)
         assert res["rel_residual"] <= 1e-12
         x_ref, f_ref = oracle_reference(host)
         T = req["T_out"].cpu().numpy()
-        assert np.linalg.norm(T - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+        assert np.linalg.norm(T - x_ref) <= 1e-10 * np.linalg.norm(x_ref), tag
         assert abs(res["k_eff"] - f_ref["k_eff"]) <= 1e-9 * f_ref["k_eff"]
         assert res["t_submit_ms"] <= res["t_admit_ms"] <= res["t_start_ms"] <= res["t_finish_ms"]
     # each request alone in a fresh server: bit-for-bit the same
-    for tag in (0, 2, 4):
+    for tag in (0, 2, 4, 5, 6):
         req, _ = built[tag]
         T_mix = req["T_out"].clone()
         req["T_out"].zero_()
@@ -180,11 +181,60 @@ def test_served_neumann_request_matches_oracle(ctx, dev, precision):
     g = O.neumann_load(xyz, tets, O.boundary_faces(tets), bt, f0)
     A, b, _ = O.apply_bc(O.assemble(V, E, star)[0], bt, np.zeros(V), E, star, neumann=g)
     ref = O.pcg(A, b, precond="jacobi", tol=1e-14, stagnation=50)
+    side = np.where(i == n, 2, 0).astype(np.int8)
+    of = O.flux_effective_conductivity(ref.x, E, star, side, neumann=True)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
     req = dict(xyz=t(xyz), tets=t(tets), kappa=t(kappa), cracks=t(cracks), bc_type=t(bt), bc_value=t(np.zeros(V)),
-               neumann_f0=t(f0), T_out=torch.zeros(V, dtype=torch.float64, device=dev))
+               neumann_f0=t(f0), side=t(side), T_out=torch.zeros(V, dtype=torch.float64, device=dev))
     other, _ = make_request(6, 3, 40, dev)
     out, _ = serve(ctx, [other, req], tol=1e-12, precision=precision)
     assert out[1]["status"] == 0 and out[0]["status"] == 0
     T = req["T_out"].cpu().numpy()
     assert np.linalg.norm(T - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    # k_eff: the flux density through the Dirichlet side x = 1 (a Neumann load is present)
+    assert abs(out[1]["k_eff"] - of["k_eff"]) <= 1e-9 * abs(of["k_eff"])
+
+
+@pytest.mark.parametrize("how", ["cap", "stagnation"])
+def test_served_fp32_fallback_matches_oracle(ctx, dev, how):
+    """The refinement loop of a served system follows the single-system one.  'cap': with
+    max_iters 400 an FP32 solve may take max(400 / 8, 64) = 64 iterations, too few for 1e-5 on
+    this system: it is not applied and FP64 finishes.  'stagnation': with inner_tol 0.9 one
+    refinement step cannot halve the residual, so FP64 finishes.  Either way the result is the
+    oracle's solution and the fallback is reported, as dec_solve reports it on the same system."""
+    req, host = make_request(24, 30, 60, dev)
+    opts = dict(max_iters=400) if how == "cap" else dict(inner_tol=0.9)
+    out, _ = serve(ctx, [req], tol=1e-12, precision=1, **opts)
+    res = out[0]
+    assert res["status"] == 0 and res["fp64_fallback"] == 1, res
+    x_ref, f_ref = oracle_reference(host)
+    T = req["T_out"].cpu().numpy()
+    assert np.linalg.norm(T - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    assert abs(res["k_eff"] - f_ref["k_eff"]) <= 1e-9 * f_ref["k_eff"]
+    m = ctx.mesh(req["xyz"], req["tets"])
+    m.hodge1(req["kappa"], req["cracks"], want_cut=False, want_star=False)
+    m.assemble()
+    m.apply_bc(req["bc_type"], req["bc_value"], want_rhs=False)
+    Ts, st, rc = m.solve(tol=1e-12, precision=1, **opts)
+    assert rc == 0 and st["fp64_fallback"] == 1, st
+    assert np.linalg.norm(Ts.cpu().numpy() - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    m.close()
+
+
+def test_served_warm_start(ctx, dev):
+    """A request warm-started from its own solution (dec_request.T0) retires at its first
+    refinement step with no inner iteration; one started from a perturbed solution converges to
+    the same solution (tolerance) in fewer iterations than a cold start."""
+    req, host = make_request(16, 12, 70, dev)
+    cold, _ = serve(ctx, [req], tol=1e-12)
+    T = req["T_out"].clone()
+    hot = dict(req, T0=T.clone(), T_out=torch.zeros_like(T))
+    out, _ = serve(ctx, [hot], tol=1e-12)
+    assert out[0]["status"] == 0 and out[0]["inner_iterations"] == 0 and torch.equal(hot["T_out"], T)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    near = dict(req, T0=T + 1e-3 * torch.randn(T.shape, generator=g, dtype=torch.float64).to(dev),
+                T_out=torch.zeros_like(T))
+    out2, _ = serve(ctx, [near], tol=1e-12)
+    assert out2[0]["status"] == 0 and out2[0]["inner_iterations"] < cold[0]["inner_iterations"]
+    x_ref, _ = oracle_reference(host)
+    assert np.linalg.norm(near["T_out"].cpu().numpy() - x_ref) <= 1e-10 * np.linalg.norm(x_ref)

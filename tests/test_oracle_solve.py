@@ -246,6 +246,38 @@ def test_neumann_inflow_linear_solution():
     A, b, _ = O.apply_bc(O.assemble(V, E, s)[0], bt, bv, E, s, neumann=g)
     res = O.pcg(A, b, precond="jacobi", tol=1e-13)
     assert np.abs(res.x - q * (1 - i / n)).max() < 1e-10
+    # k_eff with a Neumann load is the flux density through the Dirichlet side (x = 1, the only
+    # one) over the gradient: q through the unit face over dT = q, i.e. 1
+    side = np.where(i == n, 2, 0).astype(np.int8)
+    f = O.flux_effective_conductivity(res.x, E, s, side, dT=q, neumann=True)
+    assert abs(f["q_out"] - q) < 1e-9 and abs(f["k_eff"] - 1.0) < 1e-9
+
+
+def test_keff_with_a_neumann_load_is_the_prescribed_flux_through_the_dirichlet_side():
+    """Lognormal conductivity, T = 1 / 0 on x = 0 / 1, outward flux densities prescribed on y = 0
+    and z = 1.  L has zero row sums, so the balances of all vertices add up to zero: the flux
+    leaving through the two Dirichlet sides, Q_out - Q_in, equals the prescribed inflow
+    -sum(g).  k_eff is Q_in length / (area dT) (the energy form, which also holds the work of the
+    prescribed fluxes, differs), and Q_out without a marked inflow face."""
+    n = 6
+    xyz, tets = W.kuhn_cube(n)
+    V = len(xyz)
+    E = O.edges_of(tets, V)
+    s = O.hodge1(xyz, tets, E, kappa=W.lognormal_kappa(len(E), 1.0, 9))
+    i, j, k = W.lattice_index(n)
+    bt0, bv, side = W.x_sides(n)
+    bt = np.where(bt0 == 1, 1, np.where((j == 0) | (k == n), 2, 0)).astype(np.int8)
+    f0 = np.where(bt == 2, np.where(j == 0, -0.8, 0.3), 0.0)
+    g = O.neumann_load(xyz, tets, O.boundary_faces(tets), bt, f0)
+    A, b, pinned = O.apply_bc(O.assemble(V, E, s)[0], bt, bv, E, s, neumann=g)
+    assert not pinned.any()
+    x = O.pcg(A, b, precond="jacobi", tol=1e-14, stagnation=50).x
+    f = O.flux_effective_conductivity(x, E, s, side, neumann=True)
+    assert abs((f["q_out"] - f["q_in"]) + g.sum()) < 1e-10
+    assert f["k_eff"] == f["q_in"] and abs(f["energy"] - f["q_in"]) > 1e-3
+    f2 = O.flux_effective_conductivity(x, E, s, np.where(side == 2, 2, 0), neumann=True)
+    assert f2["k_eff"] == f2["q_out"] == f["q_out"]
+    assert np.isnan(O.flux_effective_conductivity(x, E, s, np.zeros(V, np.int8), neumann=True)["k_eff"])
 
 
 def test_neumann_faces_next_to_dirichlet():
