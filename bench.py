@@ -42,17 +42,18 @@ def spmv_bytes(V, nnz, s_v):
     return nnz * (s_v + 4) + 4 * (V + 1) + 2 * V * s_v
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_fp64_kuhn128_traffic.txt")
-DUAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_diff_fp64_kuhn128_tets_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_fp64_kuhn{n}_traffic.txt")
+DUAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_diff_fp64_kuhn{n}_tets_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("sell.h", "common.h")]
 
 
 def measured_traffic(n, path=TRAFFIC_FILE):
-    """HBM bytes per SpMV launch from the committed counter summary, or None when the kernel
-    sources changed since the counters were taken (or for another mesh size)."""
+    """HBM bytes per SpMV launch from the committed counter summary of this mesh size, or None when
+    there is none or the kernel sources changed since the counters were taken."""
     import hashlib
 
-    if n != 128 or not os.path.exists(path):
+    path = path.format(n=n)
+    if not os.path.exists(path):
         return None
     kv = dict(ln.strip().split("=", 1) for ln in open(path) if "=" in ln and not ln.startswith("#"))
     h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
@@ -116,7 +117,12 @@ def precision_preconditioner_table(ctx, inp, n):
                    "fp64_fallback": st["fp64_fallback"], "k_eff": f["k_eff"]}
             if ref is not None:
                 meta, vs, xs = ref
-                row["max_sampled_error_vs_reference"] = float(np.abs(T[vs].cpu().numpy() - xs).max() / meta["x_norm"])
+                # ||x_S - x*_S||_2 / ||x*_S||_2 on the stored 65,536-vertex sample, beside the same
+                # measure of the oracle's own solve stopped at the same tolerance
+                row["sampled_error_vs_reference"] = float(np.linalg.norm(T[vs].cpu().numpy() - xs) / np.linalg.norm(xs))
+                # the oracle's FP64 Jacobi PCG, or its FP64 refinement around FP32 Jacobi PCG, at 1e-10
+                key = "ir_sample_error_vs_ref" if pname == "mixed" else "loose_sample_error_vs_ref"
+                row["oracle_same_method_sampled_error"] = meta.get(key)
                 row["k_eff_rel_error"] = abs(f["k_eff"] - meta["k_eff"]) / meta["k_eff"]
             table[f"{pname}_{cname}"] = row
     mesh.close()
@@ -220,6 +226,40 @@ def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96,
             "outer_iterations": outer, "failed": status_bad}, keff
 
 
+SERVE_GOLDEN = os.path.join(ROOT, "tests", "golden", "serve512_every16")
+
+
+def stream_oracle_errors(reqs, keff, mixed):
+    """Errors of the results now in the requests' T_out against the stored oracle values of requests
+    0, 16, ..., 496 (||x_S - x*_S||_2 / ||x*_S||_2 on each request's vertex sample), beside the same
+    measure of the oracle's own 1e-10 solves (FP64 Jacobi PCG; with `mixed`, the larger of that and
+    its FP64 refinement around FP32 Jacobi PCG); None without the stored values or for another stream."""
+    import torch
+
+    if not os.path.exists(SERVE_GOLDEN + ".npz") or len(reqs) != 512:
+        return None
+    meta = json.load(open(SERVE_GOLDEN + ".json"))
+    arr = np.load(SERVE_GOLDEN + ".npz")
+
+    def ref_error(r):  # FP64: the oracle's FP64 PCG; mixed: the larger of its two errors at 1e-10
+        return max(r["loose_sample_error_vs_ref"], r["ir_sample_error_vs_ref"]) if mixed else r["loose_sample_error_vs_ref"]
+
+    worst, worst_ratio, worst_k, rows = 0.0, 0.0, 0.0, 0
+    for r in meta["requests"]:
+        q = r["index"]
+        worst_k = max(worst_k, abs(keff[q] - r["k_eff"]) / r["k_eff"])
+        T = reqs[q]["T_out"]
+        vs = torch.as_tensor(arr[f"vertex_sample_{q}"], device=T.device)
+        xs = arr[f"x_sample_{q}"]
+        e = float(np.linalg.norm(T[vs].cpu().numpy() - xs) / np.linalg.norm(xs))
+        worst = max(worst, e)
+        worst_ratio = max(worst_ratio, e / ref_error(r))
+        rows += 1
+    return {"requests_checked": rows, "worst_sampled_error_vs_reference": worst,
+            "worst_ratio_to_oracle_tol_solve_error": round(worst_ratio, 3), "worst_k_eff_rel_error": worst_k,
+            "oracle_tol_solve_worst_sampled_error": max(ref_error(r) for r in meta["requests"])}
+
+
 def serving_benchmark(ctx, dev, count):
     """Saturated throughput (all requests queued at t = 0) and latency under Poisson arrivals at
     0.8 x the FP64 baseline's saturated rate, plain FP64 one-at-a-time vs mixed batched (and, saturated,
@@ -231,7 +271,9 @@ def serving_benchmark(ctx, dev, count):
     print(f"[bench] serving: {count} requests generated", file=sys.stderr, flush=True)
     f64_sat, k64 = serve_fp64_sequential(ctx, reqs, zero)
     print(f"[bench] serving fp64 saturated: {f64_sat}", file=sys.stderr, flush=True)
+    f64_err = stream_oracle_errors(reqs, k64, False)
     mix_sat, kmix = serve_batched(ctx, reqs, zero, dec.DEC_PREC_MIXED)
+    mix_err = stream_oracle_errors(reqs, kmix, True)
     print(f"[bench] serving mixed saturated: {mix_sat}", file=sys.stderr, flush=True)
     # the same server in FP64: separates what batching gives from what FP32 inner solves give
     b64_sat, kb64 = serve_batched(ctx, reqs, zero, dec.DEC_PREC_FP64)
@@ -254,6 +296,7 @@ def serving_benchmark(ctx, dev, count):
         "speedup_mixed_vs_fp64_batched": round(mix_sat["solves_per_sec"] / b64_sat["solves_per_sec"], 3),
         "max_rel_keff_diff_fp64_batched_vs_sequential": max(abs(a - b) / abs(b) for a, b in zip(kb64, k64)),
         "max_rel_keff_diff_mixed_vs_fp64": dk,
+        "oracle_errors": {"fp64_sequential": f64_err, "mixed_batched": mix_err},
     }
 
 
@@ -667,6 +710,36 @@ def cpu_baseline(n=80):
     }
 
 
+def spmv_roofline(st, n, kernel="k_sell<double, MODE_DOT> (sliced-ELL SpMV + p.Ap partials)"):
+    """The roofline object of a profiled solve's SpMV launches (HIP events on the solve stream)."""
+    per, launches, ms = st["spmv_bytes"], st["spmv_launches"], st["spmv_ms"]
+    achieved = per * launches / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(n), "kernel": kernel,
+            "bytes_per_launch": per, "mean_launch_us": round(1e3 * ms / launches, 3), "launches": launches}
+
+
+def roofline_256(ctx, dev, profile=8):
+    """The dominant kernel where its working set cannot stay in the 256 MB Infinity Cache: the same
+    recipe (lognormal kappa sigma 1 seed 1, 200 penny cracks seed 2, T = 1 / 0 on x = 0 / 1) on the
+    256^3 Kuhn cube (16,974,593 vertices), one warm-up solve (tuning) and one profiled FP64 Jacobi
+    solve to 1e-10; measured outside the timed steps."""
+    inp = make_inputs(256, dev)
+    mesh = ctx.mesh(inp["xyz"], inp["tets"])
+    mesh.hodge1(inp["kappa"], inp["cracks"], want_cut=False, want_star=False)
+    mesh.assemble()
+    mesh.apply_bc(inp["bt"], inp["bv"], want_rhs=False)
+    mesh.solve(tol=1e-10)
+    T, st, rc = mesh.solve(tol=1e-10, profile=profile)
+    out = spmv_roofline(st, 256)
+    out.update({"workload": "kuhn256_lognormal1_cracks200_fp64_jacobi", "V": mesh.V, "spmv_nnz": st["spmv_nnz"],
+                "pcg_iterations": st["iterations"], "solve_ms": round(st["solve_ms"], 3), "status": rc,
+                "column_bytes": round((st["spmv_bytes"] - 20 * mesh.V - 4) / st["spmv_nnz"] - 8, 3)})
+    mesh.close()
+    del inp
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -681,6 +754,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--serve-requests", type=int, default=512, help="serving stream length (0: skip)")
+    ap.add_argument("--no-roofline-256", dest="roofline_256", action="store_false",
+                    help="skip the SpMV roofline on the 256^3 mesh (outside the timed steps)")
     ap.add_argument("--cracking", action="store_true",
                     help="instead of the default line: the deterministic and Monte Carlo cracking processes")
     ap.add_argument("--growth-n", type=int, default=256)
@@ -776,12 +851,12 @@ def main():
         "status": rc,
     }
     if launches:
-        achieved = per * launches / (spmv_ms / 1e3) / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(args.n),
-                           "kernel": "k_sell<double, MODE_DOT> (sliced-ELL SpMV + p.Ap partials)",
-                           "bytes_per_launch": per, "mean_launch_us": round(1e3 * spmv_ms / launches, 3),
-                           "launches": launches}
+        agg = {"spmv_bytes": per, "spmv_launches": launches, "spmv_ms": spmv_ms}
+        out["roofline"] = spmv_roofline(agg, args.n)
+        out["roofline"]["column_bytes"] = round((per - 20 * counts["V"] - 4) / st["spmv_nnz"] - 8, 3)
+    if args.roofline_256 and profile:
+        out["roofline_256"] = roofline_256(ctx, dev, profile)
+        print(f"[bench] roofline_256: {out['roofline_256']}", file=sys.stderr, flush=True)
     if not args.no_extras:
         out["mixed_vs_fp64"] = precision_preconditioner_table(ctx, inp, args.n)
     if args.copy_probe_mib:

@@ -3,7 +3,9 @@
 // 2.3): L_ij = -*1_e, L_ii = sum of *1_e over the row's edges in ascending
 // column order.  No atomics, so the values are deterministic.  The FP32 copy and the sliced-ELL copies are refreshed
 // from the FP64 CSR values.
-#include "common.h"
+#include <climits>
+
+#include "sell.h"
 
 struct SolveCache;
 void clear_graphs(SolveCache* c);
@@ -124,10 +126,45 @@ __global__ void k_sell_values(int64_t n, const int32_t* __restrict__ ssrc, const
     }
 }
 
-// Column offsets col - row as int16 in the same slots; flags an offset that does not fit.
-__global__ void k_sell_offsets(int64_t nslices, const int64_t* __restrict__ sptr, const int32_t* __restrict__ scol,
-                               int16_t* __restrict__ dcol, unsigned* __restrict__ wide) {
-    bool over = false;
+// The column offsets col - row of a sliced-ELL matrix (rows past V count as
+// offset 0), in one pass: as int16 in the same slots (with a flag when one
+// does not fit), and as the set of distinct values, collected in an
+// open-addressing hash set of OSET_CAP slots: each workgroup first gathers
+// its own in LDS, then adds them to the global set, so the global atomics
+// number (workgroups x distinct offsets).  flags: [0] an offset beyond 16 bits,
+// [1] distinct offsets, [2] more than OTAB_MAX of them (in one workgroup or
+// in all).
+constexpr int OSET_CAP = 1024;
+constexpr int32_t OSET_EMPTY = INT32_MIN;
+
+__device__ __forceinline__ uint32_t oset_hash(int32_t d) { return (static_cast<uint32_t>(d) * 2654435761u) >> 22; }
+
+// insert d into a set of OSET_CAP slots; returns 1 when this call added it, 0 when present,
+// -1 when the set is full
+template <bool SHARED>
+__device__ __forceinline__ int oset_insert(int32_t* set, int32_t d) {
+    uint32_t h = oset_hash(d);
+    for (int probe = 0; probe < OSET_CAP; ++probe, h = (h + 1) & (OSET_CAP - 1)) {
+        int32_t cur = SHARED ? set[h] : coherent_load(set + h);
+        if (cur == d) return 0;
+        if (cur == OSET_EMPTY) {
+            cur = atomicCAS(set + h, OSET_EMPTY, d);
+            if (cur == OSET_EMPTY) return 1;
+            if (cur == d) return 0;
+        }
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sell_offsets(int64_t V, int64_t nslices, const int64_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ scol, int16_t* __restrict__ dcol,
+                                                        int32_t* __restrict__ gset, unsigned* __restrict__ flags) {
+    __shared__ int32_t lset[OSET_CAP];
+    __shared__ int lcount;
+    for (int t = threadIdx.x; t < OSET_CAP; t += BLOCK) lset[t] = OSET_EMPTY;
+    if (threadIdx.x == 0) lcount = 0;
+    __syncthreads();
+    bool over16 = false;
     RANGE_LOOP(i, nslices * SELL_C) {
         const int64_t s = i / SELL_C;
         const int lane = static_cast<int>(i % SELL_C);
@@ -135,12 +172,86 @@ __global__ void k_sell_offsets(int64_t nslices, const int64_t* __restrict__ sptr
         for (int j = 0; j < width; ++j) {
             const int64_t idx = sell_index(sptr[s], width, j, lane);
             const int64_t d = static_cast<int64_t>(scol[idx]) - i;  // row i = s * SELL_C + lane
-            over |= d < INT16_MIN || d > INT16_MAX;
+            over16 |= d < INT16_MIN || d > INT16_MAX;
             dcol[idx] = static_cast<int16_t>(d);  // unused when any offset is out of range
+            if (lcount > OTAB_MAX) continue;  // too many for a table already
+            const int r = oset_insert<true>(lset, i < V ? static_cast<int32_t>(d) : 0);
+            if (r != 0) atomicAdd(&lcount, r > 0 ? 1 : OTAB_MAX + 1);
         }
     }
-    if (over) atomicOr(wide, 1u);
+    if (over16) atomicOr(flags, 1u);
+    __syncthreads();
+    if (lcount > OTAB_MAX) {
+        if (threadIdx.x == 0) atomicOr(flags + 2, 1u);
+        return;
+    }
+    for (int t = threadIdx.x; t < OSET_CAP; t += BLOCK) {
+        if (lset[t] == OSET_EMPTY) continue;
+        const int r = oset_insert<false>(gset, lset[t]);
+        if (r > 0) atomicAdd(flags + 1, 1u);
+        if (r < 0) atomicOr(flags + 2, 1u);
+    }
 }
+
+// One workgroup of OSET_CAP threads: the set's values in ascending order into
+// otab (bitonic sort in LDS; the empty slots, INT32_MIN, sort first), when
+// there are at most OTAB_MAX of them.
+__global__ __launch_bounds__(OSET_CAP) void k_offset_sort(const int32_t* __restrict__ gset,
+                                                          const unsigned* __restrict__ flags,
+                                                          int32_t* __restrict__ otab) {
+    __shared__ int32_t v[OSET_CAP];
+    const unsigned count = flags[1];
+    if (flags[2] || count > (unsigned)OTAB_MAX) return;
+    const int t = threadIdx.x;
+    v[t] = gset[t];
+    __syncthreads();
+    for (int k = 2; k <= OSET_CAP; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int p = t ^ j;
+            if (p > t) {
+                const bool up = (t & k) == 0;
+                const int32_t a = v[t], b = v[p];
+                if ((a > b) == up) {
+                    v[t] = b;
+                    v[p] = a;
+                }
+            }
+            __syncthreads();
+        }
+    if (t < (int)count) otab[t] = v[OSET_CAP - count + t];
+}
+
+// The index of col - row in the ascending offset table (staged in LDS), per
+// stored entry, when the table was built.
+__global__ __launch_bounds__(BLOCK) void k_offset_index(int64_t V, int64_t nslices, const int64_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ scol, const int32_t* __restrict__ otab,
+                                                        const unsigned* __restrict__ flags, uint8_t* __restrict__ tcol) {
+    __shared__ int32_t tab[OTAB_MAX];
+    const unsigned count = flags[1];
+    if (flags[2] || count > (unsigned)OTAB_MAX) return;
+    const int ntab = static_cast<int>(count);
+    stage_offsets(otab, ntab, tab);
+    RANGE_LOOP(i, nslices * SELL_C) {
+        const int64_t s = i / SELL_C;
+        const int lane = static_cast<int>(i % SELL_C);
+        const int width = static_cast<int>((sptr[s + 1] - sptr[s]) / SELL_C);
+        for (int j = 0; j < width; ++j) {
+            const int64_t idx = sell_index(sptr[s], width, j, lane);
+            const int32_t d = i < V ? scol[idx] - static_cast<int32_t>(i) : 0;
+            int lo = 0, hi = ntab - 1;  // d is in the table
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (tab[mid] < d)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            tcol[idx] = static_cast<uint8_t>(lo);
+        }
+    }
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t* __restrict__ out) { GRID_STRIDE_LOOP(i, n) out[i] = v; }
 
 void build_sell_pattern(dec_mesh* m) {
     dec_ctx* ctx = m->ctx;
@@ -165,23 +276,44 @@ void build_sell_pattern(dec_mesh* m) {
     hipLaunchKernelGGL(k_sell_fill, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, m->V,
                        S.nslices, m->row_ptr.p, m->col.p, m->nz_edge.p, geo, S.ptr.p, S.col.p, S.src.p);
     HIP_CHECK(hipGetLastError());
-    build_sell_offsets(ctx, S);
+    build_sell_offsets(ctx, S, m->V);
 }
 
 }  // namespace
 
-void build_sell_offsets(dec_ctx* ctx, SellMatrix& S) {
+void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V) {
     S.dcol = DBuf<int16_t>();
+    S.tcol = DBuf<uint8_t>();
+    S.otab = DBuf<int32_t>();
+    S.ntab = 0;
     if (S.entries == 0) return;
+    hipStream_t st = ctx->stream;
     DBuf<int16_t> d;
     d.alloc(ctx, S.entries);
-    DBuf<unsigned> wide;
-    wide.alloc(ctx, 1);
-    wide.zero();
-    hipLaunchKernelGGL(k_sell_offsets, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, ctx->stream, S.nslices,
-                       S.ptr.p, S.col.p, d.p, wide.p);
+    DBuf<uint8_t> t;
+    t.alloc(ctx, S.entries);
+    DBuf<int32_t> tab, gset;
+    tab.alloc(ctx, OTAB_MAX);
+    gset.alloc(ctx, OSET_CAP);
+    DBuf<unsigned> flags;  // see k_sell_offsets
+    flags.alloc(ctx, 3);
+    flags.zero();
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(OSET_CAP)), dim3(BLOCK), 0, st, (int64_t)OSET_CAP, OSET_EMPTY, gset.p);
+    const unsigned g = grid_xcd(S.nslices * SELL_C);
+    hipLaunchKernelGGL(k_sell_offsets, dim3(g), dim3(BLOCK), 0, st, V, S.nslices, S.ptr.p, S.col.p, d.p, gset.p,
+                       flags.p);
+    hipLaunchKernelGGL(k_offset_sort, dim3(1), dim3(OSET_CAP), 0, st, gset.p, flags.p, tab.p);
+    hipLaunchKernelGGL(k_offset_index, dim3(g), dim3(BLOCK), 0, st, V, S.nslices, S.ptr.p, S.col.p, tab.p, flags.p,
+                       t.p);
     HIP_CHECK(hipGetLastError());
-    if (*static_cast<unsigned*>(ctx->readback(wide.p, sizeof(unsigned))) == 0) S.dcol = std::move(d);
+    unsigned h[3];
+    std::memcpy(h, ctx->readback(flags.p, sizeof(h)), sizeof(h));  // the one synchronisation
+    if (h[0] == 0) S.dcol = std::move(d);
+    if (h[2] == 0 && h[1] <= (unsigned)OTAB_MAX) {
+        S.tcol = std::move(t);
+        S.otab = std::move(tab);
+        S.ntab = (int32_t)h[1];
+    }
 }
 
 // Copy the CSR values into the sliced-ELL layout (after assembly or boundary edits).

@@ -49,8 +49,9 @@ struct dec_ctx {
     int num_cus = 256;
     int num_xcds = 8;
     int live_children = 0;  // meshes and servers created on this context and not yet destroyed
-    // SpMV variant (unroll, non-temporal) chosen per (precision, V, slices, stored entries)
-    std::map<std::array<int64_t, 4>, std::pair<int, int>> spmv_tune;
+    // SpMV variant (unroll, non-temporal loads, column format) chosen per (kind of matrix and
+    // precision, V, slices, stored entries)
+    std::map<std::array<int64_t, 4>, std::array<int, 3>> spmv_tune;
     // small pinned staging area for scalar read-backs
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
@@ -138,11 +139,17 @@ struct SellMatrix {
     DBuf<double> excess64;  // [V] row excess for the difference-form product (empty: plain form)
     DBuf<float> excess32;   // [V]
     DBuf<int16_t> dcol;     // [entries] col - row, kept only when every offset fits in 16 bits
+    DBuf<uint8_t> tcol;     // [entries] index into otab of col - row (0 past the last row), kept only
+                            // when the entries take at most 256 distinct offsets
+    DBuf<int32_t> otab;     // [ntab] those offsets, ascending
+    int32_t ntab = 0;
 };
 
 // Fill S.dcol from S.col (rows of V, padding included), or leave it empty when
-// some column lies 2^15 or more from its row.  Synchronises the stream.
-void build_sell_offsets(dec_ctx* ctx, SellMatrix& S);
+// some column lies 2^15 or more from its row; and S.tcol / S.otab when the
+// offsets take at most 256 distinct values (rows past V count as offset 0).
+// Synchronises the stream.
+void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V);
 
 // Lower-triangular FSAI factor G (CSR) and its transpose (CSR of G^T).
 struct FsaiFactor {
@@ -229,6 +236,7 @@ struct dec_mesh {
     DBuf<double> invdiag64;  // [V]
     DBuf<float> invdiag32;   // [V]
     int64_t n_pinned = 0;
+    bool neumann = false;    // the boundary data carry a Neumann load (neumann_f0 given)
 
     FsaiFactor fsai;
     JacobiSplit jsplit;
@@ -283,6 +291,18 @@ __device__ __forceinline__ FrontRange front_range(int64_t n) {
     r.step = per * blockDim.x;
     r.end = n * (xcd + 1) / 8;
     return r;
+}
+
+// The same range in unsigned 32-bit row numbers (n < 2^31, so every row and
+// every row plus a few strides fits): kernels that index several vectors with
+// it address them as a uniform base plus a 32-bit offset per lane.
+struct FrontRange32 {
+    uint32_t first, step, end;
+};
+
+__device__ __forceinline__ FrontRange32 front_range32(int64_t n) {
+    const FrontRange r = front_range(n);
+    return FrontRange32{static_cast<uint32_t>(r.first), static_cast<uint32_t>(r.step), static_cast<uint32_t>(r.end)};
 }
 
 // Grid for block_range: about `per_block` items per block, at most `cap`
@@ -395,14 +415,20 @@ __device__ __forceinline__ double thread_fold(const double* __restrict__ p, int 
     return acc;
 }
 
-// Fixed-order sum of `n` partials written by an earlier kernel, returned to
-// every thread of the block.  lds holds BLOCK/64 + 1 doubles.
-__device__ __forceinline__ double reduce_bcast(const double* __restrict__ partials, int n, double* lds) {
-    const double t = block_sum(thread_fold(partials, n), lds);
+// The block's sum of thread values t, returned to every thread.  lds holds
+// BLOCK/64 + 1 doubles.
+__device__ __forceinline__ double bcast_sum(double t, double* lds) {
+    t = block_sum(t, lds);
     __syncthreads();
     if (threadIdx.x == 0) lds[BLOCK / 64] = t;
     __syncthreads();
     return lds[BLOCK / 64];
+}
+
+// Fixed-order sum of `n` partials written by an earlier kernel, returned to
+// every thread of the block.  lds holds BLOCK/64 + 1 doubles.
+__device__ __forceinline__ double reduce_bcast(const double* __restrict__ partials, int n, double* lds) {
+    return bcast_sum(thread_fold(partials, n), lds);
 }
 
 // Two fixed-order sums (each as reduce_bcast computes it) with the loads of

@@ -191,7 +191,7 @@ void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, c
     hipLaunchKernelGGL(k_csr_sell_fill, dim3(grid_xcd(S.nslices * SELL_C)), dim3(BLOCK), 0, s, V, S.nslices, ptr, col,
                        v64, v32, S.ptr.p, S.col.p, S.val64.p, S.val32.p);
     HIP_CHECK(hipGetLastError());
-    build_sell_offsets(ctx, S);
+    build_sell_offsets(ctx, S, V);
 }
 
 void fsai_setup(dec_mesh* m) {

@@ -24,8 +24,19 @@
 
 namespace {
 
-constexpr int PREFETCH = 4;        // rows per thread the update kernel loads ahead of its opening fold
-constexpr int CLOSE_PREFETCH = 8;  // the same for the closing kernel (two vectors per row)
+// Rows per thread whose loads the update and closing kernels issue together:
+// the first group before the opening fold (so the fold's latency overlaps
+// their transfer), every later group before any of its rows is used, so that
+// each wavefront keeps ROWS x 3 loads in flight instead of 3.  Measured on the
+// box: the update kernel is fastest with groups of 4 while a thread has about
+// 8 rows (128^3 on 1024 workgroups: 12.3 against 12.7 us for 4 rows before
+// the fold and then one at a time, 13.2 with groups of 8) and with groups of
+// 8 when it has about 32 (256^3 on 2048 workgroups: 94.8 against 101.5 us);
+// the closing kernel with 6 to 8 at both sizes; issuing the fold's loads
+// before the rows' gained nothing.
+constexpr int CLOSE_ROWS = 8;
+constexpr int64_t VEC_WIDE_ROWS = int64_t(1) << 22;  // from here the vector kernels take 8 blocks per CU
+constexpr int UPDATE_ROWS_FEW = 4, UPDATE_ROWS_MANY = 8;
 // regions of the partials array, G doubles each
 enum { R_PQ = 0, R_RR = 1, R_RZ = 2 };
 enum { FIN_NORM2 = 0, FIN_RR = 1, FIN_START = 2 };
@@ -205,19 +216,17 @@ __global__ void k_split_x(int64_t V, double* __restrict__ x, const double* __res
 // (`invd` is then D itself).
 enum { PJ_NONE = 0, PJ_JACOBI = 1, PJ_SPLIT = 2 };
 
-template <class VT, int PJ>
+template <class VT, int PJ, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r, const VT* __restrict__ q,
                                                   const VT* __restrict__ invd, double* __restrict__ partials,
                                                   int P, int n_pq, PcgScalars* __restrict__ S) {
     __shared__ double lds[BLOCK / 64 + 1];
     if (S->done) return;
-    const FrontRange R = front_range(V);
-    // the first PREFETCH rows of each thread are loaded before the fold, so
-    // the fold's latency overlaps with their transfer
-    VT fr[PREFETCH], fq[PREFETCH], fd[PREFETCH];
+    const FrontRange32 R = front_range32(V);
+    VT fr[ROWS], fq[ROWS], fd[ROWS];
 #pragma unroll
-    for (int k = 0; k < PREFETCH; ++k) {
-        const int64_t i = R.first + k * R.step;
+    for (int k = 0; k < ROWS; ++k) {
+        const uint32_t i = R.first + k * R.step;
         if (i < R.end) {
             fr[k] = r[i];
             fq[k] = q[i];
@@ -229,23 +238,29 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
     if (!(pq > 0.0) || !isfinite(pq)) return;
     const VT a = static_cast<VT>(S->rho / pq);
     VT rz = 0, rr = 0;
+    for (uint32_t first = R.first; first < R.end; first += ROWS * R.step) {
+        if (first != R.first) {
 #pragma unroll
-    for (int k = 0; k < PREFETCH; ++k) {
-        const int64_t i = R.first + k * R.step;
-        if (i < R.end) {
-            const VT ri = fr[k] - a * fq[k];
-            r[i] = ri;
-            if (PJ == PJ_JACOBI) rz += ri * (fd[k] * ri);
-            if (PJ == PJ_SPLIT) rz += ri * ri;
-            rr += PJ == PJ_SPLIT ? (ri * ri) * fd[k] : ri * ri;
+            for (int k = 0; k < ROWS; ++k) {
+                const uint32_t i = first + k * R.step;
+                if (i < R.end) {
+                    fr[k] = r[i];
+                    fq[k] = q[i];
+                    fd[k] = PJ != PJ_NONE ? invd[i] : VT(0);
+                }
+            }
         }
-    }
-    for (int64_t i = R.first + PREFETCH * R.step; i < R.end; i += R.step) {
-        const VT ri = r[i] - a * q[i];
-        r[i] = ri;
-        if (PJ == PJ_JACOBI) rz += ri * (invd[i] * ri);
-        if (PJ == PJ_SPLIT) rz += ri * ri;
-        rr += PJ == PJ_SPLIT ? (ri * ri) * invd[i] : ri * ri;
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const uint32_t i = first + k * R.step;
+            if (i < R.end) {
+                const VT ri = fr[k] - a * fq[k];
+                r[i] = ri;
+                if (PJ == PJ_JACOBI) rz += ri * (fd[k] * ri);
+                if (PJ == PJ_SPLIT) rz += ri * ri;
+                rr += PJ == PJ_SPLIT ? (ri * ri) * fd[k] : ri * ri;
+            }
+        }
     }
     const double b2 = block_sum(static_cast<double>(rr), lds);
     if (threadIdx.x == 0) partials[R_RR * P + blockIdx.x] = b2;
@@ -286,12 +301,13 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         return;
     }
     const int G = gridDim.x;
-    const FrontRange R = front_range(V);
+    const FrontRange32 R = front_range32(V);
+    constexpr int ROWS = CLOSE_ROWS;
     // z (or D^-1 r), p and x of the first rows, loaded before the fold
-    VT fz[CLOSE_PREFETCH], fp[CLOSE_PREFETCH], fx[CLOSE_PREFETCH];
+    VT fz[ROWS], fp[ROWS], fx[ROWS];
 #pragma unroll
-    for (int k = 0; k < CLOSE_PREFETCH; ++k) {
-        const int64_t i = R.first + k * R.step;
+    for (int k = 0; k < ROWS; ++k) {
+        const uint32_t i = R.first + k * R.step;
         if (i < R.end) {
             fz[k] = PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i]);
             fp[k] = p[i];
@@ -314,18 +330,26 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         const VT a = static_cast<VT>(S->rho / pq);
         const VT bt = static_cast<VT>(beta);
         const bool run = done == PCG_RUNNING;
+        for (uint32_t first = R.first; first < R.end; first += ROWS * R.step) {
+            if (first != R.first) {
 #pragma unroll
-        for (int k = 0; k < CLOSE_PREFETCH; ++k) {
-            const int64_t i = R.first + k * R.step;
-            if (i < R.end) {
-                x[i] = fx[k] + a * fp[k];
-                if (run) p[i] = fz[k] + bt * fp[k];
+                for (int k = 0; k < ROWS; ++k) {
+                    const uint32_t i = first + k * R.step;
+                    if (i < R.end) {
+                        if (run) fz[k] = PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i]);
+                        fp[k] = p[i];
+                        fx[k] = x[i];
+                    }
+                }
             }
-        }
-        for (int64_t i = R.first + CLOSE_PREFETCH * R.step; i < R.end; i += R.step) {
-            const VT pi = p[i];
-            x[i] = x[i] + a * pi;
-            if (run) p[i] = (PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i])) + bt * pi;
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+                const uint32_t i = first + k * R.step;
+                if (i < R.end) {
+                    x[i] = fx[k] + a * fp[k];
+                    if (run) p[i] = fz[k] + bt * fp[k];
+                }
+            }
         }
     }
     if (lead) {
@@ -397,31 +421,37 @@ struct Run {
 
 // With events, the launch carries them (hipExtLaunchKernelGGL): the
 // timestamps are those of the dispatch itself, not of separate markers.
-template <class VT, int MODE, int U, bool NT, bool DIFF, bool D16>
+template <class VT, int MODE, int U, bool NT, bool DIFF, int CF>
 void launch_sell_k(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
     const dim3 g(c->Gs), blk(BLOCK);
     if (ev_a)
-        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, D16>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
+        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
                               part, done);
     else
-        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, D16>), g, blk, 0, c->stream, A, x, y, b, part, done);
+        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF>), g, blk, 0, c->stream, A, x, y, b, part, done);
 }
 
+template <class VT, int MODE, int U, bool NT, bool DIFF>
+void launch_sell_d(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                   const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
+    if (A.tcol)
+        launch_sell_k<VT, MODE, U, NT, DIFF, CF_U8>(c, A, x, y, b, part, done, ev_a, ev_b);
+    else if (A.dcol)
+        launch_sell_k<VT, MODE, U, NT, DIFF, CF_I16>(c, A, x, y, b, part, done, ev_a, ev_b);
+    else
+        launch_sell_k<VT, MODE, U, NT, DIFF, CF_I32>(c, A, x, y, b, part, done, ev_a, ev_b);
+}
+
+// the column format is the one the view carries (A.tcol, A.dcol, or neither)
 template <class VT, int MODE, int U, bool NT>
 void launch_sell_u(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const PcgScalars* st, hipEvent_t ev_a, hipEvent_t ev_b) {
     const int32_t* done = st ? &st->done : nullptr;
-    if (A.excess) {
-        if (A.dcol)
-            launch_sell_k<VT, MODE, U, NT, true, true>(c, A, x, y, b, part, done, ev_a, ev_b);
-        else
-            launch_sell_k<VT, MODE, U, NT, true, false>(c, A, x, y, b, part, done, ev_a, ev_b);
-    } else if (A.dcol) {
-        launch_sell_k<VT, MODE, U, NT, false, true>(c, A, x, y, b, part, done, ev_a, ev_b);
-    } else {
-        launch_sell_k<VT, MODE, U, NT, false, false>(c, A, x, y, b, part, done, ev_a, ev_b);
-    }
+    if (A.excess)
+        launch_sell_d<VT, MODE, U, NT, true>(c, A, x, y, b, part, done, ev_a, ev_b);
+    else
+        launch_sell_d<VT, MODE, U, NT, false>(c, A, x, y, b, part, done, ev_a, ev_b);
 }
 
 template <class VT, int MODE, bool NT>
@@ -460,31 +490,107 @@ void launch_sell(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const
 int stride(const SolveCache* c) { return c->G > c->Gs ? c->G : c->Gs; }
 double* region(SolveCache* c, int r) { return c->partials.p + (int64_t)r * stride(c); }
 
-// Pick the sliced-ELL variant (2, 3 or 4 entry pairs in flight, non-temporal loads on/off) by
-// timing the iteration's product (y = A x with the partials of x.y) on this matrix.  All
-// variants sum every row in the same order, so the choice never changes a result.
 template <class VT>
-void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const VT* x, VT* y) {
-    const int pi = prec_index<VT>();
-    if (c->tuned[pi] || c->pinned_variant) return;
-    const std::array<int64_t, 4> shape{pi + (A.excess ? 2 : 0) + (A.dcol ? 4 : 0), A.V, A.nslices, entries};
-    auto known = c->ctx->spmv_tune.find(shape);
-    if (known != c->ctx->spmv_tune.end()) {  // a matrix of this shape was timed before on this context
-        c->unroll[pi] = known->second.first;
-        c->nt[pi] = known->second.second;
-        c->tuned[pi] = true;
-        return;
+const VT* values(const SellMatrix& S);
+template <>
+const double* values<double>(const SellMatrix& S) {
+    return S.val64.p;
+}
+template <>
+const float* values<float>(const SellMatrix& S) {
+    return S.val32.p;
+}
+template <class VT>
+const VT* excess(const SellMatrix& S);
+template <>
+const double* excess<double>(const SellMatrix& S) {
+    return S.excess64.p;
+}
+template <>
+const float* excess<float>(const SellMatrix& S) {
+    return S.excess32.p;
+}
+
+// A view of the sliced-ELL matrix S (V rows) whose product reads its columns in
+// format `cf`, or in the most compact format S has below it (every matrix has
+// its int32 columns); its row excess if any.
+template <class VT>
+SellView<VT> view_cf(const SellMatrix& S, int64_t V, int cf) {
+    SellView<VT> v{S.ptr.p, S.col.p, values<VT>(S), S.nslices, V, excess<VT>(S)};
+    if (cf >= CF_U8 && S.tcol.p) {
+        v.tcol = S.tcol.p;
+        v.otab = S.otab.p;
+        v.ntab = S.ntab;
+    } else if (cf >= CF_I16 && S.dcol.p) {
+        v.dcol = S.dcol.p;
     }
-    const int cand[6][2] = {{4, 1}, {4, 0}, {3, 1}, {3, 0}, {2, 1}, {2, 0}};
-    // four rounds over the variants, each timing three launches; a variant's
+    return v;
+}
+
+// The solver's view: the column format chosen for this precision.
+template <class VT>
+SellView<VT> view(const SolveCache* c, const SellMatrix& S, int64_t V) {
+    return view_cf<VT>(S, V, c->cf[prec_index<VT>()]);
+}
+
+// Bytes one stored column costs the product of a view.
+template <class VT>
+double column_bytes(const SellView<VT>& v) {
+    return v.tcol ? 1.0 : v.dcol ? 2.0 : 4.0;
+}
+
+// Pick the sliced-ELL variant by timing the iteration's product (y = A x with
+// the partials of x.y) on this matrix: the column format (one-byte table
+// indices, 16-bit offsets or int32 columns, as far as S has them), 2, 3 or 4
+// entry pairs in flight, non-temporal loads on or off.  Every variant sums
+// each row in the same order over the same columns, so the choice never
+// changes a result.
+template <class VT>
+void autotune_spmv(SolveCache* c, const SellMatrix& S, int64_t V, const VT* x, VT* y) {
+    const int pi = prec_index<VT>();
+    if (c->tuned[pi]) return;
+    std::vector<int> formats;
+    if (c->force_cols) {  // that format, or the most compact one S has below it
+        const int want = c->force_cols == 8 ? CF_U8 : c->force_cols == 16 ? CF_I16 : CF_I32;
+        const double cb = column_bytes(view_cf<VT>(S, V, want));
+        formats.push_back(cb == 1.0 ? CF_U8 : cb == 2.0 ? CF_I16 : CF_I32);
+    } else {
+        for (int cf : {CF_U8, CF_I16, CF_I32})
+            if ((cf != CF_U8 || S.tcol.p) && (cf != CF_I16 || S.dcol.p)) formats.push_back(cf);
+    }
+    std::vector<std::array<int, 3>> cand;  // unroll, non-temporal, column format
+    for (int cf : formats) {
+        if (c->pinned_variant) {
+            cand.push_back({c->unroll[pi], c->nt[pi], cf});
+            continue;
+        }
+        for (int u : {4, 3, 2})
+            for (int nt : {1, 0}) cand.push_back({u, nt, cf});
+    }
+    const bool free_choice = !c->pinned_variant && c->force_cols == 0;
+    const std::array<int64_t, 4> shape{pi + (S.excess64.p ? 2 : 0) + (S.dcol.p ? 4 : 0) + (S.tcol.p ? 8 : 0), V,
+                                       S.nslices, S.entries};
+    auto pick_as = [&](const std::array<int, 3>& v) {
+        c->unroll[pi] = v[0];
+        c->nt[pi] = v[1];
+        c->cf[pi] = v[2];
+        c->tuned[pi] = true;
+    };
+    if (cand.size() == 1) return pick_as(cand[0]);
+    if (free_choice) {
+        auto known = c->ctx->spmv_tune.find(shape);
+        if (known != c->ctx->spmv_tune.end()) return pick_as(known->second);  // timed before on this context
+    }
+    // three rounds over the variants, each timing three launches; a variant's
     // figure is its best round, so that one slow round (clock or
     // neighbouring-work noise) does not decide the pick
-    float best[6];
-    for (int k = 0; k < 6; ++k) best[k] = 1e30f;
-    for (int round = 0; round < 4; ++round) {
-        for (int k = 0; k < 6; ++k) {
+    const int nc = (int)cand.size();
+    std::vector<float> best(nc, 1e30f);
+    for (int round = 0; round < 3; ++round) {
+        for (int k = 0; k < nc; ++k) {
             c->unroll[pi] = cand[k][0];
             c->nt[pi] = cand[k][1];
+            const SellView<VT> A = view_cf<VT>(S, V, cand[k][2]);
             // the iteration's own mode (y = A x with the partials of x.y)
             launch_sell<VT, MODE_DOT>(c, A, x, y, nullptr, region(c, R_PQ), nullptr);
             HIP_CHECK(hipEventRecord(c->t0, c->stream));
@@ -497,12 +603,10 @@ void autotune_spmv(SolveCache* c, const SellView<VT>& A, int64_t entries, const 
         }
     }
     int pick = 0;
-    for (int k = 1; k < 6; ++k)
+    for (int k = 1; k < nc; ++k)
         if (best[k] < best[pick]) pick = k;
-    c->unroll[pi] = cand[pick][0];
-    c->nt[pi] = cand[pick][1];
-    c->tuned[pi] = true;
-    c->ctx->spmv_tune[shape] = {c->unroll[pi], c->nt[pi]};
+    pick_as(cand[pick]);
+    if (free_choice) c->ctx->spmv_tune[shape] = cand[pick];
 }
 
 
@@ -516,6 +620,19 @@ void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, Pc
 // FSAI product G^T w and the block-Jacobi product on the SpMV's Gs blocks
 int rz_parts(const SolveCache* c, int precond) { return precond == DEC_PRECOND_JACOBI ? c->G : c->Gs; }
 
+// The update kernel on G blocks, its row groups sized by the rows each thread has.
+template <class VT, int PJ>
+void launch_update(hipStream_t s, int G, int64_t V, VT* r, const VT* q, const VT* invd, double* part, int P, int n_pq,
+                   PcgScalars* S) {
+    const int64_t rows_per_thread = (V + (int64_t)G * BLOCK - 1) / ((int64_t)G * BLOCK);
+    if (rows_per_thread > 12)
+        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_MANY>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part, P,
+                           n_pq, S);
+    else
+        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_FEW>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part, P,
+                           n_pq, S);
+}
+
 template <class VT>
 void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a = nullptr,
                        hipEvent_t ev_b = nullptr) {
@@ -526,24 +643,20 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     PcgScalars* N = R.st + (par ^ 1);
     launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
     if (R.precond == DEC_PRECOND_JACOBI && R.split) {
-        hipLaunchKernelGGL((k_update<VT, PJ_SPLIT>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part, P,
-                           n_pq, S);
+        launch_update<VT, PJ_SPLIT>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
         hipLaunchKernelGGL((k_close<VT, PJ_SPLIT>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
                            (const VT*)nullptr, (const VT*)nullptr, R.p, part, P, G, S, N);
     } else if (R.precond == DEC_PRECOND_JACOBI) {
-        hipLaunchKernelGGL((k_update<VT, PJ_JACOBI>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q, R.invd, part,
-                           P, n_pq, S);
+        launch_update<VT, PJ_JACOBI>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
         hipLaunchKernelGGL((k_close<VT, PJ_JACOBI>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
                            (const VT*)nullptr, R.p, part, P, G, S, N);
     } else if (R.precond == DEC_PRECOND_BLOCK) {
-        hipLaunchKernelGGL((k_update<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q,
-                           (const VT*)nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, (const VT*)nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.z, R.r, region(c, R_RZ), S);       // z = M r, r.z partials
         hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
                            (const VT*)nullptr, R.z, R.p, part, P, c->Gs, S, N);
     } else {
-        hipLaunchKernelGGL((k_update<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.r, R.q,
-                           (const VT*)nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, (const VT*)nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
         hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
@@ -630,7 +743,7 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             continue;
         }
         if (o.use_graph) {
-            GraphKey key{prec, R.precond + (R.split ? 8 : 0), chunk, c->unroll[prec], c->nt[prec]};
+            GraphKey key{prec, R.precond + (R.split ? 8 : 0), chunk, c->unroll[prec], c->nt[prec], c->cf[prec]};
             auto it = c->graphs.find(key);
             hipGraphExec_t exec = nullptr;
             if (it == c->graphs.end()) {
@@ -655,35 +768,6 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
     }
 }
 
-template <class VT>
-const VT* values(const SellMatrix& S);
-template <>
-const double* values<double>(const SellMatrix& S) {
-    return S.val64.p;
-}
-template <>
-const float* values<float>(const SellMatrix& S) {
-    return S.val32.p;
-}
-template <class VT>
-const VT* excess(const SellMatrix& S);
-template <>
-const double* excess<double>(const SellMatrix& S) {
-    return S.excess64.p;
-}
-template <>
-const float* excess<float>(const SellMatrix& S) {
-    return S.excess32.p;
-}
-
-// The solver's view of a sliced-ELL matrix with V rows: its 16-bit column
-// offsets where it has them (unless switched off), its row excess if any.
-template <class VT>
-SellView<VT> view(const SolveCache* c, const SellMatrix& S, int64_t V) {
-    SellView<VT> v{S.ptr.p, S.col.p, values<VT>(S), S.nslices, V, excess<VT>(S)};
-    if (!c->wide_cols) v.dcol = S.dcol.p;
-    return v;
-}
 
 template <class VT>
 Run<VT> make_run(dec_mesh* m, SolveCache* c, int precond);
@@ -988,14 +1072,16 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
         const int64_t g = want < cap ? want : cap;
         return (int)(((g + 7) / 8) * 8);
     };
-    c.G = blocks(BLOCK, 4);
+    c.G = blocks(BLOCK, V >= VEC_WIDE_ROWS ? 8 : 4);
     c.Gs = blocks(SELL_C * (BLOCK / 64), 8);
-    const std::array<int64_t, 4> shape{0 + (m->sell.excess64.p ? 2 : 0) + (m->sell.dcol.p ? 4 : 0), V,
-                                       m->sell.nslices, m->sell.entries};
+    const SellMatrix& S = m->sell;
+    const std::array<int64_t, 4> shape{0 + (S.excess64.p ? 2 : 0) + (S.dcol.p ? 4 : 0) + (S.tcol.p ? 8 : 0), V,
+                                       S.nslices, S.entries};
     auto known = ctx->spmv_tune.find(shape);  // a variant timed earlier for this shape, else the default
     if (known != ctx->spmv_tune.end()) {
-        c.unroll[0] = known->second.first;
-        c.nt[0] = known->second.second;
+        c.unroll[0] = known->second[0];
+        c.nt[0] = known->second[1];
+        c.cf[0] = known->second[2];
     }
     const SellView<double> A = view<double>(&c, m->sell, V);
     const int G = c.G, Gs = c.Gs;
@@ -1044,8 +1130,7 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
                 PcgScalars* S = st + (k & 1);
                 PcgScalars* N = st + ((k & 1) ^ 1);
                 launch_sell<double, MODE_DOT>(&c, A, p, q, nullptr, part + R_PQ * P, S);
-                hipLaunchKernelGGL((k_update<double, PJ_JACOBI>), dim3(G), blk, 0, c.stream, V, r, q,
-                                   m->invdiag64.p, part, P, Gs, S);
+                launch_update<double, PJ_JACOBI>(c.stream, G, V, r, q, m->invdiag64.p, part, P, Gs, S);
                 hipLaunchKernelGGL((k_close<double, PJ_JACOBI>), dim3(G), blk, 0, c.stream, V, T, r,
                                    m->invdiag64.p, (const double*)nullptr, p, part, P, G, S, N);
             }
@@ -1122,8 +1207,10 @@ SolveCache* get_solve_cache(dec_mesh* m) {
         HIP_CHECK(hipEventCreate(&c->t0));
         HIP_CHECK(hipEventCreate(&c->t1));
         // one block per 256 rows (64 rows for the SpMV) up to a fixed number of
-        // blocks per CU, rounded to a multiple of 8 (one share per XCD)
-        int per_cu = 4, per_cu_s = 8;
+        // blocks per CU, rounded to a multiple of 8 (one share per XCD): the
+        // vector kernels take 8 per CU from 2^22 rows (256^3: 848 against 880 ms
+        // per solve), 4 below (128^3: 48.8 against 54.3 ms)
+        int per_cu = m->V >= VEC_WIDE_ROWS ? 8 : 4, per_cu_s = 8;
         if (const char* env = getenv("DEC_BLOCKS_PER_CU")) per_cu = atoi(env) > 0 ? atoi(env) : per_cu;
         if (const char* env = getenv("DEC_SPMV_BLOCKS_PER_CU")) per_cu_s = atoi(env) > 0 ? atoi(env) : per_cu_s;
         if (const char* env = getenv("DEC_SELL_UNROLL")) {
@@ -1134,7 +1221,7 @@ SolveCache* get_solve_cache(dec_mesh* m) {
             c->nt[0] = c->nt[1] = atoi(env);
             c->pinned_variant = true;
         }
-        if (const char* env = getenv("DEC_SELL_COLS")) c->wide_cols = atoi(env) == 32;
+        if (const char* env = getenv("DEC_SELL_COLS")) c->force_cols = atoi(env);
         if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->split = atoi(env) != 0;
         auto blocks = [&](int64_t rows_per_block, int pc) {
             const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
@@ -1196,20 +1283,22 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
                     "the energy-norm test is for FP64 solves");
         ctx->set_device();
         SolveCache* c = get_solve_cache(m);
+        if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
+        ensure_vectors(m, c, o.precision);
+        ctx->sync();  // inputs written on the caller's stream are complete
+        autotune_spmv<double>(c, m->sell, m->V, c->p64.p, c->q64.p);
+        if (o.precision == DEC_PREC_MIXED) autotune_spmv<float>(c, m->sell, m->V, c->p32.p, c->q32.p);
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
-            const double s = o.precision == DEC_PREC_MIXED ? 4.0 : 8.0, nz = (double)m->sell.kept;
-            const double cb = view<double>(c, m->sell, m->V).dcol ? 2.0 : 4.0;  // bytes per column
+            const bool mixed = o.precision == DEC_PREC_MIXED;
+            const double s = mixed ? 4.0 : 8.0, nz = (double)m->sell.kept;
+            // bytes per column of the format the iteration's product reads
+            const double cb = mixed ? column_bytes(view<float>(c, m->sell, m->V))
+                                    : column_bytes(view<double>(c, m->sell, m->V));
             stats->spmv_nnz = m->sell.kept;
             stats->spmv_bytes = nz * (s + cb) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
             if (m->sell.excess64.p) stats->spmv_bytes += s * (double)m->V;  // difference form: the row excess
         }
-        if (o.precond == DEC_PRECOND_FSAI) fsai_setup(m);
-        ensure_vectors(m, c, o.precision);
-        ctx->sync();  // inputs written on the caller's stream are complete
-        autotune_spmv<double>(c, sell64(m, c), m->sell.entries, c->p64.p, c->q64.p);
-        if (o.precision == DEC_PREC_MIXED)
-            autotune_spmv<float>(c, view<float>(c, m->sell, m->V), m->sell.entries, c->p32.p, c->q32.p);
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,
                            m->bc_value.p, o.warm_start ? T : nullptr, c->x64.p);
@@ -1278,7 +1367,12 @@ int dec_solve_noalloc(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_so
         std::lock_guard<std::mutex> solve_lock(na_solve_mutex[ctx->device]);
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
-            const double cb = m->sell.dcol.p ? 2.0 : 4.0, nz = (double)m->sell.kept;
+            SolveCache probe;  // the format this call reads: a variant timed earlier for the shape, else the default
+            const std::array<int64_t, 4> shape{(m->sell.excess64.p ? 2 : 0) + (m->sell.dcol.p ? 4 : 0) +
+                                                   (m->sell.tcol.p ? 8 : 0), m->V, m->sell.nslices, m->sell.entries};
+            auto known = ctx->spmv_tune.find(shape);
+            if (known != ctx->spmv_tune.end()) probe.cf[0] = known->second[2];
+            const double cb = column_bytes(view<double>(&probe, m->sell, m->V)), nz = (double)m->sell.kept;
             stats->spmv_bytes = nz * (8.0 + cb) + 4.0 * (double)(m->V + 1) + 16.0 * (double)m->V;
             if (m->sell.excess64.p) stats->spmv_bytes += 8.0 * (double)m->V;
         }

@@ -9,7 +9,11 @@
 // entry's column lies within 2^15 of its row, the columns are read as 16-bit
 // offsets from the row instead (one 256 B segment per pair): a spatially
 // numbered mesh keeps its neighbours that close, and the bytes per stored
-// entry fall from 12 to 10 (FP64) and from 8 to 6 (FP32).
+// entry fall from 12 to 10 (FP64) and from 8 to 6 (FP32).  Where the stored
+// entries take at most 256 distinct offsets (a lattice numbered in order has
+// seven, whatever its size), each column is one byte, an index into the
+// matrix's table of offsets, which every workgroup stages in LDS: 9 bytes per
+// FP64 entry, 5 per FP32 entry, and the same columns.
 #pragma once
 
 #include "common.h"
@@ -30,7 +34,15 @@ struct SellView {
     int64_t V;
     const VT* excess = nullptr;  // [V], or null for the plain product
     const int16_t* dcol = nullptr;  // [entries] col - row, or null: the int32 columns
+    const uint8_t* tcol = nullptr;  // [entries] index into otab of col - row, or null
+    const int32_t* otab = nullptr;  // [ntab] the offsets tcol indexes
+    int32_t ntab = 0;
 };
+
+// How the product reads its columns: int32 columns, 16-bit offsets from the
+// row, or one-byte indices into the offset table.
+enum { CF_I32 = 0, CF_I16 = 1, CF_U8 = 2 };
+constexpr int OTAB_MAX = 256;
 
 // Native two-element vectors for the paired loads.
 template <class T>
@@ -42,6 +54,10 @@ struct Pair<int32_t> {
 template <>
 struct Pair<int16_t> {
     typedef int16_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<uint8_t> {
+    typedef uint8_t type __attribute__((ext_vector_type(2)));
 };
 template <>
 struct Pair<double> {
@@ -59,22 +75,30 @@ __device__ __forceinline__ T stream_load(const T* p) {
 }
 
 // Row `lane` of the slice starting at `base` with `width` stored entries per
-// row: sum over the row's entries in stored (ascending column) order.  The
+// row: sum over the row's entries in stored (ascending column) order.  x is
+// indexed with unsigned 32-bit columns (every column is in [0, V), V < 2^31),
+// so a gather's address is the uniform base plus a 32-bit offset.  The
 // pairs go in groups of U: all column and value loads of a group are issued
 // before its x gathers, and the last group is predicated (the width is
 // uniform across the wavefront), so no entry waits on the one before; an odd
 // last entry follows.  The terms are added in entry order, so every layout
-// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).  D16:
-// the columns come from the 16-bit offsets (A.dcol) added to `row`.
-template <class VT, int U, bool NT = true, bool DIFF = false, bool D16 = false>
+// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).  CF:
+// the columns as int32 (A.col), 16-bit offsets (A.dcol) added to `row`, or
+// one-byte indices (A.tcol) into the offset table `tab` (in LDS) added to
+// `row` (for a lane past the last row, row is the last row and its entries
+// index the offset 0).
+template <class VT, int U, bool NT = true, bool DIFF = false, int CF = CF_I32>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
-                                       const VT* __restrict__ x, VT xi = 0, int32_t row = 0) {
+                                       const VT* __restrict__ x, VT xi = 0, int32_t row = 0,
+                                       const int32_t* tab = nullptr) {
     typedef typename Pair<int32_t>::type C2;
     typedef typename Pair<int16_t>::type D2;
+    typedef typename Pair<uint8_t>::type B2;
     typedef typename Pair<VT>::type V2;
     const int np = width >> 1;
     const C2* cp = reinterpret_cast<const C2*>(A.col + base) + lane;
     const D2* dp = reinterpret_cast<const D2*>(A.dcol + base) + lane;
+    const B2* bp = reinterpret_cast<const B2*>(A.tcol + base) + lane;
     const V2* vp = reinterpret_cast<const V2*>(A.val + base) + lane;
     VT acc = 0;
     for (int t = 0; t < np; t += U) {
@@ -84,7 +108,11 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = t + u < np;
-            if (D16) {
+            if (CF == CF_U8) {
+                const B2 d = ok ? stream_load<B2, NT>(bp + u * SELL_C) : B2(0);
+                c[u].x = row + tab[d.x];
+                c[u].y = row + tab[d.y];
+            } else if (CF == CF_I16) {
                 const D2 d = ok ? stream_load<D2, NT>(dp + u * SELL_C) : D2(0);
                 c[u].x = row + d.x;
                 c[u].y = row + d.y;
@@ -96,8 +124,8 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool ok = t + u < np;
-            x0[u] = ok ? x[c[u].x] : VT(0);
-            x1[u] = ok ? x[c[u].y] : VT(0);
+            x0[u] = ok ? x[static_cast<uint32_t>(c[u].x)] : VT(0);
+            x1[u] = ok ? x[static_cast<uint32_t>(c[u].y)] : VT(0);
             if (DIFF) {
                 x0[u] -= xi;
                 x1[u] -= xi;
@@ -111,14 +139,24 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
             }
         cp += U * SELL_C;
         dp += U * SELL_C;
+        bp += U * SELL_C;
         vp += U * SELL_C;
     }
     if (width & 1) {
         const int64_t k = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
-        const int32_t c = D16 ? row + stream_load<int16_t, NT>(A.dcol + k) : stream_load<int32_t, NT>(A.col + k);
-        acc += stream_load<VT, NT>(A.val + k) * (DIFF ? x[c] - xi : x[c]);
+        const int32_t c = CF == CF_U8    ? row + tab[stream_load<uint8_t, NT>(A.tcol + k)]
+                          : CF == CF_I16 ? row + stream_load<int16_t, NT>(A.dcol + k)
+                                         : stream_load<int32_t, NT>(A.col + k);
+        acc += stream_load<VT, NT>(A.val + k) * (DIFF ? x[static_cast<uint32_t>(c)] - xi : x[static_cast<uint32_t>(c)]);
     }
     return acc;
+}
+
+// Stage the offset table of a CF_U8 product in LDS (every thread of the block
+// calls this before its first row).
+__device__ __forceinline__ void stage_offsets(const int32_t* __restrict__ otab, int ntab, int32_t* tab) {
+    for (int t = threadIdx.x; t < ntab; t += blockDim.x) tab[t] = otab[t];
+    __syncthreads();
 }
 
 enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
@@ -128,7 +166,8 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // per-block partials of b.y (DOTB).  A launch whose `done` flag (if given)
 // is set returns at once: inside a batch of PCG iterations that has
 // converged, the remaining launches do nothing.  DIFF: the difference form
-// (A.excess set).  D16: the 16-bit column offsets (A.dcol set).
+// (A.excess set).  CF: the column format (CF_I16: A.dcol set, CF_U8: A.tcol
+// and A.otab set).
 //
 // Order of the slices: XCD x (workgroups are dispatched round-robin, so
 // blockIdx.x & 7 names it) owns the contiguous x-th eighth of the slices,
@@ -141,41 +180,49 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // workgroup a contiguous stretch of its own, as the other kernels do, was
 // 9% slower at 128^3: 31.2 against 28.6 us.)  gridDim.x must be a multiple
 // of 8.
-template <class VT, int MODE, int U, bool NT, bool DIFF = false, bool D16 = false>
+// The contribution of row `row` (the product acc of its stored entries) to
+// y and to the block's partial sum d.
+template <class VT, int MODE, bool DIFF>
+__device__ __forceinline__ void sell_finish(const SellView<VT>& A, int64_t row, VT acc, VT xi, const VT* __restrict__ x,
+                                            VT* __restrict__ y, const VT* __restrict__ b, VT& d) {
+    if (row >= A.V) return;
+    if (DIFF) acc += A.excess[row] * xi;
+    if (MODE == MODE_RESID) {
+        const VT ri = b[row] - acc;
+        y[row] = ri;
+        d += ri * ri;
+    } else {
+        y[row] = acc;
+        if (MODE == MODE_DOT) d += x[row] * acc;
+        if (MODE == MODE_DOTB) d += b[row] * acc;
+    }
+}
+
+template <class VT, int MODE, int U, bool NT, bool DIFF = false, int CF = CF_I32>
 __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
                                                 const int32_t* __restrict__ done) {
     __shared__ double lds[BLOCK / 64 + 1];
+    __shared__ int32_t tab[CF == CF_U8 ? OTAB_MAX : 1];
     if (done != nullptr && *done) return;
+    if (CF == CF_U8) stage_offsets(A.otab, A.ntab, tab);
     constexpr int WAVES = BLOCK / 64;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
     const int64_t s1 = A.nslices * (xcd + 1) / 8;
     const int64_t step = static_cast<int64_t>(gridDim.x >> 3) * WAVES;
     VT d = 0;
+    // the row the columns are decoded from (a lane past the last row takes the last row)
+    auto decode_row = [&](int64_t row) {
+        return static_cast<int32_t>(CF == CF_U8 && row >= A.V ? A.V - 1 : row);
+    };
     for (int64_t s = A.nslices * xcd / 8 + j * WAVES + w; s < s1; s += step) {
         const int64_t base = A.ptr[s];
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;
-        VT acc;
-        if (DIFF) {
-            const VT xi = row < A.V ? x[row] : VT(0);
-            acc = sell_row<VT, U, NT, true, D16>(A, base, width, lane, x, xi, static_cast<int32_t>(row));
-            if (row < A.V) acc += A.excess[row] * xi;
-        } else {
-            acc = sell_row<VT, U, NT, false, D16>(A, base, width, lane, x, VT(0), static_cast<int32_t>(row));
-        }
-        if (row < A.V) {
-            if (MODE == MODE_RESID) {
-                const VT ri = b[row] - acc;
-                y[row] = ri;
-                d += ri * ri;
-            } else {
-                y[row] = acc;
-                if (MODE == MODE_DOT) d += x[row] * acc;
-                if (MODE == MODE_DOTB) d += b[row] * acc;
-            }
-        }
+        const VT xi = DIFF && row < A.V ? x[row] : VT(0);
+        const VT acc = sell_row<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab);
+        sell_finish<VT, MODE, DIFF>(A, row, acc, xi, x, y, b, d);
     }
     if (MODE == MODE_PLAIN) return;
     const double bs = block_sum(static_cast<double>(d), lds);

@@ -56,13 +56,14 @@ __device__ __forceinline__ VT csr_row(const CsrView<VT>& A, int64_t row, const V
 
 // ---------------------------------------------------------------- host side
 struct GraphKey {
-    int prec, precond, chunk, unroll, nt;
+    int prec, precond, chunk, unroll, nt, cf;
     bool operator<(const GraphKey& o) const {
         if (prec != o.prec) return prec < o.prec;
         if (precond != o.precond) return precond < o.precond;
         if (chunk != o.chunk) return chunk < o.chunk;
         if (unroll != o.unroll) return unroll < o.unroll;
-        return nt < o.nt;
+        if (nt != o.nt) return nt < o.nt;
+        return cf < o.cf;
     }
 };
 
@@ -74,10 +75,11 @@ struct SolveCache {
     // sliced-ELL variant per precision ([0] FP64, [1] FP32), chosen by the
     // tuner among variants whose products are bit-for-bit identical
     int unroll[2] = {4, 4};
-    int nt[2] = {1, 0};  // non-temporal matrix loads
+    int nt[2] = {1, 0};            // non-temporal matrix loads
+    int cf[2] = {CF_U8, CF_U8};    // column format, the most compact a matrix has up to this
     bool tuned[2] = {false, false};
-    bool pinned_variant = false;  // set through the environment: no tuning
-    bool wide_cols = false;       // int32 columns even where 16-bit offsets exist (environment)
+    bool pinned_variant = false;  // unroll / non-temporal loads set through the environment
+    int force_cols = 0;           // 32, 16 or 8: this column format where a matrix has it (environment)
     int split = -1;               // Jacobi in split form: 1 always, 0 never, -1 by size (environment)
     DBuf<double> x64, r64, p64, q64, z64, w64, t64;
     DBuf<float> x32, r32, p32, q32, z32, w32;
