@@ -220,10 +220,16 @@ def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96,
             if wait > 0:
                 time.sleep(wait)
     total = time.perf_counter() - t0
+    bs = srv.stats()
     srv.close()
+    achieved = bs["batch_bytes"] / (bs["batch_ms"] / 1e3) / 1e9 if bs["batch_ms"] > 0 else 0.0
+    # the batched iterations (SpMV + p.q, update, close of every resident system) against HBM peak
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "batch_ms": round(bs["batch_ms"], 3),
+            "batch_bytes": bs["batch_bytes"], "system_iterations": bs["batch_iterations"]}
     return {"solves_per_sec": round(len(reqs) / (total - arrivals[0]), 3), **_percentiles(lat),
             "seconds": round(total, 3), "steps": steps, "peak_resident": peak, "inner_iterations": inner,
-            "outer_iterations": outer, "failed": status_bad}, keff
+            "outer_iterations": outer, "failed": status_bad, "batched_iterations_roofline": roof}, keff
 
 
 SERVE_GOLDEN = os.path.join(ROOT, "tests", "golden", "serve512_every16")
@@ -435,7 +441,65 @@ def _parallel_paths(dev, n, orders, threads):
     return out, wall
 
 
-def cracking_processes(ctx, dev, n_det=(16, 24), n_mc=(8, 16), paths=8, threads=8, seed=7):
+def served_paths(ctx, dev, n, orders, precision=1, max_slots=128, chunk=8, budget=8 << 30, max_steps=None):
+    """Monte Carlo cracking paths as served requests: every step of every path is one request to one
+    server (one more face cracked, warm-started from the path's last temperature), all on the topology,
+    geometry and pattern of one prepared mesh; a path submits its next step when its result arrives,
+    until the domain stops conducting (k_eff <= 1e-12 of its start).  Returns per path the k_eff after
+    every step, and the wall time, the steps and the server's batch counters."""
+    import torch
+
+    import paper_2104_05999_amd as dec
+
+    xyz, tets = W.kuhn_cube(n, device=dev)
+    bt, bv, side = (torch.as_tensor(a, device=dev) for a in W.x_sides(n))
+    base = ctx.mesh(xyz, tets)
+    base.hodge1(torch.ones(base.E, dtype=torch.float64, device=dev), want_cut=False, want_star=False)
+    base.assemble()
+    paths = [{"kappa": torch.ones(base.E, dtype=torch.float64, device=dev),
+              "T": [torch.zeros(base.V, dtype=torch.float64, device=dev) for _ in range(2)], "step": 0, "ks": [],
+              "its": 0} for _ in orders]
+    srv = dec.Server(ctx, budget, precision=precision, max_slots=max_slots, chunk=chunk, tol=1e-10)
+
+    def submit(i):
+        p, k = paths[i], paths[i]["step"]
+        req = {"mesh": base, "kappa": p["kappa"], "bc_type": bt, "bc_value": bv, "side": side, "T_out": p["T"][k % 2]}
+        if k > 0:
+            req["T0"] = p["T"][(k - 1) % 2]
+        srv.submit(req, user_tag=i)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(orders)):
+        submit(i)
+    active, status = len(orders), 0
+    while active:
+        srv.step()
+        for res in srv.poll():
+            i = res["user_tag"]
+            p = paths[i]
+            p["ks"].append(res["k_eff"])
+            p["its"] += res["inner_iterations"]
+            status = status or res["status"]
+            limit = len(orders[i]) if max_steps is None else min(max_steps, len(orders[i]))
+            if res["status"] != 0 or res["k_eff"] <= 1e-12 * p["ks"][0] or p["step"] >= limit:
+                active -= 1
+                continue
+            p["kappa"][int(orders[i][p["step"]])] = 0.0
+            p["step"] += 1
+            submit(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    counters = srv.stats()
+    srv.close()
+    base.close()
+    return {"ks": [p["ks"] for p in paths], "steps": [p["step"] for p in paths],
+            "inner_iterations": sum(p["its"] for p in paths), "wall_seconds": wall, "status": status,
+            "batch": counters}
+
+
+def cracking_processes(ctx, dev, n_det=(16, 24), n_mc=(8, 16), paths=8, threads=8, seed=7, served_n=8,
+                       served_paths_count=100):
     """Section 3's cracking processes on homogeneous Kuhn cubes: the deterministic one (crack the
     face of largest flux density) on each n_det^3 (24^3 has 45,000 faces, the size of the paper's
     mesh), and `paths` Monte Carlo paths (faces in seeded random orders) on each n_mc^3, run
@@ -460,6 +524,36 @@ def cracking_processes(ctx, dev, n_det=(16, 24), n_mc=(8, 16), paths=8, threads=
                                   "max": round(max(dn), 4)},
             "steps": steps, "wall_seconds": round(wall, 3), "steps_per_sec": round(steps / wall, 1),
             "k_eff_curve_path0": mc[0]["k_eff_curve"]})
+    # the Monte Carlo paths as served requests (one request per step, warm-started, mixed precision)
+    n = served_n
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    faces = _faces_of(ctx, dev, n)
+    orders = [rng.permutation(faces) for _ in range(served_paths_count)]
+    r = served_paths(ctx, dev, n, orders)
+    nf = len(faces)
+    dn = [st / nf for st in r["steps"]]
+    grid = np.linspace(0.0, 0.8, 17)
+    curves = np.full((len(orders), len(grid)), np.nan)
+    for i, ks in enumerate(r["ks"]):  # k_eff / k_eff(0) at D_n = grid (0 beyond separation)
+        d = np.arange(len(ks)) / nf
+        rel = np.asarray(ks) / ks[0]
+        curves[i] = np.interp(grid, d, rel, right=0.0)
+    steps = sum(len(ks) for ks in r["ks"])
+    print(f"[bench] cracking n={n}: {len(orders)} served paths, {steps} requests in {r['wall_seconds']:.1f} s",
+          file=sys.stderr, flush=True)
+    out["stochastic_served"] = {
+        "workload": f"kuhn{n}_homogeneous_{len(orders)}paths_seed{seed + 1}", "paths": len(orders), "faces": nf,
+        "how": "one request per step to one mixed-precision server, warm-started from the path's last T, "
+               "topology copied from one prepared mesh",
+        "requests": steps, "wall_seconds": round(r["wall_seconds"], 3),
+        "steps_per_sec": round(steps / r["wall_seconds"], 1), "inner_iterations": r["inner_iterations"],
+        "status": r["status"],
+        "D_n_at_separation": {"mean": round(float(np.mean(dn)), 4), "min": round(min(dn), 4), "max": round(max(dn), 4),
+                              "all": [round(x, 4) for x in dn]},
+        "k_eff_vs_D_n": {"D_n": [round(float(g), 3) for g in grid],
+                         "mean": [round(float(v), 5) for v in curves.mean(axis=0)],
+                         "min": [round(float(v), 5) for v in curves.min(axis=0)],
+                         "max": [round(float(v), 5) for v in curves.max(axis=0)]}}
     return out
 
 

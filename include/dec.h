@@ -456,9 +456,17 @@ typedef struct dec_request {
     const double* T0;          /* [V] device or NULL: initial guess (warm start, e.g. the
                                   previous step of a cracking path); Dirichlet values and
                                   pinned zeros are imposed on it                          */
+    const dec_mesh* mesh;      /* NULL, or a mesh of vertex unknowns from dec_build_topology
+                                  on the server's device with V and T as above: the server
+                                  copies its topology (and its geometry and solver pattern
+                                  when it has them, after dec_hodge1 / dec_assemble)
+                                  instead of building them from xyz and tets, which may then
+                                  be NULL; many requests on one mesh (the steps of cracking
+                                  paths) share that work                                  */
 } dec_request;
 /* The request's input arrays must stay valid until its result is polled
- * (they are read when the request is admitted); T_out likewise. */
+ * (they are read when the request is admitted); T_out likewise, and the
+ * request's mesh, which must not change or be destroyed before then. */
 
 typedef struct dec_result {
     uint64_t ticket;
@@ -510,6 +518,17 @@ int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out)
 /* Cancel a pending or admitted request; its result has status DEC_ECANCELED.
  * DEC_EINVAL when the ticket is unknown or already finished. */
 int dec_server_cancel(dec_server* s, uint64_t ticket);
+/* Counters of the batched inner iterations since the server was created (for
+ * the roofline of serving; host outputs, each NULL ok): batch_ms, the time of
+ * the steps' graph replays (HIP events on the server's stream); batch_bytes,
+ * the algorithmic bytes of the iterations they ran, per system and iteration
+ * kept entries x (value + column bytes) + 4 (V + 1) + 14 V value bytes (the
+ * product's row pointer, x and y; the update's r, q, D^-1 and r; the closing
+ * kernel's D^-1, r, p, x, x and p); batch_iterations, the system-iterations
+ * run.  The server's batched product picks its variant (entry pairs in
+ * flight, non-temporal loads) per precision by timing it on the first batch
+ * of that precision; the choice changes no result. */
+int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations);
 int dec_server_destroy(dec_server* s);
 
 #ifdef __cplusplus

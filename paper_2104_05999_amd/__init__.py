@@ -377,8 +377,9 @@ class Server:
     A request is a dict of device tensors: xyz [V,3] f64, tets [T,4] i32,
     kappa [E] f64 (optional), cracks [n,7] f64 (optional), bc_type [V] i8,
     bc_value [V] f64, neumann_f0 [V] f64 (optional), side [V] i8 (optional),
-    T_out [V] f64 (optional), T0 [V] f64 (optional warm start), and scalars
-    length/area/dT.  The tensors are
+    T_out [V] f64 (optional), T0 [V] f64 (optional warm start), mesh (optional Mesh
+    whose topology the server copies instead of building it from xyz and tets),
+    and scalars length/area/dT.  The tensors are
     kept referenced until the request's result has been polled.
     """
 
@@ -399,13 +400,18 @@ class Server:
         self._keep = {}
 
     def submit(self, req, user_tag=0):
-        V, T = int(req["xyz"].shape[0]), int(req["tets"].shape[0])
+        mesh = req.get("mesh")
+        if mesh is not None:
+            V, T = mesh.V, mesh.T
+        else:
+            V, T = int(req["xyz"].shape[0]), int(req["tets"].shape[0])
         cracks = req.get("cracks")
         n = 0 if cracks is None else int(cracks.shape[0])
         r = _lib.Request()
         r.V, r.T = V, T
-        r.xyz = _ptr(req["xyz"], torch.float64, 3 * V, "xyz")
-        r.tets = _ptr(req["tets"], torch.int32, 4 * T, "tets")
+        r.xyz = _ptr(req.get("xyz"), torch.float64, 3 * V, "xyz")
+        r.tets = _ptr(req.get("tets"), torch.int32, 4 * T, "tets")
+        r.mesh = mesh.handle if mesh is not None else None
         r.kappa = _ptr(req.get("kappa"), torch.float64, None, "kappa")
         r.n_cracks = n
         r.cracks = _ptr(cracks, torch.float64, 7 * n, "cracks") if n else None
@@ -440,6 +446,13 @@ class Server:
 
     def cancel(self, ticket):
         return self.lib.dec_server_cancel(self.handle, int(ticket))
+
+    def stats(self):
+        """Batched inner iterations so far: replay time (ms), algorithmic bytes, system-iterations."""
+        ms, by, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(it)),
+                       "dec_server_stats")
+        return {"batch_ms": ms.value, "batch_bytes": by.value, "batch_iterations": it.value}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -71,7 +71,7 @@ class Request(ctypes.Structure):
         ("V", ctypes.c_int64), ("xyz", vp), ("T", ctypes.c_int64), ("tets", vp), ("kappa", vp),
         ("n_cracks", ctypes.c_int32), ("cracks", vp), ("bc_type", vp), ("bc_value", vp), ("neumann_f0", vp),
         ("side", vp), ("length", ctypes.c_double), ("area", ctypes.c_double), ("dT", ctypes.c_double),
-        ("T_out", vp), ("user_tag", ctypes.c_uint64), ("T0", vp),
+        ("T_out", vp), ("user_tag", ctypes.c_uint64), ("T0", vp), ("mesh", vp),
     ]
 
 
@@ -133,6 +133,7 @@ SIGNATURES = {
     "dec_server_step": (c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_poll": (c_int, [vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_cancel": (c_int, [vp, ctypes.c_uint64]),
+    "dec_server_stats": (c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
     "dec_server_destroy": (c_int, [vp]),
 }
 

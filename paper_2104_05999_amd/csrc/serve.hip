@@ -24,6 +24,7 @@
 #include "solver.h"
 
 void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets);
+void clone_topology_device(dec_mesh* m, const dec_mesh* src);
 void hodge1_device(dec_mesh* m, const double* kappa, int32_t n_cracks, const double* cracks);
 void assemble_device(dec_mesh* m);
 void apply_bc_internal(dec_mesh* m, const int8_t* bc_type, const double* bc_value, const double* f0);
@@ -37,8 +38,12 @@ enum { Q_PQ = 0, Q_RR = 1, Q_RZ = 2, Q_OUT = 3 };  // partial regions, nchunks d
 // Device descriptor of one admitted system.
 struct BSlot {
     const int64_t* sptr;
-    const int32_t* scol;   // int32 columns, null when the 16-bit offsets are kept instead
+    const int32_t* scol;   // int32 columns, null when a more compact format is kept instead
     const int16_t* sdcol;  // 16-bit column offsets, or null
+    const uint8_t* stcol;  // one-byte indices into sotab, or null
+    const int32_t* sotab;  // [sntab] the column offsets stcol indexes
+    int32_t sntab;
+    int32_t pad3;
     const double* sval64;
     const float* sval32;
     const double* invd64;
@@ -104,33 +109,73 @@ __device__ __forceinline__ void chunk_rows(const BSlot& S, int c, int64_t* r0, i
 }
 
 // ---------------------------------------------------------------- batched inner PCG
+// A system's matrix as the product reads it: in the most compact column format
+// the system keeps (one-byte table indices, 16-bit offsets, int32 columns).
+template <class VT>
+__device__ __forceinline__ SellView<VT> slot_view(const BSlot& S, const VT* val) {
+    SellView<VT> A{S.sptr, S.scol, val, S.nslices, S.V, nullptr, S.sdcol};
+    A.tcol = S.stcol;
+    A.otab = S.sotab;
+    A.ntab = S.sntab;
+    return A;
+}
+
+// y = A x over the rows of one work item (the slices [s0, s1)), in column
+// format CF; the sum of w[row] * y[row] (w = x for DOT, b for RESID's r.r).
+template <class VT, int U, bool NT, int CF, bool RESID>
+__device__ __forceinline__ VT item_product(const SellView<VT>& A, int64_t s0, int64_t s1, const VT* __restrict__ x,
+                                           VT* __restrict__ y, const VT* __restrict__ b, const int32_t* tab) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    VT d = 0;
+    for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
+        const int64_t base = A.ptr[s];
+        const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
+        const int64_t row = s * SELL_C + lane;
+        const int32_t rowc = static_cast<int32_t>(CF == CF_U8 && row >= A.V ? A.V - 1 : row);
+        const VT acc = sell_row<VT, U, NT, false, CF>(A, base, width, lane, x, VT(0), rowc, tab);
+        if (row < A.V) {
+            if (RESID) {
+                const VT ri = b[row] - acc;
+                y[row] = ri;
+                d += ri * ri;
+            } else {
+                y[row] = acc;
+                d += x[row] * acc;
+            }
+        }
+    }
+    return d;
+}
+
+// item_product in the format the system keeps; a one-byte table is first
+// staged in LDS (the block's threads all take this item; the barrier of the
+// previous item's block sum has ended that item's reads of the table).
+template <class VT, int U, bool NT, bool RESID>
+__device__ __forceinline__ VT item_product_any(const BSlot& S, const SellView<VT>& A, int64_t s0, int64_t s1,
+                                               const VT* __restrict__ x, VT* __restrict__ y, const VT* __restrict__ b,
+                                               int32_t* tab) {
+    if (A.tcol) {
+        stage_offsets(A.otab, A.ntab, tab);
+        return item_product<VT, U, NT, CF_U8, RESID>(A, s0, s1, x, y, b, tab);
+    }
+    if (A.dcol) return item_product<VT, U, NT, CF_I16, RESID>(A, s0, s1, x, y, b, tab);
+    return item_product<VT, U, NT, CF_I32, RESID>(A, s0, s1, x, y, b, tab);
+}
+
 template <class VT, int U, bool NT>
 __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                      const int32_t* __restrict__ n_items, int par) {
     __shared__ double lds[BLOCK / 64 + 1];
+    __shared__ int32_t tab[OTAB_MAX];
     const int n = *n_items;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
         if (S.st[par].done) continue;
-        const SellView<VT> A{S.sptr, S.scol, SlotVec<VT>::val(S), S.nslices, S.V, nullptr, S.sdcol};
-        const VT* p = SlotVec<VT>::p(S);
-        VT* q = SlotVec<VT>::q(S);
+        const SellView<VT> A = slot_view<VT>(S, SlotVec<VT>::val(S));
         const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
         const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
-        VT d = 0;
-        for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
-            const int64_t base = A.ptr[s];
-            const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
-            const int64_t row = s * SELL_C + lane;
-            const VT acc = A.dcol ? sell_row<VT, U, NT, false, true>(A, base, width, lane, p, VT(0), (int32_t)row)
-                                  : sell_row<VT, U, NT>(A, base, width, lane, p);
-            if (row < A.V) {
-                q[row] = acc;
-                d += p[row] * acc;
-            }
-        }
+        const VT d = item_product_any<VT, U, NT, false>(S, A, s0, s1, SlotVec<VT>::p(S), SlotVec<VT>::q(S), nullptr, tab);
         const double bs = block_sum(static_cast<double>(d), lds);
         if (threadIdx.x == 0) S.part[Q_PQ * S.nchunks + item.chunk] = bs;
     }
@@ -318,27 +363,14 @@ __global__ void bk_undo(const BSlot* __restrict__ slots, const BItem* __restrict
 __global__ __launch_bounds__(BLOCK) void bk_residual(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                      int n) {
     __shared__ double lds[BLOCK / 64 + 1];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ int32_t tab[OTAB_MAX];
     ITEM_LOOP(it, n) {
         const BItem item = items[it];
         const BSlot& S = slots[item.slot];
-        const SellView<double> A{S.sptr, S.scol, S.sval64, S.nslices, S.V, nullptr, S.sdcol};
+        const SellView<double> A = slot_view<double>(S, S.sval64);
         const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
         const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
-        double d = 0.0;
-        for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
-            const int64_t base = A.ptr[s];
-            const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
-            const int64_t row = s * SELL_C + lane;
-            const double acc = A.dcol ? sell_row<double, 4, true, false, true>(A, base, width, lane, S.x64, 0.0,
-                                                                              (int32_t)row)
-                                      : sell_row<double, 4, true>(A, base, width, lane, S.x64);
-            if (row < A.V) {
-                const double ri = S.b[row] - acc;
-                S.r64[row] = ri;
-                d += ri * ri;
-            }
-        }
+        const double d = item_product_any<double, 4, true, true>(S, A, s0, s1, S.x64, S.r64, S.b, tab);
         const double bs = block_sum(d, lds);
         if (threadIdx.x == 0) S.part[Q_OUT * S.nchunks + item.chunk] = bs;
     }
@@ -453,6 +485,7 @@ struct ServeSlot {
     bool fresh = true;      // no inner solve yet
     bool fallback = false;  // a mixed-precision system that went on in FP64
     bool broke = false;     // its last FP64 inner solve broke down
+    int64_t iter_mark = 0;  // inner iterations of the current inner solve already counted in the batch bytes
 };
 
 struct dec_server {
@@ -482,6 +515,13 @@ struct dec_server {
     int max_items = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] FP64 inner, [1] FP32 inner
     hipEvent_t ev_chunk = nullptr;
+    // batched SpMV variant per precision ([0] FP64, [1] FP32), tuned on the live batch
+    int unroll[2] = {4, 4};
+    int nt[2] = {1, 0};
+    bool tuned[2] = {false, false};
+    hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;  // around a step's graph replays (timing)
+    double batch_ms = 0, batch_bytes = 0;         // replay time and algorithmic bytes of the batched iterations
+    int64_t batch_iterations = 0;                 // system-iterations in them
 };
 
 namespace {
@@ -520,7 +560,9 @@ void compact_mesh(dec_mesh* m) {
     m->val64.release();
     m->val32.release();
     m->sell.src.release();
-    if (m->sell.dcol.p) m->sell.col.release();  // the product reads the 16-bit offsets
+    // the products read the most compact column format the system has
+    if (m->sell.tcol.p) m->sell.dcol.release();
+    if (m->sell.tcol.p || m->sell.dcol.p) m->sell.col.release();
     m->geo.release();
 }
 
@@ -531,6 +573,9 @@ BSlot describe(dec_server* s, int k) {
     d.sptr = m->sell.ptr.p;
     d.scol = m->sell.col.p;
     d.sdcol = m->sell.dcol.p;
+    d.stcol = m->sell.tcol.p;
+    d.sotab = m->sell.otab.p;
+    d.sntab = m->sell.ntab;
     d.sval64 = m->sell.val64.p;
     d.sval32 = m->sell.val32.p;
     d.invd64 = m->invdiag64.p;
@@ -582,7 +627,10 @@ bool admit(dec_server* s, const ServeReq& q, int k) {
     try {
         // the caller's writes to the request arrays (on its stream, before submit) come first
         HIP_CHECK(hipStreamWaitEvent(s->setup_stream, q.inputs, 0));
-        build_topology_device(m, q.req.xyz, q.req.tets);
+        if (q.req.mesh)
+            clone_topology_device(m, q.req.mesh);
+        else
+            build_topology_device(m, q.req.xyz, q.req.tets);
         hodge1_device(m, q.req.kappa, q.req.n_cracks, q.req.cracks);
         assemble_device(m);
         apply_bc_internal(m, q.req.bc_type, q.req.bc_value, q.req.neumann_f0);
@@ -643,18 +691,82 @@ void upload_slots(dec_server* s) {
 }
 
 template <class VT>
+void launch_batched_spmv(dec_server* s, int unroll, int nt, const BItem* items, const int32_t* n_items, int par) {
+    const dim3 g(s->G), b(BLOCK);
+    const BSlot* sl = s->d_slots.p;
+#define BK_SPMV(U, NT) hipLaunchKernelGGL((bk_spmv_dot<VT, U, NT>), g, b, 0, s->solve_stream, sl, items, n_items, par)
+    if (nt) {
+        if (unroll == 2) BK_SPMV(2, true);
+        else if (unroll == 3) BK_SPMV(3, true);
+        else BK_SPMV(4, true);
+    } else {
+        if (unroll == 2) BK_SPMV(2, false);
+        else if (unroll == 3) BK_SPMV(3, false);
+        else BK_SPMV(4, false);
+    }
+#undef BK_SPMV
+}
+
+template <class VT>
 void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t* n_items, int par) {
     const dim3 g(s->G), b(BLOCK);
-    if (sizeof(VT) == 8)
-        hipLaunchKernelGGL((bk_spmv_dot<VT, 4, true>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
-    else
-        hipLaunchKernelGGL((bk_spmv_dot<VT, 4, false>), g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
+    const int pi = sizeof(VT) == 8 ? 0 : 1;
+    launch_batched_spmv<VT>(s, s->unroll[pi], s->nt[pi], items, n_items, par);
     hipLaunchKernelGGL(bk_update<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
     hipLaunchKernelGGL(bk_close<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
 }
 
+// Pick the batched SpMV variant (2, 3 or 4 entry pairs in flight, non-temporal
+// loads on or off) for a precision by timing it on the batch about to run:
+// three rounds of two launches per variant, each variant's best round.  The
+// extra launches recompute q = A p and the p.q partials of the same p, which
+// the batch's first iteration computes again, and every variant sums each row
+// in the same order, so the choice changes no result.
+template <class VT>
+void tune_batched_spmv(dec_server* s, const BItem* items, const int32_t* n_items) {
+    const int pi = sizeof(VT) == 8 ? 0 : 1;
+    const int cand[6][2] = {{4, 1}, {4, 0}, {3, 1}, {3, 0}, {2, 1}, {2, 0}};
+    float best[6];
+    for (int k = 0; k < 6; ++k) best[k] = 1e30f;
+    for (int round = 0; round < 3; ++round)
+        for (int k = 0; k < 6; ++k) {
+            launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], items, n_items, 0);
+            HIP_CHECK(hipEventRecord(s->ev_b0, s->solve_stream));
+            for (int r = 0; r < 2; ++r) launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], items, n_items, 0);
+            HIP_CHECK(hipEventRecord(s->ev_b1, s->solve_stream));
+            HIP_CHECK(hipEventSynchronize(s->ev_b1));
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, s->ev_b0, s->ev_b1));
+            if (ms < best[k]) best[k] = ms;
+        }
+    int pick = 0;
+    for (int k = 1; k < 6; ++k)
+        if (best[k] < best[pick]) pick = k;
+    s->unroll[pi] = cand[pick][0];
+    s->nt[pi] = cand[pick][1];
+    s->tuned[pi] = true;
+}
+
+// Algorithmic bytes of one batched iteration of a system: the product
+// (kept entries x (value + column) + row pointer + x and y, the CSR
+// definition over the entries it uses) and the vector kernels (update: r, q,
+// D^-1 read, r written; close: D^-1, r, p, x read, x and p written).
+double batched_iteration_bytes(const dec_mesh* m, int mode) {
+    const double sv = mode == DEC_PREC_MIXED ? 4.0 : 8.0;
+    const double cb = m->sell.tcol.p ? 1.0 : m->sell.dcol.p ? 2.0 : 4.0;
+    const double V = (double)m->V;
+    return (double)m->sell.kept * (sv + cb) + 4.0 * (V + 1) + 2.0 * sv * V + 4.0 * sv * V + 6.0 * sv * V;
+}
+
 hipGraphExec_t batched_graph(dec_server* s, int prec) {
     if (s->graph[prec]) return s->graph[prec];
+    // prec: 0 FP64 (graph and tuning index 0), 1 FP32 (index 1)
+    if (!s->tuned[prec]) {
+        if (prec == 1)
+            tune_batched_spmv<float>(s, s->d_items32.p, s->d_n.p);
+        else
+            tune_batched_spmv<double>(s, s->d_items64.p, s->d_n.p + 1);
+    }
     const int chunk = s->opts.chunk;
     hipGraph_t g;
     HIP_CHECK(hipStreamBeginCapture(s->solve_stream, hipStreamCaptureModeThreadLocal));
@@ -859,6 +971,7 @@ void outer_steps(dec_server* s, const std::vector<int>& ids) {
             ServeSlot& sl = s->slots[k];
             if (sl.phase != PH_INNER) sl.t_start = sl.t_start > 0 ? sl.t_start : now_ms(s->t0);
             sl.phase = PH_INNER;
+            sl.iter_mark = 0;  // a new inner solve
         }
     }
 }
@@ -901,6 +1014,9 @@ int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_op
         HIP_CHECK(hipStreamCreateWithFlags(&s->solve_stream, hipStreamNonBlocking));
         HIP_CHECK(hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking));
         HIP_CHECK(hipEventCreateWithFlags(&s->ev_chunk, hipEventDisableTiming));
+        // timing events without the system-scope fence (its cache writeback would slow the batch)
+        HIP_CHECK(hipEventCreateWithFlags(&s->ev_b0, hipEventDisableSystemFence));
+        HIP_CHECK(hipEventCreateWithFlags(&s->ev_b1, hipEventDisableSystemFence));
         s->setup_ctx.device = ctx->device;
         s->setup_ctx.stream = s->setup_stream;
         s->setup_ctx.alloc = ctx->alloc;
@@ -938,8 +1054,12 @@ int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_op
 int dec_server_submit(dec_server* s, const dec_request* req, uint64_t* ticket) {
     if (!s || !req) return DEC_EINVAL;
     try {
-        DEC_REQUIRE(req->V > 0 && req->T > 0 && req->xyz && req->tets && req->bc_type && req->bc_value,
-                    DEC_EINVAL, "request needs xyz, tets, bc_type and bc_value");
+        if (req->mesh)
+            DEC_REQUIRE(req->V == req->mesh->V && req->T == req->mesh->T && !req->mesh->dual &&
+                            req->mesh->ctx->device == s->ctx->device,
+                        DEC_EINVAL, "a request's mesh must match its V and T, hold vertex unknowns and share the device");
+        DEC_REQUIRE(req->V > 0 && req->T > 0 && (req->mesh || (req->xyz && req->tets)) && req->bc_type && req->bc_value,
+                    DEC_EINVAL, "request needs a mesh or xyz and tets, and bc_type and bc_value");
         DEC_REQUIRE(req->n_cracks >= 0 && (req->n_cracks == 0 || req->cracks), DEC_EINVAL, "bad crack array");
         DEC_REQUIRE(estimate_bytes(req->V, req->T) <= (int64_t)s->budget, DEC_EBUDGET,
                     "request does not fit the HBM budget even alone");
@@ -985,8 +1105,12 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             s->h_n[0] = n32;
             s->h_n[1] = n64;
             HIP_CHECK(hipMemcpyAsync(s->d_n.p, s->h_n, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s->solve_stream));
-            if (n32) HIP_CHECK(hipGraphLaunch(batched_graph(s, 1), s->solve_stream));
-            if (n64) HIP_CHECK(hipGraphLaunch(batched_graph(s, 0), s->solve_stream));
+            hipGraphExec_t g32 = n32 ? batched_graph(s, 1) : nullptr;  // captured (and tuned) on first use
+            hipGraphExec_t g64 = n64 ? batched_graph(s, 0) : nullptr;
+            HIP_CHECK(hipEventRecord(s->ev_b0, s->solve_stream));
+            if (g32) HIP_CHECK(hipGraphLaunch(g32, s->solve_stream));
+            if (g64) HIP_CHECK(hipGraphLaunch(g64, s->solve_stream));
+            HIP_CHECK(hipEventRecord(s->ev_b1, s->solve_stream));
             HIP_CHECK(hipEventRecord(s->ev_chunk, s->solve_stream));
             launched = true;
         }
@@ -1010,6 +1134,19 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
         HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost,
                                  s->solve_stream));
         HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+        if (launched) {  // the batch's replay time and the iterations it ran
+            float ms = 0.0f;
+            HIP_CHECK(hipEventElapsedTime(&ms, s->ev_b0, s->ev_b1));
+            s->batch_ms += ms;
+            for (int prec = 0; prec < 2; ++prec)
+                for (int k : inner[prec]) {
+                    ServeSlot& sl = s->slots[k];
+                    const int64_t ran = s->h_st[3 * k].iter - sl.iter_mark;
+                    s->batch_iterations += ran;
+                    s->batch_bytes += (double)ran * batched_iteration_bytes(sl.mesh, sl.mode);
+                    sl.iter_mark = s->h_st[3 * k].iter;
+                }
+        }
         std::vector<int> outer;
         for (int k = 0; k < ns; ++k) {
             ServeSlot& sl = s->slots[k];
@@ -1041,6 +1178,14 @@ int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out)
     for (int i = 0; i < n; ++i) out[i] = s->done[i];
     s->done.erase(s->done.begin(), s->done.begin() + n);
     *n_out = n;
+    return DEC_OK;
+}
+
+int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations) {
+    if (!s) return DEC_EINVAL;
+    if (batch_ms) *batch_ms = s->batch_ms;
+    if (batch_bytes) *batch_bytes = s->batch_bytes;
+    if (batch_iterations) *batch_iterations = s->batch_iterations;
     return DEC_OK;
 }
 
@@ -1109,6 +1254,8 @@ int dec_server_destroy(dec_server* s) {
     if (s->h_ids) (void)hipHostFree(s->h_ids);
     if (s->h_st) (void)hipHostFree(s->h_st);
     if (s->ev_chunk) (void)hipEventDestroy(s->ev_chunk);
+    if (s->ev_b0) (void)hipEventDestroy(s->ev_b0);
+    if (s->ev_b1) (void)hipEventDestroy(s->ev_b1);
     if (s->setup_ctx.pinned) (void)hipHostFree(s->setup_ctx.pinned);
     if (s->solve_stream) (void)hipStreamDestroy(s->solve_stream);
     if (s->setup_stream) (void)hipStreamDestroy(s->setup_stream);

@@ -455,6 +455,63 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
 }
 
 
+// The topology of src copied into the empty mesh m (same device, m's stream),
+// with src's geometry (the dual areas over edge lengths) when src has it and
+// its sliced-ELL pattern when src built one for the same pruning: what
+// build_topology_device, the geometry and the pattern build would compute for
+// src's xyz and tets, without their kernels and read-backs.
+void clone_topology_device(dec_mesh* m, const dec_mesh* src) {
+    DEC_REQUIRE(!src->dual && src->tets.p && src->vt_list.p && src->et_inc.p, DEC_EINVAL,
+                "a request's mesh must be a mesh of vertex unknowns from dec_build_topology");
+    dec_ctx* ctx = m->ctx;
+    hipStream_t s = ctx->stream;
+    m->V = src->V;
+    m->T = src->T;
+    m->E = src->E;
+    m->F = src->F;
+    m->Fb = src->Fb;
+    m->nnz = src->nnz;
+    auto dup = [&](auto& dst, const auto& from, int64_t count) {
+        dst.alloc(ctx, count);
+        if (count) HIP_CHECK(hipMemcpyAsync(dst.p, from.p, count * sizeof(*from.p), hipMemcpyDeviceToDevice, s));
+    };
+    const int64_t V = m->V, T = m->T, E = m->E, nnz = m->nnz;
+    dup(m->xyz, src->xyz, 3 * V);
+    dup(m->tets, src->tets, 4 * T);
+    dup(m->vt_ptr, src->vt_ptr, V + 1);
+    dup(m->vt_list, src->vt_list, 4 * T);
+    dup(m->edges, src->edges, 2 * E);
+    dup(m->up_ptr, src->up_ptr, V + 1);
+    dup(m->et_ptr, src->et_ptr, E + 1);
+    dup(m->et_inc, src->et_inc, 6 * T);
+    dup(m->tet_bface, src->tet_bface, T);
+    dup(m->row_ptr, src->row_ptr, V + 1);
+    dup(m->col, src->col, nnz);
+    dup(m->nz_edge, src->nz_edge, nnz);
+    dup(m->diag_pos, src->diag_pos, V);
+    if (src->geo_ready) {
+        dup(m->geo, src->geo, E);
+        std::memcpy(m->extent, src->extent, sizeof(m->extent));
+        m->geo_ready = true;
+    }
+    const SellMatrix& S = src->sell;
+    if (S.nslices && S.src.p && src->prune_geometric_zeros == m->prune_geometric_zeros) {
+        SellMatrix& D = m->sell;
+        D.nslices = S.nslices;
+        D.entries = S.entries;
+        D.kept = S.kept;
+        D.ntab = S.ntab;
+        dup(D.ptr, S.ptr, S.nslices + 1);
+        dup(D.col, S.col, S.entries);
+        dup(D.src, S.src, S.entries);
+        if (S.dcol.p) dup(D.dcol, S.dcol, S.entries);
+        if (S.tcol.p) dup(D.tcol, S.tcol, S.entries);
+        if (S.otab.p) dup(D.otab, S.otab, S.ntab);
+        D.val64.alloc(ctx, S.entries);
+        D.val32.alloc(ctx, S.entries);
+    }
+}
+
 extern "C" {
 
 int dec_build_topology(dec_ctx* ctx, int64_t V, const double* xyz, int64_t T, const int32_t* tets, dec_mesh** out) {

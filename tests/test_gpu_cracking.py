@@ -171,3 +171,43 @@ def test_paths_from_parallel_threads_match_sequential(dev):
     for c in ctxs:
         c.close()
     assert par == seq
+
+
+def test_monte_carlo_paths_served_with_warm_starts(ctx, dev):
+    """Monte Carlo paths as served requests (bench.served_paths: one request per step, warm-started
+    from the path's last temperature, the topology copied from one prepared mesh), mixed precision
+    at 1e-10: after every crack k_eff equals that of the same path solved step by step with
+    dec_solve (FP64, warm-started) to 1e-9 of the uncracked value, and path 0 equals the oracle's
+    step by step (direct solves)."""
+    import bench
+    n, paths, steps = 4, 4, 60
+    rng = np.random.Generator(np.random.PCG64(31))
+    xyz, tets = W.kuhn_cube(n)
+    bt, bv, side = W.x_sides(n)
+    E = W.kuhn_counts(n)["E"]
+    s0 = C.CrackingSystem(xyz, tets, np.ones(E), bt, bv, side)
+    faces = np.flatnonzero(C.faces(s0.area))
+    orders = [rng.permutation(faces)[:steps] for _ in range(paths)]
+    served = bench.served_paths(ctx, dev, n, orders, precision=1, max_steps=steps)
+    assert served["status"] == 0 and served["steps"] == [steps] * paths
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), device=dev)  # noqa: E731
+    for i, order in enumerate(orders):
+        m = ctx.mesh(t(xyz), t(tets))
+        kappa = torch.ones(E, dtype=torch.float64, device=dev)
+        T, f = _gpu_solve(m, kappa, t(bt), t(bv), t(side))
+        ks = [f["k_eff"]]
+        for e in order:
+            kappa[int(e)] = 0.0
+            T, f = _gpu_solve(m, kappa, t(bt), t(bv), t(side), T)
+            ks.append(f["k_eff"])
+        m.close()
+        k0 = ks[0]
+        assert len(served["ks"][i]) == len(ks)
+        assert max(abs(a - b) for a, b in zip(served["ks"][i], ks)) <= 1e-9 * k0, i
+    s = C.CrackingSystem(xyz, tets, np.ones(E), bt, bv, side)
+    _, fo = s.solve()
+    ko = [fo["k_eff"]]
+    for e in orders[0]:
+        s.crack(int(e))
+        ko.append(s.solve()[1]["k_eff"])
+    assert max(abs(a - b) for a, b in zip(served["ks"][0], ko)) <= 1e-9 * ko[0]

@@ -238,3 +238,32 @@ def test_served_warm_start(ctx, dev):
     assert out2[0]["status"] == 0 and out2[0]["inner_iterations"] < cold[0]["inner_iterations"]
     x_ref, _ = oracle_reference(host)
     assert np.linalg.norm(near["T_out"].cpu().numpy() - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_server_batch_counters(ctx, dev, precision):
+    """dec_server_stats: the system-iterations its batches ran are the results' inner iterations;
+    the bytes are those of the batched kernels (per iteration between 14 and 20 value-sized words
+    per row plus the product's entries), over a positive replay time."""
+    import paper_2104_05999_amd as dec
+    built = [make_request(n, c, 80 + n, dev) for n, c in ((10, 6), (14, 9), (20, 12))]
+    srv = dec.Server(ctx, 4 << 30, precision=precision, tol=1e-10)
+    for k, (req, _) in enumerate(built):
+        srv.submit(req, user_tag=k)
+    out = {}
+    for _ in range(20000):
+        srv.step()
+        for res in srv.poll():
+            out[res["user_tag"]] = res
+        if len(out) == len(built):
+            break
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in out.values())
+    its = sum(r["inner_iterations"] for r in out.values())
+    assert st["batch_iterations"] == its and its > 0
+    sv = 4 if precision == 1 else 8
+    rows = sum((n + 1) ** 3 for n in (10, 14, 20)) / 3
+    per_it = st["batch_bytes"] / its
+    assert 14 * sv * rows * 0.5 < per_it < (20 * sv + 15 * (sv + 4)) * rows * 2
+    assert st["batch_ms"] > 0
