@@ -47,6 +47,12 @@ DUAL_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sell_diff_fp64_kuhn{n}_tet
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in ("sell.h", "common.h")]
 
 
+def _variant(st):
+    """The product variant the autotuner chose for a solve (from its stats)."""
+    return {"unroll": st["spmv_unroll"], "nontemporal": st["spmv_nontemporal"], "col_bytes": st["spmv_col_bytes"],
+            "band": st["spmv_band"]}
+
+
 def measured_traffic(n, path=TRAFFIC_FILE):
     """HBM bytes per SpMV launch from the committed counter summary of this mesh size, or None when
     there is none or the kernel sources changed since the counters were taken."""
@@ -226,7 +232,8 @@ def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96,
     # the batched iterations (SpMV + p.q, update, close of every resident system) against HBM peak
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "batch_ms": round(bs["batch_ms"], 3),
-            "batch_bytes": bs["batch_bytes"], "system_iterations": bs["batch_iterations"]}
+            "batch_bytes": bs["batch_bytes"], "system_iterations": bs["batch_iterations"],
+            "variant": bs["variant_fp32" if precision == 1 else "variant_fp64"]}
     return {"solves_per_sec": round(len(reqs) / (total - arrivals[0]), 3), **_percentiles(lat),
             "seconds": round(total, 3), "steps": steps, "peak_resident": peak, "inner_iterations": inner,
             "outer_iterations": outer, "failed": status_bad, "batched_iterations_roofline": roof}, keff
@@ -645,7 +652,7 @@ def dual_benchmark(ctx, dev, n, steps, warmup, cpu=True, order=None):
                            "traffic": measured_traffic(n, DUAL_TRAFFIC_FILE),
                            "kernel": "k_sell<double, MODE_DOT, difference form> (tet system SpMV + p.Ap partials)",
                            "bytes_per_launch": per, "mean_launch_us": round(1e3 * spmv_ms / launches, 3),
-                           "launches": launches}
+                           "launches": launches, "variant": _variant(st)}
     if cpu:
         out["cpu_baseline"] = dual_cpu_baseline()
     return out
@@ -828,7 +835,7 @@ def roofline_256(ctx, dev, profile=8):
     out = spmv_roofline(st, 256)
     out.update({"workload": "kuhn256_lognormal1_cracks200_fp64_jacobi", "V": mesh.V, "spmv_nnz": st["spmv_nnz"],
                 "pcg_iterations": st["iterations"], "solve_ms": round(st["solve_ms"], 3), "status": rc,
-                "column_bytes": round((st["spmv_bytes"] - 20 * mesh.V - 4) / st["spmv_nnz"] - 8, 3)})
+                "column_bytes": st["spmv_col_bytes"], "variant": _variant(st)})
     mesh.close()
     del inp
     return out
@@ -947,7 +954,8 @@ def main():
     if launches:
         agg = {"spmv_bytes": per, "spmv_launches": launches, "spmv_ms": spmv_ms}
         out["roofline"] = spmv_roofline(agg, args.n)
-        out["roofline"]["column_bytes"] = round((per - 20 * counts["V"] - 4) / st["spmv_nnz"] - 8, 3)
+        out["roofline"]["column_bytes"] = st["spmv_col_bytes"]
+        out["roofline"]["variant"] = _variant(st)
     if args.roofline_256 and profile:
         out["roofline_256"] = roofline_256(ctx, dev, profile)
         print(f"[bench] roofline_256: {out['roofline_256']}", file=sys.stderr, flush=True)

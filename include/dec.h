@@ -156,10 +156,13 @@ int dec_hodge1(dec_mesh* m, const double* kappa, int32_t n_cracks, const double*
  * solver multiplies with.  By default the sliced-ELL copy leaves out edges
  * whose geometric dual area is exactly zero (L_ij = -0 for every kappa and
  * crack set), which leaves every product bit-for-bit unchanged;
- * DEC_ASM_FULL_PATTERN keeps them.  When every stored column lies within
- * 2^15 of its row (a spatially numbered mesh), the sliced-ELL copy also
- * holds the columns as 16-bit offsets from the row, which the solver's
- * product reads instead of the int32 columns (same entries, same sums). */
+ * DEC_ASM_FULL_PATTERN keeps them.  Beside its int32 columns the
+ * sliced-ELL copy holds two compact encodings where they fit: 16-bit
+ * offsets j - i when every stored column lies within 2^15 of its row, and
+ * one-byte indices into a table of the matrix's distinct offsets (sorted,
+ * at most 256; on a Kuhn lattice the 14 neighbour offsets and 0).  The
+ * solver's product reads whichever encoding the autotuner timed fastest on
+ * the matrix (the same columns, so the same sums). */
 #define DEC_ASM_DEFAULT 0u
 #define DEC_ASM_FULL_PATTERN 1u
 int dec_assemble(dec_mesh* m, uint32_t flags);
@@ -214,7 +217,7 @@ typedef struct dec_solve_opts {
     int32_t adaptive_final_inner;/* mixed: inner tol max(inner_tol, 0.5 tol||b||/||r||) */
     int32_t warm_start;          /* T holds the initial guess (Dirichlet values are imposed) */
     int64_t max_iters;           /* cap on PCG iterations (FP64) / inner iterations (mixed;
-                                    one FP32 solve gets at most max_iters / 8)      */
+                                    one FP32 solve gets at most max(max_iters / 8, 64)) */
     int32_t format;              /* DEC_FMT_* for the SpMV                         */
     int32_t chunk;               /* iterations per launch batch (0: default)       */
     int32_t use_graph;           /* capture each batch in a hipGraph               */
@@ -243,6 +246,12 @@ typedef struct dec_solve_stats {
                                  with 16-bit column offsets, else 4)                       */
     int64_t spmv_nnz;         /* entries the product uses (full pattern or pruned)       */
     double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
+    int32_t spmv_unroll;      /* the product variant of the iteration's precision: entry
+                                 pairs in flight per lane (2, 3, 4; timed by the autotuner) */
+    int32_t spmv_nontemporal; /* 1 when its matrix loads are non-temporal                  */
+    int32_t spmv_col_bytes;   /* its column encoding: 1 one-byte offset-table index, 2
+                                 16-bit offset, 4 int32 column                             */
+    int32_t spmv_band;        /* slices per band of its banded slice order, 0 for plain    */
 } dec_solve_stats;
 
 /* Solver knobs read from the environment when a mesh's solver state is
@@ -251,12 +260,22 @@ typedef struct dec_solve_stats {
  * form's arithmetic, or how the reductions are partitioned):
  *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1  pin the sliced-ELL variant the
  *       autotuner would pick (entry pairs in flight, non-temporal loads);
- *   DEC_SELL_COLS=32      read int32 columns even where 16-bit offsets exist;
+ *   DEC_SELL_COLS=8|16|32 read the columns through the one-byte offset
+ *       table, the 16-bit offsets or the int32 columns (when the matrix
+ *       lacks that encoding, the next wider one it holds);
+ *   DEC_SELL_BAND=plane,band | auto  read at assembly: the product walks
+ *       each XCD's share of slices band by band across planes of `plane`
+ *       slices (`auto`: planes of the farthest column offset, bands of about
+ *       1 MiB of matrix, where that offset spans more than 2 MiB of matrix),
+ *       so a gather one plane back stays in L2; unset, plain order (on this
+ *       GPU the bands cut the fetched bytes but not the time).  Changes the
+ *       grouping of the product's partial sums, so the rounding of solves;
  *   DEC_JACOBI_SPLIT=0|1  run Jacobi PCG on A, or always in split form (CG
  *       on D^-1/2 A D^-1/2); unset, the split form is taken for plain
  *       systems of 65,536 rows or more with a positive diagonal;
  *   DEC_BLOCKS_PER_CU, DEC_SPMV_BLOCKS_PER_CU  workgroups per CU of the
- *       vector kernels (default 4) and of the SpMV (default 8). */
+ *       vector kernels (default 4; 8 from 2^22 rows) and of the SpMV
+ *       (default 8). */
 
 /* Fill opts (host) with the defaults: FP64, Jacobi, tol 1e-10 (the relative
  * tolerance of Section 3.1's solves), inner_tol 1e-5, adaptive final inner
@@ -522,13 +541,15 @@ int dec_server_cancel(dec_server* s, uint64_t ticket);
  * the roofline of serving; host outputs, each NULL ok): batch_ms, the time of
  * the steps' graph replays (HIP events on the server's stream); batch_bytes,
  * the algorithmic bytes of the iterations they ran, per system and iteration
- * kept entries x (value + column bytes) + 4 (V + 1) + 14 V value bytes (the
- * product's row pointer, x and y; the update's r, q, D^-1 and r; the closing
- * kernel's D^-1, r, p, x, x and p); batch_iterations, the system-iterations
- * run.  The server's batched product picks its variant (entry pairs in
- * flight, non-temporal loads) per precision by timing it on the first batch
- * of that precision; the choice changes no result. */
-int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations);
+ * kept entries x (value + column bytes) + 4 (V + 1) + 12 V values (the
+ * product's x and y; the update's r, q, D^-1 and r; the closing kernel's
+ * D^-1, r, p, x, x and p); batch_iterations, the system-iterations run;
+ * variant [4] int32: the batched product's entry pairs in flight and
+ * non-temporal loads (0/1) for FP64, then for FP32 (0 where that precision
+ * has not run).  The server picks them per precision by timing its product on
+ * the first batch of that precision; the choice changes no result. */
+int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations,
+                     int32_t* variant);
 int dec_server_destroy(dec_server* s);
 
 #ifdef __cplusplus

@@ -448,11 +448,15 @@ class Server:
         return self.lib.dec_server_cancel(self.handle, int(ticket))
 
     def stats(self):
-        """Batched inner iterations so far: replay time (ms), algorithmic bytes, system-iterations."""
+        """Batched inner iterations so far: replay time (ms), algorithmic bytes, system-iterations, and the
+        batched product's variant per precision (entry pairs in flight, non-temporal loads)."""
         ms, by, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(it)),
-                       "dec_server_stats")
-        return {"batch_ms": ms.value, "batch_bytes": by.value, "batch_iterations": it.value}
+        var = (ctypes.c_int32 * 4)()
+        self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(it),
+                                                 var), "dec_server_stats")
+        return {"batch_ms": ms.value, "batch_bytes": by.value, "batch_iterations": it.value,
+                "variant_fp64": {"unroll": var[0], "nontemporal": var[1]},
+                "variant_fp32": {"unroll": var[2], "nontemporal": var[3]}}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -60,6 +60,10 @@ class SolveStats(ctypes.Structure):
         ("spmv_bytes", ctypes.c_double),
         ("spmv_nnz", ctypes.c_int64),
         ("plain_residual", ctypes.c_double),
+        ("spmv_unroll", ctypes.c_int32),
+        ("spmv_nontemporal", ctypes.c_int32),
+        ("spmv_col_bytes", ctypes.c_int32),
+        ("spmv_band", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -133,7 +137,7 @@ SIGNATURES = {
     "dec_server_step": (c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_poll": (c_int, [vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_cancel": (c_int, [vp, ctypes.c_uint64]),
-    "dec_server_stats": (c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+    "dec_server_stats": (c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_destroy": (c_int, [vp]),
 }
 

@@ -4,6 +4,9 @@
 // column order.  No atomics, so the values are deterministic.  The FP32 copy and the sliced-ELL copies are refreshed
 // from the FP64 CSR values.
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 
 #include "sell.h"
 
@@ -133,7 +136,7 @@ __global__ void k_sell_values(int64_t n, const int32_t* __restrict__ ssrc, const
 // its own in LDS, then adds them to the global set, so the global atomics
 // number (workgroups x distinct offsets).  flags: [0] an offset beyond 16 bits,
 // [1] distinct offsets, [2] more than OTAB_MAX of them (in one workgroup or
-// in all).
+// in all), [3] the largest |offset| (written with the table).
 constexpr int OSET_CAP = 1024;
 constexpr int32_t OSET_EMPTY = INT32_MIN;
 
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) void k_sell_offsets(int64_t V, int64_t nslic
 // otab (bitonic sort in LDS; the empty slots, INT32_MIN, sort first), when
 // there are at most OTAB_MAX of them.
 __global__ __launch_bounds__(OSET_CAP) void k_offset_sort(const int32_t* __restrict__ gset,
-                                                          const unsigned* __restrict__ flags,
+                                                          unsigned* __restrict__ flags,
                                                           int32_t* __restrict__ otab) {
     __shared__ int32_t v[OSET_CAP];
     const unsigned count = flags[1];
@@ -219,6 +222,10 @@ __global__ __launch_bounds__(OSET_CAP) void k_offset_sort(const int32_t* __restr
             __syncthreads();
         }
     if (t < (int)count) otab[t] = v[OSET_CAP - count + t];
+    if (t == 0 && count > 0) {
+        const int64_t lo = v[OSET_CAP - count], hi = v[OSET_CAP - 1];
+        flags[3] = static_cast<unsigned>(-lo > hi ? -lo : hi);
+    }
 }
 
 // The index of col - row in the ascending offset table (staged in LDS), per
@@ -286,6 +293,8 @@ void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V) {
     S.tcol = DBuf<uint8_t>();
     S.otab = DBuf<int32_t>();
     S.ntab = 0;
+    S.far = -1;
+    S.band_plane = S.band = 0;
     if (S.entries == 0) return;
     hipStream_t st = ctx->stream;
     DBuf<int16_t> d;
@@ -296,7 +305,7 @@ void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V) {
     tab.alloc(ctx, OTAB_MAX);
     gset.alloc(ctx, OSET_CAP);
     DBuf<unsigned> flags;  // see k_sell_offsets
-    flags.alloc(ctx, 3);
+    flags.alloc(ctx, 4);
     flags.zero();
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(OSET_CAP)), dim3(BLOCK), 0, st, (int64_t)OSET_CAP, OSET_EMPTY, gset.p);
     const unsigned g = grid_xcd(S.nslices * SELL_C);
@@ -306,14 +315,46 @@ void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V) {
     hipLaunchKernelGGL(k_offset_index, dim3(g), dim3(BLOCK), 0, st, V, S.nslices, S.ptr.p, S.col.p, tab.p, flags.p,
                        t.p);
     HIP_CHECK(hipGetLastError());
-    unsigned h[3];
+    unsigned h[4];
     std::memcpy(h, ctx->readback(flags.p, sizeof(h)), sizeof(h));  // the one synchronisation
     if (h[0] == 0) S.dcol = std::move(d);
     if (h[2] == 0 && h[1] <= (unsigned)OTAB_MAX) {
         S.tcol = std::move(t);
         S.otab = std::move(tab);
         S.ntab = (int32_t)h[1];
+        S.far = (int32_t)h[3];
     }
+    choose_band(S, V);
+}
+
+// The product's slice order (sell.h banded_slice), plain unless
+// DEC_SELL_BAND asks for bands: "plane,band" sets them for every matrix,
+// "auto" applies this rule.  Between reading x_j for row j and gathering it
+// for row j + far, an XCD streams about far times the bytes one row costs the
+// FP64 product with one-byte columns; above BAND_REUSE_BYTES the order is
+// banded, with planes of far / 64 slices (rounded) and bands of about
+// BAND_BYTES of matrix.  On gfx950 the rule removes the repeated fetches of
+// those gathers from L2 but not their time (the Infinity Cache serves them),
+// so plain order is the default.
+void choose_band(SellMatrix& S, int64_t V) {
+    S.band_plane = S.band = 0;
+    const char* env = getenv("DEC_SELL_BAND");
+    if (!env) return;
+    unsigned p = 0, b = 0;
+    if (sscanf(env, "%u,%u", &p, &b) == 2 && p > 0 && b > 0) {
+        S.band_plane = p;
+        S.band = b;
+        return;
+    }
+    if (strcmp(env, "auto") != 0) return;
+    if (S.far < 0 || V == 0) return;
+    const double row_bytes = (9.0 * (double)S.entries + 20.0 * (double)V) / (double)V;
+    if ((double)S.far * row_bytes <= BAND_REUSE_BYTES) return;
+    const uint32_t plane = (uint32_t)((S.far + SELL_C / 2) / SELL_C);
+    double w = BAND_BYTES / (SELL_C * row_bytes);
+    if (w < 16.0) w = 16.0;
+    S.band_plane = plane;
+    S.band = (uint32_t)w < plane ? (uint32_t)w : plane;
 }
 
 // Copy the CSR values into the sliced-ELL layout (after assembly or boundary edits).

@@ -143,13 +143,21 @@ struct SellMatrix {
                             // when the entries take at most 256 distinct offsets
     DBuf<int32_t> otab;     // [ntab] those offsets, ascending
     int32_t ntab = 0;
+    int32_t far = -1;        // largest |col - row| over the entries when otab exists, else -1
+    uint32_t band_plane = 0;  // the product's banded slice order (sell.h banded_slice), 0: plain order
+    uint32_t band = 0;
 };
 
 // Fill S.dcol from S.col (rows of V, padding included), or leave it empty when
 // some column lies 2^15 or more from its row; and S.tcol / S.otab when the
 // offsets take at most 256 distinct values (rows past V count as offset 0).
+// Then the product's slice order (choose_band): plain, or banded
+// (S.band_plane, S.band) on request through DEC_SELL_BAND.
 // Synchronises the stream.
+constexpr double BAND_REUSE_BYTES = 2.0 * (1 << 20);  // half an XCD's 4 MiB L2
+constexpr double BAND_BYTES = 1.0 * (1 << 20);
 void build_sell_offsets(dec_ctx* ctx, SellMatrix& S, int64_t V);
+void choose_band(SellMatrix& S, int64_t V);
 
 // Lower-triangular FSAI factor G (CSR) and its transpose (CSR of G^T).
 struct FsaiFactor {

@@ -517,6 +517,8 @@ const float* excess<float>(const SellMatrix& S) {
 template <class VT>
 SellView<VT> view_cf(const SellMatrix& S, int64_t V, int cf) {
     SellView<VT> v{S.ptr.p, S.col.p, values<VT>(S), S.nslices, V, excess<VT>(S)};
+    v.band_plane = S.band_plane;
+    v.band = S.band;
     if (cf >= CF_U8 && S.tcol.p) {
         v.tcol = S.tcol.p;
         v.otab = S.otab.p;
@@ -1084,6 +1086,12 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
         c.cf[0] = known->second[2];
     }
     const SellView<double> A = view<double>(&c, m->sell, V);
+    if (stats) {
+        stats->spmv_unroll = c.unroll[0];
+        stats->spmv_nontemporal = c.nt[0];
+        stats->spmv_col_bytes = (int32_t)column_bytes(A);
+        stats->spmv_band = (int32_t)S.band;
+    }
     const int G = c.G, Gs = c.Gs;
     const dim3 blk(BLOCK);
     auto fin = [&](int what, int n_rr, int n_rz, double factor, PcgScalars* s) {
@@ -1298,6 +1306,11 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
             stats->spmv_nnz = m->sell.kept;
             stats->spmv_bytes = nz * (s + cb) + 4.0 * (double)(m->V + 1) + 2.0 * s * (double)m->V;
             if (m->sell.excess64.p) stats->spmv_bytes += s * (double)m->V;  // difference form: the row excess
+            const int pi = mixed ? 1 : 0;
+            stats->spmv_unroll = c->unroll[pi];
+            stats->spmv_nontemporal = c->nt[pi];
+            stats->spmv_col_bytes = (int32_t)cb;
+            stats->spmv_band = (int32_t)m->sell.band;
         }
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,

@@ -37,6 +37,8 @@ struct SellView {
     const uint8_t* tcol = nullptr;  // [entries] index into otab of col - row, or null
     const int32_t* otab = nullptr;  // [ntab] the offsets tcol indexes
     int32_t ntab = 0;
+    uint32_t band_plane = 0;  // banded slice order (see banded_slice): slices per plane, 0 for none
+    uint32_t band = 0;        // slices per band
 };
 
 // How the product reads its columns: int32 columns, 16-bit offsets from the
@@ -80,9 +82,12 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // so a gather's address is the uniform base plus a 32-bit offset.  The
 // pairs go in groups of U: all column and value loads of a group are issued
 // before its x gathers, and the last group is predicated (the width is
-// uniform across the wavefront), so no entry waits on the one before; an odd
-// last entry follows.  The terms are added in entry order, so every layout
-// and unroll gives the same sum.  DIFF: each term is a_ij (x_j - xi).  CF:
+// uniform across the wavefront), so no entry waits on the one before.  An odd
+// last entry (rows of 7 entries are the common case on these meshes) has its
+// column and value loaded before the first group and its x gathered with the
+// last group's, so a row costs one round trip for the matrix and one for x.
+// The terms are added in entry order, so every layout and unroll gives the
+// same sum.  DIFF: each term is a_ij (x_j - xi).  CF:
 // the columns as int32 (A.col), 16-bit offsets (A.dcol) added to `row`, or
 // one-byte indices (A.tcol) into the offset table `tab` (in LDS) added to
 // `row` (for a lane past the last row, row is the last row and its entries
@@ -100,6 +105,20 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
     const D2* dp = reinterpret_cast<const D2*>(A.dcol + base) + lane;
     const B2* bp = reinterpret_cast<const B2*>(A.tcol + base) + lane;
     const V2* vp = reinterpret_cast<const V2*>(A.val + base) + lane;
+    const bool odd = width & 1;
+    const int64_t ko = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
+    int32_t oc = 0;  // the odd entry's column as stored (index, offset or column)
+    VT vo = 0, xo = 0;
+    if (odd) {
+        oc = CF == CF_U8    ? static_cast<int32_t>(stream_load<uint8_t, NT>(A.tcol + ko))
+             : CF == CF_I16 ? static_cast<int32_t>(stream_load<int16_t, NT>(A.dcol + ko))
+                            : stream_load<int32_t, NT>(A.col + ko);
+        vo = stream_load<VT, NT>(A.val + ko);
+    }
+    auto odd_gather = [&]() {
+        const int32_t c = CF == CF_U8 ? row + tab[oc] : CF == CF_I16 ? row + oc : oc;
+        xo = DIFF ? x[static_cast<uint32_t>(c)] - xi : x[static_cast<uint32_t>(c)];
+    };
     VT acc = 0;
     for (int t = 0; t < np; t += U) {
         C2 c[U];
@@ -131,6 +150,7 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
                 x1[u] -= xi;
             }
         }
+        if (odd && t + U >= np) odd_gather();
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (t + u < np) {
@@ -142,12 +162,9 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
         bp += U * SELL_C;
         vp += U * SELL_C;
     }
-    if (width & 1) {
-        const int64_t k = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;
-        const int32_t c = CF == CF_U8    ? row + tab[stream_load<uint8_t, NT>(A.tcol + k)]
-                          : CF == CF_I16 ? row + stream_load<int16_t, NT>(A.dcol + k)
-                                         : stream_load<int32_t, NT>(A.col + k);
-        acc += stream_load<VT, NT>(A.val + k) * (DIFF ? x[static_cast<uint32_t>(c)] - xi : x[static_cast<uint32_t>(c)]);
+    if (odd) {
+        if (np == 0) odd_gather();
+        acc += vo * xo;
     }
     return acc;
 }
@@ -178,8 +195,31 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // apart (a neighbour one lattice or cube plane away) are gathered close in
 // time, while that part of x is still in the XCD's L2.  (Giving each
 // workgroup a contiguous stretch of its own, as the other kernels do, was
-// 9% slower at 128^3: 31.2 against 28.6 us.)  gridDim.x must be a multiple
-// of 8.
+// 9% slower at 128^3: 31.2 against 28.6 us.)  A banded matrix has the front
+// walk the XCD's share band by band (banded_slice).  gridDim.x must be a
+// multiple of 8.
+// The slice an XCD takes at step l of its range of n slices.  In plain order
+// step l takes slice l.  A banded matrix (band_plane > 0) has its far column
+// offsets near one plane of band_plane slices (a lattice or cube plane), and
+// an XCD that walked its range in plain order would stream a whole plane of
+// the matrix between reading x_j as a row's own value and gathering it for
+// the row one plane on, more than its L2 holds.  Its range is then cut into
+// planes, the planes into bands of `band` slices, and the XCD takes band 0 of
+// every plane, then band 1 of every plane, and so on: the gather one plane on
+// comes one band later.  Slices past the last whole plane follow in order.
+// A bijection of [0, n) for any plane >= 1 and band >= 1.
+__device__ __forceinline__ uint32_t banded_slice(uint32_t l, uint32_t n, uint32_t plane, uint32_t band) {
+    if (plane == 0) return l;
+    const uint32_t planes = n / plane;
+    if (l >= planes * plane) return l;
+    const uint32_t stripe = band * planes;  // one band of every plane
+    const uint32_t b = l / stripe;
+    const uint32_t in = l - b * stripe;
+    const uint32_t w = band < plane - b * band ? band : plane - b * band;  // the last band may be narrower
+    const uint32_t p = in / w;
+    return p * plane + b * band + (in - p * w);
+}
+
 // The contribution of row `row` (the product acc of its stored entries) to
 // y and to the block's partial sum d.
 template <class VT, int MODE, bool DIFF>
@@ -208,15 +248,17 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
     if (CF == CF_U8) stage_offsets(A.otab, A.ntab, tab);
     constexpr int WAVES = BLOCK / 64;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int64_t s1 = A.nslices * (xcd + 1) / 8;
-    const int64_t step = static_cast<int64_t>(gridDim.x >> 3) * WAVES;
+    const int64_t xcd = blockIdx.x & 7;
+    const int64_t s0 = A.nslices * xcd / 8;
+    const uint32_t n = static_cast<uint32_t>(A.nslices * (xcd + 1) / 8 - s0);
+    const uint32_t step = (gridDim.x >> 3) * WAVES;
     VT d = 0;
     // the row the columns are decoded from (a lane past the last row takes the last row)
     auto decode_row = [&](int64_t row) {
         return static_cast<int32_t>(CF == CF_U8 && row >= A.V ? A.V - 1 : row);
     };
-    for (int64_t s = A.nslices * xcd / 8 + j * WAVES + w; s < s1; s += step) {
+    for (uint32_t l = (blockIdx.x >> 3) * WAVES + w; l < n; l += step) {
+        const int64_t s = s0 + banded_slice(l, n, A.band_plane, A.band);
         const int64_t base = A.ptr[s];
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;

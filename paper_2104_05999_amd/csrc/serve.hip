@@ -1181,11 +1181,17 @@ int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out)
     return DEC_OK;
 }
 
-int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations) {
+int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations,
+                     int32_t* variant) {
     if (!s) return DEC_EINVAL;
     if (batch_ms) *batch_ms = s->batch_ms;
     if (batch_bytes) *batch_bytes = s->batch_bytes;
     if (batch_iterations) *batch_iterations = s->batch_iterations;
+    if (variant)
+        for (int k = 0; k < 2; ++k) {
+            variant[2 * k] = s->tuned[k] ? s->unroll[k] : 0;
+            variant[2 * k + 1] = s->tuned[k] ? s->nt[k] : 0;
+        }
     return DEC_OK;
 }
 

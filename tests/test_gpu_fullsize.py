@@ -8,7 +8,8 @@ counts, the whole set of cut edges, the pinned vertices.  Floating point:
 solves to 1e-14, as the oracle's reference did: on this conditioning a 1e-10
 residual leaves ~1e-7 relative error); k_eff to 1e-9 relative.  The
 throughput configuration (tol 1e-10) is held, in the same measure on the same
-sample, to twice the error of the oracle's own 1e-10 solve.
+sample, to twice the error of the oracle's own 1e-10 solve (FP64 Jacobi PCG;
+for mixed precision the larger of that and the oracle's own refinement).
 """
 import json
 import os
@@ -92,16 +93,27 @@ def test_solution_against_reference(mesh128, golden, precision, precond):
     assert abs(f["q_out"] - meta["q_out"]) <= 1e-9 * meta["k_eff"]
 
 
-def test_throughput_tolerance_error(mesh128, golden):
+@pytest.mark.parametrize("precision,precond", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_throughput_tolerance_error(mesh128, golden, precision, precond):
+    """At the benchmark's tolerance 1e-10: FP64 within 2x the error of the oracle's own FP64 Jacobi
+    PCG stopped there; mixed precision within 2x the larger of that and the oracle's own refinement
+    (FP32 Jacobi PCG inside FP64 refinement) stopped there."""
     meta, arr = golden
     m = mesh128["m"]
-    T, st, rc = m.solve(tol=1e-10)
+    T, st, rc = m.solve(tol=1e-10, precision=precision, precond=precond)
     assert rc == 0 and st["rel_residual"] <= 1e-10
     err = sample_error(T, arr)
-    assert err <= 2 * meta["loose_sample_error_vs_ref"], (err, meta["loose_sample_error_vs_ref"])
+    ref = meta["loose_sample_error_vs_ref"]
+    if precision == 1:
+        ref = max(ref, meta["ir_sample_error_vs_ref"])
+    print(f"sample error {err:.3e} = {err / ref:.2f} x the oracle's", flush=True)
+    assert err <= 2 * ref, (err, ref)
     f = m.flux(T, mesh128["side"])
     assert abs(f["k_eff"] - meta["k_eff"]) <= 1e-9 * meta["k_eff"]
-    assert abs(f["energy"] - f["q_in"]) <= 1e-7 * f["energy"]
+    # E - Q_in = -sum over free rows of T_v r_v (r = b - A T), so by Cauchy-Schwarz
+    # |E - Q_in| <= ||T||_2 ||r||_2 = ||T||_2 rel_residual ||b||_2
+    bound = float(torch.linalg.norm(T)) * st["rel_residual"] * float(torch.linalg.norm(mesh128["b"]))
+    assert abs(f["energy"] - f["q_in"]) <= 1.01 * bound, (f["energy"] - f["q_in"], bound)
 
 
 def test_full_size_runs_are_deterministic(mesh128):

@@ -244,7 +244,8 @@ def test_served_warm_start(ctx, dev):
 def test_server_batch_counters(ctx, dev, precision):
     """dec_server_stats: the system-iterations its batches ran are the results' inner iterations;
     the bytes are those of the batched kernels (per iteration between 14 and 20 value-sized words
-    per row plus the product's entries), over a positive replay time."""
+    per row plus the product's entries), over a positive replay time; the batched product's
+    variant the server timed for the precision that ran (none for the other)."""
     import paper_2104_05999_amd as dec
     built = [make_request(n, c, 80 + n, dev) for n, c in ((10, 6), (14, 9), (20, 12))]
     srv = dec.Server(ctx, 4 << 30, precision=precision, tol=1e-10)
@@ -267,3 +268,6 @@ def test_server_batch_counters(ctx, dev, precision):
     per_it = st["batch_bytes"] / its
     assert 14 * sv * rows * 0.5 < per_it < (20 * sv + 15 * (sv + 4)) * rows * 2
     assert st["batch_ms"] > 0
+    ran, idle = ("variant_fp32", "variant_fp64") if precision == 1 else ("variant_fp64", "variant_fp32")
+    assert st[ran]["unroll"] in (2, 3, 4) and st[ran]["nontemporal"] in (0, 1)
+    assert st[idle] == {"unroll": 0, "nontemporal": 0}
