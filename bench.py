@@ -236,7 +236,8 @@ def serve_batched(ctx, reqs, arrivals, precision, budget=32 << 30, max_slots=96,
             "variant": bs["variant_fp32" if precision == 1 else "variant_fp64"]}
     return {"solves_per_sec": round(len(reqs) / (total - arrivals[0]), 3), **_percentiles(lat),
             "seconds": round(total, 3), "steps": steps, "peak_resident": peak, "inner_iterations": inner,
-            "outer_iterations": outer, "failed": status_bad, "batched_iterations_roofline": roof}, keff
+            "outer_iterations": outer, "failed": status_bad, "batched_iterations_roofline": roof,
+            "host_ms": {k: round(v, 1) for k, v in bs["host_ms"].items()}}, keff
 
 
 SERVE_GOLDEN = os.path.join(ROOT, "tests", "golden", "serve512_every16")

@@ -537,19 +537,24 @@ int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out)
 /* Cancel a pending or admitted request; its result has status DEC_ECANCELED.
  * DEC_EINVAL when the ticket is unknown or already finished. */
 int dec_server_cancel(dec_server* s, uint64_t ticket);
-/* Counters of the batched inner iterations since the server was created (for
- * the roofline of serving; host outputs, each NULL ok): batch_ms, the time of
- * the steps' graph replays (HIP events on the server's stream); batch_bytes,
- * the algorithmic bytes of the iterations they ran, per system and iteration
- * kept entries x (value + column bytes) + 4 (V + 1) + 12 V values (the
- * product's x and y; the update's r, q, D^-1 and r; the closing kernel's
- * D^-1, r, p, x, x and p); batch_iterations, the system-iterations run;
- * variant [4] int32: the batched product's entry pairs in flight and
- * non-temporal loads (0/1) for FP64, then for FP32 (0 where that precision
- * has not run).  The server picks them per precision by timing its product on
- * the first batch of that precision; the choice changes no result. */
-int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations,
-                     int32_t* variant);
+/* Counters since the server was created, for the roofline of serving. */
+typedef struct dec_server_counters {
+    double batch_ms;          /* time of the steps' graph replays (HIP events on the server's stream) */
+    double batch_bytes;       /* algorithmic bytes of the iterations they ran, per system and iteration
+                                 kept entries x (value + column bytes) + 4 (V + 1) + 12 V values (the
+                                 product's x and y; the update's r, q, D^-1 and r; the closing kernel's
+                                 D^-1, r, p, x, x and p)                                              */
+    int64_t batch_iterations; /* system-iterations run in them                                        */
+    int32_t variant[4];       /* the batched product's entry pairs in flight and non-temporal loads
+                                 (0/1) for FP64, then for FP32 (0 where that precision has not run);
+                                 the server picks them per precision by timing its product on the
+                                 first batch of that precision; the choice changes no result         */
+    double host_ms[4];        /* host wall time of dec_server_step's phases: building and launching
+                                 the batch, admissions, waiting for the batch, refinement steps       */
+    int64_t steps;            /* dec_server_step calls                                                */
+} dec_server_counters;
+/* Fill *out (host).  DEC_EINVAL when s or out is NULL. */
+int dec_server_stats(const dec_server* s, dec_server_counters* out);
 int dec_server_destroy(dec_server* s);
 
 #ifdef __cplusplus

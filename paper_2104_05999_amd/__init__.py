@@ -450,13 +450,13 @@ class Server:
     def stats(self):
         """Batched inner iterations so far: replay time (ms), algorithmic bytes, system-iterations, and the
         batched product's variant per precision (entry pairs in flight, non-temporal loads)."""
-        ms, by, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        var = (ctypes.c_int32 * 4)()
-        self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(it),
-                                                 var), "dec_server_stats")
-        return {"batch_ms": ms.value, "batch_bytes": by.value, "batch_iterations": it.value,
-                "variant_fp64": {"unroll": var[0], "nontemporal": var[1]},
-                "variant_fp32": {"unroll": var[2], "nontemporal": var[3]}}
+        c = _lib.ServerCounters()
+        self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(c)), "dec_server_stats")
+        v, h = list(c.variant), list(c.host_ms)
+        return {"batch_ms": c.batch_ms, "batch_bytes": c.batch_bytes, "batch_iterations": c.batch_iterations,
+                "variant_fp64": {"unroll": v[0], "nontemporal": v[1]},
+                "variant_fp32": {"unroll": v[2], "nontemporal": v[3]},
+                "host_ms": {"launch": h[0], "admit": h[1], "wait": h[2], "refine": h[3]}, "steps": c.steps}
 
     def close(self):
         if getattr(self, "handle", None):

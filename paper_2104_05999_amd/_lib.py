@@ -70,6 +70,17 @@ class SolveStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerCounters(ctypes.Structure):
+    _fields_ = [
+        ("batch_ms", ctypes.c_double),
+        ("batch_bytes", ctypes.c_double),
+        ("batch_iterations", ctypes.c_int64),
+        ("variant", ctypes.c_int32 * 4),
+        ("host_ms", ctypes.c_double * 4),
+        ("steps", ctypes.c_int64),
+    ]
+
+
 class Request(ctypes.Structure):
     _fields_ = [
         ("V", ctypes.c_int64), ("xyz", vp), ("T", ctypes.c_int64), ("tets", vp), ("kappa", vp),
@@ -137,7 +148,7 @@ SIGNATURES = {
     "dec_server_step": (c_int, [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_poll": (c_int, [vp, ctypes.POINTER(Result), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "dec_server_cancel": (c_int, [vp, ctypes.c_uint64]),
-    "dec_server_stats": (c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "dec_server_stats": (c_int, [vp, vp]),
     "dec_server_destroy": (c_int, [vp]),
 }
 

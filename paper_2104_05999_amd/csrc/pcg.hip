@@ -216,21 +216,51 @@ __global__ void k_split_x(int64_t V, double* __restrict__ x, const double* __res
 // (`invd` is then D itself).
 enum { PJ_NONE = 0, PJ_JACOBI = 1, PJ_SPLIT = 2 };
 
-template <class VT, int PJ, int ROWS>
+// The vector kernels take W consecutive rows per element: FP32 vectors are
+// read and written as float2, so each load of a wavefront moves as many bytes
+// as in FP64 (one float per lane left the FP32 kernels at two thirds of the
+// FP64 kernels' rate).  The last row of an odd V is taken by block 0's first
+// thread after its elements.
+template <class VT, int W>
+struct Rows;
+template <class VT>
+struct Rows<VT, 1> {
+    typedef VT T;
+    static __device__ __forceinline__ VT get(const T& v, int) { return v; }
+    static __device__ __forceinline__ void set(T& v, int, VT x) { v = x; }
+};
+template <>
+struct Rows<float, 2> {
+    typedef float2 T;
+    static __device__ __forceinline__ float get(const float2& v, int c) { return c ? v.y : v.x; }
+    static __device__ __forceinline__ void set(float2& v, int c, float x) {
+        if (c)
+            v.y = x;
+        else
+            v.x = x;
+    }
+};
+
+template <class VT, int PJ, int ROWS, int W>
 __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r, const VT* __restrict__ q,
                                                   const VT* __restrict__ invd, double* __restrict__ partials,
                                                   int P, int n_pq, PcgScalars* __restrict__ S) {
+    typedef Rows<VT, W> RW;
+    typedef typename RW::T E;
     __shared__ double lds[BLOCK / 64 + 1];
     if (S->done) return;
-    const FrontRange32 R = front_range32(V);
-    VT fr[ROWS], fq[ROWS], fd[ROWS];
+    E* re = reinterpret_cast<E*>(r);
+    const E* qe = reinterpret_cast<const E*>(q);
+    const E* de = reinterpret_cast<const E*>(invd);
+    const FrontRange32 R = front_range32(V / W);
+    E fr[ROWS], fq[ROWS], fd[ROWS];
 #pragma unroll
     for (int k = 0; k < ROWS; ++k) {
         const uint32_t i = R.first + k * R.step;
         if (i < R.end) {
-            fr[k] = r[i];
-            fq[k] = q[i];
-            fd[k] = PJ != PJ_NONE ? invd[i] : VT(0);
+            fr[k] = re[i];
+            fq[k] = qe[i];
+            fd[k] = PJ != PJ_NONE ? de[i] : E{};
         }
     }
     const double pq = reduce_bcast(partials + R_PQ * P, n_pq, lds);
@@ -238,15 +268,22 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
     if (!(pq > 0.0) || !isfinite(pq)) return;
     const VT a = static_cast<VT>(S->rho / pq);
     VT rz = 0, rr = 0;
+    auto row = [&](VT fri, VT fqi, VT fdi) {  // r_i - a q_i and its terms of r.z and r.r
+        const VT ri = fri - a * fqi;
+        if (PJ == PJ_JACOBI) rz += ri * (fdi * ri);
+        if (PJ == PJ_SPLIT) rz += ri * ri;
+        rr += PJ == PJ_SPLIT ? (ri * ri) * fdi : ri * ri;
+        return ri;
+    };
     for (uint32_t first = R.first; first < R.end; first += ROWS * R.step) {
         if (first != R.first) {
 #pragma unroll
             for (int k = 0; k < ROWS; ++k) {
                 const uint32_t i = first + k * R.step;
                 if (i < R.end) {
-                    fr[k] = r[i];
-                    fq[k] = q[i];
-                    fd[k] = PJ != PJ_NONE ? invd[i] : VT(0);
+                    fr[k] = re[i];
+                    fq[k] = qe[i];
+                    fd[k] = PJ != PJ_NONE ? de[i] : E{};
                 }
             }
         }
@@ -254,14 +291,15 @@ __global__ __launch_bounds__(BLOCK) void k_update(int64_t V, VT* __restrict__ r,
         for (int k = 0; k < ROWS; ++k) {
             const uint32_t i = first + k * R.step;
             if (i < R.end) {
-                const VT ri = fr[k] - a * fq[k];
-                r[i] = ri;
-                if (PJ == PJ_JACOBI) rz += ri * (fd[k] * ri);
-                if (PJ == PJ_SPLIT) rz += ri * ri;
-                rr += PJ == PJ_SPLIT ? (ri * ri) * fd[k] : ri * ri;
+                E o;
+#pragma unroll
+                for (int c = 0; c < W; ++c) RW::set(o, c, row(RW::get(fr[k], c), RW::get(fq[k], c), RW::get(fd[k], c)));
+                re[i] = o;
             }
         }
     }
+    if (W > 1 && blockIdx.x == 0 && threadIdx.x == 0)
+        for (int64_t t = V / W * W; t < V; ++t) r[t] = row(r[t], q[t], PJ != PJ_NONE ? invd[t] : VT(0));
     const double b2 = block_sum(static_cast<double>(rr), lds);
     if (threadIdx.x == 0) partials[R_RR * P + blockIdx.x] = b2;
     if (PJ != PJ_NONE) {
@@ -288,12 +326,14 @@ __device__ __forceinline__ bool energy_converged(const PcgScalars* S, double pq)
 // broke down), then p = z + beta p while running (z = D^-1 r for Jacobi);
 // block 0 writes the next state N.  A finished state is carried forward
 // unchanged.
-template <class VT, int PJ>
+template <class VT, int PJ, int W>
 __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, const VT* __restrict__ r,
                                                  const VT* __restrict__ invd, const VT* __restrict__ z,
                                                  VT* __restrict__ p, const double* __restrict__ partials, int P,
                                                  int n_rz, const PcgScalars* __restrict__ S,
                                                  PcgScalars* __restrict__ N) {
+    typedef Rows<VT, W> RW;
+    typedef typename RW::T E;
     __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (S->done) {
@@ -301,17 +341,31 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         return;
     }
     const int G = gridDim.x;
-    const FrontRange32 R = front_range32(V);
+    E* xe = reinterpret_cast<E*>(x);
+    E* pe = reinterpret_cast<E*>(p);
+    const E* re = reinterpret_cast<const E*>(r);
+    const E* de = reinterpret_cast<const E*>(invd);
+    const E* ze = reinterpret_cast<const E*>(z);
+    const FrontRange32 R = front_range32(V / W);
     constexpr int ROWS = CLOSE_ROWS;
-    // z (or D^-1 r), p and x of the first rows, loaded before the fold
-    VT fz[ROWS], fp[ROWS], fx[ROWS];
+    // z (or D^-1 r), p and x of the first elements, loaded before the fold
+    auto zof = [&](uint32_t i) {
+        if (PJ == PJ_SPLIT) return re[i];
+        if (PJ == PJ_NONE) return ze[i];
+        const E rv = re[i], dv = de[i];
+        E o;
+#pragma unroll
+        for (int c = 0; c < W; ++c) RW::set(o, c, RW::get(dv, c) * RW::get(rv, c));
+        return o;
+    };
+    E fz[ROWS], fp[ROWS], fx[ROWS];
 #pragma unroll
     for (int k = 0; k < ROWS; ++k) {
         const uint32_t i = R.first + k * R.step;
         if (i < R.end) {
-            fz[k] = PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i]);
-            fp[k] = p[i];
-            fx[k] = x[i];
+            fz[k] = zof(i);
+            fp[k] = pe[i];
+            fx[k] = xe[i];
         }
     }
     const double pq = S->pq_now;
@@ -336,9 +390,9 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
                 for (int k = 0; k < ROWS; ++k) {
                     const uint32_t i = first + k * R.step;
                     if (i < R.end) {
-                        if (run) fz[k] = PJ == PJ_JACOBI ? invd[i] * r[i] : (PJ == PJ_SPLIT ? r[i] : z[i]);
-                        fp[k] = p[i];
-                        fx[k] = x[i];
+                        if (run) fz[k] = zof(i);
+                        fp[k] = pe[i];
+                        fx[k] = xe[i];
                     }
                 }
             }
@@ -346,11 +400,24 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
             for (int k = 0; k < ROWS; ++k) {
                 const uint32_t i = first + k * R.step;
                 if (i < R.end) {
-                    x[i] = fx[k] + a * fp[k];
-                    if (run) p[i] = fz[k] + bt * fp[k];
+                    E ox, op;
+#pragma unroll
+                    for (int c = 0; c < W; ++c) {
+                        RW::set(ox, c, RW::get(fx[k], c) + a * RW::get(fp[k], c));
+                        RW::set(op, c, RW::get(fz[k], c) + bt * RW::get(fp[k], c));
+                    }
+                    xe[i] = ox;
+                    if (run) pe[i] = op;
                 }
             }
         }
+        if (W > 1 && lead)
+            for (int64_t t = V / W * W; t < V; ++t) {
+                const VT zt = PJ == PJ_JACOBI ? invd[t] * r[t] : (PJ == PJ_SPLIT ? r[t] : z[t]);
+                const VT pt = p[t];
+                x[t] = x[t] + a * pt;
+                if (run) p[t] = zt + bt * pt;
+            }
     }
     if (lead) {
         N->rho = rz;
@@ -623,16 +690,46 @@ void finalize(SolveCache* c, int what, int n_rr, double factor, int relative, Pc
 int rz_parts(const SolveCache* c, int precond) { return precond == DEC_PRECOND_JACOBI ? c->G : c->Gs; }
 
 // The update kernel on G blocks, its row groups sized by the rows each thread has.
+// Rows per element of the vector kernels: 2 for FP32 vectors that all sit on
+// 8-byte boundaries (every buffer this library allocates does), else 1.
+template <class VT>
+int vec_lanes(std::initializer_list<const void*> ptrs) {
+    uintptr_t o = 0;
+    for (const void* q : ptrs) o |= reinterpret_cast<uintptr_t>(q);
+    return (o & 7) == 0 ? 2 : 1;
+}
+
+// The update kernel on G blocks, its element groups sized by the elements each thread has.
+template <class VT, int PJ, int W>
+void launch_update_w(hipStream_t s, int G, int64_t V, VT* r, const VT* q, const VT* invd, double* part, int P,
+                     int n_pq, PcgScalars* S) {
+    const int64_t per_thread = (V / W + (int64_t)G * BLOCK - 1) / ((int64_t)G * BLOCK);
+    if (per_thread > 12)
+        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_MANY, W>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part,
+                           P, n_pq, S);
+    else
+        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_FEW, W>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part,
+                           P, n_pq, S);
+}
+
 template <class VT, int PJ>
 void launch_update(hipStream_t s, int G, int64_t V, VT* r, const VT* q, const VT* invd, double* part, int P, int n_pq,
                    PcgScalars* S) {
-    const int64_t rows_per_thread = (V + (int64_t)G * BLOCK - 1) / ((int64_t)G * BLOCK);
-    if (rows_per_thread > 12)
-        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_MANY>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part, P,
-                           n_pq, S);
-    else
-        hipLaunchKernelGGL((k_update<VT, PJ, UPDATE_ROWS_FEW>), dim3(G), dim3(BLOCK), 0, s, V, r, q, invd, part, P,
-                           n_pq, S);
+    if constexpr (sizeof(VT) == 4)
+        if (vec_lanes<VT>({r, q, invd}) == 2) return launch_update_w<VT, PJ, 2>(s, G, V, r, q, invd, part, P, n_pq, S);
+    launch_update_w<VT, PJ, 1>(s, G, V, r, q, invd, part, P, n_pq, S);
+}
+
+template <class VT, int PJ>
+void launch_close(hipStream_t s, int G, int64_t V, VT* x, const VT* r, const VT* invd, const VT* z, VT* p,
+                  const double* part, int P, int n_rz, const PcgScalars* S, PcgScalars* N) {
+    if constexpr (sizeof(VT) == 4)
+        if (vec_lanes<VT>({x, r, invd, z, p}) == 2) {
+            hipLaunchKernelGGL((k_close<VT, PJ, 2>), dim3(G), dim3(BLOCK), 0, s, V, x, r, invd, z, p, part, P, n_rz,
+                               S, N);
+            return;
+        }
+    hipLaunchKernelGGL((k_close<VT, PJ, 1>), dim3(G), dim3(BLOCK), 0, s, V, x, r, invd, z, p, part, P, n_rz, S, N);
 }
 
 template <class VT>
@@ -646,23 +743,19 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
     if (R.precond == DEC_PRECOND_JACOBI && R.split) {
         launch_update<VT, PJ_SPLIT>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
-        hipLaunchKernelGGL((k_close<VT, PJ_SPLIT>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
-                           (const VT*)nullptr, (const VT*)nullptr, R.p, part, P, G, S, N);
+        launch_close<VT, PJ_SPLIT>(c->stream, G, V, R.x, R.r, nullptr, nullptr, R.p, part, P, G, S, N);
     } else if (R.precond == DEC_PRECOND_JACOBI) {
         launch_update<VT, PJ_JACOBI>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
-        hipLaunchKernelGGL((k_close<VT, PJ_JACOBI>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r, R.invd,
-                           (const VT*)nullptr, R.p, part, P, G, S, N);
+        launch_close<VT, PJ_JACOBI>(c->stream, G, V, R.x, R.r, R.invd, nullptr, R.p, part, P, G, S, N);
     } else if (R.precond == DEC_PRECOND_BLOCK) {
-        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, (const VT*)nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.z, R.r, region(c, R_RZ), S);       // z = M r, r.z partials
-        hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
-                           (const VT*)nullptr, R.z, R.p, part, P, c->Gs, S, N);
+        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N);
     } else {
-        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, (const VT*)nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S);
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
-        hipLaunchKernelGGL((k_close<VT, PJ_NONE>), dim3(G), dim3(BLOCK), 0, c->stream, V, R.x, R.r,
-                           (const VT*)nullptr, R.z, R.p, part, P, c->Gs, S, N);
+        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N);
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -1139,8 +1232,7 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
                 PcgScalars* N = st + ((k & 1) ^ 1);
                 launch_sell<double, MODE_DOT>(&c, A, p, q, nullptr, part + R_PQ * P, S);
                 launch_update<double, PJ_JACOBI>(c.stream, G, V, r, q, m->invdiag64.p, part, P, Gs, S);
-                hipLaunchKernelGGL((k_close<double, PJ_JACOBI>), dim3(G), blk, 0, c.stream, V, T, r,
-                                   m->invdiag64.p, (const double*)nullptr, p, part, P, G, S, N);
+                launch_close<double, PJ_JACOBI>(c.stream, G, V, T, r, m->invdiag64.p, nullptr, p, part, P, G, S, N);
             }
             HIP_CHECK(hipGetLastError());
             s = state(st);

@@ -522,6 +522,8 @@ struct dec_server {
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;  // around a step's graph replays (timing)
     double batch_ms = 0, batch_bytes = 0;         // replay time and algorithmic bytes of the batched iterations
     int64_t batch_iterations = 0;                 // system-iterations in them
+    double host_ms[4] = {0, 0, 0, 0};             // dec_server_step phases: launch, admissions, wait, refinement
+    int64_t steps = 0;
 };
 
 namespace {
@@ -1089,6 +1091,13 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
     try {
         s->ctx->set_device();
         const int ns = (int)s->slots.size();
+        ++s->steps;
+        double mark = now_ms(s->t0);
+        auto phase = [&](int k) {  // host time of a phase of this step
+            const double t = now_ms(s->t0);
+            s->host_ms[k] += t - mark;
+            mark = t;
+        };
         // 1. one batch of inner iterations for every system in PH_INNER
         std::vector<int> inner[2];
         for (int k = 0; k < ns; ++k)
@@ -1114,6 +1123,7 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             HIP_CHECK(hipEventRecord(s->ev_chunk, s->solve_stream));
             launched = true;
         }
+        phase(0);
         // 2. admissions (setup overlaps the batch on the setup stream)
         while (!s->pending.empty()) {
             int free_k = -1;
@@ -1129,11 +1139,13 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             s->pending.pop_front();
             admit(s, qq, free_k);
         }
+        phase(1);
         // 3. wait for the batch, then refinement steps for systems whose inner solve ended
         if (launched) HIP_CHECK(hipEventSynchronize(s->ev_chunk));
         HIP_CHECK(hipMemcpyAsync(s->h_st, s->d_st.p, 3 * ns * sizeof(PcgScalars), hipMemcpyDeviceToHost,
                                  s->solve_stream));
         HIP_CHECK(hipStreamSynchronize(s->solve_stream));
+        phase(2);
         if (launched) {  // the batch's replay time and the iterations it ran
             float ms = 0.0f;
             HIP_CHECK(hipEventElapsedTime(&ms, s->ev_b0, s->ev_b1));
@@ -1161,6 +1173,7 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
         for (int k : outer) (s->slots[k].fresh ? fresh : old).push_back(k);
         outer_steps(s, fresh);
         outer_steps(s, old);
+        phase(3);
         int act = 0;
         for (int k = 0; k < ns; ++k) act += s->slots[k].phase != PH_FREE;
         if (n_active) *n_active = act;
@@ -1181,17 +1194,17 @@ int dec_server_poll(dec_server* s, dec_result* out, int32_t max, int32_t* n_out)
     return DEC_OK;
 }
 
-int dec_server_stats(const dec_server* s, double* batch_ms, double* batch_bytes, int64_t* batch_iterations,
-                     int32_t* variant) {
-    if (!s) return DEC_EINVAL;
-    if (batch_ms) *batch_ms = s->batch_ms;
-    if (batch_bytes) *batch_bytes = s->batch_bytes;
-    if (batch_iterations) *batch_iterations = s->batch_iterations;
-    if (variant)
-        for (int k = 0; k < 2; ++k) {
-            variant[2 * k] = s->tuned[k] ? s->unroll[k] : 0;
-            variant[2 * k + 1] = s->tuned[k] ? s->nt[k] : 0;
-        }
+int dec_server_stats(const dec_server* s, dec_server_counters* out) {
+    if (!s || !out) return DEC_EINVAL;
+    out->batch_ms = s->batch_ms;
+    out->batch_bytes = s->batch_bytes;
+    out->batch_iterations = s->batch_iterations;
+    for (int k = 0; k < 2; ++k) {
+        out->variant[2 * k] = s->tuned[k] ? s->unroll[k] : 0;
+        out->variant[2 * k + 1] = s->tuned[k] ? s->nt[k] : 0;
+    }
+    for (int k = 0; k < 4; ++k) out->host_ms[k] = s->host_ms[k];
+    out->steps = s->steps;
     return DEC_OK;
 }
 
