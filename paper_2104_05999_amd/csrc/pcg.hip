@@ -317,6 +317,7 @@ __device__ __forceinline__ bool energy_converged(const PcgScalars* S, double pq)
     const double term = S->rho * (S->rho / pq);
     const int slot = static_cast<int>(k % ENERGY_DELAY);
     double win = 0.0;
+#pragma unroll 1
     for (int j = 0; j < ENERGY_DELAY; ++j) win += j == slot ? term : S->hist[j];
     return win <= S->rr_stop * (S->cum + term);
 }
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
     __shared__ double lds[2 * (BLOCK / 64 + 1)];
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (S->done) {
-        if (lead) *N = *S;
+        if (lead) copy_state(N, S);
         return;
     }
     const int G = gridDim.x;
@@ -434,6 +435,7 @@ __global__ __launch_bounds__(BLOCK) void k_close(int64_t V, VT* __restrict__ x, 
         if (S->use_energy) {
             const double term = S->rho * (S->rho / pq);
             N->cum = S->cum + term;
+#pragma unroll 1
             for (int j = 0; j < ENERGY_DELAY; ++j) N->hist[j] = S->hist[j];
             N->hist[S->iter % ENERGY_DELAY] = term;
         }

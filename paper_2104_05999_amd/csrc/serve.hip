@@ -186,11 +186,15 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
 // r.r), the closing kernel moves x together with p (x += alpha p, p = D^-1 r
 // + beta p), so p is read once per iteration.  The update's first item
 // stores its fold of p.q in the system's scalars, where the closing kernel
-// reads it instead of folding the partials again.  A thread loads its rows of
-// the chunk (eight of them) before folding the system's partials, so the
-// fold's latency overlaps with their transfer.
+// reads it instead of folding the partials again.  A thread takes eight rows
+// of the chunk in groups of four: the first group's loads are issued before
+// the fold of the system's partials, so the fold's latency overlaps with their
+// transfer, and holding one group at a time leaves registers for more
+// resident waves.  The rows are taken in the same order either way.
 constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
 static_assert(ROWS_PER_THREAD * BLOCK == CHUNK_ROWS, "a chunk is a whole number of rows per thread");
+constexpr int ROW_GROUP = 4;
+static_assert(ROWS_PER_THREAD % ROW_GROUP == 0, "whole groups of rows per thread");
 
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
@@ -206,29 +210,35 @@ __global__ __launch_bounds__(BLOCK) void bk_update(const BSlot* __restrict__ slo
         const VT *q = SlotVec<VT>::q(S), *invd = SlotVec<VT>::invd(S);
         int64_t r0, r1;
         chunk_rows(S, item.chunk, &r0, &r1);
-        VT fr[ROWS_PER_THREAD], fq[ROWS_PER_THREAD], fd[ROWS_PER_THREAD];
+        VT fr[ROW_GROUP], fq[ROW_GROUP], fd[ROW_GROUP];
+        auto load = [&](int g) {
 #pragma unroll
-        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-            const int64_t i = r0 + threadIdx.x + k * BLOCK;
-            if (i < r1) {
-                fr[k] = r[i];
-                fq[k] = q[i];
-                fd[k] = invd[i];
+            for (int k = 0; k < ROW_GROUP; ++k) {
+                const int64_t i = r0 + threadIdx.x + (g * ROW_GROUP + k) * BLOCK;
+                if (i < r1) {
+                    fr[k] = r[i];
+                    fq[k] = q[i];
+                    fd[k] = invd[i];
+                }
             }
-        }
+        };
+        load(0);
         const double pq = reduce_bcast(S.part + Q_PQ * S.nchunks, S.nchunks, lds);
         if (item.chunk == 0 && threadIdx.x == 0) st->pq_now = pq;
         if (!(pq > 0.0) || !isfinite(pq)) continue;
         const VT a = static_cast<VT>(st->rho / pq);
         VT rz = 0, rr = 0;
+        for (int g = 0; g < ROWS_PER_THREAD / ROW_GROUP; ++g) {
+            if (g > 0) load(g);
 #pragma unroll
-        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-            const int64_t i = r0 + threadIdx.x + k * BLOCK;
-            if (i < r1) {
-                const VT ri = fr[k] - a * fq[k];
-                r[i] = ri;
-                rz += ri * (fd[k] * ri);
-                rr += ri * ri;
+            for (int k = 0; k < ROW_GROUP; ++k) {
+                const int64_t i = r0 + threadIdx.x + (g * ROW_GROUP + k) * BLOCK;
+                if (i < r1) {
+                    const VT ri = fr[k] - a * fq[k];
+                    r[i] = ri;
+                    rz += ri * (fd[k] * ri);
+                    rr += ri * ri;
+                }
             }
         }
         const double b1 = block_sum(static_cast<double>(rz), lds);
@@ -252,23 +262,26 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
         PcgScalars* N = S.st + (par ^ 1);
         const bool lead = item.chunk == 0 && threadIdx.x == 0;
         if (Sp->done) {
-            if (lead) *N = *Sp;
+            if (lead) copy_state(N, Sp);
             continue;
         }
         VT *x = SlotVec<VT>::x(S), *p = SlotVec<VT>::p(S);
         const VT *r = SlotVec<VT>::r(S), *invd = SlotVec<VT>::invd(S);
         int64_t r0, r1;
         chunk_rows(S, item.chunk, &r0, &r1);
-        VT fz[ROWS_PER_THREAD], fp[ROWS_PER_THREAD], fx[ROWS_PER_THREAD];
+        VT fz[ROW_GROUP], fp[ROW_GROUP], fx[ROW_GROUP];
+        auto load = [&](int g) {
 #pragma unroll
-        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-            const int64_t i = r0 + threadIdx.x + k * BLOCK;
-            if (i < r1) {
-                fz[k] = invd[i] * r[i];
-                fp[k] = p[i];
-                fx[k] = x[i];
+            for (int k = 0; k < ROW_GROUP; ++k) {
+                const int64_t i = r0 + threadIdx.x + (g * ROW_GROUP + k) * BLOCK;
+                if (i < r1) {
+                    fz[k] = invd[i] * r[i];
+                    fp[k] = p[i];
+                    fx[k] = x[i];
+                }
             }
-        }
+        };
+        load(0);
         const int nc = S.nchunks;
         const double pq = Sp->pq_now;
         double rr, rz;
@@ -286,12 +299,15 @@ __global__ __launch_bounds__(BLOCK) void bk_close(const BSlot* __restrict__ slot
             const VT a = static_cast<VT>(Sp->rho / pq);
             const VT bt = static_cast<VT>(beta);
             const bool run = done == PCG_RUNNING;
+            for (int g = 0; g < ROWS_PER_THREAD / ROW_GROUP; ++g) {
+                if (g > 0) load(g);
 #pragma unroll
-            for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-                const int64_t i = r0 + threadIdx.x + k * BLOCK;
-                if (i < r1) {
-                    x[i] = fx[k] + a * fp[k];
-                    if (run) p[i] = fz[k] + bt * fp[k];
+                for (int k = 0; k < ROW_GROUP; ++k) {
+                    const int64_t i = r0 + threadIdx.x + (g * ROW_GROUP + k) * BLOCK;
+                    if (i < r1) {
+                        x[i] = fx[k] + a * fp[k];
+                        if (run) p[i] = fz[k] + bt * fp[k];
+                    }
                 }
             }
         }
@@ -1124,7 +1140,9 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             launched = true;
         }
         phase(0);
-        // 2. admissions (setup overlaps the batch on the setup stream)
+        // 2. admissions (setup overlaps the batch on the setup stream); once the
+        // batch has ended, the rest wait for the next step, so the host's setup
+        // work does not hold back the next batch
         while (!s->pending.empty()) {
             int free_k = -1;
             for (int k = 0; k < ns; ++k)
@@ -1138,6 +1156,7 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             ServeReq qq = q;
             s->pending.pop_front();
             admit(s, qq, free_k);
+            if (launched && hipEventQuery(s->ev_chunk) == hipSuccess) break;
         }
         phase(1);
         // 3. wait for the batch, then refinement steps for systems whose inner solve ended

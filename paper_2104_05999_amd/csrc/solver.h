@@ -36,6 +36,16 @@ struct PcgScalars {
 };
 
 constexpr int ENERGY_DELAY = 16;
+static_assert(sizeof(PcgScalars) % 8 == 0, "PcgScalars is copied in 8-byte words");
+
+// Copy a state word by word: a plain struct copy stages all of its bytes in
+// registers at once, which in the closing kernels cost half the resident waves.
+__device__ __forceinline__ void copy_state(PcgScalars* __restrict__ dst, const PcgScalars* __restrict__ src) {
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
+    uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+#pragma unroll 1
+    for (int w = 0; w < static_cast<int>(sizeof(PcgScalars) / 8); ++w) d[w] = s[w];
+}
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAXITER = 2, PCG_BREAKDOWN = 3 };
 
