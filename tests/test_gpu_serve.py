@@ -137,6 +137,27 @@ def test_cancel_pending_and_admitted(ctx, dev):
     assert alone[0]["k_eff"] == out[1]["k_eff"]
 
 
+def test_close_with_requests_in_setup_and_pending(ctx, dev):
+    """Setup runs on the server's admission thread: closing a server while requests are in setup,
+    handed over or still pending stops and joins that thread and releases everything; a server
+    created afterwards on the same context serves a request as one that never saw the first."""
+    import paper_2104_05999_amd as dec
+    built = [make_request(10, 6, 40 + k, dev) for k in range(6)]
+    reqs = [b[0] for b in built]
+    before, _ = serve(ctx, [reqs[0]])
+    t_before = reqs[0]["T_out"].clone()
+    for steps in (0, 1, 2):
+        srv = dec.Server(ctx, 4 << 30, max_slots=2)
+        for k, r in enumerate(reqs):
+            srv.submit(r, user_tag=k)
+        for _ in range(steps):
+            srv.step()
+        srv.close()
+    reqs[0]["T_out"].zero_()
+    after, _ = serve(ctx, [reqs[0]])
+    assert before[0]["status"] == 0 and after[0]["status"] == 0
+    assert after[0]["k_eff"] == before[0]["k_eff"] and torch.equal(reqs[0]["T_out"], t_before)
+
 def test_a_bad_request_fails_alone(ctx, dev):
     """A request whose boundary data is invalid (a bc_type of 7) or whose mesh is not a valid
     tetrahedralisation (a repeated vertex) ends with its own error status; the requests around it
