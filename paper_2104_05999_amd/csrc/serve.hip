@@ -548,6 +548,8 @@ struct dec_server {
     int unroll[2] = {4, 4};
     int nt[2] = {1, 0};
     bool tuned[2] = {false, false};
+    int tuned_items[2] = {0, 0};  // work items of the batch the variant was timed on
+    int tunings[2] = {0, 0};
     hipEvent_t ev_b0 = nullptr, ev_b1 = nullptr;  // around a step's graph replays (timing)
     double batch_ms = 0, batch_bytes = 0;         // replay time and algorithmic bytes of the batched iterations
     int64_t batch_iterations = 0;                 // system-iterations in them
@@ -861,7 +863,11 @@ void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t*
 // three rounds of two launches per variant, each variant's best round.  The
 // extra launches recompute q = A p and the p.q partials of the same p, which
 // the batch's first iteration computes again, and every variant sums each row
-// in the same order, so the choice changes no result.
+// in the same order, so the choice changes no result.  The first batch of a
+// stream may hold a single small system, so the variant is timed again each
+// time the batch has doubled since (at most MAX_TUNINGS times per precision).
+constexpr int MAX_TUNINGS = 5;
+
 template <class VT>
 void tune_batched_spmv(dec_server* s, const BItem* items, const int32_t* n_items) {
     const int pi = sizeof(VT) == 8 ? 0 : 1;
@@ -1257,6 +1263,18 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             s->h_n[0] = n32;
             s->h_n[1] = n64;
             HIP_CHECK(hipMemcpyAsync(s->d_n.p, s->h_n, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s->solve_stream));
+            for (int prec = 0; prec < 2; ++prec) {  // time the variant again on a batch twice as large
+                const int n = prec == 1 ? n32 : n64;
+                if (s->tuned[prec] && n >= 2 * s->tuned_items[prec] && s->tunings[prec] < MAX_TUNINGS) {
+                    s->tuned[prec] = false;
+                    if (s->graph[prec]) HIP_CHECK(hipGraphExecDestroy(s->graph[prec]));
+                    s->graph[prec] = nullptr;
+                }
+                if (n && !s->tuned[prec]) {
+                    s->tuned_items[prec] = n;
+                    ++s->tunings[prec];
+                }
+            }
             hipGraphExec_t g32 = n32 ? batched_graph(s, 1) : nullptr;  // captured (and tuned) on first use
             hipGraphExec_t g64 = n64 ? batched_graph(s, 0) : nullptr;
             HIP_CHECK(hipEventRecord(s->ev_b0, s->solve_stream));
