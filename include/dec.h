@@ -270,6 +270,8 @@ typedef struct dec_solve_stats {
  *       so a gather one plane back stays in L2; unset, plain order (on this
  *       GPU the bands cut the fetched bytes but not the time).  Changes the
  *       grouping of the product's partial sums, so the rounding of solves;
+ *   DEC_VEC_PAIRS=0       FP32 vector kernels one row per lane instead of
+ *       two (float2 elements);
  *   DEC_JACOBI_SPLIT=0|1  run Jacobi PCG on A, or always in split form (CG
  *       on D^-1/2 A D^-1/2); unset, the split form is taken for plain
  *       systems of 65,536 rows or more with a positive diagonal;

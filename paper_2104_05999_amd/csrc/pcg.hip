@@ -714,19 +714,21 @@ void launch_update_w(hipStream_t s, int G, int64_t V, VT* r, const VT* q, const 
                            P, n_pq, S);
 }
 
+// pairs = false keeps one row per element (DEC_VEC_PAIRS=0, for tests)
 template <class VT, int PJ>
 void launch_update(hipStream_t s, int G, int64_t V, VT* r, const VT* q, const VT* invd, double* part, int P, int n_pq,
-                   PcgScalars* S) {
+                   PcgScalars* S, bool pairs = true) {
     if constexpr (sizeof(VT) == 4)
-        if (vec_lanes<VT>({r, q, invd}) == 2) return launch_update_w<VT, PJ, 2>(s, G, V, r, q, invd, part, P, n_pq, S);
+        if (pairs && vec_lanes<VT>({r, q, invd}) == 2)
+            return launch_update_w<VT, PJ, 2>(s, G, V, r, q, invd, part, P, n_pq, S);
     launch_update_w<VT, PJ, 1>(s, G, V, r, q, invd, part, P, n_pq, S);
 }
 
 template <class VT, int PJ>
 void launch_close(hipStream_t s, int G, int64_t V, VT* x, const VT* r, const VT* invd, const VT* z, VT* p,
-                  const double* part, int P, int n_rz, const PcgScalars* S, PcgScalars* N) {
+                  const double* part, int P, int n_rz, const PcgScalars* S, PcgScalars* N, bool pairs = true) {
     if constexpr (sizeof(VT) == 4)
-        if (vec_lanes<VT>({x, r, invd, z, p}) == 2) {
+        if (pairs && vec_lanes<VT>({x, r, invd, z, p}) == 2) {
             hipLaunchKernelGGL((k_close<VT, PJ, 2>), dim3(G), dim3(BLOCK), 0, s, V, x, r, invd, z, p, part, P, n_rz,
                                S, N);
             return;
@@ -743,21 +745,22 @@ void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a
     PcgScalars* S = R.st + par;
     PcgScalars* N = R.st + (par ^ 1);
     launch_sell<VT, MODE_DOT>(c, R.A, R.p, R.q, nullptr, region(c, R_PQ), S, ev_a, ev_b);
+    const bool pp = c->vec_pairs;
     if (R.precond == DEC_PRECOND_JACOBI && R.split) {
-        launch_update<VT, PJ_SPLIT>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
-        launch_close<VT, PJ_SPLIT>(c->stream, G, V, R.x, R.r, nullptr, nullptr, R.p, part, P, G, S, N);
+        launch_update<VT, PJ_SPLIT>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S, pp);
+        launch_close<VT, PJ_SPLIT>(c->stream, G, V, R.x, R.r, nullptr, nullptr, R.p, part, P, G, S, N, pp);
     } else if (R.precond == DEC_PRECOND_JACOBI) {
-        launch_update<VT, PJ_JACOBI>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S);
-        launch_close<VT, PJ_JACOBI>(c->stream, G, V, R.x, R.r, R.invd, nullptr, R.p, part, P, G, S, N);
+        launch_update<VT, PJ_JACOBI>(c->stream, G, V, R.r, R.q, R.invd, part, P, n_pq, S, pp);
+        launch_close<VT, PJ_JACOBI>(c->stream, G, V, R.x, R.r, R.invd, nullptr, R.p, part, P, G, S, N, pp);
     } else if (R.precond == DEC_PRECOND_BLOCK) {
-        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S, pp);
         launch_sell<VT, MODE_DOTB>(c, R.M, R.r, R.z, R.r, region(c, R_RZ), S);       // z = M r, r.z partials
-        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N);
+        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N, pp);
     } else {
-        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S);
+        launch_update<VT, PJ_NONE>(c->stream, G, V, R.r, R.q, nullptr, part, P, n_pq, S, pp);
         launch_sell<VT, MODE_PLAIN>(c, R.G, R.r, R.w, nullptr, nullptr, S);          // w = G r
         launch_sell<VT, MODE_DOTB>(c, R.GT, R.w, R.z, R.r, region(c, R_RZ), S);      // z = G^T w, r.z partials
-        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N);
+        launch_close<VT, PJ_NONE>(c->stream, G, V, R.x, R.r, nullptr, R.z, R.p, part, P, c->Gs, S, N, pp);
     }
     HIP_CHECK(hipGetLastError());
 }
@@ -1325,6 +1328,7 @@ SolveCache* get_solve_cache(dec_mesh* m) {
         }
         if (const char* env = getenv("DEC_SELL_COLS")) c->force_cols = atoi(env);
         if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->split = atoi(env) != 0;
+        if (const char* env = getenv("DEC_VEC_PAIRS")) c->vec_pairs = atoi(env) != 0;
         auto blocks = [&](int64_t rows_per_block, int pc) {
             const int64_t want = (m->V + rows_per_block - 1) / rows_per_block;
             const int64_t cap = (int64_t)pc * m->ctx->num_cus;

@@ -91,6 +91,7 @@ struct SolveCache {
     bool pinned_variant = false;  // unroll / non-temporal loads set through the environment
     int force_cols = 0;           // 32, 16 or 8: this column format where a matrix has it (environment)
     int split = -1;               // Jacobi in split form: 1 always, 0 never, -1 by size (environment)
+    bool vec_pairs = true;        // FP32 vector kernels on float2 elements where the vectors allow (environment)
     DBuf<double> x64, r64, p64, q64, z64, w64, t64;
     DBuf<float> x32, r32, p32, q32, z32, w32;
     DBuf<double> partials;  // [3G]: per-block partial sums of p.q, r.r, r.z
