@@ -18,11 +18,8 @@
 
 #include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <deque>
 #include <memory>
-#include <mutex>
-#include <thread>
 
 #include "solver.h"
 
@@ -477,7 +474,7 @@ double now_ms(std::chrono::steady_clock::time_point t0) {
 }  // namespace
 
 // ---------------------------------------------------------------- host side
-enum SlotPhase { PH_FREE = 0, PH_OUTER = 1, PH_INNER = 2, PH_ADMITTING = 3 };
+enum SlotPhase { PH_FREE = 0, PH_OUTER = 1, PH_INNER = 2 };
 
 struct ServeReq {
     uint64_t ticket;
@@ -505,16 +502,6 @@ struct ServeSlot {
     bool fallback = false;  // a mixed-precision system that went on in FP64
     bool broke = false;     // its last FP64 inner solve broke down
     int64_t iter_mark = 0;  // inner iterations of the current inner solve already counted in the batch bytes
-    bool cancel = false;    // PH_ADMITTING: canceled while its setup runs
-};
-
-// A request handed to the admission thread: its slot is PH_ADMITTING while the
-// thread builds the system into `sl` on the setup stream.
-struct AdmitJob {
-    ServeReq q{};
-    int slot = -1;
-    std::unique_ptr<ServeSlot> sl;
-    int status = DEC_OK;
 };
 
 struct dec_server {
@@ -555,15 +542,6 @@ struct dec_server {
     int64_t batch_iterations = 0;                 // system-iterations in them
     double host_ms[4] = {0, 0, 0, 0};             // dec_server_step phases: launch, admissions, wait, refinement
     int64_t steps = 0;
-    // Admissions run on a host thread of their own (the setup synchronises the
-    // setup stream a dozen times; the step loop does not wait for it).  The
-    // thread touches only the jobs it is given, the setup context and stream;
-    // `mu` guards the two queues and `stop`.
-    std::thread admitter;
-    std::mutex mu;
-    std::condition_variable cv;
-    bool stop = false;
-    std::deque<AdmitJob> todo, finished;
 };
 
 namespace {
@@ -648,169 +626,69 @@ BSlot describe(dec_server* s, int k) {
 }
 
 // Setup of one request on the setup stream.  Returns false when it failed (result recorded).
-// Build the system of request q into sl (admission thread, setup stream):
-// topology, *1 and cut, assembly, boundary data, the server's vectors, and the
-// `ready` event on the setup stream.  Throws DecError; the caller releases sl.
-void prepare_slot(dec_server* s, const ServeReq& q, ServeSlot& sl) {
+bool admit(dec_server* s, const ServeReq& q, int k) {
+    ServeSlot& sl = s->slots[k];
+    hipEvent_t ev = sl.ready;  // events are kept across reuse of a slot
+    sl = ServeSlot();
+    sl.ready = ev;
     sl.ticket = q.ticket;
     sl.req = q.req;
     sl.t_submit = q.t_submit;
     sl.t_admit = now_ms(s->t0);
     sl.mode = s->opts.precision;
     sl.inputs = q.inputs;
+    sl.budget_bytes = estimate_bytes(q.req.V, q.req.T);
+    s->committed += sl.budget_bytes;
     dec_mesh* m = new dec_mesh();
     m->ctx = &s->setup_ctx;
     m->V = q.req.V;
     m->T = q.req.T;
     sl.mesh = m;
-    // the caller's writes to the request arrays (on its stream, before submit) come first
-    HIP_CHECK(hipStreamWaitEvent(s->setup_stream, q.inputs, 0));
-    if (q.req.mesh)
-        clone_topology_device(m, q.req.mesh);
-    else
-        build_topology_device(m, q.req.xyz, q.req.tets);
-    hodge1_device(m, q.req.kappa, q.req.n_cracks, q.req.cracks);
-    assemble_device(m);
-    apply_bc_internal(m, q.req.bc_type, q.req.bc_value, q.req.neumann_f0);
-    compact_mesh(m);
-    const int64_t V = m->V;
-    sl.nchunks = (int32_t)((V + CHUNK_ROWS - 1) / CHUNK_ROWS);
-    dec_ctx* c = &s->setup_ctx;
-    sl.x64.alloc(c, V);
-    sl.r64.alloc(c, V);
-    sl.part.alloc(c, 4 * (int64_t)sl.nchunks);
-    if (sl.mode == DEC_PREC_MIXED) {
-        sl.x32.alloc(c, V);
-        sl.r32.alloc(c, V);
-        sl.p32.alloc(c, V);
-        sl.q32.alloc(c, V);
-    } else {
-        sl.p64.alloc(c, V);
-        sl.q64.alloc(c, V);
-    }
-    if (!sl.ready) HIP_CHECK(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming));
-    HIP_CHECK(hipEventRecord(sl.ready, s->setup_stream));
-}
-
-// The admission thread: builds the jobs it is handed, in order, until stopped.
-void admission_loop(dec_server* s) {
-    (void)hipSetDevice(s->setup_ctx.device);
-    for (;;) {
-        AdmitJob job;
-        {
-            std::unique_lock<std::mutex> lock(s->mu);
-            s->cv.wait(lock, [s] { return s->stop || !s->todo.empty(); });
-            if (s->stop) return;
-            job = std::move(s->todo.front());
-            s->todo.pop_front();
+    try {
+        // the caller's writes to the request arrays (on its stream, before submit) come first
+        HIP_CHECK(hipStreamWaitEvent(s->setup_stream, q.inputs, 0));
+        if (q.req.mesh)
+            clone_topology_device(m, q.req.mesh);
+        else
+            build_topology_device(m, q.req.xyz, q.req.tets);
+        hodge1_device(m, q.req.kappa, q.req.n_cracks, q.req.cracks);
+        assemble_device(m);
+        apply_bc_internal(m, q.req.bc_type, q.req.bc_value, q.req.neumann_f0);
+        compact_mesh(m);
+        const int64_t V = m->V;
+        sl.nchunks = (int32_t)((V + CHUNK_ROWS - 1) / CHUNK_ROWS);
+        dec_ctx* c = &s->setup_ctx;
+        sl.x64.alloc(c, V);
+        sl.r64.alloc(c, V);
+        sl.part.alloc(c, 4 * (int64_t)sl.nchunks);
+        if (sl.mode == DEC_PREC_MIXED) {
+            sl.x32.alloc(c, V);
+            sl.r32.alloc(c, V);
+            sl.p32.alloc(c, V);
+            sl.q32.alloc(c, V);
+        } else {
+            sl.p64.alloc(c, V);
+            sl.q64.alloc(c, V);
         }
-        try {
-            prepare_slot(s, job.q, *job.sl);
-        } catch (const DecError& e) {
-            job.status = e.code;
-            s->setup_ctx.last_error = e.msg;
-            (void)hipStreamSynchronize(s->setup_stream);  // no setup kernel may still use what is released
-        } catch (const std::exception& e) {
-            job.status = DEC_ENOMEM;
-            s->setup_ctx.last_error = e.what();
-            (void)hipStreamSynchronize(s->setup_stream);
-        }
-        std::lock_guard<std::mutex> lock(s->mu);
-        s->finished.push_back(std::move(job));
-    }
-}
-
-void release_slot_buffers(ServeSlot& sl) {
-    if (sl.mesh) {
-        delete sl.mesh;
-        sl.mesh = nullptr;
-    }
-    if (sl.inputs) {
-        (void)hipEventDestroy(sl.inputs);
-        sl.inputs = nullptr;
-    }
-    for (DBuf<double>* b : {&sl.x64, &sl.r64, &sl.p64, &sl.q64, &sl.part}) b->release();
-    for (DBuf<float>* b : {&sl.x32, &sl.r32, &sl.p32, &sl.q32}) b->release();
-}
-
-// Hand the admissible pending requests to the admission thread: a free slot
-// and room in the budget each (both reserved now).
-void hand_off(dec_server* s) {
-    const int ns = (int)s->slots.size();
-    std::vector<AdmitJob> jobs;
-    while (!s->pending.empty()) {
-        int free_k = -1;
-        for (int k = 0; k < ns; ++k)
-            if (s->slots[k].phase == PH_FREE) {
-                free_k = k;
-                break;
-            }
-        if (free_k < 0) break;
-        const ServeReq& q = s->pending.front();
-        const int64_t est = estimate_bytes(q.req.V, q.req.T);
-        if (s->committed + est > (int64_t)s->budget) break;
-        ServeSlot& sl = s->slots[free_k];
-        hipEvent_t ev = sl.ready;  // events are kept across reuse of a slot
-        sl = ServeSlot();
-        sl.phase = PH_ADMITTING;
-        sl.ticket = q.ticket;
-        sl.req = q.req;
-        sl.t_submit = q.t_submit;
-        sl.budget_bytes = est;
-        s->committed += est;
-        AdmitJob job;
-        job.q = q;
-        job.slot = free_k;
-        job.sl.reset(new ServeSlot());
-        job.sl->ready = ev;
-        s->pending.pop_front();
-        jobs.push_back(std::move(job));
-    }
-    if (jobs.empty()) return;
-    {
-        std::lock_guard<std::mutex> lock(s->mu);
-        for (AdmitJob& j : jobs) s->todo.push_back(std::move(j));
-    }
-    s->cv.notify_one();
-}
-
-// Take the jobs the admission thread has finished: a built system becomes
-// PH_OUTER (its first refinement step waits for its `ready` event); a failed
-// or canceled one posts its result and frees its slot and budget.
-void collect_admissions(dec_server* s) {
-    std::deque<AdmitJob> got;
-    {
-        std::lock_guard<std::mutex> lock(s->mu);
-        got.swap(s->finished);
-    }
-    for (AdmitJob& job : got) {
-        ServeSlot& sl = s->slots[job.slot];
-        const int64_t est = sl.budget_bytes;
-        if (job.status == DEC_OK && !sl.cancel) {
-            const double t_admit = job.sl->t_admit;
-            sl = std::move(*job.sl);
-            sl.budget_bytes = est;
-            sl.t_admit = t_admit;
-            sl.phase = PH_OUTER;
-            sl.fresh = true;
-            continue;
-        }
-        if (job.status == DEC_OK) (void)hipStreamSynchronize(s->setup_stream);  // canceled: setup may still run
+        if (!sl.ready) HIP_CHECK(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(sl.ready, s->setup_stream));
+    } catch (const DecError& e) {
         dec_result r{};
-        r.ticket = job.q.ticket;
-        r.user_tag = job.q.req.user_tag;
-        r.status = sl.cancel ? DEC_ECANCELED : job.status;
-        r.t_submit_ms = job.q.t_submit;
-        r.t_admit_ms = job.sl->t_admit;
+        r.ticket = q.ticket;
+        r.user_tag = q.req.user_tag;
+        r.status = e.code;
+        r.t_submit_ms = q.t_submit;
+        r.t_admit_ms = sl.t_admit;
         r.t_finish_ms = now_ms(s->t0);
         s->done.push_back(r);
-        hipEvent_t ev = job.sl->ready;
-        job.sl->ready = nullptr;
-        release_slot_buffers(*job.sl);
-        sl = ServeSlot();
-        sl.ready = ev;
-        s->committed -= est;
+        s->setup_ctx.last_error = e.msg;
+        (void)hipStreamSynchronize(s->setup_stream);  // no setup kernel may still use what free_slot returns
+        free_slot(s, sl);
+        return false;
     }
+    sl.phase = PH_OUTER;
+    sl.fresh = true;
+    return true;
 }
 
 // The item table of the slots in `ids` into dst (room for `cap` items), returning the item
@@ -828,7 +706,7 @@ int build_items(dec_server* s, const std::vector<int>& ids, BItem* dst, int64_t 
 void upload_slots(dec_server* s) {
     const int ns = (int)s->slots.size();
     for (int k = 0; k < ns; ++k)
-        if (s->slots[k].phase == PH_OUTER || s->slots[k].phase == PH_INNER) s->h_slots[k] = describe(s, k);
+        if (s->slots[k].phase != PH_FREE) s->h_slots[k] = describe(s, k);
     HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, ns * sizeof(BSlot), hipMemcpyHostToDevice, s->solve_stream));
 }
 
@@ -864,7 +742,7 @@ void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t*
 // extra launches recompute q = A p and the p.q partials of the same p, which
 // the batch's first iteration computes again, and every variant sums each row
 // in the same order, so the choice changes no result.  The first batch of a
-// stream may hold a single small system, so the variant is timed again each
+// stream may hold a few small systems, so the variant is timed again each
 // time the batch has doubled since (at most MAX_TUNINGS times per precision).
 constexpr int MAX_TUNINGS = 5;
 
@@ -1188,11 +1066,6 @@ int dec_server_create(dec_ctx* ctx, size_t hbm_budget_bytes, const dec_server_op
         HIP_CHECK(hipHostMalloc((void**)&s->h_st, 3 * o.max_slots * sizeof(PcgScalars), hipHostMallocDefault));
         std::memset(s->h_slots, 0, o.max_slots * sizeof(BSlot));
         HIP_CHECK(hipStreamSynchronize(s->solve_stream));
-        try {
-            s->admitter = std::thread(admission_loop, s);
-        } catch (const std::exception&) {
-            dec_fail(DEC_ENOMEM, "could not start the admission thread");
-        }
     } catch (const DecError& e) {
         ctx->last_error = e.msg;
         dec_server_destroy(s);
@@ -1285,11 +1158,21 @@ int dec_server_step(dec_server* s, int32_t* n_active, int32_t* n_pending) {
             launched = true;
         }
         phase(0);
-        // 2. admissions: hand the admissible requests to the admission thread
-        // (their setup overlaps the batch on the setup stream) and take the
-        // systems it has finished
-        hand_off(s);
-        collect_admissions(s);
+        // 2. admissions (setup overlaps the batch on the setup stream)
+        while (!s->pending.empty()) {
+            int free_k = -1;
+            for (int k = 0; k < ns; ++k)
+                if (s->slots[k].phase == PH_FREE) {
+                    free_k = k;
+                    break;
+                }
+            if (free_k < 0) break;
+            const ServeReq& q = s->pending.front();
+            if (s->committed + estimate_bytes(q.req.V, q.req.T) > (int64_t)s->budget) break;
+            ServeReq qq = q;
+            s->pending.pop_front();
+            admit(s, qq, free_k);
+        }
         phase(1);
         // 3. wait for the batch, then refinement steps for systems whose inner solve ended
         if (launched) HIP_CHECK(hipEventSynchronize(s->ev_chunk));
@@ -1378,11 +1261,6 @@ int dec_server_cancel(dec_server* s, uint64_t ticket) {
     try {
         for (size_t k = 0; k < s->slots.size(); ++k) {
             ServeSlot& sl = s->slots[k];
-            if (sl.phase == PH_ADMITTING && sl.ticket == ticket) {
-                if (sl.cancel) return DEC_EINVAL;  // already canceled
-                sl.cancel = true;  // its result is posted once its setup has finished
-                return DEC_OK;
-            }
             if (sl.phase != PH_FREE && sl.ticket == ticket) {
                 HIP_CHECK(hipStreamSynchronize(s->solve_stream));
                 HIP_CHECK(hipStreamSynchronize(s->setup_stream));
@@ -1407,23 +1285,8 @@ int dec_server_cancel(dec_server* s, uint64_t ticket) {
 
 int dec_server_destroy(dec_server* s) {
     if (!s) return DEC_EINVAL;
-    if (s->admitter.joinable()) {
-        {
-            std::lock_guard<std::mutex> lock(s->mu);
-            s->stop = true;
-        }
-        s->cv.notify_all();
-        s->admitter.join();
-    }
     if (s->solve_stream) (void)hipStreamSynchronize(s->solve_stream);
     if (s->setup_stream) (void)hipStreamSynchronize(s->setup_stream);
-    for (std::deque<AdmitJob>* q : {&s->todo, &s->finished})
-        for (AdmitJob& job : *q) {
-            if (job.sl->ready) (void)hipEventDestroy(job.sl->ready);
-            job.sl->ready = nullptr;
-            if (!job.sl->inputs) job.sl->inputs = job.q.inputs;  // not started: the request's event
-            release_slot_buffers(*job.sl);
-        }
     for (auto& sl : s->slots) {
         if (sl.phase != PH_FREE) free_slot(s, sl);
         if (sl.ready) (void)hipEventDestroy(sl.ready);

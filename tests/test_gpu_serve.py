@@ -138,9 +138,9 @@ def test_cancel_pending_and_admitted(ctx, dev):
 
 
 def test_close_with_requests_in_setup_and_pending(ctx, dev):
-    """Setup runs on the server's admission thread: closing a server while requests are in setup,
-    handed over or still pending stops and joins that thread and releases everything; a server
-    created afterwards on the same context serves a request as one that never saw the first."""
+    """Closing a server while requests are admitted (their setup on the side stream) or still
+    pending releases everything; a server created afterwards on the same context serves a request
+    bit for bit as one served before."""
     import paper_2104_05999_amd as dec
     built = [make_request(10, 6, 40 + k, dev) for k in range(6)]
     reqs = [b[0] for b in built]
