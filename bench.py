@@ -50,7 +50,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2104_05999_amd", "csrc", f) for f in
 def _variant(st):
     """The product variant the autotuner chose for a solve (from its stats)."""
     return {"unroll": st["spmv_unroll"], "nontemporal": st["spmv_nontemporal"], "col_bytes": st["spmv_col_bytes"],
-            "band": st["spmv_band"]}
+            "band": st["spmv_band"], "columns_first": st["spmv_order"]}
 
 
 def measured_traffic(n, path=TRAFFIC_FILE):

@@ -252,14 +252,18 @@ typedef struct dec_solve_stats {
     int32_t spmv_col_bytes;   /* its column encoding: 1 one-byte offset-table index, 2
                                  16-bit offset, 4 int32 column                             */
     int32_t spmv_band;        /* slices per band of its banded slice order, 0 for plain    */
+    int32_t spmv_order;       /* 1 when each row issues its column loads ahead of its value
+                                 loads (the tuner's pick where HBM latency dominates), 0
+                                 for the two interleaved                                   */
 } dec_solve_stats;
 
 /* Solver knobs read from the environment when a mesh's solver state is
  * first created (first dec_solve or dec_spmv on it), for tests and timing.
  * The first three change no result; the others change rounding (the split
  * form's arithmetic, or how the reductions are partitioned):
- *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1  pin the sliced-ELL variant the
- *       autotuner would pick (entry pairs in flight, non-temporal loads);
+ *   DEC_SELL_UNROLL=2|3|4, DEC_SELL_NT=0|1, DEC_SELL_ORDER=0|1  pin the
+ *       sliced-ELL variant the autotuner would pick (entry pairs in flight,
+ *       non-temporal loads, a row's loads interleaved or columns first);
  *   DEC_SELL_COLS=8|16|32 read the columns through the one-byte offset
  *       table, the 16-bit offsets or the int32 columns (when the matrix
  *       lacks that encoding, the next wider one it holds);

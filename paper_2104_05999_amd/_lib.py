@@ -64,6 +64,7 @@ class SolveStats(ctypes.Structure):
         ("spmv_nontemporal", ctypes.c_int32),
         ("spmv_col_bytes", ctypes.c_int32),
         ("spmv_band", ctypes.c_int32),
+        ("spmv_order", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -51,7 +51,7 @@ struct dec_ctx {
     int live_children = 0;  // meshes and servers created on this context and not yet destroyed
     // SpMV variant (unroll, non-temporal loads, column format) chosen per (kind of matrix and
     // precision, V, slices, stored entries)
-    std::map<std::array<int64_t, 4>, std::array<int, 3>> spmv_tune;
+    std::map<std::array<int64_t, 4>, std::array<int, 4>> spmv_tune;
     // small pinned staging area for scalar read-backs
     void* pinned = nullptr;
     size_t pinned_bytes = 0;

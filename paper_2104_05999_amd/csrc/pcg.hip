@@ -488,17 +488,33 @@ struct Run {
     const double* sc;    // split Jacobi: s = D^-1/2 (null otherwise)
 };
 
+template <class VT>
+constexpr int prec_index() {
+    return sizeof(VT) == 8 ? 0 : 1;
+}
+
 // With events, the launch carries them (hipExtLaunchKernelGGL): the
 // timestamps are those of the dispatch itself, not of separate markers.
-template <class VT, int MODE, int U, bool NT, bool DIFF, int CF>
-void launch_sell_k(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+template <class VT, int MODE, int U, bool NT, bool DIFF, int CF, int ORD>
+void launch_sell_o(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
     const dim3 g(c->Gs), blk(BLOCK);
     if (ev_a)
-        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x, y, b,
-                              part, done);
+        hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF, ORD>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x,
+                              y, b, part, done);
     else
-        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF>), g, blk, 0, c->stream, A, x, y, b, part, done);
+        hipLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF, ORD>), g, blk, 0, c->stream, A, x, y, b, part, done);
+}
+
+// the load order is the tuner's for the iteration's product (MODE_DOT); the
+// other modes keep the interleaved order
+template <class VT, int MODE, int U, bool NT, bool DIFF, int CF>
+void launch_sell_k(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
+                   const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
+    if constexpr (MODE == MODE_DOT)
+        if (c->order[prec_index<VT>()] == 1)
+            return launch_sell_o<VT, MODE, U, NT, DIFF, CF, 1>(c, A, x, y, b, part, done, ev_a, ev_b);
+    launch_sell_o<VT, MODE, U, NT, DIFF, CF, 0>(c, A, x, y, b, part, done, ev_a, ev_b);
 }
 
 template <class VT, int MODE, int U, bool NT, bool DIFF>
@@ -538,11 +554,6 @@ void launch_sell_nt(SolveCache* c, int unroll, const SellView<VT>& A, const VT* 
             launch_sell_u<VT, MODE, 4, NT>(c, A, x, y, b, part, st, ev_a, ev_b);
             break;
     }
-}
-
-template <class VT>
-constexpr int prec_index() {
-    return sizeof(VT) == 8 ? 0 : 1;
 }
 
 // SpMV launch on Gs blocks; MODE_DOT / MODE_RESID leave Gs partials in `part`
@@ -613,9 +624,10 @@ double column_bytes(const SellView<VT>& v) {
 // Pick the sliced-ELL variant by timing the iteration's product (y = A x with
 // the partials of x.y) on this matrix: the column format (one-byte table
 // indices, 16-bit offsets or int32 columns, as far as S has them), 2, 3 or 4
-// entry pairs in flight, non-temporal loads on or off.  Every variant sums
-// each row in the same order over the same columns, so the choice never
-// changes a result.
+// entry pairs in flight, non-temporal loads on or off, and the order of a
+// row's loads (interleaved, or columns first).  Every variant sums each row
+// in the same order over the same columns, so the choice never changes a
+// result.
 template <class VT>
 void autotune_spmv(SolveCache* c, const SellMatrix& S, int64_t V, const VT* x, VT* y) {
     const int pi = prec_index<VT>();
@@ -629,22 +641,24 @@ void autotune_spmv(SolveCache* c, const SellMatrix& S, int64_t V, const VT* x, V
         for (int cf : {CF_U8, CF_I16, CF_I32})
             if ((cf != CF_U8 || S.tcol.p) && (cf != CF_I16 || S.dcol.p)) formats.push_back(cf);
     }
-    std::vector<std::array<int, 3>> cand;  // unroll, non-temporal, column format
+    std::vector<std::array<int, 4>> cand;  // unroll, non-temporal, column format, load order
     for (int cf : formats) {
         if (c->pinned_variant) {
-            cand.push_back({c->unroll[pi], c->nt[pi], cf});
+            cand.push_back({c->unroll[pi], c->nt[pi], cf, c->order[pi]});
             continue;
         }
         for (int u : {4, 3, 2})
-            for (int nt : {1, 0}) cand.push_back({u, nt, cf});
+            for (int nt : {1, 0})
+                for (int ord : {0, 1}) cand.push_back({u, nt, cf, ord});
     }
     const bool free_choice = !c->pinned_variant && c->force_cols == 0;
     const std::array<int64_t, 4> shape{pi + (S.excess64.p ? 2 : 0) + (S.dcol.p ? 4 : 0) + (S.tcol.p ? 8 : 0), V,
                                        S.nslices, S.entries};
-    auto pick_as = [&](const std::array<int, 3>& v) {
+    auto pick_as = [&](const std::array<int, 4>& v) {
         c->unroll[pi] = v[0];
         c->nt[pi] = v[1];
         c->cf[pi] = v[2];
+        c->order[pi] = v[3];
         c->tuned[pi] = true;
     };
     if (cand.size() == 1) return pick_as(cand[0]);
@@ -661,6 +675,7 @@ void autotune_spmv(SolveCache* c, const SellMatrix& S, int64_t V, const VT* x, V
         for (int k = 0; k < nc; ++k) {
             c->unroll[pi] = cand[k][0];
             c->nt[pi] = cand[k][1];
+            c->order[pi] = cand[k][3];
             const SellView<VT> A = view_cf<VT>(S, V, cand[k][2]);
             // the iteration's own mode (y = A x with the partials of x.y)
             launch_sell<VT, MODE_DOT>(c, A, x, y, nullptr, region(c, R_PQ), nullptr);
@@ -843,7 +858,8 @@ PcgScalars iterate(SolveCache* c, const Run<VT>& R, const dec_solve_opts& o, dec
             continue;
         }
         if (o.use_graph) {
-            GraphKey key{prec, R.precond + (R.split ? 8 : 0), chunk, c->unroll[prec], c->nt[prec], c->cf[prec]};
+            GraphKey key{prec,         R.precond + (R.split ? 8 : 0), chunk, c->unroll[prec], c->nt[prec],
+                         c->cf[prec], c->order[prec]};
             auto it = c->graphs.find(key);
             hipGraphExec_t exec = nullptr;
             if (it == c->graphs.end()) {
@@ -1182,6 +1198,7 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
         c.unroll[0] = known->second[0];
         c.nt[0] = known->second[1];
         c.cf[0] = known->second[2];
+        c.order[0] = known->second[3];
     }
     const SellView<double> A = view<double>(&c, m->sell, V);
     if (stats) {
@@ -1189,6 +1206,7 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
         stats->spmv_nontemporal = c.nt[0];
         stats->spmv_col_bytes = (int32_t)column_bytes(A);
         stats->spmv_band = (int32_t)S.band;
+        stats->spmv_order = c.order[0];
     }
     const int G = c.G, Gs = c.Gs;
     const dim3 blk(BLOCK);
@@ -1326,6 +1344,10 @@ SolveCache* get_solve_cache(dec_mesh* m) {
             c->nt[0] = c->nt[1] = atoi(env);
             c->pinned_variant = true;
         }
+        if (const char* env = getenv("DEC_SELL_ORDER")) {
+            c->order[0] = c->order[1] = atoi(env) == 1 ? 1 : 0;
+            c->pinned_variant = true;
+        }
         if (const char* env = getenv("DEC_SELL_COLS")) c->force_cols = atoi(env);
         if (const char* env = getenv("DEC_JACOBI_SPLIT")) c->split = atoi(env) != 0;
         if (const char* env = getenv("DEC_VEC_PAIRS")) c->vec_pairs = atoi(env) != 0;
@@ -1409,6 +1431,7 @@ int dec_solve(dec_mesh* m, const dec_solve_opts* opts, double* T, dec_solve_stat
             stats->spmv_nontemporal = c->nt[pi];
             stats->spmv_col_bytes = (int32_t)cb;
             stats->spmv_band = (int32_t)m->sell.band;
+            stats->spmv_order = c->order[pi];
         }
         HIP_CHECK(hipEventRecord(c->t0, c->stream));
         hipLaunchKernelGGL(k_init_x, dim3(grid_for(m->V)), dim3(BLOCK), 0, c->stream, m->V, m->fixed.p,

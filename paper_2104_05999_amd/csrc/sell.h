@@ -16,6 +16,8 @@
 // FP64 entry, 5 per FP32 entry, and the same columns.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 // With `excess` set, the product is taken in difference form,
@@ -69,6 +71,56 @@ template <>
 struct Pair<float> {
     typedef float type __attribute__((ext_vector_type(2)));
 };
+
+// How a pair of stored columns is loaded (one load per pair) and split: the
+// pair is kept as the bits it was loaded as and split only where the columns
+// are used, so the load can stay in flight until then.
+template <int CF>
+struct RawCol;
+template <>
+struct RawCol<CF_U8> {
+    typedef uint16_t pair;  // two one-byte indices
+    typedef uint8_t one;
+    typedef uint32_t bits;
+    static __device__ __forceinline__ int32_t lo(bits b, int32_t row, const int32_t* tab) { return row + tab[b & 0xff]; }
+    static __device__ __forceinline__ int32_t hi(bits b, int32_t row, const int32_t* tab) { return row + tab[b >> 8]; }
+};
+template <>
+struct RawCol<CF_I16> {
+    typedef uint32_t pair;  // two 16-bit offsets
+    typedef int16_t one;
+    typedef uint32_t bits;
+    static __device__ __forceinline__ int32_t lo(bits b, int32_t row, const int32_t*) {
+        return row + static_cast<int16_t>(b & 0xffff);
+    }
+    static __device__ __forceinline__ int32_t hi(bits b, int32_t row, const int32_t*) {
+        return row + (static_cast<int32_t>(b) >> 16);
+    }
+};
+template <>
+struct RawCol<CF_I32> {
+    typedef Pair<int32_t>::type pair;
+    typedef int32_t one;
+    typedef Pair<int32_t>::type bits;
+    static __device__ __forceinline__ int32_t lo(bits b, int32_t, const int32_t*) { return b.x; }
+    static __device__ __forceinline__ int32_t hi(bits b, int32_t, const int32_t*) { return b.y; }
+};
+
+template <int CF, class VT>
+__device__ __forceinline__ const typename RawCol<CF>::one* raw_cols(const SellView<VT>& A) {
+    if constexpr (CF == CF_U8)
+        return A.tcol;
+    else if constexpr (CF == CF_I16)
+        return A.dcol;
+    else
+        return A.col;
+}
+
+// the column of one stored entry from its stored form
+template <int CF>
+__device__ __forceinline__ int32_t one_col(int32_t raw, int32_t row, const int32_t* tab) {
+    return CF == CF_U8 ? row + tab[raw] : CF == CF_I16 ? row + raw : raw;
+}
 
 template <class T, bool NT>
 __device__ __forceinline__ T stream_load(const T* p) {
@@ -169,6 +221,90 @@ __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int 
     return acc;
 }
 
+// sell_row with each group's loads in another order: all of the group's
+// columns first (the first group also takes the odd entry's), then all of its
+// values, so that the columns are decoded and the gathers issued while the
+// values are still on their way (loads complete in the order they are
+// issued).  Where HBM latency is what a row waits for (a matrix far larger
+// than the caches) this hides more of it; where the matrix and x come from
+// the caches, the interleaved order of sell_row was faster on this GPU, so
+// the autotuner times both.  The same terms are added in the same order.
+template <class VT, int U, bool NT = true, bool DIFF = false, int CF = CF_I32>
+__device__ __forceinline__ VT sell_row_cfirst(const SellView<VT>& A, int64_t base, int width, int lane,
+                                       const VT* __restrict__ x, VT xi = 0, int32_t row = 0,
+                                       const int32_t* tab = nullptr) {
+    typedef RawCol<CF> RC;
+    typedef typename RC::pair RP;
+    typedef typename Pair<VT>::type V2;
+    const int np = width >> 1;
+    const bool odd = width & 1;
+    const int64_t ko = base + static_cast<int64_t>(np) * (2 * SELL_C) + lane;  // the odd entry
+    auto gather = [&](int32_t c) {
+        const VT xg = x[static_cast<uint32_t>(c)];
+        return DIFF ? xg - xi : xg;
+    };
+    if (np == 0) {
+        if (!odd) return VT(0);
+        const int32_t oc = static_cast<int32_t>(stream_load<typename RC::one, NT>(raw_cols<CF>(A) + ko));
+        const VT vo = stream_load<VT, NT>(A.val + ko);
+        return vo * gather(one_col<CF>(oc, row, tab));
+    }
+    const RP* rp = reinterpret_cast<const RP*>(raw_cols<CF>(A) + base) + lane;
+    const V2* vp = reinterpret_cast<const V2*>(A.val + base) + lane;
+    // One group of up to U pairs: its columns first, then its values (loads
+    // complete in the order they are issued, so the columns are decoded while
+    // the values are still on their way), then the gathers.  Every load is
+    // issued whatever the width, so that the waits count them exactly: a pair
+    // past the last one is loaded from the group's first pair and not added,
+    // and in the first group the odd entry of an even row is loaded from the
+    // row's first entry and not used.  The first group also takes the odd
+    // entry, so a row of at most 2U + 1 entries costs one round trip for its
+    // columns and one for its values and x.
+    VT acc = 0, vo = 0, xo = 0;
+    auto group = [&](int t, auto first) {
+        typename RC::bits rc[U];
+        int32_t c0[U], c1[U];
+        V2 v[U];
+        VT x0[U], x1[U];
+        const int64_t ke = odd ? ko : base + lane;
+        int32_t oc = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) rc[u] = stream_load<RP, NT>(rp + (t + u < np ? u : 0) * SELL_C);
+        if constexpr (first()) oc = static_cast<int32_t>(stream_load<typename RC::one, NT>(raw_cols<CF>(A) + ke));
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = stream_load<V2, NT>(vp + (t + u < np ? u : 0) * SELL_C);
+        if constexpr (first()) vo = stream_load<VT, NT>(A.val + ke);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c0[u] = RC::lo(rc[u], row, tab);
+            c1[u] = RC::hi(rc[u], row, tab);
+        }
+        // decoded whether or not the row has an odd entry (an even row's stand-in is
+        // another row's column, so the row itself is gathered instead)
+        const int32_t cod = one_col<CF>(oc, row, tab);
+        const int32_t co = odd ? cod : row;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x0[u] = gather(c0[u]);
+            x1[u] = gather(c1[u]);
+        }
+        if constexpr (first()) xo = gather(co);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t + u < np) {
+                acc += v[u].x * x0[u];
+                acc += v[u].y * x1[u];
+            }
+        rp += U * SELL_C;
+        vp += U * SELL_C;
+    };
+    group(0, std::true_type{});
+#pragma unroll 1
+    for (int t = U; t < np; t += U) group(t, std::false_type{});
+    if (odd) acc += vo * xo;
+    return acc;
+}
+
 // Stage the offset table of a CF_U8 product in LDS (every thread of the block
 // calls this before its first row).
 __device__ __forceinline__ void stage_offsets(const int32_t* __restrict__ otab, int ntab, int32_t* tab) {
@@ -184,7 +320,9 @@ enum { MODE_PLAIN = 0, MODE_DOT = 1, MODE_RESID = 2, MODE_DOTB = 3 };
 // is set returns at once: inside a batch of PCG iterations that has
 // converged, the remaining launches do nothing.  DIFF: the difference form
 // (A.excess set).  CF: the column format (CF_I16: A.dcol set, CF_U8: A.tcol
-// and A.otab set).
+// and A.otab set).  ORD: the order of a row's loads (0 sell_row, 1
+// sell_row_cfirst).  Up to 3 pairs in flight the kernel is held to 64
+// registers, 8 waves per SIMD.
 //
 // Order of the slices: XCD x (workgroups are dispatched round-robin, so
 // blockIdx.x & 7 names it) owns the contiguous x-th eighth of the slices,
@@ -225,21 +363,26 @@ __device__ __forceinline__ uint32_t banded_slice(uint32_t l, uint32_t n, uint32_
 template <class VT, int MODE, bool DIFF>
 __device__ __forceinline__ void sell_finish(const SellView<VT>& A, int64_t row, VT acc, VT xi, const VT* __restrict__ x,
                                             VT* __restrict__ y, const VT* __restrict__ b, VT& d) {
-    if (row >= A.V) return;
-    if (DIFF) acc += A.excess[row] * xi;
+    // a lane past the last row reads the last row's data and keeps nothing (its loads are
+    // unconditional: a load that only some waves issue makes later waits count it)
+    const bool in = row < A.V;
+    const int64_t rc = in ? row : A.V - 1;
+    if (DIFF) acc += A.excess[rc] * xi;
+    VT out = acc, t = 0;
     if (MODE == MODE_RESID) {
-        const VT ri = b[row] - acc;
-        y[row] = ri;
-        d += ri * ri;
-    } else {
-        y[row] = acc;
-        if (MODE == MODE_DOT) d += x[row] * acc;
-        if (MODE == MODE_DOTB) d += b[row] * acc;
+        out = b[rc] - acc;
+        t = out * out;
+    } else if (MODE == MODE_DOT) {
+        t = xi * acc;
+    } else if (MODE == MODE_DOTB) {
+        t = b[rc] * acc;
     }
+    d += in ? t : VT(0);
+    if (in) y[row] = out;
 }
 
-template <class VT, int MODE, int U, bool NT, bool DIFF = false, int CF = CF_I32>
-__global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
+template <class VT, int MODE, int U, bool NT, bool DIFF = false, int CF = CF_I32, int ORD = 0>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(U <= 3 ? 8 : 6))) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
                                                 const VT* __restrict__ b, double* __restrict__ partials,
                                                 const int32_t* __restrict__ done) {
     __shared__ double lds[BLOCK / 64 + 1];
@@ -247,7 +390,8 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
     if (done != nullptr && *done) return;
     if (CF == CF_U8) stage_offsets(A.otab, A.ntab, tab);
     constexpr int WAVES = BLOCK / 64;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index, uniform across the wavefront (scalar registers for the slice bookkeeping)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t xcd = blockIdx.x & 7;
     const int64_t s0 = A.nslices * xcd / 8;
     const uint32_t n = static_cast<uint32_t>(A.nslices * (xcd + 1) / 8 - s0);
@@ -262,8 +406,11 @@ __global__ __launch_bounds__(BLOCK) void k_sell(SellView<VT> A, const VT* __rest
         const int64_t base = A.ptr[s];
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;
-        const VT xi = DIFF && row < A.V ? x[row] : VT(0);
-        const VT acc = sell_row<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab);
+        // the row's own x (DIFF: for the differences, DOT: for x.y), loaded with the matrix
+        const VT xr = x[row < A.V ? row : A.V - 1];
+        const VT xi = (DIFF || MODE == MODE_DOT) && row < A.V ? xr : VT(0);
+        const VT acc = ORD == 1 ? sell_row_cfirst<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab)
+                                : sell_row<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab);
         sell_finish<VT, MODE, DIFF>(A, row, acc, xi, x, y, b, d);
     }
     if (MODE == MODE_PLAIN) return;

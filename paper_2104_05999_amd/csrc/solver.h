@@ -66,14 +66,15 @@ __device__ __forceinline__ VT csr_row(const CsrView<VT>& A, int64_t row, const V
 
 // ---------------------------------------------------------------- host side
 struct GraphKey {
-    int prec, precond, chunk, unroll, nt, cf;
+    int prec, precond, chunk, unroll, nt, cf, order;
     bool operator<(const GraphKey& o) const {
         if (prec != o.prec) return prec < o.prec;
         if (precond != o.precond) return precond < o.precond;
         if (chunk != o.chunk) return chunk < o.chunk;
         if (unroll != o.unroll) return unroll < o.unroll;
         if (nt != o.nt) return nt < o.nt;
-        return cf < o.cf;
+        if (cf != o.cf) return cf < o.cf;
+        return order < o.order;
     }
 };
 
@@ -87,8 +88,9 @@ struct SolveCache {
     int unroll[2] = {4, 4};
     int nt[2] = {1, 0};            // non-temporal matrix loads
     int cf[2] = {CF_U8, CF_U8};    // column format, the most compact a matrix has up to this
+    int order[2] = {0, 0};         // load order of the iteration's product: 0 interleaved, 1 columns first
     bool tuned[2] = {false, false};
-    bool pinned_variant = false;  // unroll / non-temporal loads set through the environment
+    bool pinned_variant = false;  // unroll / non-temporal loads / load order set through the environment
     int force_cols = 0;           // 32, 16 or 8: this column format where a matrix has it (environment)
     int split = -1;               // Jacobi in split form: 1 always, 0 never, -1 by size (environment)
     bool vec_pairs = true;        // FP32 vector kernels on float2 elements where the vectors allow (environment)

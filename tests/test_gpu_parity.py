@@ -624,14 +624,16 @@ def test_nonfinite_conductivity_breaks_down(ctx, dev):
         m.close()
 
 
+@pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("cols", [8, 16, 32])
 @pytest.mark.parametrize("unroll,nt", [(2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1)])
-def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt, cols):
-    """The autotuner's variants (pairs in flight, non-temporal loads) sum every row in the same
-    order and fold the partials in the same order, and the one-byte offset indices and 16-bit
-    offsets name the same columns as the int32 columns: pinned through the environment, each
-    gives the tuned solve's bits, on a vertex system and on a tet system, in FP64 and with FP32
-    inner solves."""
+def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt, cols, order):
+    """The autotuner's variants (pairs in flight, non-temporal loads, a row's loads interleaved or
+    columns first) sum every row in the same order and fold the partials in the same order, and
+    the one-byte offset indices and 16-bit offsets name the same columns as the int32 columns:
+    pinned through the environment, each gives the tuned solve's bits, on a vertex system and on
+    a tet system, in FP64 and with FP32 inner solves (most vertex rows store 7 entries: with 2, 3
+    and 4 pairs in flight such a row needs more pairs than one group holds, as many, and fewer)."""
     import os
     import paper_2104_05999_amd as dec
     s = _system(12, n_cracks=20)
@@ -647,14 +649,15 @@ def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt, cols):
     ref_d = d.solve(tol=1e-11)[0]
     d.close()
     os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"] = str(unroll), str(nt)
-    os.environ["DEC_SELL_COLS"] = str(cols)
+    os.environ["DEC_SELL_COLS"], os.environ["DEC_SELL_ORDER"] = str(cols), str(order)
     try:
         m2, _, _, _, _ = _gpu(ctx, s, dev)
         for p, r in zip((0, 1), ref):
             T, st, rc = m2.solve(tol=1e-11, precision=p)
             assert rc == 0 and torch.equal(T, r), p
             # the stats report the variant the solve ran (this lattice holds every encoding)
-            assert (st["spmv_unroll"], st["spmv_nontemporal"], st["spmv_col_bytes"]) == (unroll, nt, cols // 8), p
+            assert (st["spmv_unroll"], st["spmv_nontemporal"], st["spmv_col_bytes"], st["spmv_order"]) == (
+                unroll, nt, cols // 8, order), p
         mt = ctx.mesh(t(xyz), t(tets))
         d = mt.dual(t(bt), t(bv), t(side), kap, t(W.penny_cracks(5, 9, 0.1, 0.3)))
         mt.close()
@@ -662,6 +665,7 @@ def test_every_sell_variant_gives_the_same_bits(ctx, dev, unroll, nt, cols):
         d.close()
     finally:
         del os.environ["DEC_SELL_UNROLL"], os.environ["DEC_SELL_NT"], os.environ["DEC_SELL_COLS"]
+        del os.environ["DEC_SELL_ORDER"]
 
 
 @pytest.mark.parametrize("band", ["7,3", "5,5", "1,1", "13,64", "40,16"])
