@@ -558,6 +558,9 @@ typedef struct dec_server_counters {
     double host_ms[4];        /* host wall time of dec_server_step's phases: building and launching
                                  the batch, admissions, waiting for the batch, refinement steps       */
     int64_t steps;            /* dec_server_step calls                                                */
+    int32_t order[2];         /* the batched product's load order for FP64, then FP32: 1 when a row's
+                                 column loads go out ahead of its value loads, 0 interleaved (timed
+                                 with the variant above)                                            */
 } dec_server_counters;
 /* Fill *out (host).  DEC_EINVAL when s or out is NULL. */
 int dec_server_stats(const dec_server* s, dec_server_counters* out);

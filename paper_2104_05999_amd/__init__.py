@@ -449,13 +449,13 @@ class Server:
 
     def stats(self):
         """Batched inner iterations so far: replay time (ms), algorithmic bytes, system-iterations, and the
-        batched product's variant per precision (entry pairs in flight, non-temporal loads)."""
+        batched product's variant per precision (entry pairs in flight, non-temporal loads, columns first)."""
         c = _lib.ServerCounters()
         self.ctx.check(self.lib.dec_server_stats(self.handle, ctypes.byref(c)), "dec_server_stats")
-        v, h = list(c.variant), list(c.host_ms)
+        v, h, o = list(c.variant), list(c.host_ms), list(c.order)
         return {"batch_ms": c.batch_ms, "batch_bytes": c.batch_bytes, "batch_iterations": c.batch_iterations,
-                "variant_fp64": {"unroll": v[0], "nontemporal": v[1]},
-                "variant_fp32": {"unroll": v[2], "nontemporal": v[3]},
+                "variant_fp64": {"unroll": v[0], "nontemporal": v[1], "columns_first": o[0]},
+                "variant_fp32": {"unroll": v[2], "nontemporal": v[3], "columns_first": o[1]},
                 "host_ms": {"launch": h[0], "admit": h[1], "wait": h[2], "refine": h[3]}, "steps": c.steps}
 
     def close(self):

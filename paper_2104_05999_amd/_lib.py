@@ -79,6 +79,7 @@ class ServerCounters(ctypes.Structure):
         ("variant", ctypes.c_int32 * 4),
         ("host_ms", ctypes.c_double * 4),
         ("steps", ctypes.c_int64),
+        ("order", ctypes.c_int32 * 2),
     ]
 
 

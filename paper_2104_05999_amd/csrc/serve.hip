@@ -122,7 +122,7 @@ __device__ __forceinline__ SellView<VT> slot_view(const BSlot& S, const VT* val)
 
 // y = A x over the rows of one work item (the slices [s0, s1)), in column
 // format CF; the sum of w[row] * y[row] (w = x for DOT, b for RESID's r.r).
-template <class VT, int U, bool NT, int CF, bool RESID>
+template <class VT, int U, bool NT, int CF, bool RESID, int ORD = 0>
 __device__ __forceinline__ VT item_product(const SellView<VT>& A, int64_t s0, int64_t s1, const VT* __restrict__ x,
                                            VT* __restrict__ y, const VT* __restrict__ b, const int32_t* tab) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -132,7 +132,8 @@ __device__ __forceinline__ VT item_product(const SellView<VT>& A, int64_t s0, in
         const int width = static_cast<int>((A.ptr[s + 1] - base) / SELL_C);
         const int64_t row = s * SELL_C + lane;
         const int32_t rowc = static_cast<int32_t>(CF == CF_U8 && row >= A.V ? A.V - 1 : row);
-        const VT acc = sell_row<VT, U, NT, false, CF>(A, base, width, lane, x, VT(0), rowc, tab);
+        const VT acc = ORD == 1 ? sell_row_cfirst<VT, U, NT, false, CF>(A, base, width, lane, x, VT(0), rowc, tab)
+                                : sell_row<VT, U, NT, false, CF>(A, base, width, lane, x, VT(0), rowc, tab);
         if (row < A.V) {
             if (RESID) {
                 const VT ri = b[row] - acc;
@@ -150,19 +151,19 @@ __device__ __forceinline__ VT item_product(const SellView<VT>& A, int64_t s0, in
 // item_product in the format the system keeps; a one-byte table is first
 // staged in LDS (the block's threads all take this item; the barrier of the
 // previous item's block sum has ended that item's reads of the table).
-template <class VT, int U, bool NT, bool RESID>
+template <class VT, int U, bool NT, bool RESID, int ORD = 0>
 __device__ __forceinline__ VT item_product_any(const BSlot& S, const SellView<VT>& A, int64_t s0, int64_t s1,
                                                const VT* __restrict__ x, VT* __restrict__ y, const VT* __restrict__ b,
                                                int32_t* tab) {
     if (A.tcol) {
         stage_offsets(A.otab, A.ntab, tab);
-        return item_product<VT, U, NT, CF_U8, RESID>(A, s0, s1, x, y, b, tab);
+        return item_product<VT, U, NT, CF_U8, RESID, ORD>(A, s0, s1, x, y, b, tab);
     }
-    if (A.dcol) return item_product<VT, U, NT, CF_I16, RESID>(A, s0, s1, x, y, b, tab);
-    return item_product<VT, U, NT, CF_I32, RESID>(A, s0, s1, x, y, b, tab);
+    if (A.dcol) return item_product<VT, U, NT, CF_I16, RESID, ORD>(A, s0, s1, x, y, b, tab);
+    return item_product<VT, U, NT, CF_I32, RESID, ORD>(A, s0, s1, x, y, b, tab);
 }
 
-template <class VT, int U, bool NT>
+template <class VT, int U, bool NT, int ORD>
 __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ slots, const BItem* __restrict__ items,
                                                      const int32_t* __restrict__ n_items, int par) {
     __shared__ double lds[BLOCK / 64 + 1];
@@ -175,7 +176,8 @@ __global__ __launch_bounds__(BLOCK) void bk_spmv_dot(const BSlot* __restrict__ s
         const SellView<VT> A = slot_view<VT>(S, SlotVec<VT>::val(S));
         const int64_t s0 = (int64_t)item.chunk * CHUNK_SLICES;
         const int64_t s1 = s0 + CHUNK_SLICES < S.nslices ? s0 + CHUNK_SLICES : S.nslices;
-        const VT d = item_product_any<VT, U, NT, false>(S, A, s0, s1, SlotVec<VT>::p(S), SlotVec<VT>::q(S), nullptr, tab);
+        const VT d =
+            item_product_any<VT, U, NT, false, ORD>(S, A, s0, s1, SlotVec<VT>::p(S), SlotVec<VT>::q(S), nullptr, tab);
         const double bs = block_sum(static_cast<double>(d), lds);
         if (threadIdx.x == 0) S.part[Q_PQ * S.nchunks + item.chunk] = bs;
     }
@@ -534,6 +536,7 @@ struct dec_server {
     // batched SpMV variant per precision ([0] FP64, [1] FP32), tuned on the live batch
     int unroll[2] = {4, 4};
     int nt[2] = {1, 0};
+    int order[2] = {0, 0};
     bool tuned[2] = {false, false};
     int tuned_items[2] = {0, 0};  // work items of the batch the variant was timed on
     int tunings[2] = {0, 0};
@@ -710,11 +713,12 @@ void upload_slots(dec_server* s) {
     HIP_CHECK(hipMemcpyAsync(s->d_slots.p, s->h_slots, ns * sizeof(BSlot), hipMemcpyHostToDevice, s->solve_stream));
 }
 
-template <class VT>
-void launch_batched_spmv(dec_server* s, int unroll, int nt, const BItem* items, const int32_t* n_items, int par) {
+template <class VT, int ORD>
+void launch_batched_spmv_o(dec_server* s, int unroll, int nt, const BItem* items, const int32_t* n_items, int par) {
     const dim3 g(s->G), b(BLOCK);
     const BSlot* sl = s->d_slots.p;
-#define BK_SPMV(U, NT) hipLaunchKernelGGL((bk_spmv_dot<VT, U, NT>), g, b, 0, s->solve_stream, sl, items, n_items, par)
+#define BK_SPMV(U, NT) \
+    hipLaunchKernelGGL((bk_spmv_dot<VT, U, NT, ORD>), g, b, 0, s->solve_stream, sl, items, n_items, par)
     if (nt) {
         if (unroll == 2) BK_SPMV(2, true);
         else if (unroll == 3) BK_SPMV(3, true);
@@ -727,17 +731,28 @@ void launch_batched_spmv(dec_server* s, int unroll, int nt, const BItem* items, 
 #undef BK_SPMV
 }
 
+// ord: the order of a row's loads (0 interleaved, 1 columns first)
+template <class VT>
+void launch_batched_spmv(dec_server* s, int unroll, int nt, int ord, const BItem* items, const int32_t* n_items,
+                         int par) {
+    if (ord == 1)
+        launch_batched_spmv_o<VT, 1>(s, unroll, nt, items, n_items, par);
+    else
+        launch_batched_spmv_o<VT, 0>(s, unroll, nt, items, n_items, par);
+}
+
 template <class VT>
 void enqueue_batched_iteration(dec_server* s, const BItem* items, const int32_t* n_items, int par) {
     const dim3 g(s->G), b(BLOCK);
     const int pi = sizeof(VT) == 8 ? 0 : 1;
-    launch_batched_spmv<VT>(s, s->unroll[pi], s->nt[pi], items, n_items, par);
+    launch_batched_spmv<VT>(s, s->unroll[pi], s->nt[pi], s->order[pi], items, n_items, par);
     hipLaunchKernelGGL(bk_update<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
     hipLaunchKernelGGL(bk_close<VT>, g, b, 0, s->solve_stream, s->d_slots.p, items, n_items, par);
 }
 
 // Pick the batched SpMV variant (2, 3 or 4 entry pairs in flight, non-temporal
-// loads on or off) for a precision by timing it on the batch about to run:
+// loads on or off, a row's loads interleaved or columns first) for a
+// precision by timing it on the batch about to run:
 // three rounds of two launches per variant, each variant's best round.  The
 // extra launches recompute q = A p and the p.q partials of the same p, which
 // the batch's first iteration computes again, and every variant sums each row
@@ -749,14 +764,21 @@ constexpr int MAX_TUNINGS = 5;
 template <class VT>
 void tune_batched_spmv(dec_server* s, const BItem* items, const int32_t* n_items) {
     const int pi = sizeof(VT) == 8 ? 0 : 1;
-    const int cand[6][2] = {{4, 1}, {4, 0}, {3, 1}, {3, 0}, {2, 1}, {2, 0}};
-    float best[6];
-    for (int k = 0; k < 6; ++k) best[k] = 1e30f;
+    constexpr int NC = 12;
+    int cand[NC][3];
+    for (int k = 0; k < NC; ++k) {
+        cand[k][0] = 4 - k / 4;     // pairs in flight
+        cand[k][1] = 1 - k / 2 % 2;  // non-temporal loads
+        cand[k][2] = k % 2;          // load order
+    }
+    float best[NC];
+    for (int k = 0; k < NC; ++k) best[k] = 1e30f;
     for (int round = 0; round < 3; ++round)
-        for (int k = 0; k < 6; ++k) {
-            launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], items, n_items, 0);
+        for (int k = 0; k < NC; ++k) {
+            launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], cand[k][2], items, n_items, 0);
             HIP_CHECK(hipEventRecord(s->ev_b0, s->solve_stream));
-            for (int r = 0; r < 2; ++r) launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], items, n_items, 0);
+            for (int r = 0; r < 2; ++r)
+                launch_batched_spmv<VT>(s, cand[k][0], cand[k][1], cand[k][2], items, n_items, 0);
             HIP_CHECK(hipEventRecord(s->ev_b1, s->solve_stream));
             HIP_CHECK(hipEventSynchronize(s->ev_b1));
             float ms = 0.0f;
@@ -764,10 +786,11 @@ void tune_batched_spmv(dec_server* s, const BItem* items, const int32_t* n_items
             if (ms < best[k]) best[k] = ms;
         }
     int pick = 0;
-    for (int k = 1; k < 6; ++k)
+    for (int k = 1; k < NC; ++k)
         if (best[k] < best[pick]) pick = k;
     s->unroll[pi] = cand[pick][0];
     s->nt[pi] = cand[pick][1];
+    s->order[pi] = cand[pick][2];
     s->tuned[pi] = true;
 }
 
@@ -1236,6 +1259,7 @@ int dec_server_stats(const dec_server* s, dec_server_counters* out) {
     for (int k = 0; k < 2; ++k) {
         out->variant[2 * k] = s->tuned[k] ? s->unroll[k] : 0;
         out->variant[2 * k + 1] = s->tuned[k] ? s->nt[k] : 0;
+        out->order[k] = s->tuned[k] ? s->order[k] : 0;
     }
     for (int k = 0; k < 4; ++k) out->host_ms[k] = s->host_ms[k];
     out->steps = s->steps;

@@ -290,6 +290,6 @@ def test_server_batch_counters(ctx, dev, precision):
     assert 14 * sv * rows * 0.5 < per_it < (20 * sv + 15 * (sv + 4)) * rows * 2
     assert st["batch_ms"] > 0
     ran, idle = ("variant_fp32", "variant_fp64") if precision == 1 else ("variant_fp64", "variant_fp32")
-    assert st[ran]["unroll"] in (2, 3, 4) and st[ran]["nontemporal"] in (0, 1)
-    assert st[idle] == {"unroll": 0, "nontemporal": 0}
+    assert st[ran]["unroll"] in (2, 3, 4) and st[ran]["nontemporal"] in (0, 1) and st[ran]["columns_first"] in (0, 1)
+    assert st[idle] == {"unroll": 0, "nontemporal": 0, "columns_first": 0}
     assert st["steps"] > 0 and all(v >= 0 for v in st["host_ms"].values())
