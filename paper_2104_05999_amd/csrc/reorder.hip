@@ -8,16 +8,14 @@
 // fastest, ties by original index.  Tets are then ordered by their smallest
 // new vertex number, ties by original index, and keep their vertex order.
 // Both orders come from a stable radix sort of (key, original index) pairs
-// with the indices in ascending order, so the result is unique, and its cost
-// is linear however unevenly the points fill the cells.
+// with the indices in ascending order (sort_indices, written here), so the
+// result is unique, and its cost is linear however unevenly the points fill
+// the cells.
 // The Z (Morton) order is offered beside it: cells by the interleaved bits of
 // (x cell, y cell, z cell) (z in the lowest bit), which keeps neighbours in
 // all three directions close in memory.
 #include <cmath>
 #include <cstring>
-
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "common.h"
 
@@ -130,22 +128,118 @@ __global__ void k_apply_tperm(int64_t T, const int32_t* __restrict__ tperm, cons
     }
 }
 
-// perm = the indices 0..n-1 ordered by key, ties in index order (a stable
-// radix sort over the low `bits` bits of the keys); keys are left sorted.
+// ---------------------------------------------------------------- stable radix sort
+// A least-significant-digit radix sort of (key, index) pairs, 8 bits a pass.
+// Block b owns the contiguous tile [b * tile, (b + 1) * tile) of the input.
+// A pass counts each block's digits (k_radix_count, digit-major: count[d * G
+// + b]), scans the counts (so block b's run of digit d starts after every
+// element of a smaller digit and after blocks 0..b-1's elements of digit d),
+// and scatters (k_radix_scatter): the block walks its tile in order, one
+// element per thread, BLOCK elements at a time; an element's place is its
+// run's start, plus the block's elements of its digit in earlier rounds,
+// plus those before it in this round (earlier waves, then earlier lanes of
+// its own wave, found with ballots on the digit's bits).  Every element
+// keeps its order among equal digits, so after the last pass the pairs are
+// ordered by key with ties in index order.
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+static_assert(BLOCK == RADIX, "one thread per digit in the block-wide steps");
+
+__global__ void k_iota(int64_t n, int32_t* __restrict__ out) {
+    GRID_STRIDE_LOOP(i, n) out[i] = static_cast<int32_t>(i);
+}
+
+template <class K>
+__global__ void k_radix_count(const K* __restrict__ key, int64_t n, int shift, int64_t tile,
+                              int32_t* __restrict__ count) {
+    __shared__ int32_t h[RADIX];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * tile;
+    const int64_t t1 = t0 + tile < n ? t0 + tile : n;
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += BLOCK)
+        atomicAdd(&h[static_cast<int>((key[i] >> shift) & (RADIX - 1))], 1);
+    __syncthreads();
+    count[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ void k_radix_scatter(const K* __restrict__ key, const int32_t* __restrict__ val, int64_t n, int shift,
+                                int64_t tile, const int64_t* __restrict__ start, K* __restrict__ key_out,
+                                int32_t* __restrict__ val_out) {
+    constexpr int WAVES = BLOCK / 64;
+    __shared__ int64_t run[RADIX];            // where the block's next element of each digit goes
+    __shared__ int32_t wave_n[WAVES][RADIX];  // this round's elements of each digit per wave
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    run[threadIdx.x] = start[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    const int64_t t0 = (int64_t)blockIdx.x * tile;
+    const int64_t t1 = t0 + tile < n ? t0 + tile : n;
+    const uint64_t lower = (uint64_t(1) << lane) - 1;
+    for (int64_t r0 = t0; r0 < t1; r0 += BLOCK) {
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) wave_n[k][threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t i = r0 + threadIdx.x;
+        const bool in = i < t1;
+        const K kv = in ? key[i] : K(0);
+        const int d = static_cast<int>((kv >> shift) & (RADIX - 1));
+        // lanes of this wave holding the same digit
+        uint64_t same = __ballot(in);
+#pragma unroll
+        for (int bit = 0; bit < RADIX_BITS; ++bit) {
+            const uint64_t ones = __ballot((d >> bit) & 1);
+            same &= (d >> bit) & 1 ? ones : ~ones;
+        }
+        const int before = __popcll(same & lower);
+        if (in && before == 0) wave_n[w][d] = __popcll(same);
+        __syncthreads();
+        if (in) {
+            int64_t pos = run[d] + before;
+            for (int k = 0; k < w; ++k) pos += wave_n[k][d];
+            key_out[pos] = kv;
+            val_out[pos] = val[i];
+        }
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int k = 0; k < WAVES; ++k) add += wave_n[k][threadIdx.x];
+        run[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+// perm = the indices 0..n-1 ordered by key, ties in index order, over the
+// low `bits` bits of the keys (key is overwritten).
 template <class K>
 void sort_indices(dec_ctx* ctx, DBuf<K>& key, int64_t n, int bits, DBuf<int32_t>& perm) {
-    DBuf<K> key_out;
-    key_out.alloc(ctx, n);
+    hipStream_t s = ctx->stream;
     perm.alloc(ctx, n);
-    const rocprim::counting_iterator<int32_t> idx(0);
-    size_t bytes = 0;
-    HIP_CHECK(rocprim::radix_sort_pairs(nullptr, bytes, key.p, key_out.p, idx, perm.p, static_cast<size_t>(n), 0,
-                                        static_cast<unsigned>(bits), ctx->stream));
-    DBuf<uint8_t> tmp;
-    tmp.alloc(ctx, bytes ? bytes : 1);
-    HIP_CHECK(rocprim::radix_sort_pairs(tmp.p, bytes, key.p, key_out.p, idx, perm.p, static_cast<size_t>(n), 0,
-                                        static_cast<unsigned>(bits), ctx->stream));
-    ctx->sync();  // tmp and key_out are released on return
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(BLOCK), 0, s, n, perm.p);
+    DBuf<K> key2;
+    DBuf<int32_t> val2;
+    key2.alloc(ctx, n);
+    val2.alloc(ctx, n);
+    // tiles of at least 16 rounds, so that a block's fixed costs are spread
+    const int64_t per_block = 16 * (int64_t)BLOCK;
+    int64_t G = (n + per_block - 1) / per_block;
+    const int64_t cap = 8 * (int64_t)ctx->num_cus;
+    if (G > cap) G = cap;
+    if (G < 1) G = 1;
+    const int64_t tile = ((n + G - 1) / G + BLOCK - 1) / BLOCK * BLOCK;
+    DBuf<int32_t> count;
+    DBuf<int64_t> start;
+    count.alloc(ctx, RADIX * G);
+    start.alloc(ctx, RADIX * G + 1);
+    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
+        hipLaunchKernelGGL(k_radix_count<K>, dim3(G), dim3(BLOCK), 0, s, key.p, n, shift, tile, count.p);
+        scan_exclusive_i32_to_i64(ctx, count.p, start.p, RADIX * G, false);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(G), dim3(BLOCK), 0, s, key.p, perm.p, n, shift, tile, start.p,
+                           key2.p, val2.p);
+        HIP_CHECK(hipGetLastError());
+        key.swap(key2);
+        perm.swap(val2);
+    }
+    ctx->sync();  // the second buffers are released on return
 }
 
 int bits_for(uint64_t n) {  // bits of the largest key below n

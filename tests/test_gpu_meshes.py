@@ -60,6 +60,18 @@ def test_reorder_matches_oracle(ctx, dev, name, order):
     assert np.array_equal(xg, xo) and np.array_equal(tg, to)
 
 
+@pytest.mark.parametrize("order", ["lexicographic", "morton"])
+def test_reorder_large_matches_oracle(ctx, dev, order):
+    """The hand-written radix sort behind the numbering at a size where its blocks take long tiles
+    (a shuffled Kuhn 112^3: 1.44M vertices, 8.43M tets, more tiles than the sort's block cap):
+    vertex and tet permutations equal the oracle's bit for bit."""
+    xyz, tets = _shuffled_kuhn(112, 5)
+    xo, to, vp, tp = O.spatial_order(xyz, tets, order=order)
+    xg, tg, vg, tpg = (a.cpu().numpy() for a in ctx.reorder(_t(xyz, dev), _t(tets, dev), order))
+    assert np.array_equal(vg, vp) and np.array_equal(tpg, tp)
+    assert np.array_equal(tg, to)
+
+
 def test_reorder_rejects_bad_index(ctx, dev):
     import paper_2104_05999_amd as dec
     xyz, tets = W.kuhn_cube(2)
