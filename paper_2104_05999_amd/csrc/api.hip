@@ -1,5 +1,6 @@
 // Context management, allocation, error reporting and the scan primitive.
 #include <cstdio>
+#include <cstring>
 
 #include "common.h"
 
@@ -58,8 +59,16 @@ namespace {
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 
-__global__ void k_scan_tile_sums(const int32_t* __restrict__ in, int64_t n, int64_t* __restrict__ bsum) {
+// Up to three scans of the same length in one set of launches (blockIdx.y
+// picks the array).
+struct ScanBatch {
+    const int32_t* in[3];
+    int64_t* out[3];
+};
+
+__global__ void k_scan_tile_sums(ScanBatch sb, int64_t n, int64_t* __restrict__ bsum) {
     __shared__ int64_t lds[BLOCK / 64];
+    const int32_t* __restrict__ in = sb.in[blockIdx.y];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int64_t s = 0;
 #pragma unroll
@@ -68,13 +77,14 @@ __global__ void k_scan_tile_sums(const int32_t* __restrict__ in, int64_t n, int6
         if (i < n) s += in[i];
     }
     s = block_sum(s, lds);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s;
+    if (threadIdx.x == 0) bsum[blockIdx.y * static_cast<int64_t>(gridDim.x) + blockIdx.x] = s;
 }
 
-// One block: exclusive scan of nb tile sums, in place.
-__global__ void k_scan_tile_offsets(int64_t* __restrict__ bsum, int64_t nb) {
+// One block per scan: exclusive scan of its nb tile sums, in place.
+__global__ void k_scan_tile_offsets(int64_t* __restrict__ bsum_all, int64_t nb) {
     __shared__ int64_t buf[1024];
     __shared__ int64_t carry;
+    int64_t* __restrict__ bsum = bsum_all + blockIdx.y * nb;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t start = 0; start < nb; start += 1024) {
@@ -96,9 +106,11 @@ __global__ void k_scan_tile_offsets(int64_t* __restrict__ bsum, int64_t nb) {
     }
 }
 
-__global__ void k_scan_tile_apply(const int32_t* __restrict__ in, int64_t n, const int64_t* __restrict__ boff,
-                                  int64_t* __restrict__ out) {
+__global__ void k_scan_tile_apply(ScanBatch sb, int64_t n, const int64_t* __restrict__ boff_all) {
     __shared__ int64_t buf[BLOCK];
+    const int32_t* __restrict__ in = sb.in[blockIdx.y];
+    int64_t* __restrict__ out = sb.out[blockIdx.y];
+    const int64_t* __restrict__ boff = boff_all + blockIdx.y * static_cast<int64_t>(gridDim.x);
     const int64_t base = static_cast<int64_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int64_t loc[SCAN_ITEMS];
     int64_t s = 0;
@@ -125,30 +137,53 @@ __global__ void k_scan_tile_apply(const int32_t* __restrict__ in, int64_t n, con
     if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
 }
 
+// the scans' totals side by side, for one read-back
+__global__ void k_scan_totals(ScanBatch sb, int m, int64_t n, int64_t* __restrict__ tot) {
+    if (threadIdx.x < static_cast<unsigned>(m)) tot[threadIdx.x] = sb.out[threadIdx.x][n];
+}
+
 __global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out, int64_t n) {
     GRID_STRIDE_LOOP(i, n) out[i] = static_cast<int32_t>(in[i]);
 }
 }  // namespace
 
-int64_t scan_exclusive_i32_to_i64(dec_ctx* ctx, const int32_t* in, int64_t* out, int64_t n, bool want_total) {
+// m (1 to 3) scans of arrays of the same length in one set of launches;
+// totals (when given) receives the m totals (one synchronisation).
+void scan_exclusive_multi(dec_ctx* ctx, int m, const int32_t* const* in, int64_t* const* out, int64_t n,
+                          int64_t* totals) {
+    DEC_REQUIRE(m >= 1 && m <= 3, DEC_EINVAL, "internal: 1 to 3 scans at a time");
     if (n == 0) {
-        HIP_CHECK(hipMemsetAsync(out, 0, sizeof(int64_t), ctx->stream));
-        return 0;
+        for (int k = 0; k < m; ++k) HIP_CHECK(hipMemsetAsync(out[k], 0, sizeof(int64_t), ctx->stream));
+        if (totals)
+            for (int k = 0; k < m; ++k) totals[k] = 0;
+        return;
+    }
+    ScanBatch sb{};
+    for (int k = 0; k < m; ++k) {
+        sb.in[k] = in[k];
+        sb.out[k] = out[k];
     }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     DBuf<int64_t> bsum;
-    bsum.alloc(ctx, nb);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(nb), dim3(BLOCK), 0, ctx->stream, in, n, bsum.p);
-    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(1024), 0, ctx->stream, bsum.p, nb);
-    hipLaunchKernelGGL(k_scan_tile_apply, dim3(nb), dim3(BLOCK), 0, ctx->stream, in, n, bsum.p, out);
+    bsum.alloc(ctx, m * nb + 3);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(nb, m), dim3(BLOCK), 0, ctx->stream, sb, n, bsum.p);
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1, m), dim3(1024), 0, ctx->stream, bsum.p, nb);
+    hipLaunchKernelGGL(k_scan_tile_apply, dim3(nb, m), dim3(BLOCK), 0, ctx->stream, sb, n, bsum.p);
     HIP_CHECK(hipGetLastError());
-    int64_t total = -1;
-    if (want_total) {
-        total = *static_cast<int64_t*>(ctx->readback(out + n, sizeof(int64_t)));
+    if (totals) {
+        int64_t* tot = bsum.p + m * nb;
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(64), 0, ctx->stream, sb, m, n, tot);
+        HIP_CHECK(hipGetLastError());
+        std::memcpy(totals, ctx->readback(tot, m * sizeof(int64_t)), m * sizeof(int64_t));
     } else {
         // keep bsum alive until the kernels ran
         ctx->sync();
     }
+}
+
+int64_t scan_exclusive_i32_to_i64(dec_ctx* ctx, const int32_t* in, int64_t* out, int64_t n, bool want_total) {
+    int64_t total = -1;
+    scan_exclusive_multi(ctx, 1, &in, &out, n, want_total ? &total : nullptr);
     return total;
 }
 

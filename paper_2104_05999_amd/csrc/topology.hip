@@ -308,42 +308,45 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
 // Faces: face k of tet t is opposite local vertex k.  The tets holding face
 // (a, b, c) are those holding both edges (a, b) and (a, c): the intersection
 // of two incidence lists, both in ascending tet order (a merge over ~10
-// contiguous integers).  The first such tet owns the face.
+// contiguous integers).  The first such tet owns the face.  Four lanes take
+// the four faces of a tet (their merges are independent chains of loads) and
+// combine their boundary bits with shuffles.
 __global__ void k_faces(int64_t T, const int32_t* __restrict__ tet_edge, const int64_t* __restrict__ et_ptr,
                         const int32_t* __restrict__ et_inc, uint8_t* __restrict__ bface,
                         unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
     __shared__ unsigned long long lds[BLOCK / 64];
     unsigned long long owned = 0, bnd = 0;
-    RANGE_LOOP(t, T) {
-        uint8_t mask = 0;
-        for (int k = 0; k < 4; ++k) {
-            const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
-            const int e1 = tet_edge[6 * t + local_edge(la, lb)];
-            const int e2 = tet_edge[6 * t + local_edge(la, lc)];
-            int64_t i = et_ptr[e1], j = et_ptr[e2];
-            const int64_t i1 = et_ptr[e1 + 1], j1 = et_ptr[e2 + 1];
-            int cnt = 0, first = -1;
-            while (i < i1 && j < j1) {
-                const int u = et_inc[i] / 6, w = et_inc[j] / 6;
-                if (u == w) {
-                    if (first < 0) first = u;
-                    ++cnt;
-                    ++i;
-                    ++j;
-                } else if (u < w) {
-                    ++i;
-                } else {
-                    ++j;
-                }
+    const int k = threadIdx.x & 3;
+    const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
+    const int ea = local_edge(la, lb), eb = local_edge(la, lc);
+    int64_t t_lo, t_hi;
+    block_range(T, &t_lo, &t_hi);
+    for (int64_t t = t_lo + threadIdx.x / 4; t < t_hi; t += blockDim.x / 4) {
+        const int e1 = tet_edge[6 * t + ea];
+        const int e2 = tet_edge[6 * t + eb];
+        int64_t i = et_ptr[e1], j = et_ptr[e2];
+        const int64_t i1 = et_ptr[e1 + 1], j1 = et_ptr[e2 + 1];
+        int cnt = 0, first = -1;
+        while (i < i1 && j < j1) {
+            const int u = et_inc[i] / 6, w = et_inc[j] / 6;
+            if (u == w) {
+                if (first < 0) first = u;
+                ++cnt;
+                ++i;
+                ++j;
+            } else if (u < w) {
+                ++i;
+            } else {
+                ++j;
             }
-            if (cnt > 2) atomicOr(err, 16u);
-            if (cnt == 1) {
-                mask |= (uint8_t)(1u << k);
-                ++bnd;
-            }
-            if (first == t) ++owned;
         }
-        bface[t] = mask;
+        if (cnt > 2) atomicOr(err, 16u);
+        unsigned mask = cnt == 1 ? 1u << k : 0u;
+        bnd += cnt == 1;
+        owned += first == t;
+        mask |= __shfl_xor(mask, 1);
+        mask |= __shfl_xor(mask, 2);
+        if (k == 0) bface[t] = static_cast<uint8_t>(mask);
     }
     owned = block_sum(owned, lds);
     bnd = block_sum(bnd, lds);
@@ -364,6 +367,12 @@ std::string topo_message(unsigned err) {
 }
 
 }  // namespace
+
+// m (1 to 3) exclusive scans of int32 arrays of the same length in one set
+// of launches, as scan_exclusive_i32_to_i64 does one; totals (when given)
+// receives their m totals with one synchronisation (api.hip).
+void scan_exclusive_multi(dec_ctx* ctx, int m, const int32_t* const* in, int64_t* const* out, int64_t n,
+                          int64_t* totals);
 
 // Build every topology array of m (V, T set) from device xyz / tets.
 void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) {
@@ -407,12 +416,14 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
                        n_up.p, row_len.p, n_inc.p);
     HIP_CHECK(hipGetLastError());
     m->up_ptr.alloc(ctx, V + 1);
-    const int64_t E = scan_exclusive_i32_to_i64(ctx, n_up.p, m->up_ptr.p, V, true);
     DBuf<int64_t> row_ptr64, inc_ptr;
     row_ptr64.alloc(ctx, V + 1);
     inc_ptr.alloc(ctx, V + 1);
-    const int64_t nnz = scan_exclusive_i32_to_i64(ctx, row_len.p, row_ptr64.p, V, true);
-    const int64_t ninc = scan_exclusive_i32_to_i64(ctx, n_inc.p, inc_ptr.p, V, true);
+    const int32_t* scan_in[3] = {n_up.p, row_len.p, n_inc.p};
+    int64_t* scan_out[3] = {m->up_ptr.p, row_ptr64.p, inc_ptr.p};
+    int64_t tot[3];
+    scan_exclusive_multi(ctx, 3, scan_in, scan_out, V, tot);
+    const int64_t E = tot[0], nnz = tot[1], ninc = tot[2];
     DEC_REQUIRE(nnz == V + 2 * E, DEC_ETOPO, "internal: pattern size mismatch");
     DEC_REQUIRE(ninc == 6 * T, DEC_ETOPO, "internal: incidence count mismatch");
     DEC_REQUIRE(nnz < (int64_t(1) << 31) && 6 * T < (int64_t(1) << 31), DEC_EINVAL,
@@ -431,26 +442,27 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(NG * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
                        m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, tet_edge.p,
                        m->col.p, m->nz_edge.p, m->diag_pos.p);
-    err.zero();
+    // [0] owned faces, [1] boundary faces, [2] error bits (low word): one read-back for all three
+    DBuf<unsigned long long> fc;
+    fc.alloc(ctx, 3);
+    fc.zero();
+    unsigned* err2 = reinterpret_cast<unsigned*>(fc.p + 2);
     hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
-                       m->up_ptr.p, m->edges.p, m->nz_edge.p, err.p);
+                       m->up_ptr.p, m->edges.p, m->nz_edge.p, err2);
     HIP_CHECK(hipGetLastError());
     m->row_ptr.alloc(ctx, V + 1);
     copy_i64_to_i32(ctx, row_ptr64.p, m->row_ptr.p, V + 1);
 
     // faces
     m->tet_bface.alloc(ctx, T);
-    DBuf<unsigned long long> fc;
-    fc.alloc(ctx, 2);
-    fc.zero();
-    hipLaunchKernelGGL(k_faces, dim3(grid_xcd(T)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
-                       m->et_inc.p, m->tet_bface.p, fc.p, err.p);
+    hipLaunchKernelGGL(k_faces, dim3(grid_xcd(4 * T)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
+                       m->et_inc.p, m->tet_bface.p, fc.p, err2);
     HIP_CHECK(hipGetLastError());
-    unsigned long long hc[2];
+    unsigned long long hc[3];
     std::memcpy(hc, ctx->readback(fc.p, sizeof(hc)), sizeof(hc));
     m->F = (int64_t)hc[0];
     m->Fb = (int64_t)hc[1];
-    unsigned e1 = *static_cast<unsigned*>(ctx->readback(err.p, sizeof(unsigned)));
+    const unsigned e1 = static_cast<unsigned>(hc[2] & 0xffffffffu);
     if (e1) dec_fail(DEC_ETOPO, topo_message(e1));
 }
 
