@@ -495,10 +495,17 @@ constexpr int prec_index() {
 
 // With events, the launch carries them (hipExtLaunchKernelGGL): the
 // timestamps are those of the dispatch itself, not of separate markers.
+// Blocks of the iteration's product (MODE_DOT) for precision VT: Gd, else Gs.
+template <class VT>
+int dot_grid(const SolveCache* c) {
+    const int g = c->Gd[prec_index<VT>()];
+    return g > 0 ? g : c->Gs;
+}
+
 template <class VT, int MODE, int U, bool NT, bool DIFF, int CF, int ORD>
 void launch_sell_o(SolveCache* c, const SellView<VT>& A, const VT* x, VT* y, const VT* b, double* part,
                    const int32_t* done, hipEvent_t ev_a, hipEvent_t ev_b) {
-    const dim3 g(c->Gs), blk(BLOCK);
+    const dim3 g(MODE == MODE_DOT ? dot_grid<VT>(c) : c->Gs), blk(BLOCK);
     if (ev_a)
         hipExtLaunchKernelGGL((k_sell<VT, MODE, U, NT, DIFF, CF, ORD>), g, blk, 0, c->stream, ev_a, ev_b, 0, A, x,
                               y, b, part, done);
@@ -755,7 +762,7 @@ template <class VT>
 void enqueue_iteration(SolveCache* c, const Run<VT>& R, int par, hipEvent_t ev_a = nullptr,
                        hipEvent_t ev_b = nullptr) {
     const int64_t V = R.A.V;
-    const int G = c->G, P = stride(c), n_pq = c->Gs;
+    const int G = c->G, P = stride(c), n_pq = dot_grid<VT>(c);
     double* part = c->partials.p;
     PcgScalars* S = R.st + par;
     PcgScalars* N = R.st + (par ^ 1);
@@ -1190,6 +1197,8 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
     };
     c.G = blocks(BLOCK, V >= VEC_WIDE_ROWS ? 8 : 4);
     c.Gs = blocks(SELL_C * (BLOCK / 64), 8);
+    c.Gd[0] = blocks(SELL_C * (BLOCK / 64), m->sell.excess64.p ? 8 : 4);  // as dec_solve's FP64 iteration
+    c.Gd[1] = c.Gs;
     const SellMatrix& S = m->sell;
     const std::array<int64_t, 4> shape{0 + (S.excess64.p ? 2 : 0) + (S.dcol.p ? 4 : 0) + (S.tcol.p ? 8 : 0), V,
                                        S.nslices, S.entries};
@@ -1254,7 +1263,8 @@ int solve_noalloc(dec_mesh* m, const dec_solve_opts& o, double* T, double* base,
                 PcgScalars* S = st + (k & 1);
                 PcgScalars* N = st + ((k & 1) ^ 1);
                 launch_sell<double, MODE_DOT>(&c, A, p, q, nullptr, part + R_PQ * P, S);
-                launch_update<double, PJ_JACOBI>(c.stream, G, V, r, q, m->invdiag64.p, part, P, Gs, S);
+                launch_update<double, PJ_JACOBI>(c.stream, G, V, r, q, m->invdiag64.p, part, P, dot_grid<double>(&c),
+                                                 S);
                 launch_close<double, PJ_JACOBI>(c.stream, G, V, T, r, m->invdiag64.p, nullptr, p, part, P, G, S, N);
             }
             HIP_CHECK(hipGetLastError());
@@ -1335,7 +1345,11 @@ SolveCache* get_solve_cache(dec_mesh* m) {
         // per solve), 4 below (128^3: 48.8 against 54.3 ms)
         int per_cu = m->V >= VEC_WIDE_ROWS ? 8 : 4, per_cu_s = 8;
         if (const char* env = getenv("DEC_BLOCKS_PER_CU")) per_cu = atoi(env) > 0 ? atoi(env) : per_cu;
-        if (const char* env = getenv("DEC_SPMV_BLOCKS_PER_CU")) per_cu_s = atoi(env) > 0 ? atoi(env) : per_cu_s;
+        bool env_cu_s = false;
+        if (const char* env = getenv("DEC_SPMV_BLOCKS_PER_CU")) {
+            per_cu_s = atoi(env) > 0 ? atoi(env) : per_cu_s;
+            env_cu_s = atoi(env) > 0;
+        }
         if (const char* env = getenv("DEC_SELL_UNROLL")) {
             c->unroll[0] = c->unroll[1] = atoi(env);
             c->pinned_variant = true;
@@ -1359,6 +1373,15 @@ SolveCache* get_solve_cache(dec_mesh* m) {
         };
         c->G = blocks(BLOCK, per_cu);
         c->Gs = blocks(SELL_C * (BLOCK / 64), per_cu_s);
+        // the iteration's product: 4 blocks per CU for FP64 on a plain matrix (its
+        // faster load orders keep enough loads in flight with fewer waves; 128^3:
+        // 25.5 against 26.3 us, 256^3: 275 against 284 us), 8 for FP32 and the
+        // difference form (128^3 FP32: 15.4 against 18.3 us, tet system: 160
+        // against 177 us).  A rule, not a timing, because the block count sets how
+        // the p.q partials group the rows, and so the rounding of the solve.
+        const int dot_cu64 = env_cu_s ? per_cu_s : (m->sell.excess64.p ? 8 : 4);
+        c->Gd[0] = blocks(SELL_C * (BLOCK / 64), dot_cu64);
+        c->Gd[1] = c->Gs;
         c->partials.alloc(m->ctx, 3 * (int64_t)stride(c));
         c->st.alloc(m->ctx, 6);
         HIP_CHECK(hipMemsetAsync(c->st.p, 0, 6 * sizeof(PcgScalars), c->stream));

@@ -83,6 +83,7 @@ struct SolveCache {
     hipStream_t stream = nullptr;  // internal stream (graph capture needs a non-null stream)
     int G = 0;                     // blocks of the vector kernels (multiple of 8)
     int Gs = 0;                    // blocks of the SpMV kernels (multiple of 8)
+    int Gd[2] = {0, 0};            // blocks of the iteration's product (y = A p, p.q partials) per precision, <= Gs
     // sliced-ELL variant per precision ([0] FP64, [1] FP32), chosen by the
     // tuner among variants whose products are bit-for-bit identical
     int unroll[2] = {4, 4};
