@@ -279,10 +279,12 @@ __device__ __forceinline__ VT sell_row_cfirst(const SellView<VT>& A, int64_t bas
             c0[u] = RC::lo(rc[u], row, tab);
             c1[u] = RC::hi(rc[u], row, tab);
         }
-        // decoded whether or not the row has an odd entry (an even row's stand-in is
-        // another row's column, so the row itself is gathered instead)
+        // decoded whether or not the row has an odd entry; an even row's stand-in is
+        // another row's column, so the gather takes the row's first column instead
+        // (a column of this lane's own row: for a lane past the last row the
+        // padding's, inside x; the row number itself can lie past the end of x)
         const int32_t cod = one_col<CF>(oc, row, tab);
-        const int32_t co = odd ? cod : row;
+        const int32_t co = odd ? cod : c0[0];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             x0[u] = gather(c0[u]);
