@@ -82,8 +82,12 @@ struct RawCol<CF_U8> {
     typedef uint16_t pair;  // two one-byte indices
     typedef uint8_t one;
     typedef uint32_t bits;
-    static __device__ __forceinline__ int32_t lo(bits b, int32_t row, const int32_t* tab) { return row + tab[b & 0xff]; }
-    static __device__ __forceinline__ int32_t hi(bits b, int32_t row, const int32_t* tab) { return row + tab[b >> 8]; }
+    static __device__ __forceinline__ int32_t lo(bits b, int32_t row, const int32_t* tab) {
+        return row + tab[b & 0xff];
+    }
+    static __device__ __forceinline__ int32_t hi(bits b, int32_t row, const int32_t* tab) {
+        return row + tab[b >> 8];
+    }
 };
 template <>
 struct RawCol<CF_I16> {
@@ -132,18 +136,22 @@ __device__ __forceinline__ T stream_load(const T* p) {
 // row: sum over the row's entries in stored (ascending column) order.  x is
 // indexed with unsigned 32-bit columns (every column is in [0, V), V < 2^31),
 // so a gather's address is the uniform base plus a 32-bit offset.  The
-// pairs go in groups of U: all column and value loads of a group are issued
-// before its x gathers, and the last group is predicated (the width is
-// uniform across the wavefront), so no entry waits on the one before.  An odd
-// last entry (rows of 7 entries are the common case on these meshes) has its
-// column and value loaded before the first group and its x gathered with the
-// last group's, so a row costs one round trip for the matrix and one for x.
-// The terms are added in entry order, so every layout and unroll gives the
-// same sum.  DIFF: each term is a_ij (x_j - xi).  CF:
+// pairs go in groups of U, each pair's column load next to its value load
+// and decoded as it arrives, the group's x gathers after them; the last
+// group is predicated (the width is uniform across the wavefront).  Loads
+// complete in the order they are issued, so decoding a pair's column also
+// waits for the values issued before it: a group's column round trips
+// follow one another (sell_row_cfirst issues the columns first instead).
+// An odd last entry (rows of 7 entries are the common case on these meshes)
+// has its column and value loaded before the first group and its x gathered
+// with the last group's.  The terms are added in entry order, so every
+// layout, unroll and load order gives the same sum.  DIFF: each term is a_ij (x_j - xi).  CF:
 // the columns as int32 (A.col), 16-bit offsets (A.dcol) added to `row`, or
 // one-byte indices (A.tcol) into the offset table `tab` (in LDS) added to
-// `row` (for a lane past the last row, row is the last row and its entries
-// index the offset 0).
+// `row`.  A lane past the last row decodes columns that lie inside x: with
+// one-byte indices its `row` is the last row and its entries index the
+// offset 0; otherwise its `row` is its own (past the end of x) and its
+// stored padding offsets or columns name a column inside x.
 template <class VT, int U, bool NT = true, bool DIFF = false, int CF = CF_I32>
 __device__ __forceinline__ VT sell_row(const SellView<VT>& A, int64_t base, int width, int lane,
                                        const VT* __restrict__ x, VT xi = 0, int32_t row = 0,
@@ -384,9 +392,9 @@ __device__ __forceinline__ void sell_finish(const SellView<VT>& A, int64_t row, 
 }
 
 template <class VT, int MODE, int U, bool NT, bool DIFF = false, int CF = CF_I32, int ORD = 0>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(U <= 3 ? 8 : 6))) void k_sell(SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y,
-                                                const VT* __restrict__ b, double* __restrict__ partials,
-                                                const int32_t* __restrict__ done) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(U <= 3 ? 8 : 6))) void k_sell(
+    SellView<VT> A, const VT* __restrict__ x, VT* __restrict__ y, const VT* __restrict__ b,
+    double* __restrict__ partials, const int32_t* __restrict__ done) {
     __shared__ double lds[BLOCK / 64 + 1];
     __shared__ int32_t tab[CF == CF_U8 ? OTAB_MAX : 1];
     if (done != nullptr && *done) return;
@@ -411,8 +419,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(U <= 3 ? 
         // the row's own x (DIFF: for the differences, DOT: for x.y), loaded with the matrix
         const VT xr = x[row < A.V ? row : A.V - 1];
         const VT xi = (DIFF || MODE == MODE_DOT) && row < A.V ? xr : VT(0);
-        const VT acc = ORD == 1 ? sell_row_cfirst<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab)
-                                : sell_row<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, decode_row(row), tab);
+        const int32_t drow = decode_row(row);
+        const VT acc = ORD == 1 ? sell_row_cfirst<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, drow, tab)
+                                : sell_row<VT, U, NT, DIFF, CF>(A, base, width, lane, x, xi, drow, tab);
         sell_finish<VT, MODE, DIFF>(A, row, acc, xi, x, y, b, d);
     }
     if (MODE == MODE_PLAIN) return;
