@@ -248,7 +248,7 @@ typedef struct dec_solve_stats {
     double plain_residual;    /* true FP64 ||b - A T||_2 / ||b||_2 at exit                 */
     int32_t spmv_unroll;      /* the product variant of the iteration's precision: entry
                                  pairs in flight per lane (2, 3, 4; timed by the autotuner) */
-    int32_t spmv_nontemporal; /* 1 when its matrix loads are non-temporal                  */
+    int32_t spmv_nontemporal; /* 1 when its matrix loads and y stores are non-temporal     */
     int32_t spmv_col_bytes;   /* its column encoding: 1 one-byte offset-table index, 2
                                  16-bit offset, 4 int32 column                             */
     int32_t spmv_band;        /* slices per band of its banded slice order, 0 for plain    */

@@ -140,7 +140,10 @@ __device__ __forceinline__ VT item_product(const SellView<VT>& A, int64_t s0, in
                 y[row] = ri;
                 d += ri * ri;
             } else {
-                y[row] = acc;
+                if (NT)  // the non-temporal variant stores y non-temporally too
+                    __builtin_nontemporal_store(acc, y + row);
+                else
+                    y[row] = acc;
                 d += x[row] * acc;
             }
         }
