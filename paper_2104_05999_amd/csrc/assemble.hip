@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "group_front.h"
 #include "sell.h"
 
 struct SolveCache;
@@ -25,9 +26,7 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
                                   const int32_t* __restrict__ diag_pos, const double* __restrict__ star1,
                                   double* __restrict__ val64, float* __restrict__ val32) {
     const int g = threadIdx.x & (ROWG - 1);
-    int64_t v0, v1;
-    block_range(V, &v0, &v1);
-    for (int64_t v = v0 + threadIdx.x / ROWG; v < v1; v += blockDim.x / ROWG) {
+    GROUP_FRONT_LOOP(v, V, ROWG) {
         const int32_t b = row_ptr[v], n = row_ptr[v + 1] - b;
         double sum = 0.0;
         for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
@@ -58,9 +57,23 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
 // area has L_ij = -kappa * 0 = -0 for every conductivity and crack set, and
 // adding its product to a row sum changes nothing, so the product y = A x is
 // bit-for-bit that of the full static pattern (which the CSR keeps).
-__device__ __forceinline__ bool kept(int32_t k, const int32_t* __restrict__ nz_edge, const double* __restrict__ geo) {
-    const int32_t e = nz_edge[k];
-    return e < 0 || geo == nullptr || geo[e] != 0.0;
+//
+// Kept flags (bit u) of entries k .. k + 7 of a row that ends before k1
+// (entries past the row: not kept); the eight loads of each kind are issued
+// together.
+__device__ __forceinline__ unsigned kept8(int32_t k, int32_t k1, const int32_t* __restrict__ nz_edge,
+                                          const double* __restrict__ geo) {
+    int32_t e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = k + u < k1 ? nz_edge[k + u] : -1;
+    unsigned mask = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const bool in = k + u < k1;
+        const double g = (in && e[u] >= 0 && geo != nullptr) ? geo[e[u]] : 1.0;
+        mask |= (in && g != 0.0) ? 1u << u : 0u;
+    }
+    return mask;
 }
 
 // Stored entries per slice: one wavefront per slice, each lane counts its
@@ -79,8 +92,10 @@ __global__ __launch_bounds__(BLOCK) void k_sell_width(int64_t V, int64_t nslices
     for (int64_t s = s0 + w; s < s1; s += BLOCK / 64) {
         const int64_t r = s * SELL_C + lane;
         int len = 0;
-        if (r < V)
-            for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) len += kept(k, nz_edge, geo);
+        if (r < V) {
+            const int32_t k1 = row_ptr[r + 1];
+            for (int32_t k = row_ptr[r]; k < k1; k += 8) len += __popc(kept8(k, k1, nz_edge, geo));
+        }
         total += len;
         int wmax = len;
 #pragma unroll
@@ -95,7 +110,7 @@ __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restric
                             const int32_t* __restrict__ col, const int32_t* __restrict__ nz_edge,
                             const double* __restrict__ geo, const int64_t* __restrict__ sptr,
                             int32_t* __restrict__ scol, int32_t* __restrict__ ssrc) {
-    RANGE_LOOP(i, nslices * SELL_C) {
+    GROUP_FRONT_LOOP(i, nslices * SELL_C, 1) {
         const int64_t s = i / SELL_C;
         const int lane = static_cast<int>(i % SELL_C);
         const int64_t row = i;
@@ -103,12 +118,20 @@ __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restric
         const int32_t pad_col = static_cast<int32_t>(row < V ? row : V - 1);
         int j = 0;
         if (row < V) {
-            for (int32_t k = row_ptr[row]; k < row_ptr[row + 1]; ++k) {
-                if (!kept(k, nz_edge, geo)) continue;
-                const int64_t idx = sell_index(sptr[s], width, j, lane);
-                scol[idx] = col[k];
-                ssrc[idx] = k;
-                ++j;
+            const int32_t k1 = row_ptr[row + 1];
+            for (int32_t k = row_ptr[row]; k < k1; k += 8) {
+                const unsigned mask = kept8(k, k1, nz_edge, geo);
+                int32_t c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = (mask >> u) & 1u ? col[k + u] : 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (!((mask >> u) & 1u)) continue;
+                    const int64_t idx = sell_index(sptr[s], width, j, lane);
+                    scol[idx] = c[u];
+                    ssrc[idx] = k + u;
+                    ++j;
+                }
             }
         }
         for (; j < width; ++j) {

@@ -89,13 +89,28 @@ __global__ void k_elementary_areas(int64_t T, const int32_t* __restrict__ tets, 
     }
 }
 
-// |*e| in ascending tet order, snapped, over |e|
+// |*e| in ascending tet order, snapped, over |e|.  Up to RING incidences are
+// loaded at once (their loads do not wait on each other), then added in order.
+constexpr int RING = 8;
+
 __global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
                                 const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
                                 const double* __restrict__ elem, double* __restrict__ geo) {
-    RANGE_LOOP(e, E) {
+    const FrontRange fr = front_range(E);
+    for (int64_t e = fr.first; e < fr.end; e += fr.step) {
+        const int64_t i0 = et_ptr[e];
+        const int m = static_cast<int>(et_ptr[e + 1] - i0);
         double area = 0.0;
-        for (int64_t k = et_ptr[e]; k < et_ptr[e + 1]; ++k) area += elem[et_inc[k]];
+        if (m <= RING) {
+            double a[RING];
+#pragma unroll
+            for (int r = 0; r < RING; ++r) a[r] = r < m ? elem[et_inc[i0 + r]] : 0.0;
+#pragma unroll
+            for (int r = 0; r < RING; ++r)
+                if (r < m) area += a[r];
+        } else {
+            for (int r = 0; r < m; ++r) area += elem[et_inc[i0 + r]];
+        }
         const d3 d = sub(load3(xyz + 3 * (int64_t)edges[2 * e + 1]), load3(xyz + 3 * (int64_t)edges[2 * e]));
         const double len = sqrt(dot(d, d));
         if (fabs(area) <= 1e-12 * len * len) area = 0.0;

@@ -5,12 +5,14 @@
 //
 // Every list is built per vertex from that vertex's sorted tet list, so the
 // result is independent of thread scheduling: integer atomics only count
-// (deterministic totals) or claim slots whose order the per-vertex sort then
-// fixes.  Compiled without floating-point contraction: the zero-volume test
+// (deterministic totals), set bits, or claim slots whose order the per-vertex
+// sort then fixes.  Compiled without floating-point contraction: the zero-volume test
 // must take the same decision as the FP64 reference.
 #include <climits>
+#include <type_traits>
 
 #include "common.h"
+#include "group_front.h"
 #include "wave_atomic.h"
 
 namespace {
@@ -75,9 +77,7 @@ __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const in
 __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
     constexpr int W = 32;
     const int lane = threadIdx.x & (W - 1);
-    int64_t v0, v1;
-    block_range(V, &v0, &v1);
-    for (int64_t v = v0 + threadIdx.x / W; v < v1; v += blockDim.x / W) {
+    GROUP_FRONT_LOOP(v, V, W) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
         if (d <= W) {
@@ -109,16 +109,24 @@ __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restric
 // INT_MAX: no neighbour left.
 constexpr int NG = 16;
 
-__device__ __forceinline__ int group_min(int v) {
-#pragma unroll
-    for (int off = NG / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, NG));
+// Reductions over one group (a row of 16 lanes, all of them active) with DPP
+// row rotations by 8 and 4, then the quad permutations [2,3,0,1] and
+// [1,0,3,2]: every lane ends with the result, and no LDS round trip is taken.
+template <class Op>
+__device__ __forceinline__ int group_reduce(int v, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false));
     return v;
 }
 
+__device__ __forceinline__ int group_min(int v) {
+    return group_reduce(v, [](int a, int b) { return min(a, b); });
+}
+
 __device__ __forceinline__ int group_sum(int v) {
-#pragma unroll
-    for (int off = NG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, NG);
-    return v;
+    return group_reduce(v, [](int a, int b) { return a + b; });
 }
 
 __device__ __forceinline__ int tet_pos(const int4& q, int w) {
@@ -163,6 +171,90 @@ __device__ __forceinline__ int group_next(const int4* __restrict__ tets, const i
     return group_min(best);
 }
 
+// Vertices of at most 2 * NG tets (every tet of the list in registers) take
+// a faster enumeration: each lane keeps the three other vertices of each of
+// its two tets as ascending keys w * 8 + tet * 4 + position (tet 0: list
+// entry g, tet 1: entry g + NG; INT_MAX past the end).  A round takes the
+// group minimum w of the lanes' first keys and each lane drops its keys of w
+// -- at most two, a tet holds w at most once, and tet 0's comes first -- so
+// the rounds visit the neighbours in ascending order without rescanning the
+// tets, and the dropped keys say which of the lane's tets hold w and where.
+// Vertex ids must stay below KEY_LIMIT for the keys to fit an int.
+constexpr int64_t KEY_LIMIT = (int64_t(1) << 28) - 1;
+constexpr int NKEY = 6;
+static_assert(NG == 16, "the group reductions work on rows of 16 lanes");
+
+__device__ __forceinline__ void cmp_swap(int& a, int& b) {
+    const int lo = min(a, b);
+    b = max(a, b);
+    a = lo;
+}
+
+// the vertices of q other than v as keys, ascending (an absent tet, all -1: four INT_MAX)
+__device__ __forceinline__ void tet_keys(const int4& q, int v, int tag, int* k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int w = vget(q, r);
+        k[r] = (w != v && w >= 0) ? (w << 3) | tag | r : INT_MAX;
+    }
+    cmp_swap(k[0], k[1]);
+    cmp_swap(k[2], k[3]);
+    cmp_swap(k[0], k[2]);
+    cmp_swap(k[1], k[3]);
+    cmp_swap(k[1], k[2]);
+}
+
+struct LaneKeys {
+    int c[NKEY];
+    __device__ __forceinline__ void pop_if(bool p) {
+#pragma unroll
+        for (int i = 0; i < NKEY - 1; ++i) c[i] = p ? c[i + 1] : c[i];
+        c[NKEY - 1] = p ? INT_MAX : c[NKEY - 1];
+    }
+};
+
+__device__ __forceinline__ LaneKeys lane_keys(const GroupTets& gt, int v) {
+    int x[8];
+    tet_keys(gt.q0, v, 0, x);
+    tet_keys(gt.q1, v, 4, x + 4);
+    // odd-even merge of the two sorted runs of four (each ends in INT_MAX, so
+    // the six smallest are all a lane can hold)
+    cmp_swap(x[0], x[4]);
+    cmp_swap(x[1], x[5]);
+    cmp_swap(x[2], x[6]);
+    cmp_swap(x[3], x[7]);
+    cmp_swap(x[2], x[4]);
+    cmp_swap(x[3], x[5]);
+    cmp_swap(x[1], x[2]);
+    cmp_swap(x[3], x[4]);
+    cmp_swap(x[5], x[6]);
+    LaneKeys k;
+#pragma unroll
+    for (int i = 0; i < NKEY; ++i) k.c[i] = x[i];
+    return k;
+}
+
+// One round: w is the group's next neighbour (INT_MAX: none left); e0 / e1
+// tell whether the lane's first / second dropped key (h0 / h1) was one of w.
+struct KeyRound {
+    int w = INT_MAX;
+    bool e0 = false, e1 = false;
+    int h0 = INT_MAX, h1 = INT_MAX;
+};
+
+__device__ __forceinline__ KeyRound next_key(LaneKeys& k) {
+    KeyRound r;
+    r.h0 = k.c[0];
+    const int m = group_min(r.h0);
+    r.w = m == INT_MAX ? INT_MAX : m >> 3;
+    r.e0 = (r.h0 >> 3) == r.w;
+    k.pop_if(r.e0);
+    r.h1 = k.c[0];
+    r.e1 = r.e0 && (r.h1 >> 3) == r.w;
+    k.pop_if(r.e1);
+    return r;
+}
+
 // Per vertex: upper neighbours (edges it is the low end of), pattern row
 // length, and the incidences of its upper edges -- each tet of v adds one per
 // vertex above v, so that count needs no enumeration.
@@ -178,13 +270,24 @@ __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __rest
         int inc = above(gt.q0, (int)v) + above(gt.q1, (int)v);
         for (int k = g + 2 * NG; k < d; k += NG) inc += above(tets[vt_list[b + k]], (int)v);
         inc = group_sum(inc);
-        int cur = -1, up = 0, all = 0;
-        while (true) {
-            const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
-            if (w == INT_MAX) break;
-            cur = w;
-            ++all;
-            up += w > v;
+        int up = 0, all = 0;
+        if (d <= 2 * NG && V <= KEY_LIMIT) {
+            LaneKeys keys = lane_keys(gt, (int)v);
+            while (true) {
+                const int w = next_key(keys).w;
+                if (w == INT_MAX) break;
+                ++all;
+                up += w > v;
+            }
+        } else {
+            int cur = -1;
+            while (true) {
+                const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
+                if (w == INT_MAX) break;
+                cur = w;
+                ++all;
+                up += w > v;
+            }
         }
         if (g == 0) {
             n_up[v] = up;
@@ -198,12 +301,12 @@ __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __rest
 // ascending).  Upper neighbours w define the edges (v, w), numbered from
 // up_ptr[v] in ascending w -- lexicographic (lo, hi) order overall -- and
 // their incidence lists: the tets of v holding w, in ascending tet order, as
-// tet * 6 + local edge, from inc_ptr[v] on.  Also the tet -> edge map.
+// tet * 6 + local edge, from inc_ptr[v] on.
 __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
                            const int32_t* __restrict__ vt_list, int64_t V, const int64_t* __restrict__ up_ptr,
                            const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ inc_ptr,
                            int32_t* __restrict__ edges, int64_t* __restrict__ et_ptr, int32_t* __restrict__ et_inc,
-                           int32_t* __restrict__ tet_edge, int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
+                           int32_t* __restrict__ col, int32_t* __restrict__ nz_edge,
                            int32_t* __restrict__ diag_pos) {
     const int lane = threadIdx.x & 63;
     const int g = threadIdx.x & (NG - 1);
@@ -214,90 +317,168 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
         const GroupTets gt = load_group_tets(tets, vt_list, b, d, g);
-        int64_t pos = row_ptr[v], ep = up_ptr[v], ip = inc_ptr[v];
-        bool diag = false;
-        int cur = -1;
-        while (true) {
-            const int w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
-            if (w == INT_MAX) break;
-            cur = w;
-            if (w > v && !diag) {
-                if (g == 0) {
-                    col[pos] = (int32_t)v;
-                    nz_edge[pos] = -1;
-                    diag_pos[v] = (int32_t)pos;
+        const int64_t row0 = row_ptr[v], up0 = up_ptr[v];
+        int64_t ip = inc_ptr[v];
+        // Row entries and upper edges are produced one per round; entry j is
+        // kept by lane j % NG and every NG of them the group stores together
+        // (one coalesced store per array), the rest after the last round.
+        int nrow = 0, nup = 0;  // row entries and upper edges so far
+        int pcol = 0, pnz = 0;  // this lane's pending row entry: column, edge id
+        int phi = 0;            // this lane's pending upper edge: its high end ...
+        int64_t pinc = 0;       // ... and its first incidence
+        int dpos = -1;          // position of the diagonal in the row
+        auto put_row = [&](int c, int z) {
+            const bool mine = (nrow & (NG - 1)) == g;
+            pcol = mine ? c : pcol;
+            pnz = mine ? z : pnz;
+            if ((++nrow & (NG - 1)) == 0) {
+                col[row0 + nrow - NG + g] = pcol;
+                nz_edge[row0 + nrow - NG + g] = pnz;
+            }
+        };
+        auto put_up = [&](int hi, int64_t first) {
+            const bool mine = (nup & (NG - 1)) == g;
+            phi = mine ? hi : phi;
+            pinc = mine ? first : pinc;
+            if ((++nup & (NG - 1)) == 0) {
+                const int64_t e = up0 + nup - NG + g;
+                reinterpret_cast<int2*>(edges)[e] = make_int2((int)v, phi);
+                et_ptr[e] = pinc;
+            }
+        };
+        // the rounds, compiled once for waves whose groups all take the fast
+        // path (no branch to the general enumeration left) and once for the rest
+        const bool fast_group = d <= 2 * NG && V <= KEY_LIMIT;
+        auto rounds = [&](auto any_slow) {
+            const bool fast = decltype(any_slow)::value ? fast_group : true;
+            int cur = -1;
+            LaneKeys keys;
+            int pv0 = -1, pv1 = -1;  // position of v in the lane's two tets
+            if (fast) {
+                keys = lane_keys(gt, (int)v);
+                pv0 = tet_pos(gt.q0, (int)v);
+                pv1 = tet_pos(gt.q1, (int)v);
+            }
+            while (true) {
+                KeyRound r;
+                if (fast)
+                    r = next_key(keys);
+                else
+                    r.w = group_next(tets, vt_list, b, d, (int)v, cur, g, gt);
+                const int w = r.w;
+                if (w == INT_MAX) break;
+                cur = w;
+                if (w > v && dpos < 0) {
+                    dpos = nrow;
+                    put_row((int)v, -1);
                 }
-                ++pos;
-                diag = true;
-            }
-            if (g == 0) {
-                col[pos] = w;
-                nz_edge[pos] = w < v ? -2 : (int32_t)ep;  // lower entries: k_lower_edge_ids
-            }
-            ++pos;
-            if (w < v) continue;
-            if (g == 0) {
-                edges[2 * ep] = (int32_t)v;
-                edges[2 * ep + 1] = w;
-                et_ptr[ep] = ip;
-            }
-            // incidences in ascending tet order: blocks of NG tets, lane order inside a block
-            for (int k0 = 0; k0 < d; k0 += NG) {
-                const int k = k0 + g;
-                int4 q = make_int4(-1, -1, -1, -1);
-                int t = -1;
-                if (k0 == 0) {
-                    q = gt.q0;
-                    t = gt.t0;
-                } else if (k0 == NG) {
-                    q = gt.q1;
-                    t = gt.t1;
-                } else if (k < d) {
-                    t = vt_list[b + k];
-                    q = tets[t];
+                put_row(w, w < v ? -2 : (int32_t)(up0 + nup));  // lower entries: k_lower_edge_ids
+                if (w < v) continue;
+                put_up(w, ip);
+                if (fast) {
+                    // tet 0 of lane g is list entry g, tet 1 entry g + NG: ascending
+                    // tet order is every lane's tet 0 in lane order, then their tets 1
+                    const bool in0 = r.e0 && !(r.h0 & 4);
+                    const bool in1 = (r.e0 && (r.h0 & 4)) || r.e1;
+                    const int p0 = r.h0 & 3, p1 = (r.e1 ? r.h1 : r.h0) & 3;
+                    const uint64_t b0 = (__ballot(in0) >> gbase) & ((uint64_t(1) << NG) - 1);
+                    const uint64_t b1 = (__ballot(in1) >> gbase) & ((uint64_t(1) << NG) - 1);
+                    const int n0 = __popcll(b0);
+                    if (in0) {
+                        const int slot = gt.t0 * 6 + local_edge(min(pv0, p0), max(pv0, p0));
+                        et_inc[ip + __popcll(b0 & below)] = slot;
+                    }
+                    if (in1) {
+                        const int slot = gt.t1 * 6 + local_edge(min(pv1, p1), max(pv1, p1));
+                        et_inc[ip + n0 + __popcll(b1 & below)] = slot;
+                    }
+                    ip += n0 + __popcll(b1);
+                    continue;
                 }
-                const int pw = tet_pos(q, w);
-                const uint64_t ball = (__ballot(pw >= 0) >> gbase) & ((uint64_t(1) << NG) - 1);
-                if (pw >= 0) {
-                    const int pv = tet_pos(q, (int)v);
-                    const int slot = t * 6 + local_edge(pv < pw ? pv : pw, pv < pw ? pw : pv);
-                    et_inc[ip + __popcll(ball & below)] = slot;
-                    tet_edge[slot] = (int32_t)ep;
+                // incidences in ascending tet order: blocks of NG tets, lane order inside a block
+                for (int k0 = 0; k0 < d; k0 += NG) {
+                    const int k = k0 + g;
+                    int4 q = make_int4(-1, -1, -1, -1);
+                    int t = -1;
+                    if (k0 == 0) {
+                        q = gt.q0;
+                        t = gt.t0;
+                    } else if (k0 == NG) {
+                        q = gt.q1;
+                        t = gt.t1;
+                    } else if (k < d) {
+                        t = vt_list[b + k];
+                        q = tets[t];
+                    }
+                    const int pw = tet_pos(q, w);
+                    const uint64_t ball = (__ballot(pw >= 0) >> gbase) & ((uint64_t(1) << NG) - 1);
+                    if (pw >= 0) {
+                        const int pv = tet_pos(q, (int)v);
+                        const int slot = t * 6 + local_edge(pv < pw ? pv : pw, pv < pw ? pw : pv);
+                        et_inc[ip + __popcll(ball & below)] = slot;
+                    }
+                    ip += __popcll(ball);
                 }
-                ip += __popcll(ball);
             }
-            ++ep;
+        };
+        if (__ballot(!fast_group) == 0)
+            rounds(std::false_type{});
+        else
+            rounds(std::true_type{});
+        if (dpos < 0) {
+            dpos = nrow;
+            put_row((int)v, -1);
         }
-        if (!diag && g == 0) {
-            col[pos] = (int32_t)v;
-            nz_edge[pos] = -1;
-            diag_pos[v] = (int32_t)pos;
+        const int rrow = nrow & (NG - 1), rup = nup & (NG - 1);  // entries not stored yet
+        if (g < rrow) {
+            col[row0 + nrow - rrow + g] = pcol;
+            nz_edge[row0 + nrow - rrow + g] = pnz;
         }
+        if (g < rup) {
+            const int64_t e = up0 + nup - rup + g;
+            reinterpret_cast<int2*>(edges)[e] = make_int2((int)v, phi);
+            et_ptr[e] = pinc;
+        }
+        if (g == 0) diag_pos[v] = (int32_t)(row0 + dpos);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) et_ptr[up_ptr[V]] = inc_ptr[V];
 }
 
-// Entries (v, w) with w < v belong to edge (w, v), found by binary search in
-// w's upper edges (sorted by hi).
+// Entries (v, w) with w < v belong to edge (w, v), found among w's upper
+// edges (sorted by hi).  One NG-lane group per row, a lane per entry; lists
+// of up to 8 upper edges are read at once and scanned, longer ones binary
+// searched.
 __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
                                  int32_t* __restrict__ nz_edge, unsigned* __restrict__ err) {
-    RANGE_LOOP(v, V) {
-        for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+    const int g = threadIdx.x & (NG - 1);
+    GROUP_FRONT_LOOP(v, V, NG) {
+        const int64_t k1 = row_ptr[v + 1];
+        for (int64_t k = row_ptr[v] + g; k < k1; k += NG) {
             const int w = col[k];
             if (w >= v) break;
-            int64_t lo = up_ptr[w], hi = up_ptr[w + 1] - 1, found = -1;
-            while (lo <= hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                const int h = edges[2 * mid + 1];
-                if (h == v) {
-                    found = mid;
-                    break;
+            const int64_t lo = up_ptr[w], n = up_ptr[w + 1] - lo;
+            int64_t found = -1;
+            if (n <= 8) {
+                int h[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) h[u] = u < n ? edges[2 * (lo + u) + 1] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) found = h[u] == v ? lo + u : found;
+            } else {
+                int64_t a = lo, b = lo + n - 1;
+                while (a <= b) {
+                    const int64_t mid = (a + b) >> 1;
+                    const int hv = edges[2 * mid + 1];
+                    if (hv == v) {
+                        found = mid;
+                        break;
+                    }
+                    if (hv < v)
+                        a = mid + 1;
+                    else
+                        b = mid - 1;
                 }
-                if (h < v)
-                    lo = mid + 1;
-                else
-                    hi = mid - 1;
             }
             if (found < 0) atomicOr(err, 8u);
             nz_edge[k] = (int32_t)found;
@@ -305,51 +486,102 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
     }
 }
 
-// Faces: face k of tet t is opposite local vertex k.  The tets holding face
-// (a, b, c) are those holding both edges (a, b) and (a, c): the intersection
-// of two incidence lists, both in ascending tet order (a merge over ~10
-// contiguous integers).  The first such tet owns the face.  Four lanes take
-// the four faces of a tet (their merges are independent chains of loads) and
-// combine their boundary bits with shuffles.
-__global__ void k_faces(int64_t T, const int32_t* __restrict__ tet_edge, const int64_t* __restrict__ et_ptr,
-                        const int32_t* __restrict__ et_inc, uint8_t* __restrict__ bface,
-                        unsigned long long* __restrict__ counts, unsigned* __restrict__ err) {
-    __shared__ unsigned long long lds[BLOCK / 64];
+// Faces: a face (a, b, x), a < b < x, is counted on its lowest edge (a, b),
+// whose incidence list holds every tet of the face.  One lane per edge: the
+// ring of tets around (a, b) (up to RING of them in registers, longer rings
+// read again from memory) gives each tet's two other vertices; the face
+// (a, b, x) with x > b is held by the ring tets that contain x -- one on the
+// boundary, two inside, more in an invalid mesh.  Its smallest tet counts it
+// once, and a boundary face sets, in its tet's byte, the bit of the local
+// vertex opposite it (an atomic OR on the byte's 32-bit word).
+constexpr int RING = 8;
+
+// the two local vertices off local edge le (the edge opposite it)
+__device__ __forceinline__ void off_edge(int le, int* c1, int* c2) {
+    *c1 = le == 0 ? 2 : (le <= 2 ? 1 : 0);
+    *c2 = (le <= 1 || le == 3) ? 3 : ((le == 2 || le == 4) ? 2 : 1);
+}
+
+struct FaceTally {
     unsigned long long owned = 0, bnd = 0;
-    const int k = threadIdx.x & 3;
-    const int la = k == 0 ? 1 : 0, lb = k <= 1 ? 2 : 1, lc = k == 3 ? 2 : 3;
-    const int ea = local_edge(la, lb), eb = local_edge(la, lc);
-    int64_t t_lo, t_hi;
-    block_range(T, &t_lo, &t_hi);
-    for (int64_t t = t_lo + threadIdx.x / 4; t < t_hi; t += blockDim.x / 4) {
-        const int e1 = tet_edge[6 * t + ea];
-        const int e2 = tet_edge[6 * t + eb];
-        int64_t i = et_ptr[e1], j = et_ptr[e2];
-        const int64_t i1 = et_ptr[e1 + 1], j1 = et_ptr[e2 + 1];
-        int cnt = 0, first = -1;
-        while (i < i1 && j < j1) {
-            const int u = et_inc[i] / 6, w = et_inc[j] / 6;
-            if (u == w) {
-                if (first < 0) first = u;
-                ++cnt;
-                ++i;
-                ++j;
-            } else if (u < w) {
-                ++i;
-            } else {
-                ++j;
+    __device__ __forceinline__ void add(int t, int opposite, int cnt, int first, uint32_t* bface_words,
+                                        unsigned* err) {
+        if (cnt > 2) atomicOr(err, 16u);
+        owned += first == t;
+        if (cnt == 1) {
+            ++bnd;
+            atomicOr(bface_words + (t >> 2), 1u << (8 * (t & 3) + opposite));
+        }
+    }
+};
+
+__global__ void k_edge_faces(int64_t E, const int32_t* __restrict__ edges, const int64_t* __restrict__ et_ptr,
+                             const int32_t* __restrict__ et_inc, const int4* __restrict__ tets,
+                             uint32_t* __restrict__ bface_words, unsigned long long* __restrict__ counts,
+                             unsigned* __restrict__ err) {
+    __shared__ unsigned long long lds[BLOCK / 64];
+    FaceTally tally;
+    RANGE_LOOP(e, E) {
+        const int b = edges[2 * e + 1];
+        const int64_t i0 = et_ptr[e];
+        const int m = (int)(et_ptr[e + 1] - i0);
+        if (m <= RING) {
+            int u[RING], x1[RING], x2[RING], o1[RING], o2[RING];
+#pragma unroll
+            for (int r = 0; r < RING; ++r) {
+                const int sl = r < m ? et_inc[i0 + r] : -1;
+                int c1, c2;
+                off_edge(sl >= 0 ? sl % 6 : 0, &c1, &c2);
+                u[r] = sl >= 0 ? sl / 6 : -1;
+                const int4 q = sl >= 0 ? tets[u[r]] : make_int4(-1, -1, -1, -1);
+                x1[r] = vget(q, c1);  // face (a, b, x1) is opposite c2
+                x2[r] = vget(q, c2);
+                o1[r] = c2;
+                o2[r] = c1;
+            }
+#pragma unroll
+            for (int r = 0; r < RING; ++r) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int x = j ? x2[r] : x1[r];
+                    if (x > b) {
+                        int cnt = 0, first = INT_MAX;
+#pragma unroll
+                        for (int r2 = 0; r2 < RING; ++r2) {
+                            const bool has = x1[r2] == x || x2[r2] == x;
+                            cnt += has;
+                            first = has ? min(first, u[r2]) : first;
+                        }
+                        tally.add(u[r], j ? o2[r] : o1[r], cnt, first, bface_words, err);
+                    }
+                }
+            }
+        } else {
+            for (int r = 0; r < m; ++r) {
+                const int sl = et_inc[i0 + r];
+                int c1, c2;
+                off_edge(sl % 6, &c1, &c2);
+                const int4 q = tets[sl / 6];
+                for (int j = 0; j < 2; ++j) {
+                    const int x = vget(q, j ? c2 : c1);
+                    if (x <= b) continue;
+                    int cnt = 0, first = INT_MAX;
+                    for (int r2 = 0; r2 < m; ++r2) {
+                        const int s2 = et_inc[i0 + r2];
+                        int d1, d2;
+                        off_edge(s2 % 6, &d1, &d2);
+                        const int4 q2 = tets[s2 / 6];
+                        const bool has = vget(q2, d1) == x || vget(q2, d2) == x;
+                        cnt += has;
+                        first = has ? min(first, s2 / 6) : first;
+                    }
+                    tally.add(sl / 6, j ? c1 : c2, cnt, first, bface_words, err);
+                }
             }
         }
-        if (cnt > 2) atomicOr(err, 16u);
-        unsigned mask = cnt == 1 ? 1u << k : 0u;
-        bnd += cnt == 1;
-        owned += first == t;
-        mask |= __shfl_xor(mask, 1);
-        mask |= __shfl_xor(mask, 2);
-        if (k == 0) bface[t] = static_cast<uint8_t>(mask);
     }
-    owned = block_sum(owned, lds);
-    bnd = block_sum(bnd, lds);
+    const unsigned long long owned = block_sum(tally.owned, lds);
+    const unsigned long long bnd = block_sum(tally.bnd, lds);
     if (threadIdx.x == 0) {
         if (owned) atomicAdd(&counts[0], owned);
         if (bnd) atomicAdd(&counts[1], bnd);
@@ -434,29 +666,29 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     m->edges.alloc(ctx, 2 * E);
     m->et_ptr.alloc(ctx, E + 1);
     m->et_inc.alloc(ctx, 6 * T);
-    DBuf<int32_t> tet_edge;
-    tet_edge.alloc(ctx, 6 * T);
     m->col.alloc(ctx, nnz);
     m->nz_edge.alloc(ctx, nnz);
     m->diag_pos.alloc(ctx, V);
     hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(NG * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
-                       m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, tet_edge.p,
-                       m->col.p, m->nz_edge.p, m->diag_pos.p);
+                       m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, m->col.p,
+                       m->nz_edge.p, m->diag_pos.p);
     // [0] owned faces, [1] boundary faces, [2] error bits (low word): one read-back for all three
     DBuf<unsigned long long> fc;
     fc.alloc(ctx, 3);
     fc.zero();
     unsigned* err2 = reinterpret_cast<unsigned*>(fc.p + 2);
-    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
+    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V, BLOCK / NG)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
                        m->up_ptr.p, m->edges.p, m->nz_edge.p, err2);
     HIP_CHECK(hipGetLastError());
     m->row_ptr.alloc(ctx, V + 1);
     copy_i64_to_i32(ctx, row_ptr64.p, m->row_ptr.p, V + 1);
 
-    // faces
-    m->tet_bface.alloc(ctx, T);
-    hipLaunchKernelGGL(k_faces, dim3(grid_xcd(4 * T)), dim3(BLOCK), 0, s, T, tet_edge.p, m->et_ptr.p,
-                       m->et_inc.p, m->tet_bface.p, fc.p, err2);
+    // faces; the boundary bytes are set by atomic ORs on their 32-bit words, so
+    // the buffer is allocated and cleared in whole words
+    m->tet_bface.alloc(ctx, (T + 3) / 4 * 4);
+    m->tet_bface.zero();
+    hipLaunchKernelGGL(k_edge_faces, dim3(grid_xcd(E)), dim3(BLOCK), 0, s, E, m->edges.p, m->et_ptr.p,
+                       m->et_inc.p, tq, reinterpret_cast<uint32_t*>(m->tet_bface.p), fc.p, err2);
     HIP_CHECK(hipGetLastError());
     unsigned long long hc[3];
     std::memcpy(hc, ctx->readback(fc.p, sizeof(hc)), sizeof(hc));
