@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "group_front.h"
+#include "row_scan.h"
 #include "sell.h"
 
 struct SolveCache;
@@ -17,9 +18,9 @@ void clear_graphs(SolveCache* c);
 namespace {
 
 // One ROWG-lane group per row: the group loads a run of ROWG entries at a
-// time (coalesced), writes the off-diagonal values, and every lane adds the
-// run's *1 values to the diagonal in ascending column order (shuffles), so
-// the diagonal is the same sequential sum as a one-thread-per-row loop.
+// time (coalesced), writes the off-diagonal values, and adds the run's *1
+// values to the diagonal in ascending column order (row_seq_sum), so the
+// diagonal is the same sequential sum as a one-thread-per-row loop.
 constexpr int ROWG = 16;
 
 __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ nz_edge,
@@ -28,7 +29,7 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
     const int g = threadIdx.x & (ROWG - 1);
     GROUP_FRONT_LOOP(v, V, ROWG) {
         const int32_t b = row_ptr[v], n = row_ptr[v + 1] - b;
-        double sum = 0.0;
+        double sum = 0.0;  // lane 0's
         for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
             const int32_t k = k0 + g;
             const int32_t e = k < n ? nz_edge[b + k] : -1;
@@ -37,12 +38,7 @@ __global__ void k_assemble_values(int64_t V, const int32_t* __restrict__ row_ptr
                 val64[b + k] = -s;
                 val32[b + k] = static_cast<float>(-s);
             }
-            const int run = min(ROWG, n - k0);
-            for (int j = 0; j < run; ++j) {
-                const double sj = __shfl(s, j, ROWG);
-                const int32_t ej = __shfl(e, j, ROWG);
-                if (ej >= 0) sum += sj;
-            }
+            sum = row_seq_sum(sum, s, e >= 0, g);
         }
         if (g == 0) {
             const int32_t d = diag_pos[v];

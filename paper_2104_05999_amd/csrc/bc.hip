@@ -12,6 +12,7 @@
 //
 // Compiled without floating-point contraction (fixed operation order).
 #include "common.h"
+#include "row_scan.h"
 #include "uf.h"
 
 void refresh_sell_values(dec_mesh* m);
@@ -210,7 +211,7 @@ __global__ void k_neumann_load(int64_t V, const int8_t* __restrict__ bc_type, co
 // b for free rows: (-g_v) - sum_k L_vk xd_k (all stored entries, ascending);
 // fixed rows: T0 (Dirichlet) or 0 (pinned).  One ROWG-lane group per row
 // loads runs of ROWG entries (coalesced); the products are added in entry
-// order through shuffles, the same sequential sum as a one-thread loop.
+// order (row_seq_sum), the same sequential sum as a one-thread loop.
 constexpr int ROWG = 16;
 
 __global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -226,12 +227,11 @@ __global__ void k_rhs(int64_t V, const int32_t* __restrict__ row_ptr, const int3
             continue;
         }
         const int32_t r0 = row_ptr[v], n = row_ptr[v + 1] - r0;
-        double acc = 0.0;
+        double acc = 0.0;  // lane 0's
         for (int32_t k0 = 0; k0 < n; k0 += ROWG) {
             const int32_t k = k0 + gl;
             const double t = k < n ? val[r0 + k] * dval[col[r0 + k]] : 0.0;
-            const int run = min(ROWG, n - k0);
-            for (int j = 0; j < run; ++j) acc += __shfl(t, j, ROWG);
+            acc = row_seq_sum(acc, t, k < n, gl);
         }
         if (gl == 0) {
             const double base = g ? (0.0 - g[v]) : 0.0;

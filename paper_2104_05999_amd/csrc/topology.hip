@@ -70,23 +70,35 @@ __global__ void k_vt_fill(const int32_t* __restrict__ tets, int64_t n4, const in
     }
 }
 
-// Sort each vertex's tet list (ascending tet id).  One 32-lane group per
-// vertex: a list of at most 32 distinct ids is ranked in registers (rank =
-// number of smaller ids) and written back; longer lists are insertion-sorted
-// by the group's first lane.
+// Sort each vertex's tet list (ascending tet id).  One 16-lane group per
+// vertex: a list of at most 32 distinct ids, two per lane, is ranked in
+// registers (rank = number of smaller ids, counted over the group's keys
+// brought by the 15 DPP row rotations) and written back; longer lists are
+// insertion-sorted by the group's first lane.
+constexpr int SG = 16;
+
+template <int R>
+__device__ __forceinline__ void rank_rotations(int k0, int k1, int& r0, int& r1) {
+    const int o0 = __builtin_amdgcn_mov_dpp(k0, 0x120 + R, 0xf, 0xf, false);  // row_ror:R
+    const int o1 = __builtin_amdgcn_mov_dpp(k1, 0x120 + R, 0xf, 0xf, false);
+    r0 += (o0 < k0) + (o1 < k0);
+    r1 += (o0 < k1) + (o1 < k1);
+    if constexpr (R < SG - 1) rank_rotations<R + 1>(k0, k1, r0, r1);
+}
+
 __global__ void k_vt_sort(const int64_t* __restrict__ vt_ptr, int32_t* __restrict__ vt_list, int64_t V) {
-    constexpr int W = 32;
-    const int lane = threadIdx.x & (W - 1);
-    GROUP_FRONT_LOOP(v, V, W) {
+    const int g = threadIdx.x & (SG - 1);
+    GROUP_FRONT_LOOP(v, V, SG) {
         const int64_t b = vt_ptr[v];
         const int d = (int)(vt_ptr[v + 1] - b);
-        if (d <= W) {
-            const int key = lane < d ? vt_list[b + lane] : INT_MAX;
-            int rank = 0;
-#pragma unroll
-            for (int k = 0; k < W; ++k) rank += __shfl(key, k, W) < key;
-            if (lane < d) vt_list[b + rank] = key;
-        } else if (lane == 0) {
+        if (d <= 2 * SG) {
+            const int k0 = g < d ? vt_list[b + g] : INT_MAX;
+            const int k1 = g + SG < d ? vt_list[b + g + SG] : INT_MAX;
+            int r0 = k1 < k0, r1 = k0 < k1;
+            rank_rotations<1>(k0, k1, r0, r1);
+            if (g < d) vt_list[b + r0] = k0;
+            if (g + SG < d) vt_list[b + r1] = k1;
+        } else if (g == 0) {
             for (int64_t i = b + 1; i < b + d; ++i) {
                 const int32_t key = vt_list[i];
                 int64_t j = i - 1;
@@ -636,7 +648,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     cnt.zero();
     hipLaunchKernelGGL(k_vt_fill, dim3(grid_for(4 * T)), dim3(BLOCK), 0, s, m->tets.p, 4 * T, m->vt_ptr.p, cnt.p,
                        m->vt_list.p);
-    hipLaunchKernelGGL(k_vt_sort, dim3(grid_xcd(V, BLOCK / 32)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
+    hipLaunchKernelGGL(k_vt_sort, dim3(grid_xcd(V, BLOCK / SG)), dim3(BLOCK), 0, s, m->vt_ptr.p, m->vt_list.p, V);
     HIP_CHECK(hipGetLastError());
 
     // neighbours: counts, then edges, incidences and the CSR pattern (one 16-lane group per vertex)
