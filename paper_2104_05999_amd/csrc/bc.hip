@@ -90,12 +90,17 @@ __global__ __launch_bounds__(NT) void k_uf_tiles(int64_t V, const int32_t* __res
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += NT) {
         const int64_t v = v0 + i;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t c = col[k];
-            if (c <= v || c >= v0 + n) continue;
-            const int32_t e = nz_edge[k];
-            if (e < 0 || star1[e] == 0.0) continue;
-            uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i, (int32_t)(c - v0));
+        const int32_t k1 = row_ptr[v + 1];
+        for (int32_t k = row_ptr[v]; k < k1; k += 8) {  // eight entries' loads at a time
+            int32_t c[8], e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = k + u < k1 ? col[k + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = (c[u] > v && c[u] < v0 + n) ? nz_edge[k + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e[u] >= 0 && star1[e[u]] != 0.0)
+                    uf_union<__HIP_MEMORY_SCOPE_WORKGROUP>(lp, i, (int32_t)(c[u] - v0));
         }
     }
     __syncthreads();
@@ -119,15 +124,21 @@ __global__ __launch_bounds__(BLOCK) void k_uf_cross(int64_t V, const int32_t* __
         int32_t c1 = -1;
         if (v < V) {
             const int64_t tile_end = (v / UF_TILE + 1) * UF_TILE;
-            for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-                const int32_t c = col[k];
-                if (c < tile_end) continue;  // a lower neighbour, or one in v's own tile
-                const int32_t e = nz_edge[k];
-                if (e < 0 || star1[e] == 0.0) continue;
-                if (c1 < 0)
-                    c1 = c;
-                else
-                    uf_union(parent, (int32_t)v, c);
+            const int32_t k1 = row_ptr[v + 1];
+            for (int32_t k = row_ptr[v]; k < k1; k += 8) {  // eight entries' loads at a time
+                int32_t c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) c[u] = k + u < k1 ? col[k + u] : -1;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (c[u] < tile_end) continue;  // a lower neighbour, or one in v's own tile
+                    const int32_t e = nz_edge[k + u];
+                    if (e < 0 || star1[e] == 0.0) continue;
+                    if (c1 < 0)
+                        c1 = c[u];
+                    else
+                        uf_union(parent, (int32_t)v, c[u]);
+                }
             }
         }
         const int32_t a = c1 >= 0 ? __hip_atomic_load(parent + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
@@ -247,12 +258,20 @@ __global__ void k_eliminate(int64_t V, const int32_t* __restrict__ row_ptr, cons
     unsigned long long bad = 0;
     RANGE_LOOP(v, V) {
         const bool fv = fixed[v] != 0;
-        for (int32_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
-            const int32_t c = col[k];
-            if (fv || fixed[c]) {
-                const double nv = (c == v && fv) ? 1.0 : 0.0;
-                val64[k] = nv;
-                val32[k] = static_cast<float>(nv);
+        const int32_t k1 = row_ptr[v + 1];
+        for (int32_t k = row_ptr[v]; k < k1; k += 8) {  // eight entries' loads at a time
+            int32_t c[8];
+            bool fc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = k + u < k1 ? col[k + u] : -1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) fc[u] = c[u] >= 0 && (fv || fixed[c[u]]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (!fc[u]) continue;
+                const double nv = (c[u] == v && fv) ? 1.0 : 0.0;
+                val64[k + u] = nv;
+                val32[k + u] = static_cast<float>(nv);
             }
         }
         const int32_t d = diag_pos[v];
