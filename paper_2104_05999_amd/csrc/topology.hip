@@ -457,16 +457,18 @@ __global__ void k_nbr_fill(const int4* __restrict__ tets, const int64_t* __restr
 }
 
 // Entries (v, w) with w < v belong to edge (w, v), found among w's upper
-// edges (sorted by hi).  One NG-lane group per row, a lane per entry; lists
-// of up to 8 upper edges are read at once and scanned, longer ones binary
-// searched.
+// edges (sorted by hi).  One LG-lane group per row, a lane per entry (a row's
+// lower entries come first, about half of it); lists of up to 8 upper edges
+// are read at once and scanned, longer ones binary searched.
+constexpr int LG = 8;
+
 __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                  const int64_t* __restrict__ up_ptr, const int32_t* __restrict__ edges,
                                  int32_t* __restrict__ nz_edge, unsigned* __restrict__ err) {
-    const int g = threadIdx.x & (NG - 1);
-    GROUP_FRONT_LOOP(v, V, NG) {
+    const int g = threadIdx.x & (LG - 1);
+    GROUP_FRONT_LOOP(v, V, LG) {
         const int64_t k1 = row_ptr[v + 1];
-        for (int64_t k = row_ptr[v] + g; k < k1; k += NG) {
+        for (int64_t k = row_ptr[v] + g; k < k1; k += LG) {
             const int w = col[k];
             if (w >= v) break;
             const int64_t lo = up_ptr[w], n = up_ptr[w + 1] - lo;
@@ -689,7 +691,7 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     fc.alloc(ctx, 3);
     fc.zero();
     unsigned* err2 = reinterpret_cast<unsigned*>(fc.p + 2);
-    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V, BLOCK / NG)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
+    hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V, BLOCK / LG)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
                        m->up_ptr.p, m->edges.p, m->nz_edge.p, err2);
     HIP_CHECK(hipGetLastError());
     m->row_ptr.alloc(ctx, V + 1);
