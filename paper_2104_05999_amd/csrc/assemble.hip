@@ -72,6 +72,8 @@ __device__ __forceinline__ unsigned kept8(int32_t k, int32_t k1, const int32_t* 
     return mask;
 }
 
+constexpr int KEPT_SPREAD = 64;
+
 // Stored entries per slice: one wavefront per slice, each lane counts its
 // row's kept entries and the wavefront takes the maximum.  Also the number of
 // kept entries, per block.
@@ -99,7 +101,9 @@ __global__ __launch_bounds__(BLOCK) void k_sell_width(int64_t V, int64_t nslices
         if (lane == 0) width64[s] = wmax * SELL_C;  // entries in the slice
     }
     total = block_sum(total, lds);
-    if (threadIdx.x == 0 && total) atomicAdd(kept_count, total);
+    // one of KEPT_SPREAD counters per block (summed on the host): thousands
+    // of blocks adding to one address would wait on each other
+    if (threadIdx.x == 0 && total) atomicAdd(kept_count + blockIdx.x % KEPT_SPREAD, total);
 }
 
 __global__ void k_sell_fill(int64_t V, int64_t nslices, const int32_t* __restrict__ row_ptr,
@@ -287,14 +291,17 @@ void build_sell_pattern(dec_mesh* m) {
     DBuf<int32_t> w;
     w.alloc(ctx, S.nslices);
     DBuf<unsigned long long> cnt;
-    cnt.alloc(ctx, 1);
+    cnt.alloc(ctx, KEPT_SPREAD);
     cnt.zero();
     const double* geo = m->prune_geometric_zeros ? m->geo.p : nullptr;
     hipLaunchKernelGGL(k_sell_width, dim3(grid_xcd(S.nslices, BLOCK / 64)), dim3(BLOCK), 0, ctx->stream, m->V,
                        S.nslices, m->row_ptr.p, m->nz_edge.p, geo, w.p, cnt.p);
     S.ptr.alloc(ctx, S.nslices + 1);
     S.entries = scan_exclusive_i32_to_i64(ctx, w.p, S.ptr.p, S.nslices, true);
-    S.kept = (int64_t) * static_cast<unsigned long long*>(ctx->readback(cnt.p, sizeof(unsigned long long)));
+    const unsigned long long* kc =
+        static_cast<const unsigned long long*>(ctx->readback(cnt.p, KEPT_SPREAD * sizeof(unsigned long long)));
+    S.kept = 0;
+    for (int k = 0; k < KEPT_SPREAD; ++k) S.kept += (int64_t)kc[k];
     S.col.alloc(ctx, S.entries);
     S.src.alloc(ctx, S.entries);
     S.val64.alloc(ctx, S.entries);

@@ -509,6 +509,7 @@ __global__ void k_lower_edge_ids(int64_t V, const int64_t* __restrict__ row_ptr,
 // once, and a boundary face sets, in its tet's byte, the bit of the local
 // vertex opposite it (an atomic OR on the byte's 32-bit word).
 constexpr int RING = 8;
+constexpr int COUNT_SPREAD = 64;
 
 // the two local vertices off local edge le (the edge opposite it)
 __device__ __forceinline__ void off_edge(int le, int* c1, int* c2) {
@@ -594,11 +595,14 @@ __global__ void k_edge_faces(int64_t E, const int32_t* __restrict__ edges, const
             }
         }
     }
+    // block totals into COUNT_SPREAD counters per sum (summed on the host):
+    // thousands of blocks adding to one address would wait on each other
     const unsigned long long owned = block_sum(tally.owned, lds);
     const unsigned long long bnd = block_sum(tally.bnd, lds);
     if (threadIdx.x == 0) {
-        if (owned) atomicAdd(&counts[0], owned);
-        if (bnd) atomicAdd(&counts[1], bnd);
+        const int slot = blockIdx.x % COUNT_SPREAD;
+        if (owned) atomicAdd(&counts[slot], owned);
+        if (bnd) atomicAdd(&counts[COUNT_SPREAD + slot], bnd);
     }
 }
 
@@ -686,11 +690,12 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(NG * V)), dim3(BLOCK), 0, s, tq, m->vt_ptr.p, m->vt_list.p, V,
                        m->up_ptr.p, row_ptr64.p, inc_ptr.p, m->edges.p, m->et_ptr.p, m->et_inc.p, m->col.p,
                        m->nz_edge.p, m->diag_pos.p);
-    // [0] owned faces, [1] boundary faces, [2] error bits (low word): one read-back for all three
+    // [0, COUNT_SPREAD) owned faces, then as many boundary faces, then the
+    // error bits (low word): one read-back for all of them
     DBuf<unsigned long long> fc;
-    fc.alloc(ctx, 3);
+    fc.alloc(ctx, 2 * COUNT_SPREAD + 1);
     fc.zero();
-    unsigned* err2 = reinterpret_cast<unsigned*>(fc.p + 2);
+    unsigned* err2 = reinterpret_cast<unsigned*>(fc.p + 2 * COUNT_SPREAD);
     hipLaunchKernelGGL(k_lower_edge_ids, dim3(grid_xcd(V, BLOCK / LG)), dim3(BLOCK), 0, s, V, row_ptr64.p, m->col.p,
                        m->up_ptr.p, m->edges.p, m->nz_edge.p, err2);
     HIP_CHECK(hipGetLastError());
@@ -704,11 +709,14 @@ void build_topology_device(dec_mesh* m, const double* xyz, const int32_t* tets) 
     hipLaunchKernelGGL(k_edge_faces, dim3(grid_xcd(E)), dim3(BLOCK), 0, s, E, m->edges.p, m->et_ptr.p,
                        m->et_inc.p, tq, reinterpret_cast<uint32_t*>(m->tet_bface.p), fc.p, err2);
     HIP_CHECK(hipGetLastError());
-    unsigned long long hc[3];
+    unsigned long long hc[2 * COUNT_SPREAD + 1];
     std::memcpy(hc, ctx->readback(fc.p, sizeof(hc)), sizeof(hc));
-    m->F = (int64_t)hc[0];
-    m->Fb = (int64_t)hc[1];
-    const unsigned e1 = static_cast<unsigned>(hc[2] & 0xffffffffu);
+    m->F = m->Fb = 0;
+    for (int k = 0; k < COUNT_SPREAD; ++k) {
+        m->F += (int64_t)hc[k];
+        m->Fb += (int64_t)hc[COUNT_SPREAD + k];
+    }
+    const unsigned e1 = static_cast<unsigned>(hc[2 * COUNT_SPREAD] & 0xffffffffu);
     if (e1) dec_fail(DEC_ETOPO, topo_message(e1));
 }
 
