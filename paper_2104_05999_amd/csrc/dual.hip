@@ -37,44 +37,91 @@ void build_sell_copy(dec_ctx* ctx, int64_t V, int64_t nnz, const int32_t* ptr, c
 
 namespace {
 
-// The tet across each face of every tet (-1 on the boundary): the tets holding
-// vertices a and b of the face (merge of two ascending tet lists) that also
-// hold c.  owned[t] counts the faces t owns (no lower tet holds them).
-__global__ void k_dual_nbr(int64_t T, const int4* __restrict__ tets, const int64_t* __restrict__ vt_ptr,
-                           const int32_t* __restrict__ vt_list, int32_t* __restrict__ nbr, int32_t* __restrict__ owned,
-                           unsigned* __restrict__ err) {
-    GRID_STRIDE_LOOP(t, T) {
-        const int4 q = tets[t];
-        int own = 0;
-        for (int k = 0; k < 4; ++k) {
-            const int a = vget(q, face_local_vertex(k, 0)), b = vget(q, face_local_vertex(k, 1));
-            const int c = vget(q, face_local_vertex(k, 2));
-            int64_t i = vt_ptr[a], j = vt_ptr[b];
-            const int64_t i1 = vt_ptr[a + 1], j1 = vt_ptr[b + 1];
-            int other = -1, cnt = 0;
-            while (i < i1 && j < j1) {
-                const int u = vt_list[i], w = vt_list[j];
-                if (u == w) {
-                    if (u != (int)t) {
-                        const int4 o = tets[u];
-                        if (o.x == c || o.y == c || o.z == c || o.w == c) {
-                            other = u;
-                            ++cnt;
+// The tet across each face of every tet (-1 on the boundary), from the edge
+// rings of the vertex topology: a face (a, b, x), a < b < x, lies in the ring
+// of tets around its lowest edge (a, b), and its tets are the ring tets that
+// hold x.  One lane per edge (up to RING ring tets in registers, longer rings
+// read again from memory); each tet's face is written by the lane of that
+// face's lowest edge, so every entry is written once.
+constexpr int RING = 8;
+
+// the two local vertices off local edge le (the edge opposite it)
+__device__ __forceinline__ void off_edge(int le, int* c1, int* c2) {
+    *c1 = le == 0 ? 2 : (le <= 2 ? 1 : 0);
+    *c2 = (le <= 1 || le == 3) ? 3 : ((le == 2 || le == 4) ? 2 : 1);
+}
+
+__global__ void k_dual_nbr(int64_t E, const int32_t* __restrict__ edges, const int64_t* __restrict__ et_ptr,
+                           const int32_t* __restrict__ et_inc, const int4* __restrict__ tets,
+                           int32_t* __restrict__ nbr, unsigned* __restrict__ err) {
+    RANGE_LOOP(e, E) {
+        const int b = edges[2 * e + 1];
+        const int64_t i0 = et_ptr[e];
+        const int m = (int)(et_ptr[e + 1] - i0);
+        if (m <= RING) {
+            int u[RING], x1[RING], x2[RING], o1[RING], o2[RING];
+#pragma unroll
+            for (int r = 0; r < RING; ++r) {
+                const int sl = r < m ? et_inc[i0 + r] : -1;
+                int c1, c2;
+                off_edge(sl >= 0 ? sl % 6 : 0, &c1, &c2);
+                u[r] = sl >= 0 ? sl / 6 : -1;
+                const int4 q = sl >= 0 ? tets[u[r]] : make_int4(-1, -1, -1, -1);
+                x1[r] = vget(q, c1);  // face (a, b, x1) is opposite c2
+                x2[r] = vget(q, c2);
+                o1[r] = c2;
+                o2[r] = c1;
+            }
+#pragma unroll
+            for (int r = 0; r < RING; ++r) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int x = j ? x2[r] : x1[r];
+                    if (x > b) {
+                        int cnt = 0, other = -1;
+#pragma unroll
+                        for (int r2 = 0; r2 < RING; ++r2) {
+                            const bool has = x1[r2] == x || x2[r2] == x;
+                            cnt += has;
+                            other = has && r2 != r ? u[r2] : other;
                         }
+                        if (cnt > 2) atomicOr(err, 1u);
+                        nbr[4 * (int64_t)u[r] + (j ? o2[r] : o1[r])] = other;
                     }
-                    ++i;
-                    ++j;
-                } else if (u < w) {
-                    ++i;
-                } else {
-                    ++j;
                 }
             }
-            if (cnt > 1) atomicOr(err, 1u);
-            nbr[4 * t + k] = other;
-            own += (other < 0 || other > (int)t);
+        } else {
+            for (int r = 0; r < m; ++r) {
+                const int sl = et_inc[i0 + r];
+                int c1, c2;
+                off_edge(sl % 6, &c1, &c2);
+                const int4 q = tets[sl / 6];
+                for (int j = 0; j < 2; ++j) {
+                    const int x = vget(q, j ? c2 : c1);
+                    if (x <= b) continue;
+                    int cnt = 0, other = -1;
+                    for (int r2 = 0; r2 < m; ++r2) {
+                        const int s2 = et_inc[i0 + r2];
+                        int d1, d2;
+                        off_edge(s2 % 6, &d1, &d2);
+                        const int4 q2 = tets[s2 / 6];
+                        const bool has = vget(q2, d1) == x || vget(q2, d2) == x;
+                        cnt += has;
+                        other = has && r2 != r ? s2 / 6 : other;
+                    }
+                    if (cnt > 2) atomicOr(err, 1u);
+                    nbr[4 * (int64_t)(sl / 6) + (j ? c1 : c2)] = other;
+                }
+            }
         }
-        owned[t] = own;
+    }
+}
+
+// owned[t]: the faces of t that no lower tet holds
+__global__ void k_dual_owned(int64_t T, const int32_t* __restrict__ nbr, int32_t* __restrict__ owned) {
+    GRID_STRIDE_LOOP(t, T) {
+        const int4 n = reinterpret_cast<const int4*>(nbr)[t];
+        owned[t] = (n.x < 0 || n.x > t) + (n.y < 0 || n.y > t) + (n.z < 0 || n.z > t) + (n.w < 0 || n.w > t);
     }
 }
 
@@ -572,7 +619,7 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
     dec_mesh* d = nullptr;
     try {
         DEC_REQUIRE(!m->dual, DEC_ESTATE, "dec_dual_build needs a mesh of vertex unknowns");
-        DEC_REQUIRE(m->vt_ptr.p && m->vt_list.p && m->xyz.p && m->tets.p, DEC_ESTATE,
+        DEC_REQUIRE(m->vt_ptr.p && m->vt_list.p && m->et_inc.p && m->edges.p && m->xyz.p && m->tets.p, DEC_ESTATE,
                     "dec_dual_build needs the topology of dec_build_topology");
         DEC_REQUIRE(n_cracks >= 0 && (n_cracks == 0 || cracks), DEC_EINVAL, "bad crack array");
         DEC_REQUIRE(5 * m->T < (int64_t(1) << 31), DEC_EINVAL, "too many tets for int32 row pointers");
@@ -595,8 +642,9 @@ int dec_dual_build(dec_mesh* m, const double* kappa_face, int32_t n_cracks, cons
         owned.alloc(ctx, T);
         err.alloc(ctx, 1);
         err.zero();
-        hipLaunchKernelGGL(k_dual_nbr, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, tq, m->vt_ptr.p, m->vt_list.p, nbr.p,
-                           owned.p, err.p);
+        hipLaunchKernelGGL(k_dual_nbr, dim3(grid_xcd(m->E)), dim3(BLOCK), 0, s, m->E, m->edges.p, m->et_ptr.p,
+                           m->et_inc.p, tq, nbr.p, err.p);
+        hipLaunchKernelGGL(k_dual_owned, dim3(grid_for(T)), dim3(BLOCK), 0, s, T, nbr.p, owned.p);
         DBuf<int64_t> face_ptr;
         face_ptr.alloc(ctx, T + 1);
         const int64_t nf = scan_exclusive_i32_to_i64(ctx, owned.p, face_ptr.p, T, true);
