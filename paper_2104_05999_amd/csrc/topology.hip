@@ -267,6 +267,35 @@ __device__ __forceinline__ KeyRound next_key(LaneKeys& k) {
     return r;
 }
 
+// The count needs the neighbours only: the lane's keys become plain vertex
+// ids, a repeat (a vertex in both of the lane's tets, next to each other in
+// the sorted keys) is dropped and the six are sorted again, so a round drops
+// at most one id per lane.
+__device__ __forceinline__ LaneKeys lane_ids(const GroupTets& gt, int v) {
+    const LaneKeys k = lane_keys(gt, v);
+    int w[NKEY];
+#pragma unroll
+    for (int i = 0; i < NKEY; ++i) w[i] = k.c[i] == INT_MAX ? INT_MAX : k.c[i] >> 3;
+    LaneKeys d;
+    d.c[0] = w[0];
+#pragma unroll
+    for (int i = 1; i < NKEY; ++i) d.c[i] = w[i] == w[i - 1] ? INT_MAX : w[i];
+    // sorting network for six
+    cmp_swap(d.c[0], d.c[5]);
+    cmp_swap(d.c[1], d.c[3]);
+    cmp_swap(d.c[2], d.c[4]);
+    cmp_swap(d.c[1], d.c[2]);
+    cmp_swap(d.c[3], d.c[4]);
+    cmp_swap(d.c[0], d.c[3]);
+    cmp_swap(d.c[2], d.c[5]);
+    cmp_swap(d.c[0], d.c[1]);
+    cmp_swap(d.c[2], d.c[3]);
+    cmp_swap(d.c[4], d.c[5]);
+    cmp_swap(d.c[1], d.c[2]);
+    cmp_swap(d.c[3], d.c[4]);
+    return d;
+}
+
 // Per vertex: upper neighbours (edges it is the low end of), pattern row
 // length, and the incidences of its upper edges -- each tet of v adds one per
 // vertex above v, so that count needs no enumeration.
@@ -284,10 +313,11 @@ __global__ void k_nbr_count(const int4* __restrict__ tets, const int64_t* __rest
         inc = group_sum(inc);
         int up = 0, all = 0;
         if (d <= 2 * NG && V <= KEY_LIMIT) {
-            LaneKeys keys = lane_keys(gt, (int)v);
+            LaneKeys ids = lane_ids(gt, (int)v);
             while (true) {
-                const int w = next_key(keys).w;
+                const int w = group_min(ids.c[0]);
                 if (w == INT_MAX) break;
+                ids.pop_if(ids.c[0] == w);
                 ++all;
                 up += w > v;
             }
