@@ -84,18 +84,24 @@ __global__ void k_elementary_areas(int64_t T, const int32_t* __restrict__ tets, 
             const double le = sqrt(dot(d, d));
             const double dk = dot(sub(pi, pk), sub(pj, pk));
             const double dl = dot(sub(pi, pl), sub(pj, pl));
-            elem[6 * t + e] = 0.25 * le * (dk * H[EL[e]] + dl * H[EK[e]]);
+            elem[e * T + t] = 0.25 * le * (dk * H[EL[e]] + dl * H[EK[e]]);
         }
     }
 }
 
 // |*e| in ascending tet order, snapped, over |e|.  Up to RING incidences are
 // loaded at once (their loads do not wait on each other), then added in order.
+// The elementary areas sit local edge by local edge (elem[e * T + t]): the
+// gathers of neighbouring edges then share more cache lines than with a
+// tet's six areas side by side.
 constexpr int RING = 8;
 
-__global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, const double* __restrict__ xyz,
-                                const int64_t* __restrict__ et_ptr, const int32_t* __restrict__ et_inc,
+__global__ void k_edge_geometry(int64_t E, int64_t T, const int32_t* __restrict__ edges,
+                                const double* __restrict__ xyz, const int64_t* __restrict__ et_ptr,
+                                const int32_t* __restrict__ et_inc,
                                 const double* __restrict__ elem, double* __restrict__ geo) {
+    // incidence tet * 6 + local edge e -> elem[e * T + tet]
+    auto at = [&](int32_t sl) { return elem[(int64_t)(sl % 6) * T + sl / 6]; };
     const FrontRange fr = front_range(E);
     for (int64_t e = fr.first; e < fr.end; e += fr.step) {
         const int64_t i0 = et_ptr[e];
@@ -104,12 +110,12 @@ __global__ void k_edge_geometry(int64_t E, const int32_t* __restrict__ edges, co
         if (m <= RING) {
             double a[RING];
 #pragma unroll
-            for (int r = 0; r < RING; ++r) a[r] = r < m ? elem[et_inc[i0 + r]] : 0.0;
+            for (int r = 0; r < RING; ++r) a[r] = r < m ? at(et_inc[i0 + r]) : 0.0;
 #pragma unroll
             for (int r = 0; r < RING; ++r)
                 if (r < m) area += a[r];
         } else {
-            for (int r = 0; r < m; ++r) area += elem[et_inc[i0 + r]];
+            for (int r = 0; r < m; ++r) area += at(et_inc[i0 + r]);
         }
         const d3 d = sub(load3(xyz + 3 * (int64_t)edges[2 * e + 1]), load3(xyz + 3 * (int64_t)edges[2 * e]));
         const double len = sqrt(dot(d, d));
@@ -312,8 +318,8 @@ void ensure_geometry(dec_mesh* m) {
     hipLaunchKernelGGL(k_elementary_areas, dim3(grid_for(m->T)), dim3(BLOCK), 0, ctx->stream, m->T, m->tets.p,
                        m->xyz.p, elem.p);
     m->geo.alloc(ctx, m->E);
-    hipLaunchKernelGGL(k_edge_geometry, dim3(grid_xcd(m->E, BLOCK, 1 << 20)), dim3(BLOCK), 0, ctx->stream, m->E, m->edges.p,
-                       m->xyz.p, m->et_ptr.p, m->et_inc.p, elem.p, m->geo.p);
+    hipLaunchKernelGGL(k_edge_geometry, dim3(grid_xcd(m->E, BLOCK, 1 << 20)), dim3(BLOCK), 0, ctx->stream, m->E, m->T,
+                       m->edges.p, m->xyz.p, m->et_ptr.p, m->et_inc.p, elem.p, m->geo.p);
     HIP_CHECK(hipGetLastError());
     ctx->sync();  // elem is released on return
     m->geo_ready = true;
